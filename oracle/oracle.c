@@ -1,0 +1,394 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle for algebraic-distance sparsification
+ * (John & Safro, "Single- and Multi-level Network Sparsification by
+ * Algebraic Distance", arXiv 1601.05527).
+ *
+ * TEST INFRASTRUCTURE.  This file exists to check the HIP library: only the
+ * tests, the smoke check and the benchmark's CPU-baseline leg call it.  It
+ * shares no code, header or table with the library; it follows the paper's
+ * algorithms step by step, in double precision, with plain loops (one
+ * sequential sum per row, in CSR order).  OpenMP only splits independent
+ * vertices across threads, as the paper's own implementation does
+ * (Section 6.4, "Parallelization").
+ *
+ * Graph input: symmetric CSR of an undirected simple graph (Preliminaries):
+ *   row_ptr[n+1] (int64), col[2m] (int32), w[2m] (float, NULL = unit),
+ *   eid[2m] (int32 undirected edge id shared by both mirror entries),
+ *   orig_id[n] (int32, NULL = identity).
+ *
+ * Readings of points the paper leaves open (the library follows the same
+ * readings with its own code):
+ *   - relaxation weight: the parameter omega multiplies the neighbour
+ *     average, the paper's alpha = 1 - omega multiplies the old value
+ *     (Algorithm 1; every experiment uses 1/2, where both coincide);
+ *   - R vectors r = 0..R-1, k sweeps t = 1..k, each reading only t-1 values
+ *     (Jacobi, Algorithm 1);
+ *   - random start: uniform values from Philox4x64-10 (Salmon et al.,
+ *     SC'11), key (seed, graph_id), counter (orig_id[i], r/4, 0, 0), word
+ *     r%4, top 24 bits scaled by 2^-24, minus 1/2;
+ *   - isolated vertices keep their value, are left out of the rescale's
+ *     min/max and have no edges;
+ *   - "rescale x back to (-0.5, 0.5)": once per vector after the sweeps, the
+ *     min-max affine map onto [-1/2, 1/2] over non-isolated vertices; a
+ *     degenerate range maps to 0;
+ *   - distance: rho_e = sqrt(sum_r (xhat_i - xhat_j)^2) (Algorithm 1), the
+ *     strength delta_e = 1/sqrt(rho_e^2 + eps) is monotone in rho_e;
+ *   - budget of vertex i: c_i = min(d_i, max(1, floor(pow(d_i, e)))) with
+ *     the C library's double pow (Section 4, "top d_i^e");
+ *   - LOCAL keeps the delta-strong edges (rho ascending), GLOBAL the
+ *     delta-weak ones (rho descending); ties in rho go to the smaller
+ *     orig_id of the neighbour in both orientations; an edge is kept when
+ *     either endpoint selects it (Algorithm 3);
+ *   - retention fit: bisection on e in [0, 1], 40 halvings, returning the
+ *     smallest e found whose retained fraction reaches the target (the
+ *     binary-search fitting of Section 7.2).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10, written from the published definition (Salmon, Moraes,
+ * Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11):
+ * ten rounds of two 64x64->128 multiplications with the round key bumped by
+ * the Weyl constants between rounds.                                        */
+
+static void orc_mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t mul0 = 0xD2E7470EE14C6C93ULL, mul1 = 0xCA5A826395121157ULL;
+    const uint64_t weyl0 = 0x9E3779B97F4A7C15ULL, weyl1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += weyl0; k1 += weyl1; }
+        uint64_t hi0, lo0, hi1, lo1;
+        orc_mulhilo64(mul0, x0, &hi0, &lo0);
+        orc_mulhilo64(mul1, x2, &hi1, &lo1);
+        uint64_t y0 = hi1 ^ x1 ^ k0;
+        uint64_t y1 = lo1;
+        uint64_t y2 = hi0 ^ x3 ^ k1;
+        uint64_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* x_i^(0) <- rand(-0.5, 0.5) for test vector r (Algorithm 1). */
+double orc_start_value(uint64_t seed, uint64_t graph_id, int32_t vertex_key, int32_t r)
+{
+    uint64_t key[2] = {seed, graph_id};
+    uint64_t ctr[4] = {(uint64_t)(uint32_t)vertex_key, (uint64_t)(r / 4), 0, 0};
+    uint64_t out[4];
+    orc_philox4x64_10(ctr, key, out);
+    uint64_t top24 = out[r % 4] >> 40;
+    return (double)top24 * (1.0 / 16777216.0) - 0.5;
+}
+
+/* All R start vectors, stored [n][R]. */
+void orc_start_vectors(int64_t n, int32_t R, uint64_t seed, uint64_t graph_id,
+                       const int32_t *orig_id, double *x0)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t r = 0; r < R; ++r)
+            x0[i * R + r] = orc_start_value(seed, graph_id,
+                                            orig_id ? orig_id[i] : (int32_t)i, r);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One JOR sweep of one test vector (Algorithm 1):
+ *   x_i^(t) = (1 - omega) x_i^(t-1) + omega * sum_j w_ij x_j^(t-1) / sum_j w_ij
+ * Isolated vertices keep their value.                                       */
+static void orc_jor_sweep(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                          const float *w, double omega, const double *x_old,
+                          double *x_new)
+{
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t beg = row_ptr[i], end = row_ptr[i + 1];
+        if (beg == end) { x_new[i] = x_old[i]; continue; }
+        double num = 0.0, den = 0.0;
+        for (int64_t p = beg; p < end; ++p) {
+            double wij = w ? (double)w[p] : 1.0;
+            num += wij * x_old[col[p]];
+            den += wij;
+        }
+        x_new[i] = (1.0 - omega) * x_old[i] + omega * (num / den);
+    }
+}
+
+/* k sweeps of one vector; x holds x^(0) on entry and x^(k) on exit.
+ * If trace != NULL it receives x^(0..k) as trace[t*n + i].                   */
+void orc_relax_vector(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                      const float *w, int32_t k, double omega, double *x,
+                      double *trace)
+{
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (trace) memcpy(trace, x, sizeof(double) * (size_t)n);
+    for (int32_t t = 1; t <= k; ++t) {
+        orc_jor_sweep(n, row_ptr, col, w, omega, x, tmp);
+        memcpy(x, tmp, sizeof(double) * (size_t)n);
+        if (trace) memcpy(trace + (size_t)t * (size_t)n, x, sizeof(double) * (size_t)n);
+    }
+    free(tmp);
+}
+
+/* "Rescale x back to (-0.5, 0.5)" (Algorithm 1): min-max map over the
+ * non-isolated vertices.  Returns min and max through lo/hi.                 */
+void orc_rescale_vector(int64_t n, const int64_t *row_ptr, const double *x,
+                        double *xhat, double *lo, double *hi)
+{
+    double mn = INFINITY, mx = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        if (row_ptr[i + 1] == row_ptr[i]) continue;
+        if (x[i] < mn) mn = x[i];
+        if (x[i] > mx) mx = x[i];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (row_ptr[i + 1] == row_ptr[i] || !(mx > mn)) xhat[i] = 0.0;
+        else xhat[i] = (x[i] - mn) / (mx - mn) - 0.5;
+    }
+    if (lo) *lo = mn;
+    if (hi) *hi = mx;
+}
+
+/* ComputeAlgDist (Algorithm 1) for R test vectors, returning the L2
+ * algebraic distance rho_e = sqrt(R_e) per undirected edge.
+ *   x0     : NULL -> Philox start vectors; else [n][R] start values.
+ *   xk     : optional [n][R] output of x^(k) (before the rescale).
+ *   xhat   : optional [n][R] output of the rescaled vectors.
+ *   minmax : optional [2R] output, min then max of each x^(k).
+ */
+void orc_algebraic_distance(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                            const float *w, const int32_t *eid,
+                            const int32_t *orig_id, int64_t m, int32_t R,
+                            int32_t k, double omega, uint64_t seed,
+                            uint64_t graph_id, const double *x0, double *rho,
+                            double *xk, double *xhat, double *minmax)
+{
+    double *acc = (double *)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
+    double *x = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *xh = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int32_t r = 0; r < R; ++r) {
+        for (int64_t i = 0; i < n; ++i)
+            x[i] = x0 ? x0[i * R + r]
+                      : orc_start_value(seed, graph_id,
+                                        orig_id ? orig_id[i] : (int32_t)i, r);
+        orc_relax_vector(n, row_ptr, col, w, k, omega, x, NULL);
+        double lo, hi;
+        orc_rescale_vector(n, row_ptr, x, xh, &lo, &hi);
+        if (minmax) { minmax[r] = lo; minmax[R + r] = hi; }
+        if (xk) for (int64_t i = 0; i < n; ++i) xk[i * R + r] = x[i];
+        if (xhat) for (int64_t i = 0; i < n; ++i) xhat[i * R + r] = xh[i];
+        /* R_ij += (x_i - x_j)^2 over every edge, visited from its upper entry */
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                int32_t j = col[p];
+                if (j <= i) continue;
+                double d = xh[i] - xh[j];
+                acc[eid[p]] += d * d;
+            }
+    }
+    for (int64_t e = 0; e < m; ++e) rho[e] = sqrt(acc[e]);
+    free(acc); free(x); free(xh);
+}
+
+/* delta_e = 1 / sqrt(rho_e^2 + eps) (Algorithm 1, return step). */
+void orc_strength(int64_t m, const double *rho, double eps, double *delta)
+{
+    for (int64_t e = 0; e < m; ++e) delta[e] = 1.0 / sqrt(rho[e] * rho[e] + eps);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sparsify (Algorithm 3).                                                   */
+
+/* Budget of a vertex of degree d: the top d^e neighbours, at least one. */
+int64_t orc_budget(int64_t d, double e)
+{
+    if (d <= 0) return 0;
+    double p = floor(pow((double)d, e));
+    int64_t c = (int64_t)p;
+    if (c < 1) c = 1;
+    if (c > d) c = d;
+    return c;
+}
+
+typedef struct { double rho; int32_t other; int32_t edge; } orc_item;
+
+static int orc_cmp_local(const void *a, const void *b)
+{
+    const orc_item *x = (const orc_item *)a, *y = (const orc_item *)b;
+    if (x->rho < y->rho) return -1;
+    if (x->rho > y->rho) return 1;
+    return (x->other > y->other) - (x->other < y->other);
+}
+
+static int orc_cmp_global(const void *a, const void *b)
+{
+    const orc_item *x = (const orc_item *)a, *y = (const orc_item *)b;
+    if (x->rho > y->rho) return -1;
+    if (x->rho < y->rho) return 1;
+    return (x->other > y->other) - (x->other < y->other);
+}
+
+/* For every vertex: sort N_i by rho (ascending for LOCAL = 0, descending
+ * for GLOBAL = 1), add the top c_i edges.  keep[m] receives 0/1; returns the
+ * number of kept edges.                                                      */
+int64_t orc_sparsify(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                     const int32_t *eid, const int32_t *orig_id, int64_t m,
+                     const double *rho, int32_t orient, double e, uint8_t *keep)
+{
+    memset(keep, 0, (size_t)m);
+#pragma omp parallel
+    {
+        orc_item *buf = NULL;
+        int64_t cap = 0;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
+            if (d == 0) continue;
+            if (d > cap) { free(buf); cap = d; buf = (orc_item *)malloc(sizeof(orc_item) * (size_t)cap); }
+            for (int64_t q = 0; q < d; ++q) {
+                int32_t j = col[beg + q];
+                buf[q].rho = rho[eid[beg + q]];
+                buf[q].other = orig_id ? orig_id[j] : j;
+                buf[q].edge = eid[beg + q];
+            }
+            qsort(buf, (size_t)d, sizeof(orc_item), orient == 0 ? orc_cmp_local : orc_cmp_global);
+            int64_t c = orc_budget(d, e);
+            for (int64_t q = 0; q < c; ++q) keep[buf[q].edge] = 1;   /* same value from any writer */
+        }
+        free(buf);
+    }
+    int64_t kept = 0;
+    for (int64_t q = 0; q < m; ++q) kept += keep[q];
+    return kept;
+}
+
+/* Binary-search fitting of e to a target retention ratio |E_s|/|E|. */
+double orc_fit_exponent(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                        const int32_t *eid, const int32_t *orig_id, int64_t m,
+                        const double *rho, int32_t orient, double target,
+                        uint8_t *keep, int64_t *n_kept)
+{
+    if (m == 0) { if (n_kept) *n_kept = 0; return 0.0; }
+    int64_t kept = orc_sparsify(n, row_ptr, col, eid, orig_id, m, rho, orient, 0.0, keep);
+    if ((double)kept / (double)m >= target) { if (n_kept) *n_kept = kept; return 0.0; }
+    double lo = 0.0, hi = 1.0;
+    for (int step = 0; step < 40; ++step) {
+        double mid = 0.5 * (lo + hi);
+        kept = orc_sparsify(n, row_ptr, col, eid, orig_id, m, rho, orient, mid, keep);
+        if ((double)kept / (double)m >= target) hi = mid; else lo = mid;
+    }
+    kept = orc_sparsify(n, row_ptr, col, eid, orig_id, m, rho, orient, hi, keep);
+    if (n_kept) *n_kept = kept;
+    return hi;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reverse-mode derivative of L = sum_e c_e rho_e with respect to the edge
+ * weights w_e (w_ij = w_ji = w_e), taken through the k sweeps, the rescale
+ * (its min and max as functions of x^(k)) and the distance.  Written by the
+ * chain rule from the forward steps above; one vector at a time, storing
+ * x^(0..k).  Start vectors do not depend on w.
+ *   c      : [m] weights of the loss.
+ *   grad_w : [m] output.                                                    */
+void orc_grad_weights(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                      const float *w, const int32_t *eid, const int32_t *orig_id,
+                      int64_t m, int32_t R, int32_t k, double omega, uint64_t seed,
+                      uint64_t graph_id, const double *x0, const double *c,
+                      double *grad_w)
+{
+    double *rho = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    double *xhat = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n * R : 1));
+    double *minmax = (double *)malloc(sizeof(double) * (size_t)(2 * R));
+    orc_algebraic_distance(n, row_ptr, col, w, eid, orig_id, m, R, k, omega, seed,
+                           graph_id, x0, rho, NULL, xhat, minmax);
+    double *s = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) acc += w ? (double)w[p] : 1.0;
+        s[i] = acc;
+    }
+    int64_t nnz = row_ptr[n];
+    double *g = (double *)calloc((size_t)(nnz > 0 ? nnz : 1), sizeof(double)); /* per directed entry */
+    double *trace = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(k + 1));
+    double *lam = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *lam_prev = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int32_t r = 0; r < R; ++r) {
+        /* forward again for this vector, keeping every sweep */
+        for (int64_t i = 0; i < n; ++i)
+            trace[i] = x0 ? x0[i * R + r]
+                          : orc_start_value(seed, graph_id, orig_id ? orig_id[i] : (int32_t)i, r);
+        double *xk = trace + (size_t)k * (size_t)n;
+        {
+            double *tmp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+            memcpy(tmp, trace, sizeof(double) * (size_t)n);
+            orc_relax_vector(n, row_ptr, col, w, k, omega, tmp, trace);
+            free(tmp);
+        }
+        double mn = minmax[r], mx = minmax[R + r];
+        for (int64_t i = 0; i < n; ++i) lam[i] = 0.0;
+        if (!(mx > mn)) continue;          /* xhat == 0: no dependence on w */
+        double D = mx - mn;
+        /* d rho_e / d xhat_i = (xhat_i - xhat_j) / rho_e  (0 when rho_e = 0) */
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                int32_t j = col[p];
+                double re = rho[eid[p]];
+                if (re > 0.0) lam[i] += c[eid[p]] * (xhat[i * R + r] - xhat[(int64_t)j * R + r]) / re;
+            }
+        /* rescale: xhat_i = (x_i - mn)/D - 1/2 over non-isolated vertices */
+        int64_t imin = -1, imax = -1;
+        for (int64_t i = 0; i < n; ++i) {
+            if (row_ptr[i + 1] == row_ptr[i]) continue;
+            if (imin < 0 || xk[i] < xk[imin]) imin = i;
+            if (imax < 0 || xk[i] > xk[imax]) imax = i;
+        }
+        double gmin = 0.0, gmax = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (row_ptr[i + 1] == row_ptr[i]) continue;
+            gmin += lam[i] * (xk[i] - mx) / (D * D);
+            gmax += -lam[i] * (xk[i] - mn) / (D * D);
+        }
+        for (int64_t i = 0; i < n; ++i)
+            lam[i] = (row_ptr[i + 1] == row_ptr[i]) ? 0.0 : lam[i] / D;
+        lam[imin] += gmin;
+        lam[imax] += gmax;
+        /* sweeps, last to first */
+        for (int32_t t = k; t >= 1; --t) {
+            const double *xp = trace + (size_t)(t - 1) * (size_t)n;
+            for (int64_t i = 0; i < n; ++i) {
+                int64_t beg = row_ptr[i], end = row_ptr[i + 1];
+                if (beg == end) continue;
+                double y = 0.0;
+                for (int64_t p = beg; p < end; ++p) y += (w ? (double)w[p] : 1.0) * xp[col[p]];
+                y /= s[i];
+                for (int64_t p = beg; p < end; ++p)
+                    g[p] += omega * lam[i] * (xp[col[p]] - y) / s[i];
+            }
+            for (int64_t i = 0; i < n; ++i) {
+                int64_t beg = row_ptr[i], end = row_ptr[i + 1];
+                if (beg == end) { lam_prev[i] = lam[i]; continue; }
+                double acc = 0.0;
+                for (int64_t p = beg; p < end; ++p) {
+                    int32_t j = col[p];
+                    acc += (w ? (double)w[p] : 1.0) * lam[j] / s[j];
+                }
+                lam_prev[i] = (1.0 - omega) * lam[i] + omega * acc;
+            }
+            memcpy(lam, lam_prev, sizeof(double) * (size_t)n);
+        }
+    }
+    for (int64_t e = 0; e < m; ++e) grad_w[e] = 0.0;
+    for (int64_t p = 0; p < nnz; ++p) grad_w[eid[p]] += g[p];
+    free(rho); free(xhat); free(minmax); free(s); free(g); free(trace); free(lam); free(lam_prev);
+}
