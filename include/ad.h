@@ -1,0 +1,232 @@
+/*
+ * ad.h -- C ABI of the MI355X (gfx950) algebraic-distance sparsification
+ * library (libad.so).
+ *
+ * The method (John & Safro, "Single- and Multi-level Network Sparsification
+ * by Algebraic Distance", arXiv 1601.05527):
+ *   Algorithm 1 (ComputeAlgDist): R random test vectors, k Jacobi
+ *     over-relaxation (JOR) sweeps each, a rescale of every vector back to
+ *     (-1/2, 1/2), and the per-edge L2 algebraic distance
+ *     rho_ij = sqrt(sum_r (xhat_i - xhat_j)^2); the paper's strength is
+ *     delta_ij = 1/sqrt(rho_ij^2 + eps), large for close (delta-strong) pairs.
+ *   Algorithm 3 (Sparsify): every vertex keeps its top d_i^e neighbours,
+ *     ranked by delta ascending or descending; the sparse graph is the union.
+ *   Section 6.2: e is fitted by binary search to a target retention ratio.
+ *
+ * Conventions for every call below.
+ *   - Pointers are DEVICE pointers unless the name ends in _host.
+ *   - The caller owns every buffer.  The library reads/writes them only from
+ *     work enqueued on the caller's stream and never keeps them after that
+ *     work completes.  No call allocates or frees device memory; scratch
+ *     space comes from the caller's workspace `ws` of `ws_bytes` bytes (at
+ *     least what the matching *_workspace_size call returns, 256-byte
+ *     aligned).
+ *   - Calls only enqueue work on `stream` and return, except where a call
+ *     says it synchronises.
+ *   - Errors: host-side argument checks return AD_ERR_INVALID_ARG,
+ *     AD_ERR_UNSUPPORTED or AD_ERR_WORKSPACE before any work is enqueued; a
+ *     failed HIP launch or copy returns AD_ERR_HIP.  ad_last_error() gives a
+ *     thread-local message for the last failure.  No C++ exception crosses
+ *     this boundary.  The library does not check the graph's structure on
+ *     the device except in ad_validate_graph.
+ *   - Calls that share a workspace must not overlap (same stream, or
+ *     ordered by the caller).
+ */
+#ifndef AD_H
+#define AD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AD_OK = 0,
+    AD_ERR_INVALID_ARG = 1,   /* a null pointer, a size or a parameter out of range  */
+    AD_ERR_UNSUPPORTED = 2,   /* a valid but unimplemented combination               */
+    AD_ERR_WORKSPACE = 3,     /* ws too small or misaligned                          */
+    AD_ERR_GRAPH = 4,         /* ad_validate_graph found a structural defect         */
+    AD_ERR_HIP = 5,           /* a HIP runtime call failed                           */
+    AD_ERR_INTERNAL = 6       /* an internal consistency check failed                */
+} ad_status;
+
+typedef enum { AD_F64 = 0, AD_F32 = 1, AD_BF16 = 2 } ad_dtype;
+
+/* Orientation of the per-vertex ranking (Algorithm 3 sorts N_i by delta in
+ * ascending or descending order; Section 4 names the two uses):
+ *   AD_LOCAL  keeps the delta-strong edges = smallest rho first
+ *             ("preserve local structure");
+ *   AD_GLOBAL keeps the delta-weak edges   = largest rho first
+ *             ("preserve global structure").
+ * Ties in rho go to the neighbour with the smaller orig_id in both. */
+typedef enum { AD_LOCAL = 0, AD_GLOBAL = 1 } ad_orient;
+
+/* Symmetric CSR of an undirected simple weighted graph G = (V, E, w)
+ * (Preliminaries: undirected, no self-loops, no multi-edges, w >= 0; this
+ * library requires finite w > 0 so that every non-isolated vertex has a
+ * positive weighted degree). */
+typedef struct {
+    int64_t n;                /* |V|                                                   */
+    int64_t m;                /* |E|, undirected edges; row_ptr[n] == 2m              */
+    const int64_t *row_ptr;   /* [n+1]                                                 */
+    const int32_t *col;       /* [2m] neighbour of each stored entry                   */
+    const float *w;           /* [2m] w_ij == w_ji; NULL means unit weights            */
+    const int32_t *eid;       /* [2m] undirected edge id in [0, m); (i,j) and (j,i)
+                                 share it                                              */
+    const int32_t *orig_id;   /* [n] vertex id before any relabelling (keys the random
+                                 start vectors, breaks ranking ties); NULL = identity  */
+    int32_t d_max;            /* host value: maximum degree (selection calls need it) */
+} ad_graph;
+
+/* Parameters of Algorithm 1's relaxation. */
+typedef struct {
+    int32_t R;                /* test vectors, 1..64                                   */
+    int32_t k;                /* JOR sweeps, >= 0                                      */
+    double omega;             /* weight on the neighbour average, (0, 1]; the paper's
+                                 alpha (weight on the old value) is 1 - omega          */
+    uint64_t seed;            /* Philox key word 0                                     */
+    uint64_t graph_id;        /* Philox key word 1                                     */
+    ad_dtype store;           /* AD_F64: FP64 storage and arithmetic.
+                                 AD_F32: FP32 storage and arithmetic.
+                                 AD_BF16: FP32 arithmetic; sweeps 1..k-fp32_tail are
+                                 stored in BF16 (round to nearest even), x^(0) and the
+                                 last fp32_tail sweeps in FP32                         */
+    int32_t fp32_tail;        /* AD_BF16 only: number of final sweeps stored in FP32
+                                 (>= 1)                                                */
+    int32_t ckpt_every;       /* 0: no checkpoints.  c > 0: write x^(0), x^(c),
+                                 x^(2c), ... (every t = q*c < k) to `ckpt` for
+                                 ad_relax_backward                                     */
+    int32_t rows_per_wave;    /* launch shape, 0 = automatic: rows sharing one 64-lane
+                                 wave (power of two); results do not depend on it
+                                 except through FP summation order                     */
+    int32_t hub_degree;       /* launch shape, 0 = automatic: rows with more neighbours
+                                 get a 256-thread workgroup each                       */
+} ad_relax_opts;
+
+/* ---------------------------------------------------------------- relax -- */
+
+/* Workspace bytes for ad_relax on this graph and these options. */
+size_t ad_relax_workspace_size(const ad_graph *g, const ad_relax_opts *o);
+
+/* Number of checkpoint slots ad_relax writes: ceil(k / ckpt_every), or 0. */
+int32_t ad_relax_num_checkpoints(const ad_relax_opts *o);
+
+/* Algorithm 1, relaxation part: the start vectors and k JOR sweeps
+ *     x_i^(t) = (1 - omega) x_i^(t-1) + omega * sum_j w_ij x_j^(t-1) / sum_j w_ij
+ * (isolated vertices keep their value), followed by the min and max of each
+ * vector over the non-isolated vertices, which define the rescale
+ *     xhat = (x - min) / (max - min) - 1/2   (0 when max == min).
+ *
+ * Start vectors: x0 == NULL draws x_i^(0) for vector r as word (r % 4) of
+ * Philox4x64-10(key = (seed, graph_id), counter = (orig_id[i], r / 4, 0, 0)),
+ * shifted right by 40 bits, times 2^-24, minus 1/2 -- uniform on the 2^24
+ * grid in [-1/2, 1/2).  Otherwise x0 holds [n][R] start values (FP64 when
+ * store == AD_F64, else FP32).
+ *
+ * Outputs:
+ *   x_out      [n][R] row-major, FP64 when store == AD_F64, else FP32.  It holds
+ *              x^(k) - shift_r, where shift_r is a per-vector constant (the
+ *              weighted mean sum_i s_i x_i^(0) / sum_i s_i rounded to a multiple
+ *              of 2^-24).  The sweeps preserve any constant vector, so this is
+ *              x^(k) exactly up to rounding, and min/max/xhat refer to it.
+ *   minmax_out [2R] doubles: min_r then max_r of x_out over non-isolated vertices.
+ *   shift_out  [R] doubles or NULL: the shifts above.
+ *   ckpt       NULL, or [ad_relax_num_checkpoints][n][R] in x_out's type:
+ *              the (shifted) x^(0), x^(c), x^(2c), ...
+ * x_out must not alias x0 or ckpt. */
+ad_status ad_relax(const ad_graph *g, const ad_relax_opts *o, const void *x0,
+                   void *x_out, double *minmax_out, double *shift_out, void *ckpt,
+                   void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------- distance -- */
+
+/* Algorithm 1, distance part: for every undirected edge e = (i, j)
+ *     rho_e = sqrt( sum_r ((x_i,r - x_j,r) / (max_r - min_r))^2 ),
+ * i.e. the L2 distance of the rescaled vectors (a vector with max_r == min_r
+ * contributes 0).  x: [n][R] in x_dtype (AD_F64 or AD_F32), as written by
+ * ad_relax; minmax: [2R] doubles as written by ad_relax.  rho: [m], FP64
+ * when x_dtype == AD_F64, else FP32.  No workspace. */
+ad_status ad_edge_dist(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
+                       const double *minmax, void *rho, hipStream_t stream);
+
+/* ------------------------------------------------------------ selection -- */
+
+/* Host helper: the per-vertex budget of Algorithm 3 for every degree,
+ *     budget_host[d] = min(d, max(1, floor(pow(d, e)))),  budget_host[0] = 0,
+ * for d = 0..d_max, with the C library's double pow.  e in [0, 1]. */
+ad_status ad_budget_table(int32_t d_max, double e, int32_t *budget_host);
+
+/* Workspace bytes for ad_sparsify / ad_sparsify_fit. */
+size_t ad_sparsify_workspace_size(const ad_graph *g);
+
+/* Algorithm 3 at a fixed exponent: every vertex i ranks its neighbours by
+ * (rho ascending for AD_LOCAL, descending for AD_GLOBAL; then neighbour
+ * orig_id ascending) and selects the first budget[d_i]; keep[e] = 1 when
+ * either endpoint selects edge e, else 0.  rho: [m] in rho_dtype (AD_F64 or
+ * AD_F32).  budget: DEVICE copy of ad_budget_table's [d_max+1] (or any
+ * budget with budget[d] in [0, d]).  n_kept: device int64, receives sum(keep).
+ */
+ad_status ad_sparsify(const ad_graph *g, ad_dtype rho_dtype, const void *rho,
+                      ad_orient orient, const int32_t *budget, uint8_t *keep,
+                      int64_t *n_kept, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Algorithm 3 with e fitted to a retention target (Section 6.2's binary
+ * search): returns, through e_used_host, the value the bisection
+ *     lo = 0, hi = 1; if ratio(0) >= target return 0;
+ *     40 times: mid = (lo + hi) / 2; ratio(mid) >= target ? hi = mid : lo = mid;
+ *     return hi
+ * returns, with ratio(e) = (edges kept at e) / m, and writes keep and n_kept
+ * at that e.  target in (0, 1].  With m == 0 it returns e = 0.
+ * SYNCHRONISES `stream` (the fit reads counts back to the host). */
+ad_status ad_sparsify_fit(const ad_graph *g, ad_dtype rho_dtype, const void *rho,
+                          ad_orient orient, double target, uint8_t *keep,
+                          int64_t *n_kept, double *e_used_host, void *ws,
+                          size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------- adjoint --- */
+
+/* Workspace bytes for ad_relax_backward. */
+size_t ad_relax_backward_workspace_size(const ad_graph *g, const ad_relax_opts *o);
+
+/* Reverse-mode derivative of a loss L(rho) with respect to the edge weights,
+ * through ad_edge_dist, the rescale and the k sweeps of ad_relax (start
+ * vectors do not depend on w).  Requires store == AD_F32 and ckpt_every > 0.
+ *   ckpt     : checkpoints written by ad_relax with the same graph and opts.
+ *   x_k      : x_out of that ad_relax call; minmax: its minmax_out.
+ *   grad_rho : [m] FP32, dL/drho_e.
+ *   grad_w   : [m] FP32 output, dL/dw_e with w_ij = w_ji = w_e.
+ * The min and max of the rescale are differentiated at the first vertex
+ * attaining them; edges with rho_e == 0 pass no gradient. */
+ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o, const void *ckpt,
+                            const void *x_k, const double *minmax, const float *grad_rho,
+                            float *grad_w, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Edge weights to CSR order: w_entries[p] = w_edge[eid[p]] for p < 2m (the
+ * layout ad_relax reads; used when the weights are the variables of the
+ * adjoint).  w_edge: [m] FP32, w_entries: [2m] FP32. */
+ad_status ad_edge_to_entries(const ad_graph *g, const float *w_edge, float *w_entries,
+                             hipStream_t stream);
+
+/* ---------------------------------------------------------- diagnostics -- */
+
+/* Checks on the device that the CSR is a valid symmetric simple graph:
+ * sorted columns in range, no self-loops or repeats, every (i,j) has its
+ * mirror (j,i) with the same eid and weight, eids in [0, m) used exactly
+ * twice, weights finite and > 0.  SYNCHRONISES `stream`.  Returns AD_OK or
+ * AD_ERR_GRAPH (message in ad_last_error()).  ws: ad_validate_workspace_size. */
+size_t ad_validate_workspace_size(const ad_graph *g);
+ad_status ad_validate_graph(const ad_graph *g, void *ws, size_t ws_bytes, hipStream_t stream);
+
+const char *ad_status_string(ad_status s);
+const char *ad_last_error(void);
+int32_t ad_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AD_H */

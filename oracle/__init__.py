@@ -5,7 +5,7 @@ CPU-baseline leg import this package; the library never does, and this
 package imports nothing from the library.  Every function here is a thin
 ctypes wrapper around the C oracle, which follows the paper's Algorithm 1
 (ComputeAlgDist), Algorithm 3 (Sparsify) and the binary-search fitting of
-Section 7.2 in double precision.
+Section 6.2 in double precision.
 
 Parity status: every function is pinned by tests that do not reuse its own
 formulas (closed forms, library routines, brute force); the one reading

@@ -41,7 +41,7 @@
  *     either endpoint selects it (Algorithm 3);
  *   - retention fit: bisection on e in [0, 1], 40 halvings, returning the
  *     smallest e found whose retained fraction reaches the target (the
- *     binary-search fitting of Section 7.2).
+ *     binary-search fitting of Section 6.2).
  */
 #include <math.h>
 #include <stdint.h>

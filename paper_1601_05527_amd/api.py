@@ -1,0 +1,343 @@
+"""Python binding of libad (the C ABI in ``include/ad.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Tensors live on the current HIP device; calls are enqueued on
+``torch.cuda.current_stream()``.  Importing this module loads ``libad.so``
+and raises if it has not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import graphs as _graphs
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libad.so")
+
+AD_F64, AD_F32, AD_BF16 = 0, 1, 2
+AD_LOCAL, AD_GLOBAL = 0, 1
+_DTYPES = {"f64": AD_F64, "f32": AD_F32, "bf16": AD_BF16}
+_STATUS = {0: "AD_OK", 1: "AD_ERR_INVALID_ARG", 2: "AD_ERR_UNSUPPORTED", 3: "AD_ERR_WORKSPACE",
+           4: "AD_ERR_GRAPH", 5: "AD_ERR_HIP", 6: "AD_ERR_INTERNAL"}
+
+
+class ADGraph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("eid", ctypes.c_void_p),
+                ("orig_id", ctypes.c_void_p), ("d_max", ctypes.c_int32)]
+
+
+class ADRelaxOpts(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int32), ("k", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("graph_id", ctypes.c_uint64), ("store", ctypes.c_int),
+                ("fp32_tail", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
+                ("rows_per_wave", ctypes.c_int32), ("hub_degree", ctypes.c_int32)]
+
+
+class ADError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load_lib():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1601_05527_amd.build_lib")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, S = ctypes.c_void_p, ctypes.c_size_t
+    G = ctypes.POINTER(ADGraph)
+    O = ctypes.POINTER(ADRelaxOpts)
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    st = ctypes.c_int
+    sig = {
+        "ad_relax_workspace_size": (S, [G, O]),
+        "ad_relax_num_checkpoints": (i32, [O]),
+        "ad_relax": (st, [G, O, P, P, P, P, P, P, S, P]),
+        "ad_edge_dist": (st, [G, i32, ctypes.c_int, P, P, P, P]),
+        "ad_budget_table": (st, [i32, f64, P]),
+        "ad_sparsify_workspace_size": (S, [G]),
+        "ad_sparsify": (st, [G, ctypes.c_int, P, ctypes.c_int, P, P, P, P, S, P]),
+        "ad_sparsify_fit": (st, [G, ctypes.c_int, P, ctypes.c_int, f64, P, P, P, P, S, P]),
+        "ad_relax_backward_workspace_size": (S, [G, O]),
+        "ad_relax_backward": (st, [G, O, P, P, P, P, P, P, S, P]),
+        "ad_edge_to_entries": (st, [G, P, P, P]),
+        "ad_validate_workspace_size": (S, [G]),
+        "ad_validate_graph": (st, [G, P, S, P]),
+        "ad_status_string": (ctypes.c_char_p, [st]),
+        "ad_last_error": (ctypes.c_char_p, []),
+        "ad_abi_version": (i32, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load_lib()
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise ADError(status, lib.ad_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns 256-byte-aligned blocks; check anyway.
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        raise ADError(3, "workspace allocation is not 256-byte aligned")
+    return ws
+
+
+# ---------------------------------------------------------------- graphs ---
+
+@dataclass
+class DeviceGraph:
+    """A symmetric CSR resident on the device, plus the ABI struct."""
+
+    n: int
+    m: int
+    d_max: int
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    w: Optional[torch.Tensor]
+    eid: torch.Tensor
+    orig_id: Optional[torch.Tensor]
+    host: Optional[_graphs.Graph] = None
+
+    @classmethod
+    def from_host(cls, g: _graphs.Graph, device="cuda", keep_host: bool = True) -> "DeviceGraph":
+        dev = torch.device(device)
+
+        def t(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
+
+        return cls(n=g.n, m=g.m, d_max=g.d_max,
+                   row_ptr=t(g.row_ptr, np.int64), col=t(g.col, np.int32),
+                   w=None if g.w is None else t(g.w, np.float32),
+                   eid=t(g.eid, np.int32), orig_id=t(g.orig_id, np.int32),
+                   host=g if keep_host else None)
+
+    @property
+    def device(self):
+        return self.row_ptr.device
+
+    def abi(self) -> ADGraph:
+        return ADGraph(self.n, self.m, self.row_ptr.data_ptr(),
+                       self.col.data_ptr() if self.col.numel() else None,
+                       None if self.w is None else self.w.data_ptr(),
+                       self.eid.data_ptr() if self.eid.numel() else None,
+                       None if self.orig_id is None else self.orig_id.data_ptr(),
+                       self.d_max)
+
+    def with_weights(self, w_entries: Optional[torch.Tensor]) -> "DeviceGraph":
+        return DeviceGraph(self.n, self.m, self.d_max, self.row_ptr, self.col, w_entries,
+                           self.eid, self.orig_id, self.host)
+
+
+def validate_graph(dg: DeviceGraph) -> None:
+    """Structural check of the CSR on the device (synchronises)."""
+    g = dg.abi()
+    ws = _workspace(lib.ad_validate_workspace_size(ctypes.byref(g)), dg.device)
+    _check(lib.ad_validate_graph(ctypes.byref(g), _ptr(ws), ws.numel(), _stream()))
+
+
+# ----------------------------------------------------------------- relax ---
+
+@dataclass
+class RelaxResult:
+    x: torch.Tensor          # [n, R] x^(k) minus the per-vector shift
+    minmax: torch.Tensor     # [2R] float64
+    shift: torch.Tensor      # [R] float64
+    ckpt: Optional[torch.Tensor]
+    store: str
+
+
+def relax_opts(R: int, k: int, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
+               store: str = "f32", fp32_tail: int = 2, ckpt_every: int = 0,
+               rows_per_wave: int = 0, hub_degree: int = 0) -> ADRelaxOpts:
+    return ADRelaxOpts(R, k, omega, seed, graph_id, _DTYPES[store], fp32_tail, ckpt_every,
+                       rows_per_wave, hub_degree)
+
+
+def relax_workspace_bytes(dg: DeviceGraph, opts: ADRelaxOpts) -> int:
+    g = dg.abi()
+    return int(lib.ad_relax_workspace_size(ctypes.byref(g), ctypes.byref(opts)))
+
+
+def relax(dg: DeviceGraph, R: int, k: int, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
+          store: str = "f32", x0: Optional[torch.Tensor] = None, fp32_tail: int = 2,
+          ckpt_every: int = 0, rows_per_wave: int = 0, hub_degree: int = 0,
+          ws: Optional[torch.Tensor] = None, out: Optional[RelaxResult] = None) -> RelaxResult:
+    """Start vectors + k JOR sweeps + rescale statistics (``ad_relax``)."""
+    opts = relax_opts(R, k, omega, seed, graph_id, store, fp32_tail, ckpt_every, rows_per_wave,
+                      hub_degree)
+    g = dg.abi()
+    dev = dg.device
+    xdt = torch.float64 if store == "f64" else torch.float32
+    if out is None:
+        nck = int(lib.ad_relax_num_checkpoints(ctypes.byref(opts)))
+        out = RelaxResult(
+            x=torch.empty((dg.n, R), dtype=xdt, device=dev),
+            minmax=torch.empty(2 * R, dtype=torch.float64, device=dev),
+            shift=torch.empty(R, dtype=torch.float64, device=dev),
+            ckpt=torch.empty((nck, dg.n, R), dtype=xdt, device=dev) if nck else None,
+            store=store)
+    if x0 is not None:
+        if x0.dtype != xdt or tuple(x0.shape) != (dg.n, R) or not x0.is_contiguous():
+            raise ValueError("x0 must be a contiguous [n, R] tensor of the storage dtype")
+    if ws is None:
+        ws = _workspace(lib.ad_relax_workspace_size(ctypes.byref(g), ctypes.byref(opts)), dev)
+    _check(lib.ad_relax(ctypes.byref(g), ctypes.byref(opts), _ptr(x0), _ptr(out.x), _ptr(out.minmax),
+                        _ptr(out.shift), _ptr(out.ckpt), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+# -------------------------------------------------------------- distance ---
+
+def edge_dist(dg: DeviceGraph, x: torch.Tensor, minmax: torch.Tensor,
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """rho[m] = L2 distance of the rescaled vectors (``ad_edge_dist``)."""
+    R = x.shape[1]
+    dt = AD_F64 if x.dtype == torch.float64 else AD_F32
+    if out is None:
+        out = torch.empty(dg.m, dtype=x.dtype, device=x.device)
+    g = dg.abi()
+    _check(lib.ad_edge_dist(ctypes.byref(g), R, dt, _ptr(x), _ptr(minmax), _ptr(out), _stream()))
+    return out
+
+
+# ------------------------------------------------------------- selection ---
+
+def budget_table(d_max: int, e: float) -> np.ndarray:
+    out = np.zeros(d_max + 1, dtype=np.int32)
+    _check(lib.ad_budget_table(d_max, float(e), out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def sparsify_workspace_bytes(dg: DeviceGraph) -> int:
+    g = dg.abi()
+    return int(lib.ad_sparsify_workspace_size(ctypes.byref(g)))
+
+
+def sparsify(dg: DeviceGraph, rho: torch.Tensor, orient: int, e: Optional[float] = None,
+             budget: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+             keep: Optional[torch.Tensor] = None, n_kept: Optional[torch.Tensor] = None):
+    """Algorithm 3 at a fixed exponent (``ad_sparsify``); returns (keep, n_kept)."""
+    dev = rho.device
+    if budget is None:
+        budget = torch.from_numpy(budget_table(dg.d_max, e)).to(dev)
+    g = dg.abi()
+    if ws is None:
+        ws = _workspace(lib.ad_sparsify_workspace_size(ctypes.byref(g)), dev)
+    if keep is None:
+        keep = torch.empty(dg.m, dtype=torch.uint8, device=dev)
+    if n_kept is None:
+        n_kept = torch.empty(1, dtype=torch.int64, device=dev)
+    dt = AD_F64 if rho.dtype == torch.float64 else AD_F32
+    _check(lib.ad_sparsify(ctypes.byref(g), dt, _ptr(rho), orient, _ptr(budget), _ptr(keep), _ptr(n_kept),
+                           _ptr(ws), ws.numel(), _stream()))
+    return keep, n_kept
+
+
+def sparsify_fit(dg: DeviceGraph, rho: torch.Tensor, orient: int, target: float,
+                 ws: Optional[torch.Tensor] = None, keep: Optional[torch.Tensor] = None,
+                 n_kept: Optional[torch.Tensor] = None):
+    """Algorithm 3 with e fitted to a retention target (``ad_sparsify_fit``);
+    returns (keep, n_kept, e).  Synchronises the current stream."""
+    dev = rho.device
+    g = dg.abi()
+    if ws is None:
+        ws = _workspace(lib.ad_sparsify_workspace_size(ctypes.byref(g)), dev)
+    if keep is None:
+        keep = torch.empty(dg.m, dtype=torch.uint8, device=dev)
+    if n_kept is None:
+        n_kept = torch.empty(1, dtype=torch.int64, device=dev)
+    e_used = ctypes.c_double(-1.0)
+    dt = AD_F64 if rho.dtype == torch.float64 else AD_F32
+    _check(lib.ad_sparsify_fit(ctypes.byref(g), dt, _ptr(rho), orient, float(target), _ptr(keep),
+                               _ptr(n_kept), ctypes.byref(e_used), _ptr(ws), ws.numel(), _stream()))
+    return keep, n_kept, e_used.value
+
+
+# --------------------------------------------------------------- adjoint ---
+
+def relax_backward(dg: DeviceGraph, res: RelaxResult, R: int, k: int, grad_rho: torch.Tensor,
+                   omega: float = 0.5, seed: int = 0, graph_id: int = 0, ckpt_every: int = 5,
+                   ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dL/dw_e given dL/drho_e (``ad_relax_backward``)."""
+    opts = relax_opts(R, k, omega, seed, graph_id, "f32", 2, ckpt_every)
+    g = dg.abi()
+    if ws is None:
+        ws = _workspace(lib.ad_relax_backward_workspace_size(ctypes.byref(g), ctypes.byref(opts)), dg.device)
+    if out is None:
+        out = torch.empty(dg.m, dtype=torch.float32, device=dg.device)
+    _check(lib.ad_relax_backward(ctypes.byref(g), ctypes.byref(opts), _ptr(res.ckpt), _ptr(res.x),
+                                 _ptr(res.minmax), _ptr(grad_rho), _ptr(out), _ptr(ws), ws.numel(),
+                                 _stream()))
+    return out
+
+
+def edge_to_entries(dg: DeviceGraph, w_edge: torch.Tensor) -> torch.Tensor:
+    """CSR-order weights w_entries[p] = w_edge[eid[p]] (``ad_edge_to_entries``)."""
+    out = torch.empty(2 * dg.m, dtype=torch.float32, device=w_edge.device)
+    g = dg.abi()
+    _check(lib.ad_edge_to_entries(ctypes.byref(g), _ptr(w_edge.contiguous()), _ptr(out), _stream()))
+    return out
+
+
+class AlgDist(torch.autograd.Function):
+    """rho = AlgDist.apply(w_edge, dg, R, k, omega, seed, ckpt_every).
+
+    Forward: ad_relax (FP32, checkpoints every ``ckpt_every`` sweeps) and
+    ad_edge_dist with the edge weights ``w_edge`` [m].  Backward:
+    ad_relax_backward gives dL/dw_e from dL/drho_e."""
+
+    @staticmethod
+    def forward(ctx, w_edge, dg, R, k, omega=0.5, seed=0, ckpt_every=5):
+        w_edge = w_edge.detach().contiguous().float()
+        dgw = dg.with_weights(edge_to_entries(dg, w_edge))
+        res = relax(dgw, R, k, omega, seed, store="f32", ckpt_every=ckpt_every)
+        rho = edge_dist(dgw, res.x, res.minmax)
+        ctx.dgw, ctx.res = dgw, res
+        ctx.args = (R, k, omega, seed, ckpt_every)
+        return rho
+
+    @staticmethod
+    def backward(ctx, grad_rho):
+        R, k, omega, seed, ckpt_every = ctx.args
+        gw = relax_backward(ctx.dgw, ctx.res, R, k, grad_rho.contiguous().float(), omega, seed,
+                            ckpt_every=ckpt_every)
+        return gw, None, None, None, None, None, None
+
+
+# ------------------------------------------------------------ whole path ---
+
+def sparsify_graph(dg: DeviceGraph, R: int, k: int, orient: int, e: Optional[float] = None,
+                   target: Optional[float] = None, omega: float = 0.5, seed: int = 0,
+                   store: str = "f32"):
+    """Algorithm 1 then Algorithm 3 on one graph.  Returns a dict with rho,
+    keep, n_kept and the exponent used."""
+    res = relax(dg, R, k, omega, seed, store=store)
+    rho = edge_dist(dg, res.x, res.minmax)
+    if target is not None:
+        keep, n_kept, e_used = sparsify_fit(dg, rho, orient, target)
+    else:
+        keep, n_kept = sparsify(dg, rho, orient, e)
+        e_used = e
+    return {"rho": rho, "keep": keep, "n_kept": n_kept, "e": e_used, "relax": res}

@@ -1,0 +1,231 @@
+// ad_common.hip -- error state, status strings, fills, row collection and
+// graph validation for libad.
+#include "ad_internal.h"
+
+#include <math.h>
+#include <stdio.h>
+
+namespace ad {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+ad_status fail(ad_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+ad_status hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return AD_ERR_HIP;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+ad_status fill_u64(unsigned long long *p, unsigned long long v, int64_t count, hipStream_t s) {
+    if (count <= 0) return AD_OK;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256)), dim3(256), 0, s, p, v, count);
+    AD_LAUNCH_CHECK("k_fill_u64");
+    return AD_OK;
+}
+ad_status fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s) {
+    if (count <= 0) return AD_OK;
+    // 16 bytes per thread when aligned
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(count, 256)), dim3(256), 0, s, p, v, count);
+    AD_LAUNCH_CHECK("k_fill_u8");
+    return AD_OK;
+}
+ad_status fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s) {
+    if (count <= 0) return AD_OK;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count, 256)), dim3(256), 0, s, p, v, count);
+    AD_LAUNCH_CHECK("k_fill_i32");
+    return AD_OK;
+}
+
+__global__ void k_collect_rows(int64_t n, const int64_t *__restrict__ row_ptr, int64_t lo,
+                               int64_t hi, int32_t *__restrict__ list, unsigned int *count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t d = row_ptr[i + 1] - row_ptr[i];
+        if (d > lo && d <= hi) {
+            unsigned int at = atomicAdd(count, 1u);
+            list[at] = (int32_t)i;
+        }
+    }
+}
+
+ad_status collect_rows(const ad_graph *g, int64_t lo, int64_t hi, int32_t *list,
+                       unsigned int *count, hipStream_t s) {
+    if (g->n <= 0) return AD_OK;
+    hipLaunchKernelGGL(k_collect_rows, dim3(grid_for(g->n, 256)), dim3(256), 0, s, g->n,
+                       g->row_ptr, lo, hi, list, count);
+    AD_LAUNCH_CHECK("k_collect_rows");
+    return AD_OK;
+}
+
+ad_status check_graph_args(const ad_graph *g) {
+    if (!g) return fail(AD_ERR_INVALID_ARG, "graph is NULL");
+    if (g->n < 0 || g->m < 0) return fail(AD_ERR_INVALID_ARG, "negative n or m");
+    if (g->n > 0x7fffffffLL) return fail(AD_ERR_UNSUPPORTED, "n must fit in int32");
+    if (g->m > 0x7fffffffLL) return fail(AD_ERR_UNSUPPORTED, "m must fit in int32");
+    if (!g->row_ptr) return fail(AD_ERR_INVALID_ARG, "row_ptr is NULL");
+    if (g->m > 0 && (!g->col || !g->eid)) return fail(AD_ERR_INVALID_ARG, "col or eid is NULL");
+    if (g->d_max < 0) return fail(AD_ERR_INVALID_ARG, "negative d_max");
+    return AD_OK;
+}
+
+// ---------------------------------------------------------------- validate --
+
+// Flags: 1 col out of range, 2 self-loop, 4 unsorted/repeat, 8 no mirror,
+// 16 mirror eid/weight mismatch, 32 bad weight, 64 eid out of range,
+// 128 eid not used exactly twice, 256 row_ptr inconsistent, 512 degree > d_max.
+__global__ void k_validate_rows(int64_t n, const int64_t *__restrict__ row_ptr,
+                                const int32_t *__restrict__ col, const float *__restrict__ w,
+                                const int32_t *__restrict__ eid, int64_t m, int32_t d_max,
+                                unsigned int *__restrict__ eid_uses, unsigned int *flags) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t b = row_ptr[i], e = row_ptr[i + 1];
+        unsigned f = 0;
+        if (e < b) { atomicOr(flags, 256u); continue; }
+        if (e - b > d_max) f |= 512u;
+        for (int64_t p = b; p < e; ++p) {
+            int32_t j = col[p];
+            if (j < 0 || j >= n) { f |= 1u; continue; }
+            if (j == i) f |= 2u;
+            if (p > b && col[p - 1] >= j) f |= 4u;
+            if (w && !(isfinite(w[p]) && w[p] > 0.f)) f |= 32u;
+            int32_t id = eid[p];
+            if (id < 0 || id >= m) { f |= 64u; continue; }
+            atomicAdd(&eid_uses[id], 1u);
+            // binary search for i in row j
+            int64_t lo = row_ptr[j], hi = row_ptr[j + 1] - 1;
+            int64_t found = -1;
+            while (lo <= hi) {
+                int64_t mid = (lo + hi) >> 1;
+                int32_t c = col[mid];
+                if (c == (int32_t)i) { found = mid; break; }
+                if (c < (int32_t)i) lo = mid + 1; else hi = mid - 1;
+            }
+            if (found < 0) f |= 8u;
+            else if (eid[found] != id || (w && w[found] != w[p])) f |= 16u;
+        }
+        if (f) atomicOr(flags, f);
+    }
+}
+
+// Structure of row_ptr alone: 0 <= row_ptr[i] <= row_ptr[i+1] <= nnz.
+__global__ void k_validate_rowptr(int64_t n, const int64_t *__restrict__ row_ptr, int64_t nnz,
+                                  unsigned int *flags) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t b = row_ptr[i], e = row_ptr[i + 1];
+        if (b < 0 || e < b || e > nnz) atomicOr(flags, 256u);
+    }
+}
+
+__global__ void k_validate_eids(int64_t m, const unsigned int *__restrict__ eid_uses,
+                                unsigned int *flags) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m;
+         q += (int64_t)gridDim.x * blockDim.x)
+        if (eid_uses[q] != 2u) atomicOr(flags, 128u);
+}
+
+}  // namespace ad
+
+using namespace ad;
+
+extern "C" size_t ad_validate_workspace_size(const ad_graph *g) {
+    if (!g) return 0;
+    Carver c(nullptr, 0);
+    c.take<unsigned int>(g->m > 0 ? g->m : 1);
+    c.take<unsigned int>(1);
+    return c.used;
+}
+
+extern "C" ad_status ad_validate_graph(const ad_graph *g, void *ws, size_t ws_bytes,
+                                       hipStream_t stream) {
+    ad_status st = check_graph_args(g);
+    if (st != AD_OK) return st;
+    if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    Carver c(ws, ws_bytes);
+    unsigned int *uses = c.take<unsigned int>(g->m > 0 ? g->m : 1);
+    unsigned int *flags = c.take<unsigned int>(1);
+    if (!c.ok()) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    int64_t rp[2] = {0, 0};
+    if (g->n >= 0) {
+        AD_HIP(hipMemcpyAsync(&rp[0], g->row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        AD_HIP(hipMemcpyAsync(&rp[1], g->row_ptr + g->n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        AD_HIP(hipStreamSynchronize(stream));
+    }
+    if (rp[0] != 0 || rp[1] != 2 * g->m)
+        return fail(AD_ERR_GRAPH, "row_ptr[0] != 0 or row_ptr[n] != 2m");
+    st = fill_i32((int32_t *)uses, 0, g->m, stream);
+    if (st != AD_OK) return st;
+    st = fill_i32((int32_t *)flags, 0, 1, stream);
+    if (st != AD_OK) return st;
+    if (g->n > 0) {
+        // row_ptr first: the per-row pass below reads col[] through it.
+        hipLaunchKernelGGL(k_validate_rowptr, dim3(grid_for(g->n, 256)), dim3(256), 0, stream,
+                           g->n, g->row_ptr, 2 * g->m, flags);
+        AD_LAUNCH_CHECK("k_validate_rowptr");
+        unsigned int rflags = 0;
+        AD_HIP(hipMemcpyAsync(&rflags, flags, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
+        AD_HIP(hipStreamSynchronize(stream));
+        if (rflags) return fail(AD_ERR_GRAPH, "invalid graph: row_ptr not monotone within [0, 2m];");
+        hipLaunchKernelGGL(k_validate_rows, dim3(grid_for(g->n, 256)), dim3(256), 0, stream, g->n,
+                           g->row_ptr, g->col, g->w, g->eid, g->m, g->d_max, uses, flags);
+        AD_LAUNCH_CHECK("k_validate_rows");
+    }
+    if (g->m > 0) {
+        hipLaunchKernelGGL(k_validate_eids, dim3(grid_for(g->m, 256)), dim3(256), 0, stream, g->m,
+                           uses, flags);
+        AD_LAUNCH_CHECK("k_validate_eids");
+    }
+    unsigned int hflags = 0;
+    AD_HIP(hipMemcpyAsync(&hflags, flags, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
+    AD_HIP(hipStreamSynchronize(stream));
+    if (hflags == 0) return AD_OK;
+    static const char *names[] = {"column out of range", "self-loop", "columns unsorted or repeated",
+                                  "missing mirror entry", "mirror eid or weight differs",
+                                  "weight not finite and > 0", "eid out of range",
+                                  "eid not used exactly twice", "row_ptr decreasing",
+                                  "degree above d_max"};
+    std::string msg = "invalid graph:";
+    for (int b = 0; b < 10; ++b)
+        if (hflags & (1u << b)) msg += std::string(" ") + names[b] + ";";
+    return fail(AD_ERR_GRAPH, msg);
+}
+
+extern "C" const char *ad_status_string(ad_status s) {
+    switch (s) {
+    case AD_OK: return "AD_OK";
+    case AD_ERR_INVALID_ARG: return "AD_ERR_INVALID_ARG";
+    case AD_ERR_UNSUPPORTED: return "AD_ERR_UNSUPPORTED";
+    case AD_ERR_WORKSPACE: return "AD_ERR_WORKSPACE";
+    case AD_ERR_GRAPH: return "AD_ERR_GRAPH";
+    case AD_ERR_HIP: return "AD_ERR_HIP";
+    case AD_ERR_INTERNAL: return "AD_ERR_INTERNAL";
+    }
+    return "AD_ERR_UNKNOWN";
+}
+
+extern "C" const char *ad_last_error(void) { return ad::g_last_error.c_str(); }
+
+extern "C" int32_t ad_abi_version(void) { return 1; }

@@ -1,0 +1,189 @@
+// ad_internal.h -- shared device/host helpers of libad (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+
+#include "../../include/ad.h"
+
+namespace ad {
+
+// ------------------------------------------------------------------ errors --
+
+void set_error(const std::string &msg);
+ad_status fail(ad_status s, const std::string &msg);
+ad_status hip_fail(hipError_t e, const char *what);
+
+#define AD_HIP(call)                                             \
+    do {                                                         \
+        hipError_t _e = (call);                                  \
+        if (_e != hipSuccess) return ::ad::hip_fail(_e, #call);  \
+    } while (0)
+
+#define AD_LAUNCH_CHECK(what)                                    \
+    do {                                                         \
+        hipError_t _e = hipGetLastError();                       \
+        if (_e != hipSuccess) return ::ad::hip_fail(_e, what);   \
+    } while (0)
+
+// --------------------------------------------------------------- workspace --
+
+// Bump allocator over the caller's workspace; every slice is 256-byte aligned.
+struct Carver {
+    char *base;
+    size_t cap;
+    size_t used = 0;
+    bool measuring;   // base == nullptr: only count bytes
+    Carver(void *b, size_t c) : base((char *)b), cap(c), measuring(b == nullptr) {}
+    template <typename T>
+    T *take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        if (bytes == 0) bytes = 256;
+        T *p = measuring ? nullptr : reinterpret_cast<T *>(base + used);
+        used += bytes;
+        return p;
+    }
+    bool ok() const { return measuring || used <= cap; }
+};
+
+// ---------------------------------------------------------------- numerics --
+
+struct bf16 { uint16_t bits; };
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+    return __uint_as_float(((uint32_t)b) << 16);
+}
+
+// Round to nearest even; NaN stays NaN (quietened).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <typename T> struct acc_of { typedef float type; };
+template <> struct acc_of<double> { typedef double type; };
+
+// Vector of VEC storage elements, naturally aligned.
+template <typename T, int VEC> struct alignas(sizeof(T) * VEC) vstore { T v[VEC]; };
+
+template <int VEC, typename T, typename A>
+__device__ __forceinline__ void load_vec(const T *p, A (&out)[VEC]) {
+    vstore<T, VEC> t = *reinterpret_cast<const vstore<T, VEC> *>(p);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) out[q] = (A)t.v[q];
+}
+template <int VEC, typename A>
+__device__ __forceinline__ void load_vec(const bf16 *p, A (&out)[VEC]) {
+    vstore<uint16_t, VEC> t = *reinterpret_cast<const vstore<uint16_t, VEC> *>(p);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) out[q] = (A)bf16_to_f32(t.v[q]);
+}
+template <int VEC, typename T, typename A>
+__device__ __forceinline__ void store_vec(T *p, const A (&in)[VEC]) {
+    vstore<T, VEC> t;
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) t.v[q] = (T)in[q];
+    *reinterpret_cast<vstore<T, VEC> *>(p) = t;
+}
+template <int VEC, typename A>
+__device__ __forceinline__ void store_vec(bf16 *p, const A (&in)[VEC]) {
+    vstore<uint16_t, VEC> t;
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) t.v[q] = f32_to_bf16((float)in[q]);
+    *reinterpret_cast<vstore<uint16_t, VEC> *>(p) = t;
+}
+
+// Order-preserving map of a double onto uint64 (for min/max atomics).
+__device__ __forceinline__ unsigned long long ord_encode(double x) {
+    unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__host__ __device__ __forceinline__ double ord_decode(unsigned long long u) {
+    unsigned long long b = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
+    double d;
+    __builtin_memcpy(&d, &b, 8);
+    return d;
+}
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64->128-bit products; round keys advance by the Weyl constants.
+__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                              uint64_t k0, uint64_t k1, uint64_t out[4]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// Uniform start value on the 2^-24 grid in [-1/2, 1/2) from a 64-bit word.
+__device__ __forceinline__ double start_from_word(uint64_t w) {
+    return (double)(w >> 40) * (1.0 / 16777216.0) - 0.5;
+}
+
+// ------------------------------------------------------------ wave helpers --
+
+constexpr int WAVE = 64;
+
+template <typename T>
+__device__ __forceinline__ T shfl_down(T v, int delta) { return __shfl_down(v, delta, WAVE); }
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src) { return __shfl(v, src, WAVE); }
+
+// Lanes per neighbour row (C) for R elements loaded VEC at a time.
+inline int lanes_per_row(int R, int vec) { return (R + vec - 1) / vec; }
+
+// Largest power of two p with p * c <= lanes.
+inline int pow2_slots(int lanes, int c) {
+    int p = 1;
+    while (p * 2 * c <= lanes) p *= 2;
+    return p;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Grid for a grid-stride loop over `count` items.
+inline unsigned grid_for(int64_t count, int block) {
+    int64_t b = ceil_div(count, block);
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return (unsigned)b;
+}
+
+// Small device fills (no hipMemsetAsync: the calls may be graph-captured).
+ad_status fill_u64(unsigned long long *p, unsigned long long v, int64_t count, hipStream_t s);
+ad_status fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s);
+ad_status fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
+
+// Rows with lo < degree <= hi appended to list (count must start at 0).
+ad_status collect_rows(const ad_graph *g, int64_t lo, int64_t hi, int32_t *list,
+                       unsigned int *count, hipStream_t s);
+
+ad_status check_graph_args(const ad_graph *g);
+
+// Launch shape of a JOR sweep (see ad_relax.hip).
+struct SweepShape {
+    int vec, C, SPR, RPW, SPRW;
+    int64_t hub_d;
+};
+SweepShape sweep_shape(int R, size_t in_bytes, double avg_deg, int rpw_req, int64_t hub_req);
+
+// xout = (1 - omega) xin + omega * diag(inv_s) W xin, FP32, rows longer than
+// sh.hub_d taken from hub_list (built with collect_rows).
+ad_status sweep_f32(const ad_graph *g, const float *inv_s, float omega, const float *xin, float *xout, int R,
+                    const SweepShape &sh, const int32_t *hub_list, const unsigned int *hub_count,
+                    hipStream_t st);
+ad_status weighted_degree_f32(const ad_graph *g, float *inv_s, float *sdeg, hipStream_t st);
+
+}  // namespace ad

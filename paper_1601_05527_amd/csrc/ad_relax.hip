@@ -1,0 +1,605 @@
+// ad_relax.hip -- start vectors, JOR sweeps and the rescale statistics of
+// Algorithm 1 (ComputeAlgDist) on gfx950.
+//
+// Data layout: the R test vectors are stored as one row-major block X[n][R],
+// so the R values of a vertex are contiguous (R * sizeof(T) bytes) and one
+// gather of a neighbour row serves all R vectors.  A sweep is a sparse-times-
+// dense product over the CSR: for row i, C lanes cover the R values of one
+// neighbour (VEC values per lane, 16-byte loads), SPR such lane groups
+// ("slots") walk the neighbour list in parallel, and a shuffle tree combines
+// the slots.  Rows longer than `hub_d` go to a second kernel that gives each
+// of them a 256-thread workgroup.  Arithmetic order is fixed, so results are
+// bitwise repeatable.
+//
+// Numerics: the start block is shifted per vector by the weighted mean
+// sum_i s_i x_i / sum_i s_i rounded to the 2^-24 grid.  The sweep matrix
+// preserves constant vectors, so this changes x^(k) by exactly that constant
+// (the start values lie on the same grid, so the subtraction itself is exact)
+// and leaves the rescaled vectors unchanged, while the sweeps then work on
+// values centred near zero, whose rounding errors are proportional to the
+// spread of the vector rather than to its mean.
+#include "ad_internal.h"
+
+#include <math.h>
+
+#include <algorithm>
+
+namespace ad {
+
+constexpr int BLOCK = 256;
+constexpr int CENTRE_ROWS = 1024;   // rows per partial-sum block (fixed: keeps sums reproducible)
+
+// s_i = sum_j w_ij (FP64, CSR order); inv_s = 1/s_i (0 for isolated vertices).
+template <typename A>
+__global__ void k_weighted_degree(int64_t n, const int64_t *__restrict__ row_ptr,
+                                  const float *__restrict__ w, A *__restrict__ inv_s,
+                                  float *__restrict__ sdeg) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t b = row_ptr[i], e = row_ptr[i + 1];
+        double s = 0.0;
+        if (w) {
+            for (int64_t p = b; p < e; ++p) s += (double)w[p];
+        } else {
+            s = (double)(e - b);
+        }
+        inv_s[i] = (e > b) ? (A)(1.0 / s) : (A)0;
+        sdeg[i] = (float)s;
+    }
+}
+
+__device__ __forceinline__ double start_value(uint64_t seed, uint64_t gid, int32_t key, int r) {
+    uint64_t out[4];
+    philox4x64_10((uint64_t)(uint32_t)key, (uint64_t)(r >> 2), 0, 0, seed, gid, out);
+    return start_from_word(out[r & 3]);
+}
+
+// Partial sums of s_i * x_i^(0) (per vector) and of s_i over CENTRE_ROWS rows.
+template <typename T>
+__global__ void k_centre_partials(int64_t n, int R, const float *__restrict__ sdeg,
+                                  const int32_t *__restrict__ orig_id, uint64_t seed,
+                                  uint64_t gid, const T *__restrict__ x0,
+                                  double *__restrict__ part, double *__restrict__ part_s) {
+    __shared__ double acc_l[BLOCK];
+    __shared__ double s_l[BLOCK];
+    const int t = threadIdx.x;
+    const int stride = BLOCK / R;            // rows visited per step by one vector's threads
+    const int r = t % R;
+    const int row_off = t / R;
+    double acc = 0.0, sacc = 0.0;
+    const int64_t r0 = (int64_t)blockIdx.x * CENTRE_ROWS;
+    const int64_t r1 = min(n, r0 + CENTRE_ROWS);
+    if (row_off < stride) {
+        for (int64_t i = r0 + row_off; i < r1; i += stride) {
+            double s = (double)sdeg[i];
+            double x = x0 ? (double)x0[i * R + r]
+                          : start_value(seed, gid, orig_id ? orig_id[i] : (int32_t)i, r);
+            acc += s * x;
+            sacc += s;
+        }
+    }
+    acc_l[t] = acc;
+    s_l[t] = sacc;
+    __syncthreads();
+    if (t < R) {
+        double a = 0.0;
+        for (int q = t; q < stride * R; q += R) a += acc_l[q];
+        part[(int64_t)blockIdx.x * R + t] = a;
+    }
+    if (t == 0) {
+        double a = 0.0;
+        for (int q = 0; q < stride * R; q += R) a += s_l[q];
+        part_s[blockIdx.x] = a;
+    }
+}
+
+// shift_r = weighted mean rounded to the 2^-24 grid; resets the min/max codes.
+__global__ void k_centre_finalize(int R, int64_t nblocks, const double *__restrict__ part,
+                                  const double *__restrict__ part_s, int centre,
+                                  double *__restrict__ shift, unsigned long long *__restrict__ mm) {
+    const int r = threadIdx.x;
+    if (r >= R) return;
+    double S = 0.0, a = 0.0;
+    for (int64_t b = 0; b < nblocks; ++b) {
+        S += part_s[b];
+        a += part[b * R + r];
+    }
+    double sh = 0.0;
+    if (centre && S > 0.0) sh = rint((a / S) * 16777216.0) * (1.0 / 16777216.0);
+    shift[r] = sh;
+    mm[r] = ~0ull;       // running min code
+    mm[R + r] = 0ull;    // running max code
+}
+
+// x^(0) - shift into the start buffer.  One Philox block feeds 4 vectors.
+template <typename T>
+__global__ void k_init(int64_t n, int R, const int32_t *__restrict__ orig_id, uint64_t seed,
+                       uint64_t gid, const T *__restrict__ x0, const double *__restrict__ shift,
+                       T *__restrict__ x) {
+    const int nq = (R + 3) >> 2;
+    const int64_t total = n * nq;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx / nq;
+        int q = (int)(idx - i * nq);
+        uint64_t words[4];
+        if (!x0) {
+            int32_t key = orig_id ? orig_id[i] : (int32_t)i;
+            philox4x64_10((uint64_t)(uint32_t)key, (uint64_t)q, 0, 0, seed, gid, words);
+        }
+        for (int c = 0; c < 4; ++c) {
+            int r = 4 * q + c;
+            if (r >= R) break;
+            double v = x0 ? (double)x0[i * R + r] : start_from_word(words[c]);
+            x[i * R + r] = (T)(v - shift[r]);
+        }
+    }
+}
+
+// One JOR sweep for rows with degree <= hub_d.
+//   lane -> (row in wave rw, slot, chunk); C lanes per neighbour row,
+//   SPR slots per row, RPW rows per wave, 4 waves per block.
+template <typename Tin, typename Tout, typename A, int VEC>
+__global__ __launch_bounds__(BLOCK) void k_sweep(
+    int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const float *__restrict__ w, const A *__restrict__ inv_s, A omega,
+    const Tin *__restrict__ xin, Tout *__restrict__ xout, int R, int C, int SPR, int RPW,
+    int64_t hub_d) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int group = C * SPR;
+    const int rw = lane / group;
+    const int sub = lane - rw * group;
+    const int slot = sub / C;
+    const int chunk = sub - slot * C;
+    const int64_t row = ((int64_t)blockIdx.x * (BLOCK / WAVE) + wave) * RPW + rw;
+    const bool active = (rw < RPW) && (row < n);
+    int64_t beg = 0, end = 0;
+    if (active) {
+        beg = row_ptr[row];
+        end = row_ptr[row + 1];
+    }
+    const bool hub = (end - beg) > hub_d;
+    A acc[VEC];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) acc[q] = (A)0;
+    if (active && !hub) {
+        const int off = chunk * VEC;
+        int64_t p = beg + slot;
+        // two neighbours per step keep two gathers in flight per lane
+        for (; p + SPR < end; p += 2 * SPR) {
+            int32_t j0 = col[p], j1 = col[p + SPR];
+            A w0 = w ? (A)w[p] : (A)1, w1 = w ? (A)w[p + SPR] : (A)1;
+            A v0[VEC], v1[VEC];
+            load_vec<VEC>(xin + (int64_t)j0 * R + off, v0);
+            load_vec<VEC>(xin + (int64_t)j1 * R + off, v1);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = fma(w0, v0[q], acc[q]);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = fma(w1, v1[q], acc[q]);
+        }
+        if (p < end) {
+            int32_t j0 = col[p];
+            A w0 = w ? (A)w[p] : (A)1;
+            A v0[VEC];
+            load_vec<VEC>(xin + (int64_t)j0 * R + off, v0);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = fma(w0, v0[q], acc[q]);
+        }
+    }
+    for (int d = SPR >> 1; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] += shfl_down(acc[q], d * C);
+    }
+    if (active && !hub && slot == 0) {
+        const int off = chunk * VEC;
+        A own[VEC], res[VEC];
+        load_vec<VEC>(xin + row * R + off, own);
+        if (end > beg) {
+            const A is = inv_s[row];
+            const A keep = (A)1 - omega;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) res[q] = fma(omega, acc[q] * is, keep * own[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) res[q] = own[q];
+        }
+        store_vec<VEC>(xout + row * R + off, res);
+    }
+}
+
+// One JOR sweep for the listed long rows: a 256-thread workgroup per row,
+// SPRW slots per wave, partial sums combined across the 4 waves in LDS.
+template <typename Tin, typename Tout, typename A, int VEC>
+__global__ __launch_bounds__(BLOCK) void k_sweep_hub(
+    const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const float *__restrict__ w, const A *__restrict__ inv_s, A omega,
+    const Tin *__restrict__ xin, Tout *__restrict__ xout, int R, int C, int SPRW) {
+    __shared__ A part[BLOCK / WAVE][64];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int slot_w = lane / C;             // slot within the wave
+    const int chunk = lane - slot_w * C;
+    const bool lane_on = slot_w < SPRW;
+    const int slots = SPRW * (BLOCK / WAVE);
+    const int slot = wave * SPRW + slot_w;
+    const unsigned int nh = *count;
+    for (unsigned int h = blockIdx.x; h < nh; h += gridDim.x) {
+        const int64_t row = list[h];
+        const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
+        const int off = chunk * VEC;
+        A acc[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] = (A)0;
+        if (lane_on) {
+            int64_t p = beg + slot;
+            for (; p + slots < end; p += 2 * slots) {
+                int32_t j0 = col[p], j1 = col[p + slots];
+                A w0 = w ? (A)w[p] : (A)1, w1 = w ? (A)w[p + slots] : (A)1;
+                A v0[VEC], v1[VEC];
+                load_vec<VEC>(xin + (int64_t)j0 * R + off, v0);
+                load_vec<VEC>(xin + (int64_t)j1 * R + off, v1);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[q] = fma(w0, v0[q], acc[q]);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[q] = fma(w1, v1[q], acc[q]);
+            }
+            if (p < end) {
+                int32_t j0 = col[p];
+                A w0 = w ? (A)w[p] : (A)1;
+                A v0[VEC];
+                load_vec<VEC>(xin + (int64_t)j0 * R + off, v0);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[q] = fma(w0, v0[q], acc[q]);
+            }
+        }
+        for (int d = SPRW >> 1; d >= 1; d >>= 1) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] += shfl_down(acc[q], d * C);
+        }
+        if (lane_on && slot_w == 0) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) part[wave][off + q] = acc[q];
+        }
+        __syncthreads();
+        if (wave == 0 && lane_on && slot_w == 0) {
+            A sum[VEC], own[VEC], res[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) sum[q] = part[0][off + q];
+            for (int wv = 1; wv < BLOCK / WAVE; ++wv) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) sum[q] += part[wv][off + q];
+            }
+            load_vec<VEC>(xin + row * R + off, own);
+            const A is = inv_s[row];
+            const A keep = (A)1 - omega;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) res[q] = fma(omega, sum[q] * is, keep * own[q]);
+            store_vec<VEC>(xout + row * R + off, res);
+        }
+        __syncthreads();
+    }
+}
+
+// Per-vector min and max of x over non-isolated rows (ordered-integer atomics).
+template <typename T>
+__global__ void k_minmax(int64_t n, int R, const int64_t *__restrict__ row_ptr,
+                         const T *__restrict__ x, unsigned long long *__restrict__ mm) {
+    __shared__ double lo_l[BLOCK];
+    __shared__ double hi_l[BLOCK];
+    const int t = threadIdx.x;
+    const int stride = BLOCK / R;
+    const int r = t % R;
+    const int row_off = t / R;
+    double lo = INFINITY, hi = -INFINITY;
+    if (row_off < stride) {
+        for (int64_t i = (int64_t)blockIdx.x * stride + row_off; i < n;
+             i += (int64_t)gridDim.x * stride) {
+            if (row_ptr[i + 1] == row_ptr[i]) continue;
+            double v = (double)x[i * R + r];
+            lo = fmin(lo, v);
+            hi = fmax(hi, v);
+        }
+    }
+    lo_l[t] = lo;
+    hi_l[t] = hi;
+    __syncthreads();
+    if (t < R) {
+        double a = INFINITY, b = -INFINITY;
+        for (int q = t; q < stride * R; q += R) {
+            a = fmin(a, lo_l[q]);
+            b = fmax(b, hi_l[q]);
+        }
+        if (a <= b) {
+            atomicMin(&mm[t], ord_encode(a));
+            atomicMax(&mm[R + t], ord_encode(b));
+        }
+    }
+}
+
+__global__ void k_minmax_out(int R, const unsigned long long *__restrict__ mm,
+                             const double *__restrict__ shift, double *__restrict__ out,
+                             double *__restrict__ shift_out) {
+    const int r = threadIdx.x;
+    if (r >= R) return;
+    unsigned long long a = mm[r], b = mm[R + r];
+    bool none = (a == ~0ull);
+    out[r] = none ? INFINITY : ord_decode(a);
+    out[R + r] = none ? -INFINITY : ord_decode(b);
+    if (shift_out) shift_out[r] = shift[r];
+}
+
+// ------------------------------------------------------------------- host --
+
+struct Buf {
+    void *p;
+    ad_dtype t;
+};
+
+static int pick_vec(int R, size_t elem_bytes) {
+    int maxv = (int)(16 / elem_bytes);
+    for (int v = maxv; v > 1; v >>= 1)
+        if (R % v == 0) return v;
+    return 1;
+}
+
+SweepShape sweep_shape(int R, size_t in_bytes, double avg_deg, int rpw_req, int64_t hub_req) {
+    SweepShape s;
+    s.vec = pick_vec(R, in_bytes);
+    s.C = lanes_per_row(R, s.vec);
+    int spr_max = pow2_slots(WAVE, s.C);
+    int rpw = rpw_req;
+    if (rpw <= 0) {
+        // aim for about two neighbours per slot on an average row
+        int want = 1;
+        while (want * 2 <= (int)ceil(avg_deg / 2.0) && want * 2 <= spr_max) want *= 2;
+        rpw = std::max(1, spr_max / want);
+    }
+    if (rpw > spr_max) rpw = spr_max;
+    // rows per wave must be a power of two dividing spr_max
+    int p = 1;
+    while (p * 2 <= rpw) p *= 2;
+    s.RPW = p;
+    s.SPR = spr_max / s.RPW;
+    s.SPRW = spr_max;
+    s.hub_d = hub_req > 0 ? hub_req : std::max<int64_t>(256, 8 * (int64_t)s.SPR);
+    return s;
+}
+
+template <typename Tin, typename Tout, typename A, int VEC>
+static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout,
+                                int R, const SweepShape &sh, const int32_t *hub_list,
+                                const unsigned int *hub_count, hipStream_t st) {
+    int64_t rows_per_block = (int64_t)(BLOCK / WAVE) * sh.RPW;
+    int64_t nb = ceil_div(g->n, rows_per_block);
+    if (nb > 0) {
+        hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC>), dim3((unsigned)nb), dim3(BLOCK), 0, st,
+                           g->n, g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C, sh.SPR,
+                           sh.RPW, sh.hub_d);
+        AD_LAUNCH_CHECK("k_sweep");
+    }
+    if (g->d_max > sh.hub_d || g->d_max == 0) {
+        unsigned grid = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, g->n));
+        hipLaunchKernelGGL((k_sweep_hub<Tin, Tout, A, VEC>), dim3(grid), dim3(BLOCK), 0, st, hub_list,
+                           hub_count, g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C,
+                           sh.SPRW);
+        AD_LAUNCH_CHECK("k_sweep_hub");
+    }
+    return AD_OK;
+}
+
+template <typename Tin, typename Tout, typename A>
+static ad_status launch_sweep(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout,
+                              int R, const SweepShape &sh, const int32_t *hub_list,
+                              const unsigned int *hub_count, hipStream_t st) {
+    switch (sh.vec) {
+    case 1: return launch_sweep_v<Tin, Tout, A, 1>(g, inv_s, omega, xin, xout, R, sh, hub_list, hub_count, st);
+    case 2: return launch_sweep_v<Tin, Tout, A, 2>(g, inv_s, omega, xin, xout, R, sh, hub_list, hub_count, st);
+    case 4: return launch_sweep_v<Tin, Tout, A, 4>(g, inv_s, omega, xin, xout, R, sh, hub_list, hub_count, st);
+    case 8: return launch_sweep_v<Tin, Tout, A, 8>(g, inv_s, omega, xin, xout, R, sh, hub_list, hub_count, st);
+    }
+    return fail(AD_ERR_INTERNAL, "bad vector width");
+}
+
+static size_t dtype_bytes(ad_dtype t) { return t == AD_F64 ? 8 : (t == AD_F32 ? 4 : 2); }
+
+struct RelaxLayout {
+    void *inv_s;
+    float *sdeg;
+    double *part, *part_s, *shift;
+    unsigned long long *mm;
+    int32_t *hub_list;
+    unsigned int *hub_count;
+    void *bufA, *bufB;
+    void *b16A, *b16B;
+};
+
+static size_t relax_layout(const ad_graph *g, const ad_relax_opts *o, void *ws, size_t ws_bytes,
+                           RelaxLayout *L) {
+    Carver c(ws, ws_bytes);
+    const int64_t n = g->n > 0 ? g->n : 1;
+    const int R = o->R;
+    const int64_t nb = std::max<int64_t>(1, ceil_div(g->n, CENTRE_ROWS));
+    const bool f64 = o->store == AD_F64;
+    RelaxLayout l;
+    l.inv_s = f64 ? (void *)c.take<double>(n) : (void *)c.take<float>(n);
+    l.sdeg = c.take<float>(n);
+    l.part = c.take<double>(nb * R);
+    l.part_s = c.take<double>(nb);
+    l.shift = c.take<double>(R);
+    l.mm = c.take<unsigned long long>(2 * R);
+    l.hub_list = c.take<int32_t>(n);
+    l.hub_count = c.take<unsigned int>(1);
+    const size_t xb = f64 ? 8 : 4;
+    l.bufA = c.take<char>((size_t)n * R * xb);
+    l.bufB = c.take<char>((size_t)n * R * xb);
+    if (o->store == AD_BF16) {
+        l.b16A = c.take<uint16_t>((size_t)n * R);
+        l.b16B = c.take<uint16_t>((size_t)n * R);
+    } else {
+        l.b16A = l.b16B = nullptr;
+    }
+    if (L) *L = l;
+    return c.ok() ? c.used : 0;
+}
+
+static ad_status check_relax_opts(const ad_relax_opts *o) {
+    if (!o) return fail(AD_ERR_INVALID_ARG, "opts is NULL");
+    if (o->R < 1 || o->R > 64) return fail(AD_ERR_INVALID_ARG, "R must be in [1, 64]");
+    if (o->k < 0) return fail(AD_ERR_INVALID_ARG, "k must be >= 0");
+    if (!(o->omega > 0.0 && o->omega <= 1.0)) return fail(AD_ERR_INVALID_ARG, "omega must be in (0, 1]");
+    if (o->store != AD_F64 && o->store != AD_F32 && o->store != AD_BF16)
+        return fail(AD_ERR_INVALID_ARG, "unknown storage type");
+    if (o->store == AD_BF16 && o->fp32_tail < 1) return fail(AD_ERR_INVALID_ARG, "fp32_tail must be >= 1");
+    if (o->ckpt_every < 0) return fail(AD_ERR_INVALID_ARG, "ckpt_every must be >= 0");
+    if (o->ckpt_every > 0 && o->store == AD_BF16)
+        return fail(AD_ERR_UNSUPPORTED, "checkpoints need FP32 or FP64 storage");
+    if (o->rows_per_wave < 0 || o->hub_degree < 0) return fail(AD_ERR_INVALID_ARG, "negative tuning value");
+    return AD_OK;
+}
+
+// Enqueue the whole relaxation.  `shift_out` may be NULL.
+template <typename T>
+static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const void *x0, void *x_out,
+                            double *minmax_out, double *shift_out, void *ckpt, const RelaxLayout &L,
+                            hipStream_t st) {
+    typedef typename acc_of<T>::type A;
+    const int R = o->R;
+    const int64_t n = g->n;
+    const int64_t nb = std::max<int64_t>(1, ceil_div(n, CENTRE_ROWS));
+    const double avg = n > 0 ? (double)(2 * g->m) / (double)n : 0.0;
+    ad_status s;
+
+    if (n > 0) {
+        hipLaunchKernelGGL((k_weighted_degree<A>), dim3(grid_for(n, BLOCK)), dim3(BLOCK), 0, st, n,
+                           g->row_ptr, g->w, (A *)L.inv_s, L.sdeg);
+        AD_LAUNCH_CHECK("k_weighted_degree");
+        hipLaunchKernelGGL((k_centre_partials<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, L.sdeg,
+                           g->orig_id, o->seed, o->graph_id, (const T *)x0, L.part, L.part_s);
+        AD_LAUNCH_CHECK("k_centre_partials");
+    }
+    hipLaunchKernelGGL(k_centre_finalize, dim3(1), dim3(64), 0, st, R, n > 0 ? nb : (int64_t)0, L.part,
+                       L.part_s, 1, L.shift, L.mm);
+    AD_LAUNCH_CHECK("k_centre_finalize");
+
+    const int nck = ad_relax_num_checkpoints(o);
+    const size_t slot_elems = (size_t)n * R;
+    T *start = (o->k == 0) ? (T *)x_out : (ckpt && nck > 0 ? (T *)ckpt : (T *)L.bufA);
+    if (n > 0) {
+        int64_t total = n * ((R + 3) / 4);
+        hipLaunchKernelGGL((k_init<T>), dim3(grid_for(total, BLOCK)), dim3(BLOCK), 0, st, n, R,
+                           g->orig_id, o->seed, o->graph_id, (const T *)x0, L.shift, start);
+        AD_LAUNCH_CHECK("k_init");
+    }
+
+    if (o->k > 0 && n > 0) {
+        SweepShape sh32 = sweep_shape(R, sizeof(T), avg, o->rows_per_wave, o->hub_degree);
+        SweepShape sh16 = sweep_shape(R, 2, avg, o->rows_per_wave, o->hub_degree);
+        // hub rows, found once per call (the list depends on the graph only)
+        const int64_t hub_d = sh32.hub_d;
+        sh16.hub_d = hub_d;
+        s = fill_i32((int32_t *)L.hub_count, 0, 1, st);
+        if (s != AD_OK) return s;
+        s = collect_rows(g, hub_d, (int64_t)1 << 62, L.hub_list, L.hub_count, st);
+        if (s != AD_OK) return s;
+
+        Buf cur = {start, o->store == AD_F64 ? AD_F64 : AD_F32};
+        const int tail = o->store == AD_BF16 ? o->fp32_tail : o->k;
+        for (int t = 1; t <= o->k; ++t) {
+            Buf dst;
+            if (t == o->k) {
+                dst = {x_out, o->store == AD_F64 ? AD_F64 : AD_F32};
+            } else if (ckpt && o->ckpt_every > 0 && t % o->ckpt_every == 0) {
+                dst = {(char *)ckpt + (size_t)(t / o->ckpt_every) * slot_elems * sizeof(T),
+                       o->store == AD_F64 ? AD_F64 : AD_F32};
+            } else if (o->store == AD_BF16 && t <= o->k - tail) {
+                dst = {cur.p == L.b16A ? L.b16B : L.b16A, AD_BF16};
+            } else {
+                dst = {cur.p == L.bufA ? L.bufB : L.bufA, o->store == AD_F64 ? AD_F64 : AD_F32};
+            }
+            const A om = (A)o->omega;
+            if (cur.t == AD_F64) {
+                s = launch_sweep<double, double, double>(g, (const double *)L.inv_s, (double)om,
+                                                         (const double *)cur.p, (double *)dst.p, R, sh32,
+                                                         L.hub_list, L.hub_count, st);
+            } else if (cur.t == AD_F32 && dst.t == AD_F32) {
+                s = launch_sweep<float, float, float>(g, (const float *)L.inv_s, (float)om,
+                                                      (const float *)cur.p, (float *)dst.p, R, sh32,
+                                                      L.hub_list, L.hub_count, st);
+            } else if (cur.t == AD_F32 && dst.t == AD_BF16) {
+                s = launch_sweep<float, bf16, float>(g, (const float *)L.inv_s, (float)om,
+                                                     (const float *)cur.p, (bf16 *)dst.p, R, sh32,
+                                                     L.hub_list, L.hub_count, st);
+            } else if (cur.t == AD_BF16 && dst.t == AD_BF16) {
+                s = launch_sweep<bf16, bf16, float>(g, (const float *)L.inv_s, (float)om,
+                                                    (const bf16 *)cur.p, (bf16 *)dst.p, R, sh16,
+                                                    L.hub_list, L.hub_count, st);
+            } else {
+                s = launch_sweep<bf16, float, float>(g, (const float *)L.inv_s, (float)om,
+                                                     (const bf16 *)cur.p, (float *)dst.p, R, sh16,
+                                                     L.hub_list, L.hub_count, st);
+            }
+            if (s != AD_OK) return s;
+            cur = dst;
+        }
+    }
+
+    if (n > 0) {
+        int stride = BLOCK / R;
+        hipLaunchKernelGGL((k_minmax<T>), dim3(grid_for(ceil_div(n, stride), 1)), dim3(BLOCK), 0, st, n,
+                           R, g->row_ptr, (const T *)x_out, L.mm);
+        AD_LAUNCH_CHECK("k_minmax");
+    }
+    hipLaunchKernelGGL(k_minmax_out, dim3(1), dim3(64), 0, st, R, L.mm, L.shift, minmax_out, shift_out);
+    AD_LAUNCH_CHECK("k_minmax_out");
+    return AD_OK;
+}
+
+ad_status sweep_f32(const ad_graph *g, const float *inv_s, float omega, const float *xin, float *xout, int R,
+                    const SweepShape &sh, const int32_t *hub_list, const unsigned int *hub_count,
+                    hipStream_t st) {
+    return launch_sweep<float, float, float>(g, inv_s, omega, xin, xout, R, sh, hub_list, hub_count, st);
+}
+
+ad_status weighted_degree_f32(const ad_graph *g, float *inv_s, float *sdeg, hipStream_t st) {
+    if (g->n <= 0) return AD_OK;
+    hipLaunchKernelGGL((k_weighted_degree<float>), dim3(grid_for(g->n, BLOCK)), dim3(BLOCK), 0, st, g->n,
+                       g->row_ptr, g->w, inv_s, sdeg);
+    AD_LAUNCH_CHECK("k_weighted_degree");
+    return AD_OK;
+}
+
+}  // namespace ad
+
+using namespace ad;
+
+extern "C" int32_t ad_relax_num_checkpoints(const ad_relax_opts *o) {
+    if (!o || o->ckpt_every <= 0 || o->k <= 0) return 0;
+    return (o->k + o->ckpt_every - 1) / o->ckpt_every;
+}
+
+extern "C" size_t ad_relax_workspace_size(const ad_graph *g, const ad_relax_opts *o) {
+    if (check_graph_args(g) != AD_OK || check_relax_opts(o) != AD_OK) return 0;
+    return relax_layout(g, o, nullptr, 0, nullptr);
+}
+
+extern "C" ad_status ad_relax(const ad_graph *g, const ad_relax_opts *o, const void *x0, void *x_out,
+                              double *minmax_out, double *shift_out, void *ckpt, void *ws,
+                              size_t ws_bytes, hipStream_t stream) {
+    ad_status s = check_graph_args(g);
+    if (s != AD_OK) return s;
+    s = check_relax_opts(o);
+    if (s != AD_OK) return s;
+    if (!minmax_out) return fail(AD_ERR_INVALID_ARG, "minmax_out is NULL");
+    if (g->n > 0 && !x_out) return fail(AD_ERR_INVALID_ARG, "x_out is NULL");
+    if (x0 && x0 == x_out) return fail(AD_ERR_INVALID_ARG, "x_out aliases x0");
+    if (ckpt && ckpt == x_out) return fail(AD_ERR_INVALID_ARG, "x_out aliases ckpt");
+    if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    RelaxLayout L;
+    if (relax_layout(g, o, ws, ws_bytes, &L) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    if (o->store == AD_F64)
+        return relax_impl<double>(g, o, x0, x_out, minmax_out, shift_out, ckpt, L, stream);
+    return relax_impl<float>(g, o, x0, x_out, minmax_out, shift_out, ckpt, L, stream);
+}

@@ -1,0 +1,121 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, every
+function declared in include/ad.h is exported, and argument validation
+rejects bad input before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ad.h")
+LIB = os.path.join(ROOT, "paper_1601_05527_amd", "libad.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ad_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libad.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_four_calls():
+    names = _declared()
+    for n in ["ad_relax", "ad_edge_dist", "ad_sparsify", "ad_relax_backward"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    from paper_1601_05527_amd import api
+    for name in _declared():
+        assert hasattr(api.lib, name)
+
+
+def _graph_struct(api, n=4, m=3):
+    return api.ADGraph(n, m, 0x1000, 0x2000, None, 0x3000, None, 3)
+
+
+def test_status_strings(lib):
+    lib.ad_status_string.restype = ctypes.c_char_p
+    assert lib.ad_status_string(0) == b"AD_OK"
+    assert lib.ad_status_string(3) == b"AD_ERR_WORKSPACE"
+
+
+def test_relax_rejects_bad_arguments():
+    from paper_1601_05527_amd import api
+    L = api.lib
+    g = _graph_struct(api)
+    ws = ctypes.c_void_p(0x10000)
+    out = ctypes.c_void_p(0x20000)
+    mm = ctypes.c_void_p(0x30000)
+
+    def call(opts, gp=ctypes.byref(g), ws_=ws, nbytes=1 << 30):
+        return L.ad_relax(gp, ctypes.byref(opts), None, out, mm, None, None, ws_, nbytes, None)
+
+    assert L.ad_relax(None, ctypes.byref(api.relax_opts(4, 2)), None, out, mm, None, None, ws,
+                      1 << 30, None) == 1
+    assert call(api.relax_opts(0, 2)) == 1          # R = 0
+    assert call(api.relax_opts(65, 2)) == 1         # R > 64
+    assert call(api.relax_opts(4, -1)) == 1         # k < 0
+    assert call(api.relax_opts(4, 2, omega=0.0)) == 1
+    assert call(api.relax_opts(4, 2, omega=1.5)) == 1
+    assert call(api.relax_opts(4, 2, store="bf16", fp32_tail=0)) == 1
+    assert call(api.relax_opts(4, 2, store="bf16", ckpt_every=2)) == 2
+    assert call(api.relax_opts(4, 2), ws_=ctypes.c_void_p(0x10001)) == 3   # misaligned
+    assert call(api.relax_opts(4, 2), nbytes=16) == 3                     # too small
+    msg = L.ad_last_error().decode()
+    assert "workspace" in msg
+    bad = api.ADGraph(4, 3, None, 0x2000, None, 0x3000, None, 3)
+    assert call(api.relax_opts(4, 2), gp=ctypes.byref(bad)) == 1
+
+
+def test_selection_rejects_bad_arguments():
+    from paper_1601_05527_amd import api
+    L = api.lib
+    g = _graph_struct(api)
+    p = ctypes.c_void_p(0x40000)
+    ws = ctypes.c_void_p(0x10000)
+    e = ctypes.c_double()
+    assert L.ad_sparsify_fit(ctypes.byref(g), 1, p, 0, 0.0, p, p, ctypes.byref(e), ws, 1 << 30, None) == 1
+    assert L.ad_sparsify_fit(ctypes.byref(g), 1, p, 0, 1.5, p, p, ctypes.byref(e), ws, 1 << 30, None) == 1
+    assert L.ad_sparsify_fit(ctypes.byref(g), 2, p, 0, 0.3, p, p, ctypes.byref(e), ws, 1 << 30, None) == 1
+    assert L.ad_sparsify(ctypes.byref(g), 1, p, 7, p, p, p, ws, 1 << 30, None) == 1
+    assert L.ad_sparsify(ctypes.byref(g), 1, p, 0, None, p, p, ws, 1 << 30, None) == 1
+    assert L.ad_edge_dist(ctypes.byref(g), 0, 1, p, p, p, None) == 1
+    assert L.ad_edge_dist(ctypes.byref(g), 4, 2, p, p, p, None) == 1
+
+
+def test_budget_table_host():
+    from paper_1601_05527_amd import api
+    import math
+    t = api.budget_table(20000, 0.5)
+    assert t[0] == 0
+    assert all(t[d] == math.isqrt(d) for d in range(1, 20001))
+    assert np.all(api.budget_table(100, 0.0)[1:] == 1)
+    assert np.all(api.budget_table(100, 1.0) == np.arange(101))
+    with pytest.raises(api.ADError):
+        api.budget_table(10, 1.5)
+
+
+def test_workspace_sizes_are_positive():
+    from paper_1601_05527_amd import api
+    L = api.lib
+    g = api.ADGraph(1000, 5000, 0x1000, 0x2000, None, 0x3000, None, 40)
+    o = api.relax_opts(16, 20)
+    assert L.ad_relax_workspace_size(ctypes.byref(g), ctypes.byref(o)) >= 2 * 1000 * 16 * 4
+    assert L.ad_sparsify_workspace_size(ctypes.byref(g)) >= 5000 * 24
+    assert L.ad_relax_num_checkpoints(ctypes.byref(api.relax_opts(16, 20, ckpt_every=5))) == 4
+    assert L.ad_relax_num_checkpoints(ctypes.byref(api.relax_opts(16, 21, ckpt_every=5))) == 5
+    assert L.ad_relax_num_checkpoints(ctypes.byref(api.relax_opts(16, 20))) == 0

@@ -1,0 +1,298 @@
+"""HIP path against the FP64 oracle, element by element, through the C ABI.
+
+Tolerances: FP64 storage 1e-12 relative on rho (the oracle itself sits
+within 1e-14 of an 80-bit evaluation on these inputs); FP32 1e-5 relative;
+selection bit-exact when both sides rank the same distances.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_05527_amd import graphs as G
+
+from gpu_helpers import announce, near_cut_mismatches, rel_stats
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1601_05527_amd import api as _api
+    return _api
+
+
+def _dg(api, g):
+    return api.DeviceGraph.from_host(g, "cuda")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _xhat(x, mm, live):
+    R = x.shape[1]
+    lo, hi = mm[:R], mm[R:]
+    span = np.where(hi > lo, hi - lo, 1.0)
+    xh = np.where(hi > lo, (x - lo) / span - 0.5, 0.0)
+    xh[~live] = 0.0
+    return xh
+
+
+# ------------------------------------------------------------------ start --
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_start_vectors_bitwise(api, store):
+    announce(f"start vectors {store}")
+    g = G.relabel(G.gnm(3000, 9000, 1), np.random.default_rng(2).permutation(3000))
+    dg = _dg(api, g)
+    R = 13
+    res = api.relax(dg, R, 0, seed=77, graph_id=5, store=store)
+    x = _np(res.x).astype(np.float64) + _np(res.shift)[None, :]
+    want = oracle.start_vectors(g.n, R, 77, 5, g.orig_id)
+    assert np.array_equal(x, want)
+    # the shift is on the 2^-24 grid and near the weighted mean
+    sh = _np(res.shift)
+    assert np.all(sh * 2**24 == np.round(sh * 2**24))
+
+
+# ------------------------------------------------------------ FP64 parity --
+
+def test_plain_fp64_gnm_parity(api):
+    announce("G(2000,10000) R=10 k=20 FP64")
+    g = G.gnm(2000, 10000, 0)
+    R, k = 10, 20
+    dg = _dg(api, g)
+    res = api.relax(dg, R, k, seed=0, store="f64")
+    rho = _np(api.edge_dist(dg, res.x, res.minmax))
+    rho_o, xk_o, xh_o, mm_o = oracle.algebraic_distance(g, R, k, 0.5, seed=0, want_vectors=True)
+    st = rel_stats(rho, rho_o)
+    assert st["max"] <= 1e-12, st["max"]
+    live = np.diff(g.row_ptr) > 0
+    xh = _xhat(_np(res.x), _np(res.minmax), live)
+    assert np.abs(xh - xh_o).max() <= 1e-12
+    # shifted x^(k) plus the shift reproduces x^(k)
+    xk = _np(res.x) + _np(res.shift)[None, :]
+    assert np.abs(xk - xk_o).max() <= 1e-13
+    # selection on the GPU's FP64 distances equals the oracle's on its own
+    for orient in (0, 1):
+        keep, n_kept = api.sparsify(dg, api.edge_dist(dg, res.x, res.minmax), orient, 0.5)
+        keep_o, kept_o = oracle.sparsify(g, rho_o, orient, 0.5)
+        bad = near_cut_mismatches(g, rho_o, _np(keep), keep_o, orient, 0.5, 1e-12)
+        assert not bad
+        assert int(_np(n_kept)[0]) == int(_np(keep).sum())
+
+
+# ------------------------------------------------------------ FP32 parity --
+
+@pytest.mark.parametrize("kind", ["chung_lu", "grid", "rmat"])
+def test_fp32_parity(api, kind):
+    announce(f"FP32 parity {kind}")
+    if kind == "chung_lu":
+        g = G.chung_lu(1 << 14, 240_000, seed=3)
+        R, k = 16, 20
+    elif kind == "grid":
+        g = G.grid_long_range(96, 230, seed=4)
+        R, k = 8, 20
+    else:
+        g = G.rmat(13, 60_000, seed=5)
+        R, k = 16, 30
+    dg = _dg(api, g)
+    res = api.relax(dg, R, k, seed=11, store="f32")
+    rho = _np(api.edge_dist(dg, res.x, res.minmax))
+    rho_o = oracle.algebraic_distance(g, R, k, 0.5, seed=11)
+    st = rel_stats(rho, rho_o)
+    print(f"{kind}: n={g.n} m={g.m} dmax={g.d_max} max rel {st['max']:.3e} p99.9 {st['p999']:.3e}")
+    assert st["max"] <= 1e-5
+
+
+def test_fp32_launch_shapes_agree(api):
+    announce("FP32 launch shapes")
+    g = G.chung_lu(1 << 13, 120_000, seed=6)
+    dg = _dg(api, g)
+    rho_o = oracle.algebraic_distance(g, 16, 20, 0.5, seed=1)
+    for rpw in (1, 2, 4, 8, 16):
+        for hub in (0, 64, 100000):
+            res = api.relax(dg, 16, 20, seed=1, store="f32", rows_per_wave=rpw, hub_degree=hub)
+            rho = _np(api.edge_dist(dg, res.x, res.minmax))
+            assert rel_stats(rho, rho_o)["max"] <= 1e-5, (rpw, hub)
+
+
+def test_repeatable_bitwise(api):
+    announce("bitwise repeatability")
+    g = G.chung_lu(1 << 13, 100_000, seed=7)
+    dg = _dg(api, g)
+    outs = []
+    for _ in range(2):
+        res = api.relax(dg, 16, 20, seed=2)
+        rho = api.edge_dist(dg, res.x, res.minmax)
+        keep, _, e = api.sparsify_fit(dg, rho, 0, 0.3)
+        outs.append((_np(res.x).copy(), _np(rho).copy(), _np(keep).copy(), e))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
+    assert outs[0][3] == outs[1][3]
+
+
+# -------------------------------------------------------------- selection --
+
+def _mixed_degree_graph():
+    """Random graph plus vertices whose degrees straddle every ranking
+    path boundary (8, 16, 32, 64, 8192) and one isolated vertex."""
+    rng = np.random.default_rng(12)
+    n = 12000
+    base = G.gnm(n - 1, 30000, 3)
+    us, vs = [base.edge_u], [base.edge_v]
+    existing = set(zip(base.edge_u.tolist(), base.edge_v.tolist()))
+    for hub, deg in [(0, 8), (1, 9), (2, 16), (3, 17), (4, 32), (5, 33), (6, 64), (7, 65),
+                     (8, 300), (9, 8192), (10, 8193), (11, 9000)]:
+        others = rng.choice(np.arange(12, n - 1), size=deg + 200, replace=False)
+        have = set(int(b) if a == hub else int(a) for a, b in existing if a == hub or b == hub)
+        add = [int(o) for o in others if int(o) not in have][: max(0, deg - len(have))]
+        for o in add:
+            a, b = min(hub, o), max(hub, o)
+            existing.add((a, b))
+            us.append(np.array([a]))
+            vs.append(np.array([b]))
+    u = np.concatenate(us)
+    v = np.concatenate(vs)
+    return G.from_edges(n, u, v, G.random_weights(u.size, 9))
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    g = _mixed_degree_graph()
+    rho = oracle.algebraic_distance(g, 8, 12, 0.5, seed=3)
+    return g, rho
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("orient", [0, 1])
+@pytest.mark.parametrize("e", [0.0, 0.25, 0.5, 0.75, 1.0])
+def test_selection_bit_exact_on_oracle_rho(api, mixed, prec, orient, e):
+    announce(f"selection {prec} orient={orient} e={e}")
+    g, rho = mixed
+    if prec == "f32":
+        rho_in = rho.astype(np.float32)
+        rho_ref = rho_in.astype(np.float64)
+    else:
+        rho_in = rho
+        rho_ref = rho
+    # force ties: quantise a third of the distances
+    rho_in = rho_in.copy()
+    rho_in[::3] = np.round(rho_in[::3], 2)
+    rho_ref = rho_in.astype(np.float64)
+    dg = _dg(api, g)
+    keep, n_kept = api.sparsify(dg, torch.from_numpy(rho_in).cuda(), orient, e)
+    keep_o, kept_o = oracle.sparsify(g, rho_ref, orient, e)
+    assert np.array_equal(_np(keep), keep_o)
+    assert int(_np(n_kept)[0]) == kept_o
+
+
+@pytest.mark.parametrize("orient", [0, 1])
+@pytest.mark.parametrize("target", [0.05, 0.3, 0.55, 0.9, 1.0])
+def test_fit_matches_oracle(api, mixed, orient, target):
+    announce(f"fit orient={orient} target={target}")
+    g, rho = mixed
+    rho32 = rho.astype(np.float32)
+    dg = _dg(api, g)
+    keep, n_kept, e = api.sparsify_fit(dg, torch.from_numpy(rho32).cuda(), orient, target)
+    e_o, keep_o, kept_o = oracle.fit_exponent(g, rho32.astype(np.float64), orient, target)
+    assert e == e_o
+    assert np.array_equal(_np(keep), keep_o)
+    assert int(_np(n_kept)[0]) == kept_o
+
+
+def test_end_to_end_masks_chung_lu(api):
+    announce("end-to-end masks Chung-Lu")
+    g = G.chung_lu(1 << 14, 240_000, seed=8)
+    R, k = 16, 20
+    dg = _dg(api, g)
+    res = api.relax(dg, R, k, seed=4)
+    rho = api.edge_dist(dg, res.x, res.minmax)
+    rho_o = oracle.algebraic_distance(g, R, k, 0.5, seed=4)
+    for orient in (0, 1):
+        e_o, keep_o, kept_o = oracle.fit_exponent(g, rho_o, orient, 0.3)
+        keep_fit, n_fit, e_fit = api.sparsify_fit(dg, rho, orient, 0.3)
+        assert abs(e_fit - e_o) <= 0.01
+        keep, n_kept = api.sparsify(dg, rho, orient, e_o)
+        bad = near_cut_mismatches(g, rho_o, _np(keep), keep_o, orient, e_o, 1e-5)
+        assert not bad, bad[:10]
+        assert abs(int(_np(n_kept)[0]) - kept_o) <= 0.001 * g.m
+
+
+# ------------------------------------------------------------- edge cases --
+
+def test_empty_and_tiny_graphs(api):
+    announce("edge cases: empty / tiny graphs")
+    # no edges at all
+    g = G.from_edges(5, np.zeros(0, int), np.zeros(0, int))
+    dg = _dg(api, g)
+    res = api.relax(dg, 3, 4, seed=1)
+    mm = _np(res.minmax)
+    assert np.all(np.isinf(mm[:3])) and np.all(mm[:3] > 0) and np.all(mm[3:] < 0)
+    x = _np(res.x).astype(np.float64) + _np(res.shift)
+    assert np.array_equal(x, oracle.start_vectors(5, 3, 1, 0, g.orig_id))
+    rho = api.edge_dist(dg, res.x, res.minmax)
+    assert rho.numel() == 0
+    keep, n_kept, e = api.sparsify_fit(dg, rho, 0, 0.3)
+    assert e == 0.0 and int(_np(n_kept)[0]) == 0
+    # one edge: both ends meet after one sweep, the rescale degenerates
+    g = G.from_edges(2, [0], [1])
+    dg = _dg(api, g)
+    for k in (1, 5):
+        res = api.relax(dg, 4, k, seed=1)
+        rho = _np(api.edge_dist(dg, res.x, res.minmax))
+        assert rho.tolist() == [0.0]
+    keep, n_kept = api.sparsify(dg, torch.zeros(1, device="cuda"), 0, 0.5)
+    assert _np(keep).tolist() == [1]
+
+
+@pytest.mark.parametrize("R", [1, 3, 8, 10, 16, 33, 64])
+@pytest.mark.parametrize("k", [0, 1, 7])
+def test_vector_counts_and_sweeps(api, R, k):
+    announce(f"R={R} k={k}")
+    g = G.relabel(G.gnm(777, 3000, 4), np.random.default_rng(1).permutation(777))
+    g = G.from_edges(780, g.edge_u, g.edge_v, G.random_weights(g.m, 3), orig_id=None)  # 3 isolated
+    dg = _dg(api, g)
+    res = api.relax(dg, R, k, seed=9, store="f64")
+    rho = _np(api.edge_dist(dg, res.x, res.minmax))
+    rho_o = oracle.algebraic_distance(g, R, k, 0.5, seed=9)
+    # Rescaled values carry absolute rounding (the oracle's "- 1/2" step alone
+    # leaves ~1e-16), so distances far below their typical size are compared
+    # against a floor of a tenth of the median distance.
+    floor = 0.1 * float(np.median(rho_o))
+    assert rel_stats(rho, rho_o, floor)["max"] <= 1e-12
+    res32 = api.relax(dg, R, k, seed=9, store="f32")
+    rho32 = _np(api.edge_dist(dg, res32.x, res32.minmax))
+    assert rel_stats(rho32, rho_o, floor)["max"] <= 1e-5
+
+
+def test_constant_start_is_fixed(api):
+    announce("constant start vector")
+    g = G.chung_lu(4000, 30000, seed=2)
+    dg = _dg(api, g)
+    x0 = torch.full((g.n, 4), 0.25, dtype=torch.float32, device="cuda")
+    res = api.relax(dg, 4, 20, x0=x0)
+    x = _np(res.x) + _np(res.shift).astype(np.float32)
+    assert np.all(x == 0.25)
+    rho = _np(api.edge_dist(dg, res.x, res.minmax))
+    assert np.all(rho == 0.0)
+
+
+def test_omega_other_than_half(api):
+    announce("omega 0.3 / 1.0")
+    g = G.chung_lu(3000, 20000, seed=5)
+    dg = _dg(api, g)
+    for om in (0.3, 1.0):
+        res = api.relax(dg, 8, 15, omega=om, store="f64")
+        rho = _np(api.edge_dist(dg, res.x, res.minmax))
+        rho_o = oracle.algebraic_distance(g, 8, 15, om, seed=0)
+        assert rel_stats(rho, rho_o)["max"] <= 1e-11
+
+
+def test_validate_graph_accepts_valid(api):
+    announce("validate graph")
+    for g in [G.gnm(500, 2000, 1), G.chung_lu(3000, 20000, seed=1), G.grid_long_range(20, 5)]:
+        api.validate_graph(_dg(api, g))
