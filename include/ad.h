@@ -221,6 +221,17 @@ ad_status ad_edge_to_entries(const ad_graph *g, const float *w_edge, float *w_en
 size_t ad_validate_workspace_size(const ad_graph *g);
 ad_status ad_validate_graph(const ad_graph *g, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Kernel timing (for measurement, off by default).  While enabled, the
+ * library brackets its main kernel launches (JOR sweep, distance, ranking,
+ * fit passes) with HIP events on the caller's stream; the events are
+ * created on the host when the launch is made.  ad_trace_summary waits for
+ * the recorded events and writes one line per kernel name,
+ * "<name> <launches> <total_ms>\n", into buf (len bytes, NUL-terminated);
+ * ad_trace_reset waits for and releases them. */
+void ad_trace_enable(int32_t on);
+void ad_trace_reset(void);
+ad_status ad_trace_summary(char *buf, size_t len);
+
 const char *ad_status_string(ad_status s);
 const char *ad_last_error(void);
 int32_t ad_abi_version(void);

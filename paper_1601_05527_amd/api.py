@@ -69,6 +69,9 @@ def _load_lib():
         "ad_edge_to_entries": (st, [G, P, P, P]),
         "ad_validate_workspace_size": (S, [G]),
         "ad_validate_graph": (st, [G, P, S, P]),
+        "ad_trace_enable": (None, [i32]),
+        "ad_trace_reset": (None, []),
+        "ad_trace_summary": (st, [ctypes.c_char_p, S]),
         "ad_status_string": (ctypes.c_char_p, [st]),
         "ad_last_error": (ctypes.c_char_p, []),
         "ad_abi_version": (i32, []),
@@ -102,6 +105,17 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     if ws.data_ptr() % 256:
         raise ADError(3, "workspace allocation is not 256-byte aligned")
     return ws
+
+
+def trace_summary() -> dict:
+    """{kernel name: (launches, total ms)} recorded while ad_trace_enable(1)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib.ad_trace_summary(buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out
 
 
 # ---------------------------------------------------------------- graphs ---

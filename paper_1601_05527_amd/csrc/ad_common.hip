@@ -4,6 +4,12 @@
 
 #include <math.h>
 #include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <vector>
 
 namespace ad {
 
@@ -146,9 +152,70 @@ __global__ void k_validate_eids(int64_t m, const unsigned int *__restrict__ eid_
         if (eid_uses[q] != 2u) atomicOr(flags, 128u);
 }
 
+// ------------------------------------------------------------------ trace --
+
+struct TraceRecord {
+    std::string name;
+    hipEvent_t a, b;
+};
+static std::atomic<bool> g_trace_on{false};
+static std::mutex g_trace_mu;
+static std::vector<TraceRecord> g_trace;
+
+TraceScope::TraceScope(const char *n, hipStream_t s) : name(n), stream(s) {
+    if (!g_trace_on.load(std::memory_order_relaxed)) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        a = b = nullptr;
+        return;
+    }
+    hipEventRecord(a, stream);
+}
+
+TraceScope::~TraceScope() {
+    if (!a) return;
+    hipEventRecord(b, stream);
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    g_trace.push_back({name, a, b});
+}
+
 }  // namespace ad
 
 using namespace ad;
+
+extern "C" void ad_trace_enable(int32_t on) { g_trace_on.store(on != 0); }
+
+extern "C" void ad_trace_reset(void) {
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    for (auto &r : g_trace) {
+        hipEventSynchronize(r.b);
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_trace.clear();
+}
+
+extern "C" ad_status ad_trace_summary(char *buf, size_t len) {
+    if (!buf || len == 0) return fail(AD_ERR_INVALID_ARG, "buffer is NULL");
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    std::map<std::string, std::pair<long long, double>> agg;
+    for (auto &r : g_trace) {
+        AD_HIP(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        AD_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        auto &e = agg[r.name];
+        e.first += 1;
+        e.second += ms;
+    }
+    std::string out;
+    char line[256];
+    for (auto &kv : agg) {
+        snprintf(line, sizeof(line), "%s %lld %.6f\n", kv.first.c_str(), kv.second.first, kv.second.second);
+        out += line;
+    }
+    if (out.size() + 1 > len) return fail(AD_ERR_INVALID_ARG, "buffer too small");
+    memcpy(buf, out.c_str(), out.size() + 1);
+    return AD_OK;
+}
 
 extern "C" size_t ad_validate_workspace_size(const ad_graph *g) {
     if (!g) return 0;

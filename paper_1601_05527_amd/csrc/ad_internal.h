@@ -172,6 +172,16 @@ ad_status collect_rows(const ad_graph *g, int64_t lo, int64_t hi, int32_t *list,
 
 ad_status check_graph_args(const ad_graph *g);
 
+// Kernel timing for ad_trace_*: while tracing is on, a TraceScope brackets
+// the launches made during its lifetime with HIP events on the stream.
+struct TraceScope {
+    const char *name;
+    hipStream_t stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    TraceScope(const char *name, hipStream_t s);
+    ~TraceScope();
+};
+
 // Launch shape of a JOR sweep (see ad_relax.hip).
 struct SweepShape {
     int vec, C, SPR, RPW, SPRW;

@@ -27,25 +27,39 @@
 namespace ad {
 
 constexpr int BLOCK = 256;
-constexpr int CENTRE_ROWS = 1024;   // rows per partial-sum block (fixed: keeps sums reproducible)
+constexpr int CENTRE_ROWS = 1024;
+constexpr int SWEEP_UNROLL = 8;     // row gathers in flight per lane   // rows per partial-sum block (fixed: keeps sums reproducible)
 
-// s_i = sum_j w_ij (FP64, CSR order); inv_s = 1/s_i (0 for isolated vertices).
+// s_i = sum_j w_ij in FP64 (LPR lanes per row, strided partial sums combined
+// by a fixed shuffle tree); inv_s = 1/s_i (0 for isolated vertices).
 template <typename A>
-__global__ void k_weighted_degree(int64_t n, const int64_t *__restrict__ row_ptr,
-                                  const float *__restrict__ w, A *__restrict__ inv_s,
-                                  float *__restrict__ sdeg) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t b = row_ptr[i], e = row_ptr[i + 1];
-        double s = 0.0;
-        if (w) {
-            for (int64_t p = b; p < e; ++p) s += (double)w[p];
-        } else {
-            s = (double)(e - b);
-        }
+__global__ __launch_bounds__(BLOCK) void k_weighted_degree(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                          const float *__restrict__ w, A *__restrict__ inv_s,
+                                                          float *__restrict__ sdeg, int LPR) {
+    const int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    int64_t b = 0, e = 0;
+    if (i < n) {
+        b = row_ptr[i];
+        e = row_ptr[i + 1];
+    }
+    double s = 0.0;
+    if (w) {
+        for (int64_t p = b + lane; p < e; p += LPR) s += (double)w[p];
+    } else if (lane == 0) {
+        s = (double)(e - b);
+    }
+    for (int d = LPR >> 1; d >= 1; d >>= 1) s += shfl_down(s, d);
+    if (i < n && lane == 0) {
         inv_s[i] = (e > b) ? (A)(1.0 / s) : (A)0;
         sdeg[i] = (float)s;
     }
+}
+
+static int degree_lanes(double avg) {
+    int lpr = 1;
+    while (lpr < 16 && lpr < avg) lpr <<= 1;
+    return lpr;
 }
 
 __device__ __forceinline__ double start_value(uint64_t seed, uint64_t gid, int32_t key, int r) {
@@ -94,21 +108,41 @@ __global__ void k_centre_partials(int64_t n, int R, const float *__restrict__ sd
 }
 
 // shift_r = weighted mean rounded to the 2^-24 grid; resets the min/max codes.
-__global__ void k_centre_finalize(int R, int64_t nblocks, const double *__restrict__ part,
-                                  const double *__restrict__ part_s, int centre,
-                                  double *__restrict__ shift, unsigned long long *__restrict__ mm) {
-    const int r = threadIdx.x;
-    if (r >= R) return;
-    double S = 0.0, a = 0.0;
-    for (int64_t b = 0; b < nblocks; ++b) {
-        S += part_s[b];
-        a += part[b * R + r];
+// One block: thread t sums partial blocks t, t+BLOCK, ... in order, then
+// thread 0 adds the BLOCK subtotals in order (a fixed summation tree).
+__global__ __launch_bounds__(BLOCK) void k_centre_finalize(int R, int64_t nblocks, const double *__restrict__ part,
+                                                          const double *__restrict__ part_s, int centre,
+                                                          double *__restrict__ shift,
+                                                          unsigned long long *__restrict__ mm) {
+    __shared__ double sub[BLOCK];
+    __shared__ double S;
+    const int t = threadIdx.x;
+    double a = 0.0;
+    for (int64_t b = t; b < nblocks; b += BLOCK) a += part_s[b];
+    sub[t] = a;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int q = 0; q < BLOCK; ++q) tot += sub[q];
+        S = tot;
     }
-    double sh = 0.0;
-    if (centre && S > 0.0) sh = rint((a / S) * 16777216.0) * (1.0 / 16777216.0);
-    shift[r] = sh;
-    mm[r] = ~0ull;       // running min code
-    mm[R + r] = 0ull;    // running max code
+    __syncthreads();
+    for (int r = 0; r < R; ++r) {
+        a = 0.0;
+        for (int64_t b = t; b < nblocks; b += BLOCK) a += part[b * R + r];
+        sub[t] = a;
+        __syncthreads();
+        if (t == 0) {
+            double tot = 0.0;
+            for (int q = 0; q < BLOCK; ++q) tot += sub[q];
+            double sh = 0.0;
+            if (centre && S > 0.0) sh = rint((tot / S) * 16777216.0) * (1.0 / 16777216.0);
+            shift[r] = sh;
+            mm[r] = ~0ull;       // running min code
+            mm[R + r] = 0ull;    // running max code
+        }
+        __syncthreads();
+    }
 }
 
 // x^(0) - shift into the start buffer.  One Philox block feeds 4 vectors.
@@ -136,23 +170,107 @@ __global__ void k_init(int64_t n, int R, const int32_t *__restrict__ orig_id, ui
     }
 }
 
-// One JOR sweep for rows with degree <= hub_d.
-//   lane -> (row in wave rw, slot, chunk); C lanes per neighbour row,
-//   SPR slots per row, RPW rows per wave, 4 waves per block.
-template <typename Tin, typename Tout, typename A, int VEC>
+// Accumulate sum_j w_ij x_j over the entries p0, p0 + stride, p0 + 2 stride,
+// ... < end into acc (VEC values of one lane's chunk), in that order.  U
+// column/weight pairs are loaded first, then U gathers are issued together,
+// so each lane keeps U row reads in flight.
+template <int U, int VEC, typename Tin, typename A>
+__device__ __forceinline__ void gather_rows(const int32_t *__restrict__ col, const float *__restrict__ w,
+                                            const Tin *__restrict__ xin, int64_t p0, int64_t end,
+                                            int64_t stride, int R, int off, A (&acc)[VEC]) {
+    for (int64_t p = p0; p < end; p += (int64_t)U * stride) {
+        int32_t jj[U];
+        A ww[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = p + u * stride;
+            const bool ok = q < end;
+            jj[u] = ok ? col[q] : -1;
+            ww[u] = ok ? (w ? (A)w[q] : (A)1) : (A)0;
+        }
+        A v[U][VEC];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (jj[u] >= 0) {
+                load_vec<VEC>(xin + (int64_t)jj[u] * R + off, v[u]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) v[u][q] = (A)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = fma(ww[u], v[u][q], acc[q]);
+        }
+    }
+}
+
+// One JOR sweep over all rows, in one launch.
+// Blocks [0, hub_blocks) take the listed long rows (degree > hub_d), one row
+// per 256-thread workgroup at a time: SPRW slots per wave, partial sums
+// combined across the 4 waves in LDS.  They come first so the longest work
+// starts first.  Blocks [hub_blocks, ...) take the other rows: per wave RPW
+// rows; per row SPR slots of C lanes, VEC values per lane.
+template <typename Tin, typename Tout, typename A, int VEC, int U>
 __global__ __launch_bounds__(BLOCK) void k_sweep(
     int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const float *__restrict__ w, const A *__restrict__ inv_s, A omega,
     const Tin *__restrict__ xin, Tout *__restrict__ xout, int R, int C, int SPR, int RPW,
-    int64_t hub_d) {
+    int64_t hub_d, int SPRW, int hub_blocks, const int32_t *__restrict__ hub_list,
+    const unsigned int *__restrict__ hub_count) {
+    __shared__ A part[BLOCK / WAVE][64];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
+    const A keep = (A)1 - omega;
+    if ((int)blockIdx.x < hub_blocks) {
+        const int slot_w = lane / C;
+        const int chunk = lane - slot_w * C;
+        const bool lane_on = slot_w < SPRW;
+        const int slots = SPRW * (BLOCK / WAVE);
+        const int slot = wave * SPRW + slot_w;
+        const int off = chunk * VEC;
+        const unsigned int nh = *hub_count;
+        for (unsigned int h = blockIdx.x; h < nh; h += hub_blocks) {
+            const int64_t row = hub_list[h];
+            const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
+            A acc[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = (A)0;
+            if (lane_on) gather_rows<U, VEC>(col, w, xin, beg + slot, end, slots, R, off, acc);
+            for (int d = SPRW >> 1; d >= 1; d >>= 1) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[q] += shfl_down(acc[q], d * C);
+            }
+            if (lane_on && slot_w == 0) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) part[wave][off + q] = acc[q];
+            }
+            __syncthreads();
+            if (wave == 0 && lane_on && slot_w == 0) {
+                A sum[VEC], own[VEC], res[VEC];
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) sum[q] = part[0][off + q];
+                for (int wv = 1; wv < BLOCK / WAVE; ++wv) {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) sum[q] += part[wv][off + q];
+                }
+                load_vec<VEC>(xin + row * R + off, own);
+                const A is = inv_s[row];
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) res[q] = fma(omega, sum[q] * is, keep * own[q]);
+                store_vec<VEC>(xout + row * R + off, res);
+            }
+            __syncthreads();
+        }
+        return;
+    }
     const int group = C * SPR;
     const int rw = lane / group;
     const int sub = lane - rw * group;
     const int slot = sub / C;
     const int chunk = sub - slot * C;
-    const int64_t row = ((int64_t)blockIdx.x * (BLOCK / WAVE) + wave) * RPW + rw;
+    const int64_t row = ((int64_t)(blockIdx.x - hub_blocks) * (BLOCK / WAVE) + wave) * RPW + rw;
     const bool active = (rw < RPW) && (row < n);
     int64_t beg = 0, end = 0;
     if (active) {
@@ -160,44 +278,26 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
         end = row_ptr[row + 1];
     }
     const bool hub = (end - beg) > hub_d;
+    const bool writer = active && !hub && slot == 0;
+    const int off = chunk * VEC;
+    // the row's own values and 1/s do not depend on the gathers: load them first
+    A own[VEC];
+    A is = (A)0;
+    if (writer) {
+        load_vec<VEC>(xin + row * R + off, own);
+        is = inv_s[row];
+    }
     A acc[VEC];
 #pragma unroll
     for (int q = 0; q < VEC; ++q) acc[q] = (A)0;
-    if (active && !hub) {
-        const int off = chunk * VEC;
-        int64_t p = beg + slot;
-        // two neighbours per step keep two gathers in flight per lane
-        for (; p + SPR < end; p += 2 * SPR) {
-            int32_t j0 = col[p], j1 = col[p + SPR];
-            A w0 = w ? (A)w[p] : (A)1, w1 = w ? (A)w[p + SPR] : (A)1;
-            A v0[VEC], v1[VEC];
-            load_vec<VEC>(xin + (int64_t)j0 * R + off, v0);
-            load_vec<VEC>(xin + (int64_t)j1 * R + off, v1);
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) acc[q] = fma(w0, v0[q], acc[q]);
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) acc[q] = fma(w1, v1[q], acc[q]);
-        }
-        if (p < end) {
-            int32_t j0 = col[p];
-            A w0 = w ? (A)w[p] : (A)1;
-            A v0[VEC];
-            load_vec<VEC>(xin + (int64_t)j0 * R + off, v0);
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) acc[q] = fma(w0, v0[q], acc[q]);
-        }
-    }
+    if (active && !hub) gather_rows<U, VEC>(col, w, xin, beg + slot, end, SPR, R, off, acc);
     for (int d = SPR >> 1; d >= 1; d >>= 1) {
 #pragma unroll
         for (int q = 0; q < VEC; ++q) acc[q] += shfl_down(acc[q], d * C);
     }
-    if (active && !hub && slot == 0) {
-        const int off = chunk * VEC;
-        A own[VEC], res[VEC];
-        load_vec<VEC>(xin + row * R + off, own);
+    if (writer) {
+        A res[VEC];
         if (end > beg) {
-            const A is = inv_s[row];
-            const A keep = (A)1 - omega;
 #pragma unroll
             for (int q = 0; q < VEC; ++q) res[q] = fma(omega, acc[q] * is, keep * own[q]);
         } else {
@@ -205,80 +305,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
             for (int q = 0; q < VEC; ++q) res[q] = own[q];
         }
         store_vec<VEC>(xout + row * R + off, res);
-    }
-}
-
-// One JOR sweep for the listed long rows: a 256-thread workgroup per row,
-// SPRW slots per wave, partial sums combined across the 4 waves in LDS.
-template <typename Tin, typename Tout, typename A, int VEC>
-__global__ __launch_bounds__(BLOCK) void k_sweep_hub(
-    const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
-    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const float *__restrict__ w, const A *__restrict__ inv_s, A omega,
-    const Tin *__restrict__ xin, Tout *__restrict__ xout, int R, int C, int SPRW) {
-    __shared__ A part[BLOCK / WAVE][64];
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = threadIdx.x >> 6;
-    const int slot_w = lane / C;             // slot within the wave
-    const int chunk = lane - slot_w * C;
-    const bool lane_on = slot_w < SPRW;
-    const int slots = SPRW * (BLOCK / WAVE);
-    const int slot = wave * SPRW + slot_w;
-    const unsigned int nh = *count;
-    for (unsigned int h = blockIdx.x; h < nh; h += gridDim.x) {
-        const int64_t row = list[h];
-        const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
-        const int off = chunk * VEC;
-        A acc[VEC];
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) acc[q] = (A)0;
-        if (lane_on) {
-            int64_t p = beg + slot;
-            for (; p + slots < end; p += 2 * slots) {
-                int32_t j0 = col[p], j1 = col[p + slots];
-                A w0 = w ? (A)w[p] : (A)1, w1 = w ? (A)w[p + slots] : (A)1;
-                A v0[VEC], v1[VEC];
-                load_vec<VEC>(xin + (int64_t)j0 * R + off, v0);
-                load_vec<VEC>(xin + (int64_t)j1 * R + off, v1);
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) acc[q] = fma(w0, v0[q], acc[q]);
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) acc[q] = fma(w1, v1[q], acc[q]);
-            }
-            if (p < end) {
-                int32_t j0 = col[p];
-                A w0 = w ? (A)w[p] : (A)1;
-                A v0[VEC];
-                load_vec<VEC>(xin + (int64_t)j0 * R + off, v0);
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) acc[q] = fma(w0, v0[q], acc[q]);
-            }
-        }
-        for (int d = SPRW >> 1; d >= 1; d >>= 1) {
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) acc[q] += shfl_down(acc[q], d * C);
-        }
-        if (lane_on && slot_w == 0) {
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) part[wave][off + q] = acc[q];
-        }
-        __syncthreads();
-        if (wave == 0 && lane_on && slot_w == 0) {
-            A sum[VEC], own[VEC], res[VEC];
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) sum[q] = part[0][off + q];
-            for (int wv = 1; wv < BLOCK / WAVE; ++wv) {
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) sum[q] += part[wv][off + q];
-            }
-            load_vec<VEC>(xin + row * R + off, own);
-            const A is = inv_s[row];
-            const A keep = (A)1 - omega;
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) res[q] = fma(omega, sum[q] * is, keep * own[q]);
-            store_vec<VEC>(xout + row * R + off, res);
-        }
-        __syncthreads();
     }
 }
 
@@ -351,9 +377,9 @@ SweepShape sweep_shape(int R, size_t in_bytes, double avg_deg, int rpw_req, int6
     int spr_max = pow2_slots(WAVE, s.C);
     int rpw = rpw_req;
     if (rpw <= 0) {
-        // aim for about two neighbours per slot on an average row
+        // enough slots that an average row needs one round of SWEEP_UNROLL gathers
         int want = 1;
-        while (want * 2 <= (int)ceil(avg_deg / 2.0) && want * 2 <= spr_max) want *= 2;
+        while (want < spr_max && want * SWEEP_UNROLL < avg_deg) want *= 2;
         rpw = std::max(1, spr_max / want);
     }
     if (rpw > spr_max) rpw = spr_max;
@@ -371,21 +397,19 @@ template <typename Tin, typename Tout, typename A, int VEC>
 static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout,
                                 int R, const SweepShape &sh, const int32_t *hub_list,
                                 const unsigned int *hub_count, hipStream_t st) {
-    int64_t rows_per_block = (int64_t)(BLOCK / WAVE) * sh.RPW;
-    int64_t nb = ceil_div(g->n, rows_per_block);
-    if (nb > 0) {
-        hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC>), dim3((unsigned)nb), dim3(BLOCK), 0, st,
-                           g->n, g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C, sh.SPR,
-                           sh.RPW, sh.hub_d);
-        AD_LAUNCH_CHECK("k_sweep");
-    }
-    if (g->d_max > sh.hub_d || g->d_max == 0) {
-        unsigned grid = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, g->n));
-        hipLaunchKernelGGL((k_sweep_hub<Tin, Tout, A, VEC>), dim3(grid), dim3(BLOCK), 0, st, hub_list,
-                           hub_count, g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C,
-                           sh.SPRW);
-        AD_LAUNCH_CHECK("k_sweep_hub");
-    }
+    const int64_t rows_per_block = (int64_t)(BLOCK / WAVE) * sh.RPW;
+    const int64_t main_blocks = ceil_div(g->n, rows_per_block);
+    // at most 2m / hub_d rows exceed hub_d; unknown d_max (0) keeps the bound
+    int64_t hub_blocks = 0;
+    if (g->d_max == 0 || g->d_max > sh.hub_d)
+        hub_blocks = std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(2 * g->m, sh.hub_d + 1)));
+    const int64_t grid = main_blocks + hub_blocks;
+    if (grid <= 0) return AD_OK;
+    TraceScope trace("k_sweep", st);
+    hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC, SWEEP_UNROLL>), dim3((unsigned)grid), dim3(BLOCK), 0, st, g->n,
+                       g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C, sh.SPR, sh.RPW, sh.hub_d,
+                       sh.SPRW, (int)hub_blocks, hub_list, hub_count);
+    AD_LAUNCH_CHECK("k_sweep");
     return AD_OK;
 }
 
@@ -472,14 +496,15 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
     ad_status s;
 
     if (n > 0) {
-        hipLaunchKernelGGL((k_weighted_degree<A>), dim3(grid_for(n, BLOCK)), dim3(BLOCK), 0, st, n,
-                           g->row_ptr, g->w, (A *)L.inv_s, L.sdeg);
+        const int lpr = degree_lanes(avg);
+        hipLaunchKernelGGL((k_weighted_degree<A>), dim3((unsigned)ceil_div(n * lpr, BLOCK)), dim3(BLOCK), 0, st,
+                           n, g->row_ptr, g->w, (A *)L.inv_s, L.sdeg, lpr);
         AD_LAUNCH_CHECK("k_weighted_degree");
         hipLaunchKernelGGL((k_centre_partials<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, L.sdeg,
                            g->orig_id, o->seed, o->graph_id, (const T *)x0, L.part, L.part_s);
         AD_LAUNCH_CHECK("k_centre_partials");
     }
-    hipLaunchKernelGGL(k_centre_finalize, dim3(1), dim3(64), 0, st, R, n > 0 ? nb : (int64_t)0, L.part,
+    hipLaunchKernelGGL(k_centre_finalize, dim3(1), dim3(BLOCK), 0, st, R, n > 0 ? nb : (int64_t)0, L.part,
                        L.part_s, 1, L.shift, L.mm);
     AD_LAUNCH_CHECK("k_centre_finalize");
 
@@ -547,7 +572,8 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
 
     if (n > 0) {
         int stride = BLOCK / R;
-        hipLaunchKernelGGL((k_minmax<T>), dim3(grid_for(ceil_div(n, stride), 1)), dim3(BLOCK), 0, st, n,
+        const int64_t mm_blocks = std::min<int64_t>(1024, ceil_div(n, stride));
+        hipLaunchKernelGGL((k_minmax<T>), dim3((unsigned)mm_blocks), dim3(BLOCK), 0, st, n,
                            R, g->row_ptr, (const T *)x_out, L.mm);
         AD_LAUNCH_CHECK("k_minmax");
     }
@@ -564,8 +590,9 @@ ad_status sweep_f32(const ad_graph *g, const float *inv_s, float omega, const fl
 
 ad_status weighted_degree_f32(const ad_graph *g, float *inv_s, float *sdeg, hipStream_t st) {
     if (g->n <= 0) return AD_OK;
-    hipLaunchKernelGGL((k_weighted_degree<float>), dim3(grid_for(g->n, BLOCK)), dim3(BLOCK), 0, st, g->n,
-                       g->row_ptr, g->w, inv_s, sdeg);
+    const int lpr = degree_lanes((double)(2 * g->m) / (double)g->n);
+    hipLaunchKernelGGL((k_weighted_degree<float>), dim3((unsigned)ceil_div(g->n * lpr, BLOCK)), dim3(BLOCK), 0,
+                       st, g->n, g->row_ptr, g->w, inv_s, sdeg, lpr);
     AD_LAUNCH_CHECK("k_weighted_degree");
     return AD_OK;
 }

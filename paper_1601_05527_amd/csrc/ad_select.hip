@@ -34,6 +34,7 @@ namespace ad {
 
 constexpr int SBLOCK = 256;
 constexpr int SORT_CAP = 8192;       // longest row ranked in LDS
+constexpr int WAVE_CAP = 512;        // longest row ranked inside one wave
 
 // ---------------------------------------------------------------- distance --
 
@@ -115,6 +116,7 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_small(
         d = row_ptr[row + 1] - beg;
     }
     const bool mine = (d > dlo && d <= SW);
+    if (!__any(mine)) return;          // wave-uniform: no row of this class here
     Tr my_rho = (Tr)0;
     int32_t my_id = 0, my_j = 0, my_e = 0;
     if (mine && q < d) {
@@ -139,6 +141,58 @@ __device__ __forceinline__ unsigned long long sort_key(float r, int32_t id, int 
     uint32_t b = __float_as_uint(r);                 // rho >= 0: bits are monotone
     if (orient == AD_GLOBAL) b = ~b;
     return ((unsigned long long)b << 32) | (unsigned long long)(uint32_t)id;
+}
+
+// Listed rows with 64 < d <= 64 * KPL (FP32 distances): one wave per row,
+// KPL keys per lane; each key's rank counts the smaller keys of the row,
+// broadcast one lane at a time.
+template <int KPL>
+__global__ __launch_bounds__(SBLOCK) void k_rank_wave(
+    const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id, const float *__restrict__ rho,
+    int orient, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
+    unsigned long long *__restrict__ sides) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned int nr = *count;
+    const unsigned int waves = gridDim.x * (SBLOCK / WAVE);
+    for (unsigned int h = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); h < nr; h += waves) {
+        const int64_t row = list[h];
+        const int64_t beg = row_ptr[row];
+        const int d = (int)(row_ptr[row + 1] - beg);
+        unsigned long long key[KPL];
+        int32_t jj[KPL], ee[KPL];
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+            const int q = t * WAVE + lane;
+            if (q < d) {
+                jj[t] = col[beg + q];
+                ee[t] = eid[beg + q];
+                key[t] = sort_key(rho[ee[t]], orig_id ? orig_id[jj[t]] : jj[t], orient);
+            } else {
+                jj[t] = 0;
+                ee[t] = 0;
+                key[t] = ~0ull;
+            }
+        }
+        int rank[KPL];
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) rank[t] = 0;
+#pragma unroll
+        for (int ts = 0; ts < KPL; ++ts) {
+            if (ts * WAVE >= d) break;                 // uniform across the wave
+            for (int src = 0; src < WAVE; ++src) {
+                const unsigned long long k = shfl(key[ts], src);
+#pragma unroll
+                for (int t = 0; t < KPL; ++t) rank[t] += (k < key[t]) ? 1 : 0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+            const int q = t * WAVE + lane;
+            if (q < d) emit(mode, row, jj[t], ee[t], d, rank[t], budget, keep, sides);
+        }
+    }
 }
 
 // Listed rows with 64 < d <= SORT_CAP (FP32 distances): bitonic sort in LDS.
@@ -225,14 +279,30 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_count(
     }
 }
 
+// Block-wide sum of per-thread counts; thread 0 adds it to *out (one atomic
+// per block; integer addition, so the total does not depend on order).
+__device__ __forceinline__ void block_add(unsigned long long c, unsigned long long *out) {
+    __shared__ unsigned long long part[SBLOCK / WAVE];
+    for (int d = WAVE / 2; d >= 1; d >>= 1) c += shfl_down(c, d);
+    if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < SBLOCK / WAVE; ++w) t += part[w];
+        if (t) atomicAdd(out, t);
+    }
+}
+
+constexpr int COUNT_BLOCKS = 512;
+
 // Sum of a byte mask into a 64-bit device counter.
-__global__ void k_count_bytes(int64_t m, const uint8_t *__restrict__ keep, unsigned long long *out) {
+__global__ __launch_bounds__(SBLOCK) void k_count_bytes(int64_t m, const uint8_t *__restrict__ keep,
+                                                       unsigned long long *out) {
     unsigned long long c = 0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m;
          q += (int64_t)gridDim.x * blockDim.x)
         c += keep[q];
-    for (int d = WAVE / 2; d >= 1; d >>= 1) c += shfl_down(c, d);
-    if ((threadIdx.x & (WAVE - 1)) == 0 && c) atomicAdd(out, c);
+    block_add(c, out);
 }
 
 // ---------------------------------------------------------------------- fit --
@@ -278,12 +348,23 @@ __global__ __launch_bounds__(SBLOCK) void k_radix_hist(int64_t m, const unsigned
     for (int b = threadIdx.x; b < NBINS; b += SBLOCK) h[b] = 0;
     __syncthreads();
     const unsigned long long prefix = state[0];
+    // runs of equal bins in one thread's sequence are added at once
+    int last = -1;
+    unsigned int run = 0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
         unsigned long long g = G[e];
         if (pass > 0 && (g >> (shift + DIGIT)) != prefix) continue;
-        atomicAdd(&h[(g >> shift) & (NBINS - 1)], 1u);
+        const int b = (int)((g >> shift) & (NBINS - 1));
+        if (b == last) {
+            ++run;
+        } else {
+            if (run) atomicAdd(&h[last], run);
+            last = b;
+            run = 1;
+        }
     }
+    if (run) atomicAdd(&h[last], run);
     __syncthreads();
     for (int b = threadIdx.x; b < NBINS; b += SBLOCK)
         if (h[b]) atomicAdd(&hist[b], h[b]);
@@ -310,7 +391,7 @@ __global__ __launch_bounds__(SBLOCK) void k_radix_pick(const unsigned int *__res
 }
 
 // Exact counts at two grid points from host budget tables; keep[] for the first.
-__global__ void k_fit_count(int64_t m, const unsigned long long *__restrict__ sides,
+__global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const unsigned long long *__restrict__ sides,
                             const int32_t *__restrict__ tab_hi, const int32_t *__restrict__ tab_lo,
                             int use_lo, uint8_t *__restrict__ keep,
                             unsigned long long *__restrict__ counts) {
@@ -325,14 +406,9 @@ __global__ void k_fit_count(int64_t m, const unsigned long long *__restrict__ si
         c_hi += k_hi;
         if (use_lo) c_lo += (ra < (unsigned long long)tab_lo[da] || rb < (unsigned long long)tab_lo[db]);
     }
-    for (int d = WAVE / 2; d >= 1; d >>= 1) {
-        c_hi += shfl_down(c_hi, d);
-        c_lo += shfl_down(c_lo, d);
-    }
-    if ((threadIdx.x & (WAVE - 1)) == 0) {
-        if (c_hi) atomicAdd(&counts[0], c_hi);
-        if (c_lo) atomicAdd(&counts[1], c_lo);
-    }
+    block_add(c_hi, &counts[0]);
+    __syncthreads();
+    block_add(c_lo, &counts[1]);
 }
 
 __global__ void k_store_count(const unsigned long long *__restrict__ c, int64_t *__restrict__ out) {
@@ -342,8 +418,8 @@ __global__ void k_store_count(const unsigned long long *__restrict__ c, int64_t 
 // ------------------------------------------------------------------- host --
 
 struct SelLayout {
-    int32_t *list_big, *list_huge;
-    unsigned int *cnt;            // [2]: big, huge
+    int32_t *list_big, *list_mid, *list_huge;
+    unsigned int *cnt;            // [3]: wave-ranked, huge, LDS-sorted
     unsigned long long *sides;    // [2m]
     unsigned long long *G;        // [m]
     unsigned int *hist;           // [NBINS]
@@ -357,8 +433,9 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     const int64_t n = std::max<int64_t>(1, g->n), m = std::max<int64_t>(1, g->m);
     SelLayout l;
     l.list_big = c.take<int32_t>(n);
+    l.list_mid = c.take<int32_t>(n);
     l.list_huge = c.take<int32_t>(n);
-    l.cnt = c.take<unsigned int>(2);
+    l.cnt = c.take<unsigned int>(3);
     l.sides = c.take<unsigned long long>(2 * m);
     l.G = c.take<unsigned long long>(m);
     l.hist = c.take<unsigned int>(NBINS);
@@ -387,6 +464,7 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, int orient, int mode
                           uint8_t *keep, const SelLayout &L, hipStream_t st) {
     const int64_t n = g->n;
     if (n <= 0 || g->m <= 0) return AD_OK;
+    TraceScope trace("k_rank", st);
     const int rows_per_block_8 = (SBLOCK / WAVE) * (WAVE / 8);
     hipLaunchKernelGGL((k_rank_small<Tr, 8>), dim3((unsigned)ceil_div(n, rows_per_block_8)), dim3(SBLOCK), 0,
                        st, n, g->row_ptr, g->col, g->eid, g->orig_id, rho, orient, mode, (int64_t)0, budget,
@@ -414,18 +492,26 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, int orient, int mode
         AD_LAUNCH_CHECK("k_rank_small<64>");
     }
     if (g->d_max > 64) {
-        ad_status s = fill_i32((int32_t *)L.cnt, 0, 2, st);
+        ad_status s = fill_i32((int32_t *)L.cnt, 0, 3, st);
         if (s != AD_OK) return s;
         const bool f32 = sizeof(Tr) == 4;
         const int64_t cap = f32 ? SORT_CAP : 64;
-        s = collect_rows(g, 64, cap, L.list_big, &L.cnt[0], st);
-        if (s != AD_OK) return s;
         unsigned grid = (unsigned)std::min<int64_t>(2048, n);
         if (f32) {
-            hipLaunchKernelGGL(k_rank_bitonic, dim3(grid), dim3(SBLOCK), 0, st, L.list_big, &L.cnt[0],
-                               g->row_ptr, g->col, g->eid, g->orig_id, (const float *)rho, orient, mode, budget,
-                               keep, L.sides);
-            AD_LAUNCH_CHECK("k_rank_bitonic");
+            s = collect_rows(g, 64, WAVE_CAP, L.list_big, &L.cnt[0], st);
+            if (s != AD_OK) return s;
+            hipLaunchKernelGGL((k_rank_wave<WAVE_CAP / WAVE>), dim3(grid), dim3(SBLOCK), 0, st, L.list_big,
+                               &L.cnt[0], g->row_ptr, g->col, g->eid, g->orig_id, (const float *)rho, orient, mode,
+                               budget, keep, L.sides);
+            AD_LAUNCH_CHECK("k_rank_wave");
+            if (g->d_max > WAVE_CAP) {
+                s = collect_rows(g, WAVE_CAP, cap, L.list_mid, &L.cnt[2], st);
+                if (s != AD_OK) return s;
+                hipLaunchKernelGGL(k_rank_bitonic, dim3(grid), dim3(SBLOCK), 0, st, L.list_mid, &L.cnt[2],
+                                   g->row_ptr, g->col, g->eid, g->orig_id, (const float *)rho, orient, mode,
+                                   budget, keep, L.sides);
+                AD_LAUNCH_CHECK("k_rank_bitonic");
+            }
         }
         if (g->d_max > cap) {
             s = collect_rows(g, cap, (int64_t)1 << 62, L.list_huge, &L.cnt[1], st);
@@ -470,6 +556,7 @@ extern "C" ad_status ad_edge_dist(const ad_graph *g, int32_t R, ad_dtype x_dtype
     int lpr = 1;
     while (lpr < 64 && lpr < avg) lpr <<= 1;   // lanes per row ~ average degree
     const unsigned nb = (unsigned)ceil_div(g->n, SBLOCK / lpr);
+    TraceScope trace("k_edge_dist", stream);
     if (x_dtype == AD_F64) {
         if (R % 2 == 0)
             hipLaunchKernelGGL((k_edge_dist<double, double, 2>), dim3(nb), dim3(SBLOCK), 0, stream, g->n, g->row_ptr,
@@ -524,7 +611,8 @@ extern "C" ad_status ad_sparsify(const ad_graph *g, ad_dtype rho_dtype, const vo
         else
             s = rank_all<double>(g, (const double *)rho, orient, MODE_FIXED, budget, keep, L, stream);
         if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_count_bytes, dim3(grid_for(g->m, SBLOCK)), dim3(SBLOCK), 0, stream, g->m, keep,
+        hipLaunchKernelGGL(k_count_bytes, dim3((unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(g->m, SBLOCK))),
+                           dim3(SBLOCK), 0, stream, g->m, keep,
                            L.counts);
         AD_LAUNCH_CHECK("k_count_bytes");
     }
@@ -563,6 +651,7 @@ extern "C" ad_status ad_sparsify_fit(const ad_graph *g, ad_dtype rho_dtype, cons
     else
         s = rank_all<double>(g, (const double *)rho, orient, MODE_SIDES, nullptr, keep, L, stream);
     if (s != AD_OK) return s;
+    TraceScope trace_fit("k_fit_select", stream);
     hipLaunchKernelGGL(k_fit_grid, dim3(grid_for(m, SBLOCK)), dim3(SBLOCK), 0, stream, m, L.sides, L.G);
     AD_LAUNCH_CHECK("k_fit_grid");
     hipLaunchKernelGGL(k_select_init, dim3(1), dim3(1), 0, stream, L.state, (unsigned long long)K);
@@ -571,7 +660,8 @@ extern "C" ad_status ad_sparsify_fit(const ad_graph *g, ad_dtype rho_dtype, cons
         const int shift = (3 - pass) * DIGIT;
         s = fill_i32((int32_t *)L.hist, 0, NBINS, stream);
         if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_radix_hist, dim3(grid_for(m, SBLOCK)), dim3(SBLOCK), 0, stream, m, L.G, shift, pass,
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, SBLOCK))),
+                           dim3(SBLOCK), 0, stream, m, L.G, shift, pass,
                            L.state, L.hist);
         AD_LAUNCH_CHECK("k_radix_hist");
         hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(SBLOCK), 0, stream, L.hist, L.state);
@@ -597,7 +687,8 @@ extern "C" ad_status ad_sparsify_fit(const ad_graph *g, ad_dtype rho_dtype, cons
         AD_HIP(hipMemcpyAsync(L.tab_lo, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
         s = fill_u64(L.counts, 0, 2, stream);
         if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_fit_count, dim3(grid_for(m, SBLOCK)), dim3(SBLOCK), 0, stream, m, L.sides, L.tab_hi,
+        hipLaunchKernelGGL(k_fit_count, dim3((unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, SBLOCK))),
+                           dim3(SBLOCK), 0, stream, m, L.sides, L.tab_hi,
                            L.tab_lo, use_lo ? 1 : 0, keep, L.counts);
         AD_LAUNCH_CHECK("k_fit_count");
         AD_HIP(hipMemcpyAsync(hc, L.counts, sizeof(hc), hipMemcpyDeviceToHost, stream));
