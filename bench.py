@@ -66,6 +66,9 @@ def main() -> int:
     ap.add_argument("--layout", choices=["degree", "given"], default="degree")
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--hub-degree", type=int, default=0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, copy a buffer of this many MiB device to device "
+                         "(a kernel of known traffic for calibrating memory counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -115,6 +118,16 @@ def main() -> int:
         _, _, e_l = api.sparsify_fit(dg, rho, api.AD_LOCAL, TARGET, ws=ws_s, keep=keep_l, n_kept=nk_l)
         _, _, e_g = api.sparsify_fit(dg, rho, api.AD_GLOBAL, TARGET, ws=ws_s, keep=keep_g, n_kept=nk_g)
         fit["e_local"], fit["e_global"] = e_l, e_g
+
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {nb} bytes done")
+        del src, dst
 
     for _ in range(args.warmup):
         step()

@@ -225,8 +225,7 @@ __global__ void k_adj_fold(int64_t nnz, const int32_t *__restrict__ eid, const f
 
 struct BwdLayout {
     float *inv_s, *sdeg, *ones;
-    int32_t *hub_list;
-    unsigned int *hub_count;
+    SweepPlan plan;
     float *xbh, *lam, *lam2, *mu, *y, *seg, *g;
     double *part;
     unsigned long long *arg;
@@ -242,8 +241,7 @@ static size_t bwd_layout(const ad_graph *g, const ad_relax_opts *o, void *ws, si
     l.inv_s = c.take<float>(n);
     l.sdeg = c.take<float>(n);
     l.ones = c.take<float>(n);
-    l.hub_list = c.take<int32_t>(n);
-    l.hub_count = c.take<unsigned int>(1);
+    sweep_plan_carve(c, n, l.plan);
     l.xbh = c.take<float>(nR);
     l.lam = c.take<float>(nR);
     l.lam2 = c.take<float>(nR);
@@ -357,10 +355,9 @@ extern "C" ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o
     AD_LAUNCH_CHECK("k_adj_corner");
 
     // reverse sweeps, one checkpoint segment at a time
-    SweepShape sh = sweep_shape(R, sizeof(float), avg, o->rows_per_wave, o->hub_degree);
-    s = fill_i32((int32_t *)L.hub_count, 0, 1, stream);
-    if (s != AD_OK) return s;
-    s = collect_rows(g, sh.hub_d, (int64_t)1 << 62, L.hub_list, L.hub_count, stream);
+    SweepPlan plan = L.plan;
+    plan.sh = sweep_shape(R, sizeof(float), o->rows_per_wave, o->hub_degree);
+    s = sweep_plan_build(g, plan, true, stream);
     if (s != AD_OK) return s;
     const int c = o->ckpt_every;
     const int nseg = ad_relax_num_checkpoints(o);
@@ -372,14 +369,14 @@ extern "C" ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o
         // seg[u] = x^(t0 + u), u = 0 .. t1 - t0 - 1
         for (int u = 1; u < t1 - t0; ++u) {
             const float *src = u == 1 ? base : L.seg + (size_t)(u - 1) * nR;
-            s = sweep_f32(g, L.inv_s, omega, src, L.seg + (size_t)u * nR, R, sh, L.hub_list, L.hub_count, stream);
+            s = sweep_f32(g, L.inv_s, omega, src, L.seg + (size_t)u * nR, R, plan, stream);
             if (s != AD_OK) return s;
         }
         for (int t = t1; t > t0; --t) {
             const int u = t - 1 - t0;
             const float *xprev = u == 0 ? base : L.seg + (size_t)u * nR;
             // y = S^-1 W x^(t-1): the sweep kernel with omega = 1
-            s = sweep_f32(g, L.inv_s, 1.0f, xprev, L.y, R, sh, L.hub_list, L.hub_count, stream);
+            s = sweep_f32(g, L.inv_s, 1.0f, xprev, L.y, R, plan, stream);
             if (s != AD_OK) return s;
             if (R <= 8) s = launch_grad<8>(g, L, omega, xprev, lam, R, lpr, stream);
             else if (R <= 16) s = launch_grad<16>(g, L, omega, xprev, lam, R, lpr, stream);
@@ -390,7 +387,7 @@ extern "C" ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o
             hipLaunchKernelGGL(k_adj_scale_rows, dim3(grid_for((int64_t)nR, BB)), dim3(BB), 0, stream, n, R, lam,
                                L.inv_s, L.mu);
             AD_LAUNCH_CHECK("k_adj_scale_rows");
-            s = sweep_f32(g, L.ones, 1.0f, L.mu, L.y, R, sh, L.hub_list, L.hub_count, stream);
+            s = sweep_f32(g, L.ones, 1.0f, L.mu, L.y, R, plan, stream);
             if (s != AD_OK) return s;
             hipLaunchKernelGGL(k_adj_axpby, dim3(grid_for((int64_t)nR, BB)), dim3(BB), 0, stream, (int64_t)nR,
                                omega, lam, L.y, lam_next);

@@ -152,6 +152,7 @@ inline int pow2_slots(int lanes, int c) {
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__device__ __forceinline__ int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Grid for a grid-stride loop over `count` items.
 inline unsigned grid_for(int64_t count, int block) {
@@ -182,18 +183,31 @@ struct TraceScope {
     ~TraceScope();
 };
 
-// Launch shape of a JOR sweep (see ad_relax.hip).
+// Launch shape and plan of a JOR sweep (see ad_relax.hip).
 struct SweepShape {
-    int vec, C, SPR, RPW, SPRW;
-    int64_t hub_d;
+    int vec, C, SPRW;     // values per lane, lanes per neighbour row, slots per wave
+    int rpw_fixed;        // 0: rows per wave chosen per tile
+    int64_t hub_d;        // rows longer than this get a workgroup each
 };
-SweepShape sweep_shape(int R, size_t in_bytes, double avg_deg, int rpw_req, int64_t hub_req);
+SweepShape sweep_shape(int R, size_t in_bytes, int rpw_req, int64_t hub_req);
 
-// xout = (1 - omega) xin + omega * diag(inv_s) W xin, FP32, rows longer than
-// sh.hub_d taken from hub_list (built with collect_rows).
+struct SweepPlan {
+    SweepShape sh;
+    int32_t *hub_list;
+    unsigned int *hub_count;
+    long long *plan;            // (first row << 8) | log2(rows per wave), one per wave
+    unsigned int *plan_count;
+    int *tile_lg;
+    unsigned int *tile_waves;
+};
+size_t sweep_plan_bytes(int64_t n);
+void sweep_plan_carve(Carver &c, int64_t n, SweepPlan &p);
+// Builds the hub list (if build_hubs) and the per-tile plan on the stream.
+ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, hipStream_t st);
+
+// xout = (1 - omega) xin + omega * diag(inv_s) W xin, FP32.
 ad_status sweep_f32(const ad_graph *g, const float *inv_s, float omega, const float *xin, float *xout, int R,
-                    const SweepShape &sh, const int32_t *hub_list, const unsigned int *hub_count,
-                    hipStream_t st);
+                    const SweepPlan &plan, hipStream_t st);
 ad_status weighted_degree_f32(const ad_graph *g, float *inv_s, float *sdeg, hipStream_t st);
 
 }  // namespace ad

@@ -210,15 +210,17 @@ __device__ __forceinline__ void gather_rows(const int32_t *__restrict__ col, con
 // Blocks [0, hub_blocks) take the listed long rows (degree > hub_d), one row
 // per 256-thread workgroup at a time: SPRW slots per wave, partial sums
 // combined across the 4 waves in LDS.  They come first so the longest work
-// starts first.  Blocks [hub_blocks, ...) take the other rows: per wave RPW
-// rows; per row SPR slots of C lanes, VEC values per lane.
+// starts first.  Blocks [hub_blocks, ...) take the other rows as a persistent
+// grid walking the launch plan (see below): per wave 2^lg rows, per row
+// SPRW / 2^lg slots of C lanes, VEC values per lane.
 template <typename Tin, typename Tout, typename A, int VEC, int U>
 __global__ __launch_bounds__(BLOCK) void k_sweep(
     int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const float *__restrict__ w, const A *__restrict__ inv_s, A omega,
-    const Tin *__restrict__ xin, Tout *__restrict__ xout, int R, int C, int SPR, int RPW,
+    const Tin *__restrict__ xin, Tout *__restrict__ xout, int R, int C,
     int64_t hub_d, int SPRW, int hub_blocks, const int32_t *__restrict__ hub_list,
-    const unsigned int *__restrict__ hub_count) {
+    const unsigned int *__restrict__ hub_count, const long long *__restrict__ plan,
+    const unsigned int *__restrict__ plan_count) {
     __shared__ A part[BLOCK / WAVE][64];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
@@ -265,46 +267,131 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
         }
         return;
     }
-    const int group = C * SPR;
-    const int rw = lane / group;
-    const int sub = lane - rw * group;
-    const int slot = sub / C;
-    const int chunk = sub - slot * C;
-    const int64_t row = ((int64_t)(blockIdx.x - hub_blocks) * (BLOCK / WAVE) + wave) * RPW + rw;
-    const bool active = (rw < RPW) && (row < n);
-    int64_t beg = 0, end = 0;
-    if (active) {
-        beg = row_ptr[row];
-        end = row_ptr[row + 1];
-    }
-    const bool hub = (end - beg) > hub_d;
-    const bool writer = active && !hub && slot == 0;
-    const int off = chunk * VEC;
-    // the row's own values and 1/s do not depend on the gathers: load them first
-    A own[VEC];
-    A is = (A)0;
-    if (writer) {
-        load_vec<VEC>(xin + row * R + off, own);
-        is = inv_s[row];
-    }
-    A acc[VEC];
-#pragma unroll
-    for (int q = 0; q < VEC; ++q) acc[q] = (A)0;
-    if (active && !hub) gather_rows<U, VEC>(col, w, xin, beg + slot, end, SPR, R, off, acc);
-    for (int d = SPR >> 1; d >= 1; d >>= 1) {
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) acc[q] += shfl_down(acc[q], d * C);
-    }
-    if (writer) {
-        A res[VEC];
-        if (end > beg) {
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) res[q] = fma(omega, acc[q] * is, keep * own[q]);
-        } else {
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) res[q] = own[q];
+    // Other rows: each wave walks plan entries (first row, log2 rows per
+    // wave); SPRW / rpw slots of C lanes per row.
+    const unsigned int np = *plan_count;
+    const unsigned int nwaves = (gridDim.x - hub_blocks) * (BLOCK / WAVE);
+    for (unsigned int pi = (blockIdx.x - hub_blocks) * (BLOCK / WAVE) + wave; pi < np; pi += nwaves) {
+        const long long e = plan[pi];
+        const int64_t row0 = e >> 8;
+        const int RPW = 1 << (int)(e & 0xff);
+        const int SPR = SPRW / RPW;
+        const int group = C * SPR;
+        const int rw = lane / group;
+        const int sub = lane - rw * group;
+        const int slot = sub / C;
+        const int chunk = sub - slot * C;
+        const int64_t row = row0 + rw;
+        const bool active = (rw < RPW) && (row < n);
+        int64_t beg = 0, end = 0;
+        if (active) {
+            beg = row_ptr[row];
+            end = row_ptr[row + 1];
         }
-        store_vec<VEC>(xout + row * R + off, res);
+        const bool hub = (end - beg) > hub_d;
+        const bool writer = active && !hub && slot == 0;
+        const int off = chunk * VEC;
+        // the row's own values and 1/s do not depend on the gathers: load them first
+        A own[VEC];
+        A is = (A)0;
+        if (writer) {
+            load_vec<VEC>(xin + row * R + off, own);
+            is = inv_s[row];
+        }
+        A acc[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] = (A)0;
+        if (active && !hub) gather_rows<U, VEC>(col, w, xin, beg + slot, end, SPR, R, off, acc);
+        for (int d = SPR >> 1; d >= 1; d >>= 1) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] += shfl_down(acc[q], d * C);
+        }
+        if (writer) {
+            A res[VEC];
+            if (end > beg) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) res[q] = fma(omega, acc[q] * is, keep * own[q]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) res[q] = own[q];
+            }
+            store_vec<VEC>(xout + row * R + off, res);
+        }
+    }
+}
+
+// Launch plan of the sweep: rows are taken in tiles of PLAN_TILE; a tile's
+// rows per wave follow its longest non-hub row, so that one round of
+// SWEEP_UNROLL gathers per slot covers it (short rows share a wave, long
+// rows get more slots).  A fixed rows-per-wave request overrides this.
+constexpr int PLAN_TILE = 64;
+
+__global__ void k_plan_tiles(int64_t n, const int64_t *__restrict__ row_ptr, int64_t hub_d, int spr_max,
+                             int rpw_fixed, int *__restrict__ tile_lg, unsigned int *__restrict__ tile_waves) {
+    const int64_t ntiles = ceil_div_dev(n, PLAN_TILE);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r0 = t * PLAN_TILE;
+        const int64_t r1 = min(n, r0 + PLAN_TILE);
+        int lg;
+        if (rpw_fixed > 0) {
+            lg = 31 - __clz(rpw_fixed);
+        } else {
+            int64_t dm = 0;
+            for (int64_t i = r0; i < r1; ++i) {
+                const int64_t d = row_ptr[i + 1] - row_ptr[i];
+                if (d <= hub_d && d > dm) dm = d;
+            }
+            int spr = 1;
+            while (spr < spr_max && (int64_t)spr * SWEEP_UNROLL < dm) spr <<= 1;
+            const int rpw = spr_max / spr;
+            lg = 31 - __clz(rpw);
+        }
+        tile_lg[t] = lg;
+        tile_waves[t] = (unsigned int)ceil_div_dev(r1 - r0, (int64_t)1 << lg);
+    }
+}
+
+// Exclusive scan of tile_waves (one block: contiguous chunks per thread,
+// then a sequential pass over the chunk totals); plan_count = total.
+__global__ __launch_bounds__(BLOCK) void k_plan_scan(int64_t ntiles, unsigned int *__restrict__ tile_waves,
+                                                     unsigned int *__restrict__ plan_count) {
+    __shared__ unsigned int part[BLOCK];
+    const int t = threadIdx.x;
+    const int64_t per = ceil_div_dev(ntiles, BLOCK);
+    const int64_t a = t * per, b = min(ntiles, a + per);
+    unsigned int sum = 0;
+    for (int64_t i = a; i < b; ++i) sum += tile_waves[i];
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        unsigned int run = 0;
+        for (int q = 0; q < BLOCK; ++q) {
+            unsigned int v = part[q];
+            part[q] = run;
+            run += v;
+        }
+        *plan_count = run;
+    }
+    __syncthreads();
+    unsigned int run = part[t];
+    for (int64_t i = a; i < b; ++i) {
+        unsigned int v = tile_waves[i];
+        tile_waves[i] = run;
+        run += v;
+    }
+}
+
+__global__ void k_plan_fill(int64_t n, const int *__restrict__ tile_lg, const unsigned int *__restrict__ tile_off,
+                            long long *__restrict__ plan) {
+    const int64_t ntiles = ceil_div_dev(n, PLAN_TILE);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r0 = t * PLAN_TILE;
+        const int64_t r1 = min(n, r0 + PLAN_TILE);
+        const int lg = tile_lg[t];
+        unsigned int o = tile_off[t];
+        for (int64_t r = r0; r < r1; r += (int64_t)1 << lg) plan[o++] = ((long long)r << 8) | lg;
     }
 }
 
@@ -370,35 +457,65 @@ static int pick_vec(int R, size_t elem_bytes) {
     return 1;
 }
 
-SweepShape sweep_shape(int R, size_t in_bytes, double avg_deg, int rpw_req, int64_t hub_req) {
+SweepShape sweep_shape(int R, size_t in_bytes, int rpw_req, int64_t hub_req) {
     SweepShape s;
     s.vec = pick_vec(R, in_bytes);
     s.C = lanes_per_row(R, s.vec);
-    int spr_max = pow2_slots(WAVE, s.C);
-    int rpw = rpw_req;
-    if (rpw <= 0) {
-        // enough slots that an average row needs one round of SWEEP_UNROLL gathers
-        int want = 1;
-        while (want < spr_max && want * SWEEP_UNROLL < avg_deg) want *= 2;
-        rpw = std::max(1, spr_max / want);
-    }
-    if (rpw > spr_max) rpw = spr_max;
-    // rows per wave must be a power of two dividing spr_max
+    s.SPRW = pow2_slots(WAVE, s.C);
+    int rpw = std::min(std::max(rpw_req, 0), s.SPRW);
     int p = 1;
-    while (p * 2 <= rpw) p *= 2;
-    s.RPW = p;
-    s.SPR = spr_max / s.RPW;
-    s.SPRW = spr_max;
-    s.hub_d = hub_req > 0 ? hub_req : std::max<int64_t>(256, 8 * (int64_t)s.SPR);
+    while (p * 2 <= rpw) p *= 2;        // a power of two dividing SPRW
+    s.rpw_fixed = rpw > 0 ? p : 0;
+    s.hub_d = hub_req > 0 ? hub_req : std::max<int64_t>(256, 2 * (int64_t)s.SPRW * SWEEP_UNROLL);
     return s;
 }
 
+size_t sweep_plan_bytes(int64_t n) {
+    Carver c(nullptr, 0);
+    SweepPlan p;
+    sweep_plan_carve(c, n, p);
+    return c.used;
+}
+
+void sweep_plan_carve(Carver &c, int64_t n, SweepPlan &p) {
+    const int64_t nn = std::max<int64_t>(1, n);
+    const int64_t ntiles = std::max<int64_t>(1, ceil_div(n, PLAN_TILE));
+    p.hub_list = c.take<int32_t>(nn);
+    p.hub_count = c.take<unsigned int>(1);
+    p.plan = c.take<long long>(nn + ntiles);
+    p.plan_count = c.take<unsigned int>(1);
+    p.tile_lg = c.take<int>(ntiles);
+    p.tile_waves = c.take<unsigned int>(ntiles);
+}
+
+ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, hipStream_t st) {
+    ad_status s;
+    if (build_hubs) {
+        s = fill_i32((int32_t *)p.hub_count, 0, 1, st);
+        if (s != AD_OK) return s;
+        s = collect_rows(g, p.sh.hub_d, (int64_t)1 << 62, p.hub_list, p.hub_count, st);
+        if (s != AD_OK) return s;
+    }
+    const int64_t ntiles = ceil_div(g->n, PLAN_TILE);
+    if (ntiles <= 0) return fill_i32((int32_t *)p.plan_count, 0, 1, st);
+    hipLaunchKernelGGL(k_plan_tiles, dim3(grid_for(ntiles, BLOCK)), dim3(BLOCK), 0, st, g->n, g->row_ptr,
+                       p.sh.hub_d, p.sh.SPRW, p.sh.rpw_fixed, p.tile_lg, p.tile_waves);
+    AD_LAUNCH_CHECK("k_plan_tiles");
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(BLOCK), 0, st, ntiles, p.tile_waves, p.plan_count);
+    AD_LAUNCH_CHECK("k_plan_scan");
+    hipLaunchKernelGGL(k_plan_fill, dim3(grid_for(ntiles, BLOCK)), dim3(BLOCK), 0, st, g->n, p.tile_lg,
+                       p.tile_waves, p.plan);
+    AD_LAUNCH_CHECK("k_plan_fill");
+    return AD_OK;
+}
+
+constexpr int64_t MAX_MAIN_BLOCKS = 4096;   // persistent: waves loop over plan entries
+
 template <typename Tin, typename Tout, typename A, int VEC>
 static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout,
-                                int R, const SweepShape &sh, const int32_t *hub_list,
-                                const unsigned int *hub_count, hipStream_t st) {
-    const int64_t rows_per_block = (int64_t)(BLOCK / WAVE) * sh.RPW;
-    const int64_t main_blocks = ceil_div(g->n, rows_per_block);
+                                int R, const SweepPlan &pl, hipStream_t st) {
+    const SweepShape &sh = pl.sh;
+    const int64_t main_blocks = std::min<int64_t>(MAX_MAIN_BLOCKS, ceil_div(g->n, BLOCK / WAVE));
     // at most 2m / hub_d rows exceed hub_d; unknown d_max (0) keeps the bound
     int64_t hub_blocks = 0;
     if (g->d_max == 0 || g->d_max > sh.hub_d)
@@ -406,22 +523,21 @@ static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, cons
     const int64_t grid = main_blocks + hub_blocks;
     if (grid <= 0) return AD_OK;
     TraceScope trace("k_sweep", st);
-    hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC, SWEEP_UNROLL>), dim3((unsigned)grid), dim3(BLOCK), 0, st, g->n,
-                       g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C, sh.SPR, sh.RPW, sh.hub_d,
-                       sh.SPRW, (int)hub_blocks, hub_list, hub_count);
+    hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC, SWEEP_UNROLL>), dim3((unsigned)grid), dim3(BLOCK), 0, st,
+                       g->n, g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C, sh.hub_d, sh.SPRW,
+                       (int)hub_blocks, pl.hub_list, pl.hub_count, pl.plan, pl.plan_count);
     AD_LAUNCH_CHECK("k_sweep");
     return AD_OK;
 }
 
 template <typename Tin, typename Tout, typename A>
-static ad_status launch_sweep(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout,
-                              int R, const SweepShape &sh, const int32_t *hub_list,
-                              const unsigned int *hub_count, hipStream_t st) {
-    switch (sh.vec) {
-    case 1: return launch_sweep_v<Tin, Tout, A, 1>(g, inv_s, omega, xin, xout, R, sh, hub_list, hub_count, st);
-    case 2: return launch_sweep_v<Tin, Tout, A, 2>(g, inv_s, omega, xin, xout, R, sh, hub_list, hub_count, st);
-    case 4: return launch_sweep_v<Tin, Tout, A, 4>(g, inv_s, omega, xin, xout, R, sh, hub_list, hub_count, st);
-    case 8: return launch_sweep_v<Tin, Tout, A, 8>(g, inv_s, omega, xin, xout, R, sh, hub_list, hub_count, st);
+static ad_status launch_sweep(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout, int R,
+                              const SweepPlan &pl, hipStream_t st) {
+    switch (pl.sh.vec) {
+    case 1: return launch_sweep_v<Tin, Tout, A, 1>(g, inv_s, omega, xin, xout, R, pl, st);
+    case 2: return launch_sweep_v<Tin, Tout, A, 2>(g, inv_s, omega, xin, xout, R, pl, st);
+    case 4: return launch_sweep_v<Tin, Tout, A, 4>(g, inv_s, omega, xin, xout, R, pl, st);
+    case 8: return launch_sweep_v<Tin, Tout, A, 8>(g, inv_s, omega, xin, xout, R, pl, st);
     }
     return fail(AD_ERR_INTERNAL, "bad vector width");
 }
@@ -433,8 +549,7 @@ struct RelaxLayout {
     float *sdeg;
     double *part, *part_s, *shift;
     unsigned long long *mm;
-    int32_t *hub_list;
-    unsigned int *hub_count;
+    SweepPlan p32, p16;
     void *bufA, *bufB;
     void *b16A, *b16B;
 };
@@ -453,8 +568,8 @@ static size_t relax_layout(const ad_graph *g, const ad_relax_opts *o, void *ws, 
     l.part_s = c.take<double>(nb);
     l.shift = c.take<double>(R);
     l.mm = c.take<unsigned long long>(2 * R);
-    l.hub_list = c.take<int32_t>(n);
-    l.hub_count = c.take<unsigned int>(1);
+    sweep_plan_carve(c, n, l.p32);
+    if (o->store == AD_BF16) sweep_plan_carve(c, n, l.p16);
     const size_t xb = f64 ? 8 : 4;
     l.bufA = c.take<char>((size_t)n * R * xb);
     l.bufB = c.take<char>((size_t)n * R * xb);
@@ -519,16 +634,18 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
     }
 
     if (o->k > 0 && n > 0) {
-        SweepShape sh32 = sweep_shape(R, sizeof(T), avg, o->rows_per_wave, o->hub_degree);
-        SweepShape sh16 = sweep_shape(R, 2, avg, o->rows_per_wave, o->hub_degree);
-        // hub rows, found once per call (the list depends on the graph only)
-        const int64_t hub_d = sh32.hub_d;
-        sh16.hub_d = hub_d;
-        s = fill_i32((int32_t *)L.hub_count, 0, 1, st);
+        RelaxLayout P = L;
+        P.p32.sh = sweep_shape(R, sizeof(T), o->rows_per_wave, o->hub_degree);
+        s = sweep_plan_build(g, P.p32, true, st);
         if (s != AD_OK) return s;
-        s = collect_rows(g, hub_d, (int64_t)1 << 62, L.hub_list, L.hub_count, st);
-        if (s != AD_OK) return s;
-
+        if (o->store == AD_BF16) {
+            P.p16.sh = sweep_shape(R, 2, o->rows_per_wave, o->hub_degree);
+            P.p16.sh.hub_d = P.p32.sh.hub_d;            // one hub list serves both
+            P.p16.hub_list = P.p32.hub_list;
+            P.p16.hub_count = P.p32.hub_count;
+            s = sweep_plan_build(g, P.p16, false, st);
+            if (s != AD_OK) return s;
+        }
         Buf cur = {start, o->store == AD_F64 ? AD_F64 : AD_F32};
         const int tail = o->store == AD_BF16 ? o->fp32_tail : o->k;
         for (int t = 1; t <= o->k; ++t) {
@@ -546,24 +663,19 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
             const A om = (A)o->omega;
             if (cur.t == AD_F64) {
                 s = launch_sweep<double, double, double>(g, (const double *)L.inv_s, (double)om,
-                                                         (const double *)cur.p, (double *)dst.p, R, sh32,
-                                                         L.hub_list, L.hub_count, st);
+                                                         (const double *)cur.p, (double *)dst.p, R, P.p32, st);
             } else if (cur.t == AD_F32 && dst.t == AD_F32) {
                 s = launch_sweep<float, float, float>(g, (const float *)L.inv_s, (float)om,
-                                                      (const float *)cur.p, (float *)dst.p, R, sh32,
-                                                      L.hub_list, L.hub_count, st);
+                                                      (const float *)cur.p, (float *)dst.p, R, P.p32, st);
             } else if (cur.t == AD_F32 && dst.t == AD_BF16) {
                 s = launch_sweep<float, bf16, float>(g, (const float *)L.inv_s, (float)om,
-                                                     (const float *)cur.p, (bf16 *)dst.p, R, sh32,
-                                                     L.hub_list, L.hub_count, st);
+                                                     (const float *)cur.p, (bf16 *)dst.p, R, P.p32, st);
             } else if (cur.t == AD_BF16 && dst.t == AD_BF16) {
                 s = launch_sweep<bf16, bf16, float>(g, (const float *)L.inv_s, (float)om,
-                                                    (const bf16 *)cur.p, (bf16 *)dst.p, R, sh16,
-                                                    L.hub_list, L.hub_count, st);
+                                                    (const bf16 *)cur.p, (bf16 *)dst.p, R, P.p16, st);
             } else {
                 s = launch_sweep<bf16, float, float>(g, (const float *)L.inv_s, (float)om,
-                                                     (const bf16 *)cur.p, (float *)dst.p, R, sh16,
-                                                     L.hub_list, L.hub_count, st);
+                                                     (const bf16 *)cur.p, (float *)dst.p, R, P.p16, st);
             }
             if (s != AD_OK) return s;
             cur = dst;
@@ -583,9 +695,8 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
 }
 
 ad_status sweep_f32(const ad_graph *g, const float *inv_s, float omega, const float *xin, float *xout, int R,
-                    const SweepShape &sh, const int32_t *hub_list, const unsigned int *hub_count,
-                    hipStream_t st) {
-    return launch_sweep<float, float, float>(g, inv_s, omega, xin, xout, R, sh, hub_list, hub_count, st);
+                    const SweepPlan &plan, hipStream_t st) {
+    return launch_sweep<float, float, float>(g, inv_s, omega, xin, xout, R, plan, st);
 }
 
 ad_status weighted_degree_f32(const ad_graph *g, float *inv_s, float *sdeg, hipStream_t st) {
