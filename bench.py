@@ -101,6 +101,7 @@ def main() -> int:
         dg, api.relax_opts(R, K, OMEGA, SEED_VEC, rows_per_wave=args.rows_per_wave,
                            hub_degree=args.hub_degree)), dev)
     ws_s = api._workspace(api.sparsify_workspace_bytes(dg), dev)
+    ws_d = api._workspace(api.edge_dist_workspace_bytes(dg), dev)
     out = api.RelaxResult(x=torch.empty((n, R), dtype=torch.float32, device=dev),
                           minmax=torch.empty(2 * R, dtype=torch.float64, device=dev),
                           shift=torch.empty(R, dtype=torch.float64, device=dev), ckpt=None, store="f32")
@@ -114,7 +115,7 @@ def main() -> int:
     def step():
         api.relax(dg, R, K, OMEGA, SEED_VEC, ws=ws_r, out=out, rows_per_wave=args.rows_per_wave,
                   hub_degree=args.hub_degree)
-        api.edge_dist(dg, out.x, out.minmax, out=rho)
+        api.edge_dist(dg, out.x, out.minmax, out=rho, ws=ws_d)
         _, _, e_l = api.sparsify_fit(dg, rho, api.AD_LOCAL, TARGET, ws=ws_s, keep=keep_l, n_kept=nk_l)
         _, _, e_g = api.sparsify_fit(dg, rho, api.AD_GLOBAL, TARGET, ws=ws_s, keep=keep_g, n_kept=nk_g)
         fit["e_local"], fit["e_global"] = e_l, e_g
@@ -153,7 +154,7 @@ def main() -> int:
     for _ in range(args.steps):
         api.relax(dg, R, K, OMEGA, SEED_VEC, ws=ws_r, out=out, rows_per_wave=args.rows_per_wave,
                   hub_degree=args.hub_degree)
-        api.edge_dist(dg, out.x, out.minmax, out=rho)
+        api.edge_dist(dg, out.x, out.minmax, out=rho, ws=ws_d)
     ev1.record()
     torch.cuda.synchronize()
     rd_ms = ev0.elapsed_time(ev1) / args.steps

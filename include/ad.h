@@ -80,6 +80,9 @@ typedef struct {
     const int32_t *orig_id;   /* [n] vertex id before any relabelling (keys the random
                                  start vectors, breaks ranking ties); NULL = identity  */
     int32_t d_max;            /* host value: maximum degree (selection calls need it) */
+    const int32_t *col_orig;  /* [2m] optional: orig_id[col[p]] per entry (ad_graph_col_orig
+                                 builds it); lets ranking read neighbour ids in storage
+                                 order instead of gathering them; NULL = gather          */
 } ad_graph;
 
 /* Parameters of Algorithm 1's relaxation. */
@@ -144,14 +147,18 @@ ad_status ad_relax(const ad_graph *g, const ad_relax_opts *o, const void *x0,
 
 /* ------------------------------------------------------------- distance -- */
 
+/* Workspace bytes for ad_edge_dist. */
+size_t ad_edge_dist_workspace_size(const ad_graph *g);
+
 /* Algorithm 1, distance part: for every undirected edge e = (i, j)
  *     rho_e = sqrt( sum_r ((x_i,r - x_j,r) / (max_r - min_r))^2 ),
  * i.e. the L2 distance of the rescaled vectors (a vector with max_r == min_r
  * contributes 0).  x: [n][R] in x_dtype (AD_F64 or AD_F32), as written by
  * ad_relax; minmax: [2R] doubles as written by ad_relax.  rho: [m], FP64
- * when x_dtype == AD_F64, else FP32.  No workspace. */
+ * when x_dtype == AD_F64, else FP32. */
 ad_status ad_edge_dist(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
-                       const double *minmax, void *rho, hipStream_t stream);
+                       const double *minmax, void *rho, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
 
 /* ------------------------------------------------------------ selection -- */
 
@@ -210,6 +217,10 @@ ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o, const voi
  * adjoint).  w_edge: [m] FP32, w_entries: [2m] FP32. */
 ad_status ad_edge_to_entries(const ad_graph *g, const float *w_edge, float *w_entries,
                              hipStream_t stream);
+
+/* Per-entry neighbour ids for ad_graph.col_orig: col_orig[p] = orig_id[col[p]]
+ * (= col[p] when orig_id is NULL), p < 2m.  Build once per graph. */
+ad_status ad_graph_col_orig(const ad_graph *g, int32_t *col_orig, hipStream_t stream);
 
 /* ---------------------------------------------------------- diagnostics -- */
 

@@ -30,7 +30,8 @@ _STATUS = {0: "AD_OK", 1: "AD_ERR_INVALID_ARG", 2: "AD_ERR_UNSUPPORTED", 3: "AD_
 class ADGraph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("eid", ctypes.c_void_p),
-                ("orig_id", ctypes.c_void_p), ("d_max", ctypes.c_int32)]
+                ("orig_id", ctypes.c_void_p), ("d_max", ctypes.c_int32),
+                ("col_orig", ctypes.c_void_p)]
 
 
 class ADRelaxOpts(ctypes.Structure):
@@ -59,7 +60,8 @@ def _load_lib():
         "ad_relax_workspace_size": (S, [G, O]),
         "ad_relax_num_checkpoints": (i32, [O]),
         "ad_relax": (st, [G, O, P, P, P, P, P, P, S, P]),
-        "ad_edge_dist": (st, [G, i32, ctypes.c_int, P, P, P, P]),
+        "ad_edge_dist_workspace_size": (S, [G]),
+        "ad_edge_dist": (st, [G, i32, ctypes.c_int, P, P, P, P, S, P]),
         "ad_budget_table": (st, [i32, f64, P]),
         "ad_sparsify_workspace_size": (S, [G]),
         "ad_sparsify": (st, [G, ctypes.c_int, P, ctypes.c_int, P, P, P, P, S, P]),
@@ -67,6 +69,7 @@ def _load_lib():
         "ad_relax_backward_workspace_size": (S, [G, O]),
         "ad_relax_backward": (st, [G, O, P, P, P, P, P, P, S, P]),
         "ad_edge_to_entries": (st, [G, P, P, P]),
+        "ad_graph_col_orig": (st, [G, P, P]),
         "ad_validate_workspace_size": (S, [G]),
         "ad_validate_graph": (st, [G, P, S, P]),
         "ad_trace_enable": (None, [i32]),
@@ -133,19 +136,28 @@ class DeviceGraph:
     eid: torch.Tensor
     orig_id: Optional[torch.Tensor]
     host: Optional[_graphs.Graph] = None
+    col_orig: Optional[torch.Tensor] = None
 
     @classmethod
-    def from_host(cls, g: _graphs.Graph, device="cuda", keep_host: bool = True) -> "DeviceGraph":
+    def from_host(cls, g: _graphs.Graph, device="cuda", keep_host: bool = True,
+                  entry_ids: bool = True) -> "DeviceGraph":
+        """Copy the CSR to the device; with entry_ids also build the
+        per-entry neighbour ids (ad_graph_col_orig) used by ranking."""
         dev = torch.device(device)
 
         def t(a, dt):
             return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
 
-        return cls(n=g.n, m=g.m, d_max=g.d_max,
-                   row_ptr=t(g.row_ptr, np.int64), col=t(g.col, np.int32),
-                   w=None if g.w is None else t(g.w, np.float32),
-                   eid=t(g.eid, np.int32), orig_id=t(g.orig_id, np.int32),
-                   host=g if keep_host else None)
+        dg = cls(n=g.n, m=g.m, d_max=g.d_max,
+                 row_ptr=t(g.row_ptr, np.int64), col=t(g.col, np.int32),
+                 w=None if g.w is None else t(g.w, np.float32),
+                 eid=t(g.eid, np.int32), orig_id=t(g.orig_id, np.int32),
+                 host=g if keep_host else None)
+        if entry_ids and g.m > 0:
+            dg.col_orig = torch.empty(2 * g.m, dtype=torch.int32, device=dev)
+            gs = dg.abi()
+            _check(lib.ad_graph_col_orig(ctypes.byref(gs), _ptr(dg.col_orig), _stream()))
+        return dg
 
     @property
     def device(self):
@@ -157,11 +169,12 @@ class DeviceGraph:
                        None if self.w is None else self.w.data_ptr(),
                        self.eid.data_ptr() if self.eid.numel() else None,
                        None if self.orig_id is None else self.orig_id.data_ptr(),
-                       self.d_max)
+                       self.d_max,
+                       None if self.col_orig is None else self.col_orig.data_ptr())
 
     def with_weights(self, w_entries: Optional[torch.Tensor]) -> "DeviceGraph":
         return DeviceGraph(self.n, self.m, self.d_max, self.row_ptr, self.col, w_entries,
-                           self.eid, self.orig_id, self.host)
+                           self.eid, self.orig_id, self.host, self.col_orig)
 
 
 def validate_graph(dg: DeviceGraph) -> None:
@@ -224,15 +237,23 @@ def relax(dg: DeviceGraph, R: int, k: int, omega: float = 0.5, seed: int = 0, gr
 
 # -------------------------------------------------------------- distance ---
 
+def edge_dist_workspace_bytes(dg: DeviceGraph) -> int:
+    g = dg.abi()
+    return int(lib.ad_edge_dist_workspace_size(ctypes.byref(g)))
+
+
 def edge_dist(dg: DeviceGraph, x: torch.Tensor, minmax: torch.Tensor,
-              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+              out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """rho[m] = L2 distance of the rescaled vectors (``ad_edge_dist``)."""
     R = x.shape[1]
     dt = AD_F64 if x.dtype == torch.float64 else AD_F32
     if out is None:
         out = torch.empty(dg.m, dtype=x.dtype, device=x.device)
     g = dg.abi()
-    _check(lib.ad_edge_dist(ctypes.byref(g), R, dt, _ptr(x), _ptr(minmax), _ptr(out), _stream()))
+    if ws is None:
+        ws = _workspace(lib.ad_edge_dist_workspace_size(ctypes.byref(g)), x.device)
+    _check(lib.ad_edge_dist(ctypes.byref(g), R, dt, _ptr(x), _ptr(minmax), _ptr(out), _ptr(ws), ws.numel(),
+                            _stream()))
     return out
 
 

@@ -35,8 +35,11 @@ static int lanes_for(double avg) {
     return lpr;
 }
 
-// xhatbar from grad_rho: one lane per stored entry, LPR lanes per row.
-template <int RB>
+// xhatbar from grad_rho: one lane per stored entry, LPR lanes per row.  rho
+// is recomputed in the forward distance kernel's order: VEC values per chunk
+// summed in order, chunks combined by a pairwise tree when their count is a
+// power of two, else in order -- so it equals the forward value bit for bit.
+template <int RB, int VEC>
 __global__ __launch_bounds__(BB) void k_adj_dist(int64_t n, const int64_t *__restrict__ row_ptr,
                                                  const int32_t *__restrict__ col,
                                                  const int32_t *__restrict__ eid,
@@ -60,15 +63,32 @@ __global__ __launch_bounds__(BB) void k_adj_dist(int64_t n, const int64_t *__res
         for (int64_t p = beg + lane; p < end; p += LPR) {
             const float *xj = x + (int64_t)col[p] * R;
             float d[RB];
-            float ss = 0.f;
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                if (r < R) {
-                    d[r] = (xi[r] - xj[r]) * inv_l[r];
-                    ss = fmaf(d[r], d[r], ss);
-                } else {
-                    d[r] = 0.f;
+            for (int r = 0; r < RB; ++r) d[r] = r < R ? (xi[r] - xj[r]) * inv_l[r] : 0.f;
+            constexpr int NC = RB / VEC;
+            const int C = R / VEC;
+            float part[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                float a = 0.f;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) a = fmaf(d[c * VEC + q], d[c * VEC + q], a);
+                part[c] = a;
+            }
+            float ss;
+            if ((C & (C - 1)) == 0) {
+#pragma unroll
+                for (int off = 1; off < NC; off <<= 1) {
+#pragma unroll
+                    for (int c = 0; c + off < NC; c += 2 * off)
+                        if (off < C) part[c] += part[c + off];
                 }
+                ss = part[0];
+            } else {
+                ss = part[0];
+#pragma unroll
+                for (int c = 1; c < NC; ++c)
+                    if (c < C) ss += part[c];
             }
             const float rho = sqrtf(ss);
             if (rho > 0.f) {
@@ -259,8 +279,18 @@ template <int RB>
 static ad_status launch_rb(const ad_graph *g, const ad_relax_opts *o, const float *x_k, const double *minmax,
                            const float *grad_rho, const BwdLayout &L, int lpr, hipStream_t st) {
     const unsigned nb = (unsigned)ceil_div(g->n, BB / lpr);
-    hipLaunchKernelGGL((k_adj_dist<RB>), dim3(nb), dim3(BB), 0, st, g->n, g->row_ptr, g->col, g->eid, x_k,
-                       minmax, grad_rho, L.xbh, o->R, lpr);
+    const int R = o->R;
+    // the forward distance kernel's vector width for FP32
+    const int vec = R % 4 == 0 ? 4 : (R % 2 == 0 ? 2 : 1);
+    if (vec == 4)
+        hipLaunchKernelGGL((k_adj_dist<RB, 4>), dim3(nb), dim3(BB), 0, st, g->n, g->row_ptr, g->col, g->eid, x_k,
+                           minmax, grad_rho, L.xbh, R, lpr);
+    else if (vec == 2)
+        hipLaunchKernelGGL((k_adj_dist<RB, 2>), dim3(nb), dim3(BB), 0, st, g->n, g->row_ptr, g->col, g->eid, x_k,
+                           minmax, grad_rho, L.xbh, R, lpr);
+    else
+        hipLaunchKernelGGL((k_adj_dist<RB, 1>), dim3(nb), dim3(BB), 0, st, g->n, g->row_ptr, g->col, g->eid, x_k,
+                           minmax, grad_rho, L.xbh, R, lpr);
     AD_LAUNCH_CHECK("k_adj_dist");
     return AD_OK;
 }
@@ -325,7 +355,11 @@ extern "C" ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o
     const float omega = (float)o->omega;
     const float *xk = (const float *)x_k;
 
-    s = weighted_degree_f32(g, L.inv_s, L.sdeg, stream);
+    SweepPlan plan = L.plan;
+    plan.sh = sweep_shape(R, sizeof(float), o->rows_per_wave, o->hub_degree);
+    s = sweep_plan_build(g, plan, true, stream);
+    if (s != AD_OK) return s;
+    s = weighted_degree_f32(g, L.inv_s, L.sdeg, plan, stream);
     if (s != AD_OK) return s;
     s = fill_i32((int32_t *)L.ones, 0x3f800000, n, stream);   // 1.0f
     if (s != AD_OK) return s;
@@ -355,10 +389,6 @@ extern "C" ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o
     AD_LAUNCH_CHECK("k_adj_corner");
 
     // reverse sweeps, one checkpoint segment at a time
-    SweepPlan plan = L.plan;
-    plan.sh = sweep_shape(R, sizeof(float), o->rows_per_wave, o->hub_degree);
-    s = sweep_plan_build(g, plan, true, stream);
-    if (s != AD_OK) return s;
     const int c = o->ckpt_every;
     const int nseg = ad_relax_num_checkpoints(o);
     float *lam = L.lam, *lam_next = L.lam2;

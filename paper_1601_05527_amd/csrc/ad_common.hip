@@ -65,13 +65,18 @@ ad_status fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s) {
 
 __global__ void k_collect_rows(int64_t n, const int64_t *__restrict__ row_ptr, int64_t lo,
                                int64_t hi, int32_t *__restrict__ list, unsigned int *count) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t d = row_ptr[i + 1] - row_ptr[i];
-        if (d > lo && d <= hi) {
-            unsigned int at = atomicAdd(count, 1u);
-            list[at] = (int32_t)i;
+    // the loop bound is uniform per wave (blocks are whole waves), so every
+    // lane reaches the wave-wide append
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n_pad = ceil_div_dev(n, stride) * stride;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += stride) {
+        bool take = false;
+        if (i < n) {
+            const int64_t d = row_ptr[i + 1] - row_ptr[i];
+            take = d > lo && d <= hi;
         }
+        const unsigned int at = wave_append(take, count);
+        if (take) list[at] = (int32_t)i;
     }
 }
 
@@ -82,6 +87,15 @@ ad_status collect_rows(const ad_graph *g, int64_t lo, int64_t hi, int32_t *list,
                        g->row_ptr, lo, hi, list, count);
     AD_LAUNCH_CHECK("k_collect_rows");
     return AD_OK;
+}
+
+__global__ void k_col_orig(int64_t nnz, const int32_t *__restrict__ col, const int32_t *__restrict__ orig_id,
+                           int32_t *__restrict__ out) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = col[p];
+        out[p] = orig_id ? orig_id[j] : j;
+    }
 }
 
 ad_status check_graph_args(const ad_graph *g) {
@@ -278,6 +292,18 @@ extern "C" ad_status ad_validate_graph(const ad_graph *g, void *ws, size_t ws_by
     for (int b = 0; b < 10; ++b)
         if (hflags & (1u << b)) msg += std::string(" ") + names[b] + ";";
     return fail(AD_ERR_GRAPH, msg);
+}
+
+extern "C" ad_status ad_graph_col_orig(const ad_graph *g, int32_t *col_orig, hipStream_t stream) {
+    ad_status s = check_graph_args(g);
+    if (s != AD_OK) return s;
+    if (g->m == 0) return AD_OK;
+    if (!col_orig) return fail(AD_ERR_INVALID_ARG, "col_orig is NULL");
+    const int64_t nnz = 2 * g->m;
+    hipLaunchKernelGGL(k_col_orig, dim3(grid_for(nnz, 256)), dim3(256), 0, stream, nnz, g->col, g->orig_id,
+                       col_orig);
+    AD_LAUNCH_CHECK("k_col_orig");
+    return AD_OK;
 }
 
 extern "C" const char *ad_status_string(ad_status s) {

@@ -162,6 +162,20 @@ inline unsigned grid_for(int64_t count, int block) {
     return (unsigned)b;
 }
 
+// Slot in a list shared by the wave: lanes with `take` get consecutive
+// slots from one atomic add on *counter (per wave, not per lane).
+__device__ __forceinline__ unsigned int wave_append(bool take, unsigned int *counter) {
+    const unsigned long long mask = __ballot(take);
+    if (mask == 0) return 0;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int leader = __ffsll((long long)mask) - 1;
+    unsigned int base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned int)__popcll(mask));
+    base = __shfl(base, leader, WAVE);
+    const unsigned long long below = lane ? (mask & ((1ull << lane) - 1)) : 0ull;
+    return base + (unsigned int)__popcll(below);
+}
+
 // Small device fills (no hipMemsetAsync: the calls may be graph-captured).
 ad_status fill_u64(unsigned long long *p, unsigned long long v, int64_t count, hipStream_t s);
 ad_status fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s);
@@ -208,6 +222,7 @@ ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, hip
 // xout = (1 - omega) xin + omega * diag(inv_s) W xin, FP32.
 ad_status sweep_f32(const ad_graph *g, const float *inv_s, float omega, const float *xin, float *xout, int R,
                     const SweepPlan &plan, hipStream_t st);
-ad_status weighted_degree_f32(const ad_graph *g, float *inv_s, float *sdeg, hipStream_t st);
+// s_i and 1/s_i; rows longer than the plan's hub degree come from its hub list.
+ad_status weighted_degree_f32(const ad_graph *g, float *inv_s, float *sdeg, const SweepPlan &pl, hipStream_t st);
 
 }  // namespace ad

@@ -35,7 +35,7 @@ constexpr int SWEEP_UNROLL = 8;     // row gathers in flight per lane   // rows 
 template <typename A>
 __global__ __launch_bounds__(BLOCK) void k_weighted_degree(int64_t n, const int64_t *__restrict__ row_ptr,
                                                           const float *__restrict__ w, A *__restrict__ inv_s,
-                                                          float *__restrict__ sdeg, int LPR) {
+                                                          float *__restrict__ sdeg, int LPR, int64_t hub_d) {
     const int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     int64_t b = 0, e = 0;
@@ -43,6 +43,7 @@ __global__ __launch_bounds__(BLOCK) void k_weighted_degree(int64_t n, const int6
         b = row_ptr[i];
         e = row_ptr[i + 1];
     }
+    if (e - b > hub_d) return;      // whole row group is one hub row: k_weighted_degree_hub
     double s = 0.0;
     if (w) {
         for (int64_t p = b + lane; p < e; p += LPR) s += (double)w[p];
@@ -56,53 +57,95 @@ __global__ __launch_bounds__(BLOCK) void k_weighted_degree(int64_t n, const int6
     }
 }
 
+// s_i for the listed long rows: a workgroup per row, strided FP64 partial
+// sums combined by a fixed tree in LDS.
+template <typename A>
+__global__ __launch_bounds__(BLOCK) void k_weighted_degree_hub(const int32_t *__restrict__ list,
+                                                              const unsigned int *__restrict__ count,
+                                                              const int64_t *__restrict__ row_ptr,
+                                                              const float *__restrict__ w, A *__restrict__ inv_s,
+                                                              float *__restrict__ sdeg) {
+    __shared__ double part[BLOCK];
+    const unsigned int nh = *count;
+    for (unsigned int h = blockIdx.x; h < nh; h += gridDim.x) {
+        const int64_t i = list[h];
+        const int64_t b = row_ptr[i], e = row_ptr[i + 1];
+        double s = 0.0;
+        if (w) {
+            for (int64_t p = b + threadIdx.x; p < e; p += BLOCK) s += (double)w[p];
+        } else if (threadIdx.x == 0) {
+            s = (double)(e - b);
+        }
+        part[threadIdx.x] = s;
+        __syncthreads();
+        for (int d = BLOCK / 2; d >= 1; d >>= 1) {
+            if ((int)threadIdx.x < d) part[threadIdx.x] += part[threadIdx.x + d];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            inv_s[i] = (A)(1.0 / part[0]);
+            sdeg[i] = (float)part[0];
+        }
+        __syncthreads();
+    }
+}
+
 static int degree_lanes(double avg) {
     int lpr = 1;
     while (lpr < 16 && lpr < avg) lpr <<= 1;
     return lpr;
 }
 
-__device__ __forceinline__ double start_value(uint64_t seed, uint64_t gid, int32_t key, int r) {
-    uint64_t out[4];
-    philox4x64_10((uint64_t)(uint32_t)key, (uint64_t)(r >> 2), 0, 0, seed, gid, out);
-    return start_from_word(out[r & 3]);
-}
 
-// Partial sums of s_i * x_i^(0) (per vector) and of s_i over CENTRE_ROWS rows.
+// Partial sums of s_i * x_i^(0) (per vector) and of s_i over CENTRE_ROWS
+// rows.  Thread (row offset, q) handles the Philox block q, i.e. vectors
+// 4q .. 4q+3, of its rows; the block then adds per vector in thread order.
 template <typename T>
-__global__ void k_centre_partials(int64_t n, int R, const float *__restrict__ sdeg,
-                                  const int32_t *__restrict__ orig_id, uint64_t seed,
-                                  uint64_t gid, const T *__restrict__ x0,
-                                  double *__restrict__ part, double *__restrict__ part_s) {
-    __shared__ double acc_l[BLOCK];
+__global__ __launch_bounds__(BLOCK) void k_centre_partials(int64_t n, int R, const float *__restrict__ sdeg,
+                                                          const int32_t *__restrict__ orig_id, uint64_t seed,
+                                                          uint64_t gid, const T *__restrict__ x0,
+                                                          double *__restrict__ part, double *__restrict__ part_s) {
+    __shared__ double acc_l[4][BLOCK];
     __shared__ double s_l[BLOCK];
     const int t = threadIdx.x;
-    const int stride = BLOCK / R;            // rows visited per step by one vector's threads
-    const int r = t % R;
-    const int row_off = t / R;
-    double acc = 0.0, sacc = 0.0;
+    const int nq = (R + 3) >> 2;
+    const int stride = BLOCK / nq;           // rows visited per step
+    const int q = t % nq;
+    const int row_off = t / nq;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double sacc = 0.0;
     const int64_t r0 = (int64_t)blockIdx.x * CENTRE_ROWS;
     const int64_t r1 = min(n, r0 + CENTRE_ROWS);
     if (row_off < stride) {
         for (int64_t i = r0 + row_off; i < r1; i += stride) {
-            double s = (double)sdeg[i];
-            double x = x0 ? (double)x0[i * R + r]
-                          : start_value(seed, gid, orig_id ? orig_id[i] : (int32_t)i, r);
-            acc += s * x;
+            const double s = (double)sdeg[i];
+            if (x0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (4 * q + c < R) acc[c] += s * (double)x0[i * R + 4 * q + c];
+            } else {
+                uint64_t words[4];
+                const int32_t key = orig_id ? orig_id[i] : (int32_t)i;
+                philox4x64_10((uint64_t)(uint32_t)key, (uint64_t)q, 0, 0, seed, gid, words);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] += s * start_from_word(words[c]);
+            }
             sacc += s;
         }
     }
-    acc_l[t] = acc;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc_l[c][t] = acc[c];
     s_l[t] = sacc;
     __syncthreads();
     if (t < R) {
+        const int qq = t >> 2, c = t & 3;
         double a = 0.0;
-        for (int q = t; q < stride * R; q += R) a += acc_l[q];
+        for (int u = qq; u < stride * nq; u += nq) a += acc_l[c][u];
         part[(int64_t)blockIdx.x * R + t] = a;
     }
     if (t == 0) {
         double a = 0.0;
-        for (int q = 0; q < stride * R; q += R) a += s_l[q];
+        for (int u = 0; u < stride * nq; u += nq) a += s_l[u];
         part_s[blockIdx.x] = a;
     }
 }
@@ -598,6 +641,26 @@ static ad_status check_relax_opts(const ad_relax_opts *o) {
     return AD_OK;
 }
 
+// s_i and 1/s_i: rows up to the plan's hub degree by lane groups, longer
+// rows (the plan's hub list) by a workgroup each.
+template <typename A>
+static ad_status weighted_degree_impl(const ad_graph *g, A *inv_s, float *sdeg, const SweepPlan &pl,
+                                      hipStream_t st) {
+    const int64_t n = g->n;
+    if (n <= 0) return AD_OK;
+    const int lpr = degree_lanes((double)(2 * g->m) / (double)n);
+    hipLaunchKernelGGL((k_weighted_degree<A>), dim3((unsigned)ceil_div(n * lpr, BLOCK)), dim3(BLOCK), 0, st, n,
+                       g->row_ptr, g->w, inv_s, sdeg, lpr, pl.sh.hub_d);
+    AD_LAUNCH_CHECK("k_weighted_degree");
+    if (g->d_max == 0 || g->d_max > pl.sh.hub_d) {
+        const unsigned grid = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(2 * g->m, pl.sh.hub_d + 1)));
+        hipLaunchKernelGGL((k_weighted_degree_hub<A>), dim3(grid), dim3(BLOCK), 0, st, pl.hub_list, pl.hub_count,
+                           g->row_ptr, g->w, inv_s, sdeg);
+        AD_LAUNCH_CHECK("k_weighted_degree_hub");
+    }
+    return AD_OK;
+}
+
 // Enqueue the whole relaxation.  `shift_out` may be NULL.
 template <typename T>
 static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const void *x0, void *x_out,
@@ -610,11 +673,25 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
     const double avg = n > 0 ? (double)(2 * g->m) / (double)n : 0.0;
     ad_status s;
 
+    // launch plans first: the hub list also serves the weighted degrees
+    RelaxLayout P = L;
+    P.p32.sh = sweep_shape(R, sizeof(T), o->rows_per_wave, o->hub_degree);
     if (n > 0) {
-        const int lpr = degree_lanes(avg);
-        hipLaunchKernelGGL((k_weighted_degree<A>), dim3((unsigned)ceil_div(n * lpr, BLOCK)), dim3(BLOCK), 0, st,
-                           n, g->row_ptr, g->w, (A *)L.inv_s, L.sdeg, lpr);
-        AD_LAUNCH_CHECK("k_weighted_degree");
+        s = sweep_plan_build(g, P.p32, true, st);
+        if (s != AD_OK) return s;
+        if (o->store == AD_BF16 && o->k > 0) {
+            P.p16.sh = sweep_shape(R, 2, o->rows_per_wave, o->hub_degree);
+            P.p16.sh.hub_d = P.p32.sh.hub_d;            // one hub list serves both
+            P.p16.hub_list = P.p32.hub_list;
+            P.p16.hub_count = P.p32.hub_count;
+            s = sweep_plan_build(g, P.p16, false, st);
+            if (s != AD_OK) return s;
+        }
+    }
+
+    if (n > 0) {
+        s = weighted_degree_impl<A>(g, (A *)L.inv_s, L.sdeg, P.p32, st);
+        if (s != AD_OK) return s;
         hipLaunchKernelGGL((k_centre_partials<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, L.sdeg,
                            g->orig_id, o->seed, o->graph_id, (const T *)x0, L.part, L.part_s);
         AD_LAUNCH_CHECK("k_centre_partials");
@@ -634,18 +711,6 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
     }
 
     if (o->k > 0 && n > 0) {
-        RelaxLayout P = L;
-        P.p32.sh = sweep_shape(R, sizeof(T), o->rows_per_wave, o->hub_degree);
-        s = sweep_plan_build(g, P.p32, true, st);
-        if (s != AD_OK) return s;
-        if (o->store == AD_BF16) {
-            P.p16.sh = sweep_shape(R, 2, o->rows_per_wave, o->hub_degree);
-            P.p16.sh.hub_d = P.p32.sh.hub_d;            // one hub list serves both
-            P.p16.hub_list = P.p32.hub_list;
-            P.p16.hub_count = P.p32.hub_count;
-            s = sweep_plan_build(g, P.p16, false, st);
-            if (s != AD_OK) return s;
-        }
         Buf cur = {start, o->store == AD_F64 ? AD_F64 : AD_F32};
         const int tail = o->store == AD_BF16 ? o->fp32_tail : o->k;
         for (int t = 1; t <= o->k; ++t) {
@@ -699,13 +764,8 @@ ad_status sweep_f32(const ad_graph *g, const float *inv_s, float omega, const fl
     return launch_sweep<float, float, float>(g, inv_s, omega, xin, xout, R, plan, st);
 }
 
-ad_status weighted_degree_f32(const ad_graph *g, float *inv_s, float *sdeg, hipStream_t st) {
-    if (g->n <= 0) return AD_OK;
-    const int lpr = degree_lanes((double)(2 * g->m) / (double)g->n);
-    hipLaunchKernelGGL((k_weighted_degree<float>), dim3((unsigned)ceil_div(g->n * lpr, BLOCK)), dim3(BLOCK), 0,
-                       st, g->n, g->row_ptr, g->w, inv_s, sdeg, lpr);
-    AD_LAUNCH_CHECK("k_weighted_degree");
-    return AD_OK;
+ad_status weighted_degree_f32(const ad_graph *g, float *inv_s, float *sdeg, const SweepPlan &pl, hipStream_t st) {
+    return weighted_degree_impl<float>(g, inv_s, sdeg, pl, st);
 }
 
 }  // namespace ad

@@ -1,17 +1,19 @@
 // ad_select.hip -- edge distances (Algorithm 1, last steps), per-vertex
 // ranking and selection (Algorithm 3) and the retention fit (Section 6.2).
 //
-// Distances: one lane per stored entry (i, j) with j > i walks the R values
-// of both rows in order r = 0..R-1, so the sum for an edge has one fixed
-// order and rho_ij == rho_ji bit for bit whichever endpoint computes it.
+// Distances: each upper entry (i, j), j > i, is handled by C lanes that
+// hold VEC consecutive values each; the squared scaled differences are
+// summed per lane in order and the lanes combined in a fixed tree, so each
+// distance has one summation order (the adjoint reproduces it).
 //
 // Ranking: every stored entry (i, j) gets its position in row i's order
 // (rho ascending for LOCAL, descending for GLOBAL; ties by orig_id[j]).
 // Keys are unique inside a row, so ranks are well defined.  Rows of degree
-// <= 64 rank by counting inside a wave (each lane compares its key with all
-// others of its row through shuffles); rows of degree <= 8192 sort their
-// keys with a bitonic network in LDS; longer rows count against keys read
-// from memory.
+// <= 64 are packed several to a wave, one entry per lane, and rank by
+// counting through shuffles; rows of degree <= 512 rank by counting inside
+// one wave with 2, 4 or 8 keys per lane; rows of degree <= 8192 sort their
+// keys with a bitonic network in LDS sized to the row; longer rows count
+// against keys read from memory.
 //
 // Selection at fixed e: entry (i, j) selects its edge when rank < budget[d_i];
 // keep[e] = 1 is written by any selecting entry (all writers store the same
@@ -34,15 +36,35 @@ namespace ad {
 
 constexpr int SBLOCK = 256;
 constexpr int SORT_CAP = 8192;       // longest row ranked in LDS
-constexpr int WAVE_CAP = 512;        // longest row ranked inside one wave
+constexpr int DIST_UNROLL = 8;       // entries per slot in flight in the distance pass
 
 // ---------------------------------------------------------------- distance --
 
-template <typename Tx, typename Tr, int VEC>
+// Sum over the C lanes of one entry's group (lanes base .. base + C - 1):
+// a butterfly when C is a power of two, ((c0 + c1) + (c2 + c3)) ..., else
+// c0 + c1 + ... in order.  Every lane of the group gets the same value.
+template <typename A>
+__device__ __forceinline__ A group_sum(A v, int C, int base) {
+    if ((C & (C - 1)) == 0) {
+        for (int off = 1; off < C; off <<= 1) v += __shfl_xor(v, off, WAVE);
+        return v;
+    }
+    A t = shfl(v, base);
+    for (int c = 1; c < C; ++c) t += shfl(v, base + c);
+    return t;
+}
+
+// rho for the upper entries (j > i) of every row.  Persistent waves walk a
+// launch plan (first row, log2 rows per wave) as the sweep does; per row
+// SPRW / rpw slots of C lanes, VEC values per lane, U entries per slot in
+// flight.  Lane chunk c sums ((x_i - x_j) * inv)^2 over its VEC values in
+// order; group_sum adds the chunks.
+template <typename Tx, typename Tr, int VEC, int U>
 __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
     int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const Tx *__restrict__ x, const double *__restrict__ minmax,
-    Tr *__restrict__ rho, int R, int LPR) {
+    Tr *__restrict__ rho, int R, int C, int SPRW, const long long *__restrict__ plan,
+    const unsigned int *__restrict__ plan_count) {
     typedef typename acc_of<Tx>::type A;
     __shared__ A inv_l[64];
     if (threadIdx.x < R) {
@@ -50,35 +72,88 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
         inv_l[threadIdx.x] = (hi > lo) ? (A)(1.0 / (hi - lo)) : (A)0;
     }
     __syncthreads();
-    // LPR lanes per row, SBLOCK / LPR rows per block
-    const int rows_per_block = SBLOCK / LPR;
-    const int64_t row = (int64_t)blockIdx.x * rows_per_block + threadIdx.x / LPR;
-    const int lane = threadIdx.x % LPR;
-    if (row >= n) return;
-    const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
-    const Tx *xi = x + row * R;
-    for (int64_t p = beg + lane; p < end; p += LPR) {
-        const int32_t j = col[p];
-        if (j <= row) continue;
-        const Tx *xj = x + (int64_t)j * R;
-        A acc = (A)0;
-        for (int r0 = 0; r0 < R; r0 += VEC) {
-            A a[VEC], b[VEC];
-            load_vec<VEC>(xi + r0, a);
-            load_vec<VEC>(xj + r0, b);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned int np = *plan_count;
+    const unsigned int nwaves = gridDim.x * (SBLOCK / WAVE);
+    for (unsigned int pi = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); pi < np; pi += nwaves) {
+        const long long pe = plan[pi];
+        const int64_t row0 = pe >> 8;
+        const int RPW = 1 << (int)(pe & 0xff);
+        const int SPR = SPRW / RPW;
+        const int group = C * SPR;
+        const int rw = lane / group;
+        const int sub = lane - rw * group;
+        const int slot = sub / C;
+        const int chunk = sub - slot * C;
+        const int base = lane - chunk;
+        const int64_t row = row0 + rw;
+        const bool active = rw < RPW && row < n;
+        int64_t beg = 0, end = 0;
+        if (active) {
+            beg = row_ptr[row];
+            end = row_ptr[row + 1];
+        }
+        const int off = chunk * VEC;
+        A xi[VEC], iv[VEC];
+        if (active) {
+            load_vec<VEC>(x + row * R + off, xi);
+        } else {
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) {
-                A d = (a[q] - b[q]) * inv_l[r0 + q];
-                acc = fma(d, d, acc);
+            for (int q = 0; q < VEC; ++q) xi[q] = (A)0;
+        }
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) iv[q] = inv_l[off + q];
+        // uniform trip count across the wave: the longest row of the wave
+        int64_t len = end - beg;
+        for (int d = WAVE / 2; d >= 1; d >>= 1) len = max(len, shfl_down(len, d));
+        len = shfl(len, 0);
+        for (int64_t k0 = slot; k0 < len; k0 += (int64_t)U * SPR) {
+            int32_t jj[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t p = beg + k0 + (int64_t)u * SPR;
+                ok[u] = active && p < end;
+                jj[u] = ok[u] ? col[p] : 0;
+                ok[u] = ok[u] && jj[u] > row;
+            }
+            A part[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                A xj[VEC];
+                if (ok[u]) {
+                    load_vec<VEC>(x + (int64_t)jj[u] * R + off, xj);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) xj[q] = xi[q];
+                }
+                A acc = (A)0;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) {
+                    const A d = (xi[q] - xj[q]) * iv[q];
+                    acc = fma(d, d, acc);
+                }
+                part[u] = acc;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const A tot = group_sum(part[u], C, base);
+                if (ok[u] && chunk == 0) rho[eid[beg + k0 + (int64_t)u * SPR]] = (Tr)sqrt(tot);
             }
         }
-        rho[eid[p]] = (Tr)sqrt(acc);
     }
 }
 
 // ------------------------------------------------------------------ ranking --
 
 enum { MODE_FIXED = 0, MODE_SIDES = 1 };
+
+// Original id of the neighbour of entry p (tie-break key): the per-entry
+// copy when the graph carries one, else a gather through orig_id.
+__device__ __forceinline__ int32_t nbr_id(int64_t p, int32_t j, const int32_t *__restrict__ col_orig,
+                                          const int32_t *__restrict__ orig_id) {
+    return col_orig ? col_orig[p] : (orig_id ? orig_id[j] : j);
+}
 
 // (rho_a, id_a) comes before (rho_b, id_b) in the row's order.
 template <typename Tr>
@@ -98,42 +173,156 @@ __device__ __forceinline__ void emit(int mode, int64_t row, int32_t j, int32_t e
     }
 }
 
-// Rows with SW/2 < d <= SW (1 <= d <= SW for the smallest class): SW lanes
-// per row, 64/SW rows per wave, ranks by counting through shuffles.
-template <typename Tr, int SW>
-__global__ __launch_bounds__(SBLOCK) void k_rank_small(
-    int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id, const Tr *__restrict__ rho,
-    int orient, int mode, int64_t dlo, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
+// Rows of degree <= 64, packed: a wave takes consecutive rows whose entries
+// fit in its 64 lanes (plan entry: first row << 8 | number of rows), one
+// entry per lane; each lane counts the entries of its own row that come
+// before it, broadcast one lane at a time.
+constexpr int RANK_TILE = 64;
+
+template <typename Tr>
+__global__ __launch_bounds__(SBLOCK) void k_rank_packed(
+    const long long *__restrict__ plan, const unsigned int *__restrict__ plan_count,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
+    const int32_t *__restrict__ col_orig, const Tr *__restrict__ rho,
+    int orient, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
     unsigned long long *__restrict__ sides) {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int seg = lane / SW;
-    const int q = lane - seg * SW;
-    const int64_t row = ((int64_t)blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6)) * (WAVE / SW) + seg;
-    int64_t beg = 0, d = 0;
-    if (row < n) {
-        beg = row_ptr[row];
-        d = row_ptr[row + 1] - beg;
+    const unsigned int np = *plan_count;
+    const unsigned int nwaves = gridDim.x * (SBLOCK / WAVE);
+    for (unsigned int pi = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); pi < np; pi += nwaves) {
+        const long long pe = plan[pi];
+        const int64_t first = pe >> 8;
+        const int nrows = (int)(pe & 0xff);
+        const int64_t rp = lane < nrows ? row_ptr[first + lane] : 0;
+        const int64_t e0 = row_ptr[first];
+        const int64_t e1 = row_ptr[first + nrows];
+        const int cnt = (int)(e1 - e0);
+        const int64_t e = e0 + lane;
+        const bool on = lane < cnt;
+        // my row: the last row of the wave that starts at or before my entry
+        int k = 0;
+        for (int q = 0; q < nrows; ++q) {
+            const int64_t rs = shfl(rp, q);
+            if (rs <= e) k = q;
+        }
+        const int64_t rb = shfl(rp, k);
+        const int64_t rn = shfl(rp, k + 1 < WAVE ? k + 1 : 0);
+        const int64_t re = (k + 1 < nrows) ? rn : e1;
+        const int s0 = (int)(rb - e0), d = (int)(re - rb);
+        Tr my_rho = (Tr)0;
+        int32_t my_id = 0, my_j = 0, my_e = 0;
+        if (on) {
+            my_j = col[e];
+            my_e = eid[e];
+            my_rho = rho[my_e];
+            my_id = nbr_id(e, my_j, col_orig, orig_id);
+        }
+        int rank = 0;
+        for (int t = 0; t < cnt; ++t) {
+            const Tr r = shfl(my_rho, t);
+            const int32_t id = shfl(my_id, t);
+            if (t >= s0 && t < s0 + d && before(r, id, my_rho, my_id, orient)) ++rank;
+        }
+        if (on) emit(mode, first + k, my_j, my_e, d, rank, budget, keep, sides);
     }
-    const bool mine = (d > dlo && d <= SW);
-    if (!__any(mine)) return;          // wave-uniform: no row of this class here
-    Tr my_rho = (Tr)0;
-    int32_t my_id = 0, my_j = 0, my_e = 0;
-    if (mine && q < d) {
-        my_j = col[beg + q];
-        my_e = eid[beg + q];
-        my_rho = rho[my_e];
-        my_id = orig_id ? orig_id[my_j] : my_j;
+}
+
+// Packing of rows with 1 <= degree <= 64 per tile of RANK_TILE rows: a wave
+// holds consecutive such rows (isolated rows ride along) while their entries
+// fit in 64 lanes; a longer row closes the wave.  fill == 0 counts waves per
+// tile, fill == 1 writes the plan entries at the scanned offsets.
+__global__ void k_rank_plan(int64_t n, const int64_t *__restrict__ row_ptr, int fill,
+                            unsigned int *__restrict__ tile_waves, long long *__restrict__ plan) {
+    const int64_t ntiles = ceil_div_dev(n, RANK_TILE);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r0 = t * RANK_TILE, r1 = min(n, r0 + RANK_TILE);
+        unsigned int waves = 0;
+        unsigned int o = fill ? tile_waves[t] : 0;
+        int64_t first = -1;
+        int cur = 0, nr = 0;
+        for (int64_t r = r0; r < r1; ++r) {
+            const int64_t d = row_ptr[r + 1] - row_ptr[r];
+            const bool small = d <= WAVE;
+            if (first >= 0 && (!small || cur + d > WAVE)) {
+                if (fill && cur > 0) plan[o++] = ((long long)first << 8) | nr;
+                if (cur > 0) ++waves;
+                first = -1;
+            }
+            if (!small) continue;
+            if (first < 0) {
+                first = r;
+                cur = 0;
+                nr = 0;
+            }
+            cur += (int)d;
+            ++nr;
+        }
+        if (first >= 0 && cur > 0) {
+            if (fill) plan[o++] = ((long long)first << 8) | nr;
+            ++waves;
+        }
+        if (!fill) tile_waves[t] = waves;
     }
-    int64_t rank = 0;
-    const int base = seg * SW;
-#pragma unroll 8
-    for (int t = 0; t < SW; ++t) {
-        Tr r = shfl(my_rho, base + t);
-        int32_t id = shfl(my_id, base + t);
-        if (t < d && before(r, id, my_rho, my_id, orient)) ++rank;
+}
+
+// Exclusive scan of per-tile counts in one block; total into *count.
+__global__ __launch_bounds__(SBLOCK) void k_scan_tiles(int64_t ntiles, unsigned int *__restrict__ v,
+                                                      unsigned int *__restrict__ count) {
+    __shared__ unsigned int part[SBLOCK];
+    const int t = threadIdx.x;
+    const int64_t per = ceil_div_dev(ntiles, SBLOCK);
+    const int64_t a = t * per, b = min(ntiles, a + per);
+    unsigned int sum = 0;
+    for (int64_t i = a; i < b; ++i) sum += v[i];
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        unsigned int run = 0;
+        for (int q = 0; q < SBLOCK; ++q) {
+            const unsigned int x = part[q];
+            part[q] = run;
+            run += x;
+        }
+        *count = run;
     }
-    if (mine && q < d) emit(mode, row, my_j, my_e, d, rank, budget, keep, sides);
+    __syncthreads();
+    unsigned int run = part[t];
+    for (int64_t i = a; i < b; ++i) {
+        const unsigned int x = v[i];
+        v[i] = run;
+        run += x;
+    }
+}
+
+// Rows with degree > 64 into per-class lists (class c holds rows with
+// lo[c] < d <= lo[c + 1]); one pass, atomic slots per class.
+constexpr int NCLASS = 8;
+struct ClassBounds {
+    int64_t lo[NCLASS + 1];
+    int64_t off[NCLASS];
+};
+
+__global__ void k_classify(int64_t n, const int64_t *__restrict__ row_ptr, ClassBounds cb,
+                           int32_t *__restrict__ lists, unsigned int *__restrict__ counts) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n_pad = ceil_div_dev(n, stride) * stride;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += stride) {
+        int c = -1;
+        if (i < n) {
+            const int64_t d = row_ptr[i + 1] - row_ptr[i];
+            if (d > cb.lo[0]) {
+                c = 0;
+                while (c + 1 < NCLASS && d > cb.lo[c + 1]) ++c;
+            }
+        }
+        if (!__any(c >= 0)) continue;       // uniform across the wave
+        for (int k = 0; k < NCLASS; ++k) {
+            const unsigned int at = wave_append(c == k, &counts[k]);
+            if (c == k) lists[cb.off[k] + at] = (int32_t)i;
+        }
+    }
 }
 
 // Order-preserving 64-bit key of (rho, orig_id) for the row's order.
@@ -143,14 +332,15 @@ __device__ __forceinline__ unsigned long long sort_key(float r, int32_t id, int 
     return ((unsigned long long)b << 32) | (unsigned long long)(uint32_t)id;
 }
 
-// Listed rows with 64 < d <= 64 * KPL (FP32 distances): one wave per row,
+// Listed rows with 32 * KPL < d <= 64 * KPL (FP32 distances): one wave per row,
 // KPL keys per lane; each key's rank counts the smaller keys of the row,
 // broadcast one lane at a time.
 template <int KPL>
 __global__ __launch_bounds__(SBLOCK) void k_rank_wave(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id, const float *__restrict__ rho,
+    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho,
     int orient, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
     unsigned long long *__restrict__ sides) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -168,7 +358,7 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_wave(
             if (q < d) {
                 jj[t] = col[beg + q];
                 ee[t] = eid[beg + q];
-                key[t] = sort_key(rho[ee[t]], orig_id ? orig_id[jj[t]] : jj[t], orient);
+                key[t] = sort_key(rho[ee[t]], nbr_id(beg + q, jj[t], col_orig, orig_id), orient);
             } else {
                 jj[t] = 0;
                 ee[t] = 0;
@@ -195,15 +385,18 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_wave(
     }
 }
 
-// Listed rows with 64 < d <= SORT_CAP (FP32 distances): bitonic sort in LDS.
-__global__ __launch_bounds__(SBLOCK) void k_rank_bitonic(
+// Listed rows with P_MAX/2 < d <= P_MAX (FP32 distances): bitonic sort in
+// LDS by a TB-thread workgroup.
+template <int P_MAX, int TB>
+__global__ __launch_bounds__(TB) void k_rank_bitonic(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id, const float *__restrict__ rho,
+    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho,
     int orient, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
     unsigned long long *__restrict__ sides) {
-    __shared__ unsigned long long key[SORT_CAP];
-    __shared__ uint16_t idx[SORT_CAP];
+    __shared__ unsigned long long key[P_MAX];
+    __shared__ uint16_t idx[P_MAX];
     const unsigned int nr = *count;
     for (unsigned int h = blockIdx.x; h < nr; h += gridDim.x) {
         const int64_t row = list[h];
@@ -211,10 +404,10 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_bitonic(
         const int d = (int)(row_ptr[row + 1] - beg);
         int P = 1;
         while (P < d) P <<= 1;
-        for (int t = threadIdx.x; t < P; t += SBLOCK) {
+        for (int t = threadIdx.x; t < P; t += TB) {
             if (t < d) {
                 int32_t j = col[beg + t];
-                key[t] = sort_key(rho[eid[beg + t]], orig_id ? orig_id[j] : j, orient);
+                key[t] = sort_key(rho[eid[beg + t]], nbr_id(beg + t, j, col_orig, orig_id), orient);
             } else {
                 key[t] = ~0ull;
             }
@@ -223,7 +416,7 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_bitonic(
         __syncthreads();
         for (int size = 2; size <= P; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int t = threadIdx.x; t < (P >> 1); t += SBLOCK) {
+                for (int t = threadIdx.x; t < (P >> 1); t += TB) {
                     int a = 2 * t - (t & (stride - 1));
                     int b = a + stride;
                     bool up = ((a & size) == 0);
@@ -239,7 +432,7 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_bitonic(
                 __syncthreads();
             }
         }
-        for (int t = threadIdx.x; t < d; t += SBLOCK) {
+        for (int t = threadIdx.x; t < d; t += TB) {
             int at = idx[t];
             int64_t p = beg + at;
             emit(mode, row, col[p], eid[p], d, t, budget, keep, sides);
@@ -249,12 +442,13 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_bitonic(
 }
 
 // Listed rows ranked by counting against keys read from memory (FP64
-// distances with d > 64, or any row longer than SORT_CAP).
+// distances with d > 64, or FP32 rows longer than SORT_CAP).
 template <typename Tr>
 __global__ __launch_bounds__(SBLOCK) void k_rank_count(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id, const Tr *__restrict__ rho,
+    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
+    const int32_t *__restrict__ col_orig, const Tr *__restrict__ rho,
     int orient, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
     unsigned long long *__restrict__ sides) {
     const unsigned int nr = *count;
@@ -266,12 +460,12 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_count(
             const int32_t j = col[beg + t];
             const int32_t e = eid[beg + t];
             const Tr r = rho[e];
-            const int32_t id = orig_id ? orig_id[j] : j;
+            const int32_t id = nbr_id(beg + t, j, col_orig, orig_id);
             int64_t rank = 0;
             for (int64_t u = 0; u < d; ++u) {
                 const int32_t ju = col[beg + u];
                 const Tr ru = rho[eid[beg + u]];
-                const int32_t iu = orig_id ? orig_id[ju] : ju;
+                const int32_t iu = nbr_id(beg + u, ju, col_orig, orig_id);
                 if (before(ru, iu, r, id, orient)) ++rank;
             }
             emit(mode, row, j, e, d, rank, budget, keep, sides);
@@ -311,9 +505,17 @@ constexpr int DIGIT = 11;
 constexpr int NBINS = 1 << DIGIT;
 constexpr double GRID = 1099511627776.0;   // 2^40
 
-// Estimated grid index of each edge's threshold (0: kept at every e).
+// logs[v] = log(v) for v = 1 .. d_max + 1 (logs[0] unused).
+__global__ void k_log_table(int64_t count, double *__restrict__ logs) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < count;
+         v += (int64_t)gridDim.x * blockDim.x)
+        logs[v] = v > 0 ? log((double)v) : 0.0;
+}
+
+// Estimated grid index of each edge's threshold (0: kept at every e): the
+// side (d, r) selects once d^e >= r + 1, i.e. e >= log(r + 1) / log(d).
 __global__ void k_fit_grid(int64_t m, const unsigned long long *__restrict__ sides,
-                           unsigned long long *__restrict__ G) {
+                           const double *__restrict__ logs, unsigned long long *__restrict__ G) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
         unsigned long long best = ~0ull;
@@ -324,7 +526,7 @@ __global__ void k_fit_grid(int64_t m, const unsigned long long *__restrict__ sid
             if (r == 0 || d < 2) {
                 gidx = 0;
             } else {
-                double t = log((double)(r + 1)) / log((double)d);
+                double t = logs[r + 1] / logs[d];
                 double gi = ceil(t * GRID);
                 gidx = gi <= 0.0 ? 0ull : (unsigned long long)gi;
             }
@@ -418,24 +620,42 @@ __global__ void k_store_count(const unsigned long long *__restrict__ c, int64_t 
 // ------------------------------------------------------------------- host --
 
 struct SelLayout {
-    int32_t *list_big, *list_mid, *list_huge;
-    unsigned int *cnt;            // [3]: wave-ranked, huge, LDS-sorted
+    int32_t *lists;               // rows of degree > 64, by class
+    unsigned int *cnt;            // [NCLASS]
+    ClassBounds cb;
+    long long *plan;              // packed small-row waves
+    unsigned int *tile_waves, *plan_count;
     unsigned long long *sides;    // [2m]
     unsigned long long *G;        // [m]
     unsigned int *hist;           // [NBINS]
     unsigned long long *state;    // [2]
     unsigned long long *counts;   // [2]
     int32_t *tab_hi, *tab_lo;     // [d_max + 1]
+    double *logs;                 // [d_max + 2]
 };
+
+// Degree classes above 64: wave counting with 2/4/8 keys per lane, bitonic
+// sorts in LDS of 1024/2048/4096/8192 keys, then counting from memory.
+static const int64_t CLASS_LO[NCLASS + 1] = {64, 128, 256, 512, 1024, 2048, 4096, 8192, (int64_t)1 << 62};
 
 static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout *L) {
     Carver c(ws, ws_bytes);
     const int64_t n = std::max<int64_t>(1, g->n), m = std::max<int64_t>(1, g->m);
+    const int64_t ntiles = std::max<int64_t>(1, ceil_div(g->n, RANK_TILE));
     SelLayout l;
-    l.list_big = c.take<int32_t>(n);
-    l.list_mid = c.take<int32_t>(n);
-    l.list_huge = c.take<int32_t>(n);
-    l.cnt = c.take<unsigned int>(3);
+    int64_t total = 0;
+    for (int k = 0; k <= NCLASS; ++k) l.cb.lo[k] = CLASS_LO[k];
+    for (int k = 0; k < NCLASS; ++k) {
+        // rows in class k have degree > lo[k]: at most 2m / (lo[k] + 1) of them
+        const int64_t cap = std::min<int64_t>(n, ceil_div(2 * m, CLASS_LO[k] + 1));
+        l.cb.off[k] = total;
+        total += cap;
+    }
+    l.lists = c.take<int32_t>(total);
+    l.cnt = c.take<unsigned int>(NCLASS);
+    l.plan = c.take<long long>(n + ntiles);
+    l.tile_waves = c.take<unsigned int>(ntiles);
+    l.plan_count = c.take<unsigned int>(1);
     l.sides = c.take<unsigned long long>(2 * m);
     l.G = c.take<unsigned long long>(m);
     l.hist = c.take<unsigned int>(NBINS);
@@ -443,6 +663,7 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     l.counts = c.take<unsigned long long>(2);
     l.tab_hi = c.take<int32_t>((size_t)g->d_max + 1);
     l.tab_lo = c.take<int32_t>((size_t)g->d_max + 1);
+    l.logs = c.take<double>((size_t)g->d_max + 2);
     if (L) *L = l;
     return c.ok() ? c.used : 0;
 }
@@ -465,63 +686,69 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, int orient, int mode
     const int64_t n = g->n;
     if (n <= 0 || g->m <= 0) return AD_OK;
     TraceScope trace("k_rank", st);
-    const int rows_per_block_8 = (SBLOCK / WAVE) * (WAVE / 8);
-    hipLaunchKernelGGL((k_rank_small<Tr, 8>), dim3((unsigned)ceil_div(n, rows_per_block_8)), dim3(SBLOCK), 0,
-                       st, n, g->row_ptr, g->col, g->eid, g->orig_id, rho, orient, mode, (int64_t)0, budget,
-                       keep, L.sides);
-    AD_LAUNCH_CHECK("k_rank_small<8>");
-    if (g->d_max > 8) {
-        const int rpb = (SBLOCK / WAVE) * (WAVE / 16);
-        hipLaunchKernelGGL((k_rank_small<Tr, 16>), dim3((unsigned)ceil_div(n, rpb)), dim3(SBLOCK), 0, st, n,
-                           g->row_ptr, g->col, g->eid, g->orig_id, rho, orient, mode, (int64_t)8, budget, keep,
-                           L.sides);
-        AD_LAUNCH_CHECK("k_rank_small<16>");
-    }
-    if (g->d_max > 16) {
-        const int rpb = (SBLOCK / WAVE) * (WAVE / 32);
-        hipLaunchKernelGGL((k_rank_small<Tr, 32>), dim3((unsigned)ceil_div(n, rpb)), dim3(SBLOCK), 0, st, n,
-                           g->row_ptr, g->col, g->eid, g->orig_id, rho, orient, mode, (int64_t)16, budget, keep,
-                           L.sides);
-        AD_LAUNCH_CHECK("k_rank_small<32>");
-    }
-    if (g->d_max > 32) {
-        const int rpb = (SBLOCK / WAVE);
-        hipLaunchKernelGGL((k_rank_small<Tr, 64>), dim3((unsigned)ceil_div(n, rpb)), dim3(SBLOCK), 0, st, n,
-                           g->row_ptr, g->col, g->eid, g->orig_id, rho, orient, mode, (int64_t)32, budget, keep,
-                           L.sides);
-        AD_LAUNCH_CHECK("k_rank_small<64>");
-    }
-    if (g->d_max > 64) {
-        ad_status s = fill_i32((int32_t *)L.cnt, 0, 3, st);
-        if (s != AD_OK) return s;
-        const bool f32 = sizeof(Tr) == 4;
-        const int64_t cap = f32 ? SORT_CAP : 64;
-        unsigned grid = (unsigned)std::min<int64_t>(2048, n);
-        if (f32) {
-            s = collect_rows(g, 64, WAVE_CAP, L.list_big, &L.cnt[0], st);
-            if (s != AD_OK) return s;
-            hipLaunchKernelGGL((k_rank_wave<WAVE_CAP / WAVE>), dim3(grid), dim3(SBLOCK), 0, st, L.list_big,
-                               &L.cnt[0], g->row_ptr, g->col, g->eid, g->orig_id, (const float *)rho, orient, mode,
-                               budget, keep, L.sides);
-            AD_LAUNCH_CHECK("k_rank_wave");
-            if (g->d_max > WAVE_CAP) {
-                s = collect_rows(g, WAVE_CAP, cap, L.list_mid, &L.cnt[2], st);
-                if (s != AD_OK) return s;
-                hipLaunchKernelGGL(k_rank_bitonic, dim3(grid), dim3(SBLOCK), 0, st, L.list_mid, &L.cnt[2],
-                                   g->row_ptr, g->col, g->eid, g->orig_id, (const float *)rho, orient, mode,
-                                   budget, keep, L.sides);
-                AD_LAUNCH_CHECK("k_rank_bitonic");
-            }
+    ad_status s;
+    // rows of degree <= 64, packed into waves
+    const int64_t ntiles = ceil_div(n, RANK_TILE);
+    hipLaunchKernelGGL(k_rank_plan, dim3(grid_for(ntiles, SBLOCK)), dim3(SBLOCK), 0, st, n, g->row_ptr, 0,
+                       L.tile_waves, L.plan);
+    AD_LAUNCH_CHECK("k_rank_plan");
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SBLOCK), 0, st, ntiles, L.tile_waves, L.plan_count);
+    AD_LAUNCH_CHECK("k_scan_tiles");
+    hipLaunchKernelGGL(k_rank_plan, dim3(grid_for(ntiles, SBLOCK)), dim3(SBLOCK), 0, st, n, g->row_ptr, 1,
+                       L.tile_waves, L.plan);
+    AD_LAUNCH_CHECK("k_rank_plan");
+    const unsigned packed_blocks = (unsigned)std::min<int64_t>(4096, ceil_div(n, SBLOCK / WAVE));
+    hipLaunchKernelGGL((k_rank_packed<Tr>), dim3(packed_blocks), dim3(SBLOCK), 0, st, L.plan, L.plan_count,
+                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rho, orient, mode, budget, keep,
+                       L.sides);
+    AD_LAUNCH_CHECK("k_rank_packed");
+    if (g->d_max <= 64) return AD_OK;
+
+    s = fill_i32((int32_t *)L.cnt, 0, NCLASS, st);
+    if (s != AD_OK) return s;
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(n, SBLOCK)), dim3(SBLOCK), 0, st, n, g->row_ptr, L.cb, L.lists,
+                       L.cnt);
+    AD_LAUNCH_CHECK("k_classify");
+    const unsigned grid = (unsigned)std::min<int64_t>(2048, n);
+    const int32_t *lst[NCLASS];
+    for (int k = 0; k < NCLASS; ++k) lst[k] = L.lists + L.cb.off[k];
+#define AD_RANK_ARGS g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rho, orient, mode, budget, keep, L.sides
+    if (sizeof(Tr) == 4) {
+        const float *rf = (const float *)rho;
+#define AD_RANK_ARGS_F g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, orient, mode, budget, keep, L.sides
+        if (g->d_max > 64)
+            hipLaunchKernelGGL((k_rank_wave<2>), dim3(grid), dim3(SBLOCK), 0, st, lst[0], &L.cnt[0], AD_RANK_ARGS_F);
+        if (g->d_max > 128)
+            hipLaunchKernelGGL((k_rank_wave<4>), dim3(grid), dim3(SBLOCK), 0, st, lst[1], &L.cnt[1], AD_RANK_ARGS_F);
+        if (g->d_max > 256)
+            hipLaunchKernelGGL((k_rank_wave<8>), dim3(grid), dim3(SBLOCK), 0, st, lst[2], &L.cnt[2], AD_RANK_ARGS_F);
+        AD_LAUNCH_CHECK("k_rank_wave");
+        if (g->d_max > 512)
+            hipLaunchKernelGGL((k_rank_bitonic<1024, 256>), dim3(grid), dim3(256), 0, st, lst[3], &L.cnt[3],
+                               AD_RANK_ARGS_F);
+        if (g->d_max > 1024)
+            hipLaunchKernelGGL((k_rank_bitonic<2048, 256>), dim3(grid), dim3(256), 0, st, lst[4], &L.cnt[4],
+                               AD_RANK_ARGS_F);
+        if (g->d_max > 2048)
+            hipLaunchKernelGGL((k_rank_bitonic<4096, 512>), dim3(grid), dim3(512), 0, st, lst[5], &L.cnt[5],
+                               AD_RANK_ARGS_F);
+        if (g->d_max > 4096)
+            hipLaunchKernelGGL((k_rank_bitonic<8192, 1024>), dim3(grid), dim3(1024), 0, st, lst[6], &L.cnt[6],
+                               AD_RANK_ARGS_F);
+        AD_LAUNCH_CHECK("k_rank_bitonic");
+#undef AD_RANK_ARGS_F
+        if (g->d_max > SORT_CAP) {
+            hipLaunchKernelGGL((k_rank_count<Tr>), dim3(grid), dim3(SBLOCK), 0, st, lst[7], &L.cnt[7], AD_RANK_ARGS);
+            AD_LAUNCH_CHECK("k_rank_count");
         }
-        if (g->d_max > cap) {
-            s = collect_rows(g, cap, (int64_t)1 << 62, L.list_huge, &L.cnt[1], st);
-            if (s != AD_OK) return s;
-            hipLaunchKernelGGL((k_rank_count<Tr>), dim3(grid), dim3(SBLOCK), 0, st, L.list_huge, &L.cnt[1],
-                               g->row_ptr, g->col, g->eid, g->orig_id, rho, orient, mode, budget, keep,
-                               L.sides);
+    } else {
+        for (int k = 0; k < NCLASS; ++k) {
+            if (g->d_max <= CLASS_LO[k]) break;
+            hipLaunchKernelGGL((k_rank_count<Tr>), dim3(grid), dim3(SBLOCK), 0, st, lst[k], &L.cnt[k], AD_RANK_ARGS);
             AD_LAUNCH_CHECK("k_rank_count");
         }
     }
+#undef AD_RANK_ARGS
     return AD_OK;
 }
 
@@ -544,37 +771,52 @@ static ad_status check_sel_args(const ad_graph *g, ad_dtype rho_dtype, const voi
 
 using namespace ad;
 
+static SweepShape dist_shape(int R, ad_dtype x_dtype) {
+    // the sweep's lane layout for this vector width; every row in the plan
+    // (no hub rows: a long row keeps one wave to itself)
+    SweepShape sh = sweep_shape(R, x_dtype == AD_F64 ? 8 : 4, 0, 0);
+    sh.hub_d = (int64_t)1 << 62;
+    return sh;
+}
+
+extern "C" size_t ad_edge_dist_workspace_size(const ad_graph *g) {
+    if (check_graph_args(g) != AD_OK) return 0;
+    return sweep_plan_bytes(g->n);
+}
+
 extern "C" ad_status ad_edge_dist(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
-                                  const double *minmax, void *rho, hipStream_t stream) {
+                                  const double *minmax, void *rho, void *ws, size_t ws_bytes,
+                                  hipStream_t stream) {
     ad_status s = check_graph_args(g);
     if (s != AD_OK) return s;
     if (R < 1 || R > 64) return fail(AD_ERR_INVALID_ARG, "R must be in [1, 64]");
     if (x_dtype != AD_F32 && x_dtype != AD_F64) return fail(AD_ERR_INVALID_ARG, "x must be F32 or F64");
     if (g->m > 0 && (!x || !minmax || !rho)) return fail(AD_ERR_INVALID_ARG, "x, minmax or rho is NULL");
+    if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    Carver c(ws, ws_bytes);
+    SweepPlan pl;
+    sweep_plan_carve(c, g->n, pl);
+    if (!c.ok()) return fail(AD_ERR_WORKSPACE, "workspace too small");
     if (g->n <= 0 || g->m <= 0) return AD_OK;
-    const double avg = (double)(2 * g->m) / (double)g->n;
-    int lpr = 1;
-    while (lpr < 64 && lpr < avg) lpr <<= 1;   // lanes per row ~ average degree
-    const unsigned nb = (unsigned)ceil_div(g->n, SBLOCK / lpr);
+    pl.sh = dist_shape(R, x_dtype);
+    s = sweep_plan_build(g, pl, false, stream);
+    if (s != AD_OK) return s;
+    const unsigned nb = (unsigned)std::min<int64_t>(4096, ceil_div(g->n, SBLOCK / WAVE));
     TraceScope trace("k_edge_dist", stream);
+#define AD_DIST(TX, TR, V)                                                                                   \
+    hipLaunchKernelGGL((k_edge_dist<TX, TR, V, DIST_UNROLL>), dim3(nb), dim3(SBLOCK), 0, stream, g->n,      \
+                       g->row_ptr, g->col, g->eid, (const TX *)x, minmax, (TR *)rho, R, pl.sh.C, pl.sh.SPRW,  \
+                       pl.plan, pl.plan_count)
     if (x_dtype == AD_F64) {
-        if (R % 2 == 0)
-            hipLaunchKernelGGL((k_edge_dist<double, double, 2>), dim3(nb), dim3(SBLOCK), 0, stream, g->n, g->row_ptr,
-                               g->col, g->eid, (const double *)x, minmax, (double *)rho, R, lpr);
-        else
-            hipLaunchKernelGGL((k_edge_dist<double, double, 1>), dim3(nb), dim3(SBLOCK), 0, stream, g->n, g->row_ptr,
-                               g->col, g->eid, (const double *)x, minmax, (double *)rho, R, lpr);
+        if (pl.sh.vec == 2) AD_DIST(double, double, 2);
+        else AD_DIST(double, double, 1);
     } else {
-        if (R % 4 == 0)
-            hipLaunchKernelGGL((k_edge_dist<float, float, 4>), dim3(nb), dim3(SBLOCK), 0, stream, g->n, g->row_ptr,
-                               g->col, g->eid, (const float *)x, minmax, (float *)rho, R, lpr);
-        else if (R % 2 == 0)
-            hipLaunchKernelGGL((k_edge_dist<float, float, 2>), dim3(nb), dim3(SBLOCK), 0, stream, g->n, g->row_ptr,
-                               g->col, g->eid, (const float *)x, minmax, (float *)rho, R, lpr);
-        else
-            hipLaunchKernelGGL((k_edge_dist<float, float, 1>), dim3(nb), dim3(SBLOCK), 0, stream, g->n, g->row_ptr,
-                               g->col, g->eid, (const float *)x, minmax, (float *)rho, R, lpr);
+        if (pl.sh.vec == 4) AD_DIST(float, float, 4);
+        else if (pl.sh.vec == 2) AD_DIST(float, float, 2);
+        else AD_DIST(float, float, 1);
     }
+#undef AD_DIST
     AD_LAUNCH_CHECK("k_edge_dist");
     return AD_OK;
 }
@@ -652,7 +894,10 @@ extern "C" ad_status ad_sparsify_fit(const ad_graph *g, ad_dtype rho_dtype, cons
         s = rank_all<double>(g, (const double *)rho, orient, MODE_SIDES, nullptr, keep, L, stream);
     if (s != AD_OK) return s;
     TraceScope trace_fit("k_fit_select", stream);
-    hipLaunchKernelGGL(k_fit_grid, dim3(grid_for(m, SBLOCK)), dim3(SBLOCK), 0, stream, m, L.sides, L.G);
+    hipLaunchKernelGGL(k_log_table, dim3(grid_for((int64_t)g->d_max + 2, SBLOCK)), dim3(SBLOCK), 0, stream,
+                       (int64_t)g->d_max + 2, L.logs);
+    AD_LAUNCH_CHECK("k_log_table");
+    hipLaunchKernelGGL(k_fit_grid, dim3(grid_for(m, SBLOCK)), dim3(SBLOCK), 0, stream, m, L.sides, L.logs, L.G);
     AD_LAUNCH_CHECK("k_fit_grid");
     hipLaunchKernelGGL(k_select_init, dim3(1), dim3(1), 0, stream, L.state, (unsigned long long)K);
     AD_LAUNCH_CHECK("k_select_init");

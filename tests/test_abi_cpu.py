@@ -44,7 +44,7 @@ def test_binding_names_match_header():
 
 
 def _graph_struct(api, n=4, m=3):
-    return api.ADGraph(n, m, 0x1000, 0x2000, None, 0x3000, None, 3)
+    return api.ADGraph(n, m, 0x1000, 0x2000, None, 0x3000, None, 3, None)
 
 
 def test_status_strings(lib):
@@ -77,7 +77,7 @@ def test_relax_rejects_bad_arguments():
     assert call(api.relax_opts(4, 2), nbytes=16) == 3                     # too small
     msg = L.ad_last_error().decode()
     assert "workspace" in msg
-    bad = api.ADGraph(4, 3, None, 0x2000, None, 0x3000, None, 3)
+    bad = api.ADGraph(4, 3, None, 0x2000, None, 0x3000, None, 3, None)
     assert call(api.relax_opts(4, 2), gp=ctypes.byref(bad)) == 1
 
 
@@ -93,8 +93,9 @@ def test_selection_rejects_bad_arguments():
     assert L.ad_sparsify_fit(ctypes.byref(g), 2, p, 0, 0.3, p, p, ctypes.byref(e), ws, 1 << 30, None) == 1
     assert L.ad_sparsify(ctypes.byref(g), 1, p, 7, p, p, p, ws, 1 << 30, None) == 1
     assert L.ad_sparsify(ctypes.byref(g), 1, p, 0, None, p, p, ws, 1 << 30, None) == 1
-    assert L.ad_edge_dist(ctypes.byref(g), 0, 1, p, p, p, None) == 1
-    assert L.ad_edge_dist(ctypes.byref(g), 4, 2, p, p, p, None) == 1
+    assert L.ad_edge_dist(ctypes.byref(g), 0, 1, p, p, p, ws, 1 << 30, None) == 1
+    assert L.ad_edge_dist(ctypes.byref(g), 4, 2, p, p, p, ws, 1 << 30, None) == 1
+    assert L.ad_edge_dist(ctypes.byref(g), 4, 1, p, p, p, ws, 16, None) == 3
 
 
 def test_budget_table_host():
@@ -112,7 +113,7 @@ def test_budget_table_host():
 def test_workspace_sizes_are_positive():
     from paper_1601_05527_amd import api
     L = api.lib
-    g = api.ADGraph(1000, 5000, 0x1000, 0x2000, None, 0x3000, None, 40)
+    g = api.ADGraph(1000, 5000, 0x1000, 0x2000, None, 0x3000, None, 40, None)
     o = api.relax_opts(16, 20)
     assert L.ad_relax_workspace_size(ctypes.byref(g), ctypes.byref(o)) >= 2 * 1000 * 16 * 4
     assert L.ad_sparsify_workspace_size(ctypes.byref(g)) >= 5000 * 24

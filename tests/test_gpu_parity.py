@@ -139,15 +139,19 @@ def test_repeatable_bitwise(api):
 
 def _mixed_degree_graph():
     """Random graph plus vertices whose degrees straddle every ranking
-    path boundary (8, 16, 32, 64, 512, 8192) and one isolated vertex."""
+    path boundary (64, 128, 256, 512, 1024, 2048, 4096, 8192) and one
+    isolated vertex."""
     rng = np.random.default_rng(12)
     n = 12000
     base = G.gnm(n - 1, 30000, 3)
     us, vs = [base.edge_u], [base.edge_v]
     existing = set(zip(base.edge_u.tolist(), base.edge_v.tolist()))
-    for hub, deg in [(0, 8), (1, 9), (2, 16), (3, 17), (4, 32), (5, 33), (6, 64), (7, 65),
-                     (8, 300), (9, 8192), (10, 8193), (11, 9000), (12, 512), (13, 513), (14, 1000)]:
-        others = rng.choice(np.arange(15, n - 1), size=deg + 200, replace=False)
+    hubs = [(0, 8), (1, 9), (2, 16), (3, 17), (4, 32), (5, 33), (6, 64), (7, 65),
+            (8, 300), (9, 8192), (10, 8193), (11, 9000), (12, 512), (13, 513), (14, 1000),
+            (15, 128), (16, 129), (17, 256), (18, 257), (19, 1024), (20, 1025), (21, 2048),
+            (22, 2049), (23, 4096), (24, 4097)]
+    for hub, deg in hubs:
+        others = rng.choice(np.arange(len(hubs), n - 1), size=deg + 200, replace=False)
         have = set(int(b) if a == hub else int(a) for a, b in existing if a == hub or b == hub)
         add = [int(o) for o in others if int(o) not in have][: max(0, deg - len(have))]
         for o in add:
