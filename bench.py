@@ -55,6 +55,23 @@ def dist_bytes(n: int, nnz: int, m: int, r: int, bx: int) -> int:
     return (n + 1) * 8 + nnz * 4 + nnz * 4 + n * r * bx + 4 * m
 
 
+def sweep_traffic() -> "float | None":
+    """HBM traffic per k_sweep launch from the committed counter summary
+    (profiles/k_sweep_traffic.json), or None when the sweep kernel's source
+    has changed since those counters were taken."""
+    import hashlib
+    try:
+        info = json.load(open(os.path.join(ROOT, "profiles", "k_sweep_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_1601_05527_amd", "csrc", "ad_relax.hip")).read()
+        i = src.index("template <int U, int VEC, typename Tin, typename A>\n__device__ __forceinline__ void gather_rows")
+        j = src.index("// Launch plan of the sweep")
+    except (OSError, ValueError):
+        return None
+    if hashlib.sha256(src[i:j].encode()).hexdigest()[:16] != info.get("kernel_source_sha256_16"):
+        return None
+    return float(info["traffic_bytes_per_launch"])
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,7 +231,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": sweep_traffic(),
             "bytes_per_launch": sb,
             "avg_launch_ms": sweep_ms,
         },

@@ -222,6 +222,50 @@ ad_status ad_edge_to_entries(const ad_graph *g, const float *w_edge, float *w_en
  * (= col[p] when orig_id is NULL), p < 2m.  Build once per graph. */
 ad_status ad_graph_col_orig(const ad_graph *g, int32_t *col_orig, hipStream_t stream);
 
+/* --------------------------------------------------------------- batch --- */
+
+/* Batched form: G independent graphs, each run through ad_relax (FP32),
+ * ad_edge_dist and ad_sparsify at one fixed e, as one captured sequence of
+ * kernel launches covering all graphs (a HIP graph replayed by
+ * ad_batch_run).  Graph q is relaxed with key word o->graph_id + q; its
+ * distances, kept edges and count equal, bit for bit, those of the three
+ * calls on graph q alone with the same options (including rows_per_wave).
+ * The batch owns a packed copy of the graphs, its workspaces and its
+ * outputs (device memory allocated by ad_batch_create, freed by
+ * ad_batch_destroy -- the one exception to "no call allocates").
+ * ad_batch_create synchronises `stream`; it may first time the candidate
+ * rows_per_wave values on the batch (autotune) and keep the fastest. */
+typedef struct ad_batch ad_batch;
+typedef struct {
+    ad_orient orient;         /* Algorithm 3 orientation for every graph          */
+    double e;                 /* fixed exponent in [0, 1]                          */
+    int32_t autotune;         /* 1: choose rows_per_wave by timing on the batch    */
+} ad_batch_opts;
+
+/* graphs: host array of G graph descriptions (device pointers, host n, m,
+ * d_max); o: relaxation options (store must be AD_F32, no checkpoints). */
+ad_status ad_batch_create(int32_t G, const ad_graph *graphs, const ad_relax_opts *o,
+                          const ad_batch_opts *bo, ad_batch **out, hipStream_t stream);
+/* Replays the captured sequence on `stream`. */
+ad_status ad_batch_run(ad_batch *b, hipStream_t stream);
+/* The same sequence enqueued kernel by kernel (no graph replay). */
+ad_status ad_batch_run_uncaptured(ad_batch *b, hipStream_t stream);
+/* Host copies of the packing: row_off_host [G+1], edge_off_host [G+1] (edge
+ * ids of graph q are [edge_off[q], edge_off[q+1]) in the packed outputs),
+ * and the rows_per_wave in use.  Any pointer may be NULL. */
+ad_status ad_batch_info(const ad_batch *b, int64_t *row_off_host, int64_t *edge_off_host,
+                        int32_t *rows_per_wave_host);
+/* Device pointers to the outputs of the last run: rho [sum m] FP32, keep
+ * [sum m], n_kept [G] int64, minmax [G][2R] doubles.  Valid until the next
+ * run or destroy. */
+ad_status ad_batch_results(const ad_batch *b, const float **rho, const uint8_t **keep,
+                           const int64_t **n_kept, const double **minmax);
+/* The same outputs copied (device to device, on `stream`) into caller
+ * buffers of the sizes above; any pointer may be NULL. */
+ad_status ad_batch_copy_results(const ad_batch *b, float *rho, uint8_t *keep, int64_t *n_kept,
+                                double *minmax, hipStream_t stream);
+void ad_batch_destroy(ad_batch *b);
+
 /* ---------------------------------------------------------- diagnostics -- */
 
 /* Checks on the device that the CSR is a valid symmetric simple graph:

@@ -41,6 +41,10 @@ class ADRelaxOpts(ctypes.Structure):
                 ("rows_per_wave", ctypes.c_int32), ("hub_degree", ctypes.c_int32)]
 
 
+class ADBatchOpts(ctypes.Structure):
+    _fields_ = [("orient", ctypes.c_int), ("e", ctypes.c_double), ("autotune", ctypes.c_int32)]
+
+
 class ADError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
@@ -70,6 +74,13 @@ def _load_lib():
         "ad_relax_backward": (st, [G, O, P, P, P, P, P, P, S, P]),
         "ad_edge_to_entries": (st, [G, P, P, P]),
         "ad_graph_col_orig": (st, [G, P, P]),
+        "ad_batch_create": (st, [i32, G, O, ctypes.POINTER(ADBatchOpts), ctypes.POINTER(P), P]),
+        "ad_batch_run": (st, [P, P]),
+        "ad_batch_run_uncaptured": (st, [P, P]),
+        "ad_batch_info": (st, [P, P, P, P]),
+        "ad_batch_results": (st, [P, P, P, P, P]),
+        "ad_batch_copy_results": (st, [P, P, P, P, P, P]),
+        "ad_batch_destroy": (None, [P]),
         "ad_validate_workspace_size": (S, [G]),
         "ad_validate_graph": (st, [G, P, S, P]),
         "ad_trace_enable": (None, [i32]),
@@ -359,6 +370,60 @@ class AlgDist(torch.autograd.Function):
         gw = relax_backward(ctx.dgw, ctx.res, R, k, grad_rho.contiguous().float(), omega, seed,
                             ckpt_every=ckpt_every)
         return gw, None, None, None, None, None, None
+
+
+# --------------------------------------------------------------- batches ---
+
+class Batch:
+    """Many graphs relaxed, measured and sparsified (fixed e) as one captured
+    launch sequence (``ad_batch_*``).  Graph q uses start-vector key word
+    graph_id + q; results equal running each graph alone, bit for bit."""
+
+    def __init__(self, graphs, R: int, k: int, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
+                 orient: int = AD_LOCAL, e: float = 0.5, autotune: bool = True,
+                 rows_per_wave: int = 0, hub_degree: int = 0):
+        self.graphs = list(graphs)        # keep the inputs alive while packing
+        self.G = len(self.graphs)
+        self.R = R
+        arr = (ADGraph * self.G)(*[dg.abi() for dg in self.graphs])
+        opts = relax_opts(R, k, omega, seed, graph_id, "f32", 2, 0, rows_per_wave, hub_degree)
+        bo = ADBatchOpts(orient, float(e), 1 if autotune else 0)
+        h = ctypes.c_void_p()
+        _check(lib.ad_batch_create(self.G, arr, ctypes.byref(opts), ctypes.byref(bo), ctypes.byref(h), _stream()))
+        self._h = h
+        ro = np.zeros(self.G + 1, dtype=np.int64)
+        eo = np.zeros(self.G + 1, dtype=np.int64)
+        rpw = ctypes.c_int32()
+        _check(lib.ad_batch_info(h, ro.ctypes.data_as(ctypes.c_void_p), eo.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(rpw)))
+        self.row_off, self.edge_off, self.rows_per_wave = ro, eo, rpw.value
+        dev = self.graphs[0].device
+        self.rho = torch.empty(int(eo[-1]), dtype=torch.float32, device=dev)
+        self.keep = torch.empty(int(eo[-1]), dtype=torch.uint8, device=dev)
+        self.n_kept = torch.empty(self.G, dtype=torch.int64, device=dev)
+        self.minmax = torch.empty((self.G, 2 * R), dtype=torch.float64, device=dev)
+
+    def run(self, captured: bool = True) -> None:
+        fn = lib.ad_batch_run if captured else lib.ad_batch_run_uncaptured
+        _check(fn(self._h, _stream()))
+
+    def fetch(self):
+        """Copy the last run's outputs into this object's tensors; returns
+        (rho, keep, n_kept, minmax) for the packed edge ranges edge_off."""
+        _check(lib.ad_batch_copy_results(self._h, _ptr(self.rho), _ptr(self.keep), _ptr(self.n_kept),
+                                         _ptr(self.minmax), _stream()))
+        return self.rho, self.keep, self.n_kept, self.minmax
+
+    def close(self) -> None:
+        if self._h:
+            lib.ad_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------ whole path ---

@@ -261,7 +261,7 @@ static size_t bwd_layout(const ad_graph *g, const ad_relax_opts *o, void *ws, si
     l.inv_s = c.take<float>(n);
     l.sdeg = c.take<float>(n);
     l.ones = c.take<float>(n);
-    sweep_plan_carve(c, n, l.plan);
+    sweep_plan_carve(c, n, ceil_div(n, PLAN_TILE), l.plan);
     l.xbh = c.take<float>(nR);
     l.lam = c.take<float>(nR);
     l.lam2 = c.take<float>(nR);
@@ -357,7 +357,7 @@ extern "C" ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o
 
     SweepPlan plan = L.plan;
     plan.sh = sweep_shape(R, sizeof(float), o->rows_per_wave, o->hub_degree);
-    s = sweep_plan_build(g, plan, true, stream);
+    s = sweep_plan_build(g, plan, true, Segs(), stream);
     if (s != AD_OK) return s;
     s = weighted_degree_f32(g, L.inv_s, L.sdeg, plan, stream);
     if (s != AD_OK) return s;

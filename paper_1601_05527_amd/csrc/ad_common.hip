@@ -176,8 +176,13 @@ static std::atomic<bool> g_trace_on{false};
 static std::mutex g_trace_mu;
 static std::vector<TraceRecord> g_trace;
 
+static thread_local int g_trace_suppress = 0;
+
+TraceSuppress::TraceSuppress() { ++g_trace_suppress; }
+TraceSuppress::~TraceSuppress() { --g_trace_suppress; }
+
 TraceScope::TraceScope(const char *n, hipStream_t s) : name(n), stream(s) {
-    if (!g_trace_on.load(std::memory_order_relaxed)) return;
+    if (!g_trace_on.load(std::memory_order_relaxed) || g_trace_suppress) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
         a = b = nullptr;
         return;

@@ -196,6 +196,55 @@ struct TraceScope {
     TraceScope(const char *name, hipStream_t s);
     ~TraceScope();
 };
+// While one exists on this thread, TraceScope records nothing (used around
+// stream capture and internal timing).
+struct TraceSuppress {
+    TraceSuppress();
+    ~TraceSuppress();
+};
+
+// Graph segments: several independent graphs packed as one block-diagonal
+// CSR (rows of graph g are [row_off[g], row_off[g+1])).  Per-graph work is
+// laid out in chunks of CENTRE_ROWS rows and tiles of PLAN_TILE rows that
+// start at each graph's first row, so every graph is processed exactly as
+// it would be alone.  G = 1 with null arrays is a single graph.
+struct Segs {
+    int32_t G = 1;
+    const int64_t *row_off = nullptr;    // [G+1]
+    const int64_t *chunk_off = nullptr;  // [G+1] cumulative CENTRE_ROWS chunks
+    const int64_t *tile_off = nullptr;   // [G+1] cumulative PLAN_TILE tiles
+    const int32_t *row_graph = nullptr;  // [n] graph of each row
+    int64_t nchunks = 0;                 // host copies of chunk_off[G], tile_off[G]
+    int64_t ntiles = 0;
+};
+
+constexpr int CENTRE_ROWS = 1024;   // rows per centring / min-max chunk
+constexpr int PLAN_TILE = 64;       // rows per launch-plan tile
+
+// Largest g in [0, G) with off[g] <= x (empty segments are skipped over).
+__device__ __forceinline__ int seg_find(const int64_t *__restrict__ off, int G, int64_t x) {
+    int lo = 0, hi = G - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Rows [r0, r1) and graph of chunk / tile `b` of size `size`.
+__device__ __forceinline__ void seg_span(const Segs &sg, const int64_t *__restrict__ off, int64_t n, int64_t b,
+                                         int64_t size, int &g, int64_t &r0, int64_t &r1) {
+    if (off) {
+        g = seg_find(off, sg.G, b);
+        r0 = sg.row_off[g] + (b - off[g]) * size;
+        r1 = min(sg.row_off[g + 1], r0 + size);
+    } else {
+        g = 0;
+        r0 = b * size;
+        r1 = min(n, r0 + size);
+    }
+}
 
 // Launch shape and plan of a JOR sweep (see ad_relax.hip).
 struct SweepShape {
@@ -209,15 +258,34 @@ struct SweepPlan {
     SweepShape sh;
     int32_t *hub_list;
     unsigned int *hub_count;
-    long long *plan;            // (first row << 8) | log2(rows per wave), one per wave
+    long long *plan;            // (first row << 16) | (rows << 8) | log2(rows per wave), per wave
     unsigned int *plan_count;
     int *tile_lg;
     unsigned int *tile_waves;
 };
-size_t sweep_plan_bytes(int64_t n);
-void sweep_plan_carve(Carver &c, int64_t n, SweepPlan &p);
+// ntiles_cap: tiles of the layout (ceil(n / PLAN_TILE) for one graph).
+size_t sweep_plan_bytes(int64_t n, int64_t ntiles_cap);
+void sweep_plan_carve(Carver &c, int64_t n, int64_t ntiles_cap, SweepPlan &p);
 // Builds the hub list (if build_hubs) and the per-tile plan on the stream.
-ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, hipStream_t st);
+ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, const Segs &sg, hipStream_t st);
+
+// The whole relaxation of ad_relax over packed graph segments: minmax_out
+// [G][2R], shift_out [G][R]; graph g's start vectors use key word
+// o->graph_id + g.
+size_t relax_segs_workspace(const ad_graph *g, const ad_relax_opts *o, const Segs &sg);
+ad_status relax_segs(const ad_graph *g, const ad_relax_opts *o, const void *x0, void *x_out, double *minmax_out,
+                     double *shift_out, void *ckpt, void *ws, size_t ws_bytes, const Segs &sg, hipStream_t st);
+
+// ad_edge_dist over packed graph segments (minmax [G][2R]).
+size_t edge_dist_segs_workspace(const ad_graph *g, const Segs &sg);
+ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x, const double *minmax,
+                         void *rho, void *ws, size_t ws_bytes, const Segs &sg, hipStream_t stream);
+
+// Algorithm 3 at fixed per-degree budgets, keep[] only (rows are independent,
+// so packed graphs need no segment information).
+size_t sparsify_workspace(const ad_graph *g);
+ad_status sparsify_fixed(const ad_graph *g, ad_dtype rho_dtype, const void *rho, ad_orient orient,
+                         const int32_t *budget, uint8_t *keep, void *ws, size_t ws_bytes, hipStream_t stream);
 
 // xout = (1 - omega) xin + omega * diag(inv_s) W xin, FP32.
 ad_status sweep_f32(const ad_graph *g, const float *inv_s, float omega, const float *xin, float *xout, int R,

@@ -27,8 +27,7 @@
 namespace ad {
 
 constexpr int BLOCK = 256;
-constexpr int CENTRE_ROWS = 1024;
-constexpr int SWEEP_UNROLL = 8;     // row gathers in flight per lane   // rows per partial-sum block (fixed: keeps sums reproducible)
+constexpr int SWEEP_UNROLL = 8;     // row gathers in flight per lane
 
 // s_i = sum_j w_ij in FP64 (LPR lanes per row, strided partial sums combined
 // by a fixed shuffle tree); inv_s = 1/s_i (0 for isolated vertices).
@@ -104,7 +103,8 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_centre_partials(int64_t n, int R, const float *__restrict__ sdeg,
                                                           const int32_t *__restrict__ orig_id, uint64_t seed,
                                                           uint64_t gid, const T *__restrict__ x0,
-                                                          double *__restrict__ part, double *__restrict__ part_s) {
+                                                          double *__restrict__ part, double *__restrict__ part_s,
+                                                          Segs sg) {
     __shared__ double acc_l[4][BLOCK];
     __shared__ double s_l[BLOCK];
     const int t = threadIdx.x;
@@ -114,8 +114,10 @@ __global__ __launch_bounds__(BLOCK) void k_centre_partials(int64_t n, int R, con
     const int row_off = t / nq;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     double sacc = 0.0;
-    const int64_t r0 = (int64_t)blockIdx.x * CENTRE_ROWS;
-    const int64_t r1 = min(n, r0 + CENTRE_ROWS);
+    int g;
+    int64_t r0, r1;
+    seg_span(sg, sg.chunk_off, n, blockIdx.x, CENTRE_ROWS, g, r0, r1);
+    const uint64_t gkey = gid + (uint64_t)g;
     if (row_off < stride) {
         for (int64_t i = r0 + row_off; i < r1; i += stride) {
             const double s = (double)sdeg[i];
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(BLOCK) void k_centre_partials(int64_t n, int R, con
             } else {
                 uint64_t words[4];
                 const int32_t key = orig_id ? orig_id[i] : (int32_t)i;
-                philox4x64_10((uint64_t)(uint32_t)key, (uint64_t)q, 0, 0, seed, gid, words);
+                philox4x64_10((uint64_t)(uint32_t)key, (uint64_t)q, 0, 0, seed, gkey, words);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) acc[c] += s * start_from_word(words[c]);
             }
@@ -151,17 +153,21 @@ __global__ __launch_bounds__(BLOCK) void k_centre_partials(int64_t n, int R, con
 }
 
 // shift_r = weighted mean rounded to the 2^-24 grid; resets the min/max codes.
-// One block: thread t sums partial blocks t, t+BLOCK, ... in order, then
-// thread 0 adds the BLOCK subtotals in order (a fixed summation tree).
+// One block per graph: thread t sums the graph's partial blocks t, t+BLOCK,
+// ... in order, then thread 0 adds the BLOCK subtotals in order (a fixed
+// summation tree).
 __global__ __launch_bounds__(BLOCK) void k_centre_finalize(int R, int64_t nblocks, const double *__restrict__ part,
                                                           const double *__restrict__ part_s, int centre,
                                                           double *__restrict__ shift,
-                                                          unsigned long long *__restrict__ mm) {
+                                                          unsigned long long *__restrict__ mm, Segs sg) {
     __shared__ double sub[BLOCK];
     __shared__ double S;
     const int t = threadIdx.x;
+    const int g = blockIdx.x;
+    const int64_t c0 = sg.chunk_off ? sg.chunk_off[g] : 0;
+    const int64_t c1 = sg.chunk_off ? sg.chunk_off[g + 1] : nblocks;
     double a = 0.0;
-    for (int64_t b = t; b < nblocks; b += BLOCK) a += part_s[b];
+    for (int64_t b = c0 + t; b < c1; b += BLOCK) a += part_s[b];
     sub[t] = a;
     __syncthreads();
     if (t == 0) {
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(BLOCK) void k_centre_finalize(int R, int64_t nblock
     __syncthreads();
     for (int r = 0; r < R; ++r) {
         a = 0.0;
-        for (int64_t b = t; b < nblocks; b += BLOCK) a += part[b * R + r];
+        for (int64_t b = c0 + t; b < c1; b += BLOCK) a += part[b * R + r];
         sub[t] = a;
         __syncthreads();
         if (t == 0) {
@@ -180,9 +186,9 @@ __global__ __launch_bounds__(BLOCK) void k_centre_finalize(int R, int64_t nblock
             for (int q = 0; q < BLOCK; ++q) tot += sub[q];
             double sh = 0.0;
             if (centre && S > 0.0) sh = rint((tot / S) * 16777216.0) * (1.0 / 16777216.0);
-            shift[r] = sh;
-            mm[r] = ~0ull;       // running min code
-            mm[R + r] = 0ull;    // running max code
+            shift[(int64_t)g * R + r] = sh;
+            mm[(int64_t)g * 2 * R + r] = ~0ull;       // running min code
+            mm[(int64_t)g * 2 * R + R + r] = 0ull;    // running max code
         }
         __syncthreads();
     }
@@ -192,23 +198,24 @@ __global__ __launch_bounds__(BLOCK) void k_centre_finalize(int R, int64_t nblock
 template <typename T>
 __global__ void k_init(int64_t n, int R, const int32_t *__restrict__ orig_id, uint64_t seed,
                        uint64_t gid, const T *__restrict__ x0, const double *__restrict__ shift,
-                       T *__restrict__ x) {
+                       T *__restrict__ x, const int32_t *__restrict__ row_graph) {
     const int nq = (R + 3) >> 2;
     const int64_t total = n * nq;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         int64_t i = idx / nq;
         int q = (int)(idx - i * nq);
+        const int g = row_graph ? row_graph[i] : 0;
         uint64_t words[4];
         if (!x0) {
             int32_t key = orig_id ? orig_id[i] : (int32_t)i;
-            philox4x64_10((uint64_t)(uint32_t)key, (uint64_t)q, 0, 0, seed, gid, words);
+            philox4x64_10((uint64_t)(uint32_t)key, (uint64_t)q, 0, 0, seed, gid + (uint64_t)g, words);
         }
         for (int c = 0; c < 4; ++c) {
             int r = 4 * q + c;
             if (r >= R) break;
             double v = x0 ? (double)x0[i * R + r] : start_from_word(words[c]);
-            x[i * R + r] = (T)(v - shift[r]);
+            x[i * R + r] = (T)(v - shift[(int64_t)g * R + r]);
         }
     }
 }
@@ -310,13 +317,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
         }
         return;
     }
-    // Other rows: each wave walks plan entries (first row, log2 rows per
+    // Other rows: each wave walks plan entries (first row, rows in the tile, log2 rows per
     // wave); SPRW / rpw slots of C lanes per row.
     const unsigned int np = *plan_count;
     const unsigned int nwaves = (gridDim.x - hub_blocks) * (BLOCK / WAVE);
     for (unsigned int pi = (blockIdx.x - hub_blocks) * (BLOCK / WAVE) + wave; pi < np; pi += nwaves) {
         const long long e = plan[pi];
-        const int64_t row0 = e >> 8;
+        const int64_t row0 = e >> 16;
+        const int nrows = (int)((e >> 8) & 0xff);      // rows of this entry inside its tile
         const int RPW = 1 << (int)(e & 0xff);
         const int SPR = SPRW / RPW;
         const int group = C * SPR;
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
         const int slot = sub / C;
         const int chunk = sub - slot * C;
         const int64_t row = row0 + rw;
-        const bool active = (rw < RPW) && (row < n);
+        const bool active = rw < nrows;
         int64_t beg = 0, end = 0;
         if (active) {
             beg = row_ptr[row];
@@ -367,15 +375,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
 // rows per wave follow its longest non-hub row, so that one round of
 // SWEEP_UNROLL gathers per slot covers it (short rows share a wave, long
 // rows get more slots).  A fixed rows-per-wave request overrides this.
-constexpr int PLAN_TILE = 64;
-
 __global__ void k_plan_tiles(int64_t n, const int64_t *__restrict__ row_ptr, int64_t hub_d, int spr_max,
-                             int rpw_fixed, int *__restrict__ tile_lg, unsigned int *__restrict__ tile_waves) {
-    const int64_t ntiles = ceil_div_dev(n, PLAN_TILE);
+                             int rpw_fixed, int *__restrict__ tile_lg, unsigned int *__restrict__ tile_waves,
+                             Segs sg, int64_t ntiles) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r0 = t * PLAN_TILE;
-        const int64_t r1 = min(n, r0 + PLAN_TILE);
+        int g;
+        int64_t r0, r1;
+        seg_span(sg, sg.tile_off, n, t, PLAN_TILE, g, r0, r1);
         int lg;
         if (rpw_fixed > 0) {
             lg = 31 - __clz(rpw_fixed);
@@ -426,32 +433,39 @@ __global__ __launch_bounds__(BLOCK) void k_plan_scan(int64_t ntiles, unsigned in
 }
 
 __global__ void k_plan_fill(int64_t n, const int *__restrict__ tile_lg, const unsigned int *__restrict__ tile_off,
-                            long long *__restrict__ plan) {
-    const int64_t ntiles = ceil_div_dev(n, PLAN_TILE);
+                            long long *__restrict__ plan, Segs sg, int64_t ntiles) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r0 = t * PLAN_TILE;
-        const int64_t r1 = min(n, r0 + PLAN_TILE);
+        int g;
+        int64_t r0, r1;
+        seg_span(sg, sg.tile_off, n, t, PLAN_TILE, g, r0, r1);
         const int lg = tile_lg[t];
         unsigned int o = tile_off[t];
-        for (int64_t r = r0; r < r1; r += (int64_t)1 << lg) plan[o++] = ((long long)r << 8) | lg;
+        for (int64_t r = r0; r < r1; r += (int64_t)1 << lg) {
+            const int64_t nr = min((int64_t)1 << lg, r1 - r);
+            plan[o++] = ((long long)r << 16) | ((long long)nr << 8) | lg;
+        }
     }
 }
 
-// Per-vector min and max of x over non-isolated rows (ordered-integer atomics).
+// Per-vector min and max of x over non-isolated rows (ordered-integer
+// atomics); one block per chunk of CENTRE_ROWS rows of one graph.
 template <typename T>
-__global__ void k_minmax(int64_t n, int R, const int64_t *__restrict__ row_ptr,
-                         const T *__restrict__ x, unsigned long long *__restrict__ mm) {
+__global__ __launch_bounds__(BLOCK) void k_minmax(int64_t n, int R, const int64_t *__restrict__ row_ptr,
+                                                 const T *__restrict__ x, unsigned long long *__restrict__ mm,
+                                                 Segs sg) {
     __shared__ double lo_l[BLOCK];
     __shared__ double hi_l[BLOCK];
     const int t = threadIdx.x;
     const int stride = BLOCK / R;
     const int r = t % R;
     const int row_off = t / R;
+    int g;
+    int64_t r0, r1;
+    seg_span(sg, sg.chunk_off, n, blockIdx.x, CENTRE_ROWS, g, r0, r1);
     double lo = INFINITY, hi = -INFINITY;
     if (row_off < stride) {
-        for (int64_t i = (int64_t)blockIdx.x * stride + row_off; i < n;
-             i += (int64_t)gridDim.x * stride) {
+        for (int64_t i = r0 + row_off; i < r1; i += stride) {
             if (row_ptr[i + 1] == row_ptr[i]) continue;
             double v = (double)x[i * R + r];
             lo = fmin(lo, v);
@@ -468,22 +482,24 @@ __global__ void k_minmax(int64_t n, int R, const int64_t *__restrict__ row_ptr,
             b = fmax(b, hi_l[q]);
         }
         if (a <= b) {
-            atomicMin(&mm[t], ord_encode(a));
-            atomicMax(&mm[R + t], ord_encode(b));
+            atomicMin(&mm[(int64_t)g * 2 * R + t], ord_encode(a));
+            atomicMax(&mm[(int64_t)g * 2 * R + R + t], ord_encode(b));
         }
     }
 }
 
-__global__ void k_minmax_out(int R, const unsigned long long *__restrict__ mm,
+__global__ void k_minmax_out(int G, int R, const unsigned long long *__restrict__ mm,
                              const double *__restrict__ shift, double *__restrict__ out,
                              double *__restrict__ shift_out) {
-    const int r = threadIdx.x;
-    if (r >= R) return;
-    unsigned long long a = mm[r], b = mm[R + r];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)G * R) return;
+    const int64_t g = idx / R;
+    const int r = (int)(idx - g * R);
+    unsigned long long a = mm[g * 2 * R + r], b = mm[g * 2 * R + R + r];
     bool none = (a == ~0ull);
-    out[r] = none ? INFINITY : ord_decode(a);
-    out[R + r] = none ? -INFINITY : ord_decode(b);
-    if (shift_out) shift_out[r] = shift[r];
+    out[g * 2 * R + r] = none ? INFINITY : ord_decode(a);
+    out[g * 2 * R + R + r] = none ? -INFINITY : ord_decode(b);
+    if (shift_out) shift_out[idx] = shift[idx];
 }
 
 // ------------------------------------------------------------------- host --
@@ -513,16 +529,16 @@ SweepShape sweep_shape(int R, size_t in_bytes, int rpw_req, int64_t hub_req) {
     return s;
 }
 
-size_t sweep_plan_bytes(int64_t n) {
+size_t sweep_plan_bytes(int64_t n, int64_t ntiles_cap) {
     Carver c(nullptr, 0);
     SweepPlan p;
-    sweep_plan_carve(c, n, p);
+    sweep_plan_carve(c, n, ntiles_cap, p);
     return c.used;
 }
 
-void sweep_plan_carve(Carver &c, int64_t n, SweepPlan &p) {
+void sweep_plan_carve(Carver &c, int64_t n, int64_t ntiles_cap, SweepPlan &p) {
     const int64_t nn = std::max<int64_t>(1, n);
-    const int64_t ntiles = std::max<int64_t>(1, ceil_div(n, PLAN_TILE));
+    const int64_t ntiles = std::max<int64_t>(1, ntiles_cap);
     p.hub_list = c.take<int32_t>(nn);
     p.hub_count = c.take<unsigned int>(1);
     p.plan = c.take<long long>(nn + ntiles);
@@ -531,7 +547,7 @@ void sweep_plan_carve(Carver &c, int64_t n, SweepPlan &p) {
     p.tile_waves = c.take<unsigned int>(ntiles);
 }
 
-ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, hipStream_t st) {
+ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, const Segs &sg, hipStream_t st) {
     ad_status s;
     if (build_hubs) {
         s = fill_i32((int32_t *)p.hub_count, 0, 1, st);
@@ -539,15 +555,15 @@ ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, hip
         s = collect_rows(g, p.sh.hub_d, (int64_t)1 << 62, p.hub_list, p.hub_count, st);
         if (s != AD_OK) return s;
     }
-    const int64_t ntiles = ceil_div(g->n, PLAN_TILE);
+    const int64_t ntiles = sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE);
     if (ntiles <= 0) return fill_i32((int32_t *)p.plan_count, 0, 1, st);
     hipLaunchKernelGGL(k_plan_tiles, dim3(grid_for(ntiles, BLOCK)), dim3(BLOCK), 0, st, g->n, g->row_ptr,
-                       p.sh.hub_d, p.sh.SPRW, p.sh.rpw_fixed, p.tile_lg, p.tile_waves);
+                       p.sh.hub_d, p.sh.SPRW, p.sh.rpw_fixed, p.tile_lg, p.tile_waves, sg, ntiles);
     AD_LAUNCH_CHECK("k_plan_tiles");
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(BLOCK), 0, st, ntiles, p.tile_waves, p.plan_count);
     AD_LAUNCH_CHECK("k_plan_scan");
     hipLaunchKernelGGL(k_plan_fill, dim3(grid_for(ntiles, BLOCK)), dim3(BLOCK), 0, st, g->n, p.tile_lg,
-                       p.tile_waves, p.plan);
+                       p.tile_waves, p.plan, sg, ntiles);
     AD_LAUNCH_CHECK("k_plan_fill");
     return AD_OK;
 }
@@ -597,22 +613,30 @@ struct RelaxLayout {
     void *b16A, *b16B;
 };
 
+static int64_t seg_chunks(const ad_graph *g, const Segs &sg) {
+    return sg.chunk_off ? sg.nchunks : ceil_div(g->n, CENTRE_ROWS);
+}
+static int64_t seg_tiles(const ad_graph *g, const Segs &sg) {
+    return sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE);
+}
+
 static size_t relax_layout(const ad_graph *g, const ad_relax_opts *o, void *ws, size_t ws_bytes,
-                           RelaxLayout *L) {
+                           RelaxLayout *L, const Segs &sg) {
     Carver c(ws, ws_bytes);
     const int64_t n = g->n > 0 ? g->n : 1;
     const int R = o->R;
-    const int64_t nb = std::max<int64_t>(1, ceil_div(g->n, CENTRE_ROWS));
+    const int64_t nb = std::max<int64_t>(1, seg_chunks(g, sg));
+    const int64_t nt = seg_tiles(g, sg);
     const bool f64 = o->store == AD_F64;
     RelaxLayout l;
     l.inv_s = f64 ? (void *)c.take<double>(n) : (void *)c.take<float>(n);
     l.sdeg = c.take<float>(n);
     l.part = c.take<double>(nb * R);
     l.part_s = c.take<double>(nb);
-    l.shift = c.take<double>(R);
-    l.mm = c.take<unsigned long long>(2 * R);
-    sweep_plan_carve(c, n, l.p32);
-    if (o->store == AD_BF16) sweep_plan_carve(c, n, l.p16);
+    l.shift = c.take<double>((size_t)sg.G * R);
+    l.mm = c.take<unsigned long long>((size_t)sg.G * 2 * R);
+    sweep_plan_carve(c, n, nt, l.p32);
+    if (o->store == AD_BF16) sweep_plan_carve(c, n, nt, l.p16);
     const size_t xb = f64 ? 8 : 4;
     l.bufA = c.take<char>((size_t)n * R * xb);
     l.bufB = c.take<char>((size_t)n * R * xb);
@@ -665,26 +689,25 @@ static ad_status weighted_degree_impl(const ad_graph *g, A *inv_s, float *sdeg, 
 template <typename T>
 static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const void *x0, void *x_out,
                             double *minmax_out, double *shift_out, void *ckpt, const RelaxLayout &L,
-                            hipStream_t st) {
+                            const Segs &sg, hipStream_t st) {
     typedef typename acc_of<T>::type A;
     const int R = o->R;
     const int64_t n = g->n;
-    const int64_t nb = std::max<int64_t>(1, ceil_div(n, CENTRE_ROWS));
-    const double avg = n > 0 ? (double)(2 * g->m) / (double)n : 0.0;
+    const int64_t nb = seg_chunks(g, sg);
     ad_status s;
 
     // launch plans first: the hub list also serves the weighted degrees
     RelaxLayout P = L;
     P.p32.sh = sweep_shape(R, sizeof(T), o->rows_per_wave, o->hub_degree);
     if (n > 0) {
-        s = sweep_plan_build(g, P.p32, true, st);
+        s = sweep_plan_build(g, P.p32, true, sg, st);
         if (s != AD_OK) return s;
         if (o->store == AD_BF16 && o->k > 0) {
             P.p16.sh = sweep_shape(R, 2, o->rows_per_wave, o->hub_degree);
             P.p16.sh.hub_d = P.p32.sh.hub_d;            // one hub list serves both
             P.p16.hub_list = P.p32.hub_list;
             P.p16.hub_count = P.p32.hub_count;
-            s = sweep_plan_build(g, P.p16, false, st);
+            s = sweep_plan_build(g, P.p16, false, sg, st);
             if (s != AD_OK) return s;
         }
     }
@@ -692,12 +715,14 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
     if (n > 0) {
         s = weighted_degree_impl<A>(g, (A *)L.inv_s, L.sdeg, P.p32, st);
         if (s != AD_OK) return s;
-        hipLaunchKernelGGL((k_centre_partials<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, L.sdeg,
-                           g->orig_id, o->seed, o->graph_id, (const T *)x0, L.part, L.part_s);
-        AD_LAUNCH_CHECK("k_centre_partials");
+        if (nb > 0) {
+            hipLaunchKernelGGL((k_centre_partials<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, L.sdeg,
+                               g->orig_id, o->seed, o->graph_id, (const T *)x0, L.part, L.part_s, sg);
+            AD_LAUNCH_CHECK("k_centre_partials");
+        }
     }
-    hipLaunchKernelGGL(k_centre_finalize, dim3(1), dim3(BLOCK), 0, st, R, n > 0 ? nb : (int64_t)0, L.part,
-                       L.part_s, 1, L.shift, L.mm);
+    hipLaunchKernelGGL(k_centre_finalize, dim3((unsigned)sg.G), dim3(BLOCK), 0, st, R, n > 0 ? nb : (int64_t)0,
+                       L.part, L.part_s, 1, L.shift, L.mm, sg);
     AD_LAUNCH_CHECK("k_centre_finalize");
 
     const int nck = ad_relax_num_checkpoints(o);
@@ -706,7 +731,7 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
     if (n > 0) {
         int64_t total = n * ((R + 3) / 4);
         hipLaunchKernelGGL((k_init<T>), dim3(grid_for(total, BLOCK)), dim3(BLOCK), 0, st, n, R,
-                           g->orig_id, o->seed, o->graph_id, (const T *)x0, L.shift, start);
+                           g->orig_id, o->seed, o->graph_id, (const T *)x0, L.shift, start, sg.row_graph);
         AD_LAUNCH_CHECK("k_init");
     }
 
@@ -747,16 +772,28 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
         }
     }
 
-    if (n > 0) {
-        int stride = BLOCK / R;
-        const int64_t mm_blocks = std::min<int64_t>(1024, ceil_div(n, stride));
-        hipLaunchKernelGGL((k_minmax<T>), dim3((unsigned)mm_blocks), dim3(BLOCK), 0, st, n,
-                           R, g->row_ptr, (const T *)x_out, L.mm);
+    if (n > 0 && nb > 0) {
+        hipLaunchKernelGGL((k_minmax<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, g->row_ptr,
+                           (const T *)x_out, L.mm, sg);
         AD_LAUNCH_CHECK("k_minmax");
     }
-    hipLaunchKernelGGL(k_minmax_out, dim3(1), dim3(64), 0, st, R, L.mm, L.shift, minmax_out, shift_out);
+    const int64_t gr = (int64_t)sg.G * R;
+    hipLaunchKernelGGL(k_minmax_out, dim3((unsigned)ceil_div(gr, BLOCK)), dim3(BLOCK), 0, st, sg.G, R, L.mm,
+                       L.shift, minmax_out, shift_out);
     AD_LAUNCH_CHECK("k_minmax_out");
     return AD_OK;
+}
+
+size_t relax_segs_workspace(const ad_graph *g, const ad_relax_opts *o, const Segs &sg) {
+    return relax_layout(g, o, nullptr, 0, nullptr, sg);
+}
+
+ad_status relax_segs(const ad_graph *g, const ad_relax_opts *o, const void *x0, void *x_out, double *minmax_out,
+                     double *shift_out, void *ckpt, void *ws, size_t ws_bytes, const Segs &sg, hipStream_t st) {
+    RelaxLayout L;
+    if (relax_layout(g, o, ws, ws_bytes, &L, sg) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    if (o->store == AD_F64) return relax_impl<double>(g, o, x0, x_out, minmax_out, shift_out, ckpt, L, sg, st);
+    return relax_impl<float>(g, o, x0, x_out, minmax_out, shift_out, ckpt, L, sg, st);
 }
 
 ad_status sweep_f32(const ad_graph *g, const float *inv_s, float omega, const float *xin, float *xout, int R,
@@ -779,7 +816,7 @@ extern "C" int32_t ad_relax_num_checkpoints(const ad_relax_opts *o) {
 
 extern "C" size_t ad_relax_workspace_size(const ad_graph *g, const ad_relax_opts *o) {
     if (check_graph_args(g) != AD_OK || check_relax_opts(o) != AD_OK) return 0;
-    return relax_layout(g, o, nullptr, 0, nullptr);
+    return relax_layout(g, o, nullptr, 0, nullptr, Segs());
 }
 
 extern "C" ad_status ad_relax(const ad_graph *g, const ad_relax_opts *o, const void *x0, void *x_out,
@@ -795,9 +832,5 @@ extern "C" ad_status ad_relax(const ad_graph *g, const ad_relax_opts *o, const v
     if (ckpt && ckpt == x_out) return fail(AD_ERR_INVALID_ARG, "x_out aliases ckpt");
     if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
-    RelaxLayout L;
-    if (relax_layout(g, o, ws, ws_bytes, &L) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
-    if (o->store == AD_F64)
-        return relax_impl<double>(g, o, x0, x_out, minmax_out, shift_out, ckpt, L, stream);
-    return relax_impl<float>(g, o, x0, x_out, minmax_out, shift_out, ckpt, L, stream);
+    return relax_segs(g, o, x0, x_out, minmax_out, shift_out, ckpt, ws, ws_bytes, Segs(), stream);
 }

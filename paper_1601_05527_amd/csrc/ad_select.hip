@@ -55,7 +55,7 @@ __device__ __forceinline__ A group_sum(A v, int C, int base) {
 }
 
 // rho for the upper entries (j > i) of every row.  Persistent waves walk a
-// launch plan (first row, log2 rows per wave) as the sweep does; per row
+// launch plan (first row, rows in the tile, log2 rows per wave) as the sweep does; per row
 // SPRW / rpw slots of C lanes, VEC values per lane, U entries per slot in
 // flight.  Lane chunk c sums ((x_i - x_j) * inv)^2 over its VEC values in
 // order; group_sum adds the chunks.
@@ -64,20 +64,15 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
     int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const Tx *__restrict__ x, const double *__restrict__ minmax,
     Tr *__restrict__ rho, int R, int C, int SPRW, const long long *__restrict__ plan,
-    const unsigned int *__restrict__ plan_count) {
+    const unsigned int *__restrict__ plan_count, const int32_t *__restrict__ row_graph) {
     typedef typename acc_of<Tx>::type A;
-    __shared__ A inv_l[64];
-    if (threadIdx.x < R) {
-        double lo = minmax[threadIdx.x], hi = minmax[R + threadIdx.x];
-        inv_l[threadIdx.x] = (hi > lo) ? (A)(1.0 / (hi - lo)) : (A)0;
-    }
-    __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned int np = *plan_count;
     const unsigned int nwaves = gridDim.x * (SBLOCK / WAVE);
     for (unsigned int pi = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); pi < np; pi += nwaves) {
         const long long pe = plan[pi];
-        const int64_t row0 = pe >> 8;
+        const int64_t row0 = pe >> 16;
+        const int nrows = (int)((pe >> 8) & 0xff);     // rows of this entry inside its tile
         const int RPW = 1 << (int)(pe & 0xff);
         const int SPR = SPRW / RPW;
         const int group = C * SPR;
@@ -87,7 +82,7 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
         const int chunk = sub - slot * C;
         const int base = lane - chunk;
         const int64_t row = row0 + rw;
-        const bool active = rw < RPW && row < n;
+        const bool active = rw < nrows;
         int64_t beg = 0, end = 0;
         if (active) {
             beg = row_ptr[row];
@@ -101,8 +96,13 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
 #pragma unroll
             for (int q = 0; q < VEC; ++q) xi[q] = (A)0;
         }
+        // 1 / (max - min) of this lane's vectors, for the graph of the entry's rows
+        const int64_t gb = (int64_t)(row_graph ? row_graph[row0] : 0) * 2 * R;
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) iv[q] = inv_l[off + q];
+        for (int q = 0; q < VEC; ++q) {
+            const double lo = minmax[gb + off + q], hi = minmax[gb + R + off + q];
+            iv[q] = (hi > lo) ? (A)(1.0 / (hi - lo)) : (A)0;
+        }
         // uniform trip count across the wave: the longest row of the wave
         int64_t len = end - beg;
         for (int d = WAVE / 2; d >= 1; d >>= 1) len = max(len, shfl_down(len, d));
@@ -771,6 +771,8 @@ static ad_status check_sel_args(const ad_graph *g, ad_dtype rho_dtype, const voi
 
 using namespace ad;
 
+namespace ad {
+
 static SweepShape dist_shape(int R, ad_dtype x_dtype) {
     // the sweep's lane layout for this vector width; every row in the plan
     // (no hub rows: a long row keeps one wave to itself)
@@ -779,9 +781,61 @@ static SweepShape dist_shape(int R, ad_dtype x_dtype) {
     return sh;
 }
 
+size_t edge_dist_segs_workspace(const ad_graph *g, const Segs &sg) {
+    return sweep_plan_bytes(g->n, sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE));
+}
+
+ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x, const double *minmax,
+                         void *rho, void *ws, size_t ws_bytes, const Segs &sg, hipStream_t stream) {
+    Carver c(ws, ws_bytes);
+    SweepPlan pl;
+    sweep_plan_carve(c, g->n, sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE), pl);
+    if (!c.ok()) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    if (g->n <= 0 || g->m <= 0) return AD_OK;
+    pl.sh = dist_shape(R, x_dtype);
+    ad_status s = sweep_plan_build(g, pl, false, sg, stream);
+    if (s != AD_OK) return s;
+    const unsigned nb = (unsigned)std::min<int64_t>(4096, ceil_div(g->n, SBLOCK / WAVE));
+    TraceScope trace("k_edge_dist", stream);
+#define AD_DIST(TX, TR, V)                                                                                   \
+    hipLaunchKernelGGL((k_edge_dist<TX, TR, V, DIST_UNROLL>), dim3(nb), dim3(SBLOCK), 0, stream, g->n,      \
+                       g->row_ptr, g->col, g->eid, (const TX *)x, minmax, (TR *)rho, R, pl.sh.C, pl.sh.SPRW,  \
+                       pl.plan, pl.plan_count, sg.row_graph)
+    if (x_dtype == AD_F64) {
+        if (pl.sh.vec == 2) AD_DIST(double, double, 2);
+        else AD_DIST(double, double, 1);
+    } else {
+        if (pl.sh.vec == 4) AD_DIST(float, float, 4);
+        else if (pl.sh.vec == 2) AD_DIST(float, float, 2);
+        else AD_DIST(float, float, 1);
+    }
+#undef AD_DIST
+    AD_LAUNCH_CHECK("k_edge_dist");
+    return AD_OK;
+}
+
+// Algorithm 3 at fixed budgets: keep[] (zeroed first) for every edge of the
+// (possibly packed) graph; no count.
+ad_status sparsify_fixed(const ad_graph *g, ad_dtype rho_dtype, const void *rho, ad_orient orient,
+                         const int32_t *budget, uint8_t *keep, void *ws, size_t ws_bytes, hipStream_t stream) {
+    SelLayout L;
+    if (sel_layout(g, ws, ws_bytes, &L) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    if (g->m <= 0) return AD_OK;
+    ad_status s = fill_u8(keep, 0, g->m, stream);
+    if (s != AD_OK) return s;
+    if (rho_dtype == AD_F32) return rank_all<float>(g, (const float *)rho, orient, MODE_FIXED, budget, keep, L, stream);
+    return rank_all<double>(g, (const double *)rho, orient, MODE_FIXED, budget, keep, L, stream);
+}
+
+size_t sparsify_workspace(const ad_graph *g) { return sel_layout(g, nullptr, 0, nullptr); }
+
+}  // namespace ad
+
+using namespace ad;
+
 extern "C" size_t ad_edge_dist_workspace_size(const ad_graph *g) {
     if (check_graph_args(g) != AD_OK) return 0;
-    return sweep_plan_bytes(g->n);
+    return edge_dist_segs_workspace(g, Segs());
 }
 
 extern "C" ad_status ad_edge_dist(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
@@ -794,31 +848,7 @@ extern "C" ad_status ad_edge_dist(const ad_graph *g, int32_t R, ad_dtype x_dtype
     if (g->m > 0 && (!x || !minmax || !rho)) return fail(AD_ERR_INVALID_ARG, "x, minmax or rho is NULL");
     if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
-    Carver c(ws, ws_bytes);
-    SweepPlan pl;
-    sweep_plan_carve(c, g->n, pl);
-    if (!c.ok()) return fail(AD_ERR_WORKSPACE, "workspace too small");
-    if (g->n <= 0 || g->m <= 0) return AD_OK;
-    pl.sh = dist_shape(R, x_dtype);
-    s = sweep_plan_build(g, pl, false, stream);
-    if (s != AD_OK) return s;
-    const unsigned nb = (unsigned)std::min<int64_t>(4096, ceil_div(g->n, SBLOCK / WAVE));
-    TraceScope trace("k_edge_dist", stream);
-#define AD_DIST(TX, TR, V)                                                                                   \
-    hipLaunchKernelGGL((k_edge_dist<TX, TR, V, DIST_UNROLL>), dim3(nb), dim3(SBLOCK), 0, stream, g->n,      \
-                       g->row_ptr, g->col, g->eid, (const TX *)x, minmax, (TR *)rho, R, pl.sh.C, pl.sh.SPRW,  \
-                       pl.plan, pl.plan_count)
-    if (x_dtype == AD_F64) {
-        if (pl.sh.vec == 2) AD_DIST(double, double, 2);
-        else AD_DIST(double, double, 1);
-    } else {
-        if (pl.sh.vec == 4) AD_DIST(float, float, 4);
-        else if (pl.sh.vec == 2) AD_DIST(float, float, 2);
-        else AD_DIST(float, float, 1);
-    }
-#undef AD_DIST
-    AD_LAUNCH_CHECK("k_edge_dist");
-    return AD_OK;
+    return edge_dist_segs(g, R, x_dtype, x, minmax, rho, ws, ws_bytes, Segs(), stream);
 }
 
 extern "C" ad_status ad_budget_table(int32_t d_max, double e, int32_t *budget_host) {
