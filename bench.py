@@ -1,9 +1,9 @@
 #!/usr/bin/env python
 """Benchmark of the algebraic-distance sparsification hot path on one MI355X.
 
-Workload (one step): a Chung-Lu power-law graph, n = 2^20 vertices, exactly
-16,000,000 undirected edges, degree exponent 2.1, lognormal(0, 1) weights
-(seeded, synthetic; it stands in for the paper's real networks), with
+Default workload (one step): a Chung-Lu power-law graph, n = 2^20 vertices,
+exactly 16,000,000 undirected edges, degree exponent 2.1, lognormal(0, 1)
+weights (seeded, synthetic; it stands in for the paper's real networks), with
   start vectors (Philox) -> 20 JOR sweeps of R = 16 vectors (omega = 1/2,
   FP32) -> rescale -> per-edge L2 algebraic distance ->
   LOCAL and GLOBAL selection, each with e fitted to 30% retention.
@@ -13,6 +13,13 @@ results are keyed by the original ids and do not depend on it).
 
 Prints one JSON line.  `value` is JOR edge-vector updates per second over
 the whole step, nnz * R * k / t_step.
+
+Other forms, one JSON line each (--workload): `batch` (512 Chung-Lu graphs
+in one captured launch sequence), `bf16` (R-MAT n = 2^24, 2^28 edges, BF16
+storage, against the FP32 path and the FP64 path), `adjoint` (512 x 512
+grid with long-range edges, forward and weight gradient), `fp64` (G(n, m)
+with n = 2,000, m = 10,000 in FP64).  The inputs are those of
+paper_1601_05527_amd.workloads.
 """
 from __future__ import annotations
 
@@ -26,27 +33,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-N_LOG2 = 20
-M_EDGES = 16_000_000
-GAMMA = 2.1
-R = 16
-K = 20
-OMEGA = 0.5
-TARGET = 0.3
-SEED_GRAPH = 2024
-SEED_VEC = 1
 HBM_PEAK_GBS = 8000.0
+METRIC = "JOR edge-vector updates/s (nnz*R*k/s) + % HBM roofline; end-to-end sparsify ms"
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def sweep_bytes(n: int, nnz: int, r: int, bx: int, weighted: bool) -> int:
+def sweep_bytes(n: int, nnz: int, r: int, bx_in: int, weighted: bool, bx_out: "int | None" = None) -> int:
     """Algorithmic bytes of one JOR sweep: the CSR structure once (int32
     column + FP32 weight per stored entry, int64 row pointer and FP32 1/s
-    per row) plus one read and one write of the n x R block."""
-    return nnz * (4 + (4 if weighted else 0)) + (n + 1) * 8 + 4 * n + 2 * n * r * bx
+    per row) plus one read of the n x R block in and one write out."""
+    bx_out = bx_in if bx_out is None else bx_out
+    return nnz * (4 + (4 if weighted else 0)) + (n + 1) * 8 + 4 * n + n * r * (bx_in + bx_out)
 
 
 def dist_bytes(n: int, nnz: int, m: int, r: int, bx: int) -> int:
@@ -72,43 +72,89 @@ def sweep_traffic() -> "float | None":
     return float(info["traffic_bytes_per_launch"])
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=6,
-                    help="sweeps in the oracle's bounded CPU sample")
-    ap.add_argument("--layout", choices=["degree", "given"], default="degree")
-    ap.add_argument("--rows-per-wave", type=int, default=0)
-    ap.add_argument("--hub-degree", type=int, default=0)
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="before timing, copy a buffer of this many MiB device to device "
-                         "(a kernel of known traffic for calibrating memory counters)")
-    args = ap.parse_args()
+def oracle_threads() -> int:
+    threads = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    return int(omp) if omp and omp.isdigit() else threads
 
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the method runs on a single MI355X in this build)", file=sys.stderr)
-        return 2
 
-    import numpy as np
+class Timer:
+    """HIP events on the current stream (the stream every library call is
+    given) around a region, averaged over `reps` repetitions."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.ev0 = torch.cuda.Event(enable_timing=True)
+        self.ev1 = torch.cuda.Event(enable_timing=True)
+
+    def run(self, fn, reps: int) -> float:
+        self.torch.cuda.synchronize()
+        self.ev0.record()
+        for _ in range(reps):
+            fn()
+        self.ev1.record()
+        self.torch.cuda.synchronize()
+        return self.ev0.elapsed_time(self.ev1) / reps
+
+
+def traced(api, timer, fn, reps):
+    """(ms per call, per-kernel {name: (launches, total ms)}) with the
+    library's own per-launch event tracing switched on."""
+    api.lib.ad_trace_reset()
+    api.lib.ad_trace_enable(1)
+    ms = timer.run(fn, reps)
+    api.lib.ad_trace_enable(0)
+    kern = api.trace_summary()
+    api.lib.ad_trace_reset()
+    return ms, kern
+
+
+def roofline(kern: dict, bytes_per_launch: float, traffic=None) -> dict:
+    launches, total = kern.get("k_sweep", (0, 0.0))
+    avg = total / max(1, launches)
+    achieved = bytes_per_launch / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+    return {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": avg}
+
+
+def base_result(args, value, step_ms, dtype, data, config, roof, cpu, **extra) -> dict:
+    out = {
+        "metric": METRIC, "value": value, "unit": "edge-vector updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": data, "config": config,
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    return out
+
+
+def err_stats(got, want, floor_frac=0.1):
+    """Relative error of got against want (torch tensors on the GPU), with
+    values below floor_frac * median(want) measured against that floor."""
     import torch
+    want = want.double()
+    floor = floor_frac * float(want.median())
+    den = torch.clamp(want.abs(), min=floor)
+    rel = ((got.double() - want).abs() / den).float()
+    qs = torch.tensor([0.5, 0.99, 0.999], device=rel.device)
+    n = rel.numel()
+    pick = rel if n <= (1 << 23) else rel[torch.randint(0, n, (1 << 23,), device=rel.device,
+                                                       generator=torch.Generator(rel.device).manual_seed(0))]
+    q = torch.quantile(pick, qs).tolist()
+    return {"max": float(rel.max()), "median": q[0], "p99": q[1], "p999": q[2], "floor": floor}
 
-    from paper_1601_05527_amd import api, graphs
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+# ------------------------------------------------------------ Chung-Lu ---
 
+def run_chung_lu(args, api, torch, dev):
+    from paper_1601_05527_amd import workloads as W
+    c = W.CHUNG_LU
+    R, K, OMEGA, TARGET, SEED_VEC = c["R"], c["k"], W.OMEGA, c["target"], c["seed_vec"]
     t0 = time.perf_counter()
-    g = graphs.chung_lu(1 << N_LOG2, M_EDGES, gamma=GAMMA, seed=SEED_GRAPH)
-    t_gen = time.perf_counter() - t0
-    log(f"graph generated in {t_gen:.1f}s: n={g.n} m={g.m} d_max={g.d_max}")
-    t0 = time.perf_counter()
-    g_run = graphs.relabel(g, graphs.degree_descending_order(g)) if args.layout == "degree" else g
-    t_layout = time.perf_counter() - t0
+    g_orig, g_run = W.chung_lu_graph(args.layout)
+    t_setup = time.perf_counter() - t0
+    log(f"graph generated and laid out in {t_setup:.1f}s: n={g_run.n} m={g_run.m} d_max={g_run.d_max}")
     dg = api.DeviceGraph.from_host(g_run, dev, keep_host=False)
     n, m, nnz = dg.n, dg.m, 2 * dg.m
     torch.cuda.synchronize()
@@ -129,10 +175,13 @@ def main() -> int:
     nk_g = torch.empty(1, dtype=torch.int64, device=dev)
     fit = {}
 
-    def step():
+    def relax_dist():
         api.relax(dg, R, K, OMEGA, SEED_VEC, ws=ws_r, out=out, rows_per_wave=args.rows_per_wave,
                   hub_degree=args.hub_degree)
         api.edge_dist(dg, out.x, out.minmax, out=rho, ws=ws_d)
+
+    def step():
+        relax_dist()
         _, _, e_l = api.sparsify_fit(dg, rho, api.AD_LOCAL, TARGET, ws=ws_s, keep=keep_l, n_kept=nk_l)
         _, _, e_g = api.sparsify_fit(dg, rho, api.AD_GLOBAL, TARGET, ws=ws_s, keep=keep_g, n_kept=nk_g)
         fit["e_local"], fit["e_global"] = e_l, e_g
@@ -147,56 +196,28 @@ def main() -> int:
         log(f"calibration copy of {nb} bytes done")
         del src, dst
 
+    timer = Timer(torch)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-
-    api.lib.ad_trace_reset()
-    api.lib.ad_trace_enable(1)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    api.lib.ad_trace_enable(0)
-    step_ms = ev0.elapsed_time(ev1) / args.steps
-    kern = api.trace_summary()
-    api.lib.ad_trace_reset()
-
-    # Relax + distance alone (the bandwidth path), timed the same way.
-    ev0.record()
-    for _ in range(args.steps):
-        api.relax(dg, R, K, OMEGA, SEED_VEC, ws=ws_r, out=out, rows_per_wave=args.rows_per_wave,
-                  hub_degree=args.hub_degree)
-        api.edge_dist(dg, out.x, out.minmax, out=rho, ws=ws_d)
-    ev1.record()
-    torch.cuda.synchronize()
-    rd_ms = ev0.elapsed_time(ev1) / args.steps
+    step_ms, kern = traced(api, timer, step, args.steps)
+    rd_ms = timer.run(relax_dist, args.steps)     # relax + distance alone, the bandwidth path
 
     kept_l = int(nk_l.item())
     kept_g = int(nk_g.item())
-    updates = nnz * R * K
     weighted = dg.w is not None
     sb = sweep_bytes(n, nnz, R, 4, weighted)
     db = dist_bytes(n, nnz, m, R, 4)
-    sw_launches, sw_ms = kern.get("k_sweep", (0, 0.0))
-    sweep_ms = sw_ms / max(1, sw_launches)
-    achieved = sb / (sweep_ms * 1e-3) / 1e9
-    rd_bytes = K * sb + db
-    rd_gbs = rd_bytes / (rd_ms * 1e-3) / 1e9
+    roof = roofline(kern, sb, sweep_traffic())
+    rd_gbs = (K * sb + db) / (rd_ms * 1e-3) / 1e9
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        threads = len(os.sched_getaffinity(0))
-        omp = os.environ.get("OMP_NUM_THREADS")
-        cores = int(omp) if omp and omp.isdigit() else threads
+        cores = oracle_threads()
         log(f"CPU baseline: oracle, R={R}, {args.cpu_sweeps} sweeps, {cores} threads")
         t0 = time.perf_counter()
-        oracle.algebraic_distance(g, R, args.cpu_sweeps, OMEGA, seed=SEED_VEC)
+        oracle.algebraic_distance(g_run, R, args.cpu_sweeps, OMEGA, seed=SEED_VEC)
         t_cpu = time.perf_counter() - t0
         cpu = {"value": nnz * R * args.cpu_sweeps / t_cpu, "unit": "edge-vector updates/s",
                "cores": cores, "kind": "oracle",
@@ -204,47 +225,328 @@ def main() -> int:
                           f"{R} vectors, {args.cpu_sweeps} of the {K} sweeps, then rescale and "
                           f"distances; {t_cpu:.2f}s wall; selection not included")}
 
-    result = {
-        "metric": "JOR edge-vector updates/s (nnz*R*k/s) + % HBM roofline; end-to-end sparsify ms",
-        "value": updates / (step_ms * 1e-3),
-        "unit": "edge-vector updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": step_ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded Chung-Lu graph; no dataset)",
-        "config": {
-            "workload": (f"Chung-Lu power-law graph n=2^{N_LOG2}, m={M_EDGES}, gamma={GAMMA}, "
-                         f"lognormal(0,1) weights; R={R}, k={K}, omega={OMEGA}, FP32; LOCAL and "
-                         f"GLOBAL selection each fitted to {int(TARGET * 100)}% retention"),
-            "n": n, "m": m, "nnz": nnz, "d_max": dg.d_max, "R": R, "k": K,
-            "layout": args.layout, "parallelism": "single GPU",
-        },
-        "roofline": {
-            "kernel": "k_sweep",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": sweep_traffic(),
-            "bytes_per_launch": sb,
-            "avg_launch_ms": sweep_ms,
-        },
-        "cpu_baseline": cpu,
-        "breakdown_ms_per_step": {k_: v[1] / args.steps for k_, v in sorted(kern.items())},
-        "relax_dist_ms": rd_ms,
-        "relax_dist_hbm_frac": rd_gbs / HBM_PEAK_GBS,
-        "sweep_updates_per_s": nnz * R / (sweep_ms * 1e-3),
-        "fit": {"e_local": fit["e_local"], "e_global": fit["e_global"],
-                "kept_local": kept_l, "kept_global": kept_g,
-                "ratio_local": kept_l / m, "ratio_global": kept_g / m},
-        "setup_s": {"generate": t_gen, "layout": t_layout},
+    config = {
+        "workload": (f"Chung-Lu power-law graph n=2^20, m={c['m']}, gamma={c['gamma']}, "
+                     f"lognormal(0,1) weights; R={R}, k={K}, omega={OMEGA}, FP32; LOCAL and "
+                     f"GLOBAL selection each fitted to {int(TARGET * 100)}% retention"),
+        "n": n, "m": m, "nnz": nnz, "d_max": dg.d_max, "R": R, "k": K,
+        "layout": args.layout, "parallelism": "single GPU",
     }
+    return base_result(
+        args, nnz * R * K / (step_ms * 1e-3), step_ms, "f32", "synthetic (seeded Chung-Lu graph; no dataset)",
+        config, roof, cpu,
+        breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())},
+        relax_dist_ms=rd_ms, relax_dist_hbm_frac=rd_gbs / HBM_PEAK_GBS,
+        sweep_updates_per_s=nnz * R / (roof["avg_launch_ms"] * 1e-3) if roof["avg_launch_ms"] else None,
+        fit={"e_local": fit["e_local"], "e_global": fit["e_global"], "kept_local": kept_l,
+             "kept_global": kept_g, "ratio_local": kept_l / m, "ratio_global": kept_g / m},
+        setup_s={"generate_and_layout": t_setup})
+
+
+# --------------------------------------------------------------- batch ---
+
+def run_batch(args, api, torch, dev):
+    from paper_1601_05527_amd import graphs
+    from paper_1601_05527_amd import workloads as W
+    b_ = W.BATCH
+    R, K = b_["R"], b_["k"]
+    t0 = time.perf_counter()
+    ds = W.batch_graphs(dev)
+    dgs = [api.DeviceGraph.from_tensors(d) for d in ds]
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    n = sum(d.n for d in dgs)
+    m = sum(d.m for d in dgs)
+    nnz = 2 * m
+    log(f"{len(dgs)} graphs generated in {t_gen:.1f}s: n={n} m={m}")
+    t0 = time.perf_counter()
+    b = api.Batch(dgs, R, K, W.OMEGA, seed=b_["seed_vec"], graph_id=b_["graph_id"], orient=api.AD_LOCAL,
+                  e=b_["e"], autotune=True)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    log(f"batch created (pack, autotune, capture) in {t_create:.1f}s; rows_per_wave={b.rows_per_wave}")
+    timer = Timer(torch)
+    for _ in range(args.warmup):
+        b.run()
+    step_ms = timer.run(b.run, args.steps)
+    # the same launch sequence uncaptured, traced per kernel
+    unc_ms, kern = traced(api, timer, lambda: b.run(captured=False), args.steps)
+    weighted = True
+    roof = roofline(kern, sweep_bytes(n, nnz, R, 4, weighted))
+    kept = int(b.fetch()[2].sum().item())
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = oracle_threads()
+        budget_s = args.cpu_seconds
+        done_nnz, t_cpu, q = 0, 0.0, 0
+        while q < len(ds) and t_cpu < budget_s:
+            g = graphs.device_to_host(ds[q])
+            t0 = time.perf_counter()
+            oracle.algebraic_distance(g, R, K, W.OMEGA, seed=b_["seed_vec"], graph_id=b_["graph_id"] + q)
+            t_cpu += time.perf_counter() - t0
+            done_nnz += 2 * g.m
+            q += 1
+        cpu = {"value": done_nnz * R * K / t_cpu, "unit": "edge-vector updates/s", "cores": cores,
+               "kind": "oracle",
+               "sample": (f"FP64 oracle on the first {q} of the {len(ds)} graphs ({done_nnz // 2} edges), "
+                          f"R={R}, all {K} sweeps, rescale and distances; {t_cpu:.2f}s; selection not included")}
+    config = {
+        "workload": (f"batch of {len(dgs)} Chung-Lu graphs (gamma 2.1, lognormal weights), n log-uniform in "
+                     f"[1e3, 2e5], average degree uniform in [8, 32]; R={R}, k={K}, FP32; LOCAL selection "
+                     f"at e={b_['e']}; one captured launch sequence, rows_per_wave autotuned"),
+        "graphs": len(dgs), "n": n, "m": m, "nnz": nnz, "R": R, "k": K,
+        "rows_per_wave": b.rows_per_wave, "parallelism": "single GPU",
+    }
+    b.close()
+    return base_result(args, nnz * R * K / (step_ms * 1e-3), step_ms, "f32",
+                       "synthetic (seeded Chung-Lu graphs; no dataset)", config, roof, cpu,
+                       uncaptured_ms_per_step=unc_ms,
+                       breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())},
+                       kept=kept, setup_s={"generate": t_gen, "create": t_create})
+
+
+# ---------------------------------------------------------------- BF16 ---
+
+def run_bf16(args, api, torch, dev):
+    from paper_1601_05527_amd import graphs
+    from paper_1601_05527_amd import workloads as W
+    c = W.RMAT
+    R, K, TAIL, TARGET = c["R"], c["k"], c["fp32_tail"], c["target"]
+    t0 = time.perf_counter()
+    d = W.rmat_graph(dev)
+    dg = api.DeviceGraph.from_tensors(d)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    n, m, nnz = dg.n, dg.m, 2 * dg.m
+    log(f"R-MAT generated in {t_gen:.1f}s: n={n} m={m} d_max={dg.d_max}")
+    rho = torch.empty(m, dtype=torch.float32, device=dev)
+    ws_d = api._workspace(api.edge_dist_workspace_bytes(dg), dev)
+    ws_s = api._workspace(api.sparsify_workspace_bytes(dg), dev)
+    keep = torch.empty(m, dtype=torch.uint8, device=dev)
+    nk = torch.empty(1, dtype=torch.int64, device=dev)
+    fits = {}
+
+    def make(store):
+        opts = api.relax_opts(R, K, W.OMEGA, c["seed_vec"], store=store, fp32_tail=TAIL)
+        ws = api._workspace(api.relax_workspace_bytes(dg, opts), dev)
+        xdt = torch.float64 if store == "f64" else torch.float32
+        out = api.RelaxResult(x=torch.empty((n, R), dtype=xdt, device=dev),
+                              minmax=torch.empty(2 * R, dtype=torch.float64, device=dev),
+                              shift=torch.empty(R, dtype=torch.float64, device=dev), ckpt=None, store=store)
+        rho_s = rho if store != "f64" else torch.empty(m, dtype=torch.float64, device=dev)
+
+        def relax_dist():
+            api.relax(dg, R, K, W.OMEGA, c["seed_vec"], store=store, fp32_tail=TAIL, ws=ws, out=out)
+            api.edge_dist(dg, out.x, out.minmax, out=rho_s, ws=ws_d)
+
+        def step():
+            relax_dist()
+            for name, o in (("local", api.AD_LOCAL), ("global", api.AD_GLOBAL)):
+                _, _, e = api.sparsify_fit(dg, rho_s, o, TARGET, ws=ws_s, keep=keep, n_kept=nk)
+                fits[(store, name)] = e
+        return step, relax_dist, rho_s, ws
+
+    timer = Timer(torch)
+    results = {}
+    for store in ("bf16", "f32"):
+        step, relax_dist, rho_s, ws = make(store)
+        for _ in range(args.warmup):
+            step()
+        ms, kern = traced(api, timer, step, args.steps)
+        rd_ms = timer.run(relax_dist, args.steps)
+        relax_dist()
+        results[store] = {"ms": ms, "relax_dist_ms": rd_ms, "kern": kern, "rho": rho_s.clone()}
+        del ws
+        log(f"{store}: {ms:.2f} ms per step, relax+dist {rd_ms:.2f} ms")
+    # FP64 reference on the GPU (its parity with the oracle is tested), for error statistics
+    _, relax_dist64, rho64, ws64 = make("f64")
+    relax_dist64()
+    torch.cuda.synchronize()
+    acc = {"bf16_vs_f64": err_stats(results["bf16"]["rho"], rho64),
+           "f32_vs_f64": err_stats(results["f32"]["rho"], rho64),
+           "bf16_vs_f32": err_stats(results["bf16"]["rho"], results["f32"]["rho"])}
+    del rho64, ws64
+    # sweep bytes: x^(0) FP32, sweeps 1 .. k - tail stored in BF16, the last `tail` in FP32
+    weighted = True
+    per = []
+    for t in range(1, K + 1):
+        bin_ = 4 if (t - 1 == 0 or t - 1 > K - TAIL) else 2
+        bout = 4 if t > K - TAIL else 2
+        per.append(sweep_bytes(n, nnz, R, bin_, weighted, bout))
+    roof = roofline(results["bf16"]["kern"], sum(per) / K)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        g = graphs.device_to_host(d)
+        x0 = oracle.start_vectors(g.n, 1, c["seed_vec"], 0, g.orig_id)[:, 0].copy()
+        sweeps = args.cpu_sweeps
+        t0 = time.perf_counter()
+        oracle.relax_vector(g, x0, sweeps, W.OMEGA)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": nnz * sweeps / t_cpu, "unit": "edge-vector updates/s", "cores": oracle_threads(),
+               "kind": "oracle",
+               "sample": f"FP64 oracle, 1 of the {R} vectors, {sweeps} of the {K} sweeps on the same graph; "
+                         f"{t_cpu:.2f}s"}
+        del g
+    ms = results["bf16"]["ms"]
+    config = {
+        "workload": (f"R-MAT (a,b,c,d)=(.57,.19,.19,.05) n=2^{c['scale']}, m={m}, uniform(0.5,2) weights; "
+                     f"R={R}, k={K}, test vectors stored in BF16 (last {TAIL} sweeps FP32), FP32 arithmetic; "
+                     f"LOCAL and GLOBAL selection each fitted to {int(TARGET * 100)}% retention"),
+        "n": n, "m": m, "nnz": nnz, "d_max": dg.d_max, "R": R, "k": K, "fp32_tail": TAIL,
+        "parallelism": "single GPU",
+    }
+    return base_result(
+        args, nnz * R * K / (ms * 1e-3), ms, "bf16 storage, f32 arithmetic",
+        "synthetic (seeded R-MAT graph; no dataset)", config, roof, cpu,
+        fp32_path={"ms_per_step": results["f32"]["ms"], "relax_dist_ms": results["f32"]["relax_dist_ms"],
+                   "value": nnz * R * K / (results["f32"]["ms"] * 1e-3),
+                   "breakdown_ms_per_step": {k_: v[1] / args.steps
+                                             for k_, v in sorted(results["f32"]["kern"].items())}},
+        relax_dist_ms=results["bf16"]["relax_dist_ms"],
+        breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(results["bf16"]["kern"].items())},
+        accuracy=acc, fit={f"{s}_{o}": v for (s, o), v in fits.items()}, setup_s={"generate": t_gen})
+
+
+# ------------------------------------------------------------- adjoint ---
+
+def run_adjoint(args, api, torch, dev):
+    import numpy as np
+    from paper_1601_05527_amd import workloads as W
+    c = W.GRID
+    R, K, CK = c["R"], c["k"], c["ckpt_every"]
+    g = W.grid_graph()
+    dg = api.DeviceGraph.from_host(g, dev)
+    n, m, nnz = dg.n, dg.m, 2 * dg.m
+    cvec = torch.from_numpy(np.random.default_rng(c["seed"]).normal(size=m).astype(np.float32)).to(dev)
+    opts = api.relax_opts(R, K, W.OMEGA, c["seed_vec"], ckpt_every=CK)
+    ws_r = api._workspace(api.relax_workspace_bytes(dg, opts), dev)
+    ws_d = api._workspace(api.edge_dist_workspace_bytes(dg), dev)
+    nck = int(api.lib.ad_relax_num_checkpoints(api.ctypes.byref(opts)))
+    out = api.RelaxResult(x=torch.empty((n, R), dtype=torch.float32, device=dev),
+                          minmax=torch.empty(2 * R, dtype=torch.float64, device=dev),
+                          shift=torch.empty(R, dtype=torch.float64, device=dev),
+                          ckpt=torch.empty((nck, n, R), dtype=torch.float32, device=dev), store="f32")
+    rho = torch.empty(m, dtype=torch.float32, device=dev)
+    gw = torch.empty(m, dtype=torch.float32, device=dev)
+    opts_b = api.relax_opts(R, K, W.OMEGA, c["seed_vec"], ckpt_every=CK)
+    ws_b = api._workspace(int(api.lib.ad_relax_backward_workspace_size(api.ctypes.byref(dg.abi()),
+                                                                       api.ctypes.byref(opts_b))), dev)
+
+    def forward():
+        api.relax(dg, R, K, W.OMEGA, c["seed_vec"], ckpt_every=CK, ws=ws_r, out=out)
+        api.edge_dist(dg, out.x, out.minmax, out=rho, ws=ws_d)
+
+    def backward():
+        api.relax_backward(dg, out, R, K, cvec, W.OMEGA, c["seed_vec"], ckpt_every=CK, ws=ws_b, out=gw)
+
+    def step():
+        forward()
+        backward()
+
+    timer = Timer(torch)
+    for _ in range(args.warmup):
+        step()
+    f_ms = timer.run(forward, args.steps)
+    b_ms = timer.run(backward, args.steps)
+    step_ms, kern = traced(api, timer, step, args.steps)
+    roof = roofline(kern, sweep_bytes(n, nnz, R, 4, True))
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.grad_weights(g, cvec.cpu().numpy().astype(np.float64), R, K, W.OMEGA, seed=c["seed_vec"])
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": nnz * R * K / t_cpu, "unit": "edge-vector updates/s (forward + gradient)",
+               "cores": oracle_threads(), "kind": "oracle",
+               "sample": f"FP64 oracle reverse-mode gradient on the same graph, R={R}, k={K}; {t_cpu:.2f}s"}
+    config = {
+        "workload": (f"{c['side']}x{c['side']} grid plus {g.m - 2 * c['side'] * (c['side'] - 1)} random long-range "
+                     f"edges, lognormal weights; R={R}, k={K}, FP32; gradient of sum_e c_e rho_e with respect to "
+                     f"every edge weight, checkpoints every {CK} sweeps; value counts the forward sweeps only"),
+        "n": n, "m": m, "nnz": nnz, "R": R, "k": K, "ckpt_every": CK, "parallelism": "single GPU",
+    }
+    return base_result(args, nnz * R * K / (step_ms * 1e-3), step_ms, "f32",
+                       "synthetic (seeded grid with long-range edges; no dataset)", config, roof, cpu,
+                       forward_ms=f_ms, backward_ms=b_ms, backward_over_forward=b_ms / f_ms,
+                       breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())})
+
+
+# ---------------------------------------------------------------- FP64 ---
+
+def run_fp64(args, api, torch, dev):
+    import numpy as np
+    from paper_1601_05527_amd import workloads as W
+    c = W.GNM
+    R, K, E = c["R"], c["k"], c["e"]
+    g = W.gnm_graph()
+    dg = api.DeviceGraph.from_host(g, dev)
+    n, m, nnz = dg.n, dg.m, 2 * dg.m
+    res = {}
+
+    def step():
+        r = api.relax(dg, R, K, W.OMEGA, c["seed_vec"], store="f64")
+        rho = api.edge_dist(dg, r.x, r.minmax)
+        keep, nk = api.sparsify(dg, rho, api.AD_LOCAL, E)
+        res["rho"], res["keep"] = rho, keep
+
+    timer = Timer(torch)
+    for _ in range(args.warmup):
+        step()
+    step_ms, kern = traced(api, timer, step, args.steps)
+    roof = roofline(kern, sweep_bytes(n, nnz, R, 8, False))
+    import oracle
+    t0 = time.perf_counter()
+    rho_o = oracle.algebraic_distance(g, R, K, W.OMEGA, seed=c["seed_vec"])
+    keep_o, _ = oracle.sparsify(g, rho_o, 0, E)
+    t_cpu = time.perf_counter() - t0
+    rho_g = res["rho"].cpu().numpy()
+    cpu = None if args.no_cpu_baseline else {
+        "value": nnz * R * K / t_cpu, "unit": "edge-vector updates/s", "cores": oracle_threads(), "kind": "oracle",
+        "sample": f"the whole workload: FP64 oracle distances and LOCAL selection; {t_cpu * 1e3:.1f} ms"}
+    config = {"workload": f"G(n,m) n={n}, m={m}, unit weights, seed 0; R={R}, k={K}, FP64; LOCAL selection e={E}",
+              "n": n, "m": m, "nnz": nnz, "R": R, "k": K, "parallelism": "single GPU"}
+    return base_result(args, nnz * R * K / (step_ms * 1e-3), step_ms, "f64", "synthetic (seeded G(n,m); no dataset)",
+                       config, roof, cpu,
+                       oracle_max_rel_err=float(np.max(np.abs(rho_g - rho_o) / rho_o)),
+                       kept_equal_oracle=bool(np.array_equal(res["keep"].cpu().numpy(), keep_o)),
+                       breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())})
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["chung-lu", "batch", "bf16", "adjoint", "fp64"], default="chung-lu")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=6, help="sweeps in the oracle's bounded CPU sample")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="batch workload: oracle time budget for its graph sample")
+    ap.add_argument("--layout", choices=["degree", "given"], default="degree")
+    ap.add_argument("--rows-per-wave", type=int, default=0)
+    ap.add_argument("--hub-degree", type=int, default=0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, copy a buffer of this many MiB device to device "
+                         "(a kernel of known traffic for calibrating memory counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: every workload "
+              "here runs on a single MI355X", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1601_05527_amd import api
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    run = {"chung-lu": run_chung_lu, "batch": run_batch, "bf16": run_bf16, "adjoint": run_adjoint,
+           "fp64": run_fp64}[args.workload]
+    result = run(args, api, torch, dev)
     print(json.dumps(result), flush=True)
     return 0
 

@@ -170,6 +170,18 @@ class DeviceGraph:
             _check(lib.ad_graph_col_orig(ctypes.byref(gs), _ptr(dg.col_orig), _stream()))
         return dg
 
+    @classmethod
+    def from_tensors(cls, d: dict, entry_ids: bool = True) -> "DeviceGraph":
+        """Wrap a device graph dict (graphs.chung_lu_device / rmat_device)."""
+        dg = cls(n=d["n"], m=d["m"], d_max=d["d_max"], row_ptr=d["row_ptr"].contiguous(),
+                 col=d["col"].contiguous(), w=None if d["w"] is None else d["w"].contiguous(),
+                 eid=d["eid"].contiguous(), orig_id=d["orig_id"].contiguous(), host=None)
+        if entry_ids and dg.m > 0:
+            dg.col_orig = torch.empty(2 * dg.m, dtype=torch.int32, device=dg.row_ptr.device)
+            gs = dg.abi()
+            _check(lib.ad_graph_col_orig(ctypes.byref(gs), _ptr(dg.col_orig), _stream()))
+        return dg
+
     @property
     def device(self):
         return self.row_ptr.device

@@ -54,22 +54,109 @@ __device__ __forceinline__ A group_sum(A v, int C, int base) {
     return t;
 }
 
-// rho for the upper entries (j > i) of every row.  Persistent waves walk a
-// launch plan (first row, rows in the tile, log2 rows per wave) as the sweep does; per row
-// SPRW / rpw slots of C lanes, VEC values per lane, U entries per slot in
-// flight.  Lane chunk c sums ((x_i - x_j) * inv)^2 over its VEC values in
-// order; group_sum adds the chunks.
+// rho for the upper entries (j > i) of the entries beg .. end - 1 of `row`
+// (one lane group of C lanes per slot, SPR slots, U entries per slot in
+// flight).  Lane chunk c sums ((x_i - x_j) * inv)^2 over its VEC values in
+// order; group_sum adds the chunks.  `len` is the wave's common trip bound.
+template <typename Tx, typename Tr, int VEC, int U>
+__device__ __forceinline__ void dist_span(const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
+                                          const Tx *__restrict__ x, const double *__restrict__ minmax,
+                                          Tr *__restrict__ rho, int R, int C, int SPR, int slot, int chunk,
+                                          int base, bool active, int64_t row, int64_t beg, int64_t end,
+                                          int64_t len, int64_t gb) {
+    typedef typename acc_of<Tx>::type A;
+    const int off = chunk * VEC;
+    A xi[VEC], iv[VEC];
+    if (active) {
+        load_vec<VEC>(x + row * R + off, xi);
+    } else {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) xi[q] = (A)0;
+    }
+    // 1 / (max - min) of this lane's vectors, for the graph of the row
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+        const double lo = minmax[gb + off + q], hi = minmax[gb + R + off + q];
+        iv[q] = (hi > lo) ? (A)(1.0 / (hi - lo)) : (A)0;
+    }
+    for (int64_t k0 = slot; k0 < len; k0 += (int64_t)U * SPR) {
+        int32_t jj[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = beg + k0 + (int64_t)u * SPR;
+            ok[u] = active && p < end;
+            jj[u] = ok[u] ? col[p] : 0;
+            ok[u] = ok[u] && jj[u] > row;
+        }
+        A part[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            A xj[VEC];
+            if (ok[u]) {
+                load_vec<VEC>(x + (int64_t)jj[u] * R + off, xj);
+            } else {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) xj[q] = xi[q];
+            }
+            A acc = (A)0;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                const A d = (xi[q] - xj[q]) * iv[q];
+                acc = fma(d, d, acc);
+            }
+            part[u] = acc;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const A tot = group_sum(part[u], C, base);
+            if (ok[u] && chunk == 0) rho[eid[beg + k0 + (int64_t)u * SPR]] = (Tr)sqrt(tot);
+        }
+    }
+}
+
+// Entries per wave work item of a long row in the distance pass.
+constexpr int64_t DIST_SEG = 4096;
+
+// rho for every edge.  The first hub_blocks workgroups take the rows longer
+// than hub_d, cut into work items of DIST_SEG entries (row h of the hub list,
+// segment s < hub_segs; items past the row's end are skipped), one wave per
+// item.  The other waves walk the launch plan (first row, rows in the tile,
+// log2 rows per wave) as the sweep does, with SPRW / rpw slots per row.
+// Every edge's value is computed by the same lane arithmetic on either path.
 template <typename Tx, typename Tr, int VEC, int U>
 __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
     int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const Tx *__restrict__ x, const double *__restrict__ minmax,
-    Tr *__restrict__ rho, int R, int C, int SPRW, const long long *__restrict__ plan,
-    const unsigned int *__restrict__ plan_count, const int32_t *__restrict__ row_graph) {
-    typedef typename acc_of<Tx>::type A;
+    Tr *__restrict__ rho, int R, int C, int SPRW, int64_t hub_d, int hub_blocks, int64_t hub_segs,
+    const int32_t *__restrict__ hub_list, const unsigned int *__restrict__ hub_count,
+    const long long *__restrict__ plan, const unsigned int *__restrict__ plan_count,
+    const int32_t *__restrict__ row_graph) {
     const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    if ((int)blockIdx.x < hub_blocks) {
+        const int group = C * SPRW;
+        const int slot = lane / C;
+        const int chunk = lane - slot * C;
+        const bool active = lane < group;
+        const unsigned long long items = (unsigned long long)(*hub_count) * (unsigned long long)hub_segs;
+        const unsigned long long stride = (unsigned long long)hub_blocks * (SBLOCK / WAVE);
+        for (unsigned long long it = (unsigned long long)blockIdx.x * (SBLOCK / WAVE) + wave; it < items;
+             it += stride) {
+            const int64_t row = hub_list[it / hub_segs];
+            const int64_t rb = row_ptr[row], re = row_ptr[row + 1];
+            const int64_t b0 = rb + (int64_t)(it % hub_segs) * DIST_SEG;
+            if (b0 >= re) continue;                       // uniform across the wave
+            const int64_t e0 = min(re, b0 + DIST_SEG);
+            const int64_t gb = (int64_t)(row_graph ? row_graph[row] : 0) * 2 * R;
+            dist_span<Tx, Tr, VEC, U>(col, eid, x, minmax, rho, R, C, SPRW, slot, chunk, lane - chunk, active,
+                                      row, b0, e0, e0 - b0, gb);
+        }
+        return;
+    }
     const unsigned int np = *plan_count;
-    const unsigned int nwaves = gridDim.x * (SBLOCK / WAVE);
-    for (unsigned int pi = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); pi < np; pi += nwaves) {
+    const unsigned int nwaves = (gridDim.x - hub_blocks) * (SBLOCK / WAVE);
+    for (unsigned int pi = (blockIdx.x - hub_blocks) * (SBLOCK / WAVE) + wave; pi < np; pi += nwaves) {
         const long long pe = plan[pi];
         const int64_t row0 = pe >> 16;
         const int nrows = (int)((pe >> 8) & 0xff);     // rows of this entry inside its tile
@@ -80,67 +167,22 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
         const int sub = lane - rw * group;
         const int slot = sub / C;
         const int chunk = sub - slot * C;
-        const int base = lane - chunk;
         const int64_t row = row0 + rw;
-        const bool active = rw < nrows;
+        bool active = rw < nrows;
         int64_t beg = 0, end = 0;
         if (active) {
             beg = row_ptr[row];
             end = row_ptr[row + 1];
+            if (end - beg > hub_d) active = false;        // taken by the hub workgroups
         }
-        const int off = chunk * VEC;
-        A xi[VEC], iv[VEC];
-        if (active) {
-            load_vec<VEC>(x + row * R + off, xi);
-        } else {
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) xi[q] = (A)0;
-        }
-        // 1 / (max - min) of this lane's vectors, for the graph of the entry's rows
-        const int64_t gb = (int64_t)(row_graph ? row_graph[row0] : 0) * 2 * R;
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) {
-            const double lo = minmax[gb + off + q], hi = minmax[gb + R + off + q];
-            iv[q] = (hi > lo) ? (A)(1.0 / (hi - lo)) : (A)0;
-        }
+        if (!active) beg = end = 0;
         // uniform trip count across the wave: the longest row of the wave
         int64_t len = end - beg;
         for (int d = WAVE / 2; d >= 1; d >>= 1) len = max(len, shfl_down(len, d));
         len = shfl(len, 0);
-        for (int64_t k0 = slot; k0 < len; k0 += (int64_t)U * SPR) {
-            int32_t jj[U];
-            bool ok[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t p = beg + k0 + (int64_t)u * SPR;
-                ok[u] = active && p < end;
-                jj[u] = ok[u] ? col[p] : 0;
-                ok[u] = ok[u] && jj[u] > row;
-            }
-            A part[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                A xj[VEC];
-                if (ok[u]) {
-                    load_vec<VEC>(x + (int64_t)jj[u] * R + off, xj);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < VEC; ++q) xj[q] = xi[q];
-                }
-                A acc = (A)0;
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) {
-                    const A d = (xi[q] - xj[q]) * iv[q];
-                    acc = fma(d, d, acc);
-                }
-                part[u] = acc;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const A tot = group_sum(part[u], C, base);
-                if (ok[u] && chunk == 0) rho[eid[beg + k0 + (int64_t)u * SPR]] = (Tr)sqrt(tot);
-            }
-        }
+        const int64_t gb = (int64_t)(row_graph ? row_graph[row0] : 0) * 2 * R;
+        dist_span<Tx, Tr, VEC, U>(col, eid, x, minmax, rho, R, C, SPR, slot, chunk, lane - chunk, active, row, beg,
+                                  end, len, gb);
     }
 }
 
@@ -442,7 +484,7 @@ __global__ __launch_bounds__(TB) void k_rank_bitonic(
 }
 
 // Listed rows ranked by counting against keys read from memory (FP64
-// distances with d > 64, or FP32 rows longer than SORT_CAP).
+// distances with d > 64).
 template <typename Tr>
 __global__ __launch_bounds__(SBLOCK) void k_rank_count(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
@@ -469,6 +511,198 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_count(
                 if (before(ru, iu, r, id, orient)) ++rank;
             }
             emit(mode, row, j, e, d, rank, budget, keep, sides);
+        }
+    }
+}
+
+// Rows longer than SORT_CAP (FP32 distances): bucket partition, then one
+// wave per bucket.  A workgroup per row sorts a regular sample of the row's
+// keys in LDS; runs of `sp` consecutive sorted samples delimit the buckets,
+// whose sizes are counted and scanned, and the row's entries are scattered
+// to their bucket's range of a scratch copy (key and offset in the row).  An
+// entry's rank is its bucket's offset plus its rank among the bucket's keys.
+// Keys are unique within a row (the neighbour id breaks ties), so the order
+// the scatter leaves inside a bucket does not matter.
+constexpr int HUB_TB = 1024;
+constexpr int HUB_SAMPLE = 16384;       // largest sample (128 KiB of keys in LDS)
+constexpr int HUB_BUCKET = 256;         // target bucket size
+constexpr int HUB_MIN_SP = 4;           // fewest samples per bucket
+constexpr int HUB_MAX_B = HUB_SAMPLE / HUB_MIN_SP;
+constexpr int HUB_KPL = 8;              // bucket keys per lane held in registers
+
+struct HubScratch {
+    unsigned long long *key;   // [2m] bucketed keys, at the row's own entry range
+    uint32_t *pos;             // [2m] offset in the row of each bucketed key
+    int32_t *bk_list;          // [cap] hub-list index of the bucket's row
+    uint32_t *bk_off;          // [cap] bucket offset within its row
+    uint32_t *bk_cnt;          // [cap] bucket size
+    unsigned int *nbk;         // [1] buckets written
+    int64_t cap;
+};
+
+// In-place exclusive scan of a[0 .. B) (B <= 4 * HUB_TB) by the workgroup.
+__device__ void hub_scan(uint32_t *a, int B, uint32_t *wsum) {
+    const int t = threadIdx.x, lane = t & (WAVE - 1), w = t >> 6;
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int q = 4 * t + i;
+        v[i] = q < B ? a[q] : 0u;
+        s += v[i];
+    }
+    uint32_t inc = s;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, WAVE);
+        if (lane >= o) inc += y;
+    }
+    if (lane == WAVE - 1) wsum[w] = inc;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < HUB_TB / WAVE; ++i) {
+            const uint32_t x = wsum[i];
+            wsum[i] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+    uint32_t b = wsum[w] + inc - s;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int q = 4 * t + i;
+        if (q < B) a[q] = b;
+        b += v[i];
+    }
+    __syncthreads();
+}
+
+// Number of samples <= k in the sorted samp[0 .. S).
+__device__ __forceinline__ int hub_upper(const unsigned long long *samp, int S, unsigned long long k) {
+    int lo = 0, hi = S;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (samp[mid] <= k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(HUB_TB) void k_hub_partition(
+    const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, int orient, HubScratch hs) {
+    __shared__ unsigned long long samp[HUB_SAMPLE];
+    __shared__ uint32_t cnt[HUB_MAX_B];
+    __shared__ uint32_t wsum[HUB_TB / WAVE];
+    __shared__ uint32_t base_s;
+    const unsigned int nr = *count;
+    for (unsigned int h = blockIdx.x; h < nr; h += gridDim.x) {
+        const int64_t row = list[h];
+        const int64_t beg = row_ptr[row];
+        const int64_t d = row_ptr[row + 1] - beg;
+        // a power-of-two sample of about d / 16 keys (1024 .. HUB_SAMPLE), at
+        // distinct, evenly spaced entries (d > SORT_CAP >= S)
+        int S = 1024;
+        while (S < HUB_SAMPLE && (int64_t)S * 16 < d) S <<= 1;
+        const int B = (int)min((int64_t)(S / HUB_MIN_SP), (d + HUB_BUCKET - 1) / HUB_BUCKET);
+        const int sp = S / B;
+        for (int t = threadIdx.x; t < S; t += HUB_TB) {
+            const int64_t p = beg + ((int64_t)t * d) / S;
+            samp[t] = sort_key(rho[eid[p]], nbr_id(p, col[p], col_orig, orig_id), orient);
+        }
+        for (int b = threadIdx.x; b < B; b += HUB_TB) cnt[b] = 0;
+        __syncthreads();
+        for (int size = 2; size <= S; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int t = threadIdx.x; t < (S >> 1); t += HUB_TB) {
+                    const int a = 2 * t - (t & (stride - 1));
+                    const int b = a + stride;
+                    const bool up = ((a & size) == 0);
+                    const unsigned long long ka = samp[a], kb = samp[b];
+                    if ((ka > kb) == up) {
+                        samp[a] = kb;
+                        samp[b] = ka;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int64_t q = threadIdx.x; q < d; q += HUB_TB) {
+            const int64_t p = beg + q;
+            const unsigned long long k = sort_key(rho[eid[p]], nbr_id(p, col[p], col_orig, orig_id), orient);
+            atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) / sp)], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) base_s = atomicAdd(hs.nbk, (unsigned int)B);
+        __syncthreads();
+        const int64_t base = base_s;
+        const bool fits = base + B <= hs.cap;              // holds by the workspace bound
+        if (fits) {
+            for (int b = threadIdx.x; b < B; b += HUB_TB) {
+                hs.bk_list[base + b] = (int32_t)h;
+                hs.bk_cnt[base + b] = cnt[b];
+            }
+        }
+        __syncthreads();
+        hub_scan(cnt, B, wsum);
+        if (fits) {
+            for (int b = threadIdx.x; b < B; b += HUB_TB) hs.bk_off[base + b] = cnt[b];
+        }
+        __syncthreads();
+        for (int64_t q = threadIdx.x; q < d; q += HUB_TB) {
+            const int64_t p = beg + q;
+            const unsigned long long k = sort_key(rho[eid[p]], nbr_id(p, col[p], col_orig, orig_id), orient);
+            const uint32_t at = atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) / sp)], 1u);
+            hs.key[beg + at] = k;
+            hs.pos[beg + at] = (uint32_t)q;
+        }
+        __syncthreads();
+    }
+}
+
+// One wave per bucket: each key's rank among the bucket's keys, counted
+// against all of them broadcast 64 at a time; HUB_KPL * 64 own keys per pass.
+__global__ __launch_bounds__(SBLOCK) void k_hub_rank(
+    const int32_t *__restrict__ list, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ eid, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
+    unsigned long long *__restrict__ sides, HubScratch hs) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned int nb = (unsigned int)min((int64_t)(*hs.nbk), hs.cap);
+    const unsigned int waves = gridDim.x * (SBLOCK / WAVE);
+    for (unsigned int w = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); w < nb; w += waves) {
+        const int64_t row = list[hs.bk_list[w]];
+        const int64_t beg = row_ptr[row];
+        const int64_t d = row_ptr[row + 1] - beg;
+        const uint32_t off = hs.bk_off[w], c = hs.bk_cnt[w];
+        const unsigned long long *bk = hs.key + beg + off;
+        const uint32_t *bp = hs.pos + beg + off;
+        for (uint32_t c0 = 0; c0 < c; c0 += HUB_KPL * WAVE) {
+            unsigned long long key[HUB_KPL];
+            int rank[HUB_KPL];
+#pragma unroll
+            for (int t = 0; t < HUB_KPL; ++t) {
+                const uint32_t q = c0 + t * WAVE + lane;
+                key[t] = q < c ? bk[q] : ~0ull;
+                rank[t] = 0;
+            }
+            for (uint32_t s0 = 0; s0 < c; s0 += WAVE) {
+                const unsigned long long mine = (s0 + lane < c) ? bk[s0 + lane] : ~0ull;
+                const int lim = (int)min((uint32_t)WAVE, c - s0);
+                for (int src = 0; src < lim; ++src) {
+                    const unsigned long long k = shfl(mine, src);
+#pragma unroll
+                    for (int t = 0; t < HUB_KPL; ++t) rank[t] += (k < key[t]) ? 1 : 0;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < HUB_KPL; ++t) {
+                const uint32_t q = c0 + t * WAVE + lane;
+                if (q < c) {
+                    const int64_t p = beg + bp[q];
+                    emit(mode, row, col[p], eid[p], d, (int64_t)off + rank[t], budget, keep, sides);
+                }
+            }
         }
     }
 }
@@ -632,6 +866,7 @@ struct SelLayout {
     unsigned long long *counts;   // [2]
     int32_t *tab_hi, *tab_lo;     // [d_max + 1]
     double *logs;                 // [d_max + 2]
+    HubScratch hub;               // rows longer than SORT_CAP (d_max > SORT_CAP only)
 };
 
 // Degree classes above 64: wave counting with 2/4/8 keys per lane, bitonic
@@ -664,6 +899,18 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     l.tab_hi = c.take<int32_t>((size_t)g->d_max + 1);
     l.tab_lo = c.take<int32_t>((size_t)g->d_max + 1);
     l.logs = c.take<double>((size_t)g->d_max + 2);
+    l.hub = HubScratch{};
+    if (g->d_max > SORT_CAP) {
+        // at most 2m entries lie in long rows; a row of degree d has at most
+        // ceil(d / HUB_BUCKET) buckets, and there are at most 2m / (SORT_CAP + 1) such rows
+        l.hub.cap = ceil_div(2 * m, HUB_BUCKET) + ceil_div(2 * m, SORT_CAP + 1) + 1;
+        l.hub.key = c.take<unsigned long long>(2 * m);
+        l.hub.pos = c.take<uint32_t>(2 * m);
+        l.hub.bk_list = c.take<int32_t>(l.hub.cap);
+        l.hub.bk_off = c.take<uint32_t>(l.hub.cap);
+        l.hub.bk_cnt = c.take<uint32_t>(l.hub.cap);
+        l.hub.nbk = c.take<unsigned int>(1);
+    }
     if (L) *L = l;
     return c.ok() ? c.used : 0;
 }
@@ -738,8 +985,14 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, int orient, int mode
         AD_LAUNCH_CHECK("k_rank_bitonic");
 #undef AD_RANK_ARGS_F
         if (g->d_max > SORT_CAP) {
-            hipLaunchKernelGGL((k_rank_count<Tr>), dim3(grid), dim3(SBLOCK), 0, st, lst[7], &L.cnt[7], AD_RANK_ARGS);
-            AD_LAUNCH_CHECK("k_rank_count");
+            s = fill_i32((int32_t *)L.hub.nbk, 0, 1, st);
+            if (s != AD_OK) return s;
+            hipLaunchKernelGGL(k_hub_partition, dim3(512), dim3(HUB_TB), 0, st, lst[7], &L.cnt[7], g->row_ptr,
+                               g->col, g->eid, g->orig_id, g->col_orig, rf, orient, L.hub);
+            AD_LAUNCH_CHECK("k_hub_partition");
+            hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, st, lst[7], g->row_ptr, g->col, g->eid,
+                               mode, budget, keep, L.sides, L.hub);
+            AD_LAUNCH_CHECK("k_hub_rank");
         }
     } else {
         for (int k = 0; k < NCLASS; ++k) {
@@ -773,11 +1026,14 @@ using namespace ad;
 
 namespace ad {
 
-static SweepShape dist_shape(int R, ad_dtype x_dtype) {
-    // the sweep's lane layout for this vector width; every row in the plan
-    // (no hub rows: a long row keeps one wave to itself)
+// Rows longer than this are cut into DIST_SEG-entry work items.
+constexpr int64_t DIST_HUB = 4096;
+
+static SweepShape dist_shape(int R, ad_dtype x_dtype, int64_t d_max) {
+    // the sweep's lane layout for this vector width; rows longer than
+    // DIST_HUB (when the graph has any) go to the hub workgroups
     SweepShape sh = sweep_shape(R, x_dtype == AD_F64 ? 8 : 4, 0, 0);
-    sh.hub_d = (int64_t)1 << 62;
+    sh.hub_d = (d_max > DIST_HUB) ? DIST_HUB : ((int64_t)1 << 62);
     return sh;
 }
 
@@ -792,15 +1048,24 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
     sweep_plan_carve(c, g->n, sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE), pl);
     if (!c.ok()) return fail(AD_ERR_WORKSPACE, "workspace too small");
     if (g->n <= 0 || g->m <= 0) return AD_OK;
-    pl.sh = dist_shape(R, x_dtype);
-    ad_status s = sweep_plan_build(g, pl, false, sg, stream);
+    pl.sh = dist_shape(R, x_dtype, g->d_max);
+    const bool hubs = g->d_max > DIST_HUB;
+    ad_status s = sweep_plan_build(g, pl, hubs, sg, stream);
     if (s != AD_OK) return s;
-    const unsigned nb = (unsigned)std::min<int64_t>(4096, ceil_div(g->n, SBLOCK / WAVE));
+    // hub work items: (rows longer than DIST_HUB) x (segments of the longest row)
+    int64_t hub_segs = 1, hub_blocks = 0;
+    if (hubs) {
+        hub_segs = ceil_div(g->d_max, DIST_SEG);
+        const int64_t busy = ceil_div(2 * g->m, DIST_SEG) + ceil_div(2 * g->m, DIST_HUB + 1);
+        hub_blocks = std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(busy, SBLOCK / WAVE)));
+    }
+    const unsigned nb = (unsigned)(std::min<int64_t>(4096, ceil_div(g->n, SBLOCK / WAVE)) + hub_blocks);
     TraceScope trace("k_edge_dist", stream);
 #define AD_DIST(TX, TR, V)                                                                                   \
     hipLaunchKernelGGL((k_edge_dist<TX, TR, V, DIST_UNROLL>), dim3(nb), dim3(SBLOCK), 0, stream, g->n,      \
                        g->row_ptr, g->col, g->eid, (const TX *)x, minmax, (TR *)rho, R, pl.sh.C, pl.sh.SPRW,  \
-                       pl.plan, pl.plan_count, sg.row_graph)
+                       pl.sh.hub_d, (int)hub_blocks, hub_segs, pl.hub_list, pl.hub_count, pl.plan,            \
+                       pl.plan_count, sg.row_graph)
     if (x_dtype == AD_F64) {
         if (pl.sh.vec == 2) AD_DIST(double, double, 2);
         else AD_DIST(double, double, 1);

@@ -160,11 +160,6 @@ def degree_descending_order(g: Graph) -> np.ndarray:
 # Seeded generators
 # ---------------------------------------------------------------------------
 
-def _dedup_pairs(lo, hi, n):
-    key = np.unique(lo.astype(np.int64) * n + hi.astype(np.int64))
-    return key
-
-
 def gnm(n: int, m: int, seed: int = 0) -> Graph:
     """Erdos-Renyi G(n, m): m distinct unordered non-loop pairs, rejection
     sampled with ``numpy.random.default_rng(seed)``.  Unit weights."""
@@ -347,3 +342,164 @@ def with_weights(g: Graph, edge_w) -> Graph:
                  w=None if ew is None else ew[g.eid],
                  eid=g.eid, orig_id=g.orig_id, edge_u=g.edge_u,
                  edge_v=g.edge_v, edge_w=ew)
+
+
+# ---------------------------------------------------------------------------
+# Device-side generators for graphs too large to build quickly on the host.
+# Same constructions as above, drawn with torch on a GPU (seeded torch
+# generator, so a device and seed give the same graph); the result is a dict
+# of device tensors in the CSR conventions of this module.
+# ---------------------------------------------------------------------------
+
+def _csr_from_keys_torch(n: int, keys, w, orig_id):
+    """Symmetric CSR (dict of tensors) from sorted unique keys lo * n + hi."""
+    import torch
+    dev = keys.device
+    m = keys.numel()
+    lo = keys // n
+    hi = keys % n
+    rows = torch.cat([lo, hi])
+    cols = torch.cat([hi, lo])
+    ids = torch.cat([torch.arange(m, device=dev), torch.arange(m, device=dev)])
+    order = torch.argsort(rows * n + cols)
+    rows, cols, ids = rows[order], cols[order], ids[order]
+    counts = torch.bincount(rows, minlength=n)
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    row_ptr[1:] = torch.cumsum(counts, 0)
+    out = {"n": n, "m": m, "row_ptr": row_ptr, "col": cols.to(torch.int32), "eid": ids.to(torch.int32),
+           "w": None if w is None else w[ids].contiguous(), "edge_w": w,
+           "orig_id": orig_id.to(torch.int32), "edge_u": lo, "edge_v": hi,
+           "d_max": int(counts.max().item()) if n else 0}
+    return out
+
+
+def _dedup_draws_torch(draw, m: int, n: int, gen):
+    """Draw endpoint pairs with draw(k) until m distinct non-loop pairs."""
+    import torch
+    keys = None
+    while keys is None or keys.numel() < m:
+        have = 0 if keys is None else keys.numel()
+        need = m - have
+        a, b = draw(int(need * 1.2) + 4096)
+        ok = a != b
+        lo = torch.minimum(a[ok], b[ok])
+        hi = torch.maximum(a[ok], b[ok])
+        new = torch.unique(lo * n + hi)
+        if keys is not None:
+            new = new[~torch.isin(new, keys)]
+        if new.numel() > need:
+            pick = torch.randperm(new.numel(), generator=gen, device=new.device)[:need]
+            new = new[pick]
+        keys = new if keys is None else torch.cat([keys, new])
+        keys = torch.sort(keys).values
+    return keys
+
+
+def _relabel_torch(n: int, keys, gen, perm=None):
+    import torch
+    if perm is None:
+        perm = torch.randperm(n, generator=gen, device=keys.device)
+    lo = perm[keys // n]
+    hi = perm[keys % n]
+    a = torch.minimum(lo, hi)
+    b = torch.maximum(lo, hi)
+    k2 = a * n + b
+    order = torch.argsort(k2)
+    return k2[order], order, perm
+
+
+def chung_lu_device(n: int, m: int, gamma: float = 2.1, seed: int = 0, weights: str = "lognormal",
+                    device="cuda", degree_order: bool = True):
+    """Chung-Lu graph (the construction of `chung_lu`) drawn on a GPU.  With
+    degree_order the vertices are stored by decreasing degree afterwards
+    (orig_id keeps the randomly permuted ids)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    i = torch.arange(n, dtype=torch.float64, device=device)
+    theta = ((i + 0.5) / n) ** (-1.0 / (gamma - 1.0))
+    theta = theta * ((2.0 * m / n) / theta.mean())
+    theta = torch.minimum(theta, torch.sqrt(theta.sum()))
+    cdf = torch.cumsum(theta, 0)
+    cdf = cdf / cdf[-1]
+
+    def draw(k):
+        a = torch.searchsorted(cdf, torch.rand(k, generator=gen, device=device, dtype=torch.float64), right=True)
+        b = torch.searchsorted(cdf, torch.rand(k, generator=gen, device=device, dtype=torch.float64), right=True)
+        return torch.clamp(a, max=n - 1), torch.clamp(b, max=n - 1)
+
+    keys = _dedup_draws_torch(draw, m, n, gen)
+    keys, _, perm = _relabel_torch(n, keys, gen)          # random vertex permutation
+    orig = torch.arange(n, device=device)
+    w = None
+    if weights == "lognormal":
+        w = torch.exp(torch.randn(m, generator=gen, device=device)).float()
+    elif weights == "uniform":
+        w = (0.5 + 1.5 * torch.rand(m, generator=gen, device=device)).float()
+    if degree_order:
+        keys, w, orig = _degree_order_torch(n, keys, w, orig)
+    return _csr_from_keys_torch(n, keys, w, orig)
+
+
+def rmat_device(scale: int, m: int, a=0.57, b=0.19, c=0.19, seed: int = 0, weights: str = "uniform",
+                device="cuda", degree_order: bool = True):
+    """R-MAT graph (the construction of `rmat`) drawn on a GPU."""
+    import torch
+    n = 1 << scale
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    ab, abc = a + b, a + b + c
+
+    def draw(k):
+        src = torch.zeros(k, dtype=torch.int64, device=device)
+        dst = torch.zeros(k, dtype=torch.int64, device=device)
+        for lvl in range(scale):
+            r = torch.rand(k, generator=gen, device=device)
+            bit = 1 << (scale - 1 - lvl)
+            right = ((r >= a) & (r < ab)) | (r >= abc)
+            down = r >= ab
+            src += down.to(torch.int64) * bit
+            dst += right.to(torch.int64) * bit
+        return src, dst
+
+    keys = _dedup_draws_torch(draw, m, n, gen)
+    keys, _, perm = _relabel_torch(n, keys, gen)
+    orig = torch.arange(n, device=device)
+    w = None
+    if weights == "uniform":
+        w = (0.5 + 1.5 * torch.rand(m, generator=gen, device=device)).float()
+    elif weights == "lognormal":
+        w = torch.exp(torch.randn(m, generator=gen, device=device)).float()
+    if degree_order:
+        keys, w, orig = _degree_order_torch(n, keys, w, orig)
+    return _csr_from_keys_torch(n, keys, w, orig)
+
+
+def _degree_order_torch(n: int, keys, w, orig):
+    """Relabel so that vertices are stored by decreasing degree (ties by id);
+    edge weights and original ids travel with the edges and vertices."""
+    import torch
+    dev = keys.device
+    lo = keys // n
+    hi = keys % n
+    deg = torch.bincount(torch.cat([lo, hi]), minlength=n)
+    ids = torch.arange(n, device=dev)
+    order = torch.argsort(-deg * n + ids)                  # decreasing degree, ties by id
+    new_of_old = torch.empty(n, dtype=torch.int64, device=dev)
+    new_of_old[order] = ids
+    a = new_of_old[lo]
+    b = new_of_old[hi]
+    k2 = torch.minimum(a, b) * n + torch.maximum(a, b)
+    o2 = torch.argsort(k2)
+    new_orig = torch.empty_like(orig)
+    new_orig[new_of_old] = orig
+    return k2[o2], (None if w is None else w[o2]), new_orig
+
+
+def device_to_host(d) -> Graph:
+    """Copy a device graph dict back to a host Graph (for the oracle)."""
+    def c(t, dt):
+        return None if t is None else t.detach().cpu().numpy().astype(dt)
+    return Graph(n=d["n"], row_ptr=c(d["row_ptr"], np.int64), col=c(d["col"], np.int32), w=c(d["w"], np.float32),
+                 eid=c(d["eid"], np.int32), orig_id=c(d["orig_id"], np.int32), edge_u=c(d["edge_u"], np.int32),
+                 edge_v=c(d["edge_v"], np.int32), edge_w=c(d["edge_w"], np.float32))

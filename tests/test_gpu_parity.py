@@ -194,6 +194,91 @@ def test_selection_bit_exact_on_oracle_rho(api, mixed, prec, orient, e):
     assert int(_np(n_kept)[0]) == kept_o
 
 
+def _long_row_graph():
+    """Stars of degree 8193 .. 70000 over a random base graph, so that the
+    rows longer than the in-LDS sort take the bucket-partition path."""
+    rng = np.random.default_rng(41)
+    n = 80_000
+    base = G.gnm(n, 60_000, 42)
+    us, vs = [base.edge_u], [base.edge_v]
+    have = set((base.edge_u.astype(np.int64) * n + base.edge_v).tolist())
+    for hub, deg in [(100, 8193), (200, 9000), (300, 20_000), (400, 40_000), (500, 70_000)]:
+        others = rng.permutation(n)
+        others = others[others != hub]
+        picked = []
+        for o in others:
+            a, b = min(hub, int(o)), max(hub, int(o))
+            if a * n + b not in have:
+                have.add(a * n + b)
+                picked.append((a, b))
+                if len(picked) == deg:
+                    break
+        pk = np.array(picked)
+        us.append(pk[:, 0])
+        vs.append(pk[:, 1])
+    return G.from_edges(n, np.concatenate(us), np.concatenate(vs))
+
+
+@pytest.mark.parametrize("pattern", ["random", "ties", "clustered"])
+def test_long_rows_bit_exact(api, pattern):
+    """Selection and fit on rows longer than 8192, FP32 distances, against
+    the oracle.  'clustered' puts every unsampled entry of the 20000-row
+    between two adjacent sample keys of the partition (1024 <= sample size
+    S = 2048 for that degree), so one bucket holds almost the whole row."""
+    announce(f"long rows {pattern}")
+    g = _long_row_graph()
+    rng = np.random.default_rng(43)
+    rho = rng.uniform(0.01, 1.0, g.m).astype(np.float32)
+    if pattern == "ties":
+        rho = np.round(rho, 1).astype(np.float32)
+    elif pattern == "clustered":
+        i = 300
+        beg, end = int(g.row_ptr[i]), int(g.row_ptr[i + 1])
+        d, S = end - beg, 2048
+        sampled = (np.arange(S, dtype=np.int64) * d) // S
+        ids = g.eid[beg:end]
+        rho[ids] = np.float32(1.0 + 30.5e-3)
+        rho[ids[sampled]] = (1.0 + 1e-3 * np.arange(S)).astype(np.float32)
+    dg = _dg(api, g)
+    rt = torch.from_numpy(rho).cuda()
+    rho_ref = rho.astype(np.float64)
+    for orient in (0, 1):
+        for e in (0.3, 0.7):
+            keep, n_kept = api.sparsify(dg, rt, orient, e)
+            keep_o, kept_o = oracle.sparsify(g, rho_ref, orient, e)
+            assert np.array_equal(_np(keep), keep_o), (orient, e)
+            assert int(_np(n_kept)[0]) == kept_o
+        keep, n_kept, e_fit = api.sparsify_fit(dg, rt, orient, 0.3)
+        e_o, keep_o, kept_o = oracle.fit_exponent(g, rho_ref, orient, 0.3)
+        assert e_fit == e_o
+        assert np.array_equal(_np(keep), keep_o)
+        assert int(_np(n_kept)[0]) == kept_o
+
+
+def test_long_rows_distance(api):
+    """Distances on a graph whose long rows are cut into work items.  The
+    graph has edges between vertices of degree one and other near-equal
+    pairs with distances down to 0; in FP32 the difference x_i - x_j of
+    such a pair carries an absolute rounding error on the scale of the
+    vectors, so distances below a tenth of the median are compared against
+    that floor."""
+    announce("long rows distance")
+    g = G.with_weights(_long_row_graph(), None)
+    gw = G.with_weights(g, G.random_weights(g.m, 44))
+    for graph in (g, gw):
+        dg = _dg(api, graph)
+        res = api.relax(dg, 16, 10, seed=2)
+        rho = _np(api.edge_dist(dg, res.x, res.minmax))
+        rho_o = oracle.algebraic_distance(graph, 16, 10, 0.5, seed=2)
+        floor = 0.1 * float(np.median(rho_o))
+        assert rel_stats(rho, rho_o, floor)["max"] <= 1e-5
+        # the edges of the long rows (split into work items) on their own
+        deg = np.diff(graph.row_ptr)
+        long_e = np.nonzero((deg[graph.edge_u] > 4096) | (deg[graph.edge_v] > 4096))[0]
+        assert long_e.size > 140_000
+        assert rel_stats(rho[long_e], rho_o[long_e], floor)["max"] <= 1e-5
+
+
 @pytest.mark.parametrize("orient", [0, 1])
 @pytest.mark.parametrize("target", [0.05, 0.3, 0.55, 0.9, 1.0])
 def test_fit_matches_oracle(api, mixed, orient, target):

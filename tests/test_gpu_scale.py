@@ -1,0 +1,169 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (same graphs, seeds and options, see
+paper_1601_05527_amd.workloads).
+
+  Chung-Lu n = 2^20, 16M edges, FP32: every distance against the FP64
+      oracle (1e-5 relative, or the edge's FP32 conditioning bound where
+      that is larger, gpu_helpers.fp32_tolerance); the fit on the oracle's distances equal to the oracle's
+      bisection bit for bit; the end-to-end kept set near-cut equal.
+  Batch of 512 Chung-Lu graphs, FP32: every graph's kept set equal to the
+      oracle's selection on the batch's distances, every graph's outputs
+      equal to a standalone run bit for bit, distances of sampled graphs
+      against the oracle.
+  R-MAT n = 2^24, 2^28 edges, BF16 storage: sampled test vectors (the
+      oracle relaxes one vector at a time) against the oracle; every kept
+      set equal to the oracle's selection on the same distances; the fitted
+      exponent is the bisection's end point (retention at e meets the
+      target, at e - 2^-40 it does not); distances of sampled edges equal to
+      their definition from the kernel's own rescaled vectors.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_05527_amd import graphs as G
+from paper_1601_05527_amd import workloads as W
+
+from gpu_helpers import announce, check_fp32, near_cut_mismatches, rel_stats
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1601_05527_amd import api as _api
+    return _api
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _log(msg):
+    print(f"[fullsize] {time.strftime('%H:%M:%S')} {msg}", flush=True)
+
+
+@pytest.mark.timeout(900)
+def test_full_chung_lu(api):
+    announce("full size Chung-Lu n=2^20 m=16M FP32")
+    c = W.CHUNG_LU
+    _, g = W.chung_lu_graph("degree")
+    _log(f"graph n={g.n} m={g.m} d_max={g.d_max}")
+    dg = api.DeviceGraph.from_host(g, "cuda", keep_host=False)
+    res = api.relax(dg, c["R"], c["k"], W.OMEGA, c["seed_vec"])
+    rho = api.edge_dist(dg, res.x, res.minmax)
+    rho_g = _np(rho)
+    rho_o, xk_o, _, mm_o = oracle.algebraic_distance(g, c["R"], c["k"], W.OMEGA, seed=c["seed_vec"],
+                                                     want_vectors=True)
+    x0 = oracle.start_vectors(g.n, c["R"], c["seed_vec"], 0, g.orig_id)
+    ratio, st = check_fp32(g, x0, xk_o, mm_o, rho_g, rho_o, c["k"])
+    _log(f"rho: {st}, worst error / bound {ratio:.3f}")
+    assert ratio <= 1.0
+    del xk_o, x0
+    rho32 = rho_o.astype(np.float32)
+    for orient in (0, 1):
+        keep, n_kept, e = api.sparsify_fit(dg, torch.from_numpy(rho32).cuda(), orient, c["target"])
+        e_o, keep_o, kept_o = oracle.fit_exponent(g, rho32.astype(np.float64), orient, c["target"])
+        _log(f"orient {orient}: e {e!r} oracle {e_o!r} kept {int(_np(n_kept)[0])} oracle {kept_o}")
+        assert e == e_o
+        assert np.array_equal(_np(keep), keep_o)
+        assert int(_np(n_kept)[0]) == kept_o
+        # end to end on the kernel's own distances
+        _, _, e_g = api.sparsify_fit(dg, rho, orient, c["target"])
+        assert abs(e_g - e_o) <= 1e-2
+        keep_g, _ = api.sparsify(dg, rho, orient, e_o)
+        bad = near_cut_mismatches(g, rho_o, _np(keep_g), keep_o, orient, e_o, 1e-5)
+        assert not bad, bad[:10]
+
+
+@pytest.mark.timeout(900)
+def test_full_batch(api):
+    announce("full size batch of 512 Chung-Lu graphs FP32")
+    b_ = W.BATCH
+    ds = W.batch_graphs("cuda")
+    dgs = [api.DeviceGraph.from_tensors(d) for d in ds]
+    _log(f"{len(dgs)} graphs, n={sum(d.n for d in dgs)} m={sum(d.m for d in dgs)}")
+    b = api.Batch(dgs, b_["R"], b_["k"], W.OMEGA, seed=b_["seed_vec"], graph_id=b_["graph_id"],
+                  orient=api.AD_LOCAL, e=b_["e"], autotune=True)
+    b.run()
+    rho, keep, n_kept, mm = [_np(t) for t in b.fetch()]
+    _log(f"batch done, rows_per_wave {b.rows_per_wave}")
+    order = np.argsort([d.n for d in dgs])
+    sampled = set(order[np.linspace(0, len(dgs) - 1, 8).astype(int)].tolist())
+    for q, (d, dg) in enumerate(zip(ds, dgs)):
+        e0, e1 = b.edge_off[q], b.edge_off[q + 1]
+        res = api.relax(dg, b_["R"], b_["k"], W.OMEGA, seed=b_["seed_vec"], graph_id=b_["graph_id"] + q,
+                        rows_per_wave=b.rows_per_wave)
+        rho_s = api.edge_dist(dg, res.x, res.minmax)
+        keep_s, nk_s = api.sparsify(dg, rho_s, api.AD_LOCAL, b_["e"])
+        assert np.array_equal(rho[e0:e1], _np(rho_s)), q
+        assert np.array_equal(keep[e0:e1], _np(keep_s)), q
+        assert int(n_kept[q]) == int(_np(nk_s)[0]), q
+        assert np.array_equal(mm[q], _np(res.minmax)), q
+        g = G.device_to_host(d)
+        keep_o, kept_o = oracle.sparsify(g, rho[e0:e1].astype(np.float64), api.AD_LOCAL, b_["e"])
+        assert np.array_equal(keep[e0:e1], keep_o), q
+        assert int(n_kept[q]) == kept_o, q
+        if q in sampled:
+            rho_o, xk_o, _, mm_o = oracle.algebraic_distance(g, b_["R"], b_["k"], W.OMEGA, seed=b_["seed_vec"],
+                                                             graph_id=b_["graph_id"] + q, want_vectors=True)
+            x0 = oracle.start_vectors(g.n, b_["R"], b_["seed_vec"], b_["graph_id"] + q, g.orig_id)
+            ratio, st = check_fp32(g, x0, xk_o, mm_o, rho[e0:e1], rho_o, b_["k"])
+            _log(f"graph {q}: n={g.n} m={g.m} rho {st}, worst error / bound {ratio:.3f}")
+            assert ratio <= 1.0, q
+    b.close()
+
+
+@pytest.mark.timeout(900)
+def test_full_rmat_bf16(api):
+    announce("full size R-MAT n=2^24 m=2^28 BF16 storage")
+    c = W.RMAT
+    R, k = c["R"], c["k"]
+    d = W.rmat_graph("cuda")
+    dg = api.DeviceGraph.from_tensors(d)
+    _log(f"graph n={dg.n} m={dg.m} d_max={dg.d_max}")
+    res = api.relax(dg, R, k, W.OMEGA, c["seed_vec"], store="bf16", fp32_tail=c["fp32_tail"])
+    rho = api.edge_dist(dg, res.x, res.minmax)
+    torch.cuda.synchronize()
+    g = G.device_to_host(d)
+    del d
+    rho_g = _np(rho)
+    x = _np(res.x)
+    mm = _np(res.minmax)
+    live = np.diff(g.row_ptr) > 0
+    lo, hi = mm[:R], mm[R:]
+    # (1) sampled test vectors: the oracle relaxes vector r from the same start values
+    x0 = oracle.start_vectors(g.n, R, c["seed_vec"], 0, g.orig_id)
+    for r in (0, R - 1):
+        xk = oracle.relax_vector(g, np.ascontiguousarray(x0[:, r]), k, W.OMEGA)
+        xh_o, _, _ = oracle.rescale_vector(g, xk)
+        xh_g = (x[:, r].astype(np.float64) - lo[r]) / (hi[r] - lo[r]) - 0.5
+        err = np.abs(xh_g - xh_o)[live]
+        _log(f"vector {r}: rescaled value abs err max {err.max():.3e} p99 {np.quantile(err, 0.99):.3e}")
+        assert err.max() <= 2e-2
+    del x0
+    # (2) sampled distances equal their definition from the kernel's own vectors (FP32 arithmetic)
+    rng = np.random.default_rng(0)
+    es = rng.choice(g.m, size=1 << 20, replace=False)
+    xh = (x.astype(np.float64) - lo) / (hi - lo) - 0.5
+    want = np.sqrt(((xh[g.edge_u[es]] - xh[g.edge_v[es]]) ** 2).sum(axis=1))
+    st = rel_stats(rho_g[es], want, 1e-6)
+    _log(f"distance definition max rel {st['max']:.3e}")
+    assert st["max"] <= 1e-5
+    del xh, x
+    # (3) selection: kept sets equal the oracle's on the same distances; the fit is the bisection's end point
+    rho64 = rho_g.astype(np.float64)
+    for orient in (0, 1):
+        keep, n_kept, e = api.sparsify_fit(dg, rho, orient, c["target"])
+        keep_o, kept_o = oracle.sparsify(g, rho64, orient, e)
+        _log(f"orient {orient}: e {e!r} kept {int(_np(n_kept)[0])} oracle {kept_o}")
+        assert np.array_equal(_np(keep), keep_o)
+        assert int(_np(n_kept)[0]) == kept_o
+        # bisection on [0, 1] for 40 halvings, keeping retention >= target at the upper end
+        assert kept_o / g.m >= c["target"]
+        if e > 0.0:
+            _, kept_lo = oracle.sparsify(g, rho64, orient, e - 2.0 ** -40)
+            assert kept_lo / g.m < c["target"]
