@@ -163,7 +163,7 @@ def run_chung_lu(args, api, torch, dev):
     ws_r = api._workspace(api.relax_workspace_bytes(
         dg, api.relax_opts(R, K, OMEGA, SEED_VEC, rows_per_wave=args.rows_per_wave,
                            hub_degree=args.hub_degree)), dev)
-    ws_s = api._workspace(api.sparsify_workspace_bytes(dg), dev)
+    ws_s = api._workspace(api.sparsify_fit_both_workspace_bytes(dg), dev)
     ws_d = api._workspace(api.edge_dist_workspace_bytes(dg), dev)
     out = api.RelaxResult(x=torch.empty((n, R), dtype=torch.float32, device=dev),
                           minmax=torch.empty(2 * R, dtype=torch.float64, device=dev),
@@ -171,8 +171,7 @@ def run_chung_lu(args, api, torch, dev):
     rho = torch.empty(m, dtype=torch.float32, device=dev)
     keep_l = torch.empty(m, dtype=torch.uint8, device=dev)
     keep_g = torch.empty(m, dtype=torch.uint8, device=dev)
-    nk_l = torch.empty(1, dtype=torch.int64, device=dev)
-    nk_g = torch.empty(1, dtype=torch.int64, device=dev)
+    nk = torch.empty(2, dtype=torch.int64, device=dev)
     fit = {}
 
     def relax_dist():
@@ -182,8 +181,9 @@ def run_chung_lu(args, api, torch, dev):
 
     def step():
         relax_dist()
-        _, _, e_l = api.sparsify_fit(dg, rho, api.AD_LOCAL, TARGET, ws=ws_s, keep=keep_l, n_kept=nk_l)
-        _, _, e_g = api.sparsify_fit(dg, rho, api.AD_GLOBAL, TARGET, ws=ws_s, keep=keep_g, n_kept=nk_g)
+        # LOCAL and GLOBAL fits from one ranking pass
+        _, _, _, (e_l, e_g) = api.sparsify_fit_both(dg, rho, TARGET, ws=ws_s, keep_local=keep_l,
+                                                    keep_global=keep_g, n_kept=nk)
         fit["e_local"], fit["e_global"] = e_l, e_g
 
     if args.calib_copy_mib > 0:
@@ -203,8 +203,7 @@ def run_chung_lu(args, api, torch, dev):
     step_ms, kern = traced(api, timer, step, args.steps)
     rd_ms = timer.run(relax_dist, args.steps)     # relax + distance alone, the bandwidth path
 
-    kept_l = int(nk_l.item())
-    kept_g = int(nk_g.item())
+    kept_l, kept_g = (int(v) for v in nk.tolist())
     weighted = dg.w is not None
     sb = sweep_bytes(n, nnz, R, 4, weighted)
     db = dist_bytes(n, nnz, m, R, 4)
@@ -322,9 +321,10 @@ def run_bf16(args, api, torch, dev):
     log(f"R-MAT generated in {t_gen:.1f}s: n={n} m={m} d_max={dg.d_max}")
     rho = torch.empty(m, dtype=torch.float32, device=dev)
     ws_d = api._workspace(api.edge_dist_workspace_bytes(dg), dev)
-    ws_s = api._workspace(api.sparsify_workspace_bytes(dg), dev)
-    keep = torch.empty(m, dtype=torch.uint8, device=dev)
-    nk = torch.empty(1, dtype=torch.int64, device=dev)
+    ws_s = api._workspace(api.sparsify_fit_both_workspace_bytes(dg), dev)
+    keep_l = torch.empty(m, dtype=torch.uint8, device=dev)
+    keep_g = torch.empty(m, dtype=torch.uint8, device=dev)
+    nk = torch.empty(2, dtype=torch.int64, device=dev)
     fits = {}
 
     def make(store):
@@ -342,9 +342,9 @@ def run_bf16(args, api, torch, dev):
 
         def step():
             relax_dist()
-            for name, o in (("local", api.AD_LOCAL), ("global", api.AD_GLOBAL)):
-                _, _, e = api.sparsify_fit(dg, rho_s, o, TARGET, ws=ws_s, keep=keep, n_kept=nk)
-                fits[(store, name)] = e
+            _, _, _, (e_l, e_g) = api.sparsify_fit_both(dg, rho_s, TARGET, ws=ws_s, keep_local=keep_l,
+                                                        keep_global=keep_g, n_kept=nk)
+            fits[(store, "local")], fits[(store, "global")] = e_l, e_g
         return step, relax_dist, rho_s, ws
 
     timer = Timer(torch)

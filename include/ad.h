@@ -73,7 +73,8 @@ typedef struct {
     int64_t n;                /* |V|                                                   */
     int64_t m;                /* |E|, undirected edges; row_ptr[n] == 2m              */
     const int64_t *row_ptr;   /* [n+1]                                                 */
-    const int32_t *col;       /* [2m] neighbour of each stored entry                   */
+    const int32_t *col;       /* [2m] neighbour of each stored entry, ascending within
+                                 each row (ad_validate_graph checks it)                 */
     const float *w;           /* [2m] w_ij == w_ji; NULL means unit weights            */
     const int32_t *eid;       /* [2m] undirected edge id in [0, m); (i,j) and (j,i)
                                  share it                                              */
@@ -193,6 +194,20 @@ ad_status ad_sparsify_fit(const ad_graph *g, ad_dtype rho_dtype, const void *rho
                           ad_orient orient, double target, uint8_t *keep,
                           int64_t *n_kept, double *e_used_host, void *ws,
                           size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes for ad_sparsify_fit_both (the ranks of both orders). */
+size_t ad_sparsify_fit_both_workspace_size(const ad_graph *g);
+
+/* ad_sparsify_fit for AD_LOCAL and AD_GLOBAL at one target from a single
+ * ranking pass (Algorithm 3's two orders share each row's comparisons: the
+ * LOCAL rank of an entry is #{rho' < rho} + #{rho' == rho, id' < id}, the
+ * GLOBAL rank #{rho' > rho} + #{rho' == rho, id' < id}).  Outputs equal those
+ * of the two single calls: keep_local, keep_global [m]; n_kept: device
+ * int64[2] (local, global); e_used_host: double[2].  SYNCHRONISES `stream`. */
+ad_status ad_sparsify_fit_both(const ad_graph *g, ad_dtype rho_dtype, const void *rho,
+                               double target, uint8_t *keep_local, uint8_t *keep_global,
+                               int64_t *n_kept, double *e_used_host, void *ws,
+                               size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------- adjoint --- */
 

@@ -70,6 +70,8 @@ def _load_lib():
         "ad_sparsify_workspace_size": (S, [G]),
         "ad_sparsify": (st, [G, ctypes.c_int, P, ctypes.c_int, P, P, P, P, S, P]),
         "ad_sparsify_fit": (st, [G, ctypes.c_int, P, ctypes.c_int, f64, P, P, P, P, S, P]),
+        "ad_sparsify_fit_both_workspace_size": (S, [G]),
+        "ad_sparsify_fit_both": (st, [G, ctypes.c_int, P, f64, P, P, P, P, P, S, P]),
         "ad_relax_backward_workspace_size": (S, [G, O]),
         "ad_relax_backward": (st, [G, O, P, P, P, P, P, P, S, P]),
         "ad_edge_to_entries": (st, [G, P, P, P]),
@@ -331,6 +333,34 @@ def sparsify_fit(dg: DeviceGraph, rho: torch.Tensor, orient: int, target: float,
     _check(lib.ad_sparsify_fit(ctypes.byref(g), dt, _ptr(rho), orient, float(target), _ptr(keep),
                                _ptr(n_kept), ctypes.byref(e_used), _ptr(ws), ws.numel(), _stream()))
     return keep, n_kept, e_used.value
+
+
+def sparsify_fit_both_workspace_bytes(dg: DeviceGraph) -> int:
+    g = dg.abi()
+    return int(lib.ad_sparsify_fit_both_workspace_size(ctypes.byref(g)))
+
+
+def sparsify_fit_both(dg: DeviceGraph, rho: torch.Tensor, target: float,
+                      ws: Optional[torch.Tensor] = None, keep_local: Optional[torch.Tensor] = None,
+                      keep_global: Optional[torch.Tensor] = None, n_kept: Optional[torch.Tensor] = None):
+    """LOCAL and GLOBAL fits from one ranking pass (``ad_sparsify_fit_both``);
+    returns (keep_local, keep_global, n_kept[2], (e_local, e_global)).
+    Synchronises the current stream."""
+    dev = rho.device
+    g = dg.abi()
+    if ws is None:
+        ws = _workspace(lib.ad_sparsify_fit_both_workspace_size(ctypes.byref(g)), dev)
+    if keep_local is None:
+        keep_local = torch.empty(dg.m, dtype=torch.uint8, device=dev)
+    if keep_global is None:
+        keep_global = torch.empty(dg.m, dtype=torch.uint8, device=dev)
+    if n_kept is None:
+        n_kept = torch.empty(2, dtype=torch.int64, device=dev)
+    e_used = (ctypes.c_double * 2)(-1.0, -1.0)
+    dt = AD_F64 if rho.dtype == torch.float64 else AD_F32
+    _check(lib.ad_sparsify_fit_both(ctypes.byref(g), dt, _ptr(rho), float(target), _ptr(keep_local),
+                                    _ptr(keep_global), _ptr(n_kept), e_used, _ptr(ws), ws.numel(), _stream()))
+    return keep_local, keep_global, n_kept, (e_used[0], e_used[1])
 
 
 # --------------------------------------------------------------- adjoint ---

@@ -30,6 +30,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 namespace ad {
@@ -115,13 +116,27 @@ __device__ __forceinline__ void dist_span(const int32_t *__restrict__ col, const
     }
 }
 
+// First entry of row `row` in [beg, end) whose column exceeds the row: the
+// upper entries (j > i) are that suffix, columns being ascending in a row.
+__device__ __forceinline__ int64_t upper_start(const int32_t *__restrict__ col, int64_t beg, int64_t end,
+                                               int64_t row) {
+    int64_t lo = beg, hi = end;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)col[mid] > row) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
 // Entries per wave work item of a long row in the distance pass.
 constexpr int64_t DIST_SEG = 4096;
 
-// rho for every edge.  The first hub_blocks workgroups take the rows longer
-// than hub_d, cut into work items of DIST_SEG entries (row h of the hub list,
-// segment s < hub_segs; items past the row's end are skipped), one wave per
-// item.  The other waves walk the launch plan (first row, rows in the tile,
+// rho for every edge, visited from its upper entry (j > i; the suffix of the
+// row after upper_start).  The first hub_blocks workgroups take the rows
+// longer than hub_d, their upper suffix cut into work items of DIST_SEG
+// entries (row h of the hub list, segment s < hub_segs; items past the row's
+// end are skipped), one wave per item.  The other waves walk the launch plan (first row, rows in the tile,
 // log2 rows per wave) as the sweep does, with SPRW / rpw slots per row.
 // Every edge's value is computed by the same lane arithmetic on either path.
 template <typename Tx, typename Tr, int VEC, int U>
@@ -144,7 +159,8 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
         for (unsigned long long it = (unsigned long long)blockIdx.x * (SBLOCK / WAVE) + wave; it < items;
              it += stride) {
             const int64_t row = hub_list[it / hub_segs];
-            const int64_t rb = row_ptr[row], re = row_ptr[row + 1];
+            const int64_t re = row_ptr[row + 1];
+            const int64_t rb = upper_start(col, row_ptr[row], re, row);
             const int64_t b0 = rb + (int64_t)(it % hub_segs) * DIST_SEG;
             if (b0 >= re) continue;                       // uniform across the wave
             const int64_t e0 = min(re, b0 + DIST_SEG);
@@ -174,6 +190,7 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
             beg = row_ptr[row];
             end = row_ptr[row + 1];
             if (end - beg > hub_d) active = false;        // taken by the hub workgroups
+            else beg = upper_start(col, beg, end, row);
         }
         if (!active) beg = end = 0;
         // uniform trip count across the wave: the longest row of the wave
@@ -197,16 +214,20 @@ __device__ __forceinline__ int32_t nbr_id(int64_t p, int32_t j, const int32_t *_
     return col_orig ? col_orig[p] : (orig_id ? orig_id[j] : j);
 }
 
-// (rho_a, id_a) comes before (rho_b, id_b) in the row's order.
-template <typename Tr>
-__device__ __forceinline__ bool before(Tr ra, int32_t ia, Tr rb, int32_t ib, int orient) {
-    if (ra != rb) return orient == AD_LOCAL ? (ra < rb) : (ra > rb);
-    return ia < ib;
-}
+// Where ranks go.  MODE_FIXED marks keep[e] when rank < budget[d];
+// MODE_SIDES stores (d << 32 | rank) at sides[2e + (row > j)].  With `both`
+// the LOCAL rank goes to (budget, keep, sides) and the GLOBAL rank to
+// (budget2, keep2, sides2); otherwise the rank of `orient` goes to the first.
+struct Emit {
+    int mode, orient, both;
+    const int32_t *budget, *budget2;
+    uint8_t *keep, *keep2;
+    unsigned long long *sides, *sides2;
+};
 
-__device__ __forceinline__ void emit(int mode, int64_t row, int32_t j, int32_t e, int64_t d, int64_t rank,
-                                     const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
-                                     unsigned long long *__restrict__ sides) {
+__device__ __forceinline__ void emit_one(int mode, int64_t row, int32_t j, int32_t e, int64_t d, int64_t rank,
+                                         const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
+                                         unsigned long long *__restrict__ sides) {
     if (mode == MODE_FIXED) {
         if (rank < budget[d]) keep[e] = 1;
     } else {
@@ -215,10 +236,37 @@ __device__ __forceinline__ void emit(int mode, int64_t row, int32_t j, int32_t e
     }
 }
 
+// Order-preserving 64-bit key of (rho, orig_id) for the row's order
+// (FP32 distances); the GLOBAL key is the LOCAL key with the rho half
+// inverted, i.e. key ^ KEY_FLIP.
+constexpr unsigned long long KEY_FLIP = 0xffffffff00000000ull;
+__device__ __forceinline__ unsigned long long sort_key(float r, int32_t id, int orient) {
+    uint32_t b = __float_as_uint(r);                 // rho >= 0: bits are monotone
+    if (orient == AD_GLOBAL) b = ~b;
+    return ((unsigned long long)b << 32) | (unsigned long long)(uint32_t)id;
+}
+
+// Rank of an entry in its row of d entries, in both orders of Algorithm 3:
+// LOCAL (rho ascending) and GLOBAL (rho descending), ties by neighbour id
+// ascending in both.  With lt = #{rho' < rho}, eq = #{rho' == rho} (itself
+// included) and eqlt = #{rho' == rho, id' < id}:
+//   rank_local = lt + eqlt,   rank_global = (d - lt - eq) + eqlt.
+__device__ __forceinline__ void emit_ranks(const Emit &em, int64_t row, int32_t j, int32_t e, int64_t d,
+                                           int64_t rank_local, int64_t rank_global) {
+    if (em.both) {
+        emit_one(em.mode, row, j, e, d, rank_local, em.budget, em.keep, em.sides);
+        emit_one(em.mode, row, j, e, d, rank_global, em.budget2, em.keep2, em.sides2);
+    } else {
+        emit_one(em.mode, row, j, e, d, em.orient == AD_LOCAL ? rank_local : rank_global, em.budget, em.keep,
+                 em.sides);
+    }
+}
+
 // Rows of degree <= 64, packed: a wave takes consecutive rows whose entries
 // fit in its 64 lanes (plan entry: first row << 8 | number of rows), one
 // entry per lane; each lane counts the entries of its own row that come
-// before it, broadcast one lane at a time.
+// before it, stepping through its row's lanes (as many steps as the wave's
+// longest row).
 constexpr int RANK_TILE = 64;
 
 template <typename Tr>
@@ -226,9 +274,7 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_packed(
     const long long *__restrict__ plan, const unsigned int *__restrict__ plan_count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const Tr *__restrict__ rho,
-    int orient, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
-    unsigned long long *__restrict__ sides) {
+    const int32_t *__restrict__ col_orig, const Tr *__restrict__ rho, Emit em) {
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned int np = *plan_count;
     const unsigned int nwaves = gridDim.x * (SBLOCK / WAVE);
@@ -236,22 +282,24 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_packed(
         const long long pe = plan[pi];
         const int64_t first = pe >> 8;
         const int nrows = (int)(pe & 0xff);
-        const int64_t rp = lane < nrows ? row_ptr[first + lane] : 0;
         const int64_t e0 = row_ptr[first];
         const int64_t e1 = row_ptr[first + nrows];
         const int cnt = (int)(e1 - e0);
+        // start of row `lane` within the wave's entries (non-decreasing in lane)
+        const int st = lane < nrows ? (int)(row_ptr[first + lane] - e0) : cnt;
         const int64_t e = e0 + lane;
         const bool on = lane < cnt;
         // my row: the last row of the wave that starts at or before my entry
+        // (binary search over the row starts; empty rows share the next start)
         int k = 0;
-        for (int q = 0; q < nrows; ++q) {
-            const int64_t rs = shfl(rp, q);
-            if (rs <= e) k = q;
+        for (int step = WAVE / 2; step >= 1; step >>= 1) {
+            const int cand = k + step;
+            const int sc = shfl(st, cand < WAVE ? cand : WAVE - 1);
+            if (cand < nrows && sc <= lane) k = cand;
         }
-        const int64_t rb = shfl(rp, k);
-        const int64_t rn = shfl(rp, k + 1 < WAVE ? k + 1 : 0);
-        const int64_t re = (k + 1 < nrows) ? rn : e1;
-        const int s0 = (int)(rb - e0), d = (int)(re - rb);
+        const int s0 = shfl(st, k);
+        const int s1 = shfl(st, k + 1 < WAVE ? k + 1 : WAVE - 1);
+        const int d = on ? ((k + 1 < nrows) ? s1 : cnt) - s0 : 0;
         Tr my_rho = (Tr)0;
         int32_t my_id = 0, my_j = 0, my_e = 0;
         if (on) {
@@ -260,13 +308,44 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_packed(
             my_rho = rho[my_e];
             my_id = nbr_id(e, my_j, col_orig, orig_id);
         }
-        int rank = 0;
-        for (int t = 0; t < cnt; ++t) {
-            const Tr r = shfl(my_rho, t);
-            const int32_t id = shfl(my_id, t);
-            if (t >= s0 && t < s0 + d && before(r, id, my_rho, my_id, orient)) ++rank;
+        // every lane walks its own row: as many steps as the wave's longest row
+        int dmax = d;
+        for (int o = WAVE / 2; o >= 1; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, WAVE));
+        if constexpr (sizeof(Tr) == 4) {
+            // FP32: the row orders are those of 64-bit keys; GLOBAL flips the rho half
+            const unsigned long long key = sort_key((float)my_rho, my_id, em.both ? AD_LOCAL : em.orient);
+            const unsigned long long keyg = key ^ KEY_FLIP;
+            int r1 = 0, r2 = 0;
+            if (em.both) {
+                for (int t = 0; t < dmax; ++t) {
+                    const unsigned long long k = shfl(key, min(s0 + t, WAVE - 1));
+                    if (t < d) {
+                        r1 += (k < key) ? 1 : 0;
+                        r2 += ((k ^ KEY_FLIP) < keyg) ? 1 : 0;
+                    }
+                }
+            } else {
+                for (int t = 0; t < dmax; ++t) {
+                    const unsigned long long k = shfl(key, min(s0 + t, WAVE - 1));
+                    if (t < d) r1 += (k < key) ? 1 : 0;
+                }
+                r2 = r1;
+            }
+            if (on) emit_ranks(em, first + k, my_j, my_e, d, r1, r2);
+        } else {
+            int lt = 0, eq = 0, eqlt = 0;
+            for (int t = 0; t < dmax; ++t) {
+                const int src = min(s0 + t, WAVE - 1);
+                const Tr r = shfl(my_rho, src);
+                const int32_t id = shfl(my_id, src);
+                if (t < d) {
+                    lt += (r < my_rho) ? 1 : 0;
+                    eq += (r == my_rho) ? 1 : 0;
+                    eqlt += (r == my_rho && id < my_id) ? 1 : 0;
+                }
+            }
+            if (on) emit_ranks(em, first + k, my_j, my_e, d, lt + eqlt, d - lt - eq + eqlt);
         }
-        if (on) emit(mode, first + k, my_j, my_e, d, rank, budget, keep, sides);
     }
 }
 
@@ -367,27 +446,20 @@ __global__ void k_classify(int64_t n, const int64_t *__restrict__ row_ptr, Class
     }
 }
 
-// Order-preserving 64-bit key of (rho, orig_id) for the row's order.
-__device__ __forceinline__ unsigned long long sort_key(float r, int32_t id, int orient) {
-    uint32_t b = __float_as_uint(r);                 // rho >= 0: bits are monotone
-    if (orient == AD_GLOBAL) b = ~b;
-    return ((unsigned long long)b << 32) | (unsigned long long)(uint32_t)id;
-}
 
 // Listed rows with 32 * KPL < d <= 64 * KPL (FP32 distances): one wave per row,
-// KPL keys per lane; each key's rank counts the smaller keys of the row,
-// broadcast one lane at a time.
+// KPL keys per lane; each key's rank counts the row's smaller keys (and,
+// for both orders, the smaller GLOBAL keys), broadcast one lane at a time.
 template <int KPL>
 __global__ __launch_bounds__(SBLOCK) void k_rank_wave(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const float *__restrict__ rho,
-    int orient, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
-    unsigned long long *__restrict__ sides) {
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, Emit em) {
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned int nr = *count;
     const unsigned int waves = gridDim.x * (SBLOCK / WAVE);
+    const int orient = em.both ? AD_LOCAL : em.orient;
     for (unsigned int h = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); h < nr; h += waves) {
         const int64_t row = list[h];
         const int64_t beg = row_ptr[row];
@@ -407,22 +479,45 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_wave(
                 key[t] = ~0ull;
             }
         }
-        int rank[KPL];
+        int r1[KPL], r2[KPL];
 #pragma unroll
-        for (int t = 0; t < KPL; ++t) rank[t] = 0;
+        for (int t = 0; t < KPL; ++t) r1[t] = r2[t] = 0;
+        if (em.both) {
+            unsigned long long keyg[KPL];
 #pragma unroll
-        for (int ts = 0; ts < KPL; ++ts) {
-            if (ts * WAVE >= d) break;                 // uniform across the wave
-            for (int src = 0; src < WAVE; ++src) {
-                const unsigned long long k = shfl(key[ts], src);
+            for (int t = 0; t < KPL; ++t) keyg[t] = key[t] ^ KEY_FLIP;
 #pragma unroll
-                for (int t = 0; t < KPL; ++t) rank[t] += (k < key[t]) ? 1 : 0;
+            for (int ts = 0; ts < KPL; ++ts) {
+                if (ts * WAVE >= d) break;                 // uniform across the wave
+                const int lim = min(WAVE, d - ts * WAVE);
+                for (int src = 0; src < lim; ++src) {
+                    const unsigned long long k = shfl(key[ts], src);
+                    const unsigned long long kg = k ^ KEY_FLIP;
+#pragma unroll
+                    for (int t = 0; t < KPL; ++t) {
+                        r1[t] += (k < key[t]) ? 1 : 0;
+                        r2[t] += (kg < keyg[t]) ? 1 : 0;
+                    }
+                }
             }
+        } else {
+#pragma unroll
+            for (int ts = 0; ts < KPL; ++ts) {
+                if (ts * WAVE >= d) break;
+                const int lim = min(WAVE, d - ts * WAVE);
+                for (int src = 0; src < lim; ++src) {
+                    const unsigned long long k = shfl(key[ts], src);
+#pragma unroll
+                    for (int t = 0; t < KPL; ++t) r1[t] += (k < key[t]) ? 1 : 0;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < KPL; ++t) r2[t] = r1[t];
         }
 #pragma unroll
         for (int t = 0; t < KPL; ++t) {
             const int q = t * WAVE + lane;
-            if (q < d) emit(mode, row, jj[t], ee[t], d, rank[t], budget, keep, sides);
+            if (q < d) emit_ranks(em, row, jj[t], ee[t], d, r1[t], r2[t]);
         }
     }
 }
@@ -434,12 +529,11 @@ __global__ __launch_bounds__(TB) void k_rank_bitonic(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const float *__restrict__ rho,
-    int orient, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
-    unsigned long long *__restrict__ sides) {
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, Emit em) {
     __shared__ unsigned long long key[P_MAX];
     __shared__ uint16_t idx[P_MAX];
     const unsigned int nr = *count;
+    const int orient = em.both ? AD_LOCAL : em.orient;
     for (unsigned int h = blockIdx.x; h < nr; h += gridDim.x) {
         const int64_t row = list[h];
         const int64_t beg = row_ptr[row];
@@ -475,9 +569,28 @@ __global__ __launch_bounds__(TB) void k_rank_bitonic(
             }
         }
         for (int t = threadIdx.x; t < d; t += TB) {
-            int at = idx[t];
-            int64_t p = beg + at;
-            emit(mode, row, col[p], eid[p], d, t, budget, keep, sides);
+            const int64_t p = beg + idx[t];
+            int64_t rank_global = t;
+            if (em.both) {
+                // sorted LOCAL: the run [a, b) of equal rho holds t; GLOBAL puts the
+                // d - b larger distances first, then the run in the same id order
+                const unsigned long long hb = key[t] >> 32;
+                int a = 0, hi = d;
+                while (a < hi) {
+                    const int mid = (a + hi) >> 1;
+                    if ((key[mid] >> 32) < hb) a = mid + 1;
+                    else hi = mid;
+                }
+                int b = a;
+                hi = d;
+                while (b < hi) {
+                    const int mid = (b + hi) >> 1;
+                    if ((key[mid] >> 32) <= hb) b = mid + 1;
+                    else hi = mid;
+                }
+                rank_global = (int64_t)(d - b) + (t - a);
+            }
+            emit_ranks(em, row, col[p], eid[p], d, t, rank_global);
         }
         __syncthreads();
     }
@@ -490,9 +603,7 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_count(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const Tr *__restrict__ rho,
-    int orient, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
-    unsigned long long *__restrict__ sides) {
+    const int32_t *__restrict__ col_orig, const Tr *__restrict__ rho, Emit em) {
     const unsigned int nr = *count;
     for (unsigned int h = blockIdx.x; h < nr; h += gridDim.x) {
         const int64_t row = list[h];
@@ -503,26 +614,29 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_count(
             const int32_t e = eid[beg + t];
             const Tr r = rho[e];
             const int32_t id = nbr_id(beg + t, j, col_orig, orig_id);
-            int64_t rank = 0;
+            int64_t lt = 0, eq = 0, eqlt = 0;
             for (int64_t u = 0; u < d; ++u) {
                 const int32_t ju = col[beg + u];
                 const Tr ru = rho[eid[beg + u]];
                 const int32_t iu = nbr_id(beg + u, ju, col_orig, orig_id);
-                if (before(ru, iu, r, id, orient)) ++rank;
+                lt += (ru < r) ? 1 : 0;
+                eq += (ru == r) ? 1 : 0;
+                eqlt += (ru == r && iu < id) ? 1 : 0;
             }
-            emit(mode, row, j, e, d, rank, budget, keep, sides);
+            emit_ranks(em, row, j, e, d, lt + eqlt, d - lt - eq + eqlt);
         }
     }
 }
 
 // Rows longer than SORT_CAP (FP32 distances): bucket partition, then one
 // wave per bucket.  A workgroup per row sorts a regular sample of the row's
-// keys in LDS; runs of `sp` consecutive sorted samples delimit the buckets,
+// keys in LDS; runs of consecutive sorted samples delimit the buckets,
 // whose sizes are counted and scanned, and the row's entries are scattered
 // to their bucket's range of a scratch copy (key and offset in the row).  An
 // entry's rank is its bucket's offset plus its rank among the bucket's keys.
 // Keys are unique within a row (the neighbour id breaks ties), so the order
-// the scatter leaves inside a bucket does not matter.
+// the scatter leaves inside a bucket does not matter.  A key with u samples
+// <= it goes to bucket floor(u * B / S): every bucket spans S / B samples.
 constexpr int HUB_TB = 1024;
 constexpr int HUB_SAMPLE = 16384;       // largest sample (128 KiB of keys in LDS)
 constexpr int HUB_BUCKET = 256;         // target bucket size
@@ -606,7 +720,6 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         int S = 1024;
         while (S < HUB_SAMPLE && (int64_t)S * 16 < d) S <<= 1;
         const int B = (int)min((int64_t)(S / HUB_MIN_SP), (d + HUB_BUCKET - 1) / HUB_BUCKET);
-        const int sp = S / B;
         for (int t = threadIdx.x; t < S; t += HUB_TB) {
             const int64_t p = beg + ((int64_t)t * d) / S;
             samp[t] = sort_key(rho[eid[p]], nbr_id(p, col[p], col_orig, orig_id), orient);
@@ -631,7 +744,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         for (int64_t q = threadIdx.x; q < d; q += HUB_TB) {
             const int64_t p = beg + q;
             const unsigned long long k = sort_key(rho[eid[p]], nbr_id(p, col[p], col_orig, orig_id), orient);
-            atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) / sp)], 1u);
+            atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
         }
         __syncthreads();
         if (threadIdx.x == 0) base_s = atomicAdd(hs.nbk, (unsigned int)B);
@@ -653,7 +766,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         for (int64_t q = threadIdx.x; q < d; q += HUB_TB) {
             const int64_t p = beg + q;
             const unsigned long long k = sort_key(rho[eid[p]], nbr_id(p, col[p], col_orig, orig_id), orient);
-            const uint32_t at = atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) / sp)], 1u);
+            const uint32_t at = atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
             hs.key[beg + at] = k;
             hs.pos[beg + at] = (uint32_t)q;
         }
@@ -663,10 +776,10 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
 
 // One wave per bucket: each key's rank among the bucket's keys, counted
 // against all of them broadcast 64 at a time; HUB_KPL * 64 own keys per pass.
+// `em` names one orientation (the one the keys were built for).
 __global__ __launch_bounds__(SBLOCK) void k_hub_rank(
     const int32_t *__restrict__ list, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ eid, int mode, const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
-    unsigned long long *__restrict__ sides, HubScratch hs) {
+    const int32_t *__restrict__ eid, Emit em, HubScratch hs) {
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned int nb = (unsigned int)min((int64_t)(*hs.nbk), hs.cap);
     const unsigned int waves = gridDim.x * (SBLOCK / WAVE);
@@ -700,7 +813,8 @@ __global__ __launch_bounds__(SBLOCK) void k_hub_rank(
                 const uint32_t q = c0 + t * WAVE + lane;
                 if (q < c) {
                     const int64_t p = beg + bp[q];
-                    emit(mode, row, col[p], eid[p], d, (int64_t)off + rank[t], budget, keep, sides);
+                    const int64_t r = (int64_t)off + rank[t];
+                    emit_ranks(em, row, col[p], eid[p], d, r, r);
                 }
             }
         }
@@ -721,7 +835,8 @@ __device__ __forceinline__ void block_add(unsigned long long c, unsigned long lo
     }
 }
 
-constexpr int COUNT_BLOCKS = 512;
+constexpr int COUNT_BLOCKS = 2048;
+constexpr int HIST_BLOCKS = 512;
 
 // Sum of a byte mask into a 64-bit device counter.
 __global__ __launch_bounds__(SBLOCK) void k_count_bytes(int64_t m, const uint8_t *__restrict__ keep,
@@ -748,26 +863,42 @@ __global__ void k_log_table(int64_t count, double *__restrict__ logs) {
 
 // Estimated grid index of each edge's threshold (0: kept at every e): the
 // side (d, r) selects once d^e >= r + 1, i.e. e >= log(r + 1) / log(d).
-__global__ void k_fit_grid(int64_t m, const unsigned long long *__restrict__ sides,
-                           const double *__restrict__ logs, unsigned long long *__restrict__ G) {
+__device__ __forceinline__ unsigned long long side_grid(unsigned long long v, const double *__restrict__ logs) {
+    const unsigned long long d = v >> 32, r = v & 0xffffffffull;
+    if (r == 0 || d < 2) return 0ull;
+    const double gi = ceil(logs[r + 1] / logs[d] * GRID);
+    return gi <= 0.0 ? 0ull : (unsigned long long)gi;
+}
+
+// G[e] = the smaller of its two sides' grid indices, and the histogram of
+// the first radix digit of G (bits 3 * DIGIT .. 4 * DIGIT - 1).
+__global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const unsigned long long *__restrict__ sides,
+                                                    const double *__restrict__ logs,
+                                                    unsigned long long *__restrict__ G,
+                                                    unsigned int *__restrict__ hist) {
+    __shared__ unsigned int h[NBINS];
+    for (int b = threadIdx.x; b < NBINS; b += SBLOCK) h[b] = 0;
+    __syncthreads();
+    int last = -1;
+    unsigned int run = 0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        unsigned long long best = ~0ull;
-        for (int s = 0; s < 2; ++s) {
-            unsigned long long v = sides[2 * e + s];
-            unsigned long long d = v >> 32, r = v & 0xffffffffull;
-            unsigned long long gidx;
-            if (r == 0 || d < 2) {
-                gidx = 0;
-            } else {
-                double t = logs[r + 1] / logs[d];
-                double gi = ceil(t * GRID);
-                gidx = gi <= 0.0 ? 0ull : (unsigned long long)gi;
-            }
-            best = gidx < best ? gidx : best;
+        const unsigned long long a = side_grid(sides[2 * e], logs), b = side_grid(sides[2 * e + 1], logs);
+        const unsigned long long g = a < b ? a : b;
+        G[e] = g;
+        const int bin = (int)((g >> (3 * DIGIT)) & (NBINS - 1));
+        if (bin == last) {
+            ++run;
+        } else {
+            if (run) atomicAdd(&h[last], run);
+            last = bin;
+            run = 1;
         }
-        G[e] = best;
     }
+    if (run) atomicAdd(&h[last], run);
+    __syncthreads();
+    for (int b = threadIdx.x; b < NBINS; b += SBLOCK)
+        if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
 // state[0] = prefix of selected digits, state[1] = rank still to skip (K-1 based).
@@ -860,11 +991,12 @@ struct SelLayout {
     long long *plan;              // packed small-row waves
     unsigned int *tile_waves, *plan_count;
     unsigned long long *sides;    // [2m]
+    unsigned long long *sides2;   // [2m] GLOBAL sides when both orientations are fitted
     unsigned long long *G;        // [m]
     unsigned int *hist;           // [NBINS]
-    unsigned long long *state;    // [2]
-    unsigned long long *counts;   // [2]
-    int32_t *tab_hi, *tab_lo;     // [d_max + 1]
+    unsigned long long *state;    // [4]: two words per fitted orientation
+    unsigned long long *counts;   // [4]: counts at the upper and lower grid point, per orientation
+    int32_t *tabs;                // [4][d_max + 1]: upper and lower budget tables, per orientation
     double *logs;                 // [d_max + 2]
     HubScratch hub;               // rows longer than SORT_CAP (d_max > SORT_CAP only)
 };
@@ -873,7 +1005,7 @@ struct SelLayout {
 // sorts in LDS of 1024/2048/4096/8192 keys, then counting from memory.
 static const int64_t CLASS_LO[NCLASS + 1] = {64, 128, 256, 512, 1024, 2048, 4096, 8192, (int64_t)1 << 62};
 
-static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout *L) {
+static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout *L, bool both = false) {
     Carver c(ws, ws_bytes);
     const int64_t n = std::max<int64_t>(1, g->n), m = std::max<int64_t>(1, g->m);
     const int64_t ntiles = std::max<int64_t>(1, ceil_div(g->n, RANK_TILE));
@@ -892,12 +1024,12 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     l.tile_waves = c.take<unsigned int>(ntiles);
     l.plan_count = c.take<unsigned int>(1);
     l.sides = c.take<unsigned long long>(2 * m);
+    l.sides2 = both ? c.take<unsigned long long>(2 * m) : nullptr;
     l.G = c.take<unsigned long long>(m);
     l.hist = c.take<unsigned int>(NBINS);
-    l.state = c.take<unsigned long long>(2);
-    l.counts = c.take<unsigned long long>(2);
-    l.tab_hi = c.take<int32_t>((size_t)g->d_max + 1);
-    l.tab_lo = c.take<int32_t>((size_t)g->d_max + 1);
+    l.state = c.take<unsigned long long>(4);
+    l.counts = c.take<unsigned long long>(4);
+    l.tabs = c.take<int32_t>(4 * ((size_t)g->d_max + 1));
     l.logs = c.take<double>((size_t)g->d_max + 2);
     l.hub = HubScratch{};
     if (g->d_max > SORT_CAP) {
@@ -915,21 +1047,51 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     return c.ok() ? c.used : 0;
 }
 
+// Budget of a vertex of degree d (Algorithm 3): floor(d^e), at least 1 and
+// at most d.
+static inline int64_t budget_of(int64_t d, double e) {
+    const double p = floor(pow((double)d, e));
+    int64_t c = (int64_t)p;
+    if (c < 1) c = 1;
+    if (c > d) c = d;
+    return c;
+}
+
+// budget_of for d = 0 .. d_max (0 for d = 0).  The budget is a
+// non-decreasing step function of d (pow(d, e) is increasing in d, and for
+// the degrees and exponents at which the budget can change the steps of
+// pow's argument are far above its rounding), so the table is filled step
+// by step: the end of the step at value c is predicted from (c + 1)^(1/e)
+// and confirmed with budget_of itself around the prediction.  Every entry
+// equals budget_of(d, e) under that monotonicity.
 static void budget_table(int32_t d_max, double e, std::vector<int32_t> &t) {
     t.assign((size_t)d_max + 1, 0);
-    for (int32_t d = 1; d <= d_max; ++d) {
-        double p = floor(pow((double)d, e));
-        int64_t c = (int64_t)p;
-        if (c < 1) c = 1;
-        if (c > d) c = d;
-        t[d] = (int32_t)c;
+    int64_t d = 1;
+    while (d <= d_max) {
+        const int64_t c = budget_of(d, e);
+        int64_t last = d;
+        if (c < d && e > 0.0) {
+            const double edge = pow((double)(c + 1), 1.0 / e);
+            int64_t guess = edge >= (double)d_max ? (int64_t)d_max : (int64_t)edge;
+            if (guess < d) guess = d;
+            if (budget_of(guess, e) == c) {
+                last = guess;
+                while (last < d_max && budget_of(last + 1, e) == c) ++last;
+            } else {
+                last = guess - 1;
+                while (last > d && budget_of(last, e) != c) --last;
+            }
+        } else if (c < d) {                 // e == 0: every budget is 1
+            last = d_max;
+        }
+        for (int64_t q = d; q <= last; ++q) t[(size_t)q] = (int32_t)c;
+        d = last + 1;
     }
 }
 
-// Rank every entry of every row and emit per `mode`.
+// Rank every entry of every row and emit per `em`.
 template <typename Tr>
-static ad_status rank_all(const ad_graph *g, const Tr *rho, int orient, int mode, const int32_t *budget,
-                          uint8_t *keep, const SelLayout &L, hipStream_t st) {
+static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, const SelLayout &L, hipStream_t st) {
     const int64_t n = g->n;
     if (n <= 0 || g->m <= 0) return AD_OK;
     TraceScope trace("k_rank", st);
@@ -946,8 +1108,7 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, int orient, int mode
     AD_LAUNCH_CHECK("k_rank_plan");
     const unsigned packed_blocks = (unsigned)std::min<int64_t>(4096, ceil_div(n, SBLOCK / WAVE));
     hipLaunchKernelGGL((k_rank_packed<Tr>), dim3(packed_blocks), dim3(SBLOCK), 0, st, L.plan, L.plan_count,
-                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rho, orient, mode, budget, keep,
-                       L.sides);
+                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rho, em);
     AD_LAUNCH_CHECK("k_rank_packed");
     if (g->d_max <= 64) return AD_OK;
 
@@ -959,10 +1120,9 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, int orient, int mode
     const unsigned grid = (unsigned)std::min<int64_t>(2048, n);
     const int32_t *lst[NCLASS];
     for (int k = 0; k < NCLASS; ++k) lst[k] = L.lists + L.cb.off[k];
-#define AD_RANK_ARGS g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rho, orient, mode, budget, keep, L.sides
     if (sizeof(Tr) == 4) {
         const float *rf = (const float *)rho;
-#define AD_RANK_ARGS_F g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, orient, mode, budget, keep, L.sides
+#define AD_RANK_ARGS_F g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, em
         if (g->d_max > 64)
             hipLaunchKernelGGL((k_rank_wave<2>), dim3(grid), dim3(SBLOCK), 0, st, lst[0], &L.cnt[0], AD_RANK_ARGS_F);
         if (g->d_max > 128)
@@ -985,28 +1145,53 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, int orient, int mode
         AD_LAUNCH_CHECK("k_rank_bitonic");
 #undef AD_RANK_ARGS_F
         if (g->d_max > SORT_CAP) {
-            s = fill_i32((int32_t *)L.hub.nbk, 0, 1, st);
-            if (s != AD_OK) return s;
-            hipLaunchKernelGGL(k_hub_partition, dim3(512), dim3(HUB_TB), 0, st, lst[7], &L.cnt[7], g->row_ptr,
-                               g->col, g->eid, g->orig_id, g->col_orig, rf, orient, L.hub);
-            AD_LAUNCH_CHECK("k_hub_partition");
-            hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, st, lst[7], g->row_ptr, g->col, g->eid,
-                               mode, budget, keep, L.sides, L.hub);
-            AD_LAUNCH_CHECK("k_hub_rank");
+            // the bucket keys carry one orientation: one partition per orientation asked for
+            for (int pass = 0; pass < (em.both ? 2 : 1); ++pass) {
+                Emit one = em;
+                one.both = 0;
+                if (em.both) {
+                    one.orient = pass == 0 ? AD_LOCAL : AD_GLOBAL;
+                    if (pass == 1) {
+                        one.budget = em.budget2;
+                        one.keep = em.keep2;
+                        one.sides = em.sides2;
+                    }
+                }
+                s = fill_i32((int32_t *)L.hub.nbk, 0, 1, st);
+                if (s != AD_OK) return s;
+                hipLaunchKernelGGL(k_hub_partition, dim3(512), dim3(HUB_TB), 0, st, lst[7], &L.cnt[7], g->row_ptr,
+                                   g->col, g->eid, g->orig_id, g->col_orig, rf, one.orient, L.hub);
+                AD_LAUNCH_CHECK("k_hub_partition");
+                hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, st, lst[7], g->row_ptr, g->col, g->eid,
+                                   one, L.hub);
+                AD_LAUNCH_CHECK("k_hub_rank");
+            }
         }
     } else {
         for (int k = 0; k < NCLASS; ++k) {
             if (g->d_max <= CLASS_LO[k]) break;
-            hipLaunchKernelGGL((k_rank_count<Tr>), dim3(grid), dim3(SBLOCK), 0, st, lst[k], &L.cnt[k], AD_RANK_ARGS);
+            hipLaunchKernelGGL((k_rank_count<Tr>), dim3(grid), dim3(SBLOCK), 0, st, lst[k], &L.cnt[k],
+                               g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rho, em);
             AD_LAUNCH_CHECK("k_rank_count");
         }
     }
-#undef AD_RANK_ARGS
     return AD_OK;
 }
 
+static Emit emit_single(int mode, int orient, const int32_t *budget, uint8_t *keep, unsigned long long *sides) {
+    Emit em{};
+    em.mode = mode;
+    em.orient = orient;
+    em.both = 0;
+    em.budget = budget;
+    em.keep = keep;
+    em.sides = sides;
+    return em;
+}
+
 static ad_status check_sel_args(const ad_graph *g, ad_dtype rho_dtype, const void *rho, ad_orient orient,
-                                uint8_t *keep, int64_t *n_kept, void *ws, size_t ws_bytes, SelLayout *L) {
+                                uint8_t *keep, int64_t *n_kept, void *ws, size_t ws_bytes, SelLayout *L,
+                                bool both = false) {
     ad_status s = check_graph_args(g);
     if (s != AD_OK) return s;
     if (rho_dtype != AD_F32 && rho_dtype != AD_F64) return fail(AD_ERR_INVALID_ARG, "rho must be F32 or F64");
@@ -1016,7 +1201,7 @@ static ad_status check_sel_args(const ad_graph *g, ad_dtype rho_dtype, const voi
     if (g->m > 0 && g->d_max <= 0) return fail(AD_ERR_INVALID_ARG, "d_max must be set for selection");
     if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
-    if (sel_layout(g, ws, ws_bytes, L) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    if (sel_layout(g, ws, ws_bytes, L, both) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
     return AD_OK;
 }
 
@@ -1088,8 +1273,9 @@ ad_status sparsify_fixed(const ad_graph *g, ad_dtype rho_dtype, const void *rho,
     if (g->m <= 0) return AD_OK;
     ad_status s = fill_u8(keep, 0, g->m, stream);
     if (s != AD_OK) return s;
-    if (rho_dtype == AD_F32) return rank_all<float>(g, (const float *)rho, orient, MODE_FIXED, budget, keep, L, stream);
-    return rank_all<double>(g, (const double *)rho, orient, MODE_FIXED, budget, keep, L, stream);
+    const Emit em = emit_single(MODE_FIXED, orient, budget, keep, nullptr);
+    if (rho_dtype == AD_F32) return rank_all<float>(g, (const float *)rho, em, L, stream);
+    return rank_all<double>(g, (const double *)rho, em, L, stream);
 }
 
 size_t sparsify_workspace(const ad_graph *g) { return sel_layout(g, nullptr, 0, nullptr); }
@@ -1143,10 +1329,11 @@ extern "C" ad_status ad_sparsify(const ad_graph *g, ad_dtype rho_dtype, const vo
     if (g->m > 0) {
         s = fill_u8(keep, 0, g->m, stream);
         if (s != AD_OK) return s;
+        const Emit em = emit_single(MODE_FIXED, orient, budget, keep, nullptr);
         if (rho_dtype == AD_F32)
-            s = rank_all<float>(g, (const float *)rho, orient, MODE_FIXED, budget, keep, L, stream);
+            s = rank_all<float>(g, (const float *)rho, em, L, stream);
         else
-            s = rank_all<double>(g, (const double *)rho, orient, MODE_FIXED, budget, keep, L, stream);
+            s = rank_all<double>(g, (const double *)rho, em, L, stream);
         if (s != AD_OK) return s;
         hipLaunchKernelGGL(k_count_bytes, dim3((unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(g->m, SBLOCK))),
                            dim3(SBLOCK), 0, stream, g->m, keep,
@@ -1158,6 +1345,171 @@ extern "C" ad_status ad_sparsify(const ad_graph *g, ad_dtype rho_dtype, const vo
     return AD_OK;
 }
 
+// Fewest kept edges meeting the target, in the bisection's own test
+// (kept / m >= target).
+static int64_t fit_count_target(int64_t m, double target) {
+    int64_t K = (int64_t)ceil(target * (double)m);
+    if (K < 1) K = 1;
+    if (K > m) K = m;
+    while (K > 1 && (double)(K - 1) / (double)m >= target) --K;
+    while (K < m && (double)K / (double)m < target) ++K;
+    return K;
+}
+
+namespace ad {
+
+// Pinned host staging for the budget tables (grown on demand, kept for the
+// life of the process; one fit at a time uses it).
+static std::mutex g_stage_mu;
+static int32_t *g_stage = nullptr;
+static size_t g_stage_cap = 0;
+
+static ad_status stage_reserve(size_t count) {
+    if (count <= g_stage_cap) return AD_OK;
+    if (g_stage) AD_HIP(hipHostFree(g_stage));
+    g_stage = nullptr;
+    g_stage_cap = 0;
+    AD_HIP(hipHostMalloc((void **)&g_stage, count * sizeof(int32_t), hipHostMallocDefault));
+    g_stage_cap = count;
+    return AD_OK;
+}
+
+// From ranked sides (one array per fitted orientation, nfit <= 2): the
+// per-edge threshold grid index, the radix select of the K-th smallest, and
+// the exact confirmation with budget tables (count at the grid point >= K,
+// count one grid step lower < K).  The orientations share each read-back:
+// one after the selects, one per confirmation round.  Writes keep[o], the
+// device counts n_kept[o] and the exponents.  L.logs must hold the log table.
+static ad_status fit_from_sides(const ad_graph *g, const SelLayout &L, int nfit,
+                                unsigned long long *const *sides, int64_t K, uint8_t *const *keep,
+                                int64_t *n_kept, double *e_used_host, hipStream_t stream) {
+    const int64_t m = g->m;
+    const size_t tl = (size_t)g->d_max + 1;
+    ad_status s;
+    const unsigned hist_blocks = (unsigned)std::min<int64_t>(HIST_BLOCKS, ceil_div(m, SBLOCK));
+    const unsigned count_blocks = (unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, SBLOCK));
+    for (int o = 0; o < nfit; ++o) {
+        unsigned long long *state = L.state + 2 * o;
+        hipLaunchKernelGGL(k_select_init, dim3(1), dim3(1), 0, stream, state, (unsigned long long)K);
+        AD_LAUNCH_CHECK("k_select_init");
+        s = fill_i32((int32_t *)L.hist, 0, NBINS, stream);
+        if (s != AD_OK) return s;
+        hipLaunchKernelGGL(k_fit_grid, dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, sides[o], L.logs, L.G, L.hist);
+        AD_LAUNCH_CHECK("k_fit_grid");
+        hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(SBLOCK), 0, stream, L.hist, state);
+        AD_LAUNCH_CHECK("k_radix_pick");
+        for (int pass = 1; pass < 4; ++pass) {
+            const int shift = (3 - pass) * DIGIT;
+            s = fill_i32((int32_t *)L.hist, 0, NBINS, stream);
+            if (s != AD_OK) return s;
+            hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, L.G, shift, pass, state,
+                               L.hist);
+            AD_LAUNCH_CHECK("k_radix_hist");
+            hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(SBLOCK), 0, stream, L.hist, state);
+            AD_LAUNCH_CHECK("k_radix_pick");
+        }
+    }
+    unsigned long long st_host[4] = {0, 0, 0, 0};
+    AD_HIP(hipMemcpyAsync(st_host, L.state, sizeof(st_host), hipMemcpyDeviceToHost, stream));
+    AD_HIP(hipStreamSynchronize(stream));
+    const unsigned long long GMAX = 1ull << 40;
+    long long g_try[2];
+    bool done[2] = {false, false};
+    for (int o = 0; o < nfit; ++o) g_try[o] = (long long)std::min(st_host[2 * o], GMAX);
+
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    s = stage_reserve(4 * tl);
+    if (s != AD_OK) return s;
+    std::vector<int32_t> t;
+    for (int attempt = 0; attempt < 64; ++attempt) {
+        // budget tables at the candidate grid point and one step below
+        for (int o = 0; o < nfit; ++o) {
+            if (done[o]) continue;
+            budget_table(g->d_max, (double)g_try[o] / GRID, t);
+            std::copy(t.begin(), t.end(), g_stage + (2 * o) * tl);
+            if (g_try[o] > 0) budget_table(g->d_max, (double)(g_try[o] - 1) / GRID, t);
+            std::copy(t.begin(), t.end(), g_stage + (2 * o + 1) * tl);
+        }
+        AD_HIP(hipMemcpyAsync(L.tabs, g_stage, 2 * nfit * tl * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        s = fill_u64(L.counts, 0, 4, stream);
+        if (s != AD_OK) return s;
+        for (int o = 0; o < nfit; ++o) {
+            if (done[o]) continue;
+            hipLaunchKernelGGL(k_fit_count, dim3(count_blocks), dim3(SBLOCK), 0, stream, m, sides[o],
+                               L.tabs + (2 * o) * tl, L.tabs + (2 * o + 1) * tl, g_try[o] > 0 ? 1 : 0, keep[o],
+                               L.counts + 2 * o);
+            AD_LAUNCH_CHECK("k_fit_count");
+        }
+        unsigned long long hc[4];
+        AD_HIP(hipMemcpyAsync(hc, L.counts, sizeof(hc), hipMemcpyDeviceToHost, stream));
+        AD_HIP(hipStreamSynchronize(stream));
+        bool all = true;
+        for (int o = 0; o < nfit; ++o) {
+            if (done[o]) continue;
+            const bool hi_ok = (int64_t)hc[2 * o] >= K;
+            const bool lo_ok = g_try[o] == 0 || (int64_t)hc[2 * o + 1] < K;
+            if (hi_ok && lo_ok) {
+                hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, stream, L.counts + 2 * o, n_kept + o);
+                AD_LAUNCH_CHECK("k_store_count");
+                e_used_host[o] = (double)g_try[o] / GRID;
+                done[o] = true;
+                continue;
+            }
+            all = false;
+            if (!hi_ok) {
+                if (g_try[o] >= (long long)GMAX) return fail(AD_ERR_INTERNAL, "retention fit found no grid point");
+                ++g_try[o];
+            } else {
+                --g_try[o];
+            }
+        }
+        if (all) return AD_OK;
+    }
+    return fail(AD_ERR_INTERNAL, "retention fit did not settle on a grid point");
+}
+
+// Both halves of the fitted sparsify: rank (one or both orientations) into
+// sides, then the fits.
+static ad_status sparsify_fit_impl(const ad_graph *g, ad_dtype rho_dtype, const void *rho, int orient, bool both,
+                                   double target, uint8_t *keep, uint8_t *keep2, int64_t *n_kept,
+                                   double *e_used_host, const SelLayout &L, hipStream_t stream) {
+    const int64_t m = g->m;
+    const int nfit = both ? 2 : 1;
+    ad_status s;
+    if (m == 0) {
+        s = fill_u64(L.counts, 0, 4, stream);
+        if (s != AD_OK) return s;
+        for (int o = 0; o < nfit; ++o) {
+            hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, stream, L.counts, n_kept + o);
+            AD_LAUNCH_CHECK("k_store_count");
+            e_used_host[o] = 0.0;
+        }
+        AD_HIP(hipStreamSynchronize(stream));
+        return AD_OK;
+    }
+    const int64_t K = fit_count_target(m, target);
+    Emit em = emit_single(MODE_SIDES, orient, nullptr, nullptr, L.sides);
+    if (both) {
+        em.orient = AD_LOCAL;
+        em.both = 1;
+        em.sides2 = L.sides2;
+    }
+    if (rho_dtype == AD_F32)
+        s = rank_all<float>(g, (const float *)rho, em, L, stream);
+    else
+        s = rank_all<double>(g, (const double *)rho, em, L, stream);
+    if (s != AD_OK) return s;
+    TraceScope trace_fit("k_fit_select", stream);
+    hipLaunchKernelGGL(k_log_table, dim3(grid_for((int64_t)g->d_max + 2, SBLOCK)), dim3(SBLOCK), 0, stream,
+                       (int64_t)g->d_max + 2, L.logs);
+    AD_LAUNCH_CHECK("k_log_table");
+    unsigned long long *sd[2] = {L.sides, L.sides2};
+    uint8_t *kp[2] = {keep, keep2};
+    return fit_from_sides(g, L, nfit, sd, K, kp, n_kept, e_used_host, stream);
+}
+
+}  // namespace ad
+
 extern "C" ad_status ad_sparsify_fit(const ad_graph *g, ad_dtype rho_dtype, const void *rho, ad_orient orient,
                                      double target, uint8_t *keep, int64_t *n_kept, double *e_used_host,
                                      void *ws, size_t ws_bytes, hipStream_t stream) {
@@ -1166,88 +1518,24 @@ extern "C" ad_status ad_sparsify_fit(const ad_graph *g, ad_dtype rho_dtype, cons
     if (s != AD_OK) return s;
     if (!(target > 0.0 && target <= 1.0)) return fail(AD_ERR_INVALID_ARG, "target must be in (0, 1]");
     if (!e_used_host) return fail(AD_ERR_INVALID_ARG, "e_used_host is NULL");
-    const int64_t m = g->m;
-    s = fill_u64(L.counts, 0, 2, stream);
-    if (s != AD_OK) return s;
-    if (m == 0) {
-        hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, stream, L.counts, n_kept);
-        AD_LAUNCH_CHECK("k_store_count");
-        AD_HIP(hipStreamSynchronize(stream));
-        *e_used_host = 0.0;
-        return AD_OK;
-    }
-    // Fewest kept edges meeting the target, in the bisection's own test.
-    int64_t K = (int64_t)ceil(target * (double)m);
-    if (K < 1) K = 1;
-    if (K > m) K = m;
-    while (K > 1 && (double)(K - 1) / (double)m >= target) --K;
-    while (K < m && (double)K / (double)m < target) ++K;
+    return sparsify_fit_impl(g, rho_dtype, rho, orient, false, target, keep, nullptr, n_kept, e_used_host, L,
+                             stream);
+}
 
-    if (rho_dtype == AD_F32)
-        s = rank_all<float>(g, (const float *)rho, orient, MODE_SIDES, nullptr, keep, L, stream);
-    else
-        s = rank_all<double>(g, (const double *)rho, orient, MODE_SIDES, nullptr, keep, L, stream);
-    if (s != AD_OK) return s;
-    TraceScope trace_fit("k_fit_select", stream);
-    hipLaunchKernelGGL(k_log_table, dim3(grid_for((int64_t)g->d_max + 2, SBLOCK)), dim3(SBLOCK), 0, stream,
-                       (int64_t)g->d_max + 2, L.logs);
-    AD_LAUNCH_CHECK("k_log_table");
-    hipLaunchKernelGGL(k_fit_grid, dim3(grid_for(m, SBLOCK)), dim3(SBLOCK), 0, stream, m, L.sides, L.logs, L.G);
-    AD_LAUNCH_CHECK("k_fit_grid");
-    hipLaunchKernelGGL(k_select_init, dim3(1), dim3(1), 0, stream, L.state, (unsigned long long)K);
-    AD_LAUNCH_CHECK("k_select_init");
-    for (int pass = 0; pass < 4; ++pass) {
-        const int shift = (3 - pass) * DIGIT;
-        s = fill_i32((int32_t *)L.hist, 0, NBINS, stream);
-        if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, SBLOCK))),
-                           dim3(SBLOCK), 0, stream, m, L.G, shift, pass,
-                           L.state, L.hist);
-        AD_LAUNCH_CHECK("k_radix_hist");
-        hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(SBLOCK), 0, stream, L.hist, L.state);
-        AD_LAUNCH_CHECK("k_radix_pick");
-    }
-    unsigned long long gstar = 0;
-    AD_HIP(hipMemcpyAsync(&gstar, L.state, sizeof(gstar), hipMemcpyDeviceToHost, stream));
-    AD_HIP(hipStreamSynchronize(stream));
-    const unsigned long long GMAX = 1ull << 40;
-    if (gstar > GMAX) gstar = GMAX;
+extern "C" size_t ad_sparsify_fit_both_workspace_size(const ad_graph *g) {
+    if (check_graph_args(g) != AD_OK) return 0;
+    return sel_layout(g, nullptr, 0, nullptr, true);
+}
 
-    // Confirm with exact budget tables: count(g) >= K and count(g - 1) < K.
-    std::vector<int32_t> th, tl;
-    unsigned long long hc[2];
-    long long g_try = (long long)gstar;
-    for (int attempt = 0; attempt < 64; ++attempt) {
-        const double e_hi = (double)g_try / GRID;
-        const bool use_lo = g_try > 0;
-        budget_table(g->d_max, e_hi, th);
-        if (use_lo) budget_table(g->d_max, (double)(g_try - 1) / GRID, tl);
-        else tl = th;
-        AD_HIP(hipMemcpyAsync(L.tab_hi, th.data(), th.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        AD_HIP(hipMemcpyAsync(L.tab_lo, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        s = fill_u64(L.counts, 0, 2, stream);
-        if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_fit_count, dim3((unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, SBLOCK))),
-                           dim3(SBLOCK), 0, stream, m, L.sides, L.tab_hi,
-                           L.tab_lo, use_lo ? 1 : 0, keep, L.counts);
-        AD_LAUNCH_CHECK("k_fit_count");
-        AD_HIP(hipMemcpyAsync(hc, L.counts, sizeof(hc), hipMemcpyDeviceToHost, stream));
-        AD_HIP(hipStreamSynchronize(stream));
-        const bool hi_ok = (int64_t)hc[0] >= K;
-        const bool lo_ok = !use_lo || (int64_t)hc[1] < K;
-        if (hi_ok && lo_ok) {
-            hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, stream, L.counts, n_kept);
-            AD_LAUNCH_CHECK("k_store_count");
-            AD_HIP(hipStreamSynchronize(stream));
-            *e_used_host = e_hi;
-            return AD_OK;
-        }
-        if (!hi_ok) {
-            if (g_try >= (long long)GMAX) break;
-            ++g_try;
-        } else {
-            --g_try;
-        }
-    }
-    return fail(AD_ERR_INTERNAL, "retention fit did not settle on a grid point");
+extern "C" ad_status ad_sparsify_fit_both(const ad_graph *g, ad_dtype rho_dtype, const void *rho, double target,
+                                          uint8_t *keep_local, uint8_t *keep_global, int64_t *n_kept,
+                                          double *e_used_host, void *ws, size_t ws_bytes, hipStream_t stream) {
+    SelLayout L;
+    ad_status s = check_sel_args(g, rho_dtype, rho, AD_LOCAL, keep_local, n_kept, ws, ws_bytes, &L, true);
+    if (s != AD_OK) return s;
+    if (g->m > 0 && !keep_global) return fail(AD_ERR_INVALID_ARG, "keep_global is NULL");
+    if (!(target > 0.0 && target <= 1.0)) return fail(AD_ERR_INVALID_ARG, "target must be in (0, 1]");
+    if (!e_used_host) return fail(AD_ERR_INVALID_ARG, "e_used_host is NULL");
+    return sparsify_fit_impl(g, rho_dtype, rho, AD_LOCAL, true, target, keep_local, keep_global, n_kept,
+                             e_used_host, L, stream);
 }

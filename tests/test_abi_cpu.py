@@ -120,3 +120,24 @@ def test_workspace_sizes_are_positive():
     assert L.ad_relax_num_checkpoints(ctypes.byref(api.relax_opts(16, 20, ckpt_every=5))) == 4
     assert L.ad_relax_num_checkpoints(ctypes.byref(api.relax_opts(16, 21, ckpt_every=5))) == 5
     assert L.ad_relax_num_checkpoints(ctypes.byref(api.relax_opts(16, 20))) == 0
+
+
+def test_budget_table_matches_oracle_budget_everywhere():
+    """The library fills budget tables step by step; every entry must equal
+    the oracle's per-degree floor(d^e) (clamped to [1, d]), including
+    exponents at which d^e hits integers (perfect squares, cubes, ...) and
+    the fit's grid points k / 2^40."""
+    import ctypes
+    import oracle
+    from paper_1601_05527_amd import api
+    lib = oracle._load()
+    lib.orc_budget.restype = ctypes.c_int64
+    rng = np.random.default_rng(5)
+    grid = [float(k) / 2.0 ** 40 for k in rng.integers(0, 1 << 40, 40)]
+    exps = [0.0, 1e-12, 0.05, 0.1, 0.25, 1.0 / 3.0, 0.5, 2.0 / 3.0, 0.75, 0.9, 0.999999, 1.0] + grid
+    exps += list(rng.uniform(0, 1, 20))
+    for d_max in (1, 2, 7, 100, 7147, 70004):
+        for e in exps:
+            t = api.budget_table(d_max, e)
+            want = np.array([0] + [lib.orc_budget(d, e) for d in range(1, d_max + 1)], dtype=np.int64)
+            assert np.array_equal(t.astype(np.int64), want), (d_max, e)

@@ -255,6 +255,35 @@ def test_long_rows_bit_exact(api, pattern):
         assert int(_np(n_kept)[0]) == kept_o
 
 
+@pytest.mark.parametrize("which", ["mixed_f32", "mixed_f64", "long_f32", "long_ties_f32", "mixed_ties_f32"])
+@pytest.mark.parametrize("target", [0.1, 0.3, 0.75])
+def test_fit_both_equals_single_fits(api, mixed, which, target):
+    """One ranking pass for both orders gives the same masks, counts and
+    exponents as the two single fits, and as the oracle's bisections."""
+    announce(f"fit both {which} target={target}")
+    if which.startswith("mixed"):
+        g, rho = mixed
+        rho = rho.astype(np.float64 if which.endswith("f64") else np.float32)
+    else:
+        g = _long_row_graph()
+        rho = np.random.default_rng(45).uniform(0.01, 1.0, g.m).astype(np.float32)
+    if "ties" in which:
+        rho = rho.copy()
+        rho[::2] = np.round(rho[::2], 2)
+    dg = _dg(api, g)
+    rt = torch.from_numpy(rho).cuda()
+    kl, kg, nk, (el, eg) = api.sparsify_fit_both(dg, rt, target)
+    nk = _np(nk)
+    for o, (keep, e) in enumerate([(kl, el), (kg, eg)]):
+        keep1, n1, e1 = api.sparsify_fit(dg, rt, o, target)
+        assert e == e1
+        assert np.array_equal(_np(keep), _np(keep1))
+        assert int(nk[o]) == int(_np(n1)[0])
+        e_o, keep_o, kept_o = oracle.fit_exponent(g, rho.astype(np.float64), o, target)
+        assert e == e_o
+        assert np.array_equal(_np(keep), keep_o)
+
+
 def test_long_rows_distance(api):
     """Distances on a graph whose long rows are cut into work items.  The
     graph has edges between vertices of degree one and other near-equal

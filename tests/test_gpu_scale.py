@@ -64,16 +64,19 @@ def test_full_chung_lu(api):
     assert ratio <= 1.0
     del xk_o, x0
     rho32 = rho_o.astype(np.float32)
-    for orient in (0, 1):
-        keep, n_kept, e = api.sparsify_fit(dg, torch.from_numpy(rho32).cuda(), orient, c["target"])
+    # both orders from one ranking pass, as the benchmark step runs them
+    kl, kg, nk, es = api.sparsify_fit_both(dg, torch.from_numpy(rho32).cuda(), c["target"])
+    _, _, _, es_g = api.sparsify_fit_both(dg, rho, c["target"])
+    nk = _np(nk)
+    for orient, keep in ((0, kl), (1, kg)):
+        e = es[orient]
         e_o, keep_o, kept_o = oracle.fit_exponent(g, rho32.astype(np.float64), orient, c["target"])
-        _log(f"orient {orient}: e {e!r} oracle {e_o!r} kept {int(_np(n_kept)[0])} oracle {kept_o}")
+        _log(f"orient {orient}: e {e!r} oracle {e_o!r} kept {int(nk[orient])} oracle {kept_o}")
         assert e == e_o
         assert np.array_equal(_np(keep), keep_o)
-        assert int(_np(n_kept)[0]) == kept_o
+        assert int(nk[orient]) == kept_o
         # end to end on the kernel's own distances
-        _, _, e_g = api.sparsify_fit(dg, rho, orient, c["target"])
-        assert abs(e_g - e_o) <= 1e-2
+        assert abs(es_g[orient] - e_o) <= 1e-2
         keep_g, _ = api.sparsify(dg, rho, orient, e_o)
         bad = near_cut_mismatches(g, rho_o, _np(keep_g), keep_o, orient, e_o, 1e-5)
         assert not bad, bad[:10]
@@ -156,12 +159,14 @@ def test_full_rmat_bf16(api):
     del xh, x
     # (3) selection: kept sets equal the oracle's on the same distances; the fit is the bisection's end point
     rho64 = rho_g.astype(np.float64)
-    for orient in (0, 1):
-        keep, n_kept, e = api.sparsify_fit(dg, rho, orient, c["target"])
+    kl, kg, nk, es = api.sparsify_fit_both(dg, rho, c["target"])
+    nk = _np(nk)
+    for orient, keep in ((0, kl), (1, kg)):
+        e = es[orient]
         keep_o, kept_o = oracle.sparsify(g, rho64, orient, e)
-        _log(f"orient {orient}: e {e!r} kept {int(_np(n_kept)[0])} oracle {kept_o}")
+        _log(f"orient {orient}: e {e!r} kept {int(nk[orient])} oracle {kept_o}")
         assert np.array_equal(_np(keep), keep_o)
-        assert int(_np(n_kept)[0]) == kept_o
+        assert int(nk[orient]) == kept_o
         # bisection on [0, 1] for 40 halvings, keeping retention >= target at the upper end
         assert kept_o / g.m >= c["target"]
         if e > 0.0:
