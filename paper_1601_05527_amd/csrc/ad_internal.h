@@ -251,7 +251,21 @@ struct SweepShape {
     int vec, C, SPRW;     // values per lane, lanes per neighbour row, slots per wave
     int rpw_fixed;        // 0: rows per wave chosen per tile
     int64_t hub_d;        // rows longer than this get a workgroup each
+    int upper_only = 0;   // rows per wave from the upper entries (j > i) only
 };
+
+// First entry of row `row` in [beg, end) whose column exceeds the row: the
+// upper entries (j > i) are that suffix, columns being ascending in a row.
+__device__ __forceinline__ int64_t upper_start(const int32_t *__restrict__ col, int64_t beg, int64_t end,
+                                               int64_t row) {
+    int64_t lo = beg, hi = end;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)col[mid] > row) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
 SweepShape sweep_shape(int R, size_t in_bytes, int rpw_req, int64_t hub_req);
 
 struct SweepPlan {

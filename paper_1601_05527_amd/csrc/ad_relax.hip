@@ -372,12 +372,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
 }
 
 // Launch plan of the sweep: rows are taken in tiles of PLAN_TILE; a tile's
-// rows per wave follow its longest non-hub row, so that one round of
+// rows per wave follow its longest non-hub row (or, with upper_only, its
+// longest upper suffix), so that one round of
 // SWEEP_UNROLL gathers per slot covers it (short rows share a wave, long
 // rows get more slots).  A fixed rows-per-wave request overrides this.
-__global__ void k_plan_tiles(int64_t n, const int64_t *__restrict__ row_ptr, int64_t hub_d, int spr_max,
-                             int rpw_fixed, int *__restrict__ tile_lg, unsigned int *__restrict__ tile_waves,
-                             Segs sg, int64_t ntiles) {
+__global__ void k_plan_tiles(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                             int upper_only, int64_t hub_d, int spr_max, int rpw_fixed,
+                             int *__restrict__ tile_lg, unsigned int *__restrict__ tile_waves, Segs sg,
+                             int64_t ntiles) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
          t += (int64_t)gridDim.x * blockDim.x) {
         int g;
@@ -389,8 +391,10 @@ __global__ void k_plan_tiles(int64_t n, const int64_t *__restrict__ row_ptr, int
         } else {
             int64_t dm = 0;
             for (int64_t i = r0; i < r1; ++i) {
-                const int64_t d = row_ptr[i + 1] - row_ptr[i];
-                if (d <= hub_d && d > dm) dm = d;
+                const int64_t beg = row_ptr[i], end = row_ptr[i + 1];
+                if (end - beg > hub_d) continue;
+                const int64_t d = upper_only ? end - upper_start(col, beg, end, i) : end - beg;
+                if (d > dm) dm = d;
             }
             int spr = 1;
             while (spr < spr_max && (int64_t)spr * SWEEP_UNROLL < dm) spr <<= 1;
@@ -557,8 +561,8 @@ ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, con
     }
     const int64_t ntiles = sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE);
     if (ntiles <= 0) return fill_i32((int32_t *)p.plan_count, 0, 1, st);
-    hipLaunchKernelGGL(k_plan_tiles, dim3(grid_for(ntiles, BLOCK)), dim3(BLOCK), 0, st, g->n, g->row_ptr,
-                       p.sh.hub_d, p.sh.SPRW, p.sh.rpw_fixed, p.tile_lg, p.tile_waves, sg, ntiles);
+    hipLaunchKernelGGL(k_plan_tiles, dim3(grid_for(ntiles, BLOCK)), dim3(BLOCK), 0, st, g->n, g->row_ptr, g->col,
+                       p.sh.upper_only, p.sh.hub_d, p.sh.SPRW, p.sh.rpw_fixed, p.tile_lg, p.tile_waves, sg, ntiles);
     AD_LAUNCH_CHECK("k_plan_tiles");
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(BLOCK), 0, st, ntiles, p.tile_waves, p.plan_count);
     AD_LAUNCH_CHECK("k_plan_scan");

@@ -116,19 +116,6 @@ __device__ __forceinline__ void dist_span(const int32_t *__restrict__ col, const
     }
 }
 
-// First entry of row `row` in [beg, end) whose column exceeds the row: the
-// upper entries (j > i) are that suffix, columns being ascending in a row.
-__device__ __forceinline__ int64_t upper_start(const int32_t *__restrict__ col, int64_t beg, int64_t end,
-                                               int64_t row) {
-    int64_t lo = beg, hi = end;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if ((int64_t)col[mid] > row) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
-}
-
 // Entries per wave work item of a long row in the distance pass.
 constexpr int64_t DIST_SEG = 4096;
 
@@ -1215,10 +1202,12 @@ namespace ad {
 constexpr int64_t DIST_HUB = 4096;
 
 static SweepShape dist_shape(int R, ad_dtype x_dtype, int64_t d_max) {
-    // the sweep's lane layout for this vector width; rows longer than
-    // DIST_HUB (when the graph has any) go to the hub workgroups
+    // the sweep's lane layout for this vector width, rows per wave sized by
+    // the upper entries; rows longer than DIST_HUB (when the graph has any)
+    // go to the hub workgroups
     SweepShape sh = sweep_shape(R, x_dtype == AD_F64 ? 8 : 4, 0, 0);
     sh.hub_d = (d_max > DIST_HUB) ? DIST_HUB : ((int64_t)1 << 62);
+    sh.upper_only = 1;
     return sh;
 }
 
