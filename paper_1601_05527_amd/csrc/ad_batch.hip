@@ -41,25 +41,29 @@ __global__ void k_fill_graph(int64_t count, int32_t g, int32_t *__restrict__ dst
         dst[i] = g;
 }
 
-// n_kept[g] = sum of keep over graph g's edges; each edge's graph comes
-// from a binary search over edge_off; counts are reduced per wave when the
-// wave lies in one graph.
+// n_kept[g] = sum of keep over graph g's edges.  A wave's 64 consecutive
+// edges mostly lie in one graph: lane 0 finds it (binary search over
+// edge_off) and the wave sums into it; a wave that straddles graphs falls
+// back to a search per lane.
 __global__ __launch_bounds__(TB) void k_count_per_graph(int64_t m, const uint8_t *__restrict__ keep,
                                                         const int64_t *__restrict__ edge_off, int G,
                                                         unsigned long long *__restrict__ counts) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t m_pad = ceil_div_dev(m, stride) * stride;
+    const int lane = threadIdx.x & (WAVE - 1);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m_pad; e += stride) {
         const bool on = e < m;
-        const int g = on ? seg_find(edge_off, G, e) : -1;
+        const int64_t e_first = e - lane;                 // the wave's first edge (< m when any lane is on)
+        int g0 = 0;
+        if (lane == 0 && e_first < m) g0 = seg_find(edge_off, G, e_first);
+        g0 = __shfl(g0, 0, WAVE);
         unsigned long long c = (on && keep[e]) ? 1ull : 0ull;
-        const int g0 = __shfl(g, 0, WAVE);
-        const bool same = __all(g == g0 || g < 0);
-        if (same) {
+        const bool mine = !on || e < edge_off[g0 + 1];
+        if (__all(mine)) {
             for (int d = WAVE / 2; d >= 1; d >>= 1) c += __shfl_down(c, d, WAVE);
-            if ((threadIdx.x & (WAVE - 1)) == 0 && c && g0 >= 0) atomicAdd(&counts[g0], c);
+            if (lane == 0 && c) atomicAdd(&counts[g0], c);
         } else if (c) {
-            atomicAdd(&counts[g], c);
+            atomicAdd(&counts[seg_find(edge_off, G, e)], c);
         }
     }
 }

@@ -246,6 +246,38 @@ __device__ __forceinline__ void seg_span(const Segs &sg, const int64_t *__restri
     }
 }
 
+// XCD-aware walk of a persistent grid over the launch-plan entries.  The
+// hardware hands workgroups to the 8 XCDs round robin (workgroup b on XCD
+// b % 8), each XCD with its own L2.  Main workgroup mb of nmb (numbered
+// after a leading group of workgroups whose count is a multiple of 8)
+// belongs to group mb % 8, and group x walks plan entries
+// [splits[x], splits[x + 1]) -- contiguous ranges holding equal shares of
+// the entries' edges -- with all its waves, so an XCD's waves work on
+// neighbouring rows (for packed batches: on the same few graphs) at any
+// time.  Every entry is visited once whatever the placement.  With
+// xcd_groups == 1 (or fewer than 8 main workgroups) one group walks [0, np)
+// cyclically: on a single graph without row locality (a random power-law
+// graph stored by degree) that keeps the XCDs' loads even and measures
+// faster; packed batches of small graphs use the 8 groups.
+constexpr unsigned int XCDS = 8;
+struct PlanWalk {
+    unsigned long long first, end, stride;
+};
+__device__ __forceinline__ PlanWalk plan_walk(unsigned int np, const unsigned int *__restrict__ splits,
+                                              int xcd_groups, unsigned int mb, unsigned int nmb, int wave,
+                                              int waves_per_block) {
+    const unsigned int groups = (xcd_groups > 1 && nmb >= XCDS) ? XCDS : 1u;
+    const unsigned int x = mb % groups, lb = mb / groups;
+    const unsigned int nb = (nmb - x + groups - 1) / groups;    // workgroups in group x
+    PlanWalk w;
+    const unsigned long long a = groups == 1 ? 0ull : splits[x];
+    w.end = groups == 1 ? (unsigned long long)np : (unsigned long long)splits[x + 1];
+    w.first = a + (unsigned long long)lb * waves_per_block + wave;
+    w.stride = (unsigned long long)nb * waves_per_block;
+    return w;
+}
+inline int64_t round_up_xcds(int64_t v) { return (v + XCDS - 1) / XCDS * XCDS; }
+
 // Launch shape and plan of a JOR sweep (see ad_relax.hip).
 struct SweepShape {
     int vec, C, SPRW;     // values per lane, lanes per neighbour row, slots per wave
@@ -274,6 +306,9 @@ struct SweepPlan {
     unsigned int *hub_count;
     long long *plan;            // (first row << 16) | (rows << 8) | log2(rows per wave), per wave
     unsigned int *plan_count;
+    unsigned int *splits;       // [XCDS + 1] plan offsets of the XCD groups' ranges
+    int xcd_groups = 1;         // XCDS for packed batches of several graphs, else 1
+    unsigned long long *tile_nnz;  // [ntiles] planned entries (non-hub; upper only if so planned)
     int *tile_lg;
     unsigned int *tile_waves;
 };

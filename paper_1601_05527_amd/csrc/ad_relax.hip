@@ -270,7 +270,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
     const Tin *__restrict__ xin, Tout *__restrict__ xout, int R, int C,
     int64_t hub_d, int SPRW, int hub_blocks, const int32_t *__restrict__ hub_list,
     const unsigned int *__restrict__ hub_count, const long long *__restrict__ plan,
-    const unsigned int *__restrict__ plan_count) {
+    const unsigned int *__restrict__ plan_count, const unsigned int *__restrict__ splits, int xcd_groups) {
     __shared__ A part[BLOCK / WAVE][64];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
@@ -317,11 +317,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
         }
         return;
     }
-    // Other rows: each wave walks plan entries (first row, rows in the tile, log2 rows per
-    // wave); SPRW / rpw slots of C lanes per row.
-    const unsigned int np = *plan_count;
-    const unsigned int nwaves = (gridDim.x - hub_blocks) * (BLOCK / WAVE);
-    for (unsigned int pi = (blockIdx.x - hub_blocks) * (BLOCK / WAVE) + wave; pi < np; pi += nwaves) {
+    // Other rows: waves walk plan entries (first row, rows in the tile, log2 rows per
+    // wave) in XCD groups (plan_walk); SPRW / rpw slots of C lanes per row.
+    const PlanWalk pw = plan_walk(*plan_count, splits, xcd_groups, blockIdx.x - hub_blocks, gridDim.x - hub_blocks,
+                                  wave, BLOCK / WAVE);
+    for (unsigned long long pi = pw.first; pi < pw.end; pi += pw.stride) {
         const long long e = plan[pi];
         const int64_t row0 = e >> 16;
         const int nrows = (int)((e >> 8) & 0xff);      // rows of this entry inside its tile
@@ -376,63 +376,107 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
 // longest upper suffix), so that one round of
 // SWEEP_UNROLL gathers per slot covers it (short rows share a wave, long
 // rows get more slots).  A fixed rows-per-wave request overrides this.
-__global__ void k_plan_tiles(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                             int upper_only, int64_t hub_d, int spr_max, int rpw_fixed,
-                             int *__restrict__ tile_lg, unsigned int *__restrict__ tile_waves, Segs sg,
-                             int64_t ntiles) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
-         t += (int64_t)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(BLOCK) void k_plan_tiles(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col, int upper_only,
+                                                      int64_t hub_d, int spr_max, int rpw_fixed,
+                                                      int *__restrict__ tile_lg,
+                                                      unsigned int *__restrict__ tile_waves,
+                                                      unsigned long long *__restrict__ tile_nnz, Segs sg,
+                                                      int64_t ntiles) {
+    // one wave per tile (PLAN_TILE == WAVE rows), one lane per row
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    for (int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + (threadIdx.x >> 6); t < ntiles; t += nw) {
         int g;
         int64_t r0, r1;
         seg_span(sg, sg.tile_off, n, t, PLAN_TILE, g, r0, r1);
+        int64_t d = 0;
+        const int64_t i = r0 + lane;
+        if (i < r1) {
+            const int64_t beg = row_ptr[i], end = row_ptr[i + 1];
+            if (end - beg <= hub_d) d = upper_only ? end - upper_start(col, beg, end, i) : end - beg;
+        }
+        int64_t dm = d, ds = d;
+        for (int o = WAVE / 2; o >= 1; o >>= 1) {
+            dm = max(dm, (int64_t)__shfl_xor(dm, o, WAVE));
+            ds += (int64_t)__shfl_xor(ds, o, WAVE);
+        }
         int lg;
         if (rpw_fixed > 0) {
             lg = 31 - __clz(rpw_fixed);
         } else {
-            int64_t dm = 0;
-            for (int64_t i = r0; i < r1; ++i) {
-                const int64_t beg = row_ptr[i], end = row_ptr[i + 1];
-                if (end - beg > hub_d) continue;
-                const int64_t d = upper_only ? end - upper_start(col, beg, end, i) : end - beg;
-                if (d > dm) dm = d;
-            }
             int spr = 1;
             while (spr < spr_max && (int64_t)spr * SWEEP_UNROLL < dm) spr <<= 1;
             const int rpw = spr_max / spr;
             lg = 31 - __clz(rpw);
         }
-        tile_lg[t] = lg;
-        tile_waves[t] = (unsigned int)ceil_div_dev(r1 - r0, (int64_t)1 << lg);
+        if (lane == 0) {
+            tile_lg[t] = lg;
+            tile_waves[t] = (unsigned int)ceil_div_dev(r1 - r0, (int64_t)1 << lg);
+            tile_nnz[t] = (unsigned long long)ds;
+        }
     }
 }
 
 // Exclusive scan of tile_waves (one block: contiguous chunks per thread,
-// then a sequential pass over the chunk totals); plan_count = total.
+// then a sequential pass over the chunk totals); plan_count = total.  Then
+// the XCD groups' plan ranges: split x (1 <= x < XCDS) starts at the tile
+// after the one holding x / XCDS of the planned entries (by tile_nnz).
 __global__ __launch_bounds__(BLOCK) void k_plan_scan(int64_t ntiles, unsigned int *__restrict__ tile_waves,
-                                                     unsigned int *__restrict__ plan_count) {
+                                                     const unsigned long long *__restrict__ tile_nnz,
+                                                     unsigned int *__restrict__ plan_count,
+                                                     unsigned int *__restrict__ splits) {
     __shared__ unsigned int part[BLOCK];
+    __shared__ unsigned long long npart[BLOCK];
+    __shared__ unsigned long long total_nnz;
     const int t = threadIdx.x;
     const int64_t per = ceil_div_dev(ntiles, BLOCK);
     const int64_t a = t * per, b = min(ntiles, a + per);
     unsigned int sum = 0;
-    for (int64_t i = a; i < b; ++i) sum += tile_waves[i];
+    unsigned long long nsum = 0;
+    for (int64_t i = a; i < b; ++i) {
+        sum += tile_waves[i];
+        nsum += tile_nnz[i];
+    }
     part[t] = sum;
+    npart[t] = nsum;
     __syncthreads();
     if (t == 0) {
         unsigned int run = 0;
+        unsigned long long nrun = 0;
         for (int q = 0; q < BLOCK; ++q) {
-            unsigned int v = part[q];
+            const unsigned int v = part[q];
             part[q] = run;
             run += v;
+            const unsigned long long nv = npart[q];
+            npart[q] = nrun;
+            nrun += nv;
         }
         *plan_count = run;
+        total_nnz = nrun;
+        splits[0] = 0;
+        splits[XCDS] = run;
+        for (unsigned int x = 1; x < XCDS; ++x) splits[x] = nrun == 0 ? 0u : run;
     }
     __syncthreads();
     unsigned int run = part[t];
     for (int64_t i = a; i < b; ++i) {
-        unsigned int v = tile_waves[i];
+        const unsigned int v = tile_waves[i];
         tile_waves[i] = run;
         run += v;
+    }
+    __syncthreads();
+    // tile i holds the target point x * total / XCDS when prefix(i) < target <= prefix(i + 1)
+    const unsigned long long tot = total_nnz;
+    unsigned long long pre = npart[t];
+    for (int64_t i = a; i < b; ++i) {
+        const unsigned long long nxt = pre + tile_nnz[i];
+        for (unsigned int x = 1; x < XCDS; ++x) {
+            const unsigned long long target = tot * x / XCDS;
+            if (target > 0 && pre < target && target <= nxt)
+                splits[x] = (i + 1 < ntiles) ? tile_waves[i + 1] : *plan_count;
+        }
+        pre = nxt;
     }
 }
 
@@ -549,10 +593,13 @@ void sweep_plan_carve(Carver &c, int64_t n, int64_t ntiles_cap, SweepPlan &p) {
     p.plan_count = c.take<unsigned int>(1);
     p.tile_lg = c.take<int>(ntiles);
     p.tile_waves = c.take<unsigned int>(ntiles);
+    p.tile_nnz = c.take<unsigned long long>(ntiles);
+    p.splits = c.take<unsigned int>(XCDS + 1);
 }
 
 ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, const Segs &sg, hipStream_t st) {
     ad_status s;
+    p.xcd_groups = (sg.tile_off && sg.G > 1) ? (int)XCDS : 1;
     if (build_hubs) {
         s = fill_i32((int32_t *)p.hub_count, 0, 1, st);
         if (s != AD_OK) return s;
@@ -560,11 +607,18 @@ ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, con
         if (s != AD_OK) return s;
     }
     const int64_t ntiles = sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE);
-    if (ntiles <= 0) return fill_i32((int32_t *)p.plan_count, 0, 1, st);
-    hipLaunchKernelGGL(k_plan_tiles, dim3(grid_for(ntiles, BLOCK)), dim3(BLOCK), 0, st, g->n, g->row_ptr, g->col,
-                       p.sh.upper_only, p.sh.hub_d, p.sh.SPRW, p.sh.rpw_fixed, p.tile_lg, p.tile_waves, sg, ntiles);
+    if (ntiles <= 0) {
+        ad_status s0 = fill_i32((int32_t *)p.splits, 0, XCDS + 1, st);
+        if (s0 != AD_OK) return s0;
+        return fill_i32((int32_t *)p.plan_count, 0, 1, st);
+    }
+    static_assert(PLAN_TILE == WAVE, "k_plan_tiles gives each tile one wave");
+    hipLaunchKernelGGL(k_plan_tiles, dim3(grid_for(ntiles, BLOCK / WAVE)), dim3(BLOCK), 0, st, g->n, g->row_ptr, g->col,
+                       p.sh.upper_only, p.sh.hub_d, p.sh.SPRW, p.sh.rpw_fixed, p.tile_lg, p.tile_waves, p.tile_nnz,
+                       sg, ntiles);
     AD_LAUNCH_CHECK("k_plan_tiles");
-    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(BLOCK), 0, st, ntiles, p.tile_waves, p.plan_count);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(BLOCK), 0, st, ntiles, p.tile_waves, p.tile_nnz, p.plan_count,
+                       p.splits);
     AD_LAUNCH_CHECK("k_plan_scan");
     hipLaunchKernelGGL(k_plan_fill, dim3(grid_for(ntiles, BLOCK)), dim3(BLOCK), 0, st, g->n, p.tile_lg,
                        p.tile_waves, p.plan, sg, ntiles);
@@ -582,13 +636,14 @@ static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, cons
     // at most 2m / hub_d rows exceed hub_d; unknown d_max (0) keeps the bound
     int64_t hub_blocks = 0;
     if (g->d_max == 0 || g->d_max > sh.hub_d)
-        hub_blocks = std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(2 * g->m, sh.hub_d + 1)));
+        hub_blocks = round_up_xcds(std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(2 * g->m, sh.hub_d + 1))));
     const int64_t grid = main_blocks + hub_blocks;
     if (grid <= 0) return AD_OK;
     TraceScope trace("k_sweep", st);
     hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC, SWEEP_UNROLL>), dim3((unsigned)grid), dim3(BLOCK), 0, st,
                        g->n, g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C, sh.hub_d, sh.SPRW,
-                       (int)hub_blocks, pl.hub_list, pl.hub_count, pl.plan, pl.plan_count);
+                       (int)hub_blocks, pl.hub_list, pl.hub_count, pl.plan, pl.plan_count, pl.splits,
+                       pl.xcd_groups);
     AD_LAUNCH_CHECK("k_sweep");
     return AD_OK;
 }

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
     Tr *__restrict__ rho, int R, int C, int SPRW, int64_t hub_d, int hub_blocks, int64_t hub_segs,
     const int32_t *__restrict__ hub_list, const unsigned int *__restrict__ hub_count,
     const long long *__restrict__ plan, const unsigned int *__restrict__ plan_count,
-    const int32_t *__restrict__ row_graph) {
+    const unsigned int *__restrict__ splits, int xcd_groups, const int32_t *__restrict__ row_graph) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
     if ((int)blockIdx.x < hub_blocks) {
@@ -157,9 +157,9 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
         }
         return;
     }
-    const unsigned int np = *plan_count;
-    const unsigned int nwaves = (gridDim.x - hub_blocks) * (SBLOCK / WAVE);
-    for (unsigned int pi = (blockIdx.x - hub_blocks) * (SBLOCK / WAVE) + wave; pi < np; pi += nwaves) {
+    const PlanWalk pw = plan_walk(*plan_count, splits, xcd_groups, blockIdx.x - hub_blocks, gridDim.x - hub_blocks,
+                                  wave, SBLOCK / WAVE);
+    for (unsigned long long pi = pw.first; pi < pw.end; pi += pw.stride) {
         const long long pe = plan[pi];
         const int64_t row0 = pe >> 16;
         const int nrows = (int)((pe >> 8) & 0xff);     // rows of this entry inside its tile
@@ -1231,7 +1231,7 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
     if (hubs) {
         hub_segs = ceil_div(g->d_max, DIST_SEG);
         const int64_t busy = ceil_div(2 * g->m, DIST_SEG) + ceil_div(2 * g->m, DIST_HUB + 1);
-        hub_blocks = std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(busy, SBLOCK / WAVE)));
+        hub_blocks = round_up_xcds(std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(busy, SBLOCK / WAVE))));
     }
     const unsigned nb = (unsigned)(std::min<int64_t>(4096, ceil_div(g->n, SBLOCK / WAVE)) + hub_blocks);
     TraceScope trace("k_edge_dist", stream);
@@ -1239,7 +1239,7 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
     hipLaunchKernelGGL((k_edge_dist<TX, TR, V, DIST_UNROLL>), dim3(nb), dim3(SBLOCK), 0, stream, g->n,      \
                        g->row_ptr, g->col, g->eid, (const TX *)x, minmax, (TR *)rho, R, pl.sh.C, pl.sh.SPRW,  \
                        pl.sh.hub_d, (int)hub_blocks, hub_segs, pl.hub_list, pl.hub_count, pl.plan,            \
-                       pl.plan_count, sg.row_graph)
+                       pl.plan_count, pl.splits, pl.xcd_groups, sg.row_graph)
     if (x_dtype == AD_F64) {
         if (pl.sh.vec == 2) AD_DIST(double, double, 2);
         else AD_DIST(double, double, 1);
