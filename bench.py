@@ -210,6 +210,14 @@ def run_chung_lu(args, api, torch, dev):
     roof = roofline(kern, sb, sweep_traffic())
     rd_gbs = (K * sb + db) / (rd_ms * 1e-3) / 1e9
 
+    # context: a device-to-device copy of 1 GiB (reads and writes 2 GiB), the streaming ceiling
+    src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    copy_ms = timer.run(lambda: dst.copy_(src), 5)
+    copy_gbs = 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9
+    del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -236,6 +244,8 @@ def run_chung_lu(args, api, torch, dev):
         config, roof, cpu,
         breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())},
         relax_dist_ms=rd_ms, relax_dist_hbm_frac=rd_gbs / HBM_PEAK_GBS,
+        copy_ceiling_GBs=copy_gbs,
+        traffic_over_algorithmic=(roof["traffic"] / sb) if roof["traffic"] else None,
         sweep_updates_per_s=nnz * R / (roof["avg_launch_ms"] * 1e-3) if roof["avg_launch_ms"] else None,
         fit={"e_local": fit["e_local"], "e_global": fit["e_global"], "kept_local": kept_l,
              "kept_global": kept_g, "ratio_local": kept_l / m, "ratio_global": kept_g / m},
