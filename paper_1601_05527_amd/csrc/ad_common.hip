@@ -2,6 +2,8 @@
 // graph validation for libad.
 #include "ad_internal.h"
 
+#include <algorithm>
+
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -56,6 +58,159 @@ ad_status fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s) {
     AD_LAUNCH_CHECK("k_fill_u8");
     return AD_OK;
 }
+// ----------------------------------------------------------- plan scans --
+
+constexpr int SCAN_TB = 256;
+constexpr int SCAN_EPT = SCAN_PER_BLOCK / SCAN_TB;     // elements per thread
+
+// Block-wide exclusive scan of one value per thread (wave scans, then the
+// wave totals); returns the thread's exclusive prefix, *block_total the sum.
+template <typename T>
+__device__ T block_exclusive(T x, T *wsum, T *block_total) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    T inc = x;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const T y = __shfl_up(inc, o, WAVE);
+        if (lane >= o) inc += y;
+    }
+    if (lane == WAVE - 1) wsum[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int i = 0; i < SCAN_TB / WAVE; ++i) {
+            const T t = wsum[i];
+            wsum[i] = run;
+            run += t;
+        }
+        *block_total = run;
+    }
+    __syncthreads();
+    return wsum[w] + inc - x;
+}
+
+__global__ __launch_bounds__(SCAN_TB) void k_scan_partials(int64_t count, const unsigned int *__restrict__ v,
+                                                           const unsigned long long *__restrict__ w,
+                                                           unsigned int *__restrict__ blk_v,
+                                                           unsigned long long *__restrict__ blk_w) {
+    __shared__ unsigned int sv[SCAN_TB / WAVE];
+    __shared__ unsigned long long sw[SCAN_TB / WAVE];
+    __shared__ unsigned int tv;
+    __shared__ unsigned long long tw;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_PER_BLOCK + (int64_t)threadIdx.x * SCAN_EPT;
+    unsigned int a = 0;
+    unsigned long long b = 0;
+    for (int q = 0; q < SCAN_EPT; ++q) {
+        const int64_t i = base + q;
+        if (i < count) {
+            a += v[i];
+            if (w) b += w[i];
+        }
+    }
+    block_exclusive(a, sv, &tv);
+    if (w) block_exclusive(b, sw, &tw);
+    if (threadIdx.x == 0) {
+        blk_v[blockIdx.x] = tv;
+        blk_w[blockIdx.x] = w ? tw : 0ull;
+    }
+}
+
+// One block: exclusive scan of the block sums (thread-contiguous chunks).
+__global__ __launch_bounds__(SCAN_TB) void k_scan_blocks(int64_t nblk, unsigned int *__restrict__ blk_v,
+                                                         unsigned long long *__restrict__ blk_w,
+                                                         unsigned int *__restrict__ total,
+                                                         unsigned long long *__restrict__ total_w,
+                                                         unsigned int *__restrict__ splits) {
+    __shared__ unsigned int sv[SCAN_TB / WAVE];
+    __shared__ unsigned long long sw[SCAN_TB / WAVE];
+    __shared__ unsigned int tv;
+    __shared__ unsigned long long tw;
+    const int64_t per = ceil_div_dev(nblk, SCAN_TB);
+    const int64_t a0 = threadIdx.x * per, a1 = min(nblk, a0 + per);
+    unsigned int a = 0;
+    unsigned long long b = 0;
+    for (int64_t i = a0; i < a1; ++i) {
+        a += blk_v[i];
+        b += blk_w[i];
+    }
+    unsigned int pa = block_exclusive(a, sv, &tv);
+    unsigned long long pb = block_exclusive(b, sw, &tw);
+    for (int64_t i = a0; i < a1; ++i) {
+        const unsigned int x = blk_v[i];
+        const unsigned long long y = blk_w[i];
+        blk_v[i] = pa;
+        blk_w[i] = pb;
+        pa += x;
+        pb += y;
+    }
+    if (threadIdx.x == 0) {
+        *total = tv;
+        *total_w = tw;
+        if (splits) {
+            splits[0] = 0;
+            splits[XCDS] = tv;
+            for (unsigned int x = 1; x < XCDS; ++x) splits[x] = tw == 0 ? 0u : tv;
+        }
+    }
+}
+
+__global__ __launch_bounds__(SCAN_TB) void k_scan_apply(int64_t count, unsigned int *__restrict__ v,
+                                                        const unsigned long long *__restrict__ w,
+                                                        const unsigned int *__restrict__ blk_v,
+                                                        const unsigned long long *__restrict__ blk_w,
+                                                        const unsigned long long *__restrict__ total_w,
+                                                        unsigned int *__restrict__ splits) {
+    __shared__ unsigned int sv[SCAN_TB / WAVE];
+    __shared__ unsigned long long sw[SCAN_TB / WAVE];
+    __shared__ unsigned int tv;
+    __shared__ unsigned long long tw;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_PER_BLOCK + (int64_t)threadIdx.x * SCAN_EPT;
+    unsigned int xv[SCAN_EPT];
+    unsigned long long xw[SCAN_EPT];
+    unsigned int a = 0;
+    unsigned long long b = 0;
+    for (int q = 0; q < SCAN_EPT; ++q) {
+        const int64_t i = base + q;
+        xv[q] = i < count ? v[i] : 0u;
+        xw[q] = (i < count && w) ? w[i] : 0ull;
+        a += xv[q];
+        b += xw[q];
+    }
+    unsigned int pa = blk_v[blockIdx.x] + block_exclusive(a, sv, &tv);
+    unsigned long long pb = blk_w[blockIdx.x] + block_exclusive(b, sw, &tw);
+    const unsigned long long tot = w ? *total_w : 0ull;
+    for (int q = 0; q < SCAN_EPT; ++q) {
+        const int64_t i = base + q;
+        if (i >= count) break;
+        v[i] = pa;
+        const unsigned long long nxt = pb + xw[q];
+        if (w && splits) {
+            // element i holds the point x * tot / XCDS when pb < target <= nxt
+            for (unsigned int x = 1; x < XCDS; ++x) {
+                const unsigned long long target = tot * x / XCDS;
+                if (target > 0 && pb < target && target <= nxt) splits[x] = pa + xv[q];
+            }
+        }
+        pa += xv[q];
+        pb = nxt;
+    }
+}
+
+size_t scan_scratch_blocks(int64_t count) { return (size_t)std::max<int64_t>(1, ceil_div(count, SCAN_PER_BLOCK)); }
+
+ad_status scan_exclusive(int64_t count, unsigned int *v, const unsigned long long *w, unsigned int *total,
+                         unsigned int *splits, const ScanScratch &sc, hipStream_t s) {
+    const int64_t nblk = (int64_t)scan_scratch_blocks(count);
+    hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nblk), dim3(SCAN_TB), 0, s, count, v, w, sc.blk_v, sc.blk_w);
+    AD_LAUNCH_CHECK("k_scan_partials");
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_TB), 0, s, nblk, sc.blk_v, sc.blk_w, total, sc.total_w,
+                       w ? splits : nullptr);
+    AD_LAUNCH_CHECK("k_scan_blocks");
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(SCAN_TB), 0, s, count, v, w, sc.blk_v, sc.blk_w,
+                       sc.total_w, w ? splits : nullptr);
+    AD_LAUNCH_CHECK("k_scan_apply");
+    return AD_OK;
+}
+
 ad_status fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s) {
     if (count <= 0) return AD_OK;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count, 256)), dim3(256), 0, s, p, v, count);

@@ -181,6 +181,21 @@ ad_status fill_u64(unsigned long long *p, unsigned long long v, int64_t count, h
 ad_status fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s);
 ad_status fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
 
+// Device-wide exclusive scan of v[0 .. count) in place, *total = the sum
+// (three launches: per-block sums, a scan of those, per-block apply).  With
+// weights w (may be NULL) it also fills splits[0 .. XCDS]: splits[0] = 0,
+// splits[XCDS] = *total and, for 0 < x < XCDS, the scanned offset of the
+// element after the one holding the point x / XCDS of the total weight.
+constexpr int SCAN_PER_BLOCK = 1024;     // elements per block (256 threads x 4)
+struct ScanScratch {
+    unsigned int *blk_v;                 // [ceil(count / SCAN_PER_BLOCK)]
+    unsigned long long *blk_w;           // same
+    unsigned long long *total_w;         // [1]
+};
+size_t scan_scratch_blocks(int64_t count);
+ad_status scan_exclusive(int64_t count, unsigned int *v, const unsigned long long *w, unsigned int *total,
+                         unsigned int *splits, const ScanScratch &sc, hipStream_t s);
+
 // Rows with lo < degree <= hi appended to list (count must start at 0).
 ad_status collect_rows(const ad_graph *g, int64_t lo, int64_t hi, int32_t *list,
                        unsigned int *count, hipStream_t s);
@@ -309,6 +324,7 @@ struct SweepPlan {
     unsigned int *splits;       // [XCDS + 1] plan offsets of the XCD groups' ranges
     int xcd_groups = 1;         // XCDS for packed batches of several graphs, else 1
     unsigned long long *tile_nnz;  // [ntiles] planned entries (non-hub; upper only if so planned)
+    ScanScratch scan;
     int *tile_lg;
     unsigned int *tile_waves;
 };

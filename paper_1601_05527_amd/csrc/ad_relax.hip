@@ -418,68 +418,6 @@ __global__ __launch_bounds__(BLOCK) void k_plan_tiles(int64_t n, const int64_t *
     }
 }
 
-// Exclusive scan of tile_waves (one block: contiguous chunks per thread,
-// then a sequential pass over the chunk totals); plan_count = total.  Then
-// the XCD groups' plan ranges: split x (1 <= x < XCDS) starts at the tile
-// after the one holding x / XCDS of the planned entries (by tile_nnz).
-__global__ __launch_bounds__(BLOCK) void k_plan_scan(int64_t ntiles, unsigned int *__restrict__ tile_waves,
-                                                     const unsigned long long *__restrict__ tile_nnz,
-                                                     unsigned int *__restrict__ plan_count,
-                                                     unsigned int *__restrict__ splits) {
-    __shared__ unsigned int part[BLOCK];
-    __shared__ unsigned long long npart[BLOCK];
-    __shared__ unsigned long long total_nnz;
-    const int t = threadIdx.x;
-    const int64_t per = ceil_div_dev(ntiles, BLOCK);
-    const int64_t a = t * per, b = min(ntiles, a + per);
-    unsigned int sum = 0;
-    unsigned long long nsum = 0;
-    for (int64_t i = a; i < b; ++i) {
-        sum += tile_waves[i];
-        nsum += tile_nnz[i];
-    }
-    part[t] = sum;
-    npart[t] = nsum;
-    __syncthreads();
-    if (t == 0) {
-        unsigned int run = 0;
-        unsigned long long nrun = 0;
-        for (int q = 0; q < BLOCK; ++q) {
-            const unsigned int v = part[q];
-            part[q] = run;
-            run += v;
-            const unsigned long long nv = npart[q];
-            npart[q] = nrun;
-            nrun += nv;
-        }
-        *plan_count = run;
-        total_nnz = nrun;
-        splits[0] = 0;
-        splits[XCDS] = run;
-        for (unsigned int x = 1; x < XCDS; ++x) splits[x] = nrun == 0 ? 0u : run;
-    }
-    __syncthreads();
-    unsigned int run = part[t];
-    for (int64_t i = a; i < b; ++i) {
-        const unsigned int v = tile_waves[i];
-        tile_waves[i] = run;
-        run += v;
-    }
-    __syncthreads();
-    // tile i holds the target point x * total / XCDS when prefix(i) < target <= prefix(i + 1)
-    const unsigned long long tot = total_nnz;
-    unsigned long long pre = npart[t];
-    for (int64_t i = a; i < b; ++i) {
-        const unsigned long long nxt = pre + tile_nnz[i];
-        for (unsigned int x = 1; x < XCDS; ++x) {
-            const unsigned long long target = tot * x / XCDS;
-            if (target > 0 && pre < target && target <= nxt)
-                splits[x] = (i + 1 < ntiles) ? tile_waves[i + 1] : *plan_count;
-        }
-        pre = nxt;
-    }
-}
-
 __global__ void k_plan_fill(int64_t n, const int *__restrict__ tile_lg, const unsigned int *__restrict__ tile_off,
                             long long *__restrict__ plan, Segs sg, int64_t ntiles) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
@@ -595,6 +533,10 @@ void sweep_plan_carve(Carver &c, int64_t n, int64_t ntiles_cap, SweepPlan &p) {
     p.tile_waves = c.take<unsigned int>(ntiles);
     p.tile_nnz = c.take<unsigned long long>(ntiles);
     p.splits = c.take<unsigned int>(XCDS + 1);
+    const size_t nblk = scan_scratch_blocks(ntiles);
+    p.scan.blk_v = c.take<unsigned int>(nblk);
+    p.scan.blk_w = c.take<unsigned long long>(nblk);
+    p.scan.total_w = c.take<unsigned long long>(1);
 }
 
 ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, const Segs &sg, hipStream_t st) {
@@ -617,9 +559,10 @@ ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, con
                        p.sh.upper_only, p.sh.hub_d, p.sh.SPRW, p.sh.rpw_fixed, p.tile_lg, p.tile_waves, p.tile_nnz,
                        sg, ntiles);
     AD_LAUNCH_CHECK("k_plan_tiles");
-    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(BLOCK), 0, st, ntiles, p.tile_waves, p.tile_nnz, p.plan_count,
-                       p.splits);
-    AD_LAUNCH_CHECK("k_plan_scan");
+    // tile offsets into the plan; for XCD groups also their edge-balanced ranges
+    s = scan_exclusive(ntiles, p.tile_waves, p.xcd_groups > 1 ? p.tile_nnz : nullptr, p.plan_count, p.splits, p.scan,
+                       st);
+    if (s != AD_OK) return s;
     hipLaunchKernelGGL(k_plan_fill, dim3(grid_for(ntiles, BLOCK)), dim3(BLOCK), 0, st, g->n, p.tile_lg,
                        p.tile_waves, p.plan, sg, ntiles);
     AD_LAUNCH_CHECK("k_plan_fill");

@@ -375,35 +375,6 @@ __global__ void k_rank_plan(int64_t n, const int64_t *__restrict__ row_ptr, int 
     }
 }
 
-// Exclusive scan of per-tile counts in one block; total into *count.
-__global__ __launch_bounds__(SBLOCK) void k_scan_tiles(int64_t ntiles, unsigned int *__restrict__ v,
-                                                      unsigned int *__restrict__ count) {
-    __shared__ unsigned int part[SBLOCK];
-    const int t = threadIdx.x;
-    const int64_t per = ceil_div_dev(ntiles, SBLOCK);
-    const int64_t a = t * per, b = min(ntiles, a + per);
-    unsigned int sum = 0;
-    for (int64_t i = a; i < b; ++i) sum += v[i];
-    part[t] = sum;
-    __syncthreads();
-    if (t == 0) {
-        unsigned int run = 0;
-        for (int q = 0; q < SBLOCK; ++q) {
-            const unsigned int x = part[q];
-            part[q] = run;
-            run += x;
-        }
-        *count = run;
-    }
-    __syncthreads();
-    unsigned int run = part[t];
-    for (int64_t i = a; i < b; ++i) {
-        const unsigned int x = v[i];
-        v[i] = run;
-        run += x;
-    }
-}
-
 // Rows with degree > 64 into per-class lists (class c holds rows with
 // lo[c] < d <= lo[c + 1]); one pass, atomic slots per class.
 constexpr int NCLASS = 8;
@@ -977,6 +948,7 @@ struct SelLayout {
     ClassBounds cb;
     long long *plan;              // packed small-row waves
     unsigned int *tile_waves, *plan_count;
+    ScanScratch scan;
     unsigned long long *sides;    // [2m]
     unsigned long long *sides2;   // [2m] GLOBAL sides when both orientations are fitted
     unsigned long long *G;        // [m]
@@ -1010,6 +982,10 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     l.plan = c.take<long long>(n + ntiles);
     l.tile_waves = c.take<unsigned int>(ntiles);
     l.plan_count = c.take<unsigned int>(1);
+    const size_t nblk = scan_scratch_blocks(ntiles);
+    l.scan.blk_v = c.take<unsigned int>(nblk);
+    l.scan.blk_w = c.take<unsigned long long>(nblk);
+    l.scan.total_w = c.take<unsigned long long>(1);
     l.sides = c.take<unsigned long long>(2 * m);
     l.sides2 = both ? c.take<unsigned long long>(2 * m) : nullptr;
     l.G = c.take<unsigned long long>(m);
@@ -1088,8 +1064,8 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
     hipLaunchKernelGGL(k_rank_plan, dim3(grid_for(ntiles, SBLOCK)), dim3(SBLOCK), 0, st, n, g->row_ptr, 0,
                        L.tile_waves, L.plan);
     AD_LAUNCH_CHECK("k_rank_plan");
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SBLOCK), 0, st, ntiles, L.tile_waves, L.plan_count);
-    AD_LAUNCH_CHECK("k_scan_tiles");
+    s = scan_exclusive(ntiles, L.tile_waves, nullptr, L.plan_count, nullptr, L.scan, st);
+    if (s != AD_OK) return s;
     hipLaunchKernelGGL(k_rank_plan, dim3(grid_for(ntiles, SBLOCK)), dim3(SBLOCK), 0, st, n, g->row_ptr, 1,
                        L.tile_waves, L.plan);
     AD_LAUNCH_CHECK("k_rank_plan");
