@@ -36,7 +36,9 @@
 namespace ad {
 
 constexpr int SBLOCK = 256;
-constexpr int SORT_CAP = 8192;       // longest row ranked in LDS
+constexpr int NCLASS = 8;            // degree classes above 64 (see CLASS_LO)
+constexpr int HUB_CLASS = 7;         // FP32 rows of class >= HUB_CLASS take the bucket partition
+constexpr int SORT_CAP = 8192;       // longest FP32 row ranked in one wave or one LDS sort
 constexpr int DIST_UNROLL = 8;       // entries per slot in flight in the distance pass
 
 // ---------------------------------------------------------------- distance --
@@ -377,7 +379,6 @@ __global__ void k_rank_plan(int64_t n, const int64_t *__restrict__ row_ptr, int 
 
 // Rows with degree > 64 into per-class lists (class c holds rows with
 // lo[c] < d <= lo[c + 1]); one pass, atomic slots per class.
-constexpr int NCLASS = 8;
 struct ClassBounds {
     int64_t lo[NCLASS + 1];
     int64_t off[NCLASS];
@@ -605,7 +606,7 @@ constexpr int HUB_KPL = 8;              // bucket keys per lane held in register
 struct HubScratch {
     unsigned long long *key;   // [2m] bucketed keys, at the row's own entry range
     uint32_t *pos;             // [2m] offset in the row of each bucketed key
-    int32_t *bk_list;          // [cap] hub-list index of the bucket's row
+    int32_t *bk_row;           // [cap] the bucket's row
     uint32_t *bk_off;          // [cap] bucket offset within its row
     uint32_t *bk_cnt;          // [cap] bucket size
     unsigned int *nbk;         // [1] buckets written
@@ -674,7 +675,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         const int64_t beg = row_ptr[row];
         const int64_t d = row_ptr[row + 1] - beg;
         // a power-of-two sample of about d / 16 keys (1024 .. HUB_SAMPLE), at
-        // distinct, evenly spaced entries (d > SORT_CAP >= S)
+        // distinct, evenly spaced entries (S < d: S = 1024 < SORT_CAP < d, or S <= d / 8)
         int S = 1024;
         while (S < HUB_SAMPLE && (int64_t)S * 16 < d) S <<= 1;
         const int B = (int)min((int64_t)(S / HUB_MIN_SP), (d + HUB_BUCKET - 1) / HUB_BUCKET);
@@ -711,7 +712,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         const bool fits = base + B <= hs.cap;              // holds by the workspace bound
         if (fits) {
             for (int b = threadIdx.x; b < B; b += HUB_TB) {
-                hs.bk_list[base + b] = (int32_t)h;
+                hs.bk_row[base + b] = (int32_t)row;
                 hs.bk_cnt[base + b] = cnt[b];
             }
         }
@@ -736,13 +737,13 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
 // against all of them broadcast 64 at a time; HUB_KPL * 64 own keys per pass.
 // `em` names one orientation (the one the keys were built for).
 __global__ __launch_bounds__(SBLOCK) void k_hub_rank(
-    const int32_t *__restrict__ list, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ eid, Emit em, HubScratch hs) {
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
+    Emit em, HubScratch hs) {
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned int nb = (unsigned int)min((int64_t)(*hs.nbk), hs.cap);
     const unsigned int waves = gridDim.x * (SBLOCK / WAVE);
     for (unsigned int w = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); w < nb; w += waves) {
-        const int64_t row = list[hs.bk_list[w]];
+        const int64_t row = hs.bk_row[w];
         const int64_t beg = row_ptr[row];
         const int64_t d = row_ptr[row + 1] - beg;
         const uint32_t off = hs.bk_off[w], c = hs.bk_cnt[w];
@@ -794,7 +795,7 @@ __device__ __forceinline__ void block_add(unsigned long long c, unsigned long lo
 }
 
 constexpr int COUNT_BLOCKS = 2048;
-constexpr int HIST_BLOCKS = 512;
+constexpr int HIST_BLOCKS = 2048;
 
 // Sum of a byte mask into a 64-bit device counter.
 __global__ __launch_bounds__(SBLOCK) void k_count_bytes(int64_t m, const uint8_t *__restrict__ keep,
@@ -841,7 +842,8 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const unsigned l
     unsigned int run = 0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const unsigned long long a = side_grid(sides[2 * e], logs), b = side_grid(sides[2 * e + 1], logs);
+        const ulonglong2 ab = reinterpret_cast<const ulonglong2 *>(sides)[e];
+        const unsigned long long a = side_grid(ab.x, logs), b = side_grid(ab.y, logs);
         const unsigned long long g = a < b ? a : b;
         G[e] = g;
         const int bin = (int)((g >> (3 * DIGIT)) & (NBINS - 1));
@@ -923,7 +925,8 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const unsigned 
     unsigned long long c_hi = 0, c_lo = 0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        unsigned long long a = sides[2 * e], b = sides[2 * e + 1];
+        const ulonglong2 ab = reinterpret_cast<const ulonglong2 *>(sides)[e];
+        const unsigned long long a = ab.x, b = ab.y;
         unsigned long long da = a >> 32, ra = a & 0xffffffffull;
         unsigned long long db = b >> 32, rb = b & 0xffffffffull;
         bool k_hi = ra < (unsigned long long)tab_hi[da] || rb < (unsigned long long)tab_hi[db];
@@ -961,7 +964,8 @@ struct SelLayout {
 };
 
 // Degree classes above 64: wave counting with 2/4/8 keys per lane, bitonic
-// sorts in LDS of 1024/2048/4096/8192 keys, then counting from memory.
+// sorts in LDS of 1024/2048/4096/8192 keys, then the bucket partition (FP32;
+// FP64 rows above 64 are counted from memory).
 static const int64_t CLASS_LO[NCLASS + 1] = {64, 128, 256, 512, 1024, 2048, 4096, 8192, (int64_t)1 << 62};
 
 static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout *L, bool both = false) {
@@ -1001,7 +1005,7 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
         l.hub.cap = ceil_div(2 * m, HUB_BUCKET) + ceil_div(2 * m, SORT_CAP + 1) + 1;
         l.hub.key = c.take<unsigned long long>(2 * m);
         l.hub.pos = c.take<uint32_t>(2 * m);
-        l.hub.bk_list = c.take<int32_t>(l.hub.cap);
+        l.hub.bk_row = c.take<int32_t>(l.hub.cap);
         l.hub.bk_off = c.take<uint32_t>(l.hub.cap);
         l.hub.bk_cnt = c.take<uint32_t>(l.hub.cap);
         l.hub.nbk = c.take<unsigned int>(1);
@@ -1105,6 +1109,8 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
         if (g->d_max > 4096)
             hipLaunchKernelGGL((k_rank_bitonic<8192, 1024>), dim3(grid), dim3(1024), 0, st, lst[6], &L.cnt[6],
                                AD_RANK_ARGS_F);
+        // (the bucket partition runs once per orientation, a sort serves both: sorts up to SORT_CAP)
+        static_assert(HUB_CLASS == 7 && SORT_CAP == 8192, "bitonic classes end where the bucket partition starts");
         AD_LAUNCH_CHECK("k_rank_bitonic");
 #undef AD_RANK_ARGS_F
         if (g->d_max > SORT_CAP) {
@@ -1122,11 +1128,14 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                 }
                 s = fill_i32((int32_t *)L.hub.nbk, 0, 1, st);
                 if (s != AD_OK) return s;
-                hipLaunchKernelGGL(k_hub_partition, dim3(512), dim3(HUB_TB), 0, st, lst[7], &L.cnt[7], g->row_ptr,
-                                   g->col, g->eid, g->orig_id, g->col_orig, rf, one.orient, L.hub);
-                AD_LAUNCH_CHECK("k_hub_partition");
-                hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, st, lst[7], g->row_ptr, g->col, g->eid,
-                                   one, L.hub);
+                for (int k = HUB_CLASS; k < NCLASS; ++k) {
+                    if (g->d_max <= CLASS_LO[k]) break;
+                    hipLaunchKernelGGL(k_hub_partition, dim3(512), dim3(HUB_TB), 0, st, lst[k], &L.cnt[k],
+                                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, one.orient, L.hub);
+                    AD_LAUNCH_CHECK("k_hub_partition");
+                }
+                hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, st, g->row_ptr, g->col, g->eid, one,
+                                   L.hub);
                 AD_LAUNCH_CHECK("k_hub_rank");
             }
         }
