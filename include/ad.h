@@ -209,6 +209,22 @@ ad_status ad_sparsify_fit_both(const ad_graph *g, ad_dtype rho_dtype, const void
                                int64_t *n_kept, double *e_used_host, void *ws,
                                size_t ws_bytes, hipStream_t stream);
 
+/* Workspace bytes for ad_normalize_dist. */
+size_t ad_normalize_dist_workspace_size(const ad_graph *g);
+
+/* Algorithm 1's optional normalization (its last step; Appendix A): delta_e
+ * divided by sqrt(f_i f_j), with f the degree d_i as Algorithm 1 writes it
+ * (by_strength = 0) or the weighted degree s_i = sum_j w_ij as the text
+ * beside it says (by_strength = 1; with unit weights the two agree).
+ * Written as a distance, so that the selection calls apply unchanged:
+ *     rho_out[e] = sqrt(rho[e]^2 + eps) * sqrt(f_i * f_j),
+ * and the normalized delta is 1 / rho_out[e] (eps >= 0, the epsilon of
+ * Algorithm 1's return step).  rho, rho_out: [m] in rho_dtype (AD_F32 or
+ * AD_F64; arithmetic in FP64); rho_out may equal rho.  Asynchronous. */
+ad_status ad_normalize_dist(const ad_graph *g, ad_dtype rho_dtype, const void *rho,
+                            int32_t by_strength, double eps, void *rho_out, void *ws,
+                            size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------- adjoint --- */
 
 /* Workspace bytes for ad_relax_backward. */

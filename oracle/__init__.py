@@ -65,6 +65,7 @@ def _load():
     lib.orc_rescale_vector.argtypes = [i64, P, P, P, P, P]
     lib.orc_algebraic_distance.argtypes = [i64, P, P, P, P, P, i64, i32, i32, f64, u64, u64, P, P, P, P, P]
     lib.orc_strength.argtypes = [i64, P, f64, P]
+    lib.orc_normalize_dist.argtypes = [i64, P, P, P, P, P, i32, f64, P]
     lib.orc_budget.argtypes = [i64, f64]
     lib.orc_budget.restype = i64
     lib.orc_sparsify.argtypes = [i64, P, P, P, P, i64, P, i32, f64, P]
@@ -148,6 +149,18 @@ def strength(rho: np.ndarray, eps: float = 1e-12) -> np.ndarray:
     r = np.ascontiguousarray(rho, dtype=np.float64)
     out = np.zeros_like(r)
     lib.orc_strength(r.size, _p(r), eps, _p(out))
+    return out
+
+
+def normalize_dist(g, rho: np.ndarray, by_strength: bool = True, eps: float = 0.0) -> np.ndarray:
+    """Algorithm 1's optional normalization, as a distance: out_e =
+    sqrt(rho_e^2 + eps) * sqrt(f_i f_j) with f the weighted degree (or the
+    degree), so that the normalized delta is 1 / out_e."""
+    lib = _load()
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    out = np.zeros(g.m, dtype=np.float64)
+    lib.orc_normalize_dist(g.n, _p(g.row_ptr), _p(g.col), _p(_c(g.w, np.float32)), _p(g.eid), _p(r),
+                           1 if by_strength else 0, float(eps), _p(out))
     return out
 
 

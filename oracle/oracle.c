@@ -207,6 +207,34 @@ void orc_strength(int64_t m, const double *rho, double eps, double *delta)
     for (int64_t e = 0; e < m; ++e) delta[e] = 1.0 / sqrt(rho[e] * rho[e] + eps);
 }
 
+/* Optional normalization (Algorithm 1, last step): delta_e is divided by
+ * sqrt(f_i f_j), where f is the degree d_i (as Algorithm 1 writes it) or,
+ * with by_strength, the weighted degree s_i = sum_j w_ij (as the text
+ * around it says).  Written as the distance whose reciprocal is the
+ * normalized delta: out_e = sqrt(rho_e^2 + eps) * sqrt(f_i * f_j), so that
+ * the normalized delta-strong edges are the ones with small out_e.
+ * Every edge is visited from its upper entry (j > i).                      */
+void orc_normalize_dist(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                        const float *w, const int32_t *eid, const double *rho,
+                        int32_t by_strength, double eps, double *out)
+{
+    double *f = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+            acc += (by_strength && w) ? (double)w[p] : 1.0;
+        f[i] = acc;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            int64_t j = col[p];
+            if (j <= i) continue;
+            double r = rho[eid[p]];
+            out[eid[p]] = sqrt(r * r + eps) * sqrt(f[i] * f[j]);
+        }
+    free(f);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sparsify (Algorithm 3).                                                   */
 

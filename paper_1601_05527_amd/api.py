@@ -71,6 +71,8 @@ def _load_lib():
         "ad_sparsify": (st, [G, ctypes.c_int, P, ctypes.c_int, P, P, P, P, S, P]),
         "ad_sparsify_fit": (st, [G, ctypes.c_int, P, ctypes.c_int, f64, P, P, P, P, S, P]),
         "ad_sparsify_fit_both_workspace_size": (S, [G]),
+        "ad_normalize_dist_workspace_size": (S, [G]),
+        "ad_normalize_dist": (st, [G, ctypes.c_int, P, ctypes.c_int32, f64, P, P, S, P]),
         "ad_sparsify_fit_both": (st, [G, ctypes.c_int, P, f64, P, P, P, P, P, S, P]),
         "ad_relax_backward_workspace_size": (S, [G, O]),
         "ad_relax_backward": (st, [G, O, P, P, P, P, P, P, S, P]),
@@ -279,6 +281,21 @@ def edge_dist(dg: DeviceGraph, x: torch.Tensor, minmax: torch.Tensor,
         ws = _workspace(lib.ad_edge_dist_workspace_size(ctypes.byref(g)), x.device)
     _check(lib.ad_edge_dist(ctypes.byref(g), R, dt, _ptr(x), _ptr(minmax), _ptr(out), _ptr(ws), ws.numel(),
                             _stream()))
+    return out
+
+
+def normalize_dist(dg: DeviceGraph, rho: torch.Tensor, by_strength: bool = True, eps: float = 0.0,
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Algorithm 1's optional normalization as a distance (``ad_normalize_dist``):
+    out_e = sqrt(rho_e^2 + eps) * sqrt(f_i f_j), f the weighted degree (or the
+    degree); the normalized delta is 1 / out_e."""
+    if out is None:
+        out = torch.empty_like(rho)
+    g = dg.abi()
+    ws = _workspace(lib.ad_normalize_dist_workspace_size(ctypes.byref(g)), rho.device)
+    dt = AD_F64 if rho.dtype == torch.float64 else AD_F32
+    _check(lib.ad_normalize_dist(ctypes.byref(g), dt, _ptr(rho), 1 if by_strength else 0, float(eps), _ptr(out),
+                                 _ptr(ws), ws.numel(), _stream()))
     return out
 
 

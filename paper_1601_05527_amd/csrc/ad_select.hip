@@ -29,6 +29,8 @@
 
 #include <math.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <mutex>
 #include <vector>
@@ -189,6 +191,67 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
         const int64_t gb = (int64_t)(row_graph ? row_graph[row0] : 0) * 2 * R;
         dist_span<Tx, Tr, VEC, U>(col, eid, x, minmax, rho, R, C, SPR, slot, chunk, lane - chunk, active, row, beg,
                                   end, len, gb);
+    }
+}
+
+// ------------------------------------------------------------ normalization --
+
+// f_i = the weighted degree s_i in FP64 (or the degree d_i): one wave per row.
+__global__ __launch_bounds__(SBLOCK) void k_vertex_weight(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                         const float *__restrict__ w, int by_strength,
+                                                         double *__restrict__ f) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (SBLOCK / WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        const int64_t beg = row_ptr[i], end = row_ptr[i + 1];
+        if (!by_strength || !w) {
+            if (lane == 0) f[i] = (double)(end - beg);
+            continue;
+        }
+        double acc = 0.0;
+        for (int64_t p = beg + lane; p < end; p += WAVE) acc += (double)w[p];
+        for (int o = WAVE / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+        if (lane == 0) f[i] = acc;
+    }
+}
+
+// Row of entry p within rows [lo, hi] (row_ptr[lo] <= p < row_ptr[hi + 1]).
+__device__ __forceinline__ int64_t row_of(const int64_t *__restrict__ row_ptr, int64_t lo, int64_t hi, int64_t p) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (row_ptr[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+constexpr int64_t NORM_CHUNK = 4096;     // stored entries per wave work item
+
+// out_e = sqrt(rho_e^2 + eps) * sqrt(f_i f_j), from each edge's upper entry
+// (j > i).  Waves take chunks of NORM_CHUNK consecutive stored entries; the
+// rows a chunk spans are found by binary search over row_ptr.
+template <typename Tr>
+__global__ __launch_bounds__(SBLOCK) void k_normalize(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
+                                                     const double *__restrict__ f, const Tr *rho, double eps,
+                                                     Tr *out) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nchunks = ceil_div_dev(nnz, NORM_CHUNK);
+    const int64_t nw = (int64_t)gridDim.x * (SBLOCK / WAVE);
+    for (int64_t c = (int64_t)blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); c < nchunks; c += nw) {
+        const int64_t p0 = c * NORM_CHUNK, p1 = min(nnz, p0 + NORM_CHUNK);
+        int64_t r = 0;
+        if (lane == 0) r = row_of(row_ptr, 0, n - 1, p0);
+        if (lane == 1) r = row_of(row_ptr, 0, n - 1, p1 - 1);
+        const int64_t r0 = __shfl(r, 0, WAVE), r1 = __shfl(r, 1, WAVE);
+        for (int64_t p = p0 + lane; p < p1; p += WAVE) {
+            const int64_t i = row_of(row_ptr, r0, r1, p);
+            const int64_t j = col[p];
+            if (j <= i) continue;
+            const int32_t e = eid[p];
+            const double v = (double)rho[e];
+            out[e] = (Tr)(sqrt(v * v + eps) * sqrt(f[i] * f[j]));
+        }
     }
 }
 
@@ -1274,6 +1337,38 @@ extern "C" ad_status ad_edge_dist(const ad_graph *g, int32_t R, ad_dtype x_dtype
     if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
     return edge_dist_segs(g, R, x_dtype, x, minmax, rho, ws, ws_bytes, Segs(), stream);
+}
+
+extern "C" size_t ad_normalize_dist_workspace_size(const ad_graph *g) {
+    if (check_graph_args(g) != AD_OK) return 0;
+    return (size_t)std::max<int64_t>(1, g->n) * sizeof(double) + 256;
+}
+
+extern "C" ad_status ad_normalize_dist(const ad_graph *g, ad_dtype rho_dtype, const void *rho, int32_t by_strength,
+                                       double eps, void *rho_out, void *ws, size_t ws_bytes, hipStream_t stream) {
+    ad_status s = check_graph_args(g);
+    if (s != AD_OK) return s;
+    if (rho_dtype != AD_F32 && rho_dtype != AD_F64) return fail(AD_ERR_INVALID_ARG, "rho must be F32 or F64");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(AD_ERR_INVALID_ARG, "eps must be finite and >= 0");
+    if (g->m > 0 && (!rho || !rho_out)) return fail(AD_ERR_INVALID_ARG, "rho or rho_out is NULL");
+    if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < ad_normalize_dist_workspace_size(g)) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    if (g->n <= 0 || g->m <= 0) return AD_OK;
+    double *f = (double *)ws;
+    hipLaunchKernelGGL(k_vertex_weight, dim3(grid_for(ceil_div(g->n, SBLOCK / WAVE), 1)), dim3(SBLOCK), 0, stream,
+                       g->n, g->row_ptr, g->w, by_strength ? 1 : 0, f);
+    AD_LAUNCH_CHECK("k_vertex_weight");
+    const int64_t nnz = 2 * g->m;
+    const unsigned nb = grid_for(ceil_div(ceil_div(nnz, NORM_CHUNK), SBLOCK / WAVE), 1);
+    if (rho_dtype == AD_F32)
+        hipLaunchKernelGGL((k_normalize<float>), dim3(nb), dim3(SBLOCK), 0, stream, g->n, nnz, g->row_ptr, g->col,
+                           g->eid, f, (const float *)rho, eps, (float *)rho_out);
+    else
+        hipLaunchKernelGGL((k_normalize<double>), dim3(nb), dim3(SBLOCK), 0, stream, g->n, nnz, g->row_ptr, g->col,
+                           g->eid, f, (const double *)rho, eps, (double *)rho_out);
+    AD_LAUNCH_CHECK("k_normalize");
+    return AD_OK;
 }
 
 extern "C" ad_status ad_budget_table(int32_t d_max, double e, int32_t *budget_host) {

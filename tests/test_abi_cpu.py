@@ -96,6 +96,14 @@ def test_selection_rejects_bad_arguments():
     assert L.ad_edge_dist(ctypes.byref(g), 0, 1, p, p, p, ws, 1 << 30, None) == 1
     assert L.ad_edge_dist(ctypes.byref(g), 4, 2, p, p, p, ws, 1 << 30, None) == 1
     assert L.ad_edge_dist(ctypes.byref(g), 4, 1, p, p, p, ws, 16, None) == 3
+    # fit of both orientations: target and keep_global
+    e2 = (ctypes.c_double * 2)()
+    assert L.ad_sparsify_fit_both(ctypes.byref(g), 1, p, 0.0, p, p, p, e2, ws, 1 << 30, None) == 1
+    assert L.ad_sparsify_fit_both(ctypes.byref(g), 1, p, 0.3, p, None, p, e2, ws, 1 << 30, None) == 1
+    # normalization: dtype, eps, workspace
+    assert L.ad_normalize_dist(ctypes.byref(g), 2, p, 1, 0.0, p, ws, 1 << 30, None) == 1
+    assert L.ad_normalize_dist(ctypes.byref(g), 1, p, 1, -1.0, p, ws, 1 << 30, None) == 1
+    assert L.ad_normalize_dist(ctypes.byref(g), 1, p, 1, 0.0, p, ws, 8, None) == 3
 
 
 def test_budget_table_host():

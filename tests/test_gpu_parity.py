@@ -284,6 +284,34 @@ def test_fit_both_equals_single_fits(api, mixed, which, target):
         assert np.array_equal(_np(keep), keep_o)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("by_strength", [False, True])
+@pytest.mark.parametrize("eps", [0.0, 1e-4])
+def test_normalize_dist_parity(api, mixed, prec, by_strength, eps):
+    """Algorithm 1's optional normalization against the oracle (FP64
+    arithmetic on both sides; FP32 output rounded once), and selection on
+    the normalized distances bit-exact against the oracle's on the same
+    values."""
+    announce(f"normalize {prec} strength={by_strength} eps={eps}")
+    g, rho = mixed
+    rho_in = rho.astype(np.float32 if prec == "f32" else np.float64)
+    dg = _dg(api, g)
+    rt = torch.from_numpy(rho_in).cuda()
+    out = _np(api.normalize_dist(dg, rt, by_strength, eps))
+    want = oracle.normalize_dist(g, rho_in.astype(np.float64), by_strength, eps)
+    tol = 2.0 ** -23 if prec == "f32" else 1e-13
+    assert rel_stats(out, want)["max"] <= tol
+    out64 = out.astype(np.float64)
+    for orient in (0, 1):
+        keep, n_kept = api.sparsify(dg, torch.from_numpy(out).cuda(), orient, 0.5)
+        keep_o, kept_o = oracle.sparsify(g, out64, orient, 0.5)
+        assert np.array_equal(_np(keep), keep_o)
+        assert int(_np(n_kept)[0]) == kept_o
+    # in place
+    api.normalize_dist(dg, rt, by_strength, eps, out=rt)
+    assert np.array_equal(_np(rt), out)
+
+
 def test_long_rows_distance(api):
     """Distances on a graph whose long rows are cut into work items.  The
     graph has edges between vertices of degree one and other near-equal

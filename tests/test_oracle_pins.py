@@ -385,3 +385,66 @@ def test_gradient_matches_torch_autograd():
     L = (torch.tensor(c) * rho).sum()
     L.backward()
     np.testing.assert_allclose(grad, wv.grad.numpy(), rtol=1e-9, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Optional normalization (Algorithm 1, last step): out_e = sqrt(rho^2 + eps)
+# * sqrt(f_i f_j), the distance whose reciprocal is the normalized delta.
+
+def test_normalization_on_complete_graph_closed_form():
+    """On K_n every degree is n - 1: out = (n - 1) * rho, with rho from the
+    closed form of the complete graph (independent of the oracle's sweeps)."""
+    n, R, k = 9, 6, 5
+    iu = np.array([(a, b) for a in range(n) for b in range(a + 1, n)])
+    g = G.from_edges(n, iu[:, 0], iu[:, 1])
+    x0 = oracle.start_vectors(n, R, 4, 0, g.orig_id)
+    xh = (x0 - x0.min(axis=0)) / (x0.max(axis=0) - x0.min(axis=0))
+    rho_cf = np.sqrt(((xh[g.edge_u] - xh[g.edge_v]) ** 2).sum(axis=1))
+    rho = oracle.algebraic_distance(g, R, k, OMEGA, seed=4)
+    for by_strength in (False, True):
+        out = oracle.normalize_dist(g, rho, by_strength=by_strength)
+        np.testing.assert_allclose(out, (n - 1) * rho_cf, rtol=1e-12)
+
+
+def test_normalization_invariances():
+    g = _tiny_weighted(n=80, m=300, seed=21)
+    rho = oracle.algebraic_distance(g, 8, 10, OMEGA, seed=2)
+    # unit weights: strength and degree normalizations coincide
+    gu = G.with_weights(g, None)
+    np.testing.assert_array_equal(oracle.normalize_dist(gu, rho, True), oracle.normalize_dist(gu, rho, False))
+    # scaling every weight by c (a power of two, exact in FP32) leaves rho and
+    # the degree form unchanged and scales the strength form by c
+    c = 4.0
+    gc = G.with_weights(g, g.edge_w * np.float32(c))
+    rho_c = oracle.algebraic_distance(gc, 8, 10, OMEGA, seed=2)
+    np.testing.assert_array_equal(rho_c, rho)
+    np.testing.assert_allclose(oracle.normalize_dist(gc, rho, True), c * oracle.normalize_dist(g, rho, True),
+                               rtol=1e-12)
+    np.testing.assert_array_equal(oracle.normalize_dist(gc, rho, False), oracle.normalize_dist(g, rho, False))
+    # eps only lifts the distance: sqrt(rho^2 + eps) >= rho, with equality at eps = 0
+    assert np.all(oracle.normalize_dist(g, rho, True, 1e-3) >= oracle.normalize_dist(g, rho, True, 0.0))
+    # a single edge collapses to rho = 0, and both ends have degree 1 and weight w
+    g1 = G.from_edges(2, [0], [1], np.array([4.0], dtype=np.float32))
+    rho1 = oracle.algebraic_distance(g1, 4, 3, OMEGA, seed=1)
+    assert oracle.normalize_dist(g1, rho1, False, 0.25).tolist() == [0.5]
+    assert oracle.normalize_dist(g1, rho1, True, 0.25).tolist() == [2.0]
+    # relabelling the vertices leaves every edge's value unchanged
+    perm = np.random.default_rng(3).permutation(g.n)
+    gr = G.relabel(g, perm)
+    rho_r = oracle.algebraic_distance(gr, 8, 10, OMEGA, seed=2)
+    out_r = oracle.normalize_dist(gr, rho_r, True)
+    np.testing.assert_allclose(out_r, oracle.normalize_dist(g, rho, True)[gr.edge_perm], rtol=1e-12)
+
+
+def test_normalization_on_regular_graph_keeps_every_selection():
+    """On a regular unweighted graph the factor sqrt(d_i d_j) is one
+    constant, so every Algorithm 3 selection is unchanged."""
+    n = 60
+    u = np.arange(n)
+    g = G.from_edges(n, np.concatenate([u, u]), np.concatenate([(u + 1) % n, (u + 7) % n]))
+    rho = oracle.algebraic_distance(g, 6, 8, OMEGA, seed=5)
+    out = oracle.normalize_dist(g, rho, False)
+    np.testing.assert_allclose(out, 4.0 * rho, rtol=1e-15)
+    for orient in (0, 1):
+        for e in (0.3, 0.6):
+            assert np.array_equal(oracle.sparsify(g, out, orient, e)[0], oracle.sparsify(g, rho, orient, e)[0])
