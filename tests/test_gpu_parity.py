@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_1601_05527_amd import graphs as G
 
-from gpu_helpers import announce, near_cut_mismatches, rel_stats
+from gpu_helpers import announce, check_fp32, near_cut_mismatches, rel_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -105,6 +105,30 @@ def test_fp32_parity(api, kind):
     st = rel_stats(rho, rho_o)
     print(f"{kind}: n={g.n} m={g.m} dmax={g.d_max} max rel {st['max']:.3e} p99.9 {st['p999']:.3e}")
     assert st["max"] <= 1e-5
+
+
+@pytest.mark.parametrize("store", ["f32", "bf16", "f64"])
+def test_degree_ordered_mid_size(api, store):
+    """A 131072-vertex Chung-Lu graph stored by decreasing degree, as the
+    benchmark stores its graph, in every storage type and two launch
+    shapes, against the oracle."""
+    announce(f"degree-ordered 2^17 {store}")
+    g0 = G.chung_lu(1 << 17, 1_000_000, seed=17)
+    g = G.relabel(g0, G.degree_descending_order(g0))
+    R, k = 16, 12
+    dg = _dg(api, g)
+    rho_o, xk_o, _, mm_o = oracle.algebraic_distance(g, R, k, 0.5, seed=3, want_vectors=True)
+    x0 = oracle.start_vectors(g.n, R, 3, 0, g.orig_id)
+    for rpw in (0, 4):
+        res = api.relax(dg, R, k, seed=3, store=store, fp32_tail=8, rows_per_wave=rpw)
+        rho = _np(api.edge_dist(dg, res.x, res.minmax))
+        if store == "f64":
+            assert rel_stats(rho, rho_o, 0.1 * float(np.median(rho_o)))["max"] <= 1e-12
+        elif store == "f32":
+            ratio, st = check_fp32(g, x0, xk_o, mm_o, rho, rho_o, k)
+            assert ratio <= 1.0, st
+        else:
+            assert rel_stats(rho, rho_o, 0.1 * float(np.median(rho_o)))["max"] <= 2e-2
 
 
 def test_fp32_launch_shapes_agree(api):
