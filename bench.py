@@ -97,6 +97,51 @@ class Timer:
         return self.ev0.elapsed_time(self.ev1) / reps
 
 
+def gather_probe_ms(torch, timer, x, col, row_bytes, reps=10):
+    """ms of one launch of the pure row-gather probe (libad_probe.so) over
+    `col`, rows of `row_bytes` bytes of `x`; None if the probe is not built."""
+    import ctypes
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1601_05527_amd", "libad_probe.so")
+    if not os.path.exists(path):
+        log("gather probe not built; no gather ceiling reported")
+        return None
+    lib = ctypes.CDLL(path)
+    i64 = ctypes.c_int64
+    lib.ad_probe_threads.restype = i64
+    lib.ad_probe_threads.argtypes = [ctypes.c_int]
+    lib.ad_probe_gather.restype = ctypes.c_int
+    lib.ad_probe_gather.argtypes = [ctypes.c_void_p, i64, ctypes.c_int, ctypes.c_void_p, i64, ctypes.c_void_p,
+                                    ctypes.c_int, ctypes.c_void_p]
+    assert x.is_contiguous() and x.shape[1] * x.element_size() == row_bytes
+    blocks = 2048
+    sums = torch.empty((lib.ad_probe_threads(blocks), 4), dtype=torch.float32, device=x.device)
+
+    def run():
+        rc = lib.ad_probe_gather(x.data_ptr(), x.shape[0], row_bytes, col.data_ptr(), col.numel(),
+                                 sums.data_ptr(), blocks, torch.cuda.current_stream().cuda_stream)
+        if rc != 0:
+            raise RuntimeError(f"ad_probe_gather returned {rc}")
+
+    run()
+    return timer.run(run, reps)
+
+
+def vendor_spmm_ms(torch, timer, dg, x, reps=5):
+    """{ms, what} of y = W x with torch's sparse CSR product (the vendor
+    sparse library on this device) over the same CSR and vector block, or
+    {error} when that path is unavailable."""
+    try:
+        w = dg.w if dg.w is not None else torch.ones(dg.col.numel(), dtype=torch.float32, device=x.device)
+        a = torch.sparse_csr_tensor(dg.row_ptr, dg.col.to(torch.int64), w, size=(dg.n, dg.n))
+        y = a @ x
+        torch.cuda.synchronize()
+        ms = timer.run(lambda: a @ x, reps)
+        del a, y
+        return {"ms": ms, "what": "torch sparse CSR x dense (W x only, no JOR blend), same CSR and FP32 block"}
+    except Exception as ex:   # reported, not fatal: the comparison is context
+        return {"error": f"{type(ex).__name__}: {ex}"[:200]}
+
+
 def traced(api, timer, fn, reps):
     """(ms per call, per-kernel {name: (launches, total ms)}) with the
     library's own per-launch event tracing switched on."""
@@ -218,6 +263,20 @@ def run_chung_lu(args, api, torch, dev):
     copy_gbs = 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9
     del src, dst
 
+    # context: the sweep's neighbour-row gathers alone, with nothing else asked of the
+    # memory system (the irregular path's practical ceiling), and the vendor SpMM
+    sweep_ms = roof["avg_launch_ms"]
+    probe_ms = gather_probe_ms(torch, timer, out.x, dg.col, R * 4)
+    gather = None
+    if probe_ms:
+        gather = {"probe_ms": probe_ms, "rows_per_s": nnz / (probe_ms * 1e-3),
+                  "sweep_rows_per_s": nnz / (sweep_ms * 1e-3) if sweep_ms else None,
+                  "sweep_frac_of_probe": probe_ms / sweep_ms if sweep_ms else None,
+                  "what": (f"one launch gathering all {nnz} neighbour rows ({R * 4} B each) in CSR "
+                           "order with the graph's own column array, summing them; no weights, no "
+                           "output rows, no arithmetic beyond the sum")}
+    spmm = vendor_spmm_ms(torch, timer, dg, out.x)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -245,6 +304,8 @@ def run_chung_lu(args, api, torch, dev):
         breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())},
         relax_dist_ms=rd_ms, relax_dist_hbm_frac=rd_gbs / HBM_PEAK_GBS,
         copy_ceiling_GBs=copy_gbs,
+        gather_ceiling=gather,
+        vendor_spmm=spmm,
         traffic_over_algorithmic=(roof["traffic"] / sb) if roof["traffic"] else None,
         sweep_updates_per_s=nnz * R / (roof["avg_launch_ms"] * 1e-3) if roof["avg_launch_ms"] else None,
         fit={"e_local": fit["e_local"], "e_global": fit["e_global"], "kept_local": kept_l,

@@ -3,7 +3,9 @@
     python -m paper_1601_05527_amd.build_lib
 
 Each ``csrc/*.hip`` file is compiled to an object with hipcc in parallel,
-then linked into ``paper_1601_05527_amd/libad.so``.
+then linked into ``paper_1601_05527_amd/libad.so``.  The measurement probe
+``probe/gather_probe.hip`` (a pure row-gather kernel the benchmark uses as a
+ceiling, not part of the method) becomes ``libad_probe.so``.
 """
 from __future__ import annotations
 
@@ -18,6 +20,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libad.so")
+PROBE_SRC = os.path.join(HERE, "probe", "gather_probe.hip")
+PROBE_LIB = os.path.join(HERE, "libad_probe.so")
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
@@ -47,8 +51,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC] + FLAGS + ["-shared", PROBE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PROBE_LIB}")
     return LIB
 
 

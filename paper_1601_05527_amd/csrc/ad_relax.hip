@@ -220,6 +220,28 @@ __global__ void k_init(int64_t n, int R, const int32_t *__restrict__ orig_id, ui
     }
 }
 
+// One lane's part of a launch-plan entry (first row << 16 | rows in the
+// entry << 8 | log2 rows per wave): its row, slot of C lanes within the
+// row's SPR slots, and chunk of the R values.
+struct EntryLane {
+    int64_t row;
+    int SPR, slot, chunk;
+    bool active;
+};
+__device__ __forceinline__ EntryLane entry_lane(long long e, int lane, int C, int SPRW) {
+    EntryLane q;
+    const int nrows = (int)((e >> 8) & 0xff);
+    q.SPR = SPRW >> (int)(e & 0xff);
+    const int group = C * q.SPR;
+    const int rw = lane / group;
+    const int sub = lane - rw * group;
+    q.slot = sub / C;
+    q.chunk = sub - q.slot * C;
+    q.row = (e >> 16) + rw;
+    q.active = rw < nrows;
+    return q;
+}
+
 // Accumulate sum_j w_ij x_j over the entries p0, p0 + stride, p0 + 2 stride,
 // ... < end into acc (VEC values of one lane's chunk), in that order.  U
 // column/weight pairs are loaded first, then U gathers are issued together,
@@ -318,30 +340,38 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
         return;
     }
     // Other rows: waves walk plan entries (first row, rows in the tile, log2 rows per
-    // wave) in XCD groups (plan_walk); SPRW / rpw slots of C lanes per row.
+    // wave) in XCD groups (plan_walk); SPRW / rpw slots of C lanes per row.  The
+    // walk is software-pipelined: while an entry's columns and rows are read, the
+    // row bounds of the next entry and the plan word of the one after are
+    // already in flight, so each entry waits on two dependent reads, not four.
     const PlanWalk pw = plan_walk(*plan_count, splits, xcd_groups, blockIdx.x - hub_blocks, gridDim.x - hub_blocks,
                                   wave, BLOCK / WAVE);
-    for (unsigned long long pi = pw.first; pi < pw.end; pi += pw.stride) {
-        const long long e = plan[pi];
-        const int64_t row0 = e >> 16;
-        const int nrows = (int)((e >> 8) & 0xff);      // rows of this entry inside its tile
-        const int RPW = 1 << (int)(e & 0xff);
-        const int SPR = SPRW / RPW;
-        const int group = C * SPR;
-        const int rw = lane / group;
-        const int sub = lane - rw * group;
-        const int slot = sub / C;
-        const int chunk = sub - slot * C;
-        const int64_t row = row0 + rw;
-        const bool active = rw < nrows;
-        int64_t beg = 0, end = 0;
-        if (active) {
-            beg = row_ptr[row];
-            end = row_ptr[row + 1];
+    const unsigned long long stride = pw.stride;
+    unsigned long long pi = pw.first;
+    long long e_cur = pi < pw.end ? plan[pi] : 0;
+    long long e_nxt = pi + stride < pw.end ? plan[pi + stride] : 0;
+    EntryLane cur = entry_lane(e_cur, lane, C, SPRW);
+    int64_t beg = 0, end = 0;
+    if (pi < pw.end && cur.active) {
+        beg = row_ptr[cur.row];
+        end = row_ptr[cur.row + 1];
+    }
+    // settle the prologue's reads here, so the loop's first use of them does not
+    // also wait for the prefetches issued ahead of it
+    __builtin_amdgcn_s_waitcnt(0x0F70);    // vmcnt(0)
+    for (; pi < pw.end; pi += stride) {
+        // prefetch: plan word two entries ahead, row bounds of the next entry
+        const long long e_nn = pi + 2 * stride < pw.end ? plan[pi + 2 * stride] : 0;
+        const EntryLane nxt = entry_lane(e_nxt, lane, C, SPRW);
+        int64_t beg_n = 0, end_n = 0;
+        if (pi + stride < pw.end && nxt.active) {
+            beg_n = row_ptr[nxt.row];
+            end_n = row_ptr[nxt.row + 1];
         }
+        const int64_t row = cur.row;
         const bool hub = (end - beg) > hub_d;
-        const bool writer = active && !hub && slot == 0;
-        const int off = chunk * VEC;
+        const bool writer = cur.active && !hub && cur.slot == 0;
+        const int off = cur.chunk * VEC;
         // the row's own values and 1/s do not depend on the gathers: load them first
         A own[VEC];
         A is = (A)0;
@@ -352,8 +382,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
         A acc[VEC];
 #pragma unroll
         for (int q = 0; q < VEC; ++q) acc[q] = (A)0;
-        if (active && !hub) gather_rows<U, VEC>(col, w, xin, beg + slot, end, SPR, R, off, acc);
-        for (int d = SPR >> 1; d >= 1; d >>= 1) {
+        if (cur.active && !hub) gather_rows<U, VEC>(col, w, xin, beg + cur.slot, end, cur.SPR, R, off, acc);
+        for (int d = cur.SPR >> 1; d >= 1; d >>= 1) {
 #pragma unroll
             for (int q = 0; q < VEC; ++q) acc[q] += shfl_down(acc[q], d * C);
         }
@@ -368,6 +398,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
             }
             store_vec<VEC>(xout + row * R + off, res);
         }
+        cur = nxt;
+        beg = beg_n;
+        end = end_n;
+        e_nxt = e_nn;
     }
 }
 

@@ -149,3 +149,25 @@ def test_budget_table_matches_oracle_budget_everywhere():
             t = api.budget_table(d_max, e)
             want = np.array([0] + [lib.orc_budget(d, e) for d in range(1, d_max + 1)], dtype=np.int64)
             assert np.array_equal(t.astype(np.int64), want), (d_max, e)
+
+
+def test_gather_probe_library_loads_and_rejects_bad_arguments():
+    """The benchmark's gather probe (a measurement aid outside the method's
+    library) is built, exports its two calls, and rejects bad arguments
+    before launching anything."""
+    path = os.path.join(ROOT, "paper_1601_05527_amd", "libad_probe.so")
+    if not os.path.exists(path):
+        pytest.fail("libad_probe.so is not built (run __graft_entry__.build())")
+    probe = ctypes.CDLL(path)
+    probe.ad_probe_threads.restype = ctypes.c_int64
+    probe.ad_probe_threads.argtypes = [ctypes.c_int]
+    assert probe.ad_probe_threads(2048) == 2048 * 256
+    i64 = ctypes.c_int64
+    probe.ad_probe_gather.argtypes = [ctypes.c_void_p, i64, ctypes.c_int, ctypes.c_void_p, i64, ctypes.c_void_p,
+                                      ctypes.c_int, ctypes.c_void_p]
+    fake = 0x1000
+    assert probe.ad_probe_gather(None, 4, 64, fake, 8, fake, 1, None) == -1      # no rows
+    assert probe.ad_probe_gather(fake, 4, 48, fake, 8, fake, 1, None) == -1      # row size
+    assert probe.ad_probe_gather(fake, 0, 64, fake, 8, fake, 1, None) == -1      # empty array
+    assert probe.ad_probe_gather(fake, 4, 64, fake, 8, fake, 0, None) == -1      # no blocks
+    assert probe.ad_probe_gather(fake, 4, 64, fake, 0, fake, 1, None) == 0       # nothing to gather
