@@ -275,6 +275,11 @@ __device__ __forceinline__ void seg_span(const Segs &sg, const int64_t *__restri
 // graph stored by degree) that keeps the XCDs' loads even and measures
 // faster; packed batches of small graphs use the 8 groups.
 constexpr unsigned int XCDS = 8;
+constexpr int MAX_DEVICES = 64;
+constexpr int QUEUE_PAD = 32;                          // words between counters (one 128-byte line)
+constexpr int QUEUE_GROUPS = 64;                       // counters per queue (hub rows, plan chunks)
+constexpr int QUEUE_SET = 2 * QUEUE_GROUPS * QUEUE_PAD;
+constexpr int QUEUE_SLOTS = 3;
 struct PlanWalk {
     unsigned long long first, end, stride;
 };
@@ -322,6 +327,11 @@ struct SweepPlan {
     long long *plan;            // (first row << 16) | (rows << 8) | log2(rows per wave), per wave
     unsigned int *plan_count;
     unsigned int *splits;       // [XCDS + 1] plan offsets of the XCD groups' ranges
+    // QUEUE_SLOTS sets of work-queue counters (QUEUE_SET words each); sweep
+    // launch t on this plan uses set t mod QUEUE_SLOTS and clears the set launch
+    // t + 2 uses (that of launch t - 1, finished by stream order)
+    unsigned int *queue;
+    mutable unsigned int turn = 0;
     int xcd_groups = 1;         // XCDS for packed batches of several graphs, else 1
     unsigned long long *tile_nnz;  // [ntiles] planned entries (non-hub; upper only if so planned)
     ScanScratch scan;

@@ -23,6 +23,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 
 namespace ad {
 
@@ -278,25 +279,121 @@ __device__ __forceinline__ void gather_rows(const int32_t *__restrict__ col, con
     }
 }
 
-// One JOR sweep over all rows, in one launch.
-// Blocks [0, hub_blocks) take the listed long rows (degree > hub_d), one row
-// per 256-thread workgroup at a time: SPRW slots per wave, partial sums
-// combined across the 4 waves in LDS.  They come first so the longest work
-// starts first.  Blocks [hub_blocks, ...) take the other rows as a persistent
-// grid walking the launch plan (see below): per wave 2^lg rows, per row
-// SPRW / 2^lg slots of C lanes, VEC values per lane.
-template <typename Tin, typename Tout, typename A, int VEC, int U>
-__global__ __launch_bounds__(BLOCK) void k_sweep(
+// Work queues of a sweep launch (one set of counters per launch, see
+// SweepPlan::queue): QUEUE_GROUPS counters hand out hub rows (group g owns
+// list positions g, g + QUEUE_GROUPS, ...) and QUEUE_GROUPS more hand out
+// chunks of SWEEP_CHUNK plan entries.  For packed batches the first XCDS
+// plan groups are the XCD groups, group g's chunk k being entries splits[g]
+// + k CH ... of its edge-balanced range; otherwise group g's chunk k is
+// entries (g + QUEUE_GROUPS k) CH ... of the whole plan.  Spreading the
+// tickets over many counters keeps each counter's atomics few: they are
+// served one at a time per address.
+constexpr int SWEEP_CHUNK = 4;
+constexpr unsigned int NO_CHUNK = 0xffffffffu;
+
+__device__ __forceinline__ bool chunk_range(bool contig, const unsigned int *__restrict__ splits, unsigned int np,
+                                            int g, unsigned int k, unsigned int &lo, unsigned int &hi) {
+    const unsigned long long a = contig ? splits[g] : 0ull;
+    const unsigned long long b = contig ? splits[g + 1] : (unsigned long long)np;
+    const unsigned long long c =
+        contig ? (unsigned long long)k : (unsigned long long)g + (unsigned long long)QUEUE_GROUPS * k;
+    const unsigned long long first = a + c * SWEEP_CHUNK;
+    if (first >= b) return false;
+    lo = (unsigned int)first;
+    hi = (unsigned int)std::min<unsigned long long>(first + SWEEP_CHUNK, b);
+    return true;
+}
+
+__device__ __forceinline__ bool hub_item(int g, unsigned int k, unsigned int nh, unsigned int &h) {
+    const unsigned long long i = (unsigned long long)g + (unsigned long long)QUEUE_GROUPS * k;
+    if (i >= nh) return false;
+    h = (unsigned int)i;
+    return true;
+}
+
+// One ticket from a queue counter for the whole wave (all lanes active).
+__device__ __forceinline__ unsigned int wave_ticket(unsigned int *q, int lane) {
+    unsigned int v = 0;
+    if (lane == 0) v = atomicAdd(q, 1u);
+    return (unsigned int)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// A wave (all lanes active) takes its next item: `pending` is a ticket
+// already drawn from group grp (or NO_CHUNK), and item(g, k, out) says
+// whether ticket k of group g names an item.  When group grp is exhausted,
+// the wave's lanes read every group's counter at once and the wave moves to
+// the first group from grp on that still has items.  Returns false once no
+// group has any.  Ends: a failed draw only happens on a group that had
+// items when probed, and the items are finite.
+template <typename Item>
+__device__ __forceinline__ bool take_item(unsigned int *ctr, int ngroups, int &grp, unsigned int pending,
+                                          int lane, Item item, unsigned int &out0, unsigned int &out1) {
+    unsigned int k = pending;
+    for (;;) {
+        if (k == NO_CHUNK) k = wave_ticket(ctr + grp * QUEUE_PAD, lane);
+        if (item(grp, k, out0, out1)) return true;
+        bool left = false;
+        if (lane < ngroups) {
+            int g2 = grp + lane;
+            if (g2 >= ngroups) g2 -= ngroups;
+            const unsigned int v =
+                __hip_atomic_load(ctr + g2 * QUEUE_PAD, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned int d0, d1;
+            left = item(g2, v, d0, d1);
+        }
+        const unsigned long long mask = __ballot(left);
+        if (mask == 0) return false;
+        grp += __ffsll((long long)mask) - 1;
+        if (grp >= ngroups) grp -= ngroups;
+        k = NO_CHUNK;
+    }
+}
+
+__device__ __forceinline__ long long lane_word(long long v, int i) {
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned int)v, i);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), i);
+    return (long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned int)lo);
+}
+
+// Waves per SIMD the sweep is compiled for: four for 4-byte arithmetic with
+// up to 16 bytes per lane (the FP32 and BF16 forms at R <= 16), which fits
+// the register budget of four waves without spilling; no request otherwise.
+template <typename A, int VEC>
+constexpr int sweep_waves_per_eu() {
+    return sizeof(A) == 4 && VEC <= 4 ? 4 : 1;
+}
+
+// One JOR sweep over all rows, in one launch.  Long rows (degree > hub_d)
+// get a 256-thread workgroup each: SPRW slots per wave, partial sums
+// combined across the 4 waves in LDS.  The other rows follow the launch plan
+// (see below): per wave 2^lg rows, per row SPRW / 2^lg slots of C lanes, VEC
+// values per lane.  Each row is summed by one wave (or one workgroup) in a
+// fixed order, so the result does not depend on which wave takes it.
+//
+// Static walk (!QUEUED, one graph): blocks [0, hub_blocks) take the listed
+// long rows, strided, and come first so the longest work starts first;
+// blocks [hub_blocks, ...) walk the plan as a persistent grid.
+//
+// Queued walk (QUEUED, packed batches): a grid no larger than the device
+// holds at once; every workgroup first takes long rows from the hub queue,
+// then its waves take chunks of the plan from the XCD groups' queues, so
+// uneven graphs and rows even out over the whole device.  Block 0 also
+// clears the counters the launch after next will use.
+template <typename Tin, typename Tout, typename A, int VEC, int U, bool QUEUED>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<A, VEC>()))) void k_sweep(
     int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const float *__restrict__ w, const A *__restrict__ inv_s, A omega,
     const Tin *__restrict__ xin, Tout *__restrict__ xout, int R, int C,
     int64_t hub_d, int SPRW, int hub_blocks, const int32_t *__restrict__ hub_list,
     const unsigned int *__restrict__ hub_count, const long long *__restrict__ plan,
-    const unsigned int *__restrict__ plan_count, const unsigned int *__restrict__ splits, int xcd_groups) {
+    const unsigned int *__restrict__ plan_count, const unsigned int *__restrict__ splits, int xcd_groups,
+    unsigned int *__restrict__ queue, unsigned int *__restrict__ queue_clear) {
     __shared__ A part[BLOCK / WAVE][64];
+    __shared__ unsigned int s_row;
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
     const A keep = (A)1 - omega;
+    if constexpr (!QUEUED) {
     if ((int)blockIdx.x < hub_blocks) {
         const int slot_w = lane / C;
         const int chunk = lane - slot_w * C;
@@ -402,6 +499,170 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(
         beg = beg_n;
         end = end_n;
         e_nxt = e_nn;
+    }
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 2 * QUEUE_GROUPS)
+        __hip_atomic_store(queue_clear + threadIdx.x * QUEUE_PAD, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+    // long rows, a workgroup each.  Wave 0 keeps the block's place in the hub
+    // queue; thread 0 draws the next row's ticket while this row runs.
+    {
+        const int slot_w = lane / C;
+        const int chunk = lane - slot_w * C;
+        const bool lane_on = slot_w < SPRW;
+        const int slots = SPRW * (BLOCK / WAVE);
+        const int slot = wave * SPRW + slot_w;
+        const int off = chunk * VEC;
+        const unsigned int nh = *hub_count;
+        int hgrp = (int)(blockIdx.x % QUEUE_GROUPS);
+        auto hub_at = [nh](int g, unsigned int k, unsigned int &h, unsigned int &) { return hub_item(g, k, nh, h); };
+        if (wave == 0) {
+            unsigned int h0 = 0, unused = 0;
+            const bool ok = take_item(queue, QUEUE_GROUPS, hgrp, NO_CHUNK, lane, hub_at, h0, unused);
+            if (lane == 0) s_row = ok ? h0 : NO_CHUNK;
+        }
+        __syncthreads();
+        unsigned int h = s_row;
+        while (h != NO_CHUNK) {
+            unsigned int ticket = 0;
+            if (threadIdx.x == 0) ticket = atomicInc(queue + hgrp * QUEUE_PAD, 0xffffffffu);
+            const int64_t row = hub_list[h];
+            const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
+            A acc[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = (A)0;
+            if (lane_on) gather_rows<U, VEC>(col, w, xin, beg + slot, end, slots, R, off, acc);
+            for (int d = SPRW >> 1; d >= 1; d >>= 1) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[q] += shfl_down(acc[q], d * C);
+            }
+            if (lane_on && slot_w == 0) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) part[wave][off + q] = acc[q];
+            }
+            __syncthreads();
+            if (wave == 0 && lane_on && slot_w == 0) {
+                A sum[VEC], own[VEC], res[VEC];
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) sum[q] = part[0][off + q];
+                for (int wv = 1; wv < BLOCK / WAVE; ++wv) {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) sum[q] += part[wv][off + q];
+                }
+                load_vec<VEC>(xin + row * R + off, own);
+                const A is = inv_s[row];
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) res[q] = fma(omega, sum[q] * is, keep * own[q]);
+                store_vec<VEC>(xout + row * R + off, res);
+            }
+            if (wave == 0) {
+                unsigned int hn = 0, unused = 0;
+                const unsigned int k = (unsigned int)__builtin_amdgcn_readfirstlane((int)ticket);
+                const bool ok = take_item(queue, QUEUE_GROUPS, hgrp, k, lane, hub_at, hn, unused);
+                if (lane == 0) s_row = ok ? hn : NO_CHUNK;
+            }
+            __syncthreads();
+            h = s_row;
+        }
+    }
+
+    // other rows: chunks of plan entries (first row, rows in the tile, log2 rows
+    // per wave), each wave starting in a group of its own.  The chunk after next
+    // is drawn while a chunk runs, its plan words are read one chunk ahead, and
+    // the row bounds of the next entry are read while an entry's rows are
+    // gathered.
+    const unsigned int np = *plan_count;
+    unsigned int *qg = queue + QUEUE_GROUPS * QUEUE_PAD;
+    const bool contig = xcd_groups > 1;
+    const int ngroups = contig ? (int)XCDS : QUEUE_GROUPS;
+    int grp = (int)((blockIdx.x * (BLOCK / WAVE) + wave) % (unsigned int)ngroups);
+    if (contig) grp = (int)(blockIdx.x % XCDS);
+    auto plan_at = [contig, splits, np](int g, unsigned int k, unsigned int &lo, unsigned int &hi) {
+        return chunk_range(contig, splits, np, g, k, lo, hi);
+    };
+    unsigned int lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+    bool more = take_item(qg, ngroups, grp, NO_CHUNK, lane, plan_at, lo0, hi0);
+    if (more) more = take_item(qg, ngroups, grp, NO_CHUNK, lane, plan_at, lo1, hi1);
+    if (!more) lo1 = hi1 = 0;
+    lo0 = (unsigned int)__builtin_amdgcn_readfirstlane((int)lo0);
+    hi0 = (unsigned int)__builtin_amdgcn_readfirstlane((int)hi0);
+    lo1 = (unsigned int)__builtin_amdgcn_readfirstlane((int)lo1);
+    hi1 = (unsigned int)__builtin_amdgcn_readfirstlane((int)hi1);
+    long long w0 = lane < (int)(hi0 - lo0) ? plan[lo0 + lane] : 0;
+    long long w1 = lane < (int)(hi1 - lo1) ? plan[lo1 + lane] : 0;
+    EntryLane cur = entry_lane(hi0 > lo0 ? lane_word(w0, 0) : 0, lane, C, SPRW);
+    int64_t beg = 0, end = 0;
+    if (cur.active) {
+        beg = row_ptr[cur.row];
+        end = row_ptr[cur.row + 1];
+    }
+    // settle the prologue's reads here: the loop's first uses of them then wait
+    // for nothing that is issued inside the loop
+    __builtin_amdgcn_s_waitcnt(0x0F70);    // vmcnt(0)
+    while (hi0 > lo0) {
+        // lane 0 draws the ticket of the chunk after next; the wave reads it after this chunk
+        const bool drawing = more;
+        unsigned int pend_raw = 0;
+        if (drawing && lane == 0) pend_raw = atomicInc(qg + grp * QUEUE_PAD, 0xffffffffu);
+        const int len0 = (int)(hi0 - lo0);
+        for (int i = 0; i < len0; ++i) {
+            const long long e_n = i + 1 < len0 ? lane_word(w0, i + 1) : (hi1 > lo1 ? lane_word(w1, 0) : 0);
+            const EntryLane nxt = entry_lane(e_n, lane, C, SPRW);
+            int64_t beg_n = 0, end_n = 0;
+            if (nxt.active) {
+                beg_n = row_ptr[nxt.row];
+                end_n = row_ptr[nxt.row + 1];
+            }
+            const int64_t row = cur.row;
+            const bool hub = (end - beg) > hub_d;
+            const bool writer = cur.active && !hub && cur.slot == 0;
+            const int off = cur.chunk * VEC;
+            // the row's own values and 1/s do not depend on the gathers: load them first
+            A own[VEC];
+            A is = (A)0;
+            if (writer) {
+                load_vec<VEC>(xin + row * R + off, own);
+                is = inv_s[row];
+            }
+            A acc[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = (A)0;
+            if (cur.active && !hub) gather_rows<U, VEC>(col, w, xin, beg + cur.slot, end, cur.SPR, R, off, acc);
+            for (int d = cur.SPR >> 1; d >= 1; d >>= 1) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[q] += shfl_down(acc[q], d * C);
+            }
+            // every read of this entry (and the next entry's bounds) has landed by
+            // now; saying so keeps the next entry from waiting on this row's store
+            __builtin_amdgcn_s_waitcnt(0x0F70);    // vmcnt(0)
+            if (writer) {
+                A res[VEC];
+                if (end > beg) {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) res[q] = fma(omega, acc[q] * is, keep * own[q]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) res[q] = own[q];
+                }
+                store_vec<VEC>(xout + row * R + off, res);
+            }
+            cur = nxt;
+            beg = beg_n;
+            end = end_n;
+        }
+        lo0 = lo1;
+        hi0 = hi1;
+        w0 = w1;
+        lo1 = hi1 = 0;
+        if (drawing) {
+            const unsigned int pend = (unsigned int)__builtin_amdgcn_readfirstlane((int)pend_raw);
+            more = take_item(qg, ngroups, grp, pend, lane, plan_at, lo1, hi1);
+            if (!more) lo1 = hi1 = 0;
+            lo1 = (unsigned int)__builtin_amdgcn_readfirstlane((int)lo1);
+            hi1 = (unsigned int)__builtin_amdgcn_readfirstlane((int)hi1);
+        }
+        w1 = lane < (int)(hi1 - lo1) ? plan[lo1 + lane] : 0;
     }
 }
 
@@ -567,6 +828,7 @@ void sweep_plan_carve(Carver &c, int64_t n, int64_t ntiles_cap, SweepPlan &p) {
     p.tile_waves = c.take<unsigned int>(ntiles);
     p.tile_nnz = c.take<unsigned long long>(ntiles);
     p.splits = c.take<unsigned int>(XCDS + 1);
+    p.queue = c.take<unsigned int>((size_t)QUEUE_SLOTS * QUEUE_SET);
     const size_t nblk = scan_scratch_blocks(ntiles);
     p.scan.blk_v = c.take<unsigned int>(nblk);
     p.scan.blk_w = c.take<unsigned long long>(nblk);
@@ -576,6 +838,10 @@ void sweep_plan_carve(Carver &c, int64_t n, int64_t ntiles_cap, SweepPlan &p) {
 ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, const Segs &sg, hipStream_t st) {
     ad_status s;
     p.xcd_groups = (sg.tile_off && sg.G > 1) ? (int)XCDS : 1;
+    // every queue set starts at zero; each launch then clears the set the launch after next uses
+    p.turn = 0;
+    s = fill_i32((int32_t *)p.queue, 0, (int64_t)QUEUE_SLOTS * QUEUE_SET, st);
+    if (s != AD_OK) return s;
     if (build_hubs) {
         s = fill_i32((int32_t *)p.hub_count, 0, 1, st);
         if (s != AD_OK) return s;
@@ -603,24 +869,54 @@ ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, con
     return AD_OK;
 }
 
-constexpr int64_t MAX_MAIN_BLOCKS = 4096;   // persistent: waves loop over plan entries
+constexpr int64_t MAX_MAIN_BLOCKS = 4096;   // static walk: persistent, waves loop over plan entries
 
 template <typename Tin, typename Tout, typename A, int VEC>
 static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout,
                                 int R, const SweepPlan &pl, hipStream_t st) {
     const SweepShape &sh = pl.sh;
-    const int64_t main_blocks = std::min<int64_t>(MAX_MAIN_BLOCKS, ceil_div(g->n, BLOCK / WAVE));
-    // at most 2m / hub_d rows exceed hub_d; unknown d_max (0) keeps the bound
-    int64_t hub_blocks = 0;
-    if (g->d_max == 0 || g->d_max > sh.hub_d)
-        hub_blocks = round_up_xcds(std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(2 * g->m, sh.hub_d + 1))));
-    const int64_t grid = main_blocks + hub_blocks;
-    if (grid <= 0) return AD_OK;
+    if (pl.xcd_groups <= 1) {
+        const int64_t main_blocks = std::min<int64_t>(MAX_MAIN_BLOCKS, ceil_div(g->n, BLOCK / WAVE));
+        // at most 2m / hub_d rows exceed hub_d; unknown d_max (0) keeps the bound
+        int64_t hub_blocks = 0;
+        if (g->d_max == 0 || g->d_max > sh.hub_d)
+            hub_blocks =
+                round_up_xcds(std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(2 * g->m, sh.hub_d + 1))));
+        const int64_t grid = main_blocks + hub_blocks;
+        if (grid <= 0) return AD_OK;
+        TraceScope trace("k_sweep", st);
+        hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC, SWEEP_UNROLL, false>), dim3((unsigned)grid), dim3(BLOCK), 0,
+                           st, g->n, g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C, sh.hub_d, sh.SPRW,
+                           (int)hub_blocks, pl.hub_list, pl.hub_count, pl.plan, pl.plan_count, pl.splits,
+                           pl.xcd_groups, (unsigned int *)nullptr, (unsigned int *)nullptr);
+        AD_LAUNCH_CHECK("k_sweep");
+        return AD_OK;
+    }
+    auto kern = k_sweep<Tin, Tout, A, VEC, SWEEP_UNROLL, true>;
+    // workgroups the device holds at once (per device, found once): the queues
+    // hand out all work, so a larger grid would only add idle workgroups
+    static std::atomic<int> resident[MAX_DEVICES];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) dev = 0;
+    int cap = resident[dev].load(std::memory_order_relaxed);
+    if (cap <= 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 1;
+        (void)hipGetLastError();
+        cap = per_cu * cus;
+        resident[dev].store(cap, std::memory_order_relaxed);
+    }
+    const int64_t grid = std::min<int64_t>(cap, std::max<int64_t>(XCDS, ceil_div(g->n, BLOCK / WAVE)));
+    unsigned int *use = pl.queue + (size_t)(pl.turn % QUEUE_SLOTS) * QUEUE_SET;
+    unsigned int *clear = pl.queue + (size_t)((pl.turn + QUEUE_SLOTS - 1) % QUEUE_SLOTS) * QUEUE_SET;
+    ++pl.turn;
     TraceScope trace("k_sweep", st);
-    hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC, SWEEP_UNROLL>), dim3((unsigned)grid), dim3(BLOCK), 0, st,
-                       g->n, g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C, sh.hub_d, sh.SPRW,
-                       (int)hub_blocks, pl.hub_list, pl.hub_count, pl.plan, pl.plan_count, pl.splits,
-                       pl.xcd_groups);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(BLOCK), 0, st, g->n, g->row_ptr, g->col, g->w, inv_s, omega,
+                       xin, xout, R, sh.C, sh.hub_d, sh.SPRW, 0, pl.hub_list, pl.hub_count, pl.plan, pl.plan_count,
+                       pl.splits, pl.xcd_groups, use, clear);
     AD_LAUNCH_CHECK("k_sweep");
     return AD_OK;
 }
