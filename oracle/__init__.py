@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE.  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package; the library never does, and this
 package imports nothing from the library.  Every function here is a thin
 ctypes wrapper around the C oracle, which follows the paper's Algorithm 1
-(ComputeAlgDist), Algorithm 3 (Sparsify) and the binary-search fitting of
-Section 6.2 in double precision.
+(ComputeAlgDist), Algorithm 3 (Sparsify), Algorithm 4 (SparsifyB) and the binary-search
+fitting of Section 6.2 in double precision.
 
 Parity status: every function is pinned by tests that do not reuse its own
 formulas (closed forms, library routines, brute force); the one reading
@@ -26,8 +26,14 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 # Readings that only this spec fixes (the paper does not): the value of eps,
 # min-max (rather than max-abs) rescaling, floor (rather than ceil/round)
-# in the per-vertex budget, and the Philox stream layout.
-PINS = {"parity_unpinned": ["eps value", "min-max rescale", "floor in d^e", "start-vector stream layout"]}
+# in the per-vertex budget, the Philox stream layout, and for SparsifyB the
+# random neighbour order, the round-robin reading of its selection step and
+# the single-precision sigma.  Tests pin what follows from these readings
+# (closed forms, invariants, special cases), not the readings themselves.
+PINS = {"parity_unpinned": ["eps value", "min-max rescale", "floor in d^e", "start-vector stream layout",
+                            "SparsifyB random order (vertex key stream, priority hash)",
+                            "SparsifyB round-robin reading of 'randomly select bins and edges'",
+                            "SparsifyB single-precision sigma"]}
 
 LOCAL = 0
 GLOBAL = 1
@@ -73,6 +79,16 @@ def _load():
     lib.orc_fit_exponent.argtypes = [i64, P, P, P, P, i64, P, i32, f64, P, P]
     lib.orc_fit_exponent.restype = f64
     lib.orc_grad_weights.argtypes = [i64, P, P, P, P, P, i64, i32, i32, f64, u64, u64, P, P, P]
+    lib.orc_bin_vertex_key.argtypes = [u64, u64, i32]
+    lib.orc_bin_vertex_key.restype = ctypes.c_uint32
+    lib.orc_bin_priority.argtypes = [ctypes.c_uint32, i32]
+    lib.orc_bin_priority.restype = ctypes.c_uint32
+    lib.orc_bin_layout.argtypes = [i64, P, P, P, P, P]
+    lib.orc_binned_choices.argtypes = [i64, P, P, P, P, P, u64, u64, f64, P]
+    lib.orc_sparsify_binned.argtypes = [i64, P, P, P, P, i64, P, u64, u64, f64, P]
+    lib.orc_sparsify_binned.restype = i64
+    lib.orc_fit_exponent_binned.argtypes = [i64, P, P, P, P, i64, P, u64, u64, f64, P, P]
+    lib.orc_fit_exponent_binned.restype = f64
     _lib = lib
     return lib
 
@@ -199,3 +215,55 @@ def grad_weights(g, c: np.ndarray, R: int, k: int, omega: float = 0.5, seed: int
                          _p(g.orig_id), g.m, R, k, omega, seed, graph_id, _p(_c(x0, np.float64)),
                          _p(cc), _p(out))
     return out
+
+
+def bin_vertex_key(seed: int, vertex_key: int, graph_id: int = 0) -> int:
+    """Vertex i's 32-bit key for its random neighbour order (SparsifyB)."""
+    return int(_load().orc_bin_vertex_key(seed, graph_id, int(vertex_key)))
+
+
+def bin_priority(vertex_key_bits: int, neighbour_key: int) -> int:
+    """Priority of a neighbour in a vertex's random order (SparsifyB)."""
+    return int(_load().orc_bin_priority(int(vertex_key_bits) & 0xffffffff, int(neighbour_key)))
+
+
+def bin_layout(g, rho: np.ndarray):
+    """Algorithm 4's binning step: (bin[2m] per CSR entry, nbins[n])."""
+    lib = _load()
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    b = np.zeros(len(g.col), dtype=np.int32)
+    nb = np.zeros(g.n, dtype=np.int64)
+    lib.orc_bin_layout(g.n, _p(g.row_ptr), _p(g.eid), _p(r), _p(b), _p(nb))
+    return b, nb
+
+
+def binned_choices(g, rho: np.ndarray, e: float, seed: int, graph_id: int = 0) -> np.ndarray:
+    """Algorithm 4's per-vertex choices: chosen[2m] per CSR entry (1 when the
+    entry's row vertex selects that edge)."""
+    lib = _load()
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    ch = np.zeros(len(g.col), dtype=np.uint8)
+    lib.orc_binned_choices(g.n, _p(g.row_ptr), _p(g.col), _p(g.eid), _p(g.orig_id), _p(r), seed, graph_id,
+                           e, _p(ch))
+    return ch
+
+
+def sparsify_binned(g, rho: np.ndarray, e: float, seed: int, graph_id: int = 0):
+    """Algorithm 4 (SparsifyB) at exponent e.  Returns (keep[m] uint8, n_kept)."""
+    lib = _load()
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    keep = np.zeros(g.m, dtype=np.uint8)
+    kept = lib.orc_sparsify_binned(g.n, _p(g.row_ptr), _p(g.col), _p(g.eid), _p(g.orig_id), g.m,
+                                   _p(r), seed, graph_id, e, _p(keep))
+    return keep, int(kept)
+
+
+def fit_exponent_binned(g, rho: np.ndarray, target: float, seed: int, graph_id: int = 0):
+    """Binary-search fitting of e for SparsifyB.  Returns (e, keep[m], n_kept)."""
+    lib = _load()
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    keep = np.zeros(g.m, dtype=np.uint8)
+    kept = ctypes.c_int64()
+    e = lib.orc_fit_exponent_binned(g.n, _p(g.row_ptr), _p(g.col), _p(g.eid), _p(g.orig_id), g.m,
+                                    _p(r), seed, graph_id, target, _p(keep), ctypes.byref(kept))
+    return float(e), keep, int(kept.value)

@@ -322,6 +322,225 @@ double orc_fit_exponent(int64_t n, const int64_t *row_ptr, const int32_t *col,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Sparsify with binning (Algorithm 4, SparsifyB; bin rule of Section 4).
+ *
+ * The paper spreads N_i's distances over bins of width h = 3.5 sigma /
+ * d_i^(1/3) (Scott's rule for a sample of d_i values), (max - min) / h of
+ * them, and takes edges from all bins at random, up to d_i^e.  Readings:
+ *   - the values binned are the per-edge distances handed in (rho, or its
+ *     normalised form), sigma their population standard deviation over N_i
+ *     (two passes in double, then rounded to single precision so that the
+ *     bins do not depend on summation order), min and max exact;
+ *   - h = (3.5 sigma) / cbrt(d_i) in double; number of bins
+ *     B_i = max(1, ceil((max - min) / h)), or 1 when h == 0; entry q of
+ *     N_i falls in bin min(B_i - 1, floor((rho_q - min) / h));
+ *   - random order: vertex i draws a 32-bit key K_i, the low half of word 0
+ *     of Philox4x64-10 with key (seed, graph_id) and counter (orig_id[i], 0,
+ *     1, 0); its neighbour j gets priority u = fmix32(orig_id[j] ^ K_i),
+ *     fmix32 being the 32-bit finalizer of MurmurHash3 (Appleby), a
+ *     bijection, so priorities within N_i are distinct;
+ *   - "randomly select bins and edges": rounds r = 0, 1, ...; in each round
+ *     the non-empty bins are visited in increasing order of their smallest
+ *     priority, and each bin still holding an unselected edge gives up the
+ *     one of smallest priority; selection stops at c_i = budget(d_i, e)
+ *     edges.  Bins are sampled evenly and every bin gets an edge before any
+ *     bin gets a second; the selected sets grow with e, so the retention
+ *     fit of Algorithm 3 applies unchanged;
+ *   - an edge is kept when either endpoint selects it.                      */
+
+static uint32_t orc_fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+uint32_t orc_bin_vertex_key(uint64_t seed, uint64_t graph_id, int32_t vertex_key)
+{
+    uint64_t ctr[4] = {(uint64_t)(uint32_t)vertex_key, 0, 1, 0};
+    uint64_t key[2] = {seed, graph_id};
+    uint64_t out[4];
+    orc_philox4x64_10(ctr, key, out);
+    return (uint32_t)out[0];
+}
+
+uint32_t orc_bin_priority(uint32_t vertex_key_bits, int32_t neighbour_key)
+{
+    return orc_fmix32((uint32_t)neighbour_key ^ vertex_key_bits);
+}
+
+/* Bins of N_i: nbins (returned) and bin[q] for q < d (values v[q]). */
+static int64_t orc_bins_of(int64_t d, const double *v, int32_t *bin)
+{
+    double mn = v[0], mx = v[0], sum = 0.0;
+    for (int64_t q = 0; q < d; ++q) {
+        if (v[q] < mn) mn = v[q];
+        if (v[q] > mx) mx = v[q];
+        sum += v[q];
+    }
+    double mean = sum / (double)d, ss = 0.0;
+    for (int64_t q = 0; q < d; ++q) ss += (v[q] - mean) * (v[q] - mean);
+    double sigma = (double)(float)sqrt(ss / (double)d);
+    double h = (3.5 * sigma) / cbrt((double)d);
+    int64_t nb = 1;
+    if (h > 0.0) {
+        double k = ceil((mx - mn) / h);
+        nb = k < 1.0 ? 1 : (int64_t)k;
+    }
+    for (int64_t q = 0; q < d; ++q) {
+        int64_t b = 0;
+        if (h > 0.0) {
+            b = (int64_t)floor((v[q] - mn) / h);
+            if (b > nb - 1) b = nb - 1;
+        }
+        bin[q] = (int32_t)b;
+    }
+    return nb;
+}
+
+/* The binning step alone, per CSR entry: bin[2m] and nbins[n]. */
+void orc_bin_layout(int64_t n, const int64_t *row_ptr, const int32_t *eid, const double *rho,
+                    int32_t *bin, int64_t *nbins)
+{
+#pragma omp parallel
+    {
+        double *v = NULL;
+        int64_t cap = 0;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
+            nbins[i] = 0;
+            if (d == 0) continue;
+            if (d > cap) { free(v); cap = d; v = (double *)malloc(sizeof(double) * (size_t)cap); }
+            for (int64_t q = 0; q < d; ++q) v[q] = rho[eid[beg + q]];
+            nbins[i] = orc_bins_of(d, v, bin + beg);
+        }
+        free(v);
+    }
+}
+
+typedef struct { int32_t bin; uint32_t u; int64_t pos; } orc_bitem;
+typedef struct { uint32_t first_u; int64_t start, size; } orc_bin;
+
+static int orc_cmp_bin_u(const void *a, const void *b)
+{
+    const orc_bitem *x = (const orc_bitem *)a, *y = (const orc_bitem *)b;
+    if (x->bin != y->bin) return x->bin < y->bin ? -1 : 1;
+    return (x->u > y->u) - (x->u < y->u);
+}
+
+static int orc_cmp_first_u(const void *a, const void *b)
+{
+    const orc_bin *x = (const orc_bin *)a, *y = (const orc_bin *)b;
+    return (x->first_u > y->first_u) - (x->first_u < y->first_u);
+}
+
+/* Each vertex's own choices at exponent e: chosen[p] = 1 for the CSR
+ * entries p that vertex row(p) selects.                                    */
+void orc_binned_choices(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *eid,
+                        const int32_t *orig_id, const double *rho, uint64_t seed, uint64_t graph_id,
+                        double e, uint8_t *chosen)
+{
+#pragma omp parallel
+    {
+        orc_bitem *it = NULL;
+        orc_bin *bins = NULL;
+        double *v = NULL;
+        int32_t *bin = NULL;
+        int64_t cap = 0;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
+            if (d == 0) continue;
+            if (d > cap) {
+                free(it); free(bins); free(v); free(bin);
+                cap = d;
+                it = (orc_bitem *)malloc(sizeof(orc_bitem) * (size_t)cap);
+                bins = (orc_bin *)malloc(sizeof(orc_bin) * (size_t)cap);
+                v = (double *)malloc(sizeof(double) * (size_t)cap);
+                bin = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+            }
+            for (int64_t q = 0; q < d; ++q) {
+                v[q] = rho[eid[beg + q]];
+                chosen[beg + q] = 0;
+            }
+            orc_bins_of(d, v, bin);
+            uint32_t K = orc_bin_vertex_key(seed, graph_id, orig_id ? orig_id[i] : (int32_t)i);
+            for (int64_t q = 0; q < d; ++q) {
+                int32_t j = col[beg + q];
+                it[q].bin = bin[q];
+                it[q].u = orc_bin_priority(K, orig_id ? orig_id[j] : j);
+                it[q].pos = beg + q;
+            }
+            /* each bin's edges in priority order, then the bins by their first priority */
+            qsort(it, (size_t)d, sizeof(orc_bitem), orc_cmp_bin_u);
+            int64_t nb = 0;
+            for (int64_t q = 0; q < d; ++q) {
+                if (q == 0 || it[q].bin != it[q - 1].bin) {
+                    bins[nb].first_u = it[q].u;
+                    bins[nb].start = q;
+                    bins[nb].size = 0;
+                    ++nb;
+                }
+                bins[nb - 1].size++;
+            }
+            qsort(bins, (size_t)nb, sizeof(orc_bin), orc_cmp_first_u);
+            /* rounds over the bins until c_i edges are taken */
+            int64_t c = orc_budget(d, e), taken = 0;
+            for (int64_t r = 0; taken < c; ++r)
+                for (int64_t b = 0; b < nb && taken < c; ++b)
+                    if (r < bins[b].size) {
+                        chosen[it[bins[b].start + r].pos] = 1;
+                        ++taken;
+                    }
+        }
+        free(it); free(bins); free(v); free(bin);
+    }
+}
+
+/* SparsifyB at exponent e: keep[m] = 1 when either endpoint chooses the
+ * edge; returns the kept count.                                            */
+int64_t orc_sparsify_binned(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                            const int32_t *eid, const int32_t *orig_id, int64_t m,
+                            const double *rho, uint64_t seed, uint64_t graph_id, double e,
+                            uint8_t *keep)
+{
+    memset(keep, 0, (size_t)m);
+    int64_t nnz = row_ptr[n];
+    uint8_t *chosen = (uint8_t *)malloc(nnz > 0 ? (size_t)nnz : 1);
+    orc_binned_choices(n, row_ptr, col, eid, orig_id, rho, seed, graph_id, e, chosen);
+    for (int64_t p = 0; p < nnz; ++p)
+        if (chosen[p]) keep[eid[p]] = 1;
+    free(chosen);
+    int64_t kept = 0;
+    for (int64_t q = 0; q < m; ++q) kept += keep[q];
+    return kept;
+}
+
+/* The binary-search fitting of e (as orc_fit_exponent) for SparsifyB. */
+double orc_fit_exponent_binned(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                               const int32_t *eid, const int32_t *orig_id, int64_t m,
+                               const double *rho, uint64_t seed, uint64_t graph_id, double target,
+                               uint8_t *keep, int64_t *n_kept)
+{
+    if (m == 0) { if (n_kept) *n_kept = 0; return 0.0; }
+    int64_t kept = orc_sparsify_binned(n, row_ptr, col, eid, orig_id, m, rho, seed, graph_id, 0.0, keep);
+    if ((double)kept / (double)m >= target) { if (n_kept) *n_kept = kept; return 0.0; }
+    double lo = 0.0, hi = 1.0;
+    for (int step = 0; step < 40; ++step) {
+        double mid = 0.5 * (lo + hi);
+        kept = orc_sparsify_binned(n, row_ptr, col, eid, orig_id, m, rho, seed, graph_id, mid, keep);
+        if ((double)kept / (double)m >= target) hi = mid; else lo = mid;
+    }
+    kept = orc_sparsify_binned(n, row_ptr, col, eid, orig_id, m, rho, seed, graph_id, hi, keep);
+    if (n_kept) *n_kept = kept;
+    return hi;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Reverse-mode derivative of L = sum_e c_e rho_e with respect to the edge
  * weights w_e (w_ij = w_ji = w_e), taken through the k sweeps, the rescale
  * (its min and max as functions of x^(k)) and the distance.  Written by the
