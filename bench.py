@@ -263,6 +263,26 @@ def run_chung_lu(args, api, torch, dev):
     copy_gbs = 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9
     del src, dst
 
+    # selection with binning (Algorithm 4) fitted to the same retention, on the step's distances
+    ws_b = api._workspace(api.sparsify_binned_workspace_bytes(dg), dev)
+    keep_b = torch.empty(m, dtype=torch.uint8, device=dev)
+    nk_b = torch.empty(1, dtype=torch.int64, device=dev)
+    binned = {}
+
+    def binned_fit():
+        _, _, e_b = api.sparsify_binned(dg, rho, c["bin_seed"], target=TARGET, ws=ws_b, keep=keep_b, n_kept=nk_b)
+        binned["e"] = e_b
+
+    binned_fit()
+    b_ms, b_kern = traced(api, timer, binned_fit, max(1, min(args.steps, 5)))
+    kept_b = int(nk_b.item())
+    binned.update(ms=b_ms, kept=kept_b, ratio=kept_b / m,
+                  breakdown_ms={k_: v[1] / max(1, min(args.steps, 5)) for k_, v in sorted(b_kern.items())},
+                  what=(f"Algorithm 4 (bins by Scott's rule per vertex, round-robin over the bins in a "
+                        f"seeded random order) with e fitted to {int(TARGET * 100)}% retention, on the "
+                        "step's own distances; synchronises for the fit"))
+    del ws_b
+
     # context: the sweep's neighbour-row gathers alone, with nothing else asked of the
     # memory system (the irregular path's practical ceiling), and the vendor SpMM
     sweep_ms = roof["avg_launch_ms"]
@@ -306,6 +326,7 @@ def run_chung_lu(args, api, torch, dev):
         copy_ceiling_GBs=copy_gbs,
         gather_ceiling=gather,
         vendor_spmm=spmm,
+        binned_selection=binned,
         traffic_over_algorithmic=(roof["traffic"] / sb) if roof["traffic"] else None,
         sweep_updates_per_s=nnz * R / (roof["avg_launch_ms"] * 1e-3) if roof["avg_launch_ms"] else None,
         fit={"e_local": fit["e_local"], "e_global": fit["e_global"], "kept_local": kept_l,

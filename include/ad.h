@@ -225,6 +225,39 @@ ad_status ad_normalize_dist(const ad_graph *g, ad_dtype rho_dtype, const void *r
                             int32_t by_strength, double eps, void *rho_out, void *ws,
                             size_t ws_bytes, hipStream_t stream);
 
+/* Workspace bytes for ad_sparsify_binned. */
+size_t ad_sparsify_binned_workspace_size(const ad_graph *g);
+
+/* Algorithm 4 (SparsifyB): selection with binning (bin rule of Section 4).
+ * Every vertex i spreads the distances of its d_i edges over bins of width
+ *     h = 3.5 sigma / cbrt(d_i)   (Scott's rule),
+ * sigma the population standard deviation of those distances (computed in
+ * double, rounded to single precision), B_i = max(1, ceil((max - min) / h))
+ * bins (one when h == 0), entry q in bin min(B_i - 1, floor((rho_q - min) /
+ * h)); cbrt is the C library's.  It then takes budget(d_i, e) of its edges
+ * (budget as ad_budget_table) in rounds: in round r every non-empty bin, in
+ * increasing order of its smallest priority, gives up its edge of (r+1)-th
+ * smallest priority, so all bins give one edge before any gives two.  The
+ * priority of neighbour j is fmix32(orig_id[j] ^ K_i) (fmix32: the 32-bit
+ * finalizer of MurmurHash3), K_i the low 32 bits of word 0 of
+ * Philox4x64-10 with key (seed, graph_id) and counter (orig_id[i], 0, 1, 0).
+ * keep[e] = 1 when either endpoint takes edge e.
+ *   rho: [m] distances (AD_F32 or AD_F64), e.g. from ad_edge_dist or
+ *        ad_normalize_dist.
+ *   target == 0: fixed exponent e in [0, 1]; target in (0, 1]: e is fitted
+ *        as in ad_sparsify_fit (the taken sets grow with e) and returned
+ *        through e_used_host, which is then required.
+ *   n_kept: device int64, receives sum(keep).  e_used_host may be NULL for a
+ *        fixed e (else it receives e).
+ * The graph needs d_max set.  SYNCHRONISES `stream` (host tables by degree
+ * are uploaded, and a fit reads counts back); not for stream capture.
+ * Errors: AD_ERR_INVALID_ARG for bad arguments, AD_ERR_WORKSPACE when ws is
+ * smaller than ad_sparsify_binned_workspace_size or not 256-byte aligned. */
+ad_status ad_sparsify_binned(const ad_graph *g, ad_dtype rho_dtype, const void *rho,
+                             uint64_t seed, uint64_t graph_id, double e, double target,
+                             uint8_t *keep, int64_t *n_kept, double *e_used_host, void *ws,
+                             size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------- adjoint --- */
 
 /* Workspace bytes for ad_relax_backward. */

@@ -73,6 +73,9 @@ def _load_lib():
         "ad_sparsify_fit_both_workspace_size": (S, [G]),
         "ad_normalize_dist_workspace_size": (S, [G]),
         "ad_normalize_dist": (st, [G, ctypes.c_int, P, ctypes.c_int32, f64, P, P, S, P]),
+        "ad_sparsify_binned_workspace_size": (S, [G]),
+        "ad_sparsify_binned": (st, [G, ctypes.c_int, P, ctypes.c_uint64, ctypes.c_uint64, f64, f64, P, P,
+                                    ctypes.POINTER(ctypes.c_double), P, S, P]),
         "ad_sparsify_fit_both": (st, [G, ctypes.c_int, P, f64, P, P, P, P, P, S, P]),
         "ad_relax_backward_workspace_size": (S, [G, O]),
         "ad_relax_backward": (st, [G, O, P, P, P, P, P, P, S, P]),
@@ -500,3 +503,30 @@ def sparsify_graph(dg: DeviceGraph, R: int, k: int, orient: int, e: Optional[flo
         keep, n_kept = sparsify(dg, rho, orient, e)
         e_used = e
     return {"rho": rho, "keep": keep, "n_kept": n_kept, "e": e_used, "relax": res}
+
+
+def sparsify_binned_workspace_bytes(dg: DeviceGraph) -> int:
+    g = dg.abi()
+    return int(lib.ad_sparsify_binned_workspace_size(ctypes.byref(g)))
+
+
+def sparsify_binned(dg: DeviceGraph, rho: torch.Tensor, seed: int, e: float = 0.5, target: float = 0.0,
+                    graph_id: int = 0, ws: Optional[torch.Tensor] = None, keep: Optional[torch.Tensor] = None,
+                    n_kept: Optional[torch.Tensor] = None):
+    """Algorithm 4, selection with binning (``ad_sparsify_binned``): at the
+    fixed exponent e, or with e fitted to `target` when target > 0.  Returns
+    (keep, n_kept, e_used).  Synchronises the current stream."""
+    dev = rho.device
+    g = dg.abi()
+    if ws is None:
+        ws = _workspace(lib.ad_sparsify_binned_workspace_size(ctypes.byref(g)), dev)
+    if keep is None:
+        keep = torch.empty(dg.m, dtype=torch.uint8, device=dev)
+    if n_kept is None:
+        n_kept = torch.empty(1, dtype=torch.int64, device=dev)
+    e_used = ctypes.c_double(-1.0)
+    dt = AD_F64 if rho.dtype == torch.float64 else AD_F32
+    _check(lib.ad_sparsify_binned(ctypes.byref(g), dt, _ptr(rho), int(seed) & (2 ** 64 - 1),
+                                  int(graph_id) & (2 ** 64 - 1), float(e), float(target), _ptr(keep),
+                                  _ptr(n_kept), ctypes.byref(e_used), _ptr(ws), ws.numel(), _stream()))
+    return keep, n_kept, e_used.value

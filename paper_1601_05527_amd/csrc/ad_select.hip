@@ -298,6 +298,15 @@ __device__ __forceinline__ unsigned long long sort_key(float r, int32_t id, int 
     return ((unsigned long long)b << 32) | (unsigned long long)(uint32_t)id;
 }
 
+// Key of CSR entry p (edge e, neighbour id `id`): the caller's own 64-bit
+// key when `keys` is given (distinct within each row and below ~0; the row
+// order is then ascending keys), else the distance key above.
+__device__ __forceinline__ unsigned long long entry_key(const unsigned long long *__restrict__ keys,
+                                                        const float *__restrict__ rho, int64_t p, int32_t e,
+                                                        int32_t id, int orient) {
+    return keys ? keys[p] : sort_key(rho[e], id, orient);
+}
+
 // Rank of an entry in its row of d entries, in both orders of Algorithm 3:
 // LOCAL (rho ascending) and GLOBAL (rho descending), ties by neighbour id
 // ascending in both.  With lt = #{rho' < rho}, eq = #{rho' == rho} (itself
@@ -326,7 +335,8 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_packed(
     const long long *__restrict__ plan, const unsigned int *__restrict__ plan_count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const Tr *__restrict__ rho, Emit em) {
+    const int32_t *__restrict__ col_orig, const Tr *__restrict__ rho,
+    const unsigned long long *__restrict__ keys, Emit em) {
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned int np = *plan_count;
     const unsigned int nwaves = gridDim.x * (SBLOCK / WAVE);
@@ -357,7 +367,7 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_packed(
         if (on) {
             my_j = col[e];
             my_e = eid[e];
-            my_rho = rho[my_e];
+            if (!keys) my_rho = rho[my_e];
             my_id = nbr_id(e, my_j, col_orig, orig_id);
         }
         // every lane walks its own row: as many steps as the wave's longest row
@@ -365,7 +375,8 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_packed(
         for (int o = WAVE / 2; o >= 1; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, WAVE));
         if constexpr (sizeof(Tr) == 4) {
             // FP32: the row orders are those of 64-bit keys; GLOBAL flips the rho half
-            const unsigned long long key = sort_key((float)my_rho, my_id, em.both ? AD_LOCAL : em.orient);
+            const unsigned long long key =
+                keys ? (on ? keys[e] : 0ull) : sort_key((float)my_rho, my_id, em.both ? AD_LOCAL : em.orient);
             const unsigned long long keyg = key ^ KEY_FLIP;
             int r1 = 0, r2 = 0;
             if (em.both) {
@@ -477,7 +488,8 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_wave(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, Emit em) {
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho,
+    const unsigned long long *__restrict__ keys, Emit em) {
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned int nr = *count;
     const unsigned int waves = gridDim.x * (SBLOCK / WAVE);
@@ -494,7 +506,7 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_wave(
             if (q < d) {
                 jj[t] = col[beg + q];
                 ee[t] = eid[beg + q];
-                key[t] = sort_key(rho[ee[t]], nbr_id(beg + q, jj[t], col_orig, orig_id), orient);
+                key[t] = entry_key(keys, rho, beg + q, ee[t], nbr_id(beg + q, jj[t], col_orig, orig_id), orient);
             } else {
                 jj[t] = 0;
                 ee[t] = 0;
@@ -551,7 +563,8 @@ __global__ __launch_bounds__(TB) void k_rank_bitonic(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, Emit em) {
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho,
+    const unsigned long long *__restrict__ keys, Emit em) {
     __shared__ unsigned long long key[P_MAX];
     __shared__ uint16_t idx[P_MAX];
     const unsigned int nr = *count;
@@ -565,7 +578,7 @@ __global__ __launch_bounds__(TB) void k_rank_bitonic(
         for (int t = threadIdx.x; t < P; t += TB) {
             if (t < d) {
                 int32_t j = col[beg + t];
-                key[t] = sort_key(rho[eid[beg + t]], nbr_id(beg + t, j, col_orig, orig_id), orient);
+                key[t] = entry_key(keys, rho, beg + t, eid[beg + t], nbr_id(beg + t, j, col_orig, orig_id), orient);
             } else {
                 key[t] = ~0ull;
             }
@@ -727,7 +740,8 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, int orient, HubScratch hs) {
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho,
+    const unsigned long long *__restrict__ keys, int orient, HubScratch hs) {
     __shared__ unsigned long long samp[HUB_SAMPLE];
     __shared__ uint32_t cnt[HUB_MAX_B];
     __shared__ uint32_t wsum[HUB_TB / WAVE];
@@ -744,7 +758,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         const int B = (int)min((int64_t)(S / HUB_MIN_SP), (d + HUB_BUCKET - 1) / HUB_BUCKET);
         for (int t = threadIdx.x; t < S; t += HUB_TB) {
             const int64_t p = beg + ((int64_t)t * d) / S;
-            samp[t] = sort_key(rho[eid[p]], nbr_id(p, col[p], col_orig, orig_id), orient);
+            samp[t] = entry_key(keys, rho, p, eid[p], nbr_id(p, col[p], col_orig, orig_id), orient);
         }
         for (int b = threadIdx.x; b < B; b += HUB_TB) cnt[b] = 0;
         __syncthreads();
@@ -765,7 +779,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         }
         for (int64_t q = threadIdx.x; q < d; q += HUB_TB) {
             const int64_t p = beg + q;
-            const unsigned long long k = sort_key(rho[eid[p]], nbr_id(p, col[p], col_orig, orig_id), orient);
+            const unsigned long long k = entry_key(keys, rho, p, eid[p], nbr_id(p, col[p], col_orig, orig_id), orient);
             atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
         }
         __syncthreads();
@@ -787,7 +801,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         __syncthreads();
         for (int64_t q = threadIdx.x; q < d; q += HUB_TB) {
             const int64_t p = beg + q;
-            const unsigned long long k = sort_key(rho[eid[p]], nbr_id(p, col[p], col_orig, orig_id), orient);
+            const unsigned long long k = entry_key(keys, rho, p, eid[p], nbr_id(p, col[p], col_orig, orig_id), orient);
             const uint32_t at = atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
             hs.key[beg + at] = k;
             hs.pos[beg + at] = (uint32_t)q;
@@ -1121,7 +1135,8 @@ static void budget_table(int32_t d_max, double e, std::vector<int32_t> &t) {
 
 // Rank every entry of every row and emit per `em`.
 template <typename Tr>
-static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, const SelLayout &L, hipStream_t st) {
+static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, const SelLayout &L, hipStream_t st,
+                          const unsigned long long *keys = nullptr) {
     const int64_t n = g->n;
     if (n <= 0 || g->m <= 0) return AD_OK;
     TraceScope trace("k_rank", st);
@@ -1138,7 +1153,7 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
     AD_LAUNCH_CHECK("k_rank_plan");
     const unsigned packed_blocks = (unsigned)std::min<int64_t>(4096, ceil_div(n, SBLOCK / WAVE));
     hipLaunchKernelGGL((k_rank_packed<Tr>), dim3(packed_blocks), dim3(SBLOCK), 0, st, L.plan, L.plan_count,
-                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rho, em);
+                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rho, keys, em);
     AD_LAUNCH_CHECK("k_rank_packed");
     if (g->d_max <= 64) return AD_OK;
 
@@ -1152,7 +1167,7 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
     for (int k = 0; k < NCLASS; ++k) lst[k] = L.lists + L.cb.off[k];
     if (sizeof(Tr) == 4) {
         const float *rf = (const float *)rho;
-#define AD_RANK_ARGS_F g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, em
+#define AD_RANK_ARGS_F g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, em
         if (g->d_max > 64)
             hipLaunchKernelGGL((k_rank_wave<2>), dim3(grid), dim3(SBLOCK), 0, st, lst[0], &L.cnt[0], AD_RANK_ARGS_F);
         if (g->d_max > 128)
@@ -1194,7 +1209,8 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                 for (int k = HUB_CLASS; k < NCLASS; ++k) {
                     if (g->d_max <= CLASS_LO[k]) break;
                     hipLaunchKernelGGL(k_hub_partition, dim3(512), dim3(HUB_TB), 0, st, lst[k], &L.cnt[k],
-                                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, one.orient, L.hub);
+                                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, one.orient,
+                                       L.hub);
                     AD_LAUNCH_CHECK("k_hub_partition");
                 }
                 hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, st, g->row_ptr, g->col, g->eid, one,
@@ -1607,4 +1623,302 @@ extern "C" ad_status ad_sparsify_fit_both(const ad_graph *g, ad_dtype rho_dtype,
     if (!e_used_host) return fail(AD_ERR_INVALID_ARG, "e_used_host is NULL");
     return sparsify_fit_impl(g, rho_dtype, rho, AD_LOCAL, true, target, keep_local, keep_global, n_kept,
                              e_used_host, L, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Sparsify with binning (Algorithm 4, SparsifyB; bin rule of Section 4).
+//
+// Readings (shared with the oracle, which is written separately):
+//   - the values binned are the per-edge distances handed in; sigma is their
+//     population standard deviation over N_i (two passes in double, rounded
+//     to single precision so that the bins do not depend on summation
+//     order), min and max are exact;
+//   - h = (3.5 sigma) / cbrt(d_i) in double, with cbrt from the host's C
+//     library (a table by degree); B_i = max(1, ceil((max - min) / h)) bins
+//     (1 when h == 0); entry q falls in bin min(B_i - 1, floor((rho_q -
+//     min) / h));
+//   - random order: vertex i's 32-bit key K_i is the low half of word 0 of
+//     Philox4x64-10 with key (seed, graph_id) and counter (orig_id[i], 0, 1,
+//     0); neighbour j's priority is fmix32(orig_id[j] ^ K_i), fmix32 being
+//     the 32-bit finalizer of MurmurHash3 (a bijection: priorities within a
+//     row are distinct);
+//   - selection: rounds r = 0, 1, ...; in each round the non-empty bins, in
+//     increasing order of their smallest priority, give up their unselected
+//     edge of smallest priority, until c_i = budget(d_i, e) edges are taken;
+//     an edge is kept when either endpoint takes it.
+//
+// On the device the rounds become two rankings of 64-bit keys per row: first
+// (bin, priority), whose rank p of an entry minus the rank of its bin's
+// first entry is the entry's round r; then (r, smallest priority of the
+// bin), whose rank is the entry's place in the selection order.  The rank
+// kernels of Algorithm 3 do both; the budget and the retention fit then
+// apply unchanged (the selected sets grow with e).
+// ---------------------------------------------------------------------------
+
+namespace ad {
+
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// Per row (one wave per row): bins by Scott's rule, the first key (bin << 32 |
+// priority) of every entry, and the row's per-bin slots [beg, beg + B_i) of
+// first_u / first_pos set to ~0 for the atomic minima that follow.
+template <typename Tr>
+__global__ __launch_bounds__(SBLOCK) void k_bin_keys(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const int32_t *__restrict__ eid,
+                                                     const int32_t *__restrict__ orig_id,
+                                                     const int32_t *__restrict__ col_orig,
+                                                     const Tr *__restrict__ rho, const double *__restrict__ cbrt_tab,
+                                                     int64_t d_max, uint64_t seed, uint64_t graph_id,
+                                                     unsigned long long *__restrict__ keys,
+                                                     uint32_t *__restrict__ first_u, uint32_t *__restrict__ first_pos) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (SBLOCK / WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        const int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
+        if (d == 0) continue;
+        double mn = INFINITY, mx = -INFINITY, sum = 0.0;
+        for (int64_t q = lane; q < d; q += WAVE) {
+            const double v = (double)rho[eid[beg + q]];
+            mn = fmin(mn, v);
+            mx = fmax(mx, v);
+            sum += v;
+        }
+        for (int o = WAVE / 2; o >= 1; o >>= 1) {
+            mn = fmin(mn, __shfl_xor(mn, o, WAVE));
+            mx = fmax(mx, __shfl_xor(mx, o, WAVE));
+            sum += __shfl_xor(sum, o, WAVE);
+        }
+        sum = __shfl(sum, 0, WAVE);    // one value for the whole wave
+        const double mean = sum / (double)d;
+        double ss = 0.0;
+        for (int64_t q = lane; q < d; q += WAVE) {
+            const double t = (double)rho[eid[beg + q]] - mean;
+            ss += t * t;
+        }
+        for (int o = WAVE / 2; o >= 1; o >>= 1) ss += __shfl_xor(ss, o, WAVE);
+        ss = __shfl(ss, 0, WAVE);
+        const double sigma = (double)(float)sqrt(ss / (double)d);
+        // (rows longer than d_max break the graph's contract; they are kept in bounds)
+        const double h = (3.5 * sigma) / (d <= d_max ? cbrt_tab[d] : cbrt((double)d));
+        int64_t nb = 1;
+        if (h > 0.0) {
+            const double k = ceil((mx - mn) / h);
+            nb = k < 1.0 ? 1 : (int64_t)k;
+            if (nb > d) nb = d;    // never binds: (max - min) / sigma <= sqrt(2 d)
+        }
+        uint64_t words[4];
+        philox4x64_10((uint64_t)(uint32_t)(orig_id ? orig_id[i] : (int32_t)i), 0, 1, 0, seed, graph_id, words);
+        const uint32_t K = (uint32_t)words[0];
+        for (int64_t q = lane; q < d; q += WAVE) {
+            const int64_t p = beg + q;
+            const double v = (double)rho[eid[p]];
+            int64_t b = 0;
+            if (h > 0.0) {
+                b = (int64_t)floor((v - mn) / h);
+                if (b > nb - 1) b = nb - 1;
+            }
+            const uint32_t u = fmix32((uint32_t)nbr_id(p, col[p], col_orig, orig_id) ^ K);
+            keys[p] = ((unsigned long long)b << 32) | u;
+        }
+        for (int64_t b = lane; b < nb; b += WAVE) {
+            first_u[beg + b] = 0xffffffffu;
+            first_pos[beg + b] = 0xffffffffu;
+        }
+    }
+}
+
+// Rank in the (bin, priority) order of an entry, from the sides written by
+// the first ranking (low half of sides[2e + (i > j)]).
+__device__ __forceinline__ uint32_t side_rank(const unsigned long long *__restrict__ sides, int32_t e, int64_t i,
+                                              int32_t j) {
+    return (uint32_t)sides[2 * (int64_t)e + (i > j ? 1 : 0)];
+}
+
+// Per row: each bin's smallest priority and the rank of its first entry.
+__global__ __launch_bounds__(SBLOCK) void k_bin_firsts(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const int32_t *__restrict__ eid,
+                                                       const unsigned long long *__restrict__ keys,
+                                                       const unsigned long long *__restrict__ sides,
+                                                       uint32_t *__restrict__ first_u, uint32_t *__restrict__ first_pos) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (SBLOCK / WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        const int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
+        for (int64_t q = lane; q < d; q += WAVE) {
+            const int64_t p = beg + q;
+            const unsigned long long k = keys[p];
+            const int64_t b = (int64_t)(k >> 32);
+            atomicMin(&first_u[beg + b], (uint32_t)k);
+            atomicMin(&first_pos[beg + b], side_rank(sides, eid[p], i, col[p]));
+        }
+    }
+}
+
+// Per entry: its round r (rank minus the rank of its bin's first entry) and
+// the second key (r << 32 | the bin's smallest priority), in place of the first.
+__global__ __launch_bounds__(SBLOCK) void k_bin_rounds(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const int32_t *__restrict__ eid,
+                                                       unsigned long long *__restrict__ keys,
+                                                       const unsigned long long *__restrict__ sides,
+                                                       const uint32_t *__restrict__ first_u,
+                                                       const uint32_t *__restrict__ first_pos) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (SBLOCK / WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        const int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
+        for (int64_t q = lane; q < d; q += WAVE) {
+            const int64_t p = beg + q;
+            const int64_t b = (int64_t)(keys[p] >> 32);
+            const uint32_t r = side_rank(sides, eid[p], i, col[p]) - first_pos[beg + b];
+            keys[p] = ((unsigned long long)r << 32) | first_u[beg + b];
+        }
+    }
+}
+
+struct BinLayout {
+    SelLayout sel;                // sides2 holds the first ranking's ranks
+    unsigned long long *keys;     // [2m]
+    uint32_t *first_u, *first_pos;  // [2m]: per-row bin slots
+    double *cbrt_tab;             // [d_max + 1]
+    int32_t *budget;              // [d_max + 1]
+};
+
+static size_t bin_layout(const ad_graph *g, void *ws, size_t ws_bytes, BinLayout *B) {
+    const size_t sel = sel_layout(g, ws, ws_bytes, B ? &B->sel : nullptr, true);
+    if (ws && sel == 0) return 0;
+    const size_t sel_bytes = sel_layout(g, nullptr, 0, nullptr, true);
+    Carver c(ws ? (char *)ws + sel_bytes : nullptr, ws ? ws_bytes - std::min(ws_bytes, sel_bytes) : 0);
+    const int64_t nnz = std::max<int64_t>(1, 2 * g->m);
+    BinLayout l;
+    l.keys = c.take<unsigned long long>(nnz);
+    l.first_u = c.take<uint32_t>(nnz);
+    l.first_pos = c.take<uint32_t>(nnz);
+    l.cbrt_tab = c.take<double>((size_t)g->d_max + 1);
+    l.budget = c.take<int32_t>((size_t)g->d_max + 1);
+    if (B) {
+        l.sel = B->sel;
+        *B = l;
+    }
+    if (ws && !c.ok()) return 0;
+    return sel_bytes + c.used;
+}
+
+static ad_status sparsify_binned_impl(const ad_graph *g, ad_dtype rho_dtype, const void *rho, uint64_t seed,
+                                      uint64_t graph_id, double e, double target, uint8_t *keep, int64_t *n_kept,
+                                      double *e_used_host, const BinLayout &B, hipStream_t stream) {
+    const SelLayout &L = B.sel;
+    const int64_t n = g->n, m = g->m;
+    ad_status s;
+    if (m == 0) {
+        s = fill_u64(L.counts, 0, 1, stream);
+        if (s != AD_OK) return s;
+        hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, stream, L.counts, n_kept);
+        AD_LAUNCH_CHECK("k_store_count");
+        if (e_used_host) {
+            *e_used_host = target > 0.0 ? 0.0 : e;
+            AD_HIP(hipStreamSynchronize(stream));
+        }
+        return AD_OK;
+    }
+    // host tables by degree (the C library's cbrt and pow), copied to the device
+    std::vector<double> cb((size_t)g->d_max + 1);
+    for (int64_t d = 0; d <= g->d_max; ++d) cb[(size_t)d] = cbrt((double)d);
+    AD_HIP(hipMemcpyAsync(B.cbrt_tab, cb.data(), cb.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    std::vector<int32_t> bt;
+    if (!(target > 0.0)) {
+        budget_table(g->d_max, e, bt);
+        AD_HIP(hipMemcpyAsync(B.budget, bt.data(), bt.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    }
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(n, SBLOCK / WAVE)));
+    {
+        TraceScope trace("k_bin", stream);
+        if (rho_dtype == AD_F32)
+            hipLaunchKernelGGL((k_bin_keys<float>), dim3(grid), dim3(SBLOCK), 0, stream, n, g->row_ptr, g->col, g->eid,
+                               g->orig_id, g->col_orig, (const float *)rho, B.cbrt_tab, (int64_t)g->d_max, seed,
+                               graph_id, B.keys, B.first_u, B.first_pos);
+        else
+            hipLaunchKernelGGL((k_bin_keys<double>), dim3(grid), dim3(SBLOCK), 0, stream, n, g->row_ptr, g->col,
+                               g->eid, g->orig_id, g->col_orig, (const double *)rho, B.cbrt_tab, (int64_t)g->d_max,
+                               seed, graph_id, B.keys, B.first_u, B.first_pos);
+        AD_LAUNCH_CHECK("k_bin_keys");
+    }
+    // first ranking: (bin, priority); ranks into sides2
+    s = rank_all<float>(g, nullptr, emit_single(MODE_SIDES, AD_LOCAL, nullptr, nullptr, L.sides2), L, stream, B.keys);
+    if (s != AD_OK) return s;
+    {
+        TraceScope trace("k_bin", stream);
+        hipLaunchKernelGGL(k_bin_firsts, dim3(grid), dim3(SBLOCK), 0, stream, n, g->row_ptr, g->col, g->eid, B.keys,
+                           L.sides2, B.first_u, B.first_pos);
+        AD_LAUNCH_CHECK("k_bin_firsts");
+        hipLaunchKernelGGL(k_bin_rounds, dim3(grid), dim3(SBLOCK), 0, stream, n, g->row_ptr, g->col, g->eid, B.keys,
+                           L.sides2, B.first_u, B.first_pos);
+        AD_LAUNCH_CHECK("k_bin_rounds");
+    }
+    if (target > 0.0) {
+        // second ranking (round, bin order) into sides, then the retention fit
+        s = rank_all<float>(g, nullptr, emit_single(MODE_SIDES, AD_LOCAL, nullptr, nullptr, L.sides), L, stream,
+                            B.keys);
+        if (s != AD_OK) return s;
+        TraceScope trace_fit("k_fit_select", stream);
+        hipLaunchKernelGGL(k_log_table, dim3(grid_for((int64_t)g->d_max + 2, SBLOCK)), dim3(SBLOCK), 0, stream,
+                           (int64_t)g->d_max + 2, L.logs);
+        AD_LAUNCH_CHECK("k_log_table");
+        unsigned long long *sd[1] = {L.sides};
+        uint8_t *kp[1] = {keep};
+        return fit_from_sides(g, L, 1, sd, fit_count_target(m, target), kp, n_kept, e_used_host, stream);
+    }
+    // second ranking straight into keep at the fixed exponent
+    s = fill_u64(L.counts, 0, 1, stream);
+    if (s != AD_OK) return s;
+    s = fill_u8(keep, 0, m, stream);
+    if (s != AD_OK) return s;
+    s = rank_all<float>(g, nullptr, emit_single(MODE_FIXED, AD_LOCAL, B.budget, keep, nullptr), L, stream, B.keys);
+    if (s != AD_OK) return s;
+    hipLaunchKernelGGL(k_count_bytes, dim3((unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, SBLOCK))),
+                       dim3(SBLOCK), 0, stream, m, keep, L.counts);
+    AD_LAUNCH_CHECK("k_count_bytes");
+    hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, stream, L.counts, n_kept);
+    AD_LAUNCH_CHECK("k_store_count");
+    // the host tables must outlive their copies
+    AD_HIP(hipStreamSynchronize(stream));
+    if (e_used_host) *e_used_host = e;
+    return AD_OK;
+}
+
+}  // namespace ad
+
+extern "C" size_t ad_sparsify_binned_workspace_size(const ad_graph *g) {
+    if (check_graph_args(g) != AD_OK) return 0;
+    return bin_layout(g, nullptr, 0, nullptr);
+}
+
+extern "C" ad_status ad_sparsify_binned(const ad_graph *g, ad_dtype rho_dtype, const void *rho, uint64_t seed,
+                                        uint64_t graph_id, double e, double target, uint8_t *keep,
+                                        int64_t *n_kept, double *e_used_host, void *ws, size_t ws_bytes,
+                                        hipStream_t stream) {
+    SelLayout L;
+    ad_status s = check_sel_args(g, rho_dtype, rho, AD_LOCAL, keep, n_kept, ws, ws_bytes, &L, true);
+    if (s != AD_OK) return s;
+    if (target > 0.0) {
+        if (!(target <= 1.0)) return fail(AD_ERR_INVALID_ARG, "target must be in (0, 1]");
+        if (!e_used_host) return fail(AD_ERR_INVALID_ARG, "e_used_host is NULL (a fit reports its exponent)");
+    } else {
+        if (target != 0.0) return fail(AD_ERR_INVALID_ARG, "target must be 0 (fixed e) or in (0, 1]");
+        if (!(e >= 0.0 && e <= 1.0)) return fail(AD_ERR_INVALID_ARG, "e must be in [0, 1]");
+    }
+    if ((size_t)g->d_max + 1 > ((size_t)1 << 31)) return fail(AD_ERR_UNSUPPORTED, "d_max too large");
+    BinLayout B;
+    B.sel = L;
+    if (bin_layout(g, ws, ws_bytes, &B) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    return sparsify_binned_impl(g, rho_dtype, rho, seed, graph_id, e, target, keep, n_kept, e_used_host, B, stream);
 }

@@ -100,6 +100,19 @@ def test_selection_rejects_bad_arguments():
     e2 = (ctypes.c_double * 2)()
     assert L.ad_sparsify_fit_both(ctypes.byref(g), 1, p, 0.0, p, p, p, e2, ws, 1 << 30, None) == 1
     assert L.ad_sparsify_fit_both(ctypes.byref(g), 1, p, 0.3, p, None, p, e2, ws, 1 << 30, None) == 1
+    # selection with binning: target, exponent, e_used_host, dtype, workspace
+    eb = ctypes.byref(e)
+    assert L.ad_sparsify_binned(ctypes.byref(g), 1, p, 7, 0, 0.5, 1.5, p, p, eb, ws, 1 << 30, None) == 1
+    assert L.ad_sparsify_binned(ctypes.byref(g), 1, p, 7, 0, 0.5, -0.1, p, p, eb, ws, 1 << 30, None) == 1
+    assert L.ad_sparsify_binned(ctypes.byref(g), 1, p, 7, 0, 1.5, 0.0, p, p, eb, ws, 1 << 30, None) == 1
+    assert L.ad_sparsify_binned(ctypes.byref(g), 1, p, 7, 0, 0.5, 0.3, p, p, None, ws, 1 << 30, None) == 1
+    assert L.ad_sparsify_binned(ctypes.byref(g), 2, p, 7, 0, 0.5, 0.0, p, p, eb, ws, 1 << 30, None) == 1
+    assert L.ad_sparsify_binned(ctypes.byref(g), 1, p, 7, 0, 0.5, 0.0, None, p, eb, ws, 1 << 30, None) == 1
+    need = L.ad_sparsify_binned_workspace_size(ctypes.byref(g))
+    assert need >= L.ad_sparsify_fit_both_workspace_size(ctypes.byref(g)) + 5 * 256   # keys, firsts, tables
+    assert L.ad_sparsify_binned(ctypes.byref(g), 1, p, 7, 0, 0.5, 0.0, p, p, eb, ws, need - 256, None) == 3
+    assert L.ad_sparsify_binned(ctypes.byref(g), 1, p, 7, 0, 0.5, 0.0, p, p, eb, ctypes.c_void_p(0x10008),
+                                need, None) == 3
     # normalization: dtype, eps, workspace
     assert L.ad_normalize_dist(ctypes.byref(g), 2, p, 1, 0.0, p, ws, 1 << 30, None) == 1
     assert L.ad_normalize_dist(ctypes.byref(g), 1, p, 1, -1.0, p, ws, 1 << 30, None) == 1

@@ -5,7 +5,8 @@ paper_1601_05527_amd.workloads).
   Chung-Lu n = 2^20, 16M edges, FP32: every distance against the FP64
       oracle (1e-5 relative, or the edge's FP32 conditioning bound where
       that is larger, gpu_helpers.fp32_tolerance); the fit on the oracle's distances equal to the oracle's
-      bisection bit for bit; the end-to-end kept set near-cut equal.
+      bisection bit for bit; the end-to-end kept set near-cut equal; the
+      selection with binning (fixed e and fitted) equal to the oracle's.
   Batch of 512 Chung-Lu graphs, FP32: every graph's kept set equal to the
       oracle's selection on the batch's distances, every graph's outputs
       equal to a standalone run bit for bit, distances of sampled graphs
@@ -80,6 +81,17 @@ def test_full_chung_lu(api):
         keep_g, _ = api.sparsify(dg, rho, orient, e_o)
         bad = near_cut_mismatches(g, rho_o, _np(keep_g), keep_o, orient, e_o, 1e-5)
         assert not bad, bad[:10]
+    # selection with binning (Algorithm 4) on the same distances: fixed e and the fit
+    rt = torch.from_numpy(rho32).cuda()
+    keep_b, nk_b, _ = api.sparsify_binned(dg, rt, c["bin_seed"], e=0.5)
+    keep_bo, kept_bo = oracle.sparsify_binned(g, rho32.astype(np.float64), 0.5, c["bin_seed"])
+    _log(f"binned e=0.5: kept {int(_np(nk_b)[0])} oracle {kept_bo}")
+    assert np.array_equal(_np(keep_b), keep_bo) and int(_np(nk_b)[0]) == kept_bo
+    keep_b, nk_b, e_b = api.sparsify_binned(dg, rt, c["bin_seed"], target=c["target"])
+    e_bo, keep_bo, kept_bo = oracle.fit_exponent_binned(g, rho32.astype(np.float64), c["target"], c["bin_seed"])
+    _log(f"binned fit: e {e_b!r} oracle {e_bo!r} kept {int(_np(nk_b)[0])} oracle {kept_bo}")
+    assert e_b == e_bo
+    assert np.array_equal(_np(keep_b), keep_bo) and int(_np(nk_b)[0]) == kept_bo
 
 
 @pytest.mark.timeout(900)
