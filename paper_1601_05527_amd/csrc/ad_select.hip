@@ -1649,8 +1649,9 @@ extern "C" ad_status ad_sparsify_fit_both(const ad_graph *g, ad_dtype rho_dtype,
 //
 // On the device the rounds become two rankings of 64-bit keys per row: first
 // (bin, priority), whose rank p of an entry minus the rank of its bin's
-// first entry is the entry's round r; then (r, smallest priority of the
-// bin), whose rank is the entry's place in the selection order.  The rank
+// first entry is the entry's round r (the bins' first entries are read off
+// the row laid out in that order); then (r, smallest priority of the bin),
+// whose rank is the entry's place in the selection order.  The rank
 // kernels of Algorithm 3 do both; the budget and the retention fit then
 // apply unchanged (the selected sets grow with e).
 // ---------------------------------------------------------------------------
@@ -1666,45 +1667,84 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     return h;
 }
 
-// Per row (one wave per row): bins by Scott's rule, the first key (bin << 32 |
-// priority) of every entry, and the row's per-bin slots [beg, beg + B_i) of
-// first_u / first_pos set to ~0 for the atomic minima that follow.
-template <typename Tr>
-__global__ __launch_bounds__(SBLOCK) void k_bin_keys(int64_t n, const int64_t *__restrict__ row_ptr,
-                                                     const int32_t *__restrict__ col,
-                                                     const int32_t *__restrict__ eid,
-                                                     const int32_t *__restrict__ orig_id,
-                                                     const int32_t *__restrict__ col_orig,
-                                                     const Tr *__restrict__ rho, const double *__restrict__ cbrt_tab,
-                                                     int64_t d_max, uint64_t seed, uint64_t graph_id,
-                                                     unsigned long long *__restrict__ keys,
-                                                     uint32_t *__restrict__ first_u, uint32_t *__restrict__ first_pos) {
+// Rows of degree <= BIN_SHORT_ROW are handled by groups of BIN_SHORT_G
+// consecutive lanes (neighbouring lanes read neighbouring entries), longer
+// rows by one wave each: every kernel below runs its row body over the
+// short rows with groups of BIN_SHORT_G lanes, then over the long rows with
+// groups of WAVE lanes (rows strided over the grid's groups, then its waves).
+constexpr int64_t BIN_SHORT_ROW = 32;
+constexpr int BIN_SHORT_G = 16;
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return __shfl(v, (int)(threadIdx.x & (WAVE - 1)) & ~(G - 1), WAVE);   // one value for the group
+}
+template <int G>
+__device__ __forceinline__ double group_min(double v) {
+    for (int o = G / 2; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+template <int G>
+__device__ __forceinline__ double group_max(double v) {
+    for (int o = G / 2; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// Runs body.template run<G>(row, lane in group) for every row with d >= 1:
+// short rows with G = BIN_SHORT_G, long rows with G = WAVE.  All lanes of a
+// wave take part in both passes (rows past n or of the other kind idle
+// through the group's loops), so the group shuffles see full waves.
+template <typename Body>
+__device__ __forceinline__ void for_bin_rows(int64_t n, const int64_t *__restrict__ row_ptr, const Body &body) {
+    constexpr int GS = BIN_SHORT_G;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t nw = (int64_t)gridDim.x * (SBLOCK / WAVE);
-    for (int64_t i = (int64_t)blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
-        const int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
-        if (d == 0) continue;
+    // short rows: the wave's groups take rows g, g + ngroups, ... in lockstep
+    for (int64_t base = (tid / WAVE) * (WAVE / GS); base < n; base += (nt / WAVE) * (WAVE / GS)) {
+        const int64_t i = base + lane / GS;
+        const int64_t d = i < n ? row_ptr[i + 1] - row_ptr[i] : 0;
+        body.template run<GS>(i, lane % GS, d >= 1 && d <= BIN_SHORT_ROW);
+    }
+    for (int64_t i = tid / WAVE; i < n; i += nt / WAVE) {
+        const int64_t d = row_ptr[i + 1] - row_ptr[i];
+        if (d > BIN_SHORT_ROW) body.template run<WAVE>(i, lane, true);
+    }
+}
+
+// Per row: bins by Scott's rule and the first key (bin << 32 | priority) of
+// every entry.
+template <typename Tr>
+struct BinKeys {
+    const int64_t *row_ptr;
+    const int32_t *col, *eid, *orig_id, *col_orig;
+    const Tr *rho;
+    const double *cbrt_tab;
+    int64_t d_max;
+    uint64_t seed, graph_id;
+    unsigned long long *keys;
+    template <int G>
+    __device__ __forceinline__ void run(int64_t i, int lane, bool on) const {
+        const int64_t beg = on ? row_ptr[i] : 0, d = on ? row_ptr[i + 1] - beg : 0;
         double mn = INFINITY, mx = -INFINITY, sum = 0.0;
-        for (int64_t q = lane; q < d; q += WAVE) {
+        for (int64_t q = lane; q < d; q += G) {
             const double v = (double)rho[eid[beg + q]];
             mn = fmin(mn, v);
             mx = fmax(mx, v);
             sum += v;
         }
-        for (int o = WAVE / 2; o >= 1; o >>= 1) {
-            mn = fmin(mn, __shfl_xor(mn, o, WAVE));
-            mx = fmax(mx, __shfl_xor(mx, o, WAVE));
-            sum += __shfl_xor(sum, o, WAVE);
-        }
-        sum = __shfl(sum, 0, WAVE);    // one value for the whole wave
-        const double mean = sum / (double)d;
+        mn = group_min<G>(mn);
+        mx = group_max<G>(mx);
+        sum = group_sum<G>(sum);
+        const double mean = d > 0 ? sum / (double)d : 0.0;
         double ss = 0.0;
-        for (int64_t q = lane; q < d; q += WAVE) {
+        for (int64_t q = lane; q < d; q += G) {
             const double t = (double)rho[eid[beg + q]] - mean;
             ss += t * t;
         }
-        for (int o = WAVE / 2; o >= 1; o >>= 1) ss += __shfl_xor(ss, o, WAVE);
-        ss = __shfl(ss, 0, WAVE);
+        ss = group_sum<G>(ss);
+        if (!on) return;
         const double sigma = (double)(float)sqrt(ss / (double)d);
         // (rows longer than d_max break the graph's contract; they are kept in bounds)
         const double h = (3.5 * sigma) / (d <= d_max ? cbrt_tab[d] : cbrt((double)d));
@@ -1717,7 +1757,7 @@ __global__ __launch_bounds__(SBLOCK) void k_bin_keys(int64_t n, const int64_t *_
         uint64_t words[4];
         philox4x64_10((uint64_t)(uint32_t)(orig_id ? orig_id[i] : (int32_t)i), 0, 1, 0, seed, graph_id, words);
         const uint32_t K = (uint32_t)words[0];
-        for (int64_t q = lane; q < d; q += WAVE) {
+        for (int64_t q = lane; q < d; q += G) {
             const int64_t p = beg + q;
             const double v = (double)rho[eid[p]];
             int64_t b = 0;
@@ -1728,11 +1768,12 @@ __global__ __launch_bounds__(SBLOCK) void k_bin_keys(int64_t n, const int64_t *_
             const uint32_t u = fmix32((uint32_t)nbr_id(p, col[p], col_orig, orig_id) ^ K);
             keys[p] = ((unsigned long long)b << 32) | u;
         }
-        for (int64_t b = lane; b < nb; b += WAVE) {
-            first_u[beg + b] = 0xffffffffu;
-            first_pos[beg + b] = 0xffffffffu;
-        }
     }
+};
+
+template <typename Tr>
+__global__ __launch_bounds__(SBLOCK) void k_bin_keys(int64_t n, BinKeys<Tr> body) {
+    for_bin_rows(n, body.row_ptr, body);
 }
 
 // Rank in the (bin, priority) order of an entry, from the sides written by
@@ -1742,53 +1783,76 @@ __device__ __forceinline__ uint32_t side_rank(const unsigned long long *__restri
     return (uint32_t)sides[2 * (int64_t)e + (i > j ? 1 : 0)];
 }
 
-// Per row: each bin's smallest priority and the rank of its first entry.
-__global__ __launch_bounds__(SBLOCK) void k_bin_firsts(int64_t n, const int64_t *__restrict__ row_ptr,
-                                                       const int32_t *__restrict__ col,
-                                                       const int32_t *__restrict__ eid,
-                                                       const unsigned long long *__restrict__ keys,
-                                                       const unsigned long long *__restrict__ sides,
-                                                       uint32_t *__restrict__ first_u, uint32_t *__restrict__ first_pos) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t nw = (int64_t)gridDim.x * (SBLOCK / WAVE);
-    for (int64_t i = (int64_t)blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+// The row in (bin, priority) order: order[beg + rank] = entry offset, and
+// every entry's rank.
+struct BinOrder {
+    const int64_t *row_ptr;
+    const int32_t *col, *eid;
+    const unsigned long long *sides;
+    uint32_t *order, *rank;
+    template <int G>
+    __device__ __forceinline__ void run(int64_t i, int lane, bool on) const {
+        if (!on) return;
         const int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
-        for (int64_t q = lane; q < d; q += WAVE) {
-            const int64_t p = beg + q;
-            const unsigned long long k = keys[p];
-            const int64_t b = (int64_t)(k >> 32);
-            atomicMin(&first_u[beg + b], (uint32_t)k);
-            atomicMin(&first_pos[beg + b], side_rank(sides, eid[p], i, col[p]));
+        for (int64_t q = lane; q < d; q += G) {
+            const uint32_t r = side_rank(sides, eid[beg + q], i, col[beg + q]);
+            order[beg + r] = (uint32_t)q;
+            rank[beg + q] = r;
         }
     }
-}
+};
+
+// Each bin's first entry in that order: its rank (first_pos) and priority
+// (first_u), at the row's bin slots [beg, beg + B_i).
+struct BinFirsts {
+    const int64_t *row_ptr;
+    const unsigned long long *keys;
+    const uint32_t *order;
+    uint32_t *first_u, *first_pos;
+    template <int G>
+    __device__ __forceinline__ void run(int64_t i, int lane, bool on) const {
+        if (!on) return;
+        const int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
+        for (int64_t t = lane; t < d; t += G) {
+            const unsigned long long k = keys[beg + order[beg + t]];
+            const uint32_t b = (uint32_t)(k >> 32);
+            if (t == 0 || (uint32_t)(keys[beg + order[beg + t - 1]] >> 32) != b) {
+                first_pos[beg + b] = (uint32_t)t;
+                first_u[beg + b] = (uint32_t)k;
+            }
+        }
+    }
+};
 
 // Per entry: its round r (rank minus the rank of its bin's first entry) and
 // the second key (r << 32 | the bin's smallest priority), in place of the first.
-__global__ __launch_bounds__(SBLOCK) void k_bin_rounds(int64_t n, const int64_t *__restrict__ row_ptr,
-                                                       const int32_t *__restrict__ col,
-                                                       const int32_t *__restrict__ eid,
-                                                       unsigned long long *__restrict__ keys,
-                                                       const unsigned long long *__restrict__ sides,
-                                                       const uint32_t *__restrict__ first_u,
-                                                       const uint32_t *__restrict__ first_pos) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t nw = (int64_t)gridDim.x * (SBLOCK / WAVE);
-    for (int64_t i = (int64_t)blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+struct BinRounds {
+    const int64_t *row_ptr;
+    unsigned long long *keys;
+    const uint32_t *rank, *first_u, *first_pos;
+    template <int G>
+    __device__ __forceinline__ void run(int64_t i, int lane, bool on) const {
+        if (!on) return;
         const int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
-        for (int64_t q = lane; q < d; q += WAVE) {
+        for (int64_t q = lane; q < d; q += G) {
             const int64_t p = beg + q;
             const int64_t b = (int64_t)(keys[p] >> 32);
-            const uint32_t r = side_rank(sides, eid[p], i, col[p]) - first_pos[beg + b];
+            const uint32_t r = rank[p] - first_pos[beg + b];
             keys[p] = ((unsigned long long)r << 32) | first_u[beg + b];
         }
     }
+};
+
+template <typename Body>
+__global__ __launch_bounds__(SBLOCK) void k_bin_rows(int64_t n, Body body) {
+    for_bin_rows(n, body.row_ptr, body);
 }
 
 struct BinLayout {
     SelLayout sel;                // sides2 holds the first ranking's ranks
     unsigned long long *keys;     // [2m]
     uint32_t *first_u, *first_pos;  // [2m]: per-row bin slots
+    uint32_t *order, *rank;         // [2m]: the row in the first order, and each entry's rank in it
     double *cbrt_tab;             // [d_max + 1]
     int32_t *budget;              // [d_max + 1]
 };
@@ -1803,6 +1867,8 @@ static size_t bin_layout(const ad_graph *g, void *ws, size_t ws_bytes, BinLayout
     l.keys = c.take<unsigned long long>(nnz);
     l.first_u = c.take<uint32_t>(nnz);
     l.first_pos = c.take<uint32_t>(nnz);
+    l.order = c.take<uint32_t>(nnz);
+    l.rank = c.take<uint32_t>(nnz);
     l.cbrt_tab = c.take<double>((size_t)g->d_max + 1);
     l.budget = c.take<int32_t>((size_t)g->d_max + 1);
     if (B) {
@@ -1839,17 +1905,19 @@ static ad_status sparsify_binned_impl(const ad_graph *g, ad_dtype rho_dtype, con
         budget_table(g->d_max, e, bt);
         AD_HIP(hipMemcpyAsync(B.budget, bt.data(), bt.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     }
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(n, SBLOCK / WAVE)));
+    // a group of lanes per short row, a wave per long row
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, SBLOCK / BIN_SHORT_G)));
     {
         TraceScope trace("k_bin", stream);
-        if (rho_dtype == AD_F32)
-            hipLaunchKernelGGL((k_bin_keys<float>), dim3(grid), dim3(SBLOCK), 0, stream, n, g->row_ptr, g->col, g->eid,
-                               g->orig_id, g->col_orig, (const float *)rho, B.cbrt_tab, (int64_t)g->d_max, seed,
-                               graph_id, B.keys, B.first_u, B.first_pos);
-        else
-            hipLaunchKernelGGL((k_bin_keys<double>), dim3(grid), dim3(SBLOCK), 0, stream, n, g->row_ptr, g->col,
-                               g->eid, g->orig_id, g->col_orig, (const double *)rho, B.cbrt_tab, (int64_t)g->d_max,
-                               seed, graph_id, B.keys, B.first_u, B.first_pos);
+        if (rho_dtype == AD_F32) {
+            const BinKeys<float> bk{g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, (const float *)rho,
+                                    B.cbrt_tab, (int64_t)g->d_max, seed, graph_id, B.keys};
+            hipLaunchKernelGGL((k_bin_keys<float>), dim3(grid), dim3(SBLOCK), 0, stream, n, bk);
+        } else {
+            const BinKeys<double> bk{g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, (const double *)rho,
+                                     B.cbrt_tab, (int64_t)g->d_max, seed, graph_id, B.keys};
+            hipLaunchKernelGGL((k_bin_keys<double>), dim3(grid), dim3(SBLOCK), 0, stream, n, bk);
+        }
         AD_LAUNCH_CHECK("k_bin_keys");
     }
     // first ranking: (bin, priority); ranks into sides2
@@ -1857,11 +1925,14 @@ static ad_status sparsify_binned_impl(const ad_graph *g, ad_dtype rho_dtype, con
     if (s != AD_OK) return s;
     {
         TraceScope trace("k_bin", stream);
-        hipLaunchKernelGGL(k_bin_firsts, dim3(grid), dim3(SBLOCK), 0, stream, n, g->row_ptr, g->col, g->eid, B.keys,
-                           L.sides2, B.first_u, B.first_pos);
+        hipLaunchKernelGGL(k_bin_rows<BinOrder>, dim3(grid), dim3(SBLOCK), 0, stream, n,
+                           BinOrder{g->row_ptr, g->col, g->eid, L.sides2, B.order, B.rank});
+        AD_LAUNCH_CHECK("k_bin_order");
+        hipLaunchKernelGGL(k_bin_rows<BinFirsts>, dim3(grid), dim3(SBLOCK), 0, stream, n,
+                           BinFirsts{g->row_ptr, B.keys, B.order, B.first_u, B.first_pos});
         AD_LAUNCH_CHECK("k_bin_firsts");
-        hipLaunchKernelGGL(k_bin_rounds, dim3(grid), dim3(SBLOCK), 0, stream, n, g->row_ptr, g->col, g->eid, B.keys,
-                           L.sides2, B.first_u, B.first_pos);
+        hipLaunchKernelGGL(k_bin_rows<BinRounds>, dim3(grid), dim3(SBLOCK), 0, stream, n,
+                           BinRounds{g->row_ptr, B.keys, B.rank, B.first_u, B.first_pos});
         AD_LAUNCH_CHECK("k_bin_rounds");
     }
     if (target > 0.0) {
