@@ -85,6 +85,8 @@ def _load():
     lib.orc_bin_priority.restype = ctypes.c_uint32
     lib.orc_bin_layout.argtypes = [i64, P, P, P, P, P]
     lib.orc_binned_choices.argtypes = [i64, P, P, P, P, P, u64, u64, f64, P]
+    lib.orc_ingest.argtypes = [i64, i64, P, P, P, P, i32, P, P, P, P, P, P]
+    lib.orc_ingest.restype = i64
     lib.orc_sparsify_binned.argtypes = [i64, P, P, P, P, i64, P, u64, u64, f64, P]
     lib.orc_sparsify_binned.restype = i64
     lib.orc_fit_exponent_binned.argtypes = [i64, P, P, P, P, i64, P, u64, u64, f64, P, P]
@@ -267,3 +269,30 @@ def fit_exponent_binned(g, rho: np.ndarray, target: float, seed: int, graph_id: 
     e = lib.orc_fit_exponent_binned(g.n, _p(g.row_ptr), _p(g.col), _p(g.eid), _p(g.orig_id), g.m,
                                     _p(r), seed, graph_id, target, _p(keep), ctypes.byref(kept))
     return float(e), keep, int(kept.value)
+
+
+def ingest(n: int, u, v, w=None, orig_id=None, order: int = 0):
+    """An edge list into the symmetric CSR of the graph model (self-loops
+    dropped, repeated pairs merged with summed weights; order 1 stores the
+    vertices by decreasing degree).  Returns (row_ptr, col, w_entries or
+    None, eid, orig_id, m, n_dropped); raises ValueError for an endpoint out
+    of range."""
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.int32)
+    vv = np.ascontiguousarray(v, dtype=np.int32)
+    ww = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
+    oi = _c(orig_id, np.int32)
+    m_in = uu.size
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(max(1, 2 * m_in), dtype=np.int32)
+    eid = np.zeros(max(1, 2 * m_in), dtype=np.int32)
+    w_out = np.zeros(max(1, 2 * m_in), dtype=np.float32) if ww is not None else None
+    orig = np.zeros(max(1, n), dtype=np.int32)
+    dropped = ctypes.c_int64()
+    m = lib.orc_ingest(n, m_in, _p(uu), _p(vv), _p(ww), _p(oi), order, _p(row_ptr), _p(col), _p(w_out),
+                       _p(eid), _p(orig), ctypes.byref(dropped))
+    if m < 0:
+        raise ValueError("vertex id out of range")
+    nnz = 2 * m
+    return (row_ptr, col[:nnz].copy(), None if w_out is None else w_out[:nnz].copy(), eid[:nnz].copy(),
+            orig[:n].copy(), int(m), int(dropped.value))

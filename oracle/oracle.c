@@ -541,6 +541,137 @@ double orc_fit_exponent_binned(int64_t n, const int64_t *row_ptr, const int32_t 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Ingest: an edge list into the graph model of Section 2 (undirected, no
+ * self-loops, no repeated pairs), as the symmetric CSR the other functions
+ * read.  Readings: a listed pair (u, v) and (v, u) name the same edge;
+ * self-loops are dropped; repeated pairs are merged into one edge whose
+ * weight is the sum of the listed weights (added in double in list order,
+ * then rounded to single precision); edge ids enumerate the edges in order
+ * of (smaller endpoint, larger endpoint), which is the CSR order of their
+ * upper entries; each row lists its neighbours in ascending order.  With
+ * order == 1 the vertices are stored by decreasing degree, ties by their id
+ * in the list, and orig_out[new id] names the listed vertex (through
+ * orig_in when given).  Returns the number of edges m, or -1 when an
+ * endpoint lies outside [0, n); n_dropped receives m_in - m.               */
+
+typedef struct { int64_t a, b, idx; } orc_pair;
+
+static int orc_cmp_pair(const void *x, const void *y)
+{
+    const orc_pair *p = (const orc_pair *)x, *q = (const orc_pair *)y;
+    if (p->a != q->a) return p->a < q->a ? -1 : 1;
+    if (p->b != q->b) return p->b < q->b ? -1 : 1;
+    return (p->idx > q->idx) - (p->idx < q->idx);
+}
+
+typedef struct { int64_t row, col, e; } orc_entry;
+
+static int orc_cmp_entry(const void *x, const void *y)
+{
+    const orc_entry *p = (const orc_entry *)x, *q = (const orc_entry *)y;
+    if (p->row != q->row) return p->row < q->row ? -1 : 1;
+    return (p->col > q->col) - (p->col < q->col);
+}
+
+typedef struct { int64_t deg, id; } orc_vdeg;
+
+static int orc_cmp_vdeg(const void *x, const void *y)
+{
+    const orc_vdeg *p = (const orc_vdeg *)x, *q = (const orc_vdeg *)y;
+    if (p->deg != q->deg) return p->deg > q->deg ? -1 : 1;     /* decreasing degree */
+    return (p->id > q->id) - (p->id < q->id);
+}
+
+int64_t orc_ingest(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v, const float *w,
+                   const int32_t *orig_in, int32_t order, int64_t *row_ptr, int32_t *col, float *w_out,
+                   int32_t *eid, int32_t *orig_out, int64_t *n_dropped)
+{
+    for (int64_t q = 0; q < m_in; ++q)
+        if (u[q] < 0 || u[q] >= n || v[q] < 0 || v[q] >= n) return -1;
+    orc_pair *pr = (orc_pair *)malloc(sizeof(orc_pair) * (size_t)(m_in > 0 ? m_in : 1));
+    int64_t k = 0;
+    for (int64_t q = 0; q < m_in; ++q) {
+        if (u[q] == v[q]) continue;                         /* self-loop */
+        pr[k].a = u[q] < v[q] ? u[q] : v[q];
+        pr[k].b = u[q] < v[q] ? v[q] : u[q];
+        pr[k].idx = q;
+        ++k;
+    }
+    qsort(pr, (size_t)k, sizeof(orc_pair), orc_cmp_pair);
+    /* merge repeated pairs: one edge, weights summed in list order */
+    int64_t *ea = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k > 0 ? k : 1));
+    int64_t *eb = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k > 0 ? k : 1));
+    float *ew = (float *)malloc(sizeof(float) * (size_t)(k > 0 ? k : 1));
+    int64_t m = 0;
+    for (int64_t q = 0; q < k;) {
+        int64_t r = q;
+        double sum = 0.0;
+        while (r < k && pr[r].a == pr[q].a && pr[r].b == pr[q].b) {
+            if (w) sum += (double)w[pr[r].idx];
+            ++r;
+        }
+        ea[m] = pr[q].a;
+        eb[m] = pr[q].b;
+        ew[m] = (float)sum;
+        ++m;
+        q = r;
+    }
+    free(pr);
+    /* vertex storage order */
+    int64_t *new_of = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) new_of[i] = i;
+    if (order == 1 && n > 0) {
+        orc_vdeg *vd = (orc_vdeg *)malloc(sizeof(orc_vdeg) * (size_t)n);
+        for (int64_t i = 0; i < n; ++i) { vd[i].deg = 0; vd[i].id = i; }
+        for (int64_t e = 0; e < m; ++e) { vd[ea[e]].deg++; vd[eb[e]].deg++; }
+        qsort(vd, (size_t)n, sizeof(orc_vdeg), orc_cmp_vdeg);
+        for (int64_t r = 0; r < n; ++r) new_of[vd[r].id] = r;
+        free(vd);
+        /* relabel, then number the edges again in (smaller, larger) order */
+        orc_pair *rp = (orc_pair *)malloc(sizeof(orc_pair) * (size_t)(m > 0 ? m : 1));
+        for (int64_t e = 0; e < m; ++e) {
+            int64_t x = new_of[ea[e]], y = new_of[eb[e]];
+            rp[e].a = x < y ? x : y;
+            rp[e].b = x < y ? y : x;
+            rp[e].idx = e;
+        }
+        qsort(rp, (size_t)m, sizeof(orc_pair), orc_cmp_pair);
+        float *ew2 = (float *)malloc(sizeof(float) * (size_t)(m > 0 ? m : 1));
+        for (int64_t e = 0; e < m; ++e) {
+            ew2[e] = ew[rp[e].idx];
+            ea[e] = rp[e].a;
+            eb[e] = rp[e].b;
+        }
+        free(ew);
+        ew = ew2;
+        free(rp);
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t id = orig_in ? orig_in[i] : (int32_t)i;
+        orig_out[new_of[i]] = id;
+    }
+    free(new_of);
+    /* both entries of every edge, sorted by (row, col) */
+    orc_entry *en = (orc_entry *)malloc(sizeof(orc_entry) * (size_t)(2 * m > 0 ? 2 * m : 1));
+    for (int64_t e = 0; e < m; ++e) {
+        en[2 * e].row = ea[e]; en[2 * e].col = eb[e]; en[2 * e].e = e;
+        en[2 * e + 1].row = eb[e]; en[2 * e + 1].col = ea[e]; en[2 * e + 1].e = e;
+    }
+    qsort(en, (size_t)(2 * m), sizeof(orc_entry), orc_cmp_entry);
+    for (int64_t i = 0; i <= n; ++i) row_ptr[i] = 0;
+    for (int64_t p = 0; p < 2 * m; ++p) row_ptr[en[p].row + 1]++;
+    for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] += row_ptr[i];
+    for (int64_t p = 0; p < 2 * m; ++p) {
+        col[p] = (int32_t)en[p].col;
+        eid[p] = (int32_t)en[p].e;
+        if (w && w_out) w_out[p] = ew[en[p].e];
+    }
+    free(en); free(ea); free(eb); free(ew);
+    if (n_dropped) *n_dropped = m_in - m;
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Reverse-mode derivative of L = sum_e c_e rho_e with respect to the edge
  * weights w_e (w_ij = w_ji = w_e), taken through the k sweeps, the rescale
  * (its min and max as functions of x^(k)) and the distance.  Written by the

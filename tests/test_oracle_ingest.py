@@ -1,0 +1,161 @@
+"""Pins of the oracle's ingest (edge list -> the symmetric CSR of the graph
+model of Section 2) by brute force on small lists and by invariants:
+
+  - a Python dictionary build of the same reading (pairs unordered, loops
+    dropped, repeats merged with weights summed in list order) gives the same
+    arrays, entry for entry;
+  - the CSR is symmetric, rows ascending, edge ids paired and numbered in
+    (smaller, larger) order; feeding its own edge list back is a fixed point;
+  - the decreasing-degree order really is one, ties by listed id, and keeps
+    the edge set (through orig_id);
+  - out-of-range endpoints are refused; the empty list gives an empty graph.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_05527_amd import graphs as G
+
+
+def _random_list(n, m_in, seed, loops=True, dups=True):
+    rng = np.random.default_rng(seed)
+    u = rng.integers(0, n, m_in)
+    v = rng.integers(0, n, m_in)
+    if not loops:
+        keep = u != v
+        u, v = u[keep], v[keep]
+    if dups and u.size > 4:
+        # repeat some pairs, some flipped
+        k = u.size // 5
+        u = np.concatenate([u, v[:k], u[k:2 * k]])
+        v = np.concatenate([v, u[:k], v[k:2 * k]])
+    w = rng.uniform(0.1, 3.0, u.size).astype(np.float32)
+    return u.astype(np.int32), v.astype(np.int32), w
+
+
+def _brute(n, u, v, w):
+    sums = {}
+    for q in range(len(u)):
+        a, b = int(u[q]), int(v[q])
+        if a == b:
+            continue
+        key = (min(a, b), max(a, b))
+        sums[key] = sums.get(key, 0.0) + float(w[q])     # double, list order
+    edges = sorted(sums)
+    eid = {e: i for i, e in enumerate(edges)}
+    rows = [[] for _ in range(n)]
+    for (a, b) in edges:
+        rows[a].append(b)
+        rows[b].append(a)
+    row_ptr, col, ws, ids = [0], [], [], []
+    for i in range(n):
+        for j in sorted(rows[i]):
+            e = (min(i, j), max(i, j))
+            col.append(j)
+            ws.append(np.float32(sums[e]))
+            ids.append(eid[e])
+        row_ptr.append(len(col))
+    return (np.array(row_ptr), np.array(col, dtype=np.int32), np.array(ws, dtype=np.float32),
+            np.array(ids, dtype=np.int32), len(edges))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ingest_equals_dictionary_build(seed):
+    n = 40 + 7 * seed
+    u, v, w = _random_list(n, 300, seed)
+    row_ptr, col, we, eid, orig, m, dropped = oracle.ingest(n, u, v, w)
+    b_rp, b_col, b_w, b_eid, b_m = _brute(n, u, v, w)
+    assert m == b_m and dropped == len(u) - m
+    np.testing.assert_array_equal(row_ptr, b_rp)
+    np.testing.assert_array_equal(col, b_col)
+    np.testing.assert_array_equal(we, b_w)
+    np.testing.assert_array_equal(eid, b_eid)
+    np.testing.assert_array_equal(orig, np.arange(n))
+
+
+def _check_csr(n, row_ptr, col, eid, m):
+    assert row_ptr[0] == 0 and row_ptr[-1] == 2 * m
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    for i in range(n):
+        r = col[row_ptr[i]:row_ptr[i + 1]]
+        assert np.all(np.diff(r) > 0) and np.all(r != i)
+    # each edge id appears exactly twice, as (a, b) and (b, a)
+    first = {}
+    for p in range(len(col)):
+        first.setdefault(int(eid[p]), []).append((int(rows[p]), int(col[p])))
+    assert sorted(first) == list(range(m))
+    pairs = []
+    for e in range(m):
+        (a, b), (c, d) = first[e]
+        assert (a, b) == (d, c)
+        pairs.append((min(a, b), max(a, b)))
+    assert pairs == sorted(pairs)          # ids follow (smaller, larger) order
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_ingest_structure_and_fixed_point(order):
+    n = 200
+    u, v, w = _random_list(n, 2000, 11)
+    row_ptr, col, we, eid, orig, m, _ = oracle.ingest(n, u, v, w, order=order)
+    _check_csr(n, row_ptr, col, eid, m)
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    up = col > rows
+    again = oracle.ingest(n, rows[up], col[up], we[up], orig_id=orig)
+    np.testing.assert_array_equal(again[0], row_ptr)
+    np.testing.assert_array_equal(again[1], col)
+    np.testing.assert_array_equal(again[2], we)
+    np.testing.assert_array_equal(again[3], eid)
+    np.testing.assert_array_equal(again[4], orig)
+
+
+def test_decreasing_degree_order():
+    n = 300
+    u, v, w = _random_list(n, 2500, 12)
+    base = oracle.ingest(n, u, v, w)
+    row_ptr, col, we, eid, orig, m, _ = oracle.ingest(n, u, v, w, order=1)
+    deg = np.diff(row_ptr)
+    assert np.all(np.diff(deg) <= 0)
+    # ties keep the listed order
+    for d in np.unique(deg):
+        ids = orig[deg == d]
+        assert np.all(np.diff(ids) > 0)
+    assert sorted(orig.tolist()) == list(range(n))
+    # the same weighted edge set, named by listed ids
+    def edge_set(rp, cl, ww, oid):
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        return {(int(min(oid[a], oid[b])), int(max(oid[a], oid[b]))): float(x)
+                for a, b, x in zip(rows, cl, ww)}
+    assert edge_set(row_ptr, col, we, orig) == edge_set(base[0], base[1], base[2], base[4])
+
+
+def test_decreasing_degree_order_matches_relabel():
+    g = G.chung_lu(3000, 20_000, seed=2)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    up = g.col > rows
+    h = G.relabel(g, G.degree_descending_order(g))
+    out = oracle.ingest(g.n, rows[up], g.col[up], g.w[up], order=1)
+    np.testing.assert_array_equal(out[0], h.row_ptr)
+    np.testing.assert_array_equal(out[1], h.col)
+    np.testing.assert_array_equal(out[2], h.w)
+    np.testing.assert_array_equal(out[3], h.eid)
+    np.testing.assert_array_equal(out[4], h.orig_id)
+
+
+def test_orig_ids_pass_through():
+    n = 50
+    u, v, w = _random_list(n, 200, 13)
+    names = np.random.default_rng(1).permutation(10_000)[:n].astype(np.int32)
+    out = oracle.ingest(n, u, v, w, orig_id=names, order=1)
+    ref = oracle.ingest(n, u, v, w, order=1)
+    np.testing.assert_array_equal(out[4], names[ref[4]])
+
+
+def test_unweighted_lists_and_edge_cases():
+    out = oracle.ingest(5, [0, 1, 1], [1, 0, 1])
+    assert out[2] is None and out[5] == 1 and out[6] == 2
+    empty = oracle.ingest(3, [], [])
+    assert empty[5] == 0 and np.all(empty[0] == 0)
+    with pytest.raises(ValueError):
+        oracle.ingest(3, [0, 3], [1, 1])
+    with pytest.raises(ValueError):
+        oracle.ingest(3, [-1], [1])
