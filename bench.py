@@ -283,6 +283,22 @@ def run_chung_lu(args, api, torch, dev):
                         "step's own distances; synchronises for the fit"))
     del ws_b
 
+    # on-device ingest of the graph as drawn (16M pairs, random labels) into the
+    # degree-ordered CSR the step runs on
+    gu = torch.from_numpy(g_orig.edge_u).to(dev)
+    gv = torch.from_numpy(g_orig.edge_v).to(dev)
+    gw = torch.from_numpy(g_orig.edge_w).to(dev)
+    di = api.ingest(n, gu, gv, gw, by_degree=True, entry_ids=False)
+    same = bool(torch.equal(di.row_ptr, dg.row_ptr) and torch.equal(di.col, dg.col) and
+                torch.equal(di.w, dg.w) and torch.equal(di.eid, dg.eid) and torch.equal(di.orig_id, dg.orig_id))
+    del di
+    ing_ms = timer.run(lambda: api.ingest(n, gu, gv, gw, by_degree=True, entry_ids=False), 3)
+    ingest = {"ms": ing_ms, "pairs_per_s": g_orig.m / (ing_ms * 1e-3), "equals_step_layout": same,
+              "what": (f"ad_ingest of the {g_orig.m} drawn pairs (random labels, lognormal weights) into the "
+                       "symmetric CSR stored by decreasing degree, outputs allocated per call; "
+                       f"(host generation and layout of the graph: {t_setup:.1f} s)")}
+    del gu, gv, gw
+
     # context: the sweep's neighbour-row gathers alone, with nothing else asked of the
     # memory system (the irregular path's practical ceiling), and the vendor SpMM
     sweep_ms = roof["avg_launch_ms"]
@@ -327,6 +343,7 @@ def run_chung_lu(args, api, torch, dev):
         gather_ceiling=gather,
         vendor_spmm=spmm,
         binned_selection=binned,
+        ingest=ingest,
         traffic_over_algorithmic=(roof["traffic"] / sb) if roof["traffic"] else None,
         sweep_updates_per_s=nnz * R / (roof["avg_launch_ms"] * 1e-3) if roof["avg_launch_ms"] else None,
         fit={"e_local": fit["e_local"], "e_global": fit["e_global"], "kept_local": kept_l,

@@ -49,7 +49,7 @@ typedef enum {
     AD_ERR_INVALID_ARG = 1,   /* a null pointer, a size or a parameter out of range  */
     AD_ERR_UNSUPPORTED = 2,   /* a valid but unimplemented combination               */
     AD_ERR_WORKSPACE = 3,     /* ws too small or misaligned                          */
-    AD_ERR_GRAPH = 4,         /* ad_validate_graph found a structural defect         */
+    AD_ERR_GRAPH = 4,         /* a structural defect (ad_validate_graph, ad_ingest)  */
     AD_ERR_HIP = 5,           /* a HIP runtime call failed                           */
     AD_ERR_INTERNAL = 6       /* an internal consistency check failed                */
 } ad_status;
@@ -257,6 +257,41 @@ ad_status ad_sparsify_binned(const ad_graph *g, ad_dtype rho_dtype, const void *
                              uint64_t seed, uint64_t graph_id, double e, double target,
                              uint8_t *keep, int64_t *n_kept, double *e_used_host, void *ws,
                              size_t ws_bytes, hipStream_t stream);
+
+/* --------------------------------------------------------------- ingest --- */
+
+/* Workspace bytes for ad_ingest (0 when n or m_in is negative or >= 2^31). */
+size_t ad_ingest_workspace_size(int64_t n, int64_t m_in);
+
+/* An undirected edge list into the symmetric CSR of the graph model every
+ * other call reads (Section 2: undirected, no self-loops, no repeated
+ * pairs).  (u[q], v[q]) and (v[q], u[q]) name the same edge; self-loops are
+ * dropped; repeated pairs become one edge whose weight is the sum of the
+ * listed weights (added in double in list order, rounded to single
+ * precision).  Edge ids enumerate the edges in (smaller, larger endpoint)
+ * order (the CSR order of their upper entries); every row lists its
+ * neighbours in ascending order.
+ *   n, m_in: vertices and listed pairs, both < 2^31; u, v: DEVICE [m_in].
+ *   w: DEVICE [m_in] or NULL (unweighted: w_out unused, may be NULL).
+ *   orig_id: DEVICE [n] names of the listed vertices or NULL (identity).
+ *   order: 0 keeps the listed ids; 1 stores vertices by decreasing degree,
+ *          ties by listed id (the layout the sweeps prefer).
+ *   Outputs (DEVICE, caller-owned): row_ptr [n+1]; col, eid and w_out
+ *   [2*m_in] (the first 2*m entries written); orig_id_out [n], the name of
+ *   every stored vertex (orig_id of its listed vertex, or the listed id).
+ *   m_host, d_max_host, n_dropped_host: HOST; the edge count m, the largest
+ *   degree and m_in - m (self-loops plus merged repeats); d_max_host and
+ *   n_dropped_host may be NULL.
+ * The sorts are rocPRIM's radix sort (stable).  SYNCHRONISES `stream` (the
+ * edge count sizes the later passes).  Errors: AD_ERR_GRAPH when an endpoint
+ * lies outside [0, n) (nothing is written past the check);
+ * AD_ERR_INVALID_ARG / AD_ERR_UNSUPPORTED for bad arguments or sizes;
+ * AD_ERR_WORKSPACE for a short or misaligned workspace. */
+ad_status ad_ingest(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v, const float *w,
+                    const int32_t *orig_id, int32_t order, int64_t *row_ptr, int32_t *col,
+                    float *w_out, int32_t *eid, int32_t *orig_id_out, int64_t *m_host,
+                    int32_t *d_max_host, int64_t *n_dropped_host, void *ws, size_t ws_bytes,
+                    hipStream_t stream);
 
 /* ------------------------------------------------------------- adjoint --- */
 

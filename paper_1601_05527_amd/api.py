@@ -73,6 +73,9 @@ def _load_lib():
         "ad_sparsify_fit_both_workspace_size": (S, [G]),
         "ad_normalize_dist_workspace_size": (S, [G]),
         "ad_normalize_dist": (st, [G, ctypes.c_int, P, ctypes.c_int32, f64, P, P, S, P]),
+        "ad_ingest_workspace_size": (S, [i64, i64]),
+        "ad_ingest": (st, [i64, i64, P, P, P, P, i32, P, P, P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                           ctypes.POINTER(i64), P, S, P]),
         "ad_sparsify_binned_workspace_size": (S, [G]),
         "ad_sparsify_binned": (st, [G, ctypes.c_int, P, ctypes.c_uint64, ctypes.c_uint64, f64, f64, P, P,
                                     ctypes.POINTER(ctypes.c_double), P, S, P]),
@@ -530,3 +533,41 @@ def sparsify_binned(dg: DeviceGraph, rho: torch.Tensor, seed: int, e: float = 0.
                                   int(graph_id) & (2 ** 64 - 1), float(e), float(target), _ptr(keep),
                                   _ptr(n_kept), ctypes.byref(e_used), _ptr(ws), ws.numel(), _stream()))
     return keep, n_kept, e_used.value
+
+
+# ---------------------------------------------------------------- ingest ---
+
+def ingest(n: int, u: torch.Tensor, v: torch.Tensor, w: Optional[torch.Tensor] = None,
+           orig_id: Optional[torch.Tensor] = None, by_degree: bool = True,
+           entry_ids: bool = True) -> DeviceGraph:
+    """An undirected edge list on the device into a ``DeviceGraph``
+    (``ad_ingest``): self-loops dropped, repeated pairs merged (weights
+    summed), vertices stored by decreasing degree unless ``by_degree`` is
+    False.  Synchronises the current stream."""
+    dev = u.device
+    m_in = int(u.numel())
+    u = u.to(torch.int32).contiguous()
+    v = v.to(torch.int32).contiguous()
+    if w is not None:
+        w = w.to(torch.float32).contiguous()
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(1, 2 * m_in), dtype=torch.int32, device=dev)
+    eid = torch.empty(max(1, 2 * m_in), dtype=torch.int32, device=dev)
+    w_out = torch.empty(max(1, 2 * m_in), dtype=torch.float32, device=dev) if w is not None else None
+    orig = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+    ws = _workspace(lib.ad_ingest_workspace_size(n, m_in), dev)
+    m = ctypes.c_int64(0)
+    d_max = ctypes.c_int32(0)
+    dropped = ctypes.c_int64(0)
+    _check(lib.ad_ingest(n, m_in, _ptr(u), _ptr(v), _ptr(w), _ptr(orig_id), 1 if by_degree else 0, _ptr(row_ptr),
+                         _ptr(col), _ptr(w_out), _ptr(eid), _ptr(orig), ctypes.byref(m), ctypes.byref(d_max),
+                         ctypes.byref(dropped), _ptr(ws), ws.numel(), _stream()))
+    nnz = 2 * m.value
+    dg = DeviceGraph(n=n, m=m.value, d_max=d_max.value, row_ptr=row_ptr, col=col[:nnz], w=None if w is None else
+                     w_out[:nnz], eid=eid[:nnz], orig_id=orig[:n])
+    dg.n_dropped = dropped.value      # type: ignore[attr-defined]
+    if entry_ids and dg.m > 0:
+        dg.col_orig = torch.empty(2 * dg.m, dtype=torch.int32, device=dev)
+        gs = dg.abi()
+        _check(lib.ad_graph_col_orig(ctypes.byref(gs), _ptr(dg.col_orig), _stream()))
+    return dg

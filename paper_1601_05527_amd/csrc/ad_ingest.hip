@@ -1,0 +1,419 @@
+// Ingest: an undirected edge list into the symmetric CSR that every other
+// call reads (the graph model of Section 2: undirected, no self-loops, no
+// repeated pairs), optionally with the vertices stored by decreasing degree.
+//
+// Readings (shared with the oracle, which is written separately): (u, v) and
+// (v, u) name the same edge; self-loops are dropped; repeated pairs become
+// one edge whose weight is the sum of the listed weights, added in double in
+// list order and rounded to single precision; edge ids enumerate the edges
+// in (smaller endpoint, larger endpoint) order, the CSR order of their upper
+// entries; rows list neighbours in ascending order; the decreasing-degree
+// order breaks ties by listed id, and orig_id names the listed vertex.
+//
+// The pipeline: canonical 64-bit pair keys, a stable radix sort (rocPRIM) of
+// (key, list index), run heads and their scan (edge ids), one thread per run
+// summing its weights in list order; for the degree order a sort of (degree,
+// id) vertex keys and a second pair sort under the new labels; then per-row
+// counts, their scans and the placement of the upper entries (edge order)
+// and of the lower entries (a stable sort of the edges by larger endpoint).
+#include "ad_internal.h"
+
+#include <cstring>    // before rocPRIM: its host code calls memset
+
+#include <rocprim/rocprim.hpp>
+
+#include <algorithm>
+#include <cstdint>
+
+namespace ad {
+
+constexpr int IBLOCK = 256;
+constexpr unsigned long long NO_PAIR = ~0ull;
+
+static unsigned bits_for(int64_t n) {
+    unsigned b = 1;
+    while (b < 32 && ((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+// Pair key (smaller << 32 | larger), NO_PAIR for self-loops; endpoints out
+// of [0, n) raise the error flag (and sort last).
+__global__ void k_pair_keys(int64_t m_in, int64_t n, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
+                            unsigned long long *__restrict__ key, uint32_t *__restrict__ idx,
+                            unsigned int *__restrict__ err) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m_in; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = u[q], b = v[q];
+        unsigned long long k = NO_PAIR;
+        if (a < 0 || a >= n || b < 0 || b >= n) {
+            atomicOr(err, 1u);
+        } else if (a != b) {
+            const uint64_t lo = (uint64_t)(a < b ? a : b), hi = (uint64_t)(a < b ? b : a);
+            k = (lo << 32) | hi;
+        }
+        key[q] = k;
+        idx[q] = (uint32_t)q;
+    }
+}
+
+// 1 at the first entry of every run of equal pair keys.
+__global__ void k_run_heads(int64_t count, const unsigned long long *__restrict__ key, uint32_t *__restrict__ head) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x)
+        head[q] = (key[q] != NO_PAIR && (q == 0 || key[q] != key[q - 1])) ? 1u : 0u;
+}
+
+// One thread per run: the edge's endpoints and its weight, the run's listed
+// weights summed in list order (the sort is stable) in double.
+__global__ void k_merge_runs(int64_t count, const unsigned long long *__restrict__ key,
+                             const uint32_t *__restrict__ idx, const uint32_t *__restrict__ head,
+                             const uint32_t *__restrict__ edge_of, const float *__restrict__ w,
+                             int32_t *__restrict__ ea, int32_t *__restrict__ eb, float *__restrict__ ew) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
+        if (!head[q]) continue;
+        const unsigned long long k = key[q];
+        const uint32_t e = edge_of[q];
+        ea[e] = (int32_t)(k >> 32);
+        eb[e] = (int32_t)(k & 0xffffffffull);
+        if (w) {
+            double sum = 0.0;
+            for (int64_t r = q; r < count && key[r] == k; ++r) sum += (double)w[idx[r]];
+            ew[e] = (float)sum;
+        }
+    }
+}
+
+__global__ void k_edge_degrees(int64_t m, const int32_t *__restrict__ ea, const int32_t *__restrict__ eb,
+                               uint32_t *__restrict__ deg, uint32_t *__restrict__ lower_cnt,
+                               uint32_t *__restrict__ upper_cnt) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        atomicAdd(&deg[ea[e]], 1u);
+        atomicAdd(&deg[eb[e]], 1u);
+        if (lower_cnt) atomicAdd(&lower_cnt[eb[e]], 1u);
+        if (upper_cnt) atomicAdd(&upper_cnt[ea[e]], 1u);
+    }
+}
+
+__global__ void k_degree_max(int64_t n, const uint32_t *__restrict__ deg, unsigned int *__restrict__ dmax) {
+    unsigned int mx = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        mx = max(mx, deg[i]);
+    for (int o = WAVE / 2; o >= 1; o >>= 1) mx = max(mx, (unsigned int)__shfl_xor((int)mx, o, WAVE));
+    if ((threadIdx.x & (WAVE - 1)) == 0) atomicMax(dmax, mx);
+}
+
+// Storage-order key of vertex i: decreasing degree, then increasing listed id.
+__global__ void k_vertex_keys(int64_t n, const uint32_t *__restrict__ deg, unsigned long long *__restrict__ vkey,
+                              uint32_t *__restrict__ vid) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        vkey[i] = ((unsigned long long)(0xffffffffu - deg[i]) << 32) | (unsigned long long)i;
+        vid[i] = (uint32_t)i;
+    }
+}
+
+__global__ void k_new_ids(int64_t n, const uint32_t *__restrict__ vid_sorted, uint32_t *__restrict__ new_of,
+                          const int32_t *__restrict__ orig_in, int32_t *__restrict__ orig_out) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = vid_sorted[r];
+        new_of[i] = (uint32_t)r;
+        orig_out[r] = orig_in ? orig_in[i] : (int32_t)i;
+    }
+}
+
+__global__ void k_orig_identity(int64_t n, const int32_t *__restrict__ orig_in, int32_t *__restrict__ orig_out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        orig_out[i] = orig_in ? orig_in[i] : (int32_t)i;
+}
+
+// Edge keys under the new labels (no repeats remain), payload the old edge id.
+__global__ void k_relabel_keys(int64_t m, const int32_t *__restrict__ ea, const int32_t *__restrict__ eb,
+                               const uint32_t *__restrict__ new_of, unsigned long long *__restrict__ key,
+                               uint32_t *__restrict__ idx) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = new_of[ea[e]], y = new_of[eb[e]];
+        key[e] = ((x < y ? x : y) << 32) | (x < y ? y : x);
+        idx[e] = (uint32_t)e;
+    }
+}
+
+__global__ void k_unpack_edges(int64_t m, const unsigned long long *__restrict__ key,
+                               const uint32_t *__restrict__ idx, const float *__restrict__ ew_old,
+                               int32_t *__restrict__ ea, int32_t *__restrict__ eb, float *__restrict__ ew) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        ea[e] = (int32_t)(key[e] >> 32);
+        eb[e] = (int32_t)(key[e] & 0xffffffffull);
+        if (ew_old) ew[e] = ew_old[idx[e]];
+    }
+}
+
+// Upper entry of edge e = (a, b): after row a's lower entries, at e's place
+// among the edges that start at a (edge ids are in (a, b) order).
+__global__ void k_place_upper(int64_t m, const int32_t *__restrict__ ea, const int32_t *__restrict__ eb,
+                              const float *__restrict__ ew, const int64_t *__restrict__ row_ptr,
+                              const uint32_t *__restrict__ lower_cnt, const uint64_t *__restrict__ upper_start,
+                              int32_t *__restrict__ col, float *__restrict__ w_out, int32_t *__restrict__ eid) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = ea[e];
+        const int64_t pos = row_ptr[a] + lower_cnt[a] + (e - (int64_t)upper_start[a]);
+        col[pos] = eb[e];
+        eid[pos] = (int32_t)e;
+        if (w_out) w_out[pos] = ew[e];
+    }
+}
+
+// Lower entry of edge e = (a, b), from the edges sorted by b (stably, so by a
+// within each b): at its place among the edges that end at b.
+__global__ void k_place_lower(int64_t m, const uint32_t *__restrict__ b_sorted, const uint32_t *__restrict__ e_sorted,
+                              const int32_t *__restrict__ ea, const float *__restrict__ ew,
+                              const int64_t *__restrict__ row_ptr, const uint64_t *__restrict__ lower_start,
+                              int32_t *__restrict__ col, float *__restrict__ w_out, int32_t *__restrict__ eid) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = b_sorted[t], e = e_sorted[t];
+        const int64_t pos = row_ptr[b] + (t - (int64_t)lower_start[b]);
+        col[pos] = ea[e];
+        eid[pos] = (int32_t)e;
+        if (w_out) w_out[pos] = ew[e];
+    }
+}
+
+__global__ void k_edge_b(int64_t m, const int32_t *__restrict__ eb, uint32_t *__restrict__ bkey,
+                         uint32_t *__restrict__ eidx) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        bkey[e] = (uint32_t)eb[e];
+        eidx[e] = (uint32_t)e;
+    }
+}
+
+__global__ void k_u32_to_u64(int64_t n, const uint32_t *__restrict__ a, uint64_t *__restrict__ b) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+struct IngestLayout {
+    unsigned long long *key0, *key1;     // [m_in] pair keys (sort double buffer)
+    uint32_t *idx0, *idx1;               // [m_in] list indices / edge ids
+    uint32_t *head, *edge_of;            // [m_in]
+    int32_t *ea, *eb;                    // [m_in] edges (a < b)
+    float *ew, *ew2;                     // [m_in]
+    uint32_t *deg, *lower_cnt, *upper_cnt, *new_of;   // [n]
+    uint64_t *lower_start, *upper_start, *deg64;      // [n]
+    unsigned long long *vkey0, *vkey1;   // [n]
+    uint32_t *vid0, *vid1;               // [n]
+    unsigned int *flags;                 // [4]: error, d_max, m
+    void *temp;                          // rocPRIM temporary storage
+    size_t temp_bytes;
+};
+
+// Largest temporary storage any of the pipeline's rocPRIM calls asks for (0
+// when a query fails; the launch then reports the error).
+static size_t rocprim_temp_bytes(int64_t m_in, int64_t n) {
+    size_t need = 0, t = 0;
+    hipError_t e = hipSuccess;
+    const size_t mm = (size_t)std::max<int64_t>(1, m_in), nn = (size_t)std::max<int64_t>(1, n);
+    e = rocprim::radix_sort_pairs(nullptr, t, (unsigned long long *)nullptr, (unsigned long long *)nullptr,
+                                  (uint32_t *)nullptr, (uint32_t *)nullptr, mm, 0, 64);
+    need = std::max(need, e == hipSuccess ? t : 0);
+    e = rocprim::radix_sort_pairs(nullptr, t, (unsigned long long *)nullptr, (unsigned long long *)nullptr,
+                                  (uint32_t *)nullptr, (uint32_t *)nullptr, nn, 0, 64);
+    need = std::max(need, e == hipSuccess ? t : 0);
+    e = rocprim::radix_sort_pairs(nullptr, t, (uint32_t *)nullptr, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                  (uint32_t *)nullptr, mm, 0, 32);
+    need = std::max(need, e == hipSuccess ? t : 0);
+    e = rocprim::exclusive_scan(nullptr, t, (uint32_t *)nullptr, (uint32_t *)nullptr, 0u, mm,
+                                rocprim::plus<uint32_t>());
+    need = std::max(need, e == hipSuccess ? t : 0);
+    e = rocprim::exclusive_scan(nullptr, t, (uint64_t *)nullptr, (uint64_t *)nullptr, (uint64_t)0, nn + 1,
+                                rocprim::plus<uint64_t>());
+    need = std::max(need, e == hipSuccess ? t : 0);
+    return need;
+}
+
+static size_t ingest_layout(int64_t n, int64_t m_in, void *ws, size_t ws_bytes, IngestLayout *L) {
+    Carver c(ws, ws_bytes);
+    const size_t mm = (size_t)std::max<int64_t>(1, m_in), nn = (size_t)std::max<int64_t>(1, n) + 1;
+    IngestLayout l;
+    l.key0 = c.take<unsigned long long>(mm);
+    l.key1 = c.take<unsigned long long>(mm);
+    l.idx0 = c.take<uint32_t>(mm);
+    l.idx1 = c.take<uint32_t>(mm);
+    l.head = c.take<uint32_t>(mm);
+    l.edge_of = c.take<uint32_t>(mm);
+    l.ea = c.take<int32_t>(mm);
+    l.eb = c.take<int32_t>(mm);
+    l.ew = c.take<float>(mm);
+    l.ew2 = c.take<float>(mm);
+    l.deg = c.take<uint32_t>(nn);
+    l.lower_cnt = c.take<uint32_t>(nn);
+    l.upper_cnt = c.take<uint32_t>(nn);
+    l.new_of = c.take<uint32_t>(nn);
+    l.lower_start = c.take<uint64_t>(nn);
+    l.upper_start = c.take<uint64_t>(nn);
+    l.deg64 = c.take<uint64_t>(nn);
+    l.vkey0 = c.take<unsigned long long>(nn);
+    l.vkey1 = c.take<unsigned long long>(nn);
+    l.vid0 = c.take<uint32_t>(nn);
+    l.vid1 = c.take<uint32_t>(nn);
+    l.flags = c.take<unsigned int>(4);
+    l.temp_bytes = rocprim_temp_bytes(m_in, n);
+    l.temp = c.take<char>(l.temp_bytes);
+    if (L) *L = l;
+    return c.ok() ? c.used : 0;
+}
+
+static unsigned igrid(int64_t count) { return grid_for(std::max<int64_t>(1, count), IBLOCK); }
+
+#define AD_RP(call)                                                         \
+    do {                                                                    \
+        hipError_t e_ = (call);                                             \
+        if (e_ != hipSuccess) return fail(AD_ERR_HIP, std::string("rocPRIM: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static ad_status ingest_impl(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v, const float *w,
+                             const int32_t *orig_in, int32_t order, int64_t *row_ptr, int32_t *col, float *w_out,
+                             int32_t *eid, int32_t *orig_out, int64_t *m_host, int32_t *d_max_host,
+                             int64_t *n_dropped_host, const IngestLayout &L, hipStream_t st) {
+    TraceScope trace("k_ingest", st);
+    ad_status s = fill_i32((int32_t *)L.flags, 0, 4, st);
+    if (s != AD_OK) return s;
+    int64_t m = 0;
+    if (m_in > 0) {
+        hipLaunchKernelGGL(k_pair_keys, dim3(igrid(m_in)), dim3(IBLOCK), 0, st, m_in, n, u, v, L.key0, L.idx0,
+                           L.flags);
+        AD_LAUNCH_CHECK("k_pair_keys");
+        size_t tb = L.temp_bytes;
+        AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.key0, L.key1, L.idx0, L.idx1, (size_t)m_in, 0, 64, st));
+        hipLaunchKernelGGL(k_run_heads, dim3(igrid(m_in)), dim3(IBLOCK), 0, st, m_in, L.key1, L.head);
+        AD_LAUNCH_CHECK("k_run_heads");
+        tb = L.temp_bytes;
+        AD_RP(rocprim::exclusive_scan(L.temp, tb, L.head, L.edge_of, 0u, (size_t)m_in, rocprim::plus<uint32_t>(),
+                                      st));
+        unsigned int hflags[2];
+        uint32_t last[2];
+        AD_HIP(hipMemcpyAsync(hflags, L.flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+        AD_HIP(hipMemcpyAsync(&last[0], L.edge_of + (m_in - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        AD_HIP(hipMemcpyAsync(&last[1], L.head + (m_in - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        AD_HIP(hipStreamSynchronize(st));
+        if (hflags[0]) return fail(AD_ERR_GRAPH, "edge list names a vertex outside [0, n)");
+        m = (int64_t)last[0] + (int64_t)last[1];
+        hipLaunchKernelGGL(k_merge_runs, dim3(igrid(m_in)), dim3(IBLOCK), 0, st, m_in, L.key1, L.idx1, L.head,
+                           L.edge_of, w, L.ea, L.eb, L.ew);
+        AD_LAUNCH_CHECK("k_merge_runs");
+    }
+    const int32_t *ea = L.ea, *eb = L.eb;
+    const float *ew = L.ew;
+    s = fill_i32((int32_t *)L.deg, 0, std::max<int64_t>(1, n), st);
+    if (s != AD_OK) return s;
+    if (order == 1 && n > 0) {
+        if (m > 0) {
+            hipLaunchKernelGGL(k_edge_degrees, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, L.deg,
+                               (uint32_t *)nullptr, (uint32_t *)nullptr);
+            AD_LAUNCH_CHECK("k_edge_degrees");
+        }
+        hipLaunchKernelGGL(k_vertex_keys, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.deg, L.vkey0, L.vid0);
+        AD_LAUNCH_CHECK("k_vertex_keys");
+        size_t tb = L.temp_bytes;
+        AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.vkey0, L.vkey1, L.vid0, L.vid1, (size_t)n, 0, 64, st));
+        hipLaunchKernelGGL(k_new_ids, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.vid1, L.new_of, orig_in, orig_out);
+        AD_LAUNCH_CHECK("k_new_ids");
+        if (m > 0) {
+            hipLaunchKernelGGL(k_relabel_keys, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, L.new_of, L.key0,
+                               L.idx0);
+            AD_LAUNCH_CHECK("k_relabel_keys");
+            tb = L.temp_bytes;
+            AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.key0, L.key1, L.idx0, L.idx1, (size_t)m, 0, 64, st));
+            hipLaunchKernelGGL(k_unpack_edges, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, L.key1, L.idx1,
+                               w ? L.ew : (const float *)nullptr, L.ea, L.eb, L.ew2);
+            AD_LAUNCH_CHECK("k_unpack_edges");
+            ew = L.ew2;
+        }
+        s = fill_i32((int32_t *)L.deg, 0, n, st);
+        if (s != AD_OK) return s;
+    } else if (n > 0) {
+        hipLaunchKernelGGL(k_orig_identity, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, orig_in, orig_out);
+        AD_LAUNCH_CHECK("k_orig_identity");
+    }
+    // per-row counts under the final labels, and their scans
+    if (n > 0) {
+        s = fill_i32((int32_t *)L.lower_cnt, 0, n, st);
+        if (s != AD_OK) return s;
+        s = fill_i32((int32_t *)L.upper_cnt, 0, n, st);
+        if (s != AD_OK) return s;
+        if (m > 0) {
+            hipLaunchKernelGGL(k_edge_degrees, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, L.deg, L.lower_cnt,
+                               L.upper_cnt);
+            AD_LAUNCH_CHECK("k_edge_degrees");
+        }
+        hipLaunchKernelGGL(k_degree_max, dim3(std::min<unsigned>(1024, igrid(n))), dim3(IBLOCK), 0, st, n, L.deg,
+                           L.flags + 1);
+        AD_LAUNCH_CHECK("k_degree_max");
+    }
+    // row_ptr = exclusive scan of the degrees over n + 1 entries (the last one 0)
+    s = fill_i32((int32_t *)(L.deg64 + n), 0, 2, st);
+    if (s != AD_OK) return s;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_u32_to_u64, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.deg, L.deg64);
+        AD_LAUNCH_CHECK("k_u32_to_u64");
+    }
+    size_t tb = L.temp_bytes;
+    AD_RP(rocprim::exclusive_scan(L.temp, tb, L.deg64, (uint64_t *)row_ptr, (uint64_t)0, (size_t)n + 1,
+                                  rocprim::plus<uint64_t>(), st));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_u32_to_u64, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.upper_cnt, L.deg64);
+        AD_LAUNCH_CHECK("k_u32_to_u64");
+        tb = L.temp_bytes;
+        AD_RP(rocprim::exclusive_scan(L.temp, tb, L.deg64, L.upper_start, (uint64_t)0, (size_t)n,
+                                      rocprim::plus<uint64_t>(), st));
+        hipLaunchKernelGGL(k_u32_to_u64, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.lower_cnt, L.deg64);
+        AD_LAUNCH_CHECK("k_u32_to_u64");
+        tb = L.temp_bytes;
+        AD_RP(rocprim::exclusive_scan(L.temp, tb, L.deg64, L.lower_start, (uint64_t)0, (size_t)n,
+                                      rocprim::plus<uint64_t>(), st));
+        hipLaunchKernelGGL(k_place_upper, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, ew, row_ptr, L.lower_cnt,
+                           L.upper_start, col, w ? w_out : (float *)nullptr, eid);
+        AD_LAUNCH_CHECK("k_place_upper");
+        // lower entries: the edges sorted (stably) by their larger endpoint
+        hipLaunchKernelGGL(k_edge_b, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, eb, L.idx0, L.head);
+        AD_LAUNCH_CHECK("k_edge_b");
+        tb = L.temp_bytes;
+        AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.idx0, L.idx1, L.head, L.edge_of, (size_t)m, 0, bits_for(n),
+                                        st));
+        hipLaunchKernelGGL(k_place_lower, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, L.idx1, L.edge_of, ea, ew, row_ptr,
+                           L.lower_start, col, w ? w_out : (float *)nullptr, eid);
+        AD_LAUNCH_CHECK("k_place_lower");
+    }
+    unsigned int dmax = 0;
+    if (n > 0) AD_HIP(hipMemcpyAsync(&dmax, L.flags + 1, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+    AD_HIP(hipStreamSynchronize(st));
+    *m_host = m;
+    if (d_max_host) *d_max_host = (int32_t)dmax;
+    if (n_dropped_host) *n_dropped_host = m_in - m;
+    return AD_OK;
+}
+
+}  // namespace ad
+
+using namespace ad;
+
+extern "C" size_t ad_ingest_workspace_size(int64_t n, int64_t m_in) {
+    if (n < 0 || m_in < 0 || n >= ((int64_t)1 << 31) || m_in >= ((int64_t)1 << 31)) return 0;
+    return ingest_layout(n, m_in, nullptr, 0, nullptr);
+}
+
+extern "C" ad_status ad_ingest(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v, const float *w,
+                               const int32_t *orig_id, int32_t order, int64_t *row_ptr, int32_t *col, float *w_out,
+                               int32_t *eid, int32_t *orig_id_out, int64_t *m_host, int32_t *d_max_host,
+                               int64_t *n_dropped_host, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || m_in < 0) return fail(AD_ERR_INVALID_ARG, "negative n or edge count");
+    if (n >= ((int64_t)1 << 31) || m_in >= ((int64_t)1 << 31))
+        return fail(AD_ERR_UNSUPPORTED, "n and the edge count must be below 2^31");
+    if (order != 0 && order != 1) return fail(AD_ERR_INVALID_ARG, "order must be 0 (as listed) or 1 (by degree)");
+    if (m_in > 0 && (!u || !v)) return fail(AD_ERR_INVALID_ARG, "u or v is NULL");
+    if (!row_ptr || !m_host) return fail(AD_ERR_INVALID_ARG, "row_ptr or m_host is NULL");
+    if (m_in > 0 && (!col || !eid)) return fail(AD_ERR_INVALID_ARG, "col or eid is NULL");
+    if (n > 0 && !orig_id_out) return fail(AD_ERR_INVALID_ARG, "orig_id_out is NULL");
+    if (w && m_in > 0 && !w_out) return fail(AD_ERR_INVALID_ARG, "w_out is NULL for a weighted list");
+    if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    IngestLayout L;
+    if (ingest_layout(n, m_in, ws, ws_bytes, &L) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    return ingest_impl(n, m_in, u, v, w, orig_id, order, row_ptr, col, w_out, eid, orig_id_out, m_host, d_max_host,
+                       n_dropped_host, L, stream);
+}

@@ -184,3 +184,33 @@ def test_gather_probe_library_loads_and_rejects_bad_arguments():
     assert probe.ad_probe_gather(fake, 0, 64, fake, 8, fake, 1, None) == -1      # empty array
     assert probe.ad_probe_gather(fake, 4, 64, fake, 8, fake, 0, None) == -1      # no blocks
     assert probe.ad_probe_gather(fake, 4, 64, fake, 0, fake, 1, None) == 0       # nothing to gather
+
+
+def test_ingest_rejects_bad_arguments():
+    from paper_1601_05527_amd import api
+    L = api.lib
+    p = ctypes.c_void_p(0x40000)
+    ws = ctypes.c_void_p(0x10000)
+    m, d, k = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+
+    def call(n=10, m_in=5, u=p, v=p, w=None, order=1, rp=p, col=p, w_out=p, eid=p, orig=p, ws_=ws, nb=1 << 30):
+        return L.ad_ingest(n, m_in, u, v, w, None, order, rp, col, w_out, eid, orig, ctypes.byref(m),
+                           ctypes.byref(d), ctypes.byref(k), ws_, nb, None)
+
+    assert call(n=-1) == 1
+    assert call(m_in=-2) == 1
+    assert call(n=1 << 31) == 2
+    assert call(order=2) == 1
+    assert call(u=None) == 1
+    assert call(rp=None) == 1
+    assert call(col=None) == 1
+    assert call(orig=None) == 1
+    assert call(w=p, w_out=None) == 1
+    need = L.ad_ingest_workspace_size(10, 5)
+    assert need > 0
+    assert call(nb=need - 256) == 3
+    assert call(ws_=ctypes.c_void_p(0x10010), nb=need) == 3
+    assert L.ad_ingest_workspace_size(-1, 5) == 0
+    assert L.ad_ingest_workspace_size(10, 1 << 31) == 0
+    # the workspace grows with the list and the vertex count
+    assert L.ad_ingest_workspace_size(1000, 100_000) > L.ad_ingest_workspace_size(1000, 1000)

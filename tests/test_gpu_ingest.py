@@ -1,0 +1,126 @@
+"""Ingest (ad_ingest: an edge list into the symmetric CSR) against the oracle,
+through the C ABI.  Integer work and a fixed summation order: every output
+array must equal the oracle's bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_05527_amd import graphs as G
+
+from gpu_helpers import announce
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1601_05527_amd import api as _api
+    return _api
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _list(n, m_in, seed, dup_frac=0.2, loop_frac=0.02):
+    rng = np.random.default_rng(seed)
+    u = rng.integers(0, n, m_in)
+    v = rng.integers(0, n, m_in)
+    k = int(m_in * dup_frac)
+    pick = rng.integers(0, m_in, k)
+    flip = rng.random(k) < 0.5
+    u = np.concatenate([u, np.where(flip, v[pick], u[pick])])
+    v = np.concatenate([v, np.where(flip, u[pick], v[pick])])
+    loops = rng.integers(0, n, int(m_in * loop_frac))
+    u = np.concatenate([u, loops])
+    v = np.concatenate([v, loops])
+    perm = rng.permutation(u.size)
+    w = rng.lognormal(0.0, 1.0, u.size).astype(np.float32)
+    return u[perm].astype(np.int32), v[perm].astype(np.int32), w
+
+
+def _run(api, n, u, v, w=None, orig=None, by_degree=True):
+    cu = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return api.ingest(n, cu(u), cu(v), cu(w), cu(orig), by_degree=by_degree)
+
+
+def _compare(dg, ref):
+    row_ptr, col, we, eid, orig, m, dropped = ref
+    assert dg.m == m and dg.n_dropped == dropped
+    assert dg.d_max == (int(np.diff(row_ptr).max()) if len(row_ptr) > 1 else 0)
+    np.testing.assert_array_equal(_np(dg.row_ptr), row_ptr)
+    np.testing.assert_array_equal(_np(dg.col), col)
+    np.testing.assert_array_equal(_np(dg.eid), eid)
+    np.testing.assert_array_equal(_np(dg.orig_id), orig)
+    if we is None:
+        assert dg.w is None
+    else:
+        np.testing.assert_array_equal(_np(dg.w), we)
+
+
+@pytest.mark.parametrize("by_degree", [False, True])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_ingest_bit_exact(api, by_degree, seed, weighted):
+    announce(f"ingest seed={seed} by_degree={by_degree} weighted={weighted}")
+    n = [300, 5000, 70_000][seed]
+    u, v, w = _list(n, 8 * n, seed)
+    w = w if weighted else None
+    dg = _run(api, n, u, v, w, by_degree=by_degree)
+    _compare(dg, oracle.ingest(n, u, v, w, order=1 if by_degree else 0))
+
+
+def test_ingest_long_runs_and_hubs(api):
+    """One pair listed 5,000 times (a long merge run, summed in list order),
+    a star of degree 20,000 and isolated vertices."""
+    announce("ingest long runs and hubs")
+    rng = np.random.default_rng(7)
+    n = 40_000
+    u = [np.full(5000, 3), np.full(20_000, 9), rng.integers(100, 30_000, 50_000)]
+    v = [np.full(5000, 17), rng.permutation(np.arange(10, 40_000))[:20_000], rng.integers(100, 30_000, 50_000)]
+    u = np.concatenate(u).astype(np.int32)
+    v = np.concatenate(v).astype(np.int32)
+    w = rng.uniform(0.01, 10.0, u.size).astype(np.float32)
+    for by_degree in (False, True):
+        dg = _run(api, n, u, v, w, by_degree=by_degree)
+        _compare(dg, oracle.ingest(n, u, v, w, order=1 if by_degree else 0))
+
+
+def test_ingest_orig_ids_and_reuse(api):
+    """Names pass through; the ingested graph relaxes exactly like the same
+    CSR uploaded from the host."""
+    announce("ingest names and use")
+    g = G.chung_lu(8000, 60_000, seed=4)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    up = g.col > rows
+    names = np.random.default_rng(3).permutation(g.n).astype(np.int32)
+    dg = _run(api, g.n, rows[up].astype(np.int32), g.col[up], g.w[up], names)
+    _compare(dg, oracle.ingest(g.n, rows[up], g.col[up], g.w[up], orig_id=names, order=1))
+    h = G.relabel(G.from_edges(g.n, rows[up], g.col[up], g.w[up], orig_id=names),
+                  G.degree_descending_order(g))
+    dh = api.DeviceGraph.from_host(h, "cuda")
+    a = api.relax(dg, 8, 10, seed=5)
+    b = api.relax(dh, 8, 10, seed=5)
+    assert torch.equal(a.x, b.x) and torch.equal(a.minmax, b.minmax)
+
+
+def test_ingest_edge_cases(api):
+    announce("ingest edge cases")
+    z = np.zeros(0, dtype=np.int32)
+    dg = _run(api, 5, z, z)
+    assert dg.m == 0 and dg.d_max == 0 and _np(dg.row_ptr).tolist() == [0] * 6
+    assert _np(dg.orig_id).tolist() == list(range(5))
+    only_loops = np.array([1, 2, 2], dtype=np.int32)
+    dg = _run(api, 4, only_loops, only_loops)
+    assert dg.m == 0 and dg.n_dropped == 3
+    one = _run(api, 2, np.array([1], dtype=np.int32), np.array([0], dtype=np.int32),
+               np.array([2.5], dtype=np.float32), by_degree=False)
+    _compare(one, oracle.ingest(2, [1], [0], [2.5], order=0))
+    with pytest.raises(api.ADError) as ex:
+        _run(api, 4, np.array([0, 4], dtype=np.int32), np.array([1, 1], dtype=np.int32))
+    assert ex.value.status == 4       # AD_ERR_GRAPH
+    with pytest.raises(api.ADError):
+        _run(api, 4, np.array([-1], dtype=np.int32), np.array([1], dtype=np.int32))

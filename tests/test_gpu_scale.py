@@ -6,7 +6,8 @@ paper_1601_05527_amd.workloads).
       oracle (1e-5 relative, or the edge's FP32 conditioning bound where
       that is larger, gpu_helpers.fp32_tolerance); the fit on the oracle's distances equal to the oracle's
       bisection bit for bit; the end-to-end kept set near-cut equal; the
-      selection with binning (fixed e and fitted) equal to the oracle's.
+      selection with binning (fixed e and fitted) equal to the oracle's; the
+      graph as drawn ingested on the device equal to the oracle's ingest.
   Batch of 512 Chung-Lu graphs, FP32: every graph's kept set equal to the
       oracle's selection on the batch's distances, every graph's outputs
       equal to a standalone run bit for bit, distances of sampled graphs
@@ -92,6 +93,21 @@ def test_full_chung_lu(api):
     _log(f"binned fit: e {e_b!r} oracle {e_bo!r} kept {int(_np(nk_b)[0])} oracle {kept_bo}")
     assert e_b == e_bo
     assert np.array_equal(_np(keep_b), keep_bo) and int(_np(nk_b)[0]) == kept_bo
+
+
+@pytest.mark.timeout(900)
+def test_full_chung_lu_ingest(api):
+    """The benchmark's graph as drawn (16M pairs, random labels), ingested on
+    the device into the degree-ordered CSR, equals the oracle's ingest."""
+    announce("full size Chung-Lu ingest")
+    g0, _ = W.chung_lu_graph("degree")
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dg = api.ingest(g0.n, cu(g0.edge_u), cu(g0.edge_v), cu(g0.edge_w), by_degree=True)
+    row_ptr, col, we, eid, orig, m, dropped = oracle.ingest(g0.n, g0.edge_u, g0.edge_v, g0.edge_w, order=1)
+    _log(f"ingest: m {dg.m} oracle {m}, d_max {dg.d_max}")
+    assert dg.m == m and dropped == 0 and dg.n_dropped == 0
+    for got, want in ((dg.row_ptr, row_ptr), (dg.col, col), (dg.w, we), (dg.eid, eid), (dg.orig_id, orig)):
+        assert np.array_equal(_np(got), want)
 
 
 @pytest.mark.timeout(900)
