@@ -86,6 +86,15 @@ def _load():
     lib.orc_bin_layout.argtypes = [i64, P, P, P, P, P]
     lib.orc_binned_choices.argtypes = [i64, P, P, P, P, P, u64, u64, f64, P]
     lib.orc_ingest.argtypes = [i64, i64, P, P, P, P, i32, P, P, P, P, P, P]
+    lib.orc_subgraph.argtypes = [i64, P, P, P, P, i64, P, P, P, P, P, P]
+    lib.orc_subgraph.restype = i64
+    lib.orc_triangles.argtypes = [i64, P, P, P]
+    lib.orc_clustering.argtypes = [i64, P, P, P]
+    lib.orc_clustering.restype = f64
+    lib.orc_components.argtypes = [i64, P, P, P]
+    lib.orc_components.restype = i64
+    lib.orc_spearman.argtypes = [i64, P, P]
+    lib.orc_spearman.restype = f64
     lib.orc_ingest.restype = i64
     lib.orc_sparsify_binned.argtypes = [i64, P, P, P, P, i64, P, u64, u64, f64, P]
     lib.orc_sparsify_binned.restype = i64
@@ -296,3 +305,44 @@ def ingest(n: int, u, v, w=None, orig_id=None, order: int = 0):
     nnz = 2 * m
     return (row_ptr, col[:nnz].copy(), None if w_out is None else w_out[:nnz].copy(), eid[:nnz].copy(),
             orig[:n].copy(), int(m), int(dropped.value))
+
+
+def subgraph(g, keep):
+    """G_s = (V, {e : keep[e]}) as CSR arrays: (row_ptr, col, w or None,
+    eid renumbered over the kept edges, original edge id per entry, m_s)."""
+    lib = _load()
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    nnz = len(g.col)
+    rp = np.zeros(g.n + 1, dtype=np.int64)
+    col = np.zeros(max(1, nnz), dtype=np.int32)
+    w = np.zeros(max(1, nnz), dtype=np.float32) if g.w is not None else None
+    eid = np.zeros(max(1, nnz), dtype=np.int32)
+    oe = np.zeros(max(1, nnz), dtype=np.int32)
+    ms = lib.orc_subgraph(g.n, _p(g.row_ptr), _p(g.col), _p(_c(g.w, np.float32)), _p(g.eid), g.m, _p(k), _p(rp),
+                          _p(col), _p(w), _p(eid), _p(oe))
+    q = int(rp[-1])
+    return rp, col[:q].copy(), None if w is None else w[:q].copy(), eid[:q].copy(), oe[:q].copy(), int(ms)
+
+
+def properties(n: int, row_ptr, col):
+    """Triangles lambda_i, clustering c_i and C_G (Eq. cc), component
+    labels (smallest id of each component) and their number."""
+    lib = _load()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    lam = np.zeros(max(1, n), dtype=np.int64)
+    c = np.zeros(max(1, n), dtype=np.float64)
+    comp = np.zeros(max(1, n), dtype=np.int32)
+    lib.orc_triangles(n, _p(rp), _p(cl), _p(lam))
+    cg = lib.orc_clustering(n, _p(rp), _p(lam), _p(c))
+    nc = lib.orc_components(n, _p(rp), _p(cl), _p(comp))
+    return {"lambda": lam[:n], "c": c[:n], "C_G": float(cg), "comp": comp[:n], "n_components": int(nc)}
+
+
+def spearman(x, y) -> float:
+    """Spearman rank correlation by the Preliminaries' formula (ties share
+    the mean of their ranks)."""
+    lib = _load()
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    return float(lib.orc_spearman(xx.size, _p(xx), _p(yy)))

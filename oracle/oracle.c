@@ -672,6 +672,144 @@ int64_t orc_ingest(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Properties of a graph and of its sparsified subgraph (Preliminaries).     */
+
+/* G_s = (V, {e : keep[e]}): the kept entries of every row, in order; the
+ * subgraph's edge ids renumber the kept edges in increasing original id;
+ * orig_edge[p] is the original id of entry p.  Returns m_s.               */
+int64_t orc_subgraph(int64_t n, const int64_t *row_ptr, const int32_t *col, const float *w,
+                     const int32_t *eid, int64_t m, const uint8_t *keep, int64_t *sub_row_ptr,
+                     int32_t *sub_col, float *sub_w, int32_t *sub_eid, int32_t *orig_edge)
+{
+    int64_t *new_id = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    int64_t ms = 0;
+    for (int64_t e = 0; e < m; ++e) new_id[e] = keep[e] ? ms++ : -1;
+    int64_t q = 0;
+    sub_row_ptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            if (!keep[eid[p]]) continue;
+            sub_col[q] = col[p];
+            if (w && sub_w) sub_w[q] = w[p];
+            sub_eid[q] = (int32_t)new_id[eid[p]];
+            if (orig_edge) orig_edge[q] = eid[p];
+            ++q;
+        }
+        sub_row_ptr[i + 1] = q;
+    }
+    free(new_id);
+    return ms;
+}
+
+/* lambda_i: triangles vertex i belongs to, by testing every pair of its
+ * neighbours for adjacency (rows are sorted: bsearch).                      */
+static int orc_cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+void orc_triangles(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t *lambda)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t t = 0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+            for (int64_t q = p + 1; q < row_ptr[i + 1]; ++q) {
+                int32_t a = col[p], b = col[q];
+                int64_t lo = row_ptr[a], len = row_ptr[a + 1] - lo;
+                if (len > 0 && bsearch(&b, col + lo, (size_t)len, sizeof(int32_t), orc_cmp_i32)) ++t;
+            }
+        lambda[i] = t;
+    }
+}
+
+/* c_i = lambda_i / tau_i, tau_i = d_i (d_i - 1) / 2 (0 where d_i <= 1), and
+ * C_G = the mean of c_i over V' = {i : d_i > 1} (Eq. cc; 0 when V' is
+ * empty).  Returns C_G.                                                     */
+double orc_clustering(int64_t n, const int64_t *row_ptr, const int64_t *lambda, double *c)
+{
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t d = row_ptr[i + 1] - row_ptr[i];
+        c[i] = 0.0;
+        if (d > 1) {
+            c[i] = (double)lambda[i] / ((double)d * (double)(d - 1) / 2.0);
+            sum += c[i];
+            ++cnt;
+        }
+    }
+    return cnt ? sum / (double)cnt : 0.0;
+}
+
+/* Connected components by breadth-first search; comp[i] = the smallest
+ * vertex id of i's component.  Returns the number of components.            */
+int64_t orc_components(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t *comp)
+{
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) comp[i] = -1;
+    int64_t ncomp = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        if (comp[s] >= 0) continue;
+        ++ncomp;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        comp[s] = (int32_t)s;      /* s is the smallest id not yet reached */
+        while (head < tail) {
+            int64_t i = queue[head++];
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+                if (comp[col[p]] < 0) {
+                    comp[col[p]] = (int32_t)s;
+                    queue[tail++] = col[p];
+                }
+        }
+    }
+    free(queue);
+    return ncomp;
+}
+
+/* Spearman rank correlation (Preliminaries): rho = 1 - 6 sum p_i^2 /
+ * (n (n^2 - 1)), p_i = x_i - y_i the difference of the ranks of X_i and
+ * Y_i; tied scores share the mean of their ranks.                          */
+typedef struct { double v; int64_t i; } orc_score;
+
+static int orc_cmp_score(const void *a, const void *b)
+{
+    const orc_score *x = (const orc_score *)a, *y = (const orc_score *)b;
+    if (x->v != y->v) return x->v < y->v ? -1 : 1;
+    return (x->i > y->i) - (x->i < y->i);
+}
+
+static void orc_ranks(int64_t n, const double *v, double *rank)
+{
+    orc_score *s = (orc_score *)malloc(sizeof(orc_score) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) { s[i].v = v[i]; s[i].i = i; }
+    qsort(s, (size_t)n, sizeof(orc_score), orc_cmp_score);
+    for (int64_t a = 0; a < n;) {
+        int64_t b = a;
+        while (b < n && s[b].v == s[a].v) ++b;
+        double r = 0.5 * (double)(a + 1 + b);          /* mean of ranks a+1 .. b */
+        for (int64_t q = a; q < b; ++q) rank[s[q].i] = r;
+        a = b;
+    }
+    free(s);
+}
+
+double orc_spearman(int64_t n, const double *x, const double *y)
+{
+    if (n < 2) return 0.0;
+    double *rx = (double *)malloc(sizeof(double) * (size_t)n);
+    double *ry = (double *)malloc(sizeof(double) * (size_t)n);
+    orc_ranks(n, x, rx);
+    orc_ranks(n, y, ry);
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += (rx[i] - ry[i]) * (rx[i] - ry[i]);
+    free(rx); free(ry);
+    return 1.0 - 6.0 * s / ((double)n * ((double)n * (double)n - 1.0));
+}
+
+/* ------------------------------------------------------------------------ */
 /* Reverse-mode derivative of L = sum_e c_e rho_e with respect to the edge
  * weights w_e (w_ij = w_ji = w_e), taken through the k sweeps, the rescale
  * (its min and max as functions of x^(k)) and the distance.  Written by the
