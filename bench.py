@@ -283,6 +283,17 @@ def run_chung_lu(args, api, torch, dev):
                         "step's own distances; synchronises for the fit"))
     del ws_b
 
+    # the property comparisons of Section 6 for the step's LOCAL selection
+    props = {}
+
+    def compare():
+        props.update(api.compare_properties(dg, keep_l))
+
+    compare()
+    p_ms = timer.run(compare, 2)
+    props.update(ms=p_ms, what=("subgraph of the LOCAL selection, triangles / clustering / components of "
+                                "both graphs, Spearman of degrees and of clustering (synchronising calls)"))
+
     # on-device ingest of the graph as drawn (16M pairs, random labels) into the
     # degree-ordered CSR the step runs on
     gu = torch.from_numpy(g_orig.edge_u).to(dev)
@@ -344,6 +355,7 @@ def run_chung_lu(args, api, torch, dev):
         vendor_spmm=spmm,
         binned_selection=binned,
         ingest=ingest,
+        properties=props,
         traffic_over_algorithmic=(roof["traffic"] / sb) if roof["traffic"] else None,
         sweep_updates_per_s=nnz * R / (roof["avg_launch_ms"] * 1e-3) if roof["avg_launch_ms"] else None,
         fit={"e_local": fit["e_local"], "e_global": fit["e_global"], "kept_local": kept_l,

@@ -293,6 +293,50 @@ ad_status ad_ingest(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v,
                     int32_t *d_max_host, int64_t *n_dropped_host, void *ws, size_t ws_bytes,
                     hipStream_t stream);
 
+/* ----------------------------------------------------------- properties -- */
+
+/* Workspace bytes for ad_subgraph. */
+size_t ad_subgraph_workspace_size(const ad_graph *g);
+
+/* The sparsified graph G_s = (V, {e : keep[e]}) as a CSR of the same vertex
+ * set: every row's kept entries in their order; sub_eid renumbers the kept
+ * edges in increasing original id (so it is a valid ad_graph eid);
+ * orig_edge[p] (DEVICE, optional) is the original id of entry p.  keep:
+ * DEVICE [m] (0 / non-zero).  Outputs DEVICE, caller-owned: sub_row_ptr
+ * [n+1]; sub_col, sub_eid, sub_w (only when g->w), orig_edge: [2m] (the
+ * first 2 * m_sub written).  m_sub_host: HOST, the kept edge count.
+ * SYNCHRONISES `stream`. */
+ad_status ad_subgraph(const ad_graph *g, const uint8_t *keep, int64_t *sub_row_ptr, int32_t *sub_col,
+                      float *sub_w, int32_t *sub_eid, int32_t *orig_edge, int64_t *m_sub_host, void *ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes for ad_graph_properties. */
+size_t ad_graph_properties_workspace_size(const ad_graph *g);
+
+/* The single-graph properties of the Preliminaries, for comparing G_s with G:
+ *   lambda[i] (DEVICE int64 [n], optional): triangles vertex i belongs to;
+ *   c[i] (DEVICE double [n], optional): lambda_i / (d_i (d_i - 1) / 2),
+ *        0 where d_i <= 1;
+ *   comp[i] (DEVICE int32 [n], optional): the smallest vertex id of i's
+ *        connected component;
+ *   summary_host[0] = C_G, the mean of c_i over {i : d_i > 1} (Eq. cc; 0 if
+ *        that set is empty), summary_host[1] = the number of components.
+ * Counts are exact; C_G is summed in a fixed order.  Needs g->col ascending
+ * within rows.  SYNCHRONISES `stream` (the component rounds read a flag). */
+ad_status ad_graph_properties(const ad_graph *g, int64_t *lambda, double *c, int32_t *comp,
+                              double *summary_host, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes for ad_spearman (0 when n < 0 or n >= 2^31). */
+size_t ad_spearman_workspace_size(int64_t n);
+
+/* Spearman rank correlation of two per-vertex scores by the Preliminaries'
+ * formula rho = 1 - 6 sum_i p_i^2 / (n (n^2 - 1)), p_i the difference of the
+ * ranks of x[i] and y[i]; tied scores share the mean of their ranks.  x, y:
+ * DEVICE double [n], no NaN.  rho_host: HOST (0 when n < 2).  SYNCHRONISES
+ * `stream`. */
+ad_status ad_spearman(int64_t n, const double *x, const double *y, double *rho_host, void *ws,
+                      size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------- adjoint --- */
 
 /* Workspace bytes for ad_relax_backward. */

@@ -73,6 +73,12 @@ def _load_lib():
         "ad_sparsify_fit_both_workspace_size": (S, [G]),
         "ad_normalize_dist_workspace_size": (S, [G]),
         "ad_normalize_dist": (st, [G, ctypes.c_int, P, ctypes.c_int32, f64, P, P, S, P]),
+        "ad_subgraph_workspace_size": (S, [G]),
+        "ad_subgraph": (st, [G, P, P, P, P, P, P, ctypes.POINTER(i64), P, S, P]),
+        "ad_graph_properties_workspace_size": (S, [G]),
+        "ad_graph_properties": (st, [G, P, P, P, P, P, S, P]),
+        "ad_spearman_workspace_size": (S, [i64]),
+        "ad_spearman": (st, [i64, P, P, ctypes.POINTER(f64), P, S, P]),
         "ad_ingest_workspace_size": (S, [i64, i64]),
         "ad_ingest": (st, [i64, i64, P, P, P, P, i32, P, P, P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i32),
                            ctypes.POINTER(i64), P, S, P]),
@@ -571,3 +577,76 @@ def ingest(n: int, u: torch.Tensor, v: torch.Tensor, w: Optional[torch.Tensor] =
         gs = dg.abi()
         _check(lib.ad_graph_col_orig(ctypes.byref(gs), _ptr(dg.col_orig), _stream()))
     return dg
+
+
+# ------------------------------------------------------------ properties ---
+
+def subgraph(dg: DeviceGraph, keep: torch.Tensor, entry_ids: bool = True) -> DeviceGraph:
+    """The sparsified graph (V, {e : keep[e]}) as a ``DeviceGraph``
+    (``ad_subgraph``); ``orig_edge`` maps each entry to the original edge id.
+    Synchronises the current stream."""
+    dev = keep.device
+    g = dg.abi()
+    nnz = max(1, 2 * dg.m)
+    row_ptr = torch.empty(dg.n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(nnz, dtype=torch.int32, device=dev)
+    eid = torch.empty(nnz, dtype=torch.int32, device=dev)
+    oe = torch.empty(nnz, dtype=torch.int32, device=dev)
+    w = torch.empty(nnz, dtype=torch.float32, device=dev) if dg.w is not None else None
+    ws = _workspace(lib.ad_subgraph_workspace_size(ctypes.byref(g)), dev)
+    ms = ctypes.c_int64(0)
+    _check(lib.ad_subgraph(ctypes.byref(g), _ptr(keep.to(torch.uint8).contiguous()), _ptr(row_ptr), _ptr(col),
+                           _ptr(w), _ptr(eid), _ptr(oe), ctypes.byref(ms), _ptr(ws), ws.numel(), _stream()))
+    q = 2 * ms.value
+    deg_max = int((row_ptr[1:] - row_ptr[:-1]).max().item()) if dg.n > 0 else 0
+    sg = DeviceGraph(n=dg.n, m=ms.value, d_max=deg_max, row_ptr=row_ptr, col=col[:q],
+                     w=None if w is None else w[:q], eid=eid[:q], orig_id=dg.orig_id)
+    sg.orig_edge = oe[:q]      # type: ignore[attr-defined]
+    if entry_ids and sg.m > 0:
+        sg.col_orig = torch.empty(q, dtype=torch.int32, device=dev)
+        gs = sg.abi()
+        _check(lib.ad_graph_col_orig(ctypes.byref(gs), _ptr(sg.col_orig), _stream()))
+    return sg
+
+
+def graph_properties(dg: DeviceGraph) -> dict:
+    """Triangles, clustering (per vertex and C_G of Eq. cc) and components
+    (``ad_graph_properties``).  Synchronises the current stream."""
+    dev = dg.device
+    g = dg.abi()
+    n = max(1, dg.n)
+    lam = torch.empty(n, dtype=torch.int64, device=dev)
+    c = torch.empty(n, dtype=torch.float64, device=dev)
+    comp = torch.empty(n, dtype=torch.int32, device=dev)
+    summary = (ctypes.c_double * 2)()
+    ws = _workspace(lib.ad_graph_properties_workspace_size(ctypes.byref(g)), dev)
+    _check(lib.ad_graph_properties(ctypes.byref(g), _ptr(lam), _ptr(c), _ptr(comp), summary, _ptr(ws), ws.numel(),
+                                   _stream()))
+    return {"lambda": lam[:dg.n], "c": c[:dg.n], "comp": comp[:dg.n], "C_G": summary[0],
+            "n_components": int(summary[1])}
+
+
+def spearman(x: torch.Tensor, y: torch.Tensor) -> float:
+    """Spearman rank correlation by the Preliminaries' formula (``ad_spearman``)."""
+    x = x.to(torch.float64).contiguous()
+    y = y.to(torch.float64).contiguous()
+    n = x.numel()
+    ws = _workspace(lib.ad_spearman_workspace_size(n), x.device)
+    rho = ctypes.c_double(0.0)
+    _check(lib.ad_spearman(n, _ptr(x), _ptr(y), ctypes.byref(rho), _ptr(ws), ws.numel(), _stream()))
+    return rho.value
+
+
+def compare_properties(dg: DeviceGraph, keep: torch.Tensor) -> dict:
+    """The comparisons of Section 6 that need no external package: the
+    sparsified graph's C_G and component count against the original's
+    (as ratios), and Spearman correlations of the degree and clustering
+    distributions."""
+    sg = subgraph(dg, keep, entry_ids=False)
+    po, ps = graph_properties(dg), graph_properties(sg)
+    deg_o = (dg.row_ptr[1:] - dg.row_ptr[:-1]).to(torch.float64)
+    deg_s = (sg.row_ptr[1:] - sg.row_ptr[:-1]).to(torch.float64)
+    return {"m": dg.m, "m_kept": sg.m, "C_G": po["C_G"], "C_G_sparse": ps["C_G"],
+            "components": po["n_components"], "components_sparse": ps["n_components"],
+            "comp_ratio": ps["n_components"] / max(1, po["n_components"]),
+            "degree_spearman": spearman(deg_o, deg_s), "clustering_spearman": spearman(po["c"], ps["c"])}

@@ -1,0 +1,582 @@
+// Properties by which the paper compares a sparsified graph with the
+// original (Preliminaries): the sparsified subgraph itself, per-vertex
+// triangle counts lambda_i, clustering c_i = lambda_i / (d_i (d_i - 1) / 2),
+// C_G = the mean of c_i over d_i > 1 (Eq. cc), connected components, and the
+// Spearman rank correlation of two per-vertex scores by the stated formula
+// rho = 1 - 6 sum p_i^2 / (n (n^2 - 1)) (tied scores share the mean of
+// their ranks).
+#include "ad_internal.h"
+
+#include <cstring>    // before rocPRIM: its host code calls memset
+
+#include <rocprim/rocprim.hpp>
+
+#include <algorithm>
+#include <cstdint>
+
+namespace ad {
+
+constexpr int PBLOCK = 256;
+constexpr int PREDUCE_BLOCKS = 1024;     // fixed grid: reductions in a fixed order
+constexpr int64_t TRI_LANE = 64;         // pairs whose shorter row fits this are counted by one lane
+
+static unsigned pgrid(int64_t count) { return grid_for(std::max<int64_t>(1, count), PBLOCK); }
+
+// ------------------------------------------------------------- subgraph --
+
+__global__ void k_keep_u32(int64_t m, const uint8_t *__restrict__ keep, uint32_t *__restrict__ k32) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+        k32[e] = keep[e] ? 1u : 0u;
+}
+
+// Kept entries per row (one wave per row).
+__global__ void k_kept_per_row(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ eid,
+                               const uint8_t *__restrict__ keep, uint64_t *__restrict__ cnt) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        int64_t c = 0;
+        for (int64_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += WAVE) c += keep[eid[p]] ? 1 : 0;
+        for (int o = WAVE / 2; o >= 1; o >>= 1) c += __shfl_xor(c, o, WAVE);
+        if (lane == 0) cnt[i] = (uint64_t)c;
+    }
+}
+
+// The kept entries of every row, in order (ballot compaction per 64 entries).
+__global__ void k_compact_rows(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                               const float *__restrict__ w, const int32_t *__restrict__ eid,
+                               const uint8_t *__restrict__ keep, const uint32_t *__restrict__ new_id,
+                               const int64_t *__restrict__ sub_row_ptr, int32_t *__restrict__ sub_col,
+                               float *__restrict__ sub_w, int32_t *__restrict__ sub_eid,
+                               int32_t *__restrict__ orig_edge) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        int64_t out = sub_row_ptr[i];
+        for (int64_t base = row_ptr[i]; base < row_ptr[i + 1]; base += WAVE) {
+            const int64_t p = base + lane;
+            const bool on = p < row_ptr[i + 1];
+            const int32_t e = on ? eid[p] : 0;
+            const bool k = on && keep[e];
+            const unsigned long long mask = __ballot(k);
+            if (k) {
+                const int64_t q = out + __popcll(mask & ((1ull << lane) - 1ull));
+                sub_col[q] = col[p];
+                if (sub_w) sub_w[q] = w[p];
+                sub_eid[q] = (int32_t)new_id[e];
+                if (orig_edge) orig_edge[q] = e;
+            }
+            out += __popcll(mask);
+        }
+    }
+}
+
+// ------------------------------------------------------------ triangles --
+
+// |N_a ∩ N_b| for sorted rows, by binary searches of the shorter row's
+// entries [s0 + first, s1) (stepping by `step`) in the longer one.
+__device__ __forceinline__ int64_t common_count(const int32_t *__restrict__ col, int64_t s0, int64_t s1,
+                                                int64_t l0, int64_t l1, int64_t first, int64_t step) {
+    int64_t t = 0;
+    for (int64_t q = s0 + first; q < s1; q += step) {
+        const int32_t x = col[q];
+        int64_t lo = l0, hi = l1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (col[mid] < x) lo = mid + 1;
+            else hi = mid;
+        }
+        t += (lo < l1 && col[lo] == x) ? 1 : 0;
+    }
+    return t;
+}
+
+// Every edge (i, j), i < j, adds |N_i ∩ N_j| to both ends (each triangle at i
+// is then counted once through each of its two edges at i).  Pairs whose
+// shorter row exceeds TRI_LANE are listed for the wave kernel.
+__global__ void k_triangles_lane(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                 unsigned long long *__restrict__ lam2, int2 *__restrict__ big,
+                                 unsigned int *__restrict__ nbig) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        const int64_t b0 = row_ptr[i], b1 = row_ptr[i + 1];
+        unsigned long long own = 0;
+        for (int64_t base = b0; base < b1; base += WAVE) {
+            const int64_t p = base + lane;
+            const int32_t j = p < b1 ? col[p] : -1;
+            const bool up = j > i;
+            int64_t c0 = 0, c1 = 0;
+            if (up) {
+                c0 = row_ptr[j];
+                c1 = row_ptr[j + 1];
+            }
+            const bool i_short = (b1 - b0) <= (c1 - c0);
+            const int64_t shorter = i_short ? b1 - b0 : c1 - c0;
+            const bool is_big = up && shorter > TRI_LANE;
+            // long pairs go to the list, one counter update per wave
+            const unsigned long long mask = __ballot(is_big);
+            unsigned int first = 0;
+            if (mask != 0ull && lane == 0) first = atomicAdd(nbig, (unsigned int)__popcll(mask));
+            first = (unsigned int)__shfl((int)first, 0, WAVE);
+            if (is_big) big[first + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2((int32_t)i, j);
+            if (up && !is_big) {
+                const int64_t t =
+                    i_short ? common_count(col, b0, b1, c0, c1, 0, 1) : common_count(col, c0, c1, b0, b1, 0, 1);
+                own += (unsigned long long)t;
+                if (t) atomicAdd(&lam2[j], (unsigned long long)t);
+            }
+        }
+        for (int o = WAVE / 2; o >= 1; o >>= 1) own += __shfl_xor(own, o, WAVE);
+        if (lane == 0 && own) atomicAdd(&lam2[i], own);
+    }
+}
+
+// Listed pairs: one wave each, lanes striding over the shorter row.
+__global__ void k_triangles_wave(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                 const int2 *__restrict__ big, const unsigned int *__restrict__ nbig,
+                                 unsigned long long *__restrict__ lam2) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned int nb = *nbig;
+    const unsigned int nw = gridDim.x * (PBLOCK / WAVE);
+    for (unsigned int k = blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); k < nb; k += nw) {
+        const int2 pr = big[k];
+        const int64_t b0 = row_ptr[pr.x], b1 = row_ptr[pr.x + 1], c0 = row_ptr[pr.y], c1 = row_ptr[pr.y + 1];
+        int64_t t = (b1 - b0) <= (c1 - c0) ? common_count(col, b0, b1, c0, c1, lane, WAVE)
+                                           : common_count(col, c0, c1, b0, b1, lane, WAVE);
+        for (int o = WAVE / 2; o >= 1; o >>= 1) t += __shfl_xor(t, o, WAVE);
+        if (lane == 0 && t) {
+            atomicAdd(&lam2[pr.x], (unsigned long long)t);
+            atomicAdd(&lam2[pr.y], (unsigned long long)t);
+        }
+    }
+}
+
+// lambda_i and c_i; per-block partial sums of c_i over d_i > 1 (and their
+// count), in a fixed order for the host to finish.
+__global__ void k_clustering(int64_t n, const int64_t *__restrict__ row_ptr, const unsigned long long *__restrict__ lam2,
+                             int64_t *__restrict__ lambda, double *__restrict__ c, double *__restrict__ part_sum,
+                             unsigned long long *__restrict__ part_cnt) {
+    __shared__ double ssum[PBLOCK];
+    __shared__ unsigned long long scnt[PBLOCK];
+    double s = 0.0;
+    unsigned long long k = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t l = (int64_t)(lam2[i] / 2);
+        const int64_t d = row_ptr[i + 1] - row_ptr[i];
+        double ci = 0.0;
+        if (d > 1) {
+            ci = (double)l / ((double)d * (double)(d - 1) / 2.0);
+            s += ci;
+            ++k;
+        }
+        if (lambda) lambda[i] = l;
+        if (c) c[i] = ci;
+    }
+    ssum[threadIdx.x] = s;
+    scnt[threadIdx.x] = k;
+    __syncthreads();
+    for (int o = PBLOCK / 2; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            ssum[threadIdx.x] += ssum[threadIdx.x + o];
+            scnt[threadIdx.x] += scnt[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part_sum[blockIdx.x] = ssum[0];
+        part_cnt[blockIdx.x] = scnt[0];
+    }
+}
+
+// ----------------------------------------------------------- components --
+
+__global__ void k_parent_init(int64_t n, int32_t *__restrict__ parent) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        parent[i] = (int32_t)i;
+}
+
+// For every edge whose ends have different parents (roots, after the last
+// jump): hook the larger parent under the smaller (atomicMin).  Parents only
+// decrease and hooks only join trees of one component, so each component
+// ends rooted at its smallest vertex.  `changed` is raised while any edge
+// still joins two trees (a hook can lose a race and leave its trees apart
+// for the next round), once per wave.
+__global__ void k_hook(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                       int32_t *__restrict__ parent, unsigned int *__restrict__ changed) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
+    bool any = false;
+    for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        for (int64_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += WAVE) {
+            const int32_t j = col[p];
+            if (j <= i) continue;
+            const int32_t pi = __hip_atomic_load(&parent[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int32_t pj = __hip_atomic_load(&parent[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (pi == pj) continue;
+            any = true;
+            const int32_t lo = pi < pj ? pi : pj, hi = pi < pj ? pj : pi;
+            atomicMin(&parent[hi], lo);
+        }
+    }
+    if (__ballot(any) != 0ull && lane == 0) atomicOr(changed, 1u);
+}
+
+// One pointer-jumping step, parent[i] <- parent[parent[i]]; `changed` is
+// raised (once per wave) while any parent moved.  Repeated, every vertex
+// points at its tree's root after log2 of the longest chain steps.
+__global__ void k_jump(int64_t n, int32_t *__restrict__ parent, unsigned int *__restrict__ changed) {
+    bool moved = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = parent[i];
+        const int32_t pp = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (pp != p) {
+            parent[i] = pp;
+            moved = true;
+        }
+    }
+    if (__ballot(moved) != 0ull && (threadIdx.x & (WAVE - 1)) == 0) atomicOr(changed, 1u);
+}
+
+__global__ void k_count_roots(int64_t n, const int32_t *__restrict__ parent, unsigned long long *__restrict__ cnt) {
+    unsigned long long k = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        k += parent[i] == (int32_t)i ? 1 : 0;
+    for (int o = WAVE / 2; o >= 1; o >>= 1) k += __shfl_xor(k, o, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && k) atomicAdd(cnt, k);
+}
+
+// ------------------------------------------------------------- spearman --
+
+__global__ void k_iota(int64_t n, uint32_t *__restrict__ idx) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        idx[i] = (uint32_t)i;
+}
+
+// Twice the mean rank of every score, from the sorted scores: a run of equal
+// scores at sorted positions [a, b) holds ranks a+1 .. b, mean (a + 1 + b) / 2.
+__global__ void k_mean_ranks(int64_t n, const double *__restrict__ sorted, const uint32_t *__restrict__ idx,
+                             int64_t *__restrict__ rank2) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const double v = sorted[t];
+        int64_t a = t, b = t + 1;
+        // run bounds by binary search over the sorted scores
+        int64_t lo = 0, hi = t;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (sorted[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        a = lo;
+        lo = t + 1;
+        hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (sorted[mid] <= v) lo = mid + 1;
+            else hi = mid;
+        }
+        b = lo;
+        rank2[idx[t]] = a + 1 + b;
+    }
+}
+
+// Per-block sums of (2 p_i)^2 in a fixed order (exact while below 2^53 per term).
+__global__ void k_rank_diff2(int64_t n, const int64_t *__restrict__ rx2, const int64_t *__restrict__ ry2,
+                             double *__restrict__ part) {
+    __shared__ double s[PBLOCK];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double d = (double)(rx2[i] - ry2[i]);
+        acc += d * d;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = PBLOCK / 2; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// ------------------------------------------------------------- layouts --
+
+struct SubLayout {
+    uint32_t *k32, *new_id;   // [m]
+    uint64_t *cnt;            // [n + 1]
+    void *temp;
+    size_t temp_bytes;
+};
+
+static size_t sub_layout(const ad_graph *g, void *ws, size_t ws_bytes, SubLayout *L) {
+    Carver c(ws, ws_bytes);
+    const size_t m = (size_t)std::max<int64_t>(1, g->m), n1 = (size_t)std::max<int64_t>(1, g->n) + 1;
+    SubLayout l;
+    l.k32 = c.take<uint32_t>(m);
+    l.new_id = c.take<uint32_t>(m);
+    l.cnt = c.take<uint64_t>(n1);
+    size_t t1 = 0, t2 = 0;
+    if (rocprim::exclusive_scan(nullptr, t1, (uint32_t *)nullptr, (uint32_t *)nullptr, 0u, m,
+                                rocprim::plus<uint32_t>()) != hipSuccess)
+        t1 = 0;
+    if (rocprim::exclusive_scan(nullptr, t2, (uint64_t *)nullptr, (uint64_t *)nullptr, (uint64_t)0, n1,
+                                rocprim::plus<uint64_t>()) != hipSuccess)
+        t2 = 0;
+    l.temp_bytes = std::max(t1, t2);
+    l.temp = c.take<char>(l.temp_bytes);
+    if (L) *L = l;
+    return c.ok() ? c.used : 0;
+}
+
+struct PropLayout {
+    unsigned long long *lam2;     // [n]
+    int2 *big;                    // [m] listed long pairs
+    unsigned int *flags;          // [4]: listed pairs, changed
+    unsigned long long *roots;    // [1]
+    double *part_sum;             // [PREDUCE_BLOCKS]
+    unsigned long long *part_cnt; // [PREDUCE_BLOCKS]
+    int32_t *parent;              // [n] when the caller passes no comp array
+};
+
+static size_t prop_layout(const ad_graph *g, void *ws, size_t ws_bytes, PropLayout *L) {
+    Carver c(ws, ws_bytes);
+    const size_t m = (size_t)std::max<int64_t>(1, g->m), n = (size_t)std::max<int64_t>(1, g->n);
+    PropLayout l;
+    l.lam2 = c.take<unsigned long long>(n);
+    l.big = c.take<int2>(m);
+    l.flags = c.take<unsigned int>(4);
+    l.roots = c.take<unsigned long long>(1);
+    l.part_sum = c.take<double>(PREDUCE_BLOCKS);
+    l.part_cnt = c.take<unsigned long long>(PREDUCE_BLOCKS);
+    l.parent = c.take<int32_t>(n);
+    if (L) *L = l;
+    return c.ok() ? c.used : 0;
+}
+
+struct RankLayout {
+    double *keys0, *keys1;        // [n]
+    uint32_t *idx0, *idx1;        // [n]
+    int64_t *rx2, *ry2;           // [n]
+    double *part;                 // [PREDUCE_BLOCKS]
+    void *temp;
+    size_t temp_bytes;
+};
+
+static size_t rank_layout(int64_t n, void *ws, size_t ws_bytes, RankLayout *L) {
+    Carver c(ws, ws_bytes);
+    const size_t nn = (size_t)std::max<int64_t>(1, n);
+    RankLayout l;
+    l.keys0 = c.take<double>(nn);
+    l.keys1 = c.take<double>(nn);
+    l.idx0 = c.take<uint32_t>(nn);
+    l.idx1 = c.take<uint32_t>(nn);
+    l.rx2 = c.take<int64_t>(nn);
+    l.ry2 = c.take<int64_t>(nn);
+    l.part = c.take<double>(PREDUCE_BLOCKS);
+    size_t t = 0;
+    if (rocprim::radix_sort_pairs(nullptr, t, (double *)nullptr, (double *)nullptr, (uint32_t *)nullptr,
+                                  (uint32_t *)nullptr, nn) != hipSuccess)
+        t = 0;
+    l.temp_bytes = t;
+    l.temp = c.take<char>(t);
+    if (L) *L = l;
+    return c.ok() ? c.used : 0;
+}
+
+#define AD_RP(call)                                                         \
+    do {                                                                    \
+        hipError_t e_ = (call);                                             \
+        if (e_ != hipSuccess) return fail(AD_ERR_HIP, std::string("rocPRIM: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static ad_status check_ws(void *ws, size_t need, size_t ws_bytes) {
+    if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    if (need == 0 || ws_bytes < need) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    return AD_OK;
+}
+
+}  // namespace ad
+
+using namespace ad;
+
+extern "C" size_t ad_subgraph_workspace_size(const ad_graph *g) {
+    if (check_graph_args(g) != AD_OK) return 0;
+    return sub_layout(g, nullptr, 0, nullptr);
+}
+
+extern "C" ad_status ad_subgraph(const ad_graph *g, const uint8_t *keep, int64_t *sub_row_ptr, int32_t *sub_col,
+                                 float *sub_w, int32_t *sub_eid, int32_t *orig_edge, int64_t *m_sub_host, void *ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+    ad_status s = check_graph_args(g);
+    if (s != AD_OK) return s;
+    if (g->m > 0 && !keep) return fail(AD_ERR_INVALID_ARG, "keep is NULL");
+    if (!sub_row_ptr || !m_sub_host) return fail(AD_ERR_INVALID_ARG, "sub_row_ptr or m_sub_host is NULL");
+    if (g->m > 0 && (!sub_col || !sub_eid)) return fail(AD_ERR_INVALID_ARG, "sub_col or sub_eid is NULL");
+    if (g->m >= ((int64_t)1 << 31)) return fail(AD_ERR_UNSUPPORTED, "more than 2^31 - 1 edges");
+    s = check_ws(ws, sub_layout(g, nullptr, 0, nullptr), ws_bytes);
+    if (s != AD_OK) return s;
+    SubLayout L;
+    if (sub_layout(g, ws, ws_bytes, &L) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    TraceScope trace("k_subgraph", stream);
+    const int64_t n = g->n, m = g->m;
+    uint32_t last[2] = {0, 0};
+    if (m > 0) {
+        hipLaunchKernelGGL(k_keep_u32, dim3(pgrid(m)), dim3(PBLOCK), 0, stream, m, keep, L.k32);
+        AD_LAUNCH_CHECK("k_keep_u32");
+        size_t tb = L.temp_bytes;
+        AD_RP(rocprim::exclusive_scan(L.temp, tb, L.k32, L.new_id, 0u, (size_t)m, rocprim::plus<uint32_t>(), stream));
+        AD_HIP(hipMemcpyAsync(&last[0], L.new_id + (m - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+        AD_HIP(hipMemcpyAsync(&last[1], L.k32 + (m - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    }
+    s = fill_i32((int32_t *)(L.cnt + n), 0, 2, stream);
+    if (s != AD_OK) return s;
+    const unsigned wgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, PBLOCK / WAVE)));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_kept_per_row, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->eid, keep, L.cnt);
+        AD_LAUNCH_CHECK("k_kept_per_row");
+    }
+    size_t tb = L.temp_bytes;
+    AD_RP(rocprim::exclusive_scan(L.temp, tb, L.cnt, (uint64_t *)sub_row_ptr, (uint64_t)0, (size_t)n + 1,
+                                  rocprim::plus<uint64_t>(), stream));
+    if (n > 0 && m > 0) {
+        hipLaunchKernelGGL(k_compact_rows, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, g->w,
+                           g->eid, keep, L.new_id, (const int64_t *)sub_row_ptr, sub_col, g->w ? sub_w : nullptr,
+                           sub_eid, orig_edge);
+        AD_LAUNCH_CHECK("k_compact_rows");
+    }
+    AD_HIP(hipStreamSynchronize(stream));
+    *m_sub_host = (int64_t)last[0] + (int64_t)last[1];
+    return AD_OK;
+}
+
+extern "C" size_t ad_graph_properties_workspace_size(const ad_graph *g) {
+    if (check_graph_args(g) != AD_OK) return 0;
+    return prop_layout(g, nullptr, 0, nullptr);
+}
+
+extern "C" ad_status ad_graph_properties(const ad_graph *g, int64_t *lambda, double *c, int32_t *comp,
+                                         double *summary_host, void *ws, size_t ws_bytes, hipStream_t stream) {
+    ad_status s = check_graph_args(g);
+    if (s != AD_OK) return s;
+    if (!summary_host) return fail(AD_ERR_INVALID_ARG, "summary_host is NULL");
+    if (g->m >= ((int64_t)1 << 31)) return fail(AD_ERR_UNSUPPORTED, "more than 2^31 - 1 edges");
+    s = check_ws(ws, prop_layout(g, nullptr, 0, nullptr), ws_bytes);
+    if (s != AD_OK) return s;
+    PropLayout L;
+    if (prop_layout(g, ws, ws_bytes, &L) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    TraceScope trace("k_properties", stream);
+    const int64_t n = g->n;
+    summary_host[0] = 0.0;
+    summary_host[1] = 0.0;
+    if (n == 0) return AD_OK;
+    const unsigned wgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, PBLOCK / WAVE)));
+    // triangles and clustering
+    s = fill_u64(L.lam2, 0, n, stream);
+    if (s != AD_OK) return s;
+    s = fill_i32((int32_t *)L.flags, 0, 4, stream);
+    if (s != AD_OK) return s;
+    if (g->m > 0) {
+        hipLaunchKernelGGL(k_triangles_lane, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, L.lam2, L.big,
+                           L.flags);
+        AD_LAUNCH_CHECK("k_triangles_lane");
+        hipLaunchKernelGGL(k_triangles_wave, dim3(4096), dim3(PBLOCK), 0, stream, g->row_ptr, g->col, L.big, L.flags,
+                           L.lam2);
+        AD_LAUNCH_CHECK("k_triangles_wave");
+    }
+    hipLaunchKernelGGL(k_clustering, dim3(PREDUCE_BLOCKS), dim3(PBLOCK), 0, stream, n, g->row_ptr, L.lam2, lambda, c,
+                       L.part_sum, L.part_cnt);
+    AD_LAUNCH_CHECK("k_clustering");
+    // components: hook and jump until no hook changes a parent
+    int32_t *parent = comp ? comp : L.parent;
+    hipLaunchKernelGGL(k_parent_init, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent);
+    AD_LAUNCH_CHECK("k_parent_init");
+    // every round joins, for each edge between two trees, its two trees; the
+    // bound only guards against a defect, it is far above the rounds needed
+    for (int round = 0;; ++round) {
+        if (round > 4096) return fail(AD_ERR_INTERNAL, "components did not settle");
+        s = fill_i32((int32_t *)L.flags + 1, 0, 1, stream);
+        if (s != AD_OK) return s;
+        if (g->m > 0) {
+            hipLaunchKernelGGL(k_hook, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, parent, L.flags + 1);
+            AD_LAUNCH_CHECK("k_hook");
+        }
+        // jump until every vertex points at a root
+        for (int step = 0;; ++step) {
+            if (step > 64) return fail(AD_ERR_INTERNAL, "pointer jumping did not settle");
+            s = fill_i32((int32_t *)L.flags + 2, 0, 1, stream);
+            if (s != AD_OK) return s;
+            hipLaunchKernelGGL(k_jump, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent, L.flags + 2);
+            AD_LAUNCH_CHECK("k_jump");
+            unsigned int moved = 0;
+            AD_HIP(hipMemcpyAsync(&moved, L.flags + 2, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
+            AD_HIP(hipStreamSynchronize(stream));
+            if (!moved) break;
+        }
+        unsigned int changed = 0;
+        AD_HIP(hipMemcpyAsync(&changed, L.flags + 1, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
+        AD_HIP(hipStreamSynchronize(stream));
+        if (!changed) break;
+    }
+    s = fill_u64(L.roots, 0, 1, stream);
+    if (s != AD_OK) return s;
+    hipLaunchKernelGGL(k_count_roots, dim3(std::min<unsigned>(1024, pgrid(n))), dim3(PBLOCK), 0, stream, n, parent,
+                       L.roots);
+    AD_LAUNCH_CHECK("k_count_roots");
+    double psum[PREDUCE_BLOCKS];
+    unsigned long long pcnt[PREDUCE_BLOCKS], roots = 0;
+    AD_HIP(hipMemcpyAsync(psum, L.part_sum, sizeof(psum), hipMemcpyDeviceToHost, stream));
+    AD_HIP(hipMemcpyAsync(pcnt, L.part_cnt, sizeof(pcnt), hipMemcpyDeviceToHost, stream));
+    AD_HIP(hipMemcpyAsync(&roots, L.roots, sizeof(roots), hipMemcpyDeviceToHost, stream));
+    AD_HIP(hipStreamSynchronize(stream));
+    double sum = 0.0;
+    unsigned long long cnt = 0;
+    for (int b = 0; b < PREDUCE_BLOCKS; ++b) {
+        sum += psum[b];
+        cnt += pcnt[b];
+    }
+    summary_host[0] = cnt ? sum / (double)cnt : 0.0;
+    summary_host[1] = (double)roots;
+    return AD_OK;
+}
+
+extern "C" size_t ad_spearman_workspace_size(int64_t n) {
+    if (n < 0 || n >= ((int64_t)1 << 31)) return 0;
+    return rank_layout(n, nullptr, 0, nullptr);
+}
+
+extern "C" ad_status ad_spearman(int64_t n, const double *x, const double *y, double *rho_host, void *ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+    if (n < 0) return fail(AD_ERR_INVALID_ARG, "negative n");
+    if (n >= ((int64_t)1 << 31)) return fail(AD_ERR_UNSUPPORTED, "n must be below 2^31");
+    if (n > 0 && (!x || !y)) return fail(AD_ERR_INVALID_ARG, "x or y is NULL");
+    if (!rho_host) return fail(AD_ERR_INVALID_ARG, "rho_host is NULL");
+    ad_status s = check_ws(ws, rank_layout(n, nullptr, 0, nullptr), ws_bytes);
+    if (s != AD_OK) return s;
+    RankLayout L;
+    if (rank_layout(n, ws, ws_bytes, &L) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    *rho_host = 0.0;
+    if (n < 2) return AD_OK;
+    TraceScope trace("k_spearman", stream);
+    const double *src[2] = {x, y};
+    int64_t *dst[2] = {L.rx2, L.ry2};
+    for (int v = 0; v < 2; ++v) {
+        AD_HIP(hipMemcpyAsync(L.keys0, src[v], (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        hipLaunchKernelGGL(k_iota, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, L.idx0);
+        AD_LAUNCH_CHECK("k_iota");
+        size_t tb = L.temp_bytes;
+        AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.keys0, L.keys1, L.idx0, L.idx1, (size_t)n, 0,
+                                        8 * (unsigned)sizeof(double), stream));
+        hipLaunchKernelGGL(k_mean_ranks, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, L.keys1, L.idx1, dst[v]);
+        AD_LAUNCH_CHECK("k_mean_ranks");
+    }
+    hipLaunchKernelGGL(k_rank_diff2, dim3(PREDUCE_BLOCKS), dim3(PBLOCK), 0, stream, n, L.rx2, L.ry2, L.part);
+    AD_LAUNCH_CHECK("k_rank_diff2");
+    double part[PREDUCE_BLOCKS];
+    AD_HIP(hipMemcpyAsync(part, L.part, sizeof(part), hipMemcpyDeviceToHost, stream));
+    AD_HIP(hipStreamSynchronize(stream));
+    double sum4 = 0.0;    // sum of (2 p_i)^2
+    for (int b = 0; b < PREDUCE_BLOCKS; ++b) sum4 += part[b];
+    const double dn = (double)n;
+    *rho_host = 1.0 - 6.0 * (sum4 / 4.0) / (dn * (dn * dn - 1.0));
+    return AD_OK;
+}

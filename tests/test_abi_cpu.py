@@ -214,3 +214,30 @@ def test_ingest_rejects_bad_arguments():
     assert L.ad_ingest_workspace_size(10, 1 << 31) == 0
     # the workspace grows with the list and the vertex count
     assert L.ad_ingest_workspace_size(1000, 100_000) > L.ad_ingest_workspace_size(1000, 1000)
+
+
+def test_property_calls_reject_bad_arguments():
+    from paper_1601_05527_amd import api
+    L = api.lib
+    g = _graph_struct(api)
+    p = ctypes.c_void_p(0x40000)
+    ws = ctypes.c_void_p(0x10000)
+    ms = ctypes.c_int64()
+    assert L.ad_subgraph(ctypes.byref(g), None, p, p, None, p, None, ctypes.byref(ms), ws, 1 << 30, None) == 1
+    assert L.ad_subgraph(ctypes.byref(g), p, None, p, None, p, None, ctypes.byref(ms), ws, 1 << 30, None) == 1
+    assert L.ad_subgraph(ctypes.byref(g), p, p, None, None, p, None, ctypes.byref(ms), ws, 1 << 30, None) == 1
+    need = L.ad_subgraph_workspace_size(ctypes.byref(g))
+    assert need > 0
+    assert L.ad_subgraph(ctypes.byref(g), p, p, p, None, p, None, ctypes.byref(ms), ws, need - 256, None) == 3
+    summ = (ctypes.c_double * 2)()
+    assert L.ad_graph_properties(ctypes.byref(g), None, None, None, None, ws, 1 << 30, None) == 1
+    needp = L.ad_graph_properties_workspace_size(ctypes.byref(g))
+    assert L.ad_graph_properties(ctypes.byref(g), None, None, None, summ, ws, needp - 256, None) == 3
+    assert L.ad_graph_properties(ctypes.byref(g), None, None, None, summ, ctypes.c_void_p(0x10010), needp,
+                                 None) == 3
+    rho = ctypes.c_double()
+    assert L.ad_spearman(-1, p, p, ctypes.byref(rho), ws, 1 << 30, None) == 1
+    assert L.ad_spearman(10, None, p, ctypes.byref(rho), ws, 1 << 30, None) == 1
+    assert L.ad_spearman(10, p, p, None, ws, 1 << 30, None) == 1
+    assert L.ad_spearman(1 << 31, p, p, ctypes.byref(rho), ws, 1 << 30, None) == 2
+    assert L.ad_spearman_workspace_size(-3) == 0

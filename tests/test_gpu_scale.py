@@ -7,7 +7,10 @@ paper_1601_05527_amd.workloads).
       that is larger, gpu_helpers.fp32_tolerance); the fit on the oracle's distances equal to the oracle's
       bisection bit for bit; the end-to-end kept set near-cut equal; the
       selection with binning (fixed e and fitted) equal to the oracle's; the
-      graph as drawn ingested on the device equal to the oracle's ingest.
+      graph as drawn ingested on the device equal to the oracle's ingest;
+      the sparsified subgraph and both graphs' component labels equal the
+      oracle's (triangle counts are checked at 30,000 vertices: the
+      oracle's pairwise count is quadratic in the hub degrees).
   Batch of 512 Chung-Lu graphs, FP32: every graph's kept set equal to the
       oracle's selection on the batch's distances, every graph's outputs
       equal to a standalone run bit for bit, distances of sampled graphs
@@ -108,6 +111,28 @@ def test_full_chung_lu_ingest(api):
     assert dg.m == m and dropped == 0 and dg.n_dropped == 0
     for got, want in ((dg.row_ptr, row_ptr), (dg.col, col), (dg.w, we), (dg.eid, eid), (dg.orig_id, orig)):
         assert np.array_equal(_np(got), want)
+
+
+@pytest.mark.timeout(900)
+def test_full_chung_lu_subgraph_and_components(api):
+    """The sparsified subgraph of a LOCAL selection on the benchmark graph,
+    and the component labels of both graphs, equal the oracle's."""
+    announce("full size Chung-Lu subgraph and components")
+    _, g = W.chung_lu_graph("degree")
+    keep = (np.random.default_rng(21).random(g.m) < 0.3).astype(np.uint8)
+    dg = api.DeviceGraph.from_host(g, "cuda", keep_host=False)
+    sg = api.subgraph(dg, torch.from_numpy(keep).cuda(), entry_ids=False)
+    rp, col, w, eid, oe, ms = oracle.subgraph(g, keep)
+    assert sg.m == ms
+    for got, want in ((sg.row_ptr, rp), (sg.col, col), (sg.w, w), (sg.eid, eid), (sg.orig_edge, oe)):
+        assert np.array_equal(_np(got), want)
+    for d, (rpp, cl) in ((dg, (g.row_ptr, g.col)), (sg, (rp, col))):
+        pr = api.graph_properties(d)
+        comp = np.zeros(d.n, dtype=np.int32)
+        nc = oracle._load().orc_components(d.n, oracle._p(np.ascontiguousarray(rpp)),
+                                           oracle._p(np.ascontiguousarray(cl)), oracle._p(comp))
+        _log(f"components {pr['n_components']} oracle {nc}, C_G {pr['C_G']:.6f}")
+        assert pr["n_components"] == nc and np.array_equal(_np(pr["comp"]), comp)
 
 
 @pytest.mark.timeout(900)
