@@ -87,6 +87,12 @@ def _load():
     lib.orc_binned_choices.argtypes = [i64, P, P, P, P, P, u64, u64, f64, P]
     lib.orc_ingest.argtypes = [i64, i64, P, P, P, P, i32, P, P, P, P, P, P]
     lib.orc_subgraph.argtypes = [i64, P, P, P, P, i64, P, P, P, P, P, P]
+    lib.orc_ml_seeds.argtypes = [i64, P, P, P, P, P, f64, f64, P]
+    lib.orc_ml_aggregates.argtypes = [i64, P, P, P, P, P, f64, P, P]
+    lib.orc_ml_aggregates.restype = i64
+    lib.orc_ml_sparsify.argtypes = [i64, P, P, P, P, P, i64, i32, i32, f64, u64, u64, i32, i64, P, f64, f64, u64,
+                                    P, P]
+    lib.orc_ml_sparsify.restype = i64
     lib.orc_subgraph.restype = i64
     lib.orc_triangles.argtypes = [i64, P, P, P]
     lib.orc_clustering.argtypes = [i64, P, P, P]
@@ -346,3 +352,37 @@ def spearman(x, y) -> float:
     xx = np.ascontiguousarray(x, dtype=np.float64)
     yy = np.ascontiguousarray(y, dtype=np.float64)
     return float(lib.orc_spearman(xx.size, _p(xx), _p(yy)))
+
+
+def ml_seeds(g, rho, eps: float = 1e-12, theta: float = 0.5) -> np.ndarray:
+    """Coarsening seeds of Algorithm 6 (uint8 [n])."""
+    lib = _load()
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    out = np.zeros(max(1, g.n), dtype=np.uint8)
+    lib.orc_ml_seeds(g.n, _p(g.row_ptr), _p(g.col), _p(g.eid), _p(g.orig_id), _p(r), eps, theta, _p(out))
+    return out[:g.n]
+
+
+def ml_aggregates(g, rho, is_seed, eps: float = 1e-12):
+    """Aggregate of every vertex under the restriction P (Eq. P), and their number."""
+    lib = _load()
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    s = np.ascontiguousarray(is_seed, dtype=np.uint8)
+    agg = np.zeros(max(1, g.n), dtype=np.int32)
+    nc = lib.orc_ml_aggregates(g.n, _p(g.row_ptr), _p(g.col), _p(g.eid), _p(g.orig_id), _p(r), eps, _p(s), _p(agg))
+    return agg[:g.n], int(nc)
+
+
+def ml_sparsify(g, R: int, k: int, e_levels, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
+                levels: int = 8, n_min: int = 1000, eps: float = 1e-12, theta: float = 0.5, bin_seed: int = 0):
+    """Algorithm 6 (MLSparsify).  Returns (keep[m], n_kept, depth)."""
+    lib = _load()
+    ev = np.ascontiguousarray(e_levels, dtype=np.float64)
+    if ev.size < levels:
+        ev = np.concatenate([ev, np.full(levels - ev.size, ev[-1])])
+    keep = np.zeros(max(1, g.m), dtype=np.uint8)
+    depth = ctypes.c_int32(0)
+    kept = lib.orc_ml_sparsify(g.n, _p(g.row_ptr), _p(g.col), _p(_c(g.w, np.float32)), _p(g.eid), _p(g.orig_id),
+                               g.m, R, k, omega, seed, graph_id, levels, n_min, _p(ev), eps, theta, bin_seed,
+                               _p(keep), ctypes.byref(depth))
+    return keep[:g.m], int(kept), int(depth.value)

@@ -810,6 +810,218 @@ double orc_spearman(int64_t n, const double *x, const double *y)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Multilevel sparsification (Algorithm 6, MLSparsify; coarsening of
+ * Section 5).  Readings:
+ *   - strength of connection delta_ij = 1 / sqrt(rho_ij^2 + eps) (Algorithm
+ *     1's return value), from the distances computed at that level;
+ *   - i and j are strongly coupled when delta_ij >= theta * smax_i or
+ *     delta_ij >= theta * smax_j, smax_i the largest strength at i;
+ *   - seeds ("traversal of F, moving to C the nodes not strongly coupled to
+ *     those already in C"): vertices in decreasing degree, ties by smaller
+ *     orig_id; a vertex becomes a seed when none of its strong neighbours is
+ *     a seed yet;
+ *   - restriction P (Eq. P): a seed is its own aggregate; any other vertex
+ *     joins the seed neighbour of largest delta_ij (the normalising sum is
+ *     the same for every j), ties by smaller orig_id; aggregates are
+ *     numbered by their seeds' ids;
+ *   - Galerkin coarse graph P^T L P: one coarse edge per pair of aggregates
+ *     joined by fine edges, weight the sum of theirs (unit weights count
+ *     edges); coarse vertices are named by their seeds' orig_id;
+ *   - coarsening stops at n <= n_min, at level levels - 1, or when it would
+ *     keep more than 90% of the vertices; that level is the coarsest;
+ *   - level l uses graph id graph_id + l for its test vectors and its bin
+ *     order, and exponent e[l] for SparsifyB;
+ *   - uncoarsening: a fine edge between two aggregates keeps the state of
+ *     their coarse edge, an edge inside an aggregate is kept; distances are
+ *     recomputed on the fine graph less the dropped edges and SparsifyB
+ *     chooses among its edges.                                               */
+
+static double orc_strength_of(double rho, double eps)
+{
+    double t = rho * rho;
+    t = t + eps;
+    return 1.0 / sqrt(t);
+}
+
+typedef struct { int64_t deg; int32_t key; int64_t i; } orc_vprio;
+
+static int orc_cmp_vprio(const void *a, const void *b)
+{
+    const orc_vprio *x = (const orc_vprio *)a, *y = (const orc_vprio *)b;
+    if (x->deg != y->deg) return x->deg > y->deg ? -1 : 1;     /* larger degree first */
+    return (x->key > y->key) - (x->key < y->key);              /* then smaller orig_id */
+}
+
+void orc_ml_seeds(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *eid,
+                  const int32_t *orig_id, const double *rho, double eps, double theta, uint8_t *is_seed)
+{
+    double *smax = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        double mx = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            double d = orc_strength_of(rho[eid[p]], eps);
+            if (d > mx) mx = d;
+        }
+        smax[i] = mx;
+        is_seed[i] = 0;
+    }
+    orc_vprio *order = (orc_vprio *)malloc(sizeof(orc_vprio) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        order[i].deg = row_ptr[i + 1] - row_ptr[i];
+        order[i].key = orig_id ? orig_id[i] : (int32_t)i;
+        order[i].i = i;
+    }
+    qsort(order, (size_t)n, sizeof(orc_vprio), orc_cmp_vprio);
+    for (int64_t r = 0; r < n; ++r) {
+        int64_t i = order[r].i;
+        int coupled = 0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1] && !coupled; ++p) {
+            int32_t j = col[p];
+            if (!is_seed[j]) continue;
+            double d = orc_strength_of(rho[eid[p]], eps);
+            if (d >= theta * smax[i] || d >= theta * smax[j]) coupled = 1;
+        }
+        if (!coupled) is_seed[i] = 1;
+    }
+    free(order);
+    free(smax);
+}
+
+/* Aggregate of every vertex under P; returns the number of aggregates. */
+int64_t orc_ml_aggregates(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *eid,
+                          const int32_t *orig_id, const double *rho, double eps, const uint8_t *is_seed,
+                          int32_t *agg)
+{
+    int64_t *rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; ++i) rank[i] = is_seed[i] ? nc++ : -1;
+    for (int64_t i = 0; i < n; ++i) {
+        if (is_seed[i]) { agg[i] = (int32_t)rank[i]; continue; }
+        int64_t best = -1;
+        double bd = -1.0;
+        int32_t bk = 0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            int32_t j = col[p];
+            if (!is_seed[j]) continue;
+            double d = orc_strength_of(rho[eid[p]], eps);
+            int32_t key = orig_id ? orig_id[j] : j;
+            if (best < 0 || d > bd || (d == bd && key < bk)) { best = j; bd = d; bk = key; }
+        }
+        agg[i] = best >= 0 ? (int32_t)rank[best] : -1;     /* -1: no seed neighbour (cannot happen) */
+    }
+    free(rank);
+    return nc;
+}
+
+typedef struct {
+    int32_t R, k, levels;
+    double omega, eps, theta;
+    int64_t n_min;
+    uint64_t seed, graph_id, bin_seed;
+    const double *e;
+} orc_ml_opts;
+
+/* keep[m] of graph (n, row_ptr, col, w, eid, orig_id) at level l. */
+static void orc_ml_level(int64_t n, const int64_t *row_ptr, const int32_t *col, const float *w,
+                         const int32_t *eid, const int32_t *orig_id, int64_t m, const orc_ml_opts *o, int32_t l,
+                         uint8_t *keep, int32_t *depth)
+{
+    uint64_t gid = o->graph_id + (uint64_t)l;
+    double *rho = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    orc_algebraic_distance(n, row_ptr, col, w, eid, orig_id, m, o->R, o->k, o->omega, o->seed, gid, NULL, rho,
+                           NULL, NULL, NULL);
+    if (*depth < l) *depth = l;
+    int coarsest = (n <= o->n_min) || (l + 1 >= o->levels) || m == 0;
+    uint8_t *is_seed = NULL;
+    int32_t *agg = NULL;
+    int64_t nc = 0;
+    if (!coarsest) {
+        is_seed = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+        agg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        orc_ml_seeds(n, row_ptr, col, eid, orig_id, rho, o->eps, o->theta, is_seed);
+        nc = orc_ml_aggregates(n, row_ptr, col, eid, orig_id, rho, o->eps, is_seed, agg);
+        if ((double)nc > 0.9 * (double)n) coarsest = 1;
+    }
+    if (coarsest) {
+        orc_sparsify_binned(n, row_ptr, col, eid, orig_id, m, rho, o->bin_seed, gid, o->e[l], keep);
+        free(rho); free(is_seed); free(agg);
+        return;
+    }
+    /* coarse graph: the fine edges' aggregate pairs, repeats merged with summed weights */
+    int32_t *cu = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
+    int32_t *cv = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
+    float *cw = (float *)malloc(sizeof(float) * (size_t)m);
+    int32_t *corig = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+            if (col[p] > i) {
+                int32_t e = eid[p];
+                cu[e] = agg[i];
+                cv[e] = agg[col[p]];
+                cw[e] = w ? w[p] : 1.0f;
+            }
+    for (int64_t i = 0; i < n; ++i)
+        if (is_seed[i]) corig[agg[i]] = orig_id ? orig_id[i] : (int32_t)i;
+    int64_t *crp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc + 1));
+    int32_t *ccol = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m));
+    float *cwo = (float *)malloc(sizeof(float) * (size_t)(2 * m));
+    int32_t *ceid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m));
+    int32_t *corig2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+    int64_t cdrop = 0;
+    int64_t mc = orc_ingest(nc, m, cu, cv, cw, corig, 0, crp, ccol, cwo, ceid, corig2, &cdrop);
+    uint8_t *ckeep = (uint8_t *)malloc((size_t)(mc > 0 ? mc : 1));
+    orc_ml_level(nc, crp, ccol, cwo, ceid, corig2, mc, o, l + 1, ckeep, depth);
+    /* inherit: an edge between aggregates keeps its coarse edge's state */
+    uint8_t *inh = (uint8_t *)malloc((size_t)m);
+    for (int64_t e = 0; e < m; ++e) {
+        int32_t a = cu[e], b = cv[e];
+        if (a == b) { inh[e] = 1; continue; }
+        int32_t x = a < b ? a : b, y = a < b ? b : a;
+        int64_t lo = crp[x], hi = crp[x + 1];
+        while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (ccol[mid] < y) lo = mid + 1; else hi = mid;
+        }
+        inh[e] = ckeep[ceid[lo]];
+    }
+    /* the fine graph less the dropped edges: distances again, SparsifyB on it */
+    int64_t *srp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int32_t *scol = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m));
+    float *sw = w ? (float *)malloc(sizeof(float) * (size_t)(2 * m)) : NULL;
+    int32_t *seid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m));
+    int32_t *soe = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m));
+    int64_t ms = orc_subgraph(n, row_ptr, col, w, eid, m, inh, srp, scol, sw, seid, soe);
+    double *srho = (double *)malloc(sizeof(double) * (size_t)(ms > 0 ? ms : 1));
+    uint8_t *skeep = (uint8_t *)malloc((size_t)(ms > 0 ? ms : 1));
+    orc_algebraic_distance(n, srp, scol, sw, seid, orig_id, ms, o->R, o->k, o->omega, o->seed, gid, NULL, srho,
+                           NULL, NULL, NULL);
+    if (ms > 0) orc_sparsify_binned(n, srp, scol, seid, orig_id, ms, srho, o->bin_seed, gid, o->e[l], skeep);
+    memset(keep, 0, (size_t)m);
+    for (int64_t p = 0; p < 2 * ms; ++p)
+        if (skeep[seid[p]]) keep[soe[p]] = 1;
+    free(rho); free(is_seed); free(agg); free(cu); free(cv); free(cw); free(corig); free(crp); free(ccol);
+    free(cwo); free(ceid); free(corig2); free(ckeep); free(inh); free(srp); free(scol); free(sw); free(seid);
+    free(soe); free(srho); free(skeep);
+}
+
+/* Algorithm 6: keep[m] of the finest graph; returns the kept count, and
+ * the index of the coarsest level reached in *depth.                       */
+int64_t orc_ml_sparsify(int64_t n, const int64_t *row_ptr, const int32_t *col, const float *w,
+                        const int32_t *eid, const int32_t *orig_id, int64_t m, int32_t R, int32_t k,
+                        double omega, uint64_t seed, uint64_t graph_id, int32_t levels, int64_t n_min,
+                        const double *e, double eps, double theta, uint64_t bin_seed, uint8_t *keep,
+                        int32_t *depth)
+{
+    orc_ml_opts o = {R, k, levels, omega, eps, theta, n_min, seed, graph_id, bin_seed, e};
+    int32_t dd = 0;
+    if (m > 0) orc_ml_level(n, row_ptr, col, w, eid, orig_id, m, &o, 0, keep, &dd);
+    if (depth) *depth = dd;
+    int64_t kept = 0;
+    for (int64_t q = 0; q < m; ++q) kept += keep[q];
+    return kept;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Reverse-mode derivative of L = sum_e c_e rho_e with respect to the edge
  * weights w_e (w_ij = w_ji = w_e), taken through the k sweeps, the rescale
  * (its min and max as functions of x^(k)) and the distance.  Written by the
