@@ -817,9 +817,10 @@ double orc_spearman(int64_t n, const double *x, const double *y)
  *   - i and j are strongly coupled when delta_ij >= theta * smax_i or
  *     delta_ij >= theta * smax_j, smax_i the largest strength at i;
  *   - seeds ("traversal of F, moving to C the nodes not strongly coupled to
- *     those already in C"): vertices in decreasing degree, ties by smaller
- *     orig_id; a vertex becomes a seed when none of its strong neighbours is
- *     a seed yet;
+ *     those already in C"): vertices in decreasing degree, ties in the
+ *     pseudo-random order of fmix32(orig_id) (MurmurHash3's finalizer, a
+ *     bijection), then smaller orig_id; a vertex becomes a seed when none of
+ *     its strong neighbours is a seed yet;
  *   - restriction P (Eq. P): a seed is its own aggregate; any other vertex
  *     joins the seed neighbour of largest delta_ij (the normalising sum is
  *     the same for every j), ties by smaller orig_id; aggregates are
@@ -843,13 +844,14 @@ static double orc_strength_of(double rho, double eps)
     return 1.0 / sqrt(t);
 }
 
-typedef struct { int64_t deg; int32_t key; int64_t i; } orc_vprio;
+typedef struct { int64_t deg; uint32_t hash; int32_t key; int64_t i; } orc_vprio;
 
 static int orc_cmp_vprio(const void *a, const void *b)
 {
     const orc_vprio *x = (const orc_vprio *)a, *y = (const orc_vprio *)b;
     if (x->deg != y->deg) return x->deg > y->deg ? -1 : 1;     /* larger degree first */
-    return (x->key > y->key) - (x->key < y->key);              /* then smaller orig_id */
+    if (x->hash != y->hash) return x->hash < y->hash ? -1 : 1; /* then the hashed name */
+    return (x->key > y->key) - (x->key < y->key);
 }
 
 void orc_ml_seeds(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *eid,
@@ -869,6 +871,7 @@ void orc_ml_seeds(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
     for (int64_t i = 0; i < n; ++i) {
         order[i].deg = row_ptr[i + 1] - row_ptr[i];
         order[i].key = orig_id ? orig_id[i] : (int32_t)i;
+        order[i].hash = orc_fmix32((uint32_t)order[i].key);
         order[i].i = i;
     }
     qsort(order, (size_t)n, sizeof(orc_vprio), orc_cmp_vprio);

@@ -3,7 +3,7 @@ paper fixes and by its parts:
 
   - seeds: no two seeds are strongly coupled, every other vertex is strongly
     coupled to a seed, and a set-based Python traversal of the vertices in
-    the stated order picks the same seeds;
+    the stated order (degree, then the hashed name) picks the same seeds;
   - P (Eq. P): seeds are their own aggregates, numbered in id order; every
     other vertex joins a seed neighbour of largest strength;
   - the coarse graph built by merging aggregate pairs is the Galerkin
@@ -48,7 +48,8 @@ def test_seed_rule_by_sets():
     for p in np.nonzero(strong)[0]:
         nbr[rows[p]].add(int(g.col[p]))
     deg = np.diff(g.row_ptr)
-    order = sorted(range(g.n), key=lambda i: (-deg[i], g.orig_id[i]))
+    hashed = [oracle.bin_priority(0, int(g.orig_id[i])) for i in range(g.n)]     # fmix32 of the name
+    order = sorted(range(g.n), key=lambda i: (-deg[i], hashed[i], g.orig_id[i]))
     chosen = set()
     for i in order:
         if not (nbr[i] & chosen):
