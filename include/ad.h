@@ -337,6 +337,67 @@ size_t ad_spearman_workspace_size(int64_t n);
 ad_status ad_spearman(int64_t n, const double *x, const double *y, double *rho_host, void *ws,
                       size_t ws_bytes, hipStream_t stream);
 
+/* ----------------------------------------------------------- multilevel -- */
+
+/* Workspace bytes for ad_ml_aggregate (0 when n < 0 or n >= 2^31). */
+size_t ad_ml_aggregate_workspace_size(const ad_graph *g);
+
+/* One coarsening step of Algorithm 6 (Section 5): the seeds and the
+ * restriction P of Eq. P from the distances rho.  With the strength
+ *     delta_e = 1 / sqrt(rho_e^2 + eps)
+ * and smax_i the largest strength at i, i and j are strongly coupled when
+ * delta_ij >= theta smax_i or delta_ij >= theta smax_j.  Seeds are chosen
+ * as by visiting the vertices in decreasing degree (ties: smaller
+ * fmix32(orig_id), then smaller orig_id) and taking each one that has no
+ * strongly coupled seed yet.  Every seed is its own aggregate, numbered in
+ * increasing vertex id; every other vertex joins its seed neighbour of
+ * largest strength (ties: smaller orig_id), -1 if it has none.
+ *   rho: DEVICE [m] (AD_F32 or AD_F64, strengths in double).
+ *   agg: DEVICE int32 [n], the aggregate (coarse vertex) of every vertex.
+ *   is_seed: DEVICE uint8 [n] or NULL.  n_coarse_host: HOST, the number of
+ *   seeds (coarse vertices).
+ * SYNCHRONISES `stream` (the seed rounds read a count back).  Errors:
+ * AD_ERR_INVALID_ARG, AD_ERR_WORKSPACE, AD_ERR_UNSUPPORTED (n >= 2^31). */
+ad_status ad_ml_aggregate(const ad_graph *g, ad_dtype rho_dtype, const void *rho, double eps,
+                          double theta, int32_t *agg, uint8_t *is_seed, int64_t *n_coarse_host,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Parameters of ad_ml_sparsify. */
+typedef struct {
+    int32_t R, k;             /* relaxation at every level (as ad_relax_opts)        */
+    double omega;
+    uint64_t seed;            /* Philox key word 0 of the test vectors and bin keys   */
+    uint64_t graph_id;        /* level l uses graph_id + l                            */
+    ad_dtype store;           /* AD_F64 or AD_F32: relaxation and distances           */
+    int32_t levels;           /* at most this many levels, 1..64 (1 = SparsifyB only) */
+    int64_t n_min;            /* a graph with n <= n_min is not coarsened            */
+    const double *e_host;     /* HOST [levels]: SparsifyB exponent of every level     */
+    double eps, theta;        /* strength and coupling of ad_ml_aggregate            */
+    uint64_t bin_seed;        /* Philox key word 0 of SparsifyB's vertex keys         */
+} ad_ml_opts;
+
+/* Algorithm 6 (MLSparsify).  Level 0 is g.  At level l: distances by
+ * ad_relax + ad_edge_dist (graph id graph_id + l); if n <= n_min, or
+ * l == levels - 1, or the graph has no edges, or ad_ml_aggregate would keep
+ * more than 90% of the vertices, SparsifyB (ad_sparsify_binned, exponent
+ * e_host[l], graph id graph_id + l) selects and the recursion ends.
+ * Otherwise the coarse graph P^T L P (aggregate pairs of the fine edges,
+ * merged by ad_ingest with summed weights; a unit weight per edge when g is
+ * unweighted; coarse vertices named by their seeds' orig_id) is sparsified
+ * at level l + 1; every fine edge joining two aggregates inherits its coarse
+ * edge's state, every edge inside an aggregate is kept; distances are then
+ * recomputed on the fine graph less the dropped edges (ad_subgraph) and
+ * SparsifyB selects among its edges: keep[e] = 1 for those.
+ *   keep: DEVICE uint8 [m].  n_kept_host: HOST, sum(keep).  depth_host:
+ *   HOST or NULL, the index of the coarsest level reached.
+ * The call allocates the per-level graphs and buffers itself (their sizes
+ * follow from the coarsening) with hipMalloc and frees them before it
+ * returns; it SYNCHRONISES `stream` and is not for stream capture.  Errors:
+ * AD_ERR_INVALID_ARG for bad options, AD_ERR_UNSUPPORTED for m >= 2^30,
+ * AD_ERR_HIP when an allocation fails. */
+ad_status ad_ml_sparsify(const ad_graph *g, const ad_ml_opts *o, uint8_t *keep,
+                         int64_t *n_kept_host, int32_t *depth_host, hipStream_t stream);
+
 /* ------------------------------------------------------------- adjoint --- */
 
 /* Workspace bytes for ad_relax_backward. */

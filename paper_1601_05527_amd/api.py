@@ -45,6 +45,13 @@ class ADBatchOpts(ctypes.Structure):
     _fields_ = [("orient", ctypes.c_int), ("e", ctypes.c_double), ("autotune", ctypes.c_int32)]
 
 
+class ADMLOpts(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int32), ("k", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("graph_id", ctypes.c_uint64), ("store", ctypes.c_int),
+                ("levels", ctypes.c_int32), ("n_min", ctypes.c_int64), ("e_host", ctypes.c_void_p),
+                ("eps", ctypes.c_double), ("theta", ctypes.c_double), ("bin_seed", ctypes.c_uint64)]
+
+
 class ADError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
@@ -85,6 +92,9 @@ def _load_lib():
         "ad_sparsify_binned_workspace_size": (S, [G]),
         "ad_sparsify_binned": (st, [G, ctypes.c_int, P, ctypes.c_uint64, ctypes.c_uint64, f64, f64, P, P,
                                     ctypes.POINTER(ctypes.c_double), P, S, P]),
+        "ad_ml_aggregate_workspace_size": (S, [G]),
+        "ad_ml_aggregate": (st, [G, ctypes.c_int, P, f64, f64, P, P, ctypes.POINTER(i64), P, S, P]),
+        "ad_ml_sparsify": (st, [G, ctypes.POINTER(ADMLOpts), P, ctypes.POINTER(i64), ctypes.POINTER(i32), P]),
         "ad_sparsify_fit_both": (st, [G, ctypes.c_int, P, f64, P, P, P, P, P, S, P]),
         "ad_relax_backward_workspace_size": (S, [G, O]),
         "ad_relax_backward": (st, [G, O, P, P, P, P, P, P, S, P]),
@@ -650,3 +660,44 @@ def compare_properties(dg: DeviceGraph, keep: torch.Tensor) -> dict:
             "components": po["n_components"], "components_sparse": ps["n_components"],
             "comp_ratio": ps["n_components"] / max(1, po["n_components"]),
             "degree_spearman": spearman(deg_o, deg_s), "clustering_spearman": spearman(po["c"], ps["c"])}
+
+
+# ------------------------------------------------------------ multilevel ---
+
+def ml_aggregate(dg: DeviceGraph, rho: torch.Tensor, eps: float = 1e-12, theta: float = 0.5):
+    """One coarsening step of Algorithm 6 (``ad_ml_aggregate``): returns
+    (agg int32 [n], is_seed uint8 [n], n_coarse).  Synchronises the current
+    stream."""
+    dev = rho.device
+    g = dg.abi()
+    ws = _workspace(lib.ad_ml_aggregate_workspace_size(ctypes.byref(g)), dev)
+    agg = torch.empty(max(1, dg.n), dtype=torch.int32, device=dev)
+    is_seed = torch.empty(max(1, dg.n), dtype=torch.uint8, device=dev)
+    nc = ctypes.c_int64(0)
+    dt = AD_F64 if rho.dtype == torch.float64 else AD_F32
+    _check(lib.ad_ml_aggregate(ctypes.byref(g), dt, _ptr(rho.contiguous()), float(eps), float(theta), _ptr(agg),
+                               _ptr(is_seed), ctypes.byref(nc), _ptr(ws), ws.numel(), _stream()))
+    return agg[:dg.n], is_seed[:dg.n], nc.value
+
+
+def ml_sparsify(dg: DeviceGraph, R: int, k: int, e_levels, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
+                levels: int = 8, n_min: int = 1000, store: str = "f32", eps: float = 1e-12, theta: float = 0.5,
+                bin_seed: int = 0, keep: Optional[torch.Tensor] = None):
+    """Algorithm 6, MLSparsify (``ad_ml_sparsify``).  ``e_levels`` gives the
+    SparsifyB exponent of every level (its last value repeats).  Returns
+    (keep uint8 [m], n_kept, depth).  Synchronises the current stream."""
+    ev = [float(x) for x in np.atleast_1d(np.asarray(e_levels, dtype=np.float64))]
+    ev = (ev + [ev[-1]] * max(0, levels - len(ev)))[:max(levels, 1)]
+    e_arr = (ctypes.c_double * len(ev))(*ev)
+    o = ADMLOpts(R=R, k=k, omega=omega, seed=int(seed) & (2 ** 64 - 1), graph_id=int(graph_id) & (2 ** 64 - 1),
+                 store=_DTYPES[store], levels=levels, n_min=n_min,
+                 e_host=ctypes.cast(e_arr, ctypes.c_void_p).value, eps=eps, theta=theta,
+                 bin_seed=int(bin_seed) & (2 ** 64 - 1))
+    g = dg.abi()
+    if keep is None:
+        keep = torch.empty(max(1, dg.m), dtype=torch.uint8, device=dg.row_ptr.device)
+    kept = ctypes.c_int64(0)
+    depth = ctypes.c_int32(0)
+    _check(lib.ad_ml_sparsify(ctypes.byref(g), ctypes.byref(o), _ptr(keep), ctypes.byref(kept), ctypes.byref(depth),
+                              _stream()))
+    return keep[:dg.m], kept.value, depth.value

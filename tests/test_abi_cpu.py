@@ -241,3 +241,53 @@ def test_property_calls_reject_bad_arguments():
     assert L.ad_spearman(10, p, p, None, ws, 1 << 30, None) == 1
     assert L.ad_spearman(1 << 31, p, p, ctypes.byref(rho), ws, 1 << 30, None) == 2
     assert L.ad_spearman_workspace_size(-3) == 0
+
+
+def test_multilevel_calls_reject_bad_arguments():
+    from paper_1601_05527_amd import api
+    L = api.lib
+    g = _graph_struct(api)
+    p = ctypes.c_void_p(0x40000)
+    ws = ctypes.c_void_p(0x10000)
+    nc = ctypes.c_int64()
+    need = L.ad_ml_aggregate_workspace_size(ctypes.byref(g))
+    assert need > 0
+    assert L.ad_ml_aggregate(ctypes.byref(g), 2, p, 1e-12, 0.5, p, None, ctypes.byref(nc), ws, need, None) == 1
+    assert L.ad_ml_aggregate(ctypes.byref(g), 1, None, 1e-12, 0.5, p, None, ctypes.byref(nc), ws, need, None) == 1
+    assert L.ad_ml_aggregate(ctypes.byref(g), 1, p, 1e-12, 0.5, None, None, ctypes.byref(nc), ws, need, None) == 1
+    assert L.ad_ml_aggregate(ctypes.byref(g), 1, p, 1e-12, 0.5, p, None, None, ws, need, None) == 1
+    assert L.ad_ml_aggregate(ctypes.byref(g), 1, p, -1.0, 0.5, p, None, ctypes.byref(nc), ws, need, None) == 1
+    assert L.ad_ml_aggregate(ctypes.byref(g), 1, p, 1e-12, 1.5, p, None, ctypes.byref(nc), ws, need, None) == 1
+    assert L.ad_ml_aggregate(ctypes.byref(g), 1, p, 1e-12, 0.5, p, None, ctypes.byref(nc), ws, need - 256,
+                             None) == 3
+    assert L.ad_ml_aggregate(ctypes.byref(g), 1, p, 1e-12, 0.5, p, None, ctypes.byref(nc),
+                             ctypes.c_void_p(0x10010), need, None) == 3
+    big = api.ADGraph(1 << 31, 3, 0x1000, 0x2000, None, 0x3000, None, 3, None)
+    assert L.ad_ml_aggregate_workspace_size(ctypes.byref(big)) == 0
+
+    e = (ctypes.c_double * 4)(0.5, 0.5, 0.5, 0.5)
+    ep = ctypes.cast(e, ctypes.c_void_p).value
+
+    def opts(**kw):
+        base = dict(R=8, k=10, omega=0.5, seed=1, graph_id=0, store=1, levels=4, n_min=10, e_host=ep, eps=1e-12,
+                    theta=0.5, bin_seed=3)
+        base.update(kw)
+        return api.ADMLOpts(**base)
+
+    kept, depth = ctypes.c_int64(), ctypes.c_int32()
+
+    def call(o, keep=p, kh=True):
+        return L.ad_ml_sparsify(ctypes.byref(g), ctypes.byref(o), keep, ctypes.byref(kept) if kh else None,
+                                ctypes.byref(depth), None)
+
+    for bad in [dict(R=0), dict(R=65), dict(k=-1), dict(omega=0.0), dict(omega=1.5), dict(store=2),
+                dict(levels=0), dict(levels=65), dict(n_min=-1), dict(e_host=None), dict(eps=-1.0),
+                dict(theta=2.0)]:
+        assert call(opts(**bad)) == 1, bad
+    e[2] = 1.5
+    assert call(opts()) == 1
+    e[2] = 0.5
+    assert call(opts(), keep=None) == 1
+    assert call(opts(), kh=False) == 1
+    huge = api.ADGraph(4, 1 << 30, 0x1000, 0x2000, None, 0x3000, None, 3, None)
+    assert L.ad_ml_sparsify(ctypes.byref(huge), ctypes.byref(opts()), p, ctypes.byref(kept), None, None) == 2
