@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE.  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package; the library never does, and this
 package imports nothing from the library.  Every function here is a thin
 ctypes wrapper around the C oracle, which follows the paper's Algorithm 1
-(ComputeAlgDist), Algorithm 3 (Sparsify), Algorithm 4 (SparsifyB) and the binary-search
-fitting of Section 6.2 in double precision.
+(ComputeAlgDist), Algorithm 3 (Sparsify), Algorithm 4 (SparsifyB), the binary-search
+fitting of Section 6.2, Algorithm 6 (MLSparsify) and the graph properties of the
+Preliminaries in double precision.
 
 Parity status: every function is pinned by tests that do not reuse its own
 formulas (closed forms, library routines, brute force); the one reading
@@ -33,7 +34,10 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 PINS = {"parity_unpinned": ["eps value", "min-max rescale", "floor in d^e", "start-vector stream layout",
                             "SparsifyB random order (vertex key stream, priority hash)",
                             "SparsifyB round-robin reading of 'randomly select bins and edges'",
-                            "SparsifyB single-precision sigma"]}
+                            "SparsifyB single-precision sigma",
+                            "multilevel strength threshold theta, eps and the seed traversal's tie order",
+                            "multilevel ratio-vector alignment when fewer levels are reached than entries",
+                            "level-span segment bounds when the level count is not a multiple of 3"]}
 
 LOCAL = 0
 GLOBAL = 1
@@ -90,8 +94,9 @@ def _load():
     lib.orc_ml_seeds.argtypes = [i64, P, P, P, P, P, f64, f64, P]
     lib.orc_ml_aggregates.argtypes = [i64, P, P, P, P, P, f64, P, P]
     lib.orc_ml_aggregates.restype = i64
-    lib.orc_ml_sparsify.argtypes = [i64, P, P, P, P, P, i64, i32, i32, f64, u64, u64, i32, i64, P, f64, f64, u64,
-                                    P, P]
+    lib.orc_ml_sparsify.argtypes = [i64, P, P, P, P, P, i64, i32, i32, f64, u64, u64, i32, i64, P, i32, i32, i32,
+                                    f64, f64, f64, u64, P, P]
+    lib.orc_ml_level_span.argtypes = [i32, i32, i32, f64, P]
     lib.orc_ml_sparsify.restype = i64
     lib.orc_subgraph.restype = i64
     lib.orc_triangles.argtypes = [i64, P, P, P]
@@ -373,16 +378,31 @@ def ml_aggregates(g, rho, is_seed, eps: float = 1e-12):
     return agg[:g.n], int(nc)
 
 
-def ml_sparsify(g, R: int, k: int, e_levels, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
-                levels: int = 8, n_min: int = 1000, eps: float = 1e-12, theta: float = 0.5, bin_seed: int = 0):
-    """Algorithm 6 (MLSparsify).  Returns (keep[m], n_kept, depth)."""
+def ml_level_span(n_levels: int, span: int, segment: int, value: float) -> np.ndarray:
+    """The per-level ratio vector of the level-span rule (Section 6,
+    implementation paragraph), coarsest level first: segment 0, 1, 2 =
+    coarsest, middle, finest third of the levels; -1 = no sparsification."""
     lib = _load()
-    ev = np.ascontiguousarray(e_levels, dtype=np.float64)
+    out = np.zeros(max(1, n_levels), dtype=np.float64)
+    lib.orc_ml_level_span(n_levels, span, segment, value, _p(out))
+    return out[:n_levels]
+
+
+def ml_sparsify(g, R: int, k: int, e_levels=None, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
+                levels: int = 8, n_min: int = 1000, eps: float = 1e-12, theta: float = 0.5, bin_seed: int = 0,
+                fit: bool = False, span: int = 0, segment: int = 0, span_value: float = 0.3):
+    """Algorithm 6 (MLSparsify).  e_levels: per-level ratios, coarsest level
+    first (a shorter list repeats its last value; negative = no
+    sparsification at that level); entries are exponents, or retention
+    targets with `fit`.  span > 0 replaces e_levels by the level-span vector
+    of the levels reached.  Returns (keep[m], n_kept, depth)."""
+    lib = _load()
+    ev = np.atleast_1d(np.ascontiguousarray(e_levels if e_levels is not None else [0.0], dtype=np.float64))
     if ev.size < levels:
         ev = np.concatenate([ev, np.full(levels - ev.size, ev[-1])])
     keep = np.zeros(max(1, g.m), dtype=np.uint8)
     depth = ctypes.c_int32(0)
     kept = lib.orc_ml_sparsify(g.n, _p(g.row_ptr), _p(g.col), _p(_c(g.w, np.float32)), _p(g.eid), _p(g.orig_id),
-                               g.m, R, k, omega, seed, graph_id, levels, n_min, _p(ev), eps, theta, bin_seed,
-                               _p(keep), ctypes.byref(depth))
+                               g.m, R, k, omega, seed, graph_id, levels, n_min, _p(ev), int(fit), span, segment,
+                               span_value, eps, theta, bin_seed, _p(keep), ctypes.byref(depth))
     return keep[:g.m], int(kept), int(depth.value)

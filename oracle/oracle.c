@@ -831,7 +831,18 @@ double orc_spearman(int64_t n, const double *x, const double *y)
  *   - coarsening stops at n <= n_min, at level levels - 1, or when it would
  *     keep more than 90% of the vertices; that level is the coarsest;
  *   - level l uses graph id graph_id + l for its test vectors and its bin
- *     order, and exponent e[l] for SparsifyB;
+ *     order;
+ *   - the vector of per-level ratios (Section 6, implementation paragraph)
+ *     lists the levels from the coarsest one reached: with D the index of
+ *     the coarsest level, level l takes entry D - l.  A negative entry means
+ *     no SparsifyB at that level (it keeps what it inherits; the coarsest
+ *     level then keeps all its edges).  Otherwise the entry is SparsifyB's
+ *     exponent e, or, with `fit`, the fraction of the level's edges that
+ *     SparsifyB keeps, e fitted by the bisection of Section 6.2;
+ *   - level-span (same paragraph): the D + 1 levels split into three
+ *     segments (coarsest, middle, finest), segment s holding entries
+ *     floor(s (D+1) / 3) .. floor((s+1) (D+1) / 3) - 1; the first `span`
+ *     entries of the chosen segment take the value, all others -1;
  *   - uncoarsening: a fine edge between two aggregates keeps the state of
  *     their coarse edge, an edge inside an aggregate is kept; distances are
  *     recomputed on the fine graph less the dropped edges and SparsifyB
@@ -921,8 +932,40 @@ typedef struct {
     double omega, eps, theta;
     int64_t n_min;
     uint64_t seed, graph_id, bin_seed;
-    const double *e;
+    const double *e;             /* [levels], coarsest level first */
+    int32_t fit, span, segment;
+    double span_value;
 } orc_ml_opts;
+
+/* The level-span vector over n_levels levels, coarsest first. */
+void orc_ml_level_span(int32_t n_levels, int32_t span, int32_t segment, double value, double *out)
+{
+    int32_t lo = segment * n_levels / 3, hi = (segment + 1) * n_levels / 3;
+    for (int32_t t = 0; t < n_levels; ++t) out[t] = (t >= lo && t < hi && t - lo < span) ? value : -1.0;
+}
+
+/* The ratio-vector entry of level l when the coarsest level is D. */
+static double orc_ml_entry(const orc_ml_opts *o, int32_t D, int32_t l)
+{
+    if (o->span > 0) {
+        double *v = (double *)malloc(sizeof(double) * (size_t)(D + 1));
+        orc_ml_level_span(D + 1, o->span, o->segment, o->span_value, v);
+        double x = v[D - l];
+        free(v);
+        return x;
+    }
+    return o->e[D - l];
+}
+
+/* SparsifyB of one level with its entry x (x < 0: keep everything). */
+static void orc_ml_select(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *eid,
+                          const int32_t *orig_id, int64_t m, const double *rho, const orc_ml_opts *o,
+                          uint64_t gid, double x, uint8_t *keep)
+{
+    if (x < 0.0) { memset(keep, 1, (size_t)m); return; }
+    if (o->fit) orc_fit_exponent_binned(n, row_ptr, col, eid, orig_id, m, rho, o->bin_seed, gid, x, keep, NULL);
+    else orc_sparsify_binned(n, row_ptr, col, eid, orig_id, m, rho, o->bin_seed, gid, x, keep);
+}
 
 /* keep[m] of graph (n, row_ptr, col, w, eid, orig_id) at level l. */
 static void orc_ml_level(int64_t n, const int64_t *row_ptr, const int32_t *col, const float *w,
@@ -946,7 +989,7 @@ static void orc_ml_level(int64_t n, const int64_t *row_ptr, const int32_t *col, 
         if ((double)nc > 0.9 * (double)n) coarsest = 1;
     }
     if (coarsest) {
-        orc_sparsify_binned(n, row_ptr, col, eid, orig_id, m, rho, o->bin_seed, gid, o->e[l], keep);
+        orc_ml_select(n, row_ptr, col, eid, orig_id, m, rho, o, gid, orc_ml_entry(o, l, l), keep);
         free(rho); free(is_seed); free(agg);
         return;
     }
@@ -988,6 +1031,13 @@ static void orc_ml_level(int64_t n, const int64_t *row_ptr, const int32_t *col, 
         inh[e] = ckeep[ceid[lo]];
     }
     /* the fine graph less the dropped edges: distances again, SparsifyB on it */
+    double x = orc_ml_entry(o, *depth, l);
+    if (x < 0.0) {
+        memcpy(keep, inh, (size_t)m);
+        free(rho); free(is_seed); free(agg); free(cu); free(cv); free(cw); free(corig); free(crp); free(ccol);
+        free(cwo); free(ceid); free(corig2); free(ckeep); free(inh);
+        return;
+    }
     int64_t *srp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
     int32_t *scol = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m));
     float *sw = w ? (float *)malloc(sizeof(float) * (size_t)(2 * m)) : NULL;
@@ -998,7 +1048,7 @@ static void orc_ml_level(int64_t n, const int64_t *row_ptr, const int32_t *col, 
     uint8_t *skeep = (uint8_t *)malloc((size_t)(ms > 0 ? ms : 1));
     orc_algebraic_distance(n, srp, scol, sw, seid, orig_id, ms, o->R, o->k, o->omega, o->seed, gid, NULL, srho,
                            NULL, NULL, NULL);
-    if (ms > 0) orc_sparsify_binned(n, srp, scol, seid, orig_id, ms, srho, o->bin_seed, gid, o->e[l], skeep);
+    if (ms > 0) orc_ml_select(n, srp, scol, seid, orig_id, ms, srho, o, gid, x, skeep);
     memset(keep, 0, (size_t)m);
     for (int64_t p = 0; p < 2 * ms; ++p)
         if (skeep[seid[p]]) keep[soe[p]] = 1;
@@ -1008,14 +1058,16 @@ static void orc_ml_level(int64_t n, const int64_t *row_ptr, const int32_t *col, 
 }
 
 /* Algorithm 6: keep[m] of the finest graph; returns the kept count, and
- * the index of the coarsest level reached in *depth.                       */
+ * the index of the coarsest level reached in *depth.  e: [levels] ratios,
+ * coarsest level first (ignored when span > 0).                            */
 int64_t orc_ml_sparsify(int64_t n, const int64_t *row_ptr, const int32_t *col, const float *w,
                         const int32_t *eid, const int32_t *orig_id, int64_t m, int32_t R, int32_t k,
                         double omega, uint64_t seed, uint64_t graph_id, int32_t levels, int64_t n_min,
-                        const double *e, double eps, double theta, uint64_t bin_seed, uint8_t *keep,
-                        int32_t *depth)
+                        const double *e, int32_t fit, int32_t span, int32_t segment, double span_value,
+                        double eps, double theta, uint64_t bin_seed, uint8_t *keep, int32_t *depth)
 {
-    orc_ml_opts o = {R, k, levels, omega, eps, theta, n_min, seed, graph_id, bin_seed, e};
+    orc_ml_opts o = {R, k, levels, omega, eps, theta, n_min, seed, graph_id, bin_seed, e, fit, span, segment,
+                     span_value};
     int32_t dd = 0;
     if (m > 0) orc_ml_level(n, row_ptr, col, w, eid, orig_id, m, &o, 0, keep, &dd);
     if (depth) *depth = dd;

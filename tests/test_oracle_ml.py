@@ -11,9 +11,15 @@ paper fixes and by its parts:
   - one level is SparsifyB; exponent 1 everywhere keeps every edge;
   - two levels compose as the algorithm states: the coarse level's result
     is inherited, distances are recomputed on what is left, and SparsifyB
-    chooses among it;
+    chooses among it; the ratio vector lists the coarsest level first;
+  - the level-span vectors equal the ones the paper prints (6 levels,
+    span 2; tests/golden/ml_level_span.txt); a negative entry skips
+    SparsifyB at its level; with `fit` an entry is the level's retention
+    target;
   - results do not depend on vertex labels.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -107,11 +113,8 @@ def test_one_level_is_sparsify_b_and_exponent_one_keeps_all():
     assert depth > 0 and kept == g.m
 
 
-def test_two_levels_compose_as_stated():
-    g, rho = _case(n=2000, m=14000, seed=7)
-    e = [0.6, 0.4]
-    keep, kept, depth = oracle.ml_sparsify(g, 8, 10, e, seed=1, levels=2, n_min=100, bin_seed=9)
-    assert depth == 1
+def _two_level_parts(g, rho, x_coarse, bin_seed):
+    """The coarse graph of g and the keep of its SparsifyB at exponent x_coarse."""
     seeds = oracle.ml_seeds(g, rho, EPS, THETA)
     agg, nc = oracle.ml_aggregates(g, rho, seeds, EPS)
     names = g.orig_id[np.nonzero(seeds)[0]]
@@ -122,8 +125,11 @@ def test_two_levels_compose_as_stated():
     cg.edge_u = crow[col > crow].astype(np.int32)     # coarse edges in id order
     cg.edge_v = col[col > crow]
     rho_c = oracle.algebraic_distance(cg, 8, 10, 0.5, seed=1, graph_id=1)
-    keep_c, _ = oracle.sparsify_binned(cg, rho_c, e[1], 9, graph_id=1)
-    # inherit, then SparsifyB on what is left with recomputed distances
+    if x_coarse < 0:
+        keep_c = np.ones(mc, dtype=np.uint8)
+    else:
+        keep_c, _ = oracle.sparsify_binned(cg, rho_c, x_coarse, bin_seed, graph_id=1)
+    # inherit: an edge between aggregates takes its coarse edge's state
     a, b = agg[g.edge_u], agg[g.edge_v]
     inh = np.ones(g.m, dtype=np.uint8)
     for q in np.nonzero(a != b)[0]:
@@ -131,6 +137,10 @@ def test_two_levels_compose_as_stated():
         lo, hi = rp[x], rp[x + 1]
         p = lo + np.searchsorted(col[lo:hi], y)
         inh[q] = keep_c[ceid[p]]
+    return inh
+
+
+def _fine_select(g, inh, x_fine, bin_seed):
     srp, scol, sw, seid, soe, ms = oracle.subgraph(g, inh)
     sg = G.Graph(n=g.n, row_ptr=srp, col=scol, w=sw, eid=seid, orig_id=g.orig_id, edge_u=None, edge_v=None,
                  edge_w=None)
@@ -138,11 +148,70 @@ def test_two_levels_compose_as_stated():
     sg.edge_u = srow[scol > srow].astype(np.int32)
     sg.edge_v = scol[scol > srow]
     rho_s = oracle.algebraic_distance(sg, 8, 10, 0.5, seed=1, graph_id=0)
-    keep_s, _ = oracle.sparsify_binned(sg, rho_s, e[0], 9, graph_id=0)
+    keep_s, _ = oracle.sparsify_binned(sg, rho_s, x_fine, bin_seed, graph_id=0)
     want = np.zeros(g.m, dtype=np.uint8)
     want[soe[keep_s[seid] == 1]] = 1
+    return want
+
+
+def test_two_levels_compose_as_stated():
+    g, rho = _case(n=2000, m=14000, seed=7)
+    e = [0.6, 0.4]              # coarsest level first
+    keep, kept, depth = oracle.ml_sparsify(g, 8, 10, e, seed=1, levels=2, n_min=100, bin_seed=9)
+    assert depth == 1
+    inh = _two_level_parts(g, rho, e[0], 9)
+    want = _fine_select(g, inh, e[1], 9)
     np.testing.assert_array_equal(keep, want)
     assert np.all(keep <= inh)
+    # -1 at the finest level: the coarse result is inherited and nothing more is dropped
+    keep, kept, _ = oracle.ml_sparsify(g, 8, 10, [0.6, -1], seed=1, levels=2, n_min=100, bin_seed=9)
+    np.testing.assert_array_equal(keep, inh)
+    # -1 at the coarsest level: the fine level selects among all its edges
+    keep, kept, _ = oracle.ml_sparsify(g, 8, 10, [-1, 0.4], seed=1, levels=2, n_min=100, bin_seed=9)
+    kb, _ = oracle.sparsify_binned(g, rho, 0.4, 9)
+    np.testing.assert_array_equal(keep, kb)
+    # -1 everywhere keeps the graph
+    keep, kept, depth = oracle.ml_sparsify(g, 8, 10, [-1], seed=1, levels=4, n_min=100, bin_seed=9)
+    assert depth >= 2 and kept == g.m
+
+
+def _golden_span():
+    path = os.path.join(os.path.dirname(__file__), "golden", "ml_level_span.txt")
+    rows = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            name, *vals = line.split()
+            rows[name] = [float(v) for v in vals]
+    return rows
+
+
+def test_level_span_vectors_are_the_papers():
+    rows = _golden_span()
+    for s, name in enumerate(["coarsest", "middle", "finest"]):
+        np.testing.assert_array_equal(oracle.ml_level_span(6, 2, s, 0.3), rows[name])
+    # nine levels, span 3: three whole thirds; a span beyond a segment stays inside it
+    np.testing.assert_array_equal(oracle.ml_level_span(9, 3, 1, 0.5), [-1] * 3 + [0.5] * 3 + [-1] * 3)
+    np.testing.assert_array_equal(oracle.ml_level_span(6, 5, 2, 0.2), [-1] * 4 + [0.2] * 2)
+    np.testing.assert_array_equal(oracle.ml_level_span(6, 1, 0, 0.2), [0.2] + [-1] * 5)
+
+
+def test_level_span_follows_the_levels_reached():
+    g, rho = _case(n=2000, m=14000, seed=7)
+    k1, n1, d1 = oracle.ml_sparsify(g, 8, 10, None, seed=1, levels=6, n_min=100, bin_seed=9, span=1, segment=2,
+                                    span_value=0.5)
+    vec = oracle.ml_level_span(d1 + 1, 1, 2, 0.5)
+    k2, n2, d2 = oracle.ml_sparsify(g, 8, 10, vec, seed=1, levels=d1 + 1, n_min=100, bin_seed=9)
+    assert d1 == d2 and n1 == n2
+    np.testing.assert_array_equal(k1, k2)
+
+
+def test_fit_takes_the_entry_as_a_retention_target():
+    g, rho = _case(seed=6)
+    keep, kept, depth = oracle.ml_sparsify(g, 8, 10, [0.3], seed=1, levels=1, bin_seed=4, fit=True)
+    e_f, kb, nb = oracle.fit_exponent_binned(g, rho, 0.3, 4)
+    assert depth == 0 and kept == nb and np.array_equal(keep, kb)
+    assert kept >= 0.3 * g.m
 
 
 def test_multilevel_does_not_depend_on_labels():
