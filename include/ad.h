@@ -12,15 +12,20 @@
  *   Algorithm 3 (Sparsify): every vertex keeps its top d_i^e neighbours,
  *     ranked by delta ascending or descending; the sparse graph is the union.
  *   Section 6.2: e is fitted by binary search to a target retention ratio.
+ *   Algorithm 4 (SparsifyB): the selection with per-vertex bins.
+ *   Algorithm 6 (MLSparsify): the multilevel cycle (coarsening by seeds and
+ *     the restriction P, Galerkin coarse graphs, inheritance on the way back).
+ *   Around the path: an edge-list ingest into the graph model of Section 2,
+ *     and the graph properties of the Preliminaries for comparing G_s with G.
  *
  * Conventions for every call below.
  *   - Pointers are DEVICE pointers unless the name ends in _host.
  *   - The caller owns every buffer.  The library reads/writes them only from
  *     work enqueued on the caller's stream and never keeps them after that
- *     work completes.  No call allocates or frees device memory; scratch
- *     space comes from the caller's workspace `ws` of `ws_bytes` bytes (at
- *     least what the matching *_workspace_size call returns, 256-byte
- *     aligned).
+ *     work completes.  No call allocates or frees device memory except
+ *     ad_ml_sparsify and the ad_batch_* object; scratch space comes from the
+ *     caller's workspace `ws` of `ws_bytes` bytes (at least what the matching
+ *     *_workspace_size call returns, 256-byte aligned).
  *   - Calls only enqueue work on `stream` and return, except where a call
  *     says it synchronises.
  *   - Errors: host-side argument checks return AD_ERR_INVALID_ARG,
@@ -371,23 +376,45 @@ typedef struct {
     ad_dtype store;           /* AD_F64 or AD_F32: relaxation and distances           */
     int32_t levels;           /* at most this many levels, 1..64 (1 = SparsifyB only) */
     int64_t n_min;            /* a graph with n <= n_min is not coarsened            */
-    const double *e_host;     /* HOST [levels]: SparsifyB exponent of every level     */
+    const double *e_host;     /* HOST [levels]: the per-level ratio vector, COARSEST
+                                 level first (entry t for the level t steps finer than
+                                 the coarsest one reached); every entry <= 1; a
+                                 negative entry: no SparsifyB at that level          */
     double eps, theta;        /* strength and coupling of ad_ml_aggregate            */
     uint64_t bin_seed;        /* Philox key word 0 of SparsifyB's vertex keys         */
+    int32_t fit;              /* 0: entries are SparsifyB exponents e in [0, 1];
+                                 1: entries are the fractions of each level's edges
+                                 SparsifyB keeps (e fitted as in ad_sparsify_binned) */
+    int32_t span;             /* > 0: e_host is ignored and the vector is
+                                 ad_ml_level_span(levels reached, span, segment,
+                                 span_value)                                       */
+    int32_t segment;          /* 0 coarsest, 1 middle, 2 finest third of the levels  */
+    double span_value;        /* the entry the level-span rule gives, <= 1           */
 } ad_ml_opts;
+
+/* Host helper: the level-span ratio vector of Section 6 (implementation
+ * paragraph) over n_levels levels (1..64), coarsest first: the levels split
+ * into thirds, third s holding entries floor(s n / 3) .. floor((s+1) n / 3) - 1;
+ * the first `span` entries of third `segment` (0 coarsest, 1 middle, 2
+ * finest) are `value`, all others -1.  out_host: HOST [n_levels]. */
+ad_status ad_ml_level_span(int32_t n_levels, int32_t span, int32_t segment, double value,
+                           double *out_host);
 
 /* Algorithm 6 (MLSparsify).  Level 0 is g.  At level l: distances by
  * ad_relax + ad_edge_dist (graph id graph_id + l); if n <= n_min, or
  * l == levels - 1, or the graph has no edges, or ad_ml_aggregate would keep
- * more than 90% of the vertices, SparsifyB (ad_sparsify_binned, exponent
- * e_host[l], graph id graph_id + l) selects and the recursion ends.
+ * more than 90% of the vertices, level l is the coarsest (D = l): SparsifyB
+ * (ad_sparsify_binned, graph id graph_id + D) selects with the vector's
+ * entry 0 and the recursion ends.
  * Otherwise the coarse graph P^T L P (aggregate pairs of the fine edges,
  * merged by ad_ingest with summed weights; a unit weight per edge when g is
  * unweighted; coarse vertices named by their seeds' orig_id) is sparsified
  * at level l + 1; every fine edge joining two aggregates inherits its coarse
  * edge's state, every edge inside an aggregate is kept; distances are then
  * recomputed on the fine graph less the dropped edges (ad_subgraph) and
- * SparsifyB selects among its edges: keep[e] = 1 for those.
+ * SparsifyB, with the vector's entry D - l, selects among its edges:
+ * keep[e] = 1 for those.  A negative entry leaves the inherited state (at the
+ * coarsest level: every edge) as the level's result.
  *   keep: DEVICE uint8 [m].  n_kept_host: HOST, sum(keep).  depth_host:
  *   HOST or NULL, the index of the coarsest level reached.
  * The call allocates the per-level graphs and buffers itself (their sizes

@@ -49,7 +49,9 @@ class ADMLOpts(ctypes.Structure):
     _fields_ = [("R", ctypes.c_int32), ("k", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("graph_id", ctypes.c_uint64), ("store", ctypes.c_int),
                 ("levels", ctypes.c_int32), ("n_min", ctypes.c_int64), ("e_host", ctypes.c_void_p),
-                ("eps", ctypes.c_double), ("theta", ctypes.c_double), ("bin_seed", ctypes.c_uint64)]
+                ("eps", ctypes.c_double), ("theta", ctypes.c_double), ("bin_seed", ctypes.c_uint64),
+                ("fit", ctypes.c_int32), ("span", ctypes.c_int32), ("segment", ctypes.c_int32),
+                ("span_value", ctypes.c_double)]
 
 
 class ADError(RuntimeError):
@@ -94,6 +96,7 @@ def _load_lib():
                                     ctypes.POINTER(ctypes.c_double), P, S, P]),
         "ad_ml_aggregate_workspace_size": (S, [G]),
         "ad_ml_aggregate": (st, [G, ctypes.c_int, P, f64, f64, P, P, ctypes.POINTER(i64), P, S, P]),
+        "ad_ml_level_span": (st, [i32, i32, i32, f64, P]),
         "ad_ml_sparsify": (st, [G, ctypes.POINTER(ADMLOpts), P, ctypes.POINTER(i64), ctypes.POINTER(i32), P]),
         "ad_sparsify_fit_both": (st, [G, ctypes.c_int, P, f64, P, P, P, P, P, S, P]),
         "ad_relax_backward_workspace_size": (S, [G, O]),
@@ -680,19 +683,32 @@ def ml_aggregate(dg: DeviceGraph, rho: torch.Tensor, eps: float = 1e-12, theta: 
     return agg[:dg.n], is_seed[:dg.n], nc.value
 
 
-def ml_sparsify(dg: DeviceGraph, R: int, k: int, e_levels, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
-                levels: int = 8, n_min: int = 1000, store: str = "f32", eps: float = 1e-12, theta: float = 0.5,
-                bin_seed: int = 0, keep: Optional[torch.Tensor] = None):
-    """Algorithm 6, MLSparsify (``ad_ml_sparsify``).  ``e_levels`` gives the
-    SparsifyB exponent of every level (its last value repeats).  Returns
-    (keep uint8 [m], n_kept, depth).  Synchronises the current stream."""
-    ev = [float(x) for x in np.atleast_1d(np.asarray(e_levels, dtype=np.float64))]
+def ml_level_span(n_levels: int, span: int, segment: int, value: float) -> np.ndarray:
+    """The level-span ratio vector (``ad_ml_level_span``), coarsest level first."""
+    out = (ctypes.c_double * max(1, n_levels))()
+    _check(lib.ad_ml_level_span(n_levels, span, segment, float(value), ctypes.cast(out, ctypes.c_void_p)))
+    return np.array(out[:n_levels], dtype=np.float64)
+
+
+def ml_sparsify(dg: DeviceGraph, R: int, k: int, e_levels=None, omega: float = 0.5, seed: int = 0,
+                graph_id: int = 0, levels: int = 8, n_min: int = 1000, store: str = "f32", eps: float = 1e-12,
+                theta: float = 0.5, bin_seed: int = 0, fit: bool = False, span: int = 0, segment: int = 0,
+                span_value: float = 0.3, keep: Optional[torch.Tensor] = None):
+    """Algorithm 6, MLSparsify (``ad_ml_sparsify``).  ``e_levels``: the
+    per-level ratio vector, coarsest level first (a shorter list repeats its
+    last value; a negative entry skips SparsifyB at that level); exponents,
+    or retention targets with ``fit``.  ``span > 0`` uses the level-span
+    vector of the levels reached instead.  Returns (keep uint8 [m], n_kept,
+    depth).  Synchronises the current stream."""
+    ev = [float(x) for x in np.atleast_1d(np.asarray(e_levels if e_levels is not None else [0.0],
+                                                     dtype=np.float64))]
     ev = (ev + [ev[-1]] * max(0, levels - len(ev)))[:max(levels, 1)]
     e_arr = (ctypes.c_double * len(ev))(*ev)
     o = ADMLOpts(R=R, k=k, omega=omega, seed=int(seed) & (2 ** 64 - 1), graph_id=int(graph_id) & (2 ** 64 - 1),
                  store=_DTYPES[store], levels=levels, n_min=n_min,
                  e_host=ctypes.cast(e_arr, ctypes.c_void_p).value, eps=eps, theta=theta,
-                 bin_seed=int(bin_seed) & (2 ** 64 - 1))
+                 bin_seed=int(bin_seed) & (2 ** 64 - 1), fit=int(fit), span=span, segment=segment,
+                 span_value=span_value)
     g = dg.abi()
     if keep is None:
         keep = torch.empty(max(1, dg.m), dtype=torch.uint8, device=dg.row_ptr.device)

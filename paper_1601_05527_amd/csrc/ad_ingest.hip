@@ -11,11 +11,14 @@
 // order breaks ties by listed id, and orig_id names the listed vertex.
 //
 // The pipeline: canonical 64-bit pair keys, a stable radix sort (rocPRIM) of
-// (key, list index), run heads and their scan (edge ids), one thread per run
-// summing its weights in list order; for the degree order a sort of (degree,
-// id) vertex keys and a second pair sort under the new labels; then per-row
-// counts, their scans and the placement of the upper entries (edge order)
-// and of the lower entries (a stable sort of the edges by larger endpoint).
+// (key, list index), run heads and their scan (edge ids), run bounds, and
+// the weights of every run summed in list order (one thread per short run,
+// one wave per long run, the same double additions in the same order); for
+// the degree order a sort of (degree, id) vertex keys and a second pair sort
+// under the new labels; then per-row counts from the run lengths of the
+// sorted endpoints (no atomics, so hub vertices cost nothing extra), their
+// scans and the placement of the upper entries (edge order) and of the
+// lower entries (a stable sort of the edges by larger endpoint).
 #include "ad_internal.h"
 
 #include <cstring>    // before rocPRIM: its host code calls memset
@@ -61,34 +64,99 @@ __global__ void k_run_heads(int64_t count, const unsigned long long *__restrict_
         head[q] = (key[q] != NO_PAIR && (q == 0 || key[q] != key[q - 1])) ? 1u : 0u;
 }
 
-// One thread per run: the edge's endpoints and its weight, the run's listed
-// weights summed in list order (the sort is stable) in double.
-__global__ void k_merge_runs(int64_t count, const unsigned long long *__restrict__ key,
-                             const uint32_t *__restrict__ idx, const uint32_t *__restrict__ head,
-                             const uint32_t *__restrict__ edge_of, const float *__restrict__ w,
-                             int32_t *__restrict__ ea, int32_t *__restrict__ eb, float *__restrict__ ew) {
+// Bounds [start, end) of every run of equal pair keys, by edge id (edge_of
+// is the exclusive scan of the run heads).
+__global__ void k_run_bounds(int64_t count, const unsigned long long *__restrict__ key,
+                             const uint32_t *__restrict__ head, const uint32_t *__restrict__ edge_of,
+                             uint2 *__restrict__ bounds) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
-        if (!head[q]) continue;
         const unsigned long long k = key[q];
-        const uint32_t e = edge_of[q];
-        ea[e] = (int32_t)(k >> 32);
-        eb[e] = (int32_t)(k & 0xffffffffull);
-        if (w) {
-            double sum = 0.0;
-            for (int64_t r = q; r < count && key[r] == k; ++r) sum += (double)w[idx[r]];
-            ew[e] = (float)sum;
-        }
+        if (k == NO_PAIR) continue;
+        const uint32_t e = head[q] ? edge_of[q] : edge_of[q] - 1u;
+        if (head[q]) bounds[e].x = (uint32_t)q;
+        if (q + 1 == count || key[q + 1] != k) bounds[e].y = (uint32_t)(q + 1);
     }
 }
 
-__global__ void k_edge_degrees(int64_t m, const int32_t *__restrict__ ea, const int32_t *__restrict__ eb,
-                               uint32_t *__restrict__ deg, uint32_t *__restrict__ lower_cnt,
-                               uint32_t *__restrict__ upper_cnt) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-        atomicAdd(&deg[ea[e]], 1u);
-        atomicAdd(&deg[eb[e]], 1u);
-        if (lower_cnt) atomicAdd(&lower_cnt[eb[e]], 1u);
-        if (upper_cnt) atomicAdd(&upper_cnt[ea[e]], 1u);
+constexpr uint32_t MERGE_SHORT = 16;     // runs up to this length are summed by one thread
+
+// One thread per run: the edge's endpoints and, for a short run, its weight:
+// the listed weights summed in list order (the sort is stable) in double.
+// Longer runs go to a list for k_merge_long.
+__global__ void k_merge_runs(int64_t m, const uint2 *__restrict__ bounds, const unsigned long long *__restrict__ key,
+                             const uint32_t *__restrict__ idx, const float *__restrict__ w, int32_t *__restrict__ ea,
+                             int32_t *__restrict__ eb, float *__restrict__ ew, uint32_t *__restrict__ long_list,
+                             unsigned int *__restrict__ long_count) {
+    // the loop bound is uniform per wave (blocks are whole waves), so every
+    // lane reaches the wave-wide append
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t m_pad = ceil_div_dev(m, stride) * stride;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m_pad; e += stride) {
+        bool defer = false;
+        if (e < m) {
+            const uint2 b = bounds[e];
+            const unsigned long long k = key[b.x];
+            ea[e] = (int32_t)(k >> 32);
+            eb[e] = (int32_t)(k & 0xffffffffull);
+            if (w) {
+                if (b.y - b.x <= MERGE_SHORT) {
+                    double sum = 0.0;
+                    for (uint32_t r = b.x; r < b.y; ++r) sum += (double)w[idx[r]];
+                    ew[e] = (float)sum;
+                } else {
+                    defer = true;
+                }
+            }
+        }
+        const unsigned int at = wave_append(defer, long_count);
+        if (defer) long_list[at] = (uint32_t)e;
+    }
+}
+
+// One wave per long run: the lanes load 64 weights at a time and the wave
+// adds them in list order, so the double sum is the one-thread sum.
+__global__ __launch_bounds__(IBLOCK) void k_merge_long(const unsigned int *__restrict__ long_count,
+                                                       const uint32_t *__restrict__ long_list,
+                                                       const uint2 *__restrict__ bounds,
+                                                       const uint32_t *__restrict__ idx, const float *__restrict__ w,
+                                                       float *__restrict__ ew) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (IBLOCK / WAVE);
+    const int64_t count = *long_count;
+    for (int64_t q = (int64_t)blockIdx.x * (IBLOCK / WAVE) + (threadIdx.x >> 6); q < count; q += nw) {
+        const uint32_t e = long_list[q];
+        const uint2 b = bounds[e];
+        double sum = 0.0;
+        for (uint32_t base = b.x; base < b.y; base += WAVE) {
+            const uint32_t r = base + (uint32_t)lane;
+            const float v = r < b.y ? w[idx[r]] : 0.0f;
+            const uint32_t cnt = min((uint32_t)WAVE, b.y - base);
+            const int bits = __float_as_int(v);
+            for (uint32_t j = 0; j < cnt; ++j)
+                sum += (double)__int_as_float(__builtin_amdgcn_readlane(bits, (int)j));
+        }
+        if (lane == 0) ew[e] = (float)sum;
+    }
+}
+
+// Run ends of a sorted key array: start[k] = first position, cnt[k] = end
+// (both zero beforehand); k_count_finish turns them into counts.
+__global__ void k_count_marks(int64_t m, const int32_t *__restrict__ keys, uint32_t *__restrict__ start,
+                              uint32_t *__restrict__ cnt) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = keys[t];
+        if (t == 0 || keys[t - 1] != k) start[k] = (uint32_t)t;
+        if (t + 1 == m || keys[t + 1] != k) cnt[k] = (uint32_t)(t + 1);
+    }
+}
+
+// cnt[i] -= start[i]; deg[i] = cnt[i] + other[i] when deg is given.
+__global__ void k_count_finish(int64_t n, const uint32_t *__restrict__ start, uint32_t *__restrict__ cnt,
+                               const uint32_t *__restrict__ other, uint32_t *__restrict__ deg) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = cnt[i] - start[i];
+        cnt[i] = c;
+        if (deg) deg[i] = c + other[i];
     }
 }
 
@@ -266,6 +334,36 @@ static unsigned igrid(int64_t count) { return grid_for(std::max<int64_t>(1, coun
         if (e_ != hipSuccess) return fail(AD_ERR_HIP, std::string("rocPRIM: ") + hipGetErrorString(e_)); \
     } while (0)
 
+// Degrees of the m edges (ea < eb, sorted by (ea, eb)) without atomics:
+// upper_cnt from the runs of ea, lower_cnt from the runs of eb after a
+// stable sort of the edge ids by eb (left in idx1 / edge_of for the lower
+// placement), deg = upper + lower.  deg, upper_cnt, lower_cnt: [n];
+// vid0 / vid1 serve as scratch.
+static ad_status edge_counts(int64_t n, int64_t m, const int32_t *ea, const int32_t *eb, const IngestLayout &L,
+                             hipStream_t st) {
+    ad_status s;
+    for (uint32_t *p : {L.upper_cnt, L.lower_cnt, L.vid0, L.vid1}) {
+        s = fill_i32((int32_t *)p, 0, n, st);
+        if (s != AD_OK) return s;
+    }
+    hipLaunchKernelGGL(k_count_marks, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, L.vid0, L.upper_cnt);
+    AD_LAUNCH_CHECK("k_count_marks");
+    hipLaunchKernelGGL(k_edge_b, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, eb, L.idx0, L.head);
+    AD_LAUNCH_CHECK("k_edge_b");
+    size_t tb = L.temp_bytes;
+    AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.idx0, L.idx1, L.head, L.edge_of, (size_t)m, 0, bits_for(n), st));
+    hipLaunchKernelGGL(k_count_marks, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, (const int32_t *)L.idx1, L.vid1,
+                       L.lower_cnt);
+    AD_LAUNCH_CHECK("k_count_marks");
+    hipLaunchKernelGGL(k_count_finish, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.vid0, L.upper_cnt,
+                       (const uint32_t *)nullptr, (uint32_t *)nullptr);
+    AD_LAUNCH_CHECK("k_count_finish");
+    hipLaunchKernelGGL(k_count_finish, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.vid1, L.lower_cnt, L.upper_cnt,
+                       L.deg);
+    AD_LAUNCH_CHECK("k_count_finish");
+    return AD_OK;
+}
+
 static ad_status ingest_impl(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v, const float *w,
                              const int32_t *orig_in, int32_t order, int64_t *row_ptr, int32_t *col, float *w_out,
                              int32_t *eid, int32_t *orig_out, int64_t *m_host, int32_t *d_max_host,
@@ -293,19 +391,31 @@ static ad_status ingest_impl(int64_t n, int64_t m_in, const int32_t *u, const in
         AD_HIP(hipStreamSynchronize(st));
         if (hflags[0]) return fail(AD_ERR_GRAPH, "edge list names a vertex outside [0, n)");
         m = (int64_t)last[0] + (int64_t)last[1];
-        hipLaunchKernelGGL(k_merge_runs, dim3(igrid(m_in)), dim3(IBLOCK), 0, st, m_in, L.key1, L.idx1, L.head,
-                           L.edge_of, w, L.ea, L.eb, L.ew);
-        AD_LAUNCH_CHECK("k_merge_runs");
+        if (m > 0) {
+            // run bounds in key0 (free after the sort), long runs listed in idx0
+            uint2 *bounds = reinterpret_cast<uint2 *>(L.key0);
+            hipLaunchKernelGGL(k_run_bounds, dim3(igrid(m_in)), dim3(IBLOCK), 0, st, m_in, L.key1, L.head, L.edge_of,
+                               bounds);
+            AD_LAUNCH_CHECK("k_run_bounds");
+            hipLaunchKernelGGL(k_merge_runs, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, bounds, L.key1, L.idx1, w, L.ea,
+                               L.eb, L.ew, L.idx0, L.flags + 3);
+            AD_LAUNCH_CHECK("k_merge_runs");
+            if (w) {
+                hipLaunchKernelGGL(k_merge_long, dim3(1024), dim3(IBLOCK), 0, st, L.flags + 3, L.idx0, bounds, L.idx1,
+                                   w, L.ew);
+                AD_LAUNCH_CHECK("k_merge_long");
+            }
+        }
     }
     const int32_t *ea = L.ea, *eb = L.eb;
     const float *ew = L.ew;
-    s = fill_i32((int32_t *)L.deg, 0, std::max<int64_t>(1, n), st);
-    if (s != AD_OK) return s;
     if (order == 1 && n > 0) {
+        s = fill_i32((int32_t *)L.deg, 0, n, st);
+        if (s != AD_OK) return s;
         if (m > 0) {
-            hipLaunchKernelGGL(k_edge_degrees, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, L.deg,
-                               (uint32_t *)nullptr, (uint32_t *)nullptr);
-            AD_LAUNCH_CHECK("k_edge_degrees");
+            // degrees before relabelling: run lengths of the sorted smaller and larger endpoints
+            s = edge_counts(n, m, ea, eb, L, st);
+            if (s != AD_OK) return s;
         }
         hipLaunchKernelGGL(k_vertex_keys, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.deg, L.vkey0, L.vid0);
         AD_LAUNCH_CHECK("k_vertex_keys");
@@ -324,22 +434,24 @@ static ad_status ingest_impl(int64_t n, int64_t m_in, const int32_t *u, const in
             AD_LAUNCH_CHECK("k_unpack_edges");
             ew = L.ew2;
         }
-        s = fill_i32((int32_t *)L.deg, 0, n, st);
-        if (s != AD_OK) return s;
     } else if (n > 0) {
         hipLaunchKernelGGL(k_orig_identity, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, orig_in, orig_out);
         AD_LAUNCH_CHECK("k_orig_identity");
     }
-    // per-row counts under the final labels, and their scans
+    // per-row counts under the final labels (upper_cnt: edges whose smaller
+    // endpoint is the row, lower_cnt: larger), the edges sorted by larger
+    // endpoint (idx1 / edge_of), and the degrees
     if (n > 0) {
-        s = fill_i32((int32_t *)L.lower_cnt, 0, n, st);
-        if (s != AD_OK) return s;
-        s = fill_i32((int32_t *)L.upper_cnt, 0, n, st);
+        s = fill_i32((int32_t *)L.deg, 0, n, st);
         if (s != AD_OK) return s;
         if (m > 0) {
-            hipLaunchKernelGGL(k_edge_degrees, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, L.deg, L.lower_cnt,
-                               L.upper_cnt);
-            AD_LAUNCH_CHECK("k_edge_degrees");
+            s = edge_counts(n, m, ea, eb, L, st);
+            if (s != AD_OK) return s;
+        } else {
+            s = fill_i32((int32_t *)L.lower_cnt, 0, n, st);
+            if (s != AD_OK) return s;
+            s = fill_i32((int32_t *)L.upper_cnt, 0, n, st);
+            if (s != AD_OK) return s;
         }
         hipLaunchKernelGGL(k_degree_max, dim3(std::min<unsigned>(1024, igrid(n))), dim3(IBLOCK), 0, st, n, L.deg,
                            L.flags + 1);
@@ -369,12 +481,7 @@ static ad_status ingest_impl(int64_t n, int64_t m_in, const int32_t *u, const in
         hipLaunchKernelGGL(k_place_upper, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, ew, row_ptr, L.lower_cnt,
                            L.upper_start, col, w ? w_out : (float *)nullptr, eid);
         AD_LAUNCH_CHECK("k_place_upper");
-        // lower entries: the edges sorted (stably) by their larger endpoint
-        hipLaunchKernelGGL(k_edge_b, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, eb, L.idx0, L.head);
-        AD_LAUNCH_CHECK("k_edge_b");
-        tb = L.temp_bytes;
-        AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.idx0, L.idx1, L.head, L.edge_of, (size_t)m, 0, bits_for(n),
-                                        st));
+        // lower entries from the edges sorted (stably) by their larger endpoint
         hipLaunchKernelGGL(k_place_lower, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, L.idx1, L.edge_of, ea, ew, row_ptr,
                            L.lower_start, col, w ? w_out : (float *)nullptr, eid);
         AD_LAUNCH_CHECK("k_place_lower");

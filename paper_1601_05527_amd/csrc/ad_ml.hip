@@ -22,8 +22,18 @@
 //     edges), coarse vertices named by their seeds;
 //   - a level is the coarsest at n <= n_min, at level levels - 1, with no
 //     edges, or when coarsening would keep more than 90% of the vertices;
-//   - level l uses graph id graph_id + l (test vectors and bin order) and
-//     exponent e[l] for SparsifyB (ad_sparsify_binned);
+//   - level l uses graph id graph_id + l (test vectors and bin order);
+//   - the per-level ratio vector (Section 6, implementation paragraph) lists
+//     the levels from the coarsest one reached: with D the index of the
+//     coarsest level, level l takes entry D - l.  A negative entry means no
+//     SparsifyB at that level (it keeps what it inherits; the coarsest level
+//     keeps all its edges); otherwise the entry is SparsifyB's exponent, or
+//     with `fit` the fraction of the level's edges to keep (e fitted as in
+//     ad_sparsify_binned);
+//   - level-span: the D + 1 levels split into thirds (coarsest, middle,
+//     finest), third s holding entries floor(s (D+1) / 3) .. floor((s+1)
+//     (D+1) / 3) - 1; the first `span` entries of the chosen third take the
+//     value, all others -1;
 //   - uncoarsening: an edge between two aggregates keeps its coarse edge's
 //     state, an edge inside an aggregate is kept; distances are recomputed
 //     on the fine graph less the dropped edges (ad_subgraph) and SparsifyB
@@ -397,15 +407,33 @@ static ad_status ml_distances(const ad_graph *g, const ad_ml_opts *o, int l, Dev
     return AD_OK;
 }
 
-static ad_status ml_binned(const ad_graph *g, const ad_ml_opts *o, int l, const void *rho, uint8_t *keep,
+static void level_span(int32_t n_levels, int32_t span, int32_t segment, double value, double *out) {
+    const int32_t lo = segment * n_levels / 3, hi = (segment + 1) * n_levels / 3;
+    for (int32_t t = 0; t < n_levels; ++t) out[t] = (t >= lo && t < hi && t - lo < span) ? value : -1.0;
+}
+
+// The ratio-vector entry of level l when the coarsest level is D.
+static double ml_entry(const ad_ml_opts *o, int32_t D, int32_t l) {
+    if (o->span > 0) {
+        std::vector<double> v((size_t)D + 1);
+        level_span(D + 1, o->span, o->segment, o->span_value, v.data());
+        return v[(size_t)(D - l)];
+    }
+    return o->e_host[D - l];
+}
+
+// SparsifyB of one level with its entry x (x < 0: keep every edge).
+static ad_status ml_binned(const ad_graph *g, const ad_ml_opts *o, int l, double x, const void *rho, uint8_t *keep,
                            hipStream_t st) {
+    if (x < 0.0) return fill_u8(keep, 1, g->m, st);
     DevMem ws, nk;
     const size_t wb = ad_sparsify_binned_workspace_size(g);
     if (wb == 0) return fail(AD_ERR_INTERNAL, "binned workspace size");
     ML_TRY(dev_alloc(ws, wb));
     ML_TRY(dev_alloc(nk, sizeof(int64_t)));
-    return ad_sparsify_binned(g, o->store, rho, o->bin_seed, o->graph_id + (uint64_t)l, o->e_host[l], 0.0, keep,
-                              nk.get<int64_t>(), nullptr, ws.p, wb, st);
+    double e_used = 0.0;
+    return ad_sparsify_binned(g, o->store, rho, o->bin_seed, o->graph_id + (uint64_t)l, o->fit ? 0.0 : x,
+                              o->fit ? x : 0.0, keep, nk.get<int64_t>(), &e_used, ws.p, wb, st);
 }
 
 // keep [g->m] for the graph at level l.
@@ -429,7 +457,7 @@ static ad_status ml_level(const ad_graph *g, const ad_ml_opts *o, int l, uint8_t
         if ((double)nc > 0.9 * (double)n) coarsest = true;
     }
     if (coarsest) {
-        ML_TRY(ml_binned(g, o, l, rho.p, keep, st));
+        ML_TRY(ml_binned(g, o, l, ml_entry(o, l, l), rho.p, keep, st));
         AD_HIP(hipStreamSynchronize(st));
         return AD_OK;
     }
@@ -484,6 +512,12 @@ static ad_status ml_level(const ad_graph *g, const ad_ml_opts *o, int l, uint8_t
                        cv.get<const int32_t>(), crp.get<const int64_t>(), ccol.get<const int32_t>(),
                        ceid.get<const int32_t>(), ckeep.get<const uint8_t>(), inh.get<uint8_t>());
     AD_LAUNCH_CHECK("k_ml_inherit");
+    const double x = ml_entry(o, *depth, l);
+    if (x < 0.0) {          // no SparsifyB here: the inherited state is the result
+        AD_HIP(hipMemcpyAsync(keep, inh.p, (size_t)m, hipMemcpyDeviceToDevice, st));
+        AD_HIP(hipStreamSynchronize(st));
+        return AD_OK;
+    }
     DevMem srp, scol, sw, seid, soe, wss, dmx;
     ML_TRY(dev_alloc(srp, (size_t)(n + 1) * sizeof(int64_t)));
     ML_TRY(dev_alloc(scol, (size_t)2 * m * sizeof(int32_t)));
@@ -519,7 +553,7 @@ static ad_status ml_level(const ad_graph *g, const ad_ml_opts *o, int l, uint8_t
         DevMem srho, skeep;
         ML_TRY(ml_distances(&sg, o, l, srho, st));
         ML_TRY(dev_alloc(skeep, (size_t)ms));
-        ML_TRY(ml_binned(&sg, o, l, srho.p, skeep.get<uint8_t>(), st));
+        ML_TRY(ml_binned(&sg, o, l, x, srho.p, skeep.get<uint8_t>(), st));
         hipLaunchKernelGGL(k_ml_map_back, dim3(mgrid(2 * ms)), dim3(MBLOCK), 0, st, 2 * ms, seid.get<const int32_t>(),
                            soe.get<const int32_t>(), skeep.get<const uint8_t>(), keep);
         AD_LAUNCH_CHECK("k_ml_map_back");
@@ -532,6 +566,15 @@ static ad_status ml_level(const ad_graph *g, const ad_ml_opts *o, int l, uint8_t
 }  // namespace ad
 
 using namespace ad;
+
+extern "C" ad_status ad_ml_level_span(int32_t n_levels, int32_t span, int32_t segment, double value,
+                                      double *out_host) {
+    if (n_levels < 1 || n_levels > 64) return fail(AD_ERR_INVALID_ARG, "n_levels must be in [1, 64]");
+    if (span < 0 || segment < 0 || segment > 2) return fail(AD_ERR_INVALID_ARG, "span >= 0, segment in 0..2");
+    if (!out_host) return fail(AD_ERR_INVALID_ARG, "out_host is NULL");
+    level_span(n_levels, span, segment, value, out_host);
+    return AD_OK;
+}
 
 extern "C" size_t ad_ml_aggregate_workspace_size(const ad_graph *g) {
     if (!g || g->n < 0 || g->n >= ((int64_t)1 << 31)) return 0;
@@ -572,9 +615,16 @@ extern "C" ad_status ad_ml_sparsify(const ad_graph *g, const ad_ml_opts *o, uint
     if (o->store != AD_F32 && o->store != AD_F64) return fail(AD_ERR_INVALID_ARG, "store must be F32 or F64");
     if (o->levels < 1 || o->levels > 64) return fail(AD_ERR_INVALID_ARG, "levels must be in [1, 64]");
     if (o->n_min < 0) return fail(AD_ERR_INVALID_ARG, "n_min must be >= 0");
-    if (!o->e_host) return fail(AD_ERR_INVALID_ARG, "e_host is NULL");
-    for (int l = 0; l < o->levels; ++l)
-        if (!(o->e_host[l] >= 0.0 && o->e_host[l] <= 1.0)) return fail(AD_ERR_INVALID_ARG, "e must be in [0, 1]");
+    if (o->fit != 0 && o->fit != 1) return fail(AD_ERR_INVALID_ARG, "fit must be 0 or 1");
+    if (o->span > 0) {
+        if (o->segment < 0 || o->segment > 2) return fail(AD_ERR_INVALID_ARG, "segment must be 0, 1 or 2");
+        if (!(o->span_value <= 1.0)) return fail(AD_ERR_INVALID_ARG, "span_value must be <= 1");
+    } else {
+        if (o->span < 0) return fail(AD_ERR_INVALID_ARG, "span must be >= 0");
+        if (!o->e_host) return fail(AD_ERR_INVALID_ARG, "e_host is NULL");
+        for (int l = 0; l < o->levels; ++l)
+            if (!(o->e_host[l] <= 1.0)) return fail(AD_ERR_INVALID_ARG, "ratio entries must be <= 1 (not NaN)");
+    }
     if (!(o->eps >= 0.0) || !(o->theta >= 0.0 && o->theta <= 1.0))
         return fail(AD_ERR_INVALID_ARG, "eps must be >= 0 and theta in [0, 1]");
     if (g->m > 0 && !keep) return fail(AD_ERR_INVALID_ARG, "keep is NULL");

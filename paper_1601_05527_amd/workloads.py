@@ -8,7 +8,9 @@ None of the method's arithmetic lives here: these are input recipes only
   CHUNG_LU   one power-law graph, n = 2^20, 16,000,000 edges, degree exponent
              2.1, lognormal(0, 1) weights; R = 16, k = 20, FP32; LOCAL and
              GLOBAL selection fitted to 30% retention; the selection with
-             binning (Algorithm 4) fitted to the same retention.
+             binning (Algorithm 4) fitted to the same retention; the
+             multilevel cycle (Algorithm 6) with at most 9 levels, n_min
+             1000, level-span 3 on the finest third, 30% per level.
   BATCH      512 Chung-Lu graphs, n log-uniform in [1e3, 2e5], average degree
              2m/n uniform in [8, 32], lognormal weights; R = 8, k = 20, FP32,
              LOCAL selection at e = 0.5, one captured launch sequence.
@@ -31,7 +33,7 @@ from . import graphs
 OMEGA = 0.5
 
 CHUNG_LU = dict(n=1 << 20, m=16_000_000, gamma=2.1, seed=2024, R=16, k=20, seed_vec=1, target=0.3,
-                bin_seed=17)
+                bin_seed=17, ml_levels=9, ml_n_min=1000, ml_span=3)
 BATCH = dict(G=512, n_lo=1e3, n_hi=2e5, deg_lo=8.0, deg_hi=32.0, seed=3, R=8, k=20, seed_vec=7,
              graph_id=0, e=0.5)
 RMAT = dict(scale=24, m=1 << 28, seed=11, R=16, k=30, seed_vec=5, fp32_tail=8, target=0.3)

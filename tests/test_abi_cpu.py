@@ -282,7 +282,8 @@ def test_multilevel_calls_reject_bad_arguments():
 
     for bad in [dict(R=0), dict(R=65), dict(k=-1), dict(omega=0.0), dict(omega=1.5), dict(store=2),
                 dict(levels=0), dict(levels=65), dict(n_min=-1), dict(e_host=None), dict(eps=-1.0),
-                dict(theta=2.0)]:
+                dict(theta=2.0), dict(fit=2), dict(span=-1), dict(span=1, segment=3), dict(span=1, segment=-1),
+                dict(span=1, span_value=1.5), dict(span=1, span_value=float("nan"))]:
         assert call(opts(**bad)) == 1, bad
     e[2] = 1.5
     assert call(opts()) == 1
@@ -291,3 +292,19 @@ def test_multilevel_calls_reject_bad_arguments():
     assert call(opts(), kh=False) == 1
     huge = api.ADGraph(4, 1 << 30, 0x1000, 0x2000, None, 0x3000, None, 3, None)
     assert L.ad_ml_sparsify(ctypes.byref(huge), ctypes.byref(opts()), p, ctypes.byref(kept), None, None) == 2
+
+
+def test_level_span_helper_matches_oracle():
+    import oracle
+    from paper_1601_05527_amd import api
+    for n in range(1, 13):
+        for span in range(0, 5):
+            for seg in range(3):
+                np.testing.assert_array_equal(api.ml_level_span(n, span, seg, 0.3),
+                                              oracle.ml_level_span(n, span, seg, 0.3))
+    out = (ctypes.c_double * 4)()
+    p = ctypes.cast(out, ctypes.c_void_p)
+    assert api.lib.ad_ml_level_span(0, 1, 0, 0.3, p) == 1
+    assert api.lib.ad_ml_level_span(4, 1, 3, 0.3, p) == 1
+    assert api.lib.ad_ml_level_span(4, -1, 0, 0.3, p) == 1
+    assert api.lib.ad_ml_level_span(4, 1, 0, 0.3, None) == 1

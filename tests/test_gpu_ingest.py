@@ -89,6 +89,32 @@ def test_ingest_long_runs_and_hubs(api):
         _compare(dg, oracle.ingest(n, u, v, w, order=1 if by_degree else 0))
 
 
+def test_ingest_run_lengths_at_the_wave_bounds(api):
+    """Runs of 1 .. 1000 repeats around the one-thread / one-wave split and
+    the 64-lane chunks, weights spread over many binades (so the order of
+    the double additions shows), listed in shuffled order; a hub that is
+    the larger endpoint of 30,000 edges and one that is the smaller."""
+    announce("ingest run lengths at wave bounds")
+    rng = np.random.default_rng(19)
+    n = 50_000
+    us, vs = [], []
+    for r, L in enumerate([1, 2, 15, 16, 17, 63, 64, 65, 127, 128, 129, 1000]):
+        us.append(np.full(L, 100 + r))
+        vs.append(np.full(L, 200 + r))
+    us.append(rng.integers(0, n - 1, 30_000))
+    vs.append(np.full(30_000, n - 1))
+    us.append(np.full(20_000, 5))
+    vs.append(rng.integers(6, n, 20_000))
+    u = np.concatenate(us).astype(np.int32)
+    v = np.concatenate(vs).astype(np.int32)
+    perm = rng.permutation(u.size)
+    u, v = u[perm], v[perm]
+    w = np.exp(rng.uniform(-20, 20, u.size)).astype(np.float32)
+    for by_degree in (False, True):
+        dg = _run(api, n, u, v, w, by_degree=by_degree)
+        _compare(dg, oracle.ingest(n, u, v, w, order=1 if by_degree else 0))
+
+
 def test_ingest_orig_ids_and_reuse(api):
     """Names pass through; the ingested graph relaxes exactly like the same
     CSR uploaded from the host."""

@@ -10,6 +10,9 @@ through the C ABI.
     relaxations agree to about 1e-12 (relative), far below the gaps the
     strength, aggregation and bin decisions compare, so on these seeded
     cases no decision flips;
+  - the per-level ratio vector (coarsest level first), negative entries
+    that skip a level, retention targets (fit) and the level-span rule,
+    against the oracle in FP64;
   - properties that hold at any size: one level is SparsifyB on the
     library's own distances, exponent 1 keeps every edge, an empty graph
     keeps nothing.
@@ -157,3 +160,29 @@ def test_small_and_empty_graphs(api):
     keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, [0.5], seed=1, levels=6, n_min=0, bin_seed=2)
     assert depth == depth_o and kept == kept_o
     np.testing.assert_array_equal(_np(keep), keep_o)
+
+
+@pytest.mark.parametrize("variant", ["skip_finest", "skip_coarsest", "fit", "span_coarsest", "span_middle",
+                                     "span_finest", "all_skipped"])
+def test_ratio_vector_variants_match_oracle(api, variant):
+    announce(f"ml sparsify ratio vector {variant}")
+    g = _graph("chung_lu")
+    dg = api.DeviceGraph.from_host(g, "cuda")
+    kw = dict(seed=5, graph_id=1, levels=4, n_min=200, bin_seed=13)
+    if variant == "skip_finest":
+        kw.update(e_levels=[0.5, 0.5, 0.6, -1])
+    elif variant == "skip_coarsest":
+        kw.update(e_levels=[-1, 0.4, 0.6, 0.7])
+    elif variant == "fit":
+        kw.update(e_levels=[0.5, -1, 0.35, 0.3], fit=True)
+    elif variant.startswith("span"):
+        kw.update(span=1, segment=["span_coarsest", "span_middle", "span_finest"].index(variant), span_value=0.4)
+    else:
+        kw.update(e_levels=[-1])
+    keep, kept, depth = api.ml_sparsify(dg, 8, 10, store="f64", **kw)
+    keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, **kw)
+    print(f"{variant}: kept {kept} of {g.m}, depth {depth}")
+    assert depth == depth_o and kept == kept_o
+    np.testing.assert_array_equal(_np(keep), keep_o)
+    if variant == "all_skipped":
+        assert kept == g.m

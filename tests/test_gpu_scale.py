@@ -135,6 +135,38 @@ def test_full_chung_lu_subgraph_and_components(api):
         assert pr["n_components"] == nc and np.array_equal(_np(pr["comp"]), comp)
 
 
+def test_full_chung_lu_multilevel(api):
+    """The multilevel cycle on the benchmark graph.  Seeds and aggregates of
+    the full graph from seeded synthetic distances equal the oracle's;
+    the cycle in the benchmark's configuration keeps a valid edge set, a
+    cycle whose levels all skip SparsifyB keeps every edge, and one level
+    is SparsifyB on the library's own distances."""
+    announce("full size Chung-Lu multilevel")
+    c = W.CHUNG_LU
+    _, g = W.chung_lu_graph("degree")
+    dg = api.DeviceGraph.from_host(g, "cuda", keep_host=False)
+    rho = np.random.default_rng(31).random(g.m).astype(np.float32)
+    agg, is_seed, nc = api.ml_aggregate(dg, torch.from_numpy(rho).cuda())
+    seeds_o = oracle.ml_seeds(g, rho.astype(np.float64))
+    agg_o, nc_o = oracle.ml_aggregates(g, rho.astype(np.float64), seeds_o)
+    _log(f"aggregates: {nc} of {g.n}")
+    assert nc == nc_o and np.array_equal(_np(is_seed), seeds_o) and np.array_equal(_np(agg), agg_o)
+    kw = dict(omega=W.OMEGA, seed=c["seed_vec"], levels=c["ml_levels"], n_min=c["ml_n_min"], store="f32",
+              bin_seed=c["bin_seed"])
+    keep, kept, depth = api.ml_sparsify(dg, c["R"], c["k"], fit=True, span=c["ml_span"], segment=2,
+                                        span_value=c["target"], **kw)
+    k = _np(keep)
+    _log(f"multilevel: kept {kept} of {g.m}, depth {depth}")
+    assert depth >= 2 and int(k.sum()) == kept and set(np.unique(k).tolist()) <= {0, 1}
+    assert 0.05 * g.m < kept < 0.6 * g.m
+    keep, kept, depth2 = api.ml_sparsify(dg, c["R"], c["k"], [-1.0], **kw)
+    assert kept == g.m and depth2 == depth
+    keep, kept, depth = api.ml_sparsify(dg, c["R"], c["k"], [0.5], **dict(kw, levels=1))
+    res = api.relax(dg, c["R"], c["k"], W.OMEGA, seed=c["seed_vec"])
+    kb, nb, _ = api.sparsify_binned(dg, api.edge_dist(dg, res.x, res.minmax), c["bin_seed"], e=0.5)
+    assert depth == 0 and kept == int(_np(nb)[0]) and torch.equal(keep, kb)
+
+
 @pytest.mark.timeout(900)
 def test_full_batch(api):
     announce("full size batch of 512 Chung-Lu graphs FP32")
