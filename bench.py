@@ -358,7 +358,8 @@ def run_chung_lu(args, api, torch, dev):
                "cores": cores, "kind": "oracle",
                "sample": (f"FP64 oracle (Algorithm 1 in the paper's order) on the same graph, all "
                           f"{R} vectors, {args.cpu_sweeps} of the {K} sweeps, then rescale and "
-                          f"distances; {t_cpu:.2f}s wall; selection not included")}
+                          f"distances; {t_cpu:.2f}s wall on {cores} threads (about {t_cpu * cores:.0f} "
+                          "core-seconds); selection not included")}
 
     config = {
         "workload": (f"Chung-Lu power-law graph n=2^20, m={c['m']}, gamma={c['gamma']}, "

@@ -113,8 +113,12 @@ __global__ void k_merge_runs(int64_t m, const uint2 *__restrict__ bounds, const 
     }
 }
 
-// One wave per long run: the lanes load 64 weights at a time and the wave
-// adds them in list order, so the double sum is the one-thread sum.
+// One wave per long run.  The lanes load the run's weights MERGE_GROUP
+// chunks of 64 at a time, the next group in flight while the wave adds the
+// current one in list order (each value broadcast from its lane), so the
+// double sum is the one-thread sum; only the chain of additions is serial.
+constexpr int MERGE_GROUP = 8;
+
 __global__ __launch_bounds__(IBLOCK) void k_merge_long(const unsigned int *__restrict__ long_count,
                                                        const uint32_t *__restrict__ long_list,
                                                        const uint2 *__restrict__ bounds,
@@ -127,13 +131,37 @@ __global__ __launch_bounds__(IBLOCK) void k_merge_long(const unsigned int *__res
         const uint32_t e = long_list[q];
         const uint2 b = bounds[e];
         double sum = 0.0;
-        for (uint32_t base = b.x; base < b.y; base += WAVE) {
-            const uint32_t r = base + (uint32_t)lane;
-            const float v = r < b.y ? w[idx[r]] : 0.0f;
-            const uint32_t cnt = min((uint32_t)WAVE, b.y - base);
-            const int bits = __float_as_int(v);
-            for (uint32_t j = 0; j < cnt; ++j)
-                sum += (double)__int_as_float(__builtin_amdgcn_readlane(bits, (int)j));
+        int cur[MERGE_GROUP], nxt[MERGE_GROUP];
+#pragma unroll
+        for (int c = 0; c < MERGE_GROUP; ++c) {
+            const uint32_t r = b.x + (uint32_t)(c * WAVE + lane);
+            cur[c] = r < b.y ? __float_as_int(w[idx[r]]) : 0;
+        }
+        for (uint32_t base = b.x; base < b.y; base += MERGE_GROUP * WAVE) {
+            const uint32_t nbase = base + MERGE_GROUP * WAVE;
+#pragma unroll
+            for (int c = 0; c < MERGE_GROUP; ++c) {
+                const uint32_t r = nbase + (uint32_t)(c * WAVE + lane);
+                nxt[c] = r < b.y ? __float_as_int(w[idx[r]]) : 0;
+            }
+            const uint32_t left = b.y - base;
+            if (left >= (uint32_t)(MERGE_GROUP * WAVE)) {
+#pragma unroll
+                for (int c = 0; c < MERGE_GROUP; ++c) {
+#pragma unroll
+                    for (int j = 0; j < WAVE; ++j)
+                        sum += (double)__int_as_float(__builtin_amdgcn_readlane(cur[c], j));
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < MERGE_GROUP; ++c) {
+                    const uint32_t cnt = left > (uint32_t)(c * WAVE) ? min((uint32_t)WAVE, left - c * WAVE) : 0u;
+                    for (uint32_t j = 0; j < cnt; ++j)
+                        sum += (double)__int_as_float(__builtin_amdgcn_readlane(cur[c], (int)j));
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < MERGE_GROUP; ++c) cur[c] = nxt[c];
         }
         if (lane == 0) ew[e] = (float)sum;
     }

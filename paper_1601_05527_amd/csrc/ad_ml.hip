@@ -100,41 +100,71 @@ __global__ __launch_bounds__(MBLOCK) void k_ml_smax(int64_t n, const int64_t *__
     }
 }
 
-// One round of the seed traversal over the undecided vertices (state 0;
-// 1 = seed, 2 = not a seed); adds the vertices still undecided to *left.
+// Coupling of every stored entry (i, j): 0 not strong, 1 strong with j
+// after i in the traversal, 2 strong with j ahead of i.
 template <typename Tr>
+__global__ __launch_bounds__(MBLOCK) void k_ml_strong(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
+                                                      const int32_t *__restrict__ orig_id, const Tr *__restrict__ rho,
+                                                      double eps, double theta, const double *__restrict__ smax,
+                                                      uint8_t *__restrict__ sflag) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (MBLOCK / WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (MBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        const int64_t b0 = row_ptr[i], b1 = row_ptr[i + 1];
+        const int32_t ki = orig_id ? orig_id[i] : (int32_t)i;
+        const double si = theta * smax[i];
+        for (int64_t p = b0 + lane; p < b1; p += WAVE) {
+            const int32_t j = col[p];
+            const double d = ml_strength(rho[eid[p]], eps);
+            uint8_t f = 0;
+            if (d >= si || d >= theta * smax[j])
+                f = ml_ahead(b1 - b0, ki, row_ptr[j + 1] - row_ptr[j], orig_id ? orig_id[j] : j) ? 2 : 1;
+            sflag[p] = f;
+        }
+    }
+}
+
+// One round of the seed traversal over the undecided vertices (state 0;
+// 1 = seed, 2 = not a seed): a vertex with a strongly coupled seed is not a
+// seed; one whose strongly coupled vertices ahead of it are all decided
+// becomes a seed; the others wait and are counted in *left.
 __global__ __launch_bounds__(MBLOCK) void k_ml_seed_round(int64_t n, const int64_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
-                                                          const int32_t *__restrict__ eid,
-                                                          const int32_t *__restrict__ orig_id,
-                                                          const Tr *__restrict__ rho, double eps, double theta,
-                                                          const double *__restrict__ smax, uint8_t *__restrict__ state,
+                                                          const uint8_t *__restrict__ sflag,
+                                                          uint8_t *__restrict__ state,
                                                           unsigned long long *__restrict__ left) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = (int64_t)gridDim.x * (MBLOCK / WAVE);
     unsigned long long waiting = 0;
-    for (int64_t i = (int64_t)blockIdx.x * (MBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
-        if (state[i] != 0) continue;
-        const int64_t b0 = row_ptr[i], b1 = row_ptr[i + 1];
-        const int32_t ki = orig_id ? orig_id[i] : (int32_t)i;
-        const double si = theta * smax[i];
-        bool seed_nb = false, blocked = false;
-        for (int64_t p = b0 + lane; p < b1; p += WAVE) {
-            const int32_t j = col[p];
-            const double d = ml_strength(rho[eid[p]], eps);
-            if (!(d >= si || d >= theta * smax[j])) continue;
-            const uint8_t sj = __hip_atomic_load(&state[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (sj == 1) seed_nb = true;
-            else if (sj == 0 && ml_ahead(b1 - b0, ki, row_ptr[j + 1] - row_ptr[j], orig_id ? orig_id[j] : j))
-                blocked = true;
+    // wave gw owns rows gw + k nw (the high-degree rows, stored first, spread
+    // over the waves); its lanes find 64 undecided ones at a time, then the
+    // wave works through them one row at a time
+    const int64_t gw = (int64_t)blockIdx.x * (MBLOCK / WAVE) + (threadIdx.x >> 6);
+    for (int64_t base = gw; base < n; base += nw * WAVE) {
+        const int64_t mine = base + (int64_t)lane * nw;
+        unsigned long long todo = __ballot(mine < n && state[mine] == 0);
+        while (todo) {
+            const int t = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t i = base + (int64_t)t * nw;
+            bool seed_nb = false, blocked = false;
+            for (int64_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += WAVE) {
+                const uint8_t f = sflag[p];
+                if (f == 0) continue;
+                const uint8_t sj = __hip_atomic_load(&state[col[p]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (sj == 1) seed_nb = true;
+                else if (sj == 0 && f == 2) blocked = true;
+            }
+            const bool any_seed = __ballot(seed_nb) != 0ull;
+            const bool any_block = __ballot(blocked) != 0ull;
+            if (lane == 0) {
+                if (any_seed) __hip_atomic_store(&state[i], (uint8_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else if (!any_block)
+                    __hip_atomic_store(&state[i], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (!any_seed && any_block) ++waiting;
         }
-        const bool any_seed = __ballot(seed_nb) != 0ull;
-        const bool any_block = __ballot(blocked) != 0ull;
-        if (lane == 0) {
-            if (any_seed) __hip_atomic_store(&state[i], (uint8_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            else if (!any_block) __hip_atomic_store(&state[i], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (!any_seed && any_block) ++waiting;
     }
     if (lane == 0 && waiting) atomicAdd(left, waiting);
 }
@@ -270,18 +300,20 @@ __global__ void k_ml_count(int64_t m, const uint8_t *__restrict__ keep, unsigned
 struct AggLayout {
     double *smax;                 // [n]
     uint8_t *state;               // [n]
+    uint8_t *sflag;               // [nnz] coupling of every entry
     unsigned int *rank;           // [n] seed flags, scanned in place into aggregate ids
     unsigned int *total;          // [1] number of seeds
     unsigned long long *left;     // [1] vertices still undecided after a round
     ScanScratch scan;
 };
 
-static size_t agg_layout(int64_t n, void *ws, size_t ws_bytes, AggLayout *L) {
+static size_t agg_layout(int64_t n, int64_t nnz, void *ws, size_t ws_bytes, AggLayout *L) {
     Carver c(ws, ws_bytes);
     const size_t nn = (size_t)std::max<int64_t>(1, n);
     AggLayout l;
     l.smax = c.take<double>(nn);
     l.state = c.take<uint8_t>(nn);
+    l.sflag = c.take<uint8_t>((size_t)std::max<int64_t>(1, nnz));
     l.rank = c.take<unsigned int>(nn);
     l.total = c.take<unsigned int>(1);
     l.left = c.take<unsigned long long>(1);
@@ -310,6 +342,9 @@ static ad_status aggregate_impl(const ad_graph *g, const Tr *rho, double eps, do
     if (n == 0) return AD_OK;
     hipLaunchKernelGGL(k_ml_smax<Tr>, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->eid, rho, eps, L.smax);
     AD_LAUNCH_CHECK("k_ml_smax");
+    hipLaunchKernelGGL(k_ml_strong<Tr>, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->col, g->eid,
+                       g->orig_id, rho, eps, theta, L.smax, L.sflag);
+    AD_LAUNCH_CHECK("k_ml_strong");
     ad_status s = fill_u8(L.state, 0, n, st);
     if (s != AD_OK) return s;
     // each round decides at least the undecided vertex of highest priority
@@ -317,8 +352,8 @@ static ad_status aggregate_impl(const ad_graph *g, const Tr *rho, double eps, do
         if (round > n) return fail(AD_ERR_INTERNAL, "seed rounds did not settle");
         s = fill_u64(L.left, 0, 1, st);
         if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_ml_seed_round<Tr>, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->col, g->eid,
-                           g->orig_id, rho, eps, theta, L.smax, L.state, L.left);
+        hipLaunchKernelGGL(k_ml_seed_round, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->col, L.sflag,
+                           L.state, L.left);
         AD_LAUNCH_CHECK("k_ml_seed_round");
         unsigned long long waiting = 0;
         AD_HIP(hipMemcpyAsync(&waiting, L.left, sizeof(waiting), hipMemcpyDeviceToHost, st));
@@ -341,18 +376,77 @@ static ad_status aggregate_impl(const ad_graph *g, const Tr *rho, double eps, do
 
 // --------------------------------------------------------------- driver --
 
-// Device memory owned for the duration of the call.
+// Device memory of the call: a stack arena.  Buffers are carved from large
+// chunks (hipMalloc'd as needed, the first sized for level 0); freeing a
+// buffer releases it at once when it is the newest live one, otherwise when
+// the buffers above it are gone (the levels' buffers are nested scopes, so
+// almost every release is immediate).  Carving is host arithmetic, so the
+// levels allocate without device calls; every chunk is freed when the call
+// ends.  Without an arena (outside a call) plain hipMalloc / hipFree.
+struct MlArena {
+    struct Chunk {
+        char *base;
+        size_t cap, top;
+    };
+    struct Block {
+        size_t chunk, off;
+        bool live;
+    };
+    std::vector<Chunk> chunks;
+    std::vector<Block> blocks;     // in allocation order
+
+    ad_status take(size_t bytes, void **out) {
+        bytes = (bytes + 255) & ~size_t(255);
+        // the first chunk with room above its top (each chunk's blocks are
+        // still released in reverse order, so its top stays a stack)
+        size_t c = 0;
+        while (c < chunks.size() && chunks[c].top + bytes > chunks[c].cap) ++c;
+        if (c == chunks.size()) {
+            const size_t want = std::max(bytes, chunks.empty() ? (size_t)(64u << 20) : 2 * chunks.back().cap);
+            void *p = nullptr;
+            const hipError_t e = hipMalloc(&p, want);
+            if (e != hipSuccess) return fail(AD_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+            chunks.push_back(Chunk{(char *)p, want, 0});
+            c = chunks.size() - 1;
+        }
+        blocks.push_back(Block{c, chunks[c].top, true});
+        *out = chunks[c].base + chunks[c].top;
+        chunks[c].top += bytes;
+        return AD_OK;
+    }
+    void give(void *p) {
+        for (size_t k = blocks.size(); k-- > 0;) {
+            const Block &b = blocks[k];
+            if (b.live && chunks[b.chunk].base + b.off == (char *)p) {
+                blocks[k].live = false;
+                break;
+            }
+        }
+        while (!blocks.empty() && !blocks.back().live) {
+            chunks[blocks.back().chunk].top = blocks.back().off;
+            blocks.pop_back();
+        }
+    }
+    void release() {
+        for (const Chunk &c : chunks) (void)hipFree(c.base);
+        chunks.clear();
+        blocks.clear();
+    }
+};
+static thread_local MlArena *ml_arena = nullptr;
+
 struct DevMem {
     void *p = nullptr;
     size_t bytes = 0;
     DevMem() = default;
     DevMem(const DevMem &) = delete;
     DevMem &operator=(const DevMem &) = delete;
-    ~DevMem() {
-        if (p) (void)hipFree(p);
-    }
+    ~DevMem() { reset(); }
     void reset() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (ml_arena) ml_arena->give(p);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -363,15 +457,42 @@ struct DevMem {
 static ad_status dev_alloc(DevMem &d, size_t bytes) {
     d.reset();
     const size_t b = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
-    const hipError_t e = hipMalloc(&d.p, b);
-    if (e != hipSuccess) {
-        d.p = nullptr;
-        d.bytes = 0;
-        return fail(AD_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    if (ml_arena) {
+        ad_status s = ml_arena->take(b, &d.p);
+        if (s != AD_OK) {
+            d.p = nullptr;
+            return s;
+        }
+    } else {
+        const hipError_t e = hipMalloc(&d.p, b);
+        if (e != hipSuccess) {
+            d.p = nullptr;
+            return fail(AD_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
     }
     d.bytes = b;
     return AD_OK;
 }
+
+// The call's arena, its first chunk sized for level 0 of a graph with n
+// vertices and m edges; the destructor waits for the stream (work in flight
+// may still use the chunks) and frees them.
+struct MlArenaScope {
+    hipStream_t stream;
+    MlArena arena;
+    MlArenaScope(hipStream_t st, int64_t n, int64_t m) : stream(st) {
+        void *p = nullptr;
+        const size_t first = (size_t)(96 * std::max<int64_t>(1, m) + 96 * std::max<int64_t>(1, n)) + (64u << 20);
+        if (hipMalloc(&p, first) == hipSuccess) arena.chunks.push_back(MlArena::Chunk{(char *)p, first, 0});
+        else (void)hipGetLastError();
+        ml_arena = &arena;
+    }
+    ~MlArenaScope() {
+        (void)hipStreamSynchronize(stream);
+        ml_arena = nullptr;
+        arena.release();
+    }
+};
 
 #define ML_TRY(x)                          \
     do {                                   \
@@ -402,8 +523,6 @@ static ad_status ml_distances(const ad_graph *g, const ad_ml_opts *o, int l, Dev
     if (db == 0) return fail(AD_ERR_INTERNAL, "distance workspace size");
     ML_TRY(dev_alloc(wsd, db));
     ML_TRY(ad_edge_dist(g, o->R, o->store, x.p, mm.get<double>(), rho.p, wsd.p, db, st));
-    // the relaxation buffers are freed on return: finish with them first
-    AD_HIP(hipStreamSynchronize(st));
     return AD_OK;
 }
 
@@ -449,18 +568,14 @@ static ad_status ml_level(const ad_graph *g, const ad_ml_opts *o, int l, uint8_t
     int64_t nc = 0;
     if (!coarsest) {
         ML_TRY(dev_alloc(agg, (size_t)n * sizeof(int32_t)));
-        const size_t ab = agg_layout(n, nullptr, 0, nullptr);
+        const size_t ab = agg_layout(n, 2 * m, nullptr, 0, nullptr);
         ML_TRY(dev_alloc(aws, ab));
         AggLayout L;
-        agg_layout(n, aws.p, aws.bytes, &L);
+        agg_layout(n, 2 * m, aws.p, aws.bytes, &L);
         ML_TRY(aggregate_impl<Tr>(g, rho.get<const Tr>(), o->eps, o->theta, agg.get<int32_t>(), nullptr, &nc, L, st));
         if ((double)nc > 0.9 * (double)n) coarsest = true;
     }
-    if (coarsest) {
-        ML_TRY(ml_binned(g, o, l, ml_entry(o, l, l), rho.p, keep, st));
-        AD_HIP(hipStreamSynchronize(st));
-        return AD_OK;
-    }
+    if (coarsest) return ml_binned(g, o, l, ml_entry(o, l, l), rho.p, keep, st);
     // coarse graph: the fine edges' aggregate pairs merged by ad_ingest (P^T L P)
     DevMem cu, cv, cw, names;
     ML_TRY(dev_alloc(cu, (size_t)m * sizeof(int32_t)));
@@ -471,7 +586,7 @@ static ad_status ml_level(const ad_graph *g, const ad_ml_opts *o, int l, uint8_t
                        agg.get<const int32_t>(), cu.get<int32_t>(), cv.get<int32_t>(), cw.get<float>());
     AD_LAUNCH_CHECK("k_ml_pairs");
     AggLayout L;
-    agg_layout(n, aws.p, aws.bytes, &L);
+    agg_layout(n, 2 * m, aws.p, aws.bytes, &L);
     hipLaunchKernelGGL(k_ml_names, dim3(mgrid(n)), dim3(MBLOCK), 0, st, n, L.state, agg.get<const int32_t>(),
                        g->orig_id, names.get<int32_t>());
     AD_LAUNCH_CHECK("k_ml_names");
@@ -515,7 +630,6 @@ static ad_status ml_level(const ad_graph *g, const ad_ml_opts *o, int l, uint8_t
     const double x = ml_entry(o, *depth, l);
     if (x < 0.0) {          // no SparsifyB here: the inherited state is the result
         AD_HIP(hipMemcpyAsync(keep, inh.p, (size_t)m, hipMemcpyDeviceToDevice, st));
-        AD_HIP(hipStreamSynchronize(st));
         return AD_OK;
     }
     DevMem srp, scol, sw, seid, soe, wss, dmx;
@@ -558,8 +672,6 @@ static ad_status ml_level(const ad_graph *g, const ad_ml_opts *o, int l, uint8_t
                            soe.get<const int32_t>(), skeep.get<const uint8_t>(), keep);
         AD_LAUNCH_CHECK("k_ml_map_back");
     }
-    // the level's buffers are freed on return: finish with them first
-    AD_HIP(hipStreamSynchronize(st));
     return AD_OK;
 }
 
@@ -578,7 +690,8 @@ extern "C" ad_status ad_ml_level_span(int32_t n_levels, int32_t span, int32_t se
 
 extern "C" size_t ad_ml_aggregate_workspace_size(const ad_graph *g) {
     if (!g || g->n < 0 || g->n >= ((int64_t)1 << 31)) return 0;
-    return agg_layout(g->n, nullptr, 0, nullptr);
+    if (g->m < 0 || g->m >= ((int64_t)1 << 31)) return 0;
+    return agg_layout(g->n, 2 * g->m, nullptr, 0, nullptr);
 }
 
 extern "C" ad_status ad_ml_aggregate(const ad_graph *g, ad_dtype rho_dtype, const void *rho, double eps, double theta,
@@ -593,11 +706,11 @@ extern "C" ad_status ad_ml_aggregate(const ad_graph *g, ad_dtype rho_dtype, cons
     if (!(eps >= 0.0) || !(theta >= 0.0 && theta <= 1.0))
         return fail(AD_ERR_INVALID_ARG, "eps must be >= 0 and theta in [0, 1]");
     if (g->n >= ((int64_t)1 << 31)) return fail(AD_ERR_UNSUPPORTED, "graph too large");
-    const size_t need = agg_layout(g->n, nullptr, 0, nullptr);
+    const size_t need = agg_layout(g->n, 2 * g->m, nullptr, 0, nullptr);
     s = ml_check_ws(ws, need, ws_bytes);
     if (s != AD_OK) return s;
     AggLayout L;
-    agg_layout(g->n, ws, ws_bytes, &L);
+    agg_layout(g->n, 2 * g->m, ws, ws_bytes, &L);
     TraceScope trace("k_ml_aggregate", stream);
     return rho_dtype == AD_F64
                ? aggregate_impl<double>(g, (const double *)rho, eps, theta, agg, is_seed, n_coarse_host, L, stream)
@@ -635,6 +748,7 @@ extern "C" ad_status ad_ml_sparsify(const ad_graph *g, const ad_ml_opts *o, uint
     *n_kept_host = 0;
     if (g->m > 0) {
         TraceScope trace("k_ml_sparsify", stream);
+        MlArenaScope arena(stream, g->n, g->m);
         s = o->store == AD_F64 ? ml_level<double>(g, o, 0, keep, &depth, stream)
                                : ml_level<float>(g, o, 0, keep, &depth, stream);
         if (s != AD_OK) return s;
