@@ -18,8 +18,9 @@ Other forms, one JSON line each (--workload): `batch` (512 Chung-Lu graphs
 in one captured launch sequence), `bf16` (R-MAT n = 2^24, 2^28 edges, BF16
 storage, against the FP32 path and the FP64 path), `adjoint` (512 x 512
 grid with long-range edges, forward and weight gradient), `fp64` (G(n, m)
-with n = 2,000, m = 10,000 in FP64).  The inputs are those of
-paper_1601_05527_amd.workloads.
+with n = 2,000, m = 10,000 in FP64), `multilevel` (the multilevel cycle of
+Algorithm 6 on the default graph; value in input edges per second).  The
+inputs are those of paper_1601_05527_amd.workloads.
 """
 from __future__ import annotations
 
@@ -387,6 +388,57 @@ def run_chung_lu(args, api, torch, dev):
         setup_s={"generate_and_layout": t_setup})
 
 
+# ----------------------------------------------------------- multilevel ---
+
+def run_multilevel(args, api, torch, dev):
+    """Algorithm 6 alone on the Chung-Lu graph, in the configuration the
+    Chung-Lu line reports under "multilevel"."""
+    from paper_1601_05527_amd import graphs
+    from paper_1601_05527_amd import workloads as W
+    c = W.CHUNG_LU
+    R, K, TARGET = c["R"], c["k"], c["target"]
+    _, g_run = W.chung_lu_graph("degree")
+    dg = api.DeviceGraph.from_host(g_run, dev, keep_host=False)
+    m = dg.m
+    kw = dict(levels=c["ml_levels"], n_min=c["ml_n_min"], bin_seed=c["bin_seed"], fit=True, span=c["ml_span"],
+              segment=2, span_value=TARGET)
+    keep = torch.empty(m, dtype=torch.uint8, device=dev)
+    res = {}
+
+    def cycle():
+        _, kept, depth = api.ml_sparsify(dg, R, K, omega=W.OMEGA, seed=c["seed_vec"], store="f32", keep=keep, **kw)
+        res.update(kept=kept, depth=depth)
+
+    timer = Timer(torch)
+    for _ in range(args.warmup):
+        cycle()
+    torch.cuda.synchronize()
+    ms, kern = traced(api, timer, cycle, args.steps)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ns, ms_ = 1 << 18, 4_000_000
+        g0 = graphs.chung_lu(ns, ms_, gamma=c["gamma"], seed=c["seed"])
+        gs = graphs.relabel(g0, graphs.degree_descending_order(g0))
+        t0 = time.perf_counter()
+        oracle.ml_sparsify(gs, R, K, None, omega=W.OMEGA, seed=c["seed_vec"], **kw)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": gs.m / t_cpu, "unit": "input edges/s", "cores": oracle_threads(), "kind": "oracle",
+               "sample": (f"FP64 oracle multilevel cycle, same parameters, on a Chung-Lu graph of the same kind "
+                          f"with n=2^18 and {gs.m} edges; {t_cpu:.2f}s wall")}
+    config = {
+        "workload": (f"Algorithm 6 on the Chung-Lu graph n=2^20, m={c['m']}, gamma={c['gamma']}, lognormal "
+                     f"weights; R={R}, k={K}, FP32 relaxation at every level; at most {c['ml_levels']} levels, "
+                     f"n_min={c['ml_n_min']}, level-span {c['ml_span']} on the finest third, each sparsified "
+                     f"level keeping {int(TARGET * 100)}% of its edges"),
+        "n": dg.n, "m": m, "R": R, "k": K, "parallelism": "single GPU",
+    }
+    return base_result(args, m / (ms * 1e-3), ms, "f32", "synthetic (seeded Chung-Lu graph; no dataset)", config,
+                       None, cpu, metric="multilevel sparsification throughput", unit="input edges/s",
+                       kept=res["kept"], depth=res["depth"], ratio=res["kept"] / m,
+                       breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())})
+
+
 # --------------------------------------------------------------- batch ---
 
 def run_batch(args, api, torch, dev):
@@ -664,7 +716,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["chung-lu", "batch", "bf16", "adjoint", "fp64"], default="chung-lu")
+    ap.add_argument("--workload", choices=["chung-lu", "batch", "bf16", "adjoint", "fp64", "multilevel"],
+                    default="chung-lu")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=6, help="sweeps in the oracle's bounded CPU sample")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -690,7 +743,7 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     run = {"chung-lu": run_chung_lu, "batch": run_batch, "bf16": run_bf16, "adjoint": run_adjoint,
-           "fp64": run_fp64}[args.workload]
+           "fp64": run_fp64, "multilevel": run_multilevel}[args.workload]
     result = run(args, api, torch, dev)
     print(json.dumps(result), flush=True)
     return 0
