@@ -1134,6 +1134,38 @@ static void budget_table(int32_t d_max, double e, std::vector<int32_t> &t) {
 }
 
 // Rank every entry of every row and emit per `em`.
+// Helper streams for the ranking classes.  The classes rank disjoint rows
+// (their outputs are distinct sides or set-only keep flags), and the long
+// classes are latency-bound (one workgroup sorts one row), so outside stream
+// capture they run beside the short rows on three more streams of the same
+// (default) priority, forked from and joined back into the caller's stream
+// with events.  Created once per device; the mutex keeps one fork/join
+// sequence's records and waits together when several host threads rank.
+struct RankFork {
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+    bool ok = false;
+    std::mutex mu;
+};
+
+static RankFork *rank_fork() {
+    static RankFork forks[MAX_DEVICES];
+    static std::once_flag once[MAX_DEVICES];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    RankFork *f = &forks[dev];
+    std::call_once(once[dev], [f]() {
+        bool ok = hipEventCreateWithFlags(&f->fork, hipEventDisableTiming) == hipSuccess;
+        for (int h = 0; h < 3 && ok; ++h) {
+            ok = hipStreamCreateWithFlags(&f->side[h], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&f->join[h], hipEventDisableTiming) == hipSuccess;
+        }
+        if (!ok) (void)hipGetLastError();
+        f->ok = ok;
+    });
+    return f->ok ? f : nullptr;
+}
+
 template <typename Tr>
 static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, const SelLayout &L, hipStream_t st,
                           const unsigned long long *keys = nullptr) {
@@ -1141,6 +1173,28 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
     if (n <= 0 || g->m <= 0) return AD_OK;
     TraceScope trace("k_rank", st);
     ad_status s;
+    // FP32 rows above 64: classify first, then fork the classes off
+    RankFork *fk = nullptr;
+    std::unique_lock<std::mutex> hold;
+    hipStream_t cls[3] = {st, st, st};
+    if (sizeof(Tr) == 4 && g->d_max > 64) {
+        s = fill_i32((int32_t *)L.cnt, 0, NCLASS, st);
+        if (s != AD_OK) return s;
+        hipLaunchKernelGGL(k_classify, dim3(grid_for(n, SBLOCK)), dim3(SBLOCK), 0, st, n, g->row_ptr, L.cb, L.lists,
+                           L.cnt);
+        AD_LAUNCH_CHECK("k_classify");
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) fk = rank_fork();
+        else (void)hipGetLastError();
+        if (fk) {
+            hold = std::unique_lock<std::mutex>(fk->mu);
+            AD_HIP(hipEventRecord(fk->fork, st));
+            for (int h = 0; h < 3; ++h) {
+                AD_HIP(hipStreamWaitEvent(fk->side[h], fk->fork, 0));
+                cls[h] = fk->side[h];
+            }
+        }
+    }
     // rows of degree <= 64, packed into waves
     const int64_t ntiles = ceil_div(n, RANK_TILE);
     hipLaunchKernelGGL(k_rank_plan, dim3(grid_for(ntiles, SBLOCK)), dim3(SBLOCK), 0, st, n, g->row_ptr, 0,
@@ -1157,39 +1211,45 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
     AD_LAUNCH_CHECK("k_rank_packed");
     if (g->d_max <= 64) return AD_OK;
 
-    s = fill_i32((int32_t *)L.cnt, 0, NCLASS, st);
-    if (s != AD_OK) return s;
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(n, SBLOCK)), dim3(SBLOCK), 0, st, n, g->row_ptr, L.cb, L.lists,
-                       L.cnt);
-    AD_LAUNCH_CHECK("k_classify");
+    if (sizeof(Tr) != 4) {
+        s = fill_i32((int32_t *)L.cnt, 0, NCLASS, st);
+        if (s != AD_OK) return s;
+        hipLaunchKernelGGL(k_classify, dim3(grid_for(n, SBLOCK)), dim3(SBLOCK), 0, st, n, g->row_ptr, L.cb, L.lists,
+                           L.cnt);
+        AD_LAUNCH_CHECK("k_classify");
+    }
     const unsigned grid = (unsigned)std::min<int64_t>(2048, n);
     const int32_t *lst[NCLASS];
     for (int k = 0; k < NCLASS; ++k) lst[k] = L.lists + L.cb.off[k];
     if (sizeof(Tr) == 4) {
         const float *rf = (const float *)rho;
 #define AD_RANK_ARGS_F g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, em
-        if (g->d_max > 64)
-            hipLaunchKernelGGL((k_rank_wave<2>), dim3(grid), dim3(SBLOCK), 0, st, lst[0], &L.cnt[0], AD_RANK_ARGS_F);
-        if (g->d_max > 128)
-            hipLaunchKernelGGL((k_rank_wave<4>), dim3(grid), dim3(SBLOCK), 0, st, lst[1], &L.cnt[1], AD_RANK_ARGS_F);
-        if (g->d_max > 256)
-            hipLaunchKernelGGL((k_rank_wave<8>), dim3(grid), dim3(SBLOCK), 0, st, lst[2], &L.cnt[2], AD_RANK_ARGS_F);
-        AD_LAUNCH_CHECK("k_rank_wave");
-        if (g->d_max > 512)
-            hipLaunchKernelGGL((k_rank_bitonic<1024, 256>), dim3(grid), dim3(256), 0, st, lst[3], &L.cnt[3],
-                               AD_RANK_ARGS_F);
-        if (g->d_max > 1024)
-            hipLaunchKernelGGL((k_rank_bitonic<2048, 256>), dim3(grid), dim3(256), 0, st, lst[4], &L.cnt[4],
+        // the longest rows first on their streams: their latency is the tail
+        if (g->d_max > 4096)
+            hipLaunchKernelGGL((k_rank_bitonic<8192, 1024>), dim3(grid), dim3(1024), 0, cls[0], lst[6], &L.cnt[6],
                                AD_RANK_ARGS_F);
         if (g->d_max > 2048)
-            hipLaunchKernelGGL((k_rank_bitonic<4096, 512>), dim3(grid), dim3(512), 0, st, lst[5], &L.cnt[5],
+            hipLaunchKernelGGL((k_rank_bitonic<4096, 512>), dim3(grid), dim3(512), 0, cls[1], lst[5], &L.cnt[5],
                                AD_RANK_ARGS_F);
-        if (g->d_max > 4096)
-            hipLaunchKernelGGL((k_rank_bitonic<8192, 1024>), dim3(grid), dim3(1024), 0, st, lst[6], &L.cnt[6],
+        if (g->d_max > 1024)
+            hipLaunchKernelGGL((k_rank_bitonic<2048, 256>), dim3(grid), dim3(256), 0, cls[2], lst[4], &L.cnt[4],
                                AD_RANK_ARGS_F);
+        if (g->d_max > 512)
+            hipLaunchKernelGGL((k_rank_bitonic<1024, 256>), dim3(grid), dim3(256), 0, cls[1], lst[3], &L.cnt[3],
+                               AD_RANK_ARGS_F);
+        AD_LAUNCH_CHECK("k_rank_bitonic");
+        if (g->d_max > 256)
+            hipLaunchKernelGGL((k_rank_wave<8>), dim3(grid), dim3(SBLOCK), 0, cls[2], lst[2], &L.cnt[2],
+                               AD_RANK_ARGS_F);
+        if (g->d_max > 128)
+            hipLaunchKernelGGL((k_rank_wave<4>), dim3(grid), dim3(SBLOCK), 0, cls[0], lst[1], &L.cnt[1],
+                               AD_RANK_ARGS_F);
+        if (g->d_max > 64)
+            hipLaunchKernelGGL((k_rank_wave<2>), dim3(grid), dim3(SBLOCK), 0, cls[2], lst[0], &L.cnt[0],
+                               AD_RANK_ARGS_F);
+        AD_LAUNCH_CHECK("k_rank_wave");
         // (the bucket partition runs once per orientation, a sort serves both: sorts up to SORT_CAP)
         static_assert(HUB_CLASS == 7 && SORT_CAP == 8192, "bitonic classes end where the bucket partition starts");
-        AD_LAUNCH_CHECK("k_rank_bitonic");
 #undef AD_RANK_ARGS_F
         if (g->d_max > SORT_CAP) {
             // the bucket keys carry one orientation: one partition per orientation asked for
@@ -1204,18 +1264,25 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                         one.sides = em.sides2;
                     }
                 }
-                s = fill_i32((int32_t *)L.hub.nbk, 0, 1, st);
+                s = fill_i32((int32_t *)L.hub.nbk, 0, 1, cls[0]);
                 if (s != AD_OK) return s;
                 for (int k = HUB_CLASS; k < NCLASS; ++k) {
                     if (g->d_max <= CLASS_LO[k]) break;
-                    hipLaunchKernelGGL(k_hub_partition, dim3(512), dim3(HUB_TB), 0, st, lst[k], &L.cnt[k],
+                    hipLaunchKernelGGL(k_hub_partition, dim3(512), dim3(HUB_TB), 0, cls[0], lst[k], &L.cnt[k],
                                        g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, one.orient,
                                        L.hub);
                     AD_LAUNCH_CHECK("k_hub_partition");
                 }
-                hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, st, g->row_ptr, g->col, g->eid, one,
+                hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, cls[0], g->row_ptr, g->col, g->eid, one,
                                    L.hub);
                 AD_LAUNCH_CHECK("k_hub_rank");
+            }
+        }
+        if (fk) {
+            // join: the caller's stream waits for the three class streams
+            for (int h = 0; h < 3; ++h) {
+                AD_HIP(hipEventRecord(fk->join[h], fk->side[h]));
+                AD_HIP(hipStreamWaitEvent(st, fk->join[h], 0));
             }
         }
     } else {
