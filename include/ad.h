@@ -508,12 +508,15 @@ size_t ad_validate_workspace_size(const ad_graph *g);
 ad_status ad_validate_graph(const ad_graph *g, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Kernel timing (for measurement, off by default).  While enabled, the
- * library brackets its main kernel launches (JOR sweep, distance, ranking,
- * fit passes) with HIP events on the caller's stream; the events are
- * created on the host when the launch is made.  ad_trace_summary waits for
+ * library brackets its main kernel launches (JOR sweeps, distance, ranking,
+ * fit passes, ...) with HIP events on the caller's stream; the k sweeps of
+ * one ad_relax call share one pair of events around the whole sequence (so
+ * the per-launch figure is the span over k, gaps between sweeps included).
+ * Events come from a pool that grows on first use.  ad_trace_summary waits for
  * the recorded events and writes one line per kernel name,
  * "<name> <launches> <total_ms>\n", into buf (len bytes, NUL-terminated);
- * ad_trace_reset waits for and releases them. */
+ * ad_trace_reset waits for them and keeps their events for reuse by later
+ * scopes (so a traced region after a first traced pass creates none). */
 void ad_trace_enable(int32_t on);
 void ad_trace_reset(void);
 ad_status ad_trace_summary(char *buf, size_t len);

@@ -325,22 +325,45 @@ __global__ void k_validate_eids(int64_t m, const unsigned int *__restrict__ eid_
 
 struct TraceRecord {
     std::string name;
+    int launches;
     hipEvent_t a, b;
 };
 static std::atomic<bool> g_trace_on{false};
 static std::mutex g_trace_mu;
 static std::vector<TraceRecord> g_trace;
+static std::vector<hipEvent_t> g_event_pool;     // released events, reused by later scopes
+
+// An event from the pool (or a new one); g_trace_mu must be held.
+static hipEvent_t pooled_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
 
 static thread_local int g_trace_suppress = 0;
 
 TraceSuppress::TraceSuppress() { ++g_trace_suppress; }
 TraceSuppress::~TraceSuppress() { --g_trace_suppress; }
 
-TraceScope::TraceScope(const char *n, hipStream_t s) : name(n), stream(s) {
+TraceScope::TraceScope(const char *n, hipStream_t s, int count) : name(n), stream(s), launches(count) {
     if (!g_trace_on.load(std::memory_order_relaxed) || g_trace_suppress) return;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-        a = b = nullptr;
-        return;
+    {
+        std::lock_guard<std::mutex> lk(g_trace_mu);
+        a = pooled_event();
+        b = a ? pooled_event() : nullptr;
+        if (!b) {
+            if (a) g_event_pool.push_back(a);
+            a = b = nullptr;
+            return;
+        }
     }
     hipEventRecord(a, stream);
 }
@@ -349,7 +372,7 @@ TraceScope::~TraceScope() {
     if (!a) return;
     hipEventRecord(b, stream);
     std::lock_guard<std::mutex> lk(g_trace_mu);
-    g_trace.push_back({name, a, b});
+    g_trace.push_back({name, launches, a, b});
 }
 
 }  // namespace ad
@@ -362,8 +385,8 @@ extern "C" void ad_trace_reset(void) {
     std::lock_guard<std::mutex> lk(g_trace_mu);
     for (auto &r : g_trace) {
         hipEventSynchronize(r.b);
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
     }
     g_trace.clear();
 }
@@ -377,7 +400,7 @@ extern "C" ad_status ad_trace_summary(char *buf, size_t len) {
         float ms = 0.f;
         AD_HIP(hipEventElapsedTime(&ms, r.a, r.b));
         auto &e = agg[r.name];
-        e.first += 1;
+        e.first += r.launches;
         e.second += ms;
     }
     std::string out;

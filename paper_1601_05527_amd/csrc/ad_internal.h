@@ -207,8 +207,9 @@ ad_status check_graph_args(const ad_graph *g);
 struct TraceScope {
     const char *name;
     hipStream_t stream;
+    int launches;                 // kernel launches the scope brackets (counted in the summary)
     hipEvent_t a = nullptr, b = nullptr;
-    TraceScope(const char *name, hipStream_t s);
+    TraceScope(const char *name, hipStream_t s, int launches = 1);
     ~TraceScope();
 };
 // While one exists on this thread, TraceScope records nothing (used around

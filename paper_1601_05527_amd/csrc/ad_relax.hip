@@ -1068,6 +1068,10 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
     }
 
     if (o->k > 0 && n > 0) {
+        // one pair of trace events around the k back-to-back sweeps (an event
+        // between two sweeps would cost the stream more than it measures)
+        TraceScope trace("k_sweep", st, o->k);
+        TraceSuppress per_launch;
         Buf cur = {start, o->store == AD_F64 ? AD_F64 : AD_F32};
         const int tail = o->store == AD_BF16 ? o->fp32_tail : o->k;
         for (int t = 1; t <= o->k; ++t) {
