@@ -186,3 +186,28 @@ def test_ratio_vector_variants_match_oracle(api, variant):
     np.testing.assert_array_equal(_np(keep), keep_o)
     if variant == "all_skipped":
         assert kept == g.m
+
+
+@pytest.mark.parametrize("shape", ["single_edge", "star", "path", "triangles_and_isolated", "complete"])
+def test_degenerate_graphs_match_oracle(api, shape):
+    """Coarsening down to one vertex (n_min = 0), stars (one seed takes
+    everything), paths (long chains of equal degree), isolated vertices and
+    a complete graph (every distance tied at the fixed point)."""
+    announce(f"ml sparsify degenerate {shape}")
+    if shape == "single_edge":
+        g = G.from_edges(2, [0], [1])
+    elif shape == "star":
+        g = G.from_edges(51, np.zeros(50, int), np.arange(1, 51))
+    elif shape == "path":
+        g = G.from_edges(100, np.arange(99), np.arange(1, 100))
+    elif shape == "triangles_and_isolated":
+        g = G.from_edges(9, [0, 1, 0, 3, 4, 3], [1, 2, 2, 4, 5, 5])
+    else:
+        u, v = np.triu_indices(12, 1)
+        g = G.from_edges(12, u, v)
+    dg = api.DeviceGraph.from_host(g, "cuda")
+    for e in ([0.5], [0.0], [-1.0, 0.7]):
+        keep, kept, depth = api.ml_sparsify(dg, 8, 10, e, seed=2, levels=5, n_min=0, store="f64", bin_seed=3)
+        keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, e, seed=2, levels=5, n_min=0, bin_seed=3)
+        assert depth == depth_o and kept == kept_o, (shape, e)
+        np.testing.assert_array_equal(_np(keep), keep_o)
