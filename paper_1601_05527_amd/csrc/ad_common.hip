@@ -327,18 +327,39 @@ struct TraceRecord {
     std::string name;
     int launches;
     hipEvent_t a, b;
+    int dev;
 };
 static std::atomic<bool> g_trace_on{false};
 static std::mutex g_trace_mu;
 static std::vector<TraceRecord> g_trace;
-static std::vector<hipEvent_t> g_event_pool;     // released events, reused by later scopes
+// Released events, per device (an event belongs to the device current when
+// it was created), reused by later scopes.
+struct PooledEvent {
+    hipEvent_t ev;
+    int dev;
+};
+static std::vector<PooledEvent> g_event_pool;
 
-// An event from the pool (or a new one); g_trace_mu must be held.
+static int current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        dev = 0;
+    }
+    return dev;
+}
+
+// An event of the current device from the pool (or a new one); g_trace_mu
+// must be held.
 static hipEvent_t pooled_event() {
-    if (!g_event_pool.empty()) {
-        hipEvent_t e = g_event_pool.back();
-        g_event_pool.pop_back();
-        return e;
+    const int dev = current_device();
+    for (size_t k = g_event_pool.size(); k-- > 0;) {
+        if (g_event_pool[k].dev == dev) {
+            hipEvent_t e = g_event_pool[k].ev;
+            g_event_pool[k] = g_event_pool.back();
+            g_event_pool.pop_back();
+            return e;
+        }
     }
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) {
@@ -360,10 +381,11 @@ TraceScope::TraceScope(const char *n, hipStream_t s, int count) : name(n), strea
         a = pooled_event();
         b = a ? pooled_event() : nullptr;
         if (!b) {
-            if (a) g_event_pool.push_back(a);
+            if (a) g_event_pool.push_back({a, current_device()});
             a = b = nullptr;
             return;
         }
+        dev = current_device();
     }
     hipEventRecord(a, stream);
 }
@@ -372,7 +394,7 @@ TraceScope::~TraceScope() {
     if (!a) return;
     hipEventRecord(b, stream);
     std::lock_guard<std::mutex> lk(g_trace_mu);
-    g_trace.push_back({name, launches, a, b});
+    g_trace.push_back({name, launches, a, b, dev});
 }
 
 }  // namespace ad
@@ -385,8 +407,8 @@ extern "C" void ad_trace_reset(void) {
     std::lock_guard<std::mutex> lk(g_trace_mu);
     for (auto &r : g_trace) {
         hipEventSynchronize(r.b);
-        g_event_pool.push_back(r.a);
-        g_event_pool.push_back(r.b);
+        g_event_pool.push_back({r.a, r.dev});
+        g_event_pool.push_back({r.b, r.dev});
     }
     g_trace.clear();
 }

@@ -209,6 +209,7 @@ struct TraceScope {
     hipStream_t stream;
     int launches;                 // kernel launches the scope brackets (counted in the summary)
     hipEvent_t a = nullptr, b = nullptr;
+    int dev = 0;                  // device of the events
     TraceScope(const char *name, hipStream_t s, int launches = 1);
     ~TraceScope();
 };
