@@ -396,6 +396,8 @@ def ml_sparsify(g, R: int, k: int, e_levels=None, omega: float = 0.5, seed: int 
     sparsification at that level); entries are exponents, or retention
     targets with `fit`.  span > 0 replaces e_levels by the level-span vector
     of the levels reached.  Returns (keep[m], n_kept, depth)."""
+    if e_levels is None and span <= 0:
+        raise ValueError("ml_sparsify needs e_levels, or span > 0 for the level-span rule")
     lib = _load()
     ev = np.atleast_1d(np.ascontiguousarray(e_levels if e_levels is not None else [0.0], dtype=np.float64))
     if ev.size < levels:

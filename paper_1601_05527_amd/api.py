@@ -700,6 +700,8 @@ def ml_sparsify(dg: DeviceGraph, R: int, k: int, e_levels=None, omega: float = 0
     or retention targets with ``fit``.  ``span > 0`` uses the level-span
     vector of the levels reached instead.  Returns (keep uint8 [m], n_kept,
     depth).  Synchronises the current stream."""
+    if e_levels is None and span <= 0:
+        raise ValueError("ml_sparsify needs e_levels, or span > 0 for the level-span rule")
     ev = [float(x) for x in np.atleast_1d(np.asarray(e_levels if e_levels is not None else [0.0],
                                                      dtype=np.float64))]
     ev = (ev + [ev[-1]] * max(0, levels - len(ev)))[:max(levels, 1)]
