@@ -288,28 +288,6 @@ def run_chung_lu(args, api, torch, dev):
                         "step's own distances; synchronises for the fit"))
     del ws_b
 
-    # multilevel sparsification (Algorithm 6) of the same graph: the finest third of
-    # the levels reached sparsified (level-span), each keeping 30% of its edges
-    ml = {}
-    ml_kw = dict(levels=c["ml_levels"], n_min=c["ml_n_min"], store="f32", bin_seed=c["bin_seed"], fit=True,
-                 span=c["ml_span"], segment=2, span_value=TARGET)
-    keep_ml = torch.empty(m, dtype=torch.uint8, device=dev)
-
-    def multilevel():
-        _, kept_ml, depth_ml = api.ml_sparsify(dg, R, K, omega=OMEGA, seed=SEED_VEC, keep=keep_ml, **ml_kw)
-        ml.update(kept=kept_ml, depth=depth_ml)
-
-    multilevel()
-    ml_ms, ml_kern = traced(api, timer, multilevel, 2)
-    ml.update(ms=ml_ms, ratio=ml["kept"] / m,
-              breakdown_ms={k_: v[1] / 2 for k_, v in sorted(ml_kern.items())},
-              what=(f"Algorithm 6 on the step's graph: coarsening by seeds and P (theta 1/2) down to "
-                    f"n <= {c['ml_n_min']} or {c['ml_levels']} levels, level-span {c['ml_span']} on the "
-                    f"finest third, each sparsified level keeping {int(TARGET * 100)}% of its edges "
-                    "(SparsifyB, fitted); relax + distances at every level and again after inheritance; "
-                    "allocates its level buffers and synchronises"))
-    del keep_ml
-
     # the property comparisons of Section 6 for the step's LOCAL selection
     props = {}
 
@@ -382,7 +360,6 @@ def run_chung_lu(args, api, torch, dev):
         gather_ceiling=gather,
         vendor_spmm=spmm,
         binned_selection=binned,
-        multilevel=ml,
         ingest=ingest,
         properties=props,
         traffic_over_algorithmic=(roof["traffic"] / sb) if roof["traffic"] else None,
@@ -395,8 +372,9 @@ def run_chung_lu(args, api, torch, dev):
 # ----------------------------------------------------------- multilevel ---
 
 def run_multilevel(args, api, torch, dev):
-    """Algorithm 6 alone on the Chung-Lu graph, in the configuration the
-    Chung-Lu line reports under "multilevel"."""
+    """Algorithm 6 alone on the Chung-Lu graph: at most 9 levels, n_min
+    1000, level-span 3 on the finest third, each sparsified level keeping
+    30% of its edges."""
     from paper_1601_05527_amd import graphs
     from paper_1601_05527_amd import workloads as W
     c = W.CHUNG_LU
