@@ -107,6 +107,8 @@ def _load():
     lib.orc_spearman.argtypes = [i64, P, P]
     lib.orc_spearman.restype = f64
     lib.orc_ingest.restype = i64
+    lib.orc_exact_sum_f32.argtypes = [P, i64]
+    lib.orc_exact_sum_f32.restype = ctypes.c_float
     lib.orc_sparsify_binned.argtypes = [i64, P, P, P, P, i64, P, u64, u64, f64, P]
     lib.orc_sparsify_binned.restype = i64
     lib.orc_fit_exponent_binned.argtypes = [i64, P, P, P, P, i64, P, u64, u64, f64, P, P]
@@ -311,11 +313,21 @@ def ingest(n: int, u, v, w=None, orig_id=None, order: int = 0):
     dropped = ctypes.c_int64()
     m = lib.orc_ingest(n, m_in, _p(uu), _p(vv), _p(ww), _p(oi), order, _p(row_ptr), _p(col), _p(w_out),
                        _p(eid), _p(orig), ctypes.byref(dropped))
-    if m < 0:
+    if m == -1:
         raise ValueError("vertex id out of range")
+    if m < 0:
+        raise ValueError("a weight is not finite and positive")
     nnz = 2 * m
     return (row_ptr, col[:nnz].copy(), None if w_out is None else w_out[:nnz].copy(), eid[:nnz].copy(),
             orig[:n].copy(), int(m), int(dropped.value))
+
+
+def exact_sum_f32(x) -> np.float32:
+    """The exact sum of positive finite float32 values, rounded once to
+    float32 (the merged weight of repeated pairs)."""
+    lib = _load()
+    xx = np.ascontiguousarray(x, dtype=np.float32)
+    return np.float32(lib.orc_exact_sum_f32(_p(xx), xx.size))
 
 
 def subgraph(g, keep):

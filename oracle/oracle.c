@@ -43,6 +43,7 @@
  *     smallest e found whose retained fraction reaches the target (the
  *     binary-search fitting of Section 6.2).
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -582,12 +583,60 @@ static int orc_cmp_vdeg(const void *x, const void *y)
     return (p->id > q->id) - (p->id < q->id);
 }
 
+/* The exact sum of cnt positive finite floats, rounded once to single
+ * precision (to nearest, ties to even).  Every float is an integer multiple
+ * of 2^-149, so the sum is kept exactly as an integer count of 2^-149 in 11
+ * base-2^32 digits (the largest float is below 2^277 such units; 2^31 of
+ * them stay below 2^308).                                                  */
+float orc_exact_sum_f32(const float *x, int64_t cnt)
+{
+    uint32_t dg[11];
+    memset(dg, 0, sizeof(dg));
+    for (int64_t q = 0; q < cnt; ++q) {
+        uint32_t bits;
+        memcpy(&bits, &x[q], sizeof(bits));
+        uint32_t ex = (bits >> 23) & 0xffu, fr = bits & 0x7fffffu;
+        uint64_t mant = ex ? (uint64_t)(fr | 0x800000u) : (uint64_t)fr;
+        int shift = ex ? (int)ex - 1 : 0;          /* x = mant * 2^(shift - 149) */
+        int k = shift / 32;
+        uint64_t add = mant << (shift % 32);       /* below 2^56 */
+        uint64_t carry = 0;
+        for (int j = k; j < 11; ++j) {
+            uint64_t part = j == k ? (add & 0xffffffffu) : (j == k + 1 ? add >> 32 : 0);
+            uint64_t t = (uint64_t)dg[j] + part + carry;
+            dg[j] = (uint32_t)t;
+            carry = t >> 32;
+            if (j > k && carry == 0) break;
+        }
+    }
+    int top = -1;                                  /* highest set bit of the count */
+    for (int j = 10; j >= 0 && top < 0; --j)
+        for (int b = 31; b >= 0; --b)
+            if ((dg[j] >> b) & 1u) { top = 32 * j + b; break; }
+    if (top < 0) return 0.0f;
+    if (top <= 23) return ldexpf((float)dg[0], -149);   /* below 2^24 units: exact */
+    uint32_t mant = 0;
+    for (int b = top; b > top - 24; --b) mant = (mant << 1) | ((dg[b / 32] >> (b % 32)) & 1u);
+    int rnd = (int)((dg[(top - 24) / 32] >> ((top - 24) % 32)) & 1u);
+    int sticky = 0;
+    for (int b = top - 25; b >= 0 && !sticky; --b) sticky = (int)((dg[b / 32] >> (b % 32)) & 1u);
+    if (rnd && (sticky || (mant & 1u))) {
+        ++mant;
+        if (mant == (1u << 24)) { mant >>= 1; ++top; }
+    }
+    if (top - 149 > 127) return INFINITY;
+    return ldexpf((float)mant, top - 23 - 149);
+}
+
 int64_t orc_ingest(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v, const float *w,
                    const int32_t *orig_in, int32_t order, int64_t *row_ptr, int32_t *col, float *w_out,
                    int32_t *eid, int32_t *orig_out, int64_t *n_dropped)
 {
     for (int64_t q = 0; q < m_in; ++q)
         if (u[q] < 0 || u[q] >= n || v[q] < 0 || v[q] >= n) return -1;
+    if (w)
+        for (int64_t q = 0; q < m_in; ++q)
+            if (!(w[q] > 0.0f && w[q] <= FLT_MAX)) return -2;      /* the graph model: finite w > 0 */
     orc_pair *pr = (orc_pair *)malloc(sizeof(orc_pair) * (size_t)(m_in > 0 ? m_in : 1));
     int64_t k = 0;
     for (int64_t q = 0; q < m_in; ++q) {
@@ -598,24 +647,26 @@ int64_t orc_ingest(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v, 
         ++k;
     }
     qsort(pr, (size_t)k, sizeof(orc_pair), orc_cmp_pair);
-    /* merge repeated pairs: one edge, weights summed in list order */
+    /* merge repeated pairs: one edge, weight the exact sum of the listed
+     * weights rounded once to single precision */
     int64_t *ea = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k > 0 ? k : 1));
     int64_t *eb = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k > 0 ? k : 1));
     float *ew = (float *)malloc(sizeof(float) * (size_t)(k > 0 ? k : 1));
+    float *run = (float *)malloc(sizeof(float) * (size_t)(k > 0 ? k : 1));
     int64_t m = 0;
     for (int64_t q = 0; q < k;) {
         int64_t r = q;
-        double sum = 0.0;
         while (r < k && pr[r].a == pr[q].a && pr[r].b == pr[q].b) {
-            if (w) sum += (double)w[pr[r].idx];
+            if (w) run[r - q] = w[pr[r].idx];
             ++r;
         }
         ea[m] = pr[q].a;
         eb[m] = pr[q].b;
-        ew[m] = (float)sum;
+        ew[m] = w ? orc_exact_sum_f32(run, r - q) : 0.0f;
         ++m;
         q = r;
     }
+    free(run);
     free(pr);
     /* vertex storage order */
     int64_t *new_of = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));

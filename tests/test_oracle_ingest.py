@@ -2,14 +2,19 @@
 model of Section 2) by brute force on small lists and by invariants:
 
   - a Python dictionary build of the same reading (pairs unordered, loops
-    dropped, repeats merged with weights summed in list order) gives the same
-    arrays, entry for entry;
+    dropped, repeats merged with the exact sum of their weights rounded once
+    to single precision, by fractions.Fraction and an exact nearest-float
+    search) gives the same arrays, entry for entry;
+  - the exact sum itself against Fraction arithmetic over weights spanning
+    the whole float range (subnormals included), and hand-worked ties;
   - the CSR is symmetric, rows ascending, edge ids paired and numbered in
     (smaller, larger) order; feeding its own edge list back is a fixed point;
   - the decreasing-degree order really is one, ties by listed id, and keeps
     the edge set (through orig_id);
   - out-of-range endpoints are refused; the empty list gives an empty graph.
 """
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -33,6 +38,19 @@ def _random_list(n, m_in, seed, loops=True, dups=True):
     return u.astype(np.int32), v.astype(np.int32), w
 
 
+def _round_f32(fr):
+    """The float32 nearest to the rational fr (ties to the even mantissa),
+    found by exact comparison among float32 neighbours."""
+    # half an ulp above FLT_MAX is a tie, which goes to the even inf
+    if fr >= Fraction(float(np.finfo(np.float32).max)) + Fraction(2) ** 103:
+        return np.float32(np.inf)
+    f = np.float32(float(fr))
+    cands = {f, np.nextafter(f, np.float32(np.inf)), np.nextafter(f, np.float32(-np.inf))}
+    cands = [c for c in cands if np.isfinite(c)]
+    best = min(cands, key=lambda c: (abs(Fraction(float(c)) - fr), int(np.array(c).view(np.uint32)) & 1))
+    return np.float32(best)
+
+
 def _brute(n, u, v, w):
     sums = {}
     for q in range(len(u)):
@@ -40,7 +58,7 @@ def _brute(n, u, v, w):
         if a == b:
             continue
         key = (min(a, b), max(a, b))
-        sums[key] = sums.get(key, 0.0) + float(w[q])     # double, list order
+        sums[key] = sums.get(key, Fraction(0)) + Fraction(float(w[q]))     # exact
     edges = sorted(sums)
     eid = {e: i for i, e in enumerate(edges)}
     rows = [[] for _ in range(n)]
@@ -52,7 +70,7 @@ def _brute(n, u, v, w):
         for j in sorted(rows[i]):
             e = (min(i, j), max(i, j))
             col.append(j)
-            ws.append(np.float32(sums[e]))
+            ws.append(_round_f32(sums[e]))
             ids.append(eid[e])
         row_ptr.append(len(col))
     return (np.array(row_ptr), np.array(col, dtype=np.int32), np.array(ws, dtype=np.float32),
@@ -159,3 +177,43 @@ def test_unweighted_lists_and_edge_cases():
         oracle.ingest(3, [0, 3], [1, 1])
     with pytest.raises(ValueError):
         oracle.ingest(3, [-1], [1])
+
+
+def test_exact_sum_against_fractions():
+    rng = np.random.default_rng(21)
+    tiny = np.float32(2.0 ** -149)
+    for trial in range(40):
+        k = int(rng.integers(1, 60))
+        # magnitudes spread over the whole float range, subnormals included
+        x = (rng.uniform(1, 2, k) * 2.0 ** rng.integers(-149, 100, k)).astype(np.float32)
+        x = np.maximum(x, tiny)
+        want = _round_f32(sum((Fraction(float(t)) for t in x), Fraction(0)))
+        assert oracle.exact_sum_f32(x) == want, (trial, x)
+    # the same order-free result for any permutation
+    x = (rng.uniform(0.5, 2, 500) * 2.0 ** rng.integers(-40, 40, 500)).astype(np.float32)
+    s0 = oracle.exact_sum_f32(x)
+    for _ in range(3):
+        assert oracle.exact_sum_f32(rng.permutation(x)) == s0
+
+
+def test_exact_sum_hand_cases():
+    f = np.float32
+    e = lambda k: f(2.0 ** k)
+    s = oracle.exact_sum_f32
+    assert s([f(1.0), e(-24)]) == f(1.0)                              # a tie goes to the even 1.0
+    assert s([f(1.0), e(-24), e(-60)]) == f(1.0 + 2.0 ** -23)         # just above the tie
+    assert s([f(1.0 + 2.0 ** -23), e(-24)]) == f(1.0 + 2.0 ** -22)    # a tie with an odd mantissa
+    assert s([e(-149), e(-149)]) == e(-148)                           # subnormals add exactly
+    assert s([f(np.finfo(np.float32).max)] * 2) == np.inf
+    assert s([f(3.0)]) == f(3.0) and s([]) == f(0.0)
+    # summing in double in list order would give 1.0 here: the exact sum does not
+    x = [f(1.0), e(-24), e(-60)]
+    assert f(np.float64(1.0) + 2.0 ** -24 + 2.0 ** -60) == f(1.0)
+    assert s(x) == f(1.0 + 2.0 ** -23)
+
+
+def test_ingest_refuses_non_positive_weights():
+    u, v = np.array([0, 1], np.int32), np.array([1, 2], np.int32)
+    for bad in (0.0, -1.0, np.inf, np.nan):
+        with pytest.raises(ValueError):
+            oracle.ingest(3, u, v, np.array([1.0, bad], np.float32))
