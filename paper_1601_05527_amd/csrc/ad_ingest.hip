@@ -4,16 +4,17 @@
 //
 // Readings (shared with the oracle, which is written separately): (u, v) and
 // (v, u) name the same edge; self-loops are dropped; repeated pairs become
-// one edge whose weight is the sum of the listed weights, added in double in
-// list order and rounded to single precision; edge ids enumerate the edges
+// one edge whose weight is the exact sum of the listed weights rounded once
+// to single precision (listed weights must be finite and positive, as the
+// graph model requires); edge ids enumerate the edges
 // in (smaller endpoint, larger endpoint) order, the CSR order of their upper
 // entries; rows list neighbours in ascending order; the decreasing-degree
 // order breaks ties by listed id, and orig_id names the listed vertex.
 //
 // The pipeline: canonical 64-bit pair keys, a stable radix sort (rocPRIM) of
 // (key, list index), run heads and their scan (edge ids), run bounds, and
-// the weights of every run summed in list order (one thread per short run,
-// one wave per long run, the same double additions in the same order); for
+// the exact weight sum of every run (one thread per short run, one wave per
+// long run); for
 // the degree order a sort of (degree, id) vertex keys and a second pair sort
 // under the new labels; then per-row counts from the run lengths of the
 // sorted endpoints (no atomics, so hub vertices cost nothing extra), their
@@ -26,6 +27,7 @@
 #include <rocprim/rocprim.hpp>
 
 #include <algorithm>
+#include <cfloat>
 #include <cstdint>
 
 namespace ad {
@@ -42,11 +44,12 @@ static unsigned bits_for(int64_t n) {
 // Pair key (smaller << 32 | larger), NO_PAIR for self-loops; endpoints out
 // of [0, n) raise the error flag (and sort last).
 __global__ void k_pair_keys(int64_t m_in, int64_t n, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
-                            unsigned long long *__restrict__ key, uint32_t *__restrict__ idx,
-                            unsigned int *__restrict__ err) {
+                            const float *__restrict__ w, unsigned long long *__restrict__ key,
+                            uint32_t *__restrict__ idx, unsigned int *__restrict__ err) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m_in; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t a = u[q], b = v[q];
         unsigned long long k = NO_PAIR;
+        if (w && !(w[q] > 0.0f && w[q] <= FLT_MAX)) atomicOr(err, 2u);
         if (a < 0 || a >= n || b < 0 || b >= n) {
             atomicOr(err, 1u);
         } else if (a != b) {
@@ -78,46 +81,145 @@ __global__ void k_run_bounds(int64_t count, const unsigned long long *__restrict
     }
 }
 
-constexpr uint32_t MERGE_SHORT = 16;     // runs up to this length are summed by one thread
+// Merged weights: the exact sum of a run's listed weights, rounded once to
+// single precision (to nearest, ties to even), so no order of additions
+// matters and a run can be summed by many lanes.  A positive finite float
+// x is mant * 2^(shift - 149) with mant < 2^24 and 0 <= shift <= 253.  When
+// every value of a run lies within 53 bits of one another (the bit span of
+// the set plus the bits its count adds), every partial sum is exact in
+// double and the double sum, rounded to float, is the answer; otherwise the
+// run is summed as an integer count of 2^-149 in XDIG base-2^32 digits with
+// deferred carries.
+constexpr uint32_t MERGE_SHORT = 16;     // runs up to this length are summed by one thread,
+constexpr uint32_t MERGE_WAVE = 4096;    // up to this one by one wave, longer ones by a workgroup
+constexpr int MERGE_TB = 1024;           // threads of a long run's workgroup
+constexpr int XDIG = 11;                 // 352 bits: 2^31 floats below 2^277 units each
 
-// One thread per run: the edge's endpoints and, for a short run, its weight:
-// the listed weights summed in list order (the sort is stable) in double.
-// Longer runs go to a list for k_merge_long.
+__device__ __forceinline__ void f32_split(float x, uint32_t &mant, int &shift) {
+    const uint32_t b = __float_as_uint(x);
+    const uint32_t ex = (b >> 23) & 0xffu, fr = b & 0x7fffffu;
+    mant = ex ? (fr | 0x800000u) : fr;
+    shift = ex ? (int)ex - 1 : 0;
+}
+
+__device__ __forceinline__ int ceil_log2_u32(uint32_t c) { return c <= 1 ? 0 : 32 - __clz((int)(c - 1)); }
+
+// Digits hold values below 2^63 for fewer than 2^31 added floats.
+__device__ __forceinline__ void digits_add(unsigned long long (&acc)[XDIG], float x) {
+    uint32_t mant;
+    int shift;
+    f32_split(x, mant, shift);
+    const int k = shift >> 5;
+    const unsigned long long add = (unsigned long long)mant << (shift & 31);
+    const unsigned long long lo = add & 0xffffffffull, hi = add >> 32;
+#pragma unroll
+    for (int d = 0; d < XDIG; ++d) {
+        acc[d] += (d == k) ? lo : 0ull;
+        acc[d] += (d == k + 1) ? hi : 0ull;
+    }
+}
+
+// The float nearest to acc * 2^-149 (ties to even; +inf past the range).
+__device__ float digits_round(const unsigned long long (&acc)[XDIG]) {
+    uint32_t dg[XDIG];
+    unsigned long long carry = 0;
+#pragma unroll
+    for (int d = 0; d < XDIG; ++d) {
+        const unsigned long long t = acc[d] + carry;
+        dg[d] = (uint32_t)t;
+        carry = t >> 32;
+    }
+    int top = -1;
+#pragma unroll
+    for (int d = XDIG - 1; d >= 0; --d)
+        if (top < 0 && dg[d] != 0u) top = 32 * d + 31 - __clz((int)dg[d]);
+    if (top < 0) return 0.0f;
+    if (top <= 23) return ldexpf((float)dg[0], -149);       // below 2^24 units: exact
+    // bits [top - 24, top] from the digits k .. k + 2, and whether any bit below is set
+    const int low = top - 24, k = low >> 5, o = low & 31;
+    uint32_t d0 = 0, d1 = 0, d2 = 0;
+    bool sticky = false;
+#pragma unroll
+    for (int d = 0; d < XDIG; ++d) {
+        d0 = (d == k) ? dg[d] : d0;
+        d1 = (d == k + 1) ? dg[d] : d1;
+        d2 = (d == k + 2) ? dg[d] : d2;
+        sticky |= (d < k) && dg[d] != 0u;
+    }
+    sticky |= o != 0 && (d0 & ((1u << o) - 1u)) != 0u;
+    unsigned long long win = ((unsigned long long)d1 << 32) | d0;
+    if (o) win = (win >> o) | ((unsigned long long)d2 << (64 - o));
+    uint32_t mant = (uint32_t)(win >> 1) & 0xffffffu;
+    const bool rnd = (win & 1ull) != 0ull;
+    if (rnd && (sticky || (mant & 1u))) {
+        ++mant;
+        if (mant == (1u << 24)) {
+            mant >>= 1;
+            ++top;
+        }
+    }
+    if (top - 149 > 127) return __int_as_float(0x7f800000);
+    return ldexpf((float)mant, top - 23 - 149);
+}
+
+// One thread per run: the edge's endpoints and, for a short run, its
+// weight.  Longer runs go to lists for k_merge_long and k_merge_big.
 __global__ void k_merge_runs(int64_t m, const uint2 *__restrict__ bounds, const unsigned long long *__restrict__ key,
                              const uint32_t *__restrict__ idx, const float *__restrict__ w, int32_t *__restrict__ ea,
                              int32_t *__restrict__ eb, float *__restrict__ ew, uint32_t *__restrict__ long_list,
-                             unsigned int *__restrict__ long_count) {
+                             unsigned int *__restrict__ long_count, uint32_t *__restrict__ big_list,
+                             unsigned int *__restrict__ big_count) {
     // the loop bound is uniform per wave (blocks are whole waves), so every
     // lane reaches the wave-wide append
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t m_pad = ceil_div_dev(m, stride) * stride;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m_pad; e += stride) {
-        bool defer = false;
+        bool defer = false, big = false;
         if (e < m) {
             const uint2 b = bounds[e];
             const unsigned long long k = key[b.x];
             ea[e] = (int32_t)(k >> 32);
             eb[e] = (int32_t)(k & 0xffffffffull);
-            if (w) {
-                if (b.y - b.x <= MERGE_SHORT) {
-                    double sum = 0.0;
-                    for (uint32_t r = b.x; r < b.y; ++r) sum += (double)w[idx[r]];
+            const uint32_t len = b.y - b.x;
+            if (w && len == 1) {
+                ew[e] = w[idx[b.x]];
+            } else if (w && len <= MERGE_SHORT) {
+                int lo = 1 << 20, hi = -1;
+                double sum = 0.0;
+                for (uint32_t r = b.x; r < b.y; ++r) {
+                    const float x = w[idx[r]];
+                    uint32_t mant;
+                    int shift;
+                    f32_split(x, mant, shift);
+                    lo = min(lo, shift);
+                    hi = max(hi, shift + 24);
+                    sum += (double)x;
+                }
+                if (hi + ceil_log2_u32(len) - lo <= 53) {
                     ew[e] = (float)sum;
                 } else {
-                    defer = true;
+                    unsigned long long acc[XDIG] = {};
+                    for (uint32_t r = b.x; r < b.y; ++r) digits_add(acc, w[idx[r]]);
+                    ew[e] = digits_round(acc);
                 }
+            } else if (w) {
+                defer = true;
+                big = len > MERGE_WAVE;
             }
         }
-        const unsigned int at = wave_append(defer, long_count);
-        if (defer) long_list[at] = (uint32_t)e;
+        const bool to_long = defer && !big, to_big = defer && big;
+        const unsigned int at = wave_append(to_long, long_count);
+        if (to_long) long_list[at] = (uint32_t)e;
+        const unsigned int bt = wave_append(to_big, big_count);
+        if (to_big) big_list[bt] = (uint32_t)e;
     }
 }
 
-// One wave per long run.  The lanes load the run's weights MERGE_GROUP
-// chunks of 64 at a time, the next group in flight while the wave adds the
-// current one in list order (each value broadcast from its lane), so the
-// double sum is the one-thread sum; only the chain of additions is serial.
-constexpr int MERGE_GROUP = 8;
+// One wave per run of MERGE_SHORT < length <= MERGE_WAVE: every lane sums
+// its share (double partial sums when the whole run spans at most 53 bits,
+// digits otherwise), then the wave combines them; both are exact, so the
+// order does not matter.
+constexpr int MERGE_LOADS = 4;           // weights each lane loads per step
 
 __global__ __launch_bounds__(IBLOCK) void k_merge_long(const unsigned int *__restrict__ long_count,
                                                        const uint32_t *__restrict__ long_list,
@@ -130,40 +232,84 @@ __global__ __launch_bounds__(IBLOCK) void k_merge_long(const unsigned int *__res
     for (int64_t q = (int64_t)blockIdx.x * (IBLOCK / WAVE) + (threadIdx.x >> 6); q < count; q += nw) {
         const uint32_t e = long_list[q];
         const uint2 b = bounds[e];
+        int lo = 1 << 20, hi = -1;
         double sum = 0.0;
-        int cur[MERGE_GROUP], nxt[MERGE_GROUP];
+        for (uint32_t base = b.x; base < b.y; base += WAVE * MERGE_LOADS) {
+            float x[MERGE_LOADS];
 #pragma unroll
-        for (int c = 0; c < MERGE_GROUP; ++c) {
-            const uint32_t r = b.x + (uint32_t)(c * WAVE + lane);
-            cur[c] = r < b.y ? __float_as_int(w[idx[r]]) : 0;
-        }
-        for (uint32_t base = b.x; base < b.y; base += MERGE_GROUP * WAVE) {
-            const uint32_t nbase = base + MERGE_GROUP * WAVE;
-#pragma unroll
-            for (int c = 0; c < MERGE_GROUP; ++c) {
-                const uint32_t r = nbase + (uint32_t)(c * WAVE + lane);
-                nxt[c] = r < b.y ? __float_as_int(w[idx[r]]) : 0;
-            }
-            const uint32_t left = b.y - base;
-            if (left >= (uint32_t)(MERGE_GROUP * WAVE)) {
-#pragma unroll
-                for (int c = 0; c < MERGE_GROUP; ++c) {
-#pragma unroll
-                    for (int j = 0; j < WAVE; ++j)
-                        sum += (double)__int_as_float(__builtin_amdgcn_readlane(cur[c], j));
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < MERGE_GROUP; ++c) {
-                    const uint32_t cnt = left > (uint32_t)(c * WAVE) ? min((uint32_t)WAVE, left - c * WAVE) : 0u;
-                    for (uint32_t j = 0; j < cnt; ++j)
-                        sum += (double)__int_as_float(__builtin_amdgcn_readlane(cur[c], (int)j));
-                }
+            for (int t = 0; t < MERGE_LOADS; ++t) {
+                const uint32_t r = base + (uint32_t)(t * WAVE + lane);
+                x[t] = r < b.y ? w[idx[r]] : 0.0f;
             }
 #pragma unroll
-            for (int c = 0; c < MERGE_GROUP; ++c) cur[c] = nxt[c];
+            for (int t = 0; t < MERGE_LOADS; ++t) {
+                if (x[t] == 0.0f) continue;                  // past the run's end
+                uint32_t mant;
+                int shift;
+                f32_split(x[t], mant, shift);
+                lo = min(lo, shift);
+                hi = max(hi, shift + 24);
+                sum += (double)x[t];
+            }
         }
-        if (lane == 0) ew[e] = (float)sum;
+        for (int o = WAVE / 2; o >= 1; o >>= 1) {
+            lo = min(lo, __shfl_xor(lo, o, WAVE));
+            hi = max(hi, __shfl_xor(hi, o, WAVE));
+            sum += __shfl_xor(sum, o, WAVE);
+        }
+        if (hi + ceil_log2_u32(b.y - b.x) - lo <= 53) {
+            if (lane == 0) ew[e] = (float)sum;
+            continue;
+        }
+        unsigned long long acc[XDIG] = {};
+        for (uint32_t r = b.x + (uint32_t)lane; r < b.y; r += WAVE) digits_add(acc, w[idx[r]]);
+#pragma unroll
+        for (int d = 0; d < XDIG; ++d)
+            for (int o = WAVE / 2; o >= 1; o >>= 1) acc[d] += __shfl_xor(acc[d], o, WAVE);
+        if (lane == 0) ew[e] = digits_round(acc);
+    }
+}
+
+// One workgroup of MERGE_TB threads per run longer than MERGE_WAVE: digits
+// always (exact at any length), MERGE_LOADS weights per thread in flight.
+__global__ __launch_bounds__(MERGE_TB) void k_merge_big(const unsigned int *__restrict__ big_count,
+                                                        const uint32_t *__restrict__ big_list,
+                                                        const uint2 *__restrict__ bounds,
+                                                        const uint32_t *__restrict__ idx, const float *__restrict__ w,
+                                                        float *__restrict__ ew) {
+    __shared__ unsigned long long part[MERGE_TB / WAVE][XDIG];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
+    const unsigned int count = *big_count;
+    for (unsigned int q = blockIdx.x; q < count; q += gridDim.x) {
+        const uint32_t e = big_list[q];
+        const uint2 b = bounds[e];
+        unsigned long long acc[XDIG] = {};
+        for (uint32_t base = b.x; base < b.y; base += MERGE_TB * MERGE_LOADS) {
+            float x[MERGE_LOADS];
+#pragma unroll
+            for (int t = 0; t < MERGE_LOADS; ++t) {
+                const uint32_t r = base + (uint32_t)(t * MERGE_TB) + threadIdx.x;
+                x[t] = r < b.y ? w[idx[r]] : 0.0f;
+            }
+#pragma unroll
+            for (int t = 0; t < MERGE_LOADS; ++t) digits_add(acc, x[t]);     // a zero adds nothing
+        }
+#pragma unroll
+        for (int d = 0; d < XDIG; ++d) {
+            for (int o = WAVE / 2; o >= 1; o >>= 1) acc[d] += __shfl_xor(acc[d], o, WAVE);
+            if (lane == 0) part[wv][d] = acc[d];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int d = 0; d < XDIG; ++d) {
+                unsigned long long t = 0;
+                for (int k = 0; k < MERGE_TB / WAVE; ++k) t += part[k][d];
+                acc[d] = t;
+            }
+            ew[e] = digits_round(acc);
+        }
+        __syncthreads();
     }
 }
 
@@ -293,7 +439,7 @@ struct IngestLayout {
     uint64_t *lower_start, *upper_start, *deg64;      // [n]
     unsigned long long *vkey0, *vkey1;   // [n]
     uint32_t *vid0, *vid1;               // [n]
-    unsigned int *flags;                 // [4]: error, d_max, m
+    unsigned int *flags;                 // [4]: error bits, d_max, runs for a workgroup, runs for a wave
     void *temp;                          // rocPRIM temporary storage
     size_t temp_bytes;
 };
@@ -401,7 +547,7 @@ static ad_status ingest_impl(int64_t n, int64_t m_in, const int32_t *u, const in
     if (s != AD_OK) return s;
     int64_t m = 0;
     if (m_in > 0) {
-        hipLaunchKernelGGL(k_pair_keys, dim3(igrid(m_in)), dim3(IBLOCK), 0, st, m_in, n, u, v, L.key0, L.idx0,
+        hipLaunchKernelGGL(k_pair_keys, dim3(igrid(m_in)), dim3(IBLOCK), 0, st, m_in, n, u, v, w, L.key0, L.idx0,
                            L.flags);
         AD_LAUNCH_CHECK("k_pair_keys");
         size_t tb = L.temp_bytes;
@@ -417,7 +563,8 @@ static ad_status ingest_impl(int64_t n, int64_t m_in, const int32_t *u, const in
         AD_HIP(hipMemcpyAsync(&last[0], L.edge_of + (m_in - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         AD_HIP(hipMemcpyAsync(&last[1], L.head + (m_in - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         AD_HIP(hipStreamSynchronize(st));
-        if (hflags[0]) return fail(AD_ERR_GRAPH, "edge list names a vertex outside [0, n)");
+        if (hflags[0] & 1u) return fail(AD_ERR_GRAPH, "edge list names a vertex outside [0, n)");
+        if (hflags[0] & 2u) return fail(AD_ERR_GRAPH, "a listed weight is not finite and positive");
         m = (int64_t)last[0] + (int64_t)last[1];
         if (m > 0) {
             // run bounds in key0 (free after the sort), long runs listed in idx0
@@ -425,13 +572,18 @@ static ad_status ingest_impl(int64_t n, int64_t m_in, const int32_t *u, const in
             hipLaunchKernelGGL(k_run_bounds, dim3(igrid(m_in)), dim3(IBLOCK), 0, st, m_in, L.key1, L.head, L.edge_of,
                                bounds);
             AD_LAUNCH_CHECK("k_run_bounds");
+            // runs for a wave listed in idx0, runs for a workgroup in ew2 (both free here)
+            uint32_t *big_list = reinterpret_cast<uint32_t *>(L.ew2);
             hipLaunchKernelGGL(k_merge_runs, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, bounds, L.key1, L.idx1, w, L.ea,
-                               L.eb, L.ew, L.idx0, L.flags + 3);
+                               L.eb, L.ew, L.idx0, L.flags + 3, big_list, L.flags + 2);
             AD_LAUNCH_CHECK("k_merge_runs");
             if (w) {
                 hipLaunchKernelGGL(k_merge_long, dim3(1024), dim3(IBLOCK), 0, st, L.flags + 3, L.idx0, bounds, L.idx1,
                                    w, L.ew);
                 AD_LAUNCH_CHECK("k_merge_long");
+                hipLaunchKernelGGL(k_merge_big, dim3(1024), dim3(MERGE_TB), 0, st, L.flags + 2, big_list, bounds,
+                                   L.idx1, w, L.ew);
+                AD_LAUNCH_CHECK("k_merge_big");
             }
         }
     }

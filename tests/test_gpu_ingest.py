@@ -115,6 +115,43 @@ def test_ingest_run_lengths_at_the_wave_bounds(api):
         _compare(dg, oracle.ingest(n, u, v, w, order=1 if by_degree else 0))
 
 
+def test_ingest_exact_weight_sums(api):
+    """Merged weights are exact sums rounded once: ties to even, a value
+    just above a tie, subnormals, runs whose values span more than 53 bits
+    (the digit path) and less (the double path), short and long, in
+    shuffled list order."""
+    announce("ingest exact weight sums")
+    f = np.float32
+    rng = np.random.default_rng(29)
+    runs = [[1.0, 2.0 ** -24], [1.0, 2.0 ** -24, 2.0 ** -60], [1.0 + 2.0 ** -23, 2.0 ** -24],
+            [2.0 ** -149] * 3, [3.0], [2.0 ** 100, 2.0 ** -100, 2.0 ** -149]]
+    runs.append(list(rng.uniform(1, 2, 40) * 2.0 ** rng.integers(-140, 100, 40)))      # short, digits
+    runs.append(list(rng.uniform(1, 2, 900) * 2.0 ** rng.integers(-3, 3, 900)))        # long, double
+    runs.append(list(rng.uniform(1, 2, 5000) * 2.0 ** rng.integers(-120, 120, 5000)))  # long, digits
+    runs.append([1.0] + [2.0 ** -30] * 63 + [2.0 ** -90] * 200)                           # long, near a tie
+    u, v, w = [], [], []
+    for r, vals in enumerate(runs):
+        u += [2 * r] * len(vals)
+        v += [2 * r + 1] * len(vals)
+        w += vals
+    u, v = np.array(u, np.int32), np.array(v, np.int32)
+    w = np.maximum(np.array(w, dtype=np.float32), f(2.0 ** -149))
+    perm = rng.permutation(u.size)
+    u, v, w = u[perm], v[perm], w[perm]
+    n = 2 * len(runs)
+    for by_degree in (False, True):
+        dg = _run(api, n, u, v, w, by_degree=by_degree)
+        _compare(dg, oracle.ingest(n, u, v, w, order=1 if by_degree else 0))
+    dg = _run(api, n, u, v, w, by_degree=False)
+    got = _np(dg.w)[_np(dg.row_ptr)[:-1:2]]          # row 2r holds the one edge of run r
+    assert got[0] == f(1.0) and got[1] == f(1.0 + 2.0 ** -23) and got[2] == f(1.0 + 2.0 ** -22)
+    assert got[3] == f(3 * 2.0 ** -149)
+    for bad in (0.0, -2.0, np.inf, np.nan):
+        with pytest.raises(api.ADError) as ex:
+            _run(api, 3, np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.array([1.0, bad], np.float32))
+        assert ex.value.status == 4       # AD_ERR_GRAPH
+
+
 def test_ingest_orig_ids_and_reuse(api):
     """Names pass through; the ingested graph relaxes exactly like the same
     CSR uploaded from the host."""
