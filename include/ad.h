@@ -271,9 +271,10 @@ size_t ad_ingest_workspace_size(int64_t n, int64_t m_in);
 /* An undirected edge list into the symmetric CSR of the graph model every
  * other call reads (Section 2: undirected, no self-loops, no repeated
  * pairs).  (u[q], v[q]) and (v[q], u[q]) name the same edge; self-loops are
- * dropped; repeated pairs become one edge whose weight is the sum of the
- * listed weights (added in double in list order, rounded to single
- * precision).  Edge ids enumerate the edges in (smaller, larger endpoint)
+ * dropped; repeated pairs become one edge whose weight is the exact sum of
+ * the listed weights, rounded once to single precision (to nearest, ties to
+ * even), so it does not depend on the list order.  Listed weights must be
+ * finite and positive.  Edge ids enumerate the edges in (smaller, larger endpoint)
  * order (the CSR order of their upper entries); every row lists its
  * neighbours in ascending order.
  *   n, m_in: vertices and listed pairs, both < 2^31; u, v: DEVICE [m_in].
@@ -288,7 +289,8 @@ size_t ad_ingest_workspace_size(int64_t n, int64_t m_in);
  *   degree and m_in - m (self-loops plus merged repeats); d_max_host and
  *   n_dropped_host may be NULL.
  * The sorts are rocPRIM's radix sort (stable).  SYNCHRONISES `stream` (the
- * edge count sizes the later passes).  Errors: AD_ERR_GRAPH when an endpoint
+ * edge count sizes the later passes).  Errors: AD_ERR_GRAPH when a weight is
+ * not finite and positive or when an endpoint
  * lies outside [0, n) (nothing is written past the check);
  * AD_ERR_INVALID_ARG / AD_ERR_UNSUPPORTED for bad arguments or sizes;
  * AD_ERR_WORKSPACE for a short or misaligned workspace. */
