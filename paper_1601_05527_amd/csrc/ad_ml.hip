@@ -297,13 +297,15 @@ __global__ void k_ml_count(int64_t m, const uint8_t *__restrict__ keep, unsigned
 
 // ---------------------------------------------------------- coarsening --
 
+constexpr int SEED_BATCH = 4;            // seed rounds per read-back
+
 struct AggLayout {
     double *smax;                 // [n]
     uint8_t *state;               // [n]
     uint8_t *sflag;               // [nnz] coupling of every entry
     unsigned int *rank;           // [n] seed flags, scanned in place into aggregate ids
     unsigned int *total;          // [1] number of seeds
-    unsigned long long *left;     // [1] vertices still undecided after a round
+    unsigned long long *left;     // [SEED_BATCH] vertices still undecided after each round of a batch
     ScanScratch scan;
 };
 
@@ -316,7 +318,7 @@ static size_t agg_layout(int64_t n, int64_t nnz, void *ws, size_t ws_bytes, AggL
     l.sflag = c.take<uint8_t>((size_t)std::max<int64_t>(1, nnz));
     l.rank = c.take<unsigned int>(nn);
     l.total = c.take<unsigned int>(1);
-    l.left = c.take<unsigned long long>(1);
+    l.left = c.take<unsigned long long>(SEED_BATCH);
     const size_t nblk = scan_scratch_blocks((int64_t)nn);
     l.scan.blk_v = c.take<unsigned int>(nblk);
     l.scan.blk_w = c.take<unsigned long long>(nblk);
@@ -348,15 +350,19 @@ static ad_status aggregate_impl(const ad_graph *g, const Tr *rho, double eps, do
     ad_status s = fill_u8(L.state, 0, n, st);
     if (s != AD_OK) return s;
     // each round decides at least the undecided vertex of highest priority
-    for (int64_t round = 0;; ++round) {
+    // rounds are enqueued SEED_BATCH at a time and only the last one's count
+    // is read back (a round after the last undecided vertex changes nothing)
+    for (int64_t round = 0;; round += SEED_BATCH) {
         if (round > n) return fail(AD_ERR_INTERNAL, "seed rounds did not settle");
-        s = fill_u64(L.left, 0, 1, st);
+        s = fill_u64(L.left, 0, SEED_BATCH, st);
         if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_ml_seed_round, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->col, L.sflag,
-                           L.state, L.left);
-        AD_LAUNCH_CHECK("k_ml_seed_round");
+        for (int b = 0; b < SEED_BATCH; ++b) {
+            hipLaunchKernelGGL(k_ml_seed_round, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->col,
+                               L.sflag, L.state, L.left + b);
+            AD_LAUNCH_CHECK("k_ml_seed_round");
+        }
         unsigned long long waiting = 0;
-        AD_HIP(hipMemcpyAsync(&waiting, L.left, sizeof(waiting), hipMemcpyDeviceToHost, st));
+        AD_HIP(hipMemcpyAsync(&waiting, L.left + (SEED_BATCH - 1), sizeof(waiting), hipMemcpyDeviceToHost, st));
         AD_HIP(hipStreamSynchronize(st));
         if (waiting == 0) break;
     }
