@@ -93,10 +93,9 @@ __device__ __forceinline__ int64_t common_count(const int32_t *__restrict__ col,
 
 // Every edge (i, j), i < j, adds |N_i ∩ N_j| to both ends (each triangle at i
 // is then counted once through each of its two edges at i).  Pairs whose
-// shorter row exceeds TRI_LANE are listed for the wave kernel.
+// shorter row exceeds TRI_LANE are left to k_triangles_hub.
 __global__ void k_triangles_lane(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                                 unsigned long long *__restrict__ lam2, int2 *__restrict__ big,
-                                 unsigned int *__restrict__ nbig) {
+                                 unsigned long long *__restrict__ lam2) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
     for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
@@ -114,12 +113,6 @@ __global__ void k_triangles_lane(int64_t n, const int64_t *__restrict__ row_ptr,
             const bool i_short = (b1 - b0) <= (c1 - c0);
             const int64_t shorter = i_short ? b1 - b0 : c1 - c0;
             const bool is_big = up && shorter > TRI_LANE;
-            // long pairs go to the list, one counter update per wave
-            const unsigned long long mask = __ballot(is_big);
-            unsigned int first = 0;
-            if (mask != 0ull && lane == 0) first = atomicAdd(nbig, (unsigned int)__popcll(mask));
-            first = (unsigned int)__shfl((int)first, 0, WAVE);
-            if (is_big) big[first + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2((int32_t)i, j);
             if (up && !is_big) {
                 const int64_t t =
                     i_short ? common_count(col, b0, b1, c0, c1, 0, 1) : common_count(col, c0, c1, b0, b1, 0, 1);
@@ -132,23 +125,66 @@ __global__ void k_triangles_lane(int64_t n, const int64_t *__restrict__ row_ptr,
     }
 }
 
-// Listed pairs: one wave each, lanes striding over the shorter row.
-__global__ void k_triangles_wave(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                                 const int2 *__restrict__ big, const unsigned int *__restrict__ nbig,
-                                 unsigned long long *__restrict__ lam2) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const unsigned int nb = *nbig;
-    const unsigned int nw = gridDim.x * (PBLOCK / WAVE);
-    for (unsigned int k = blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); k < nb; k += nw) {
-        const int2 pr = big[k];
-        const int64_t b0 = row_ptr[pr.x], b1 = row_ptr[pr.x + 1], c0 = row_ptr[pr.y], c1 = row_ptr[pr.y + 1];
-        int64_t t = (b1 - b0) <= (c1 - c0) ? common_count(col, b0, b1, c0, c1, lane, WAVE)
-                                           : common_count(col, c0, c1, b0, b1, lane, WAVE);
-        for (int o = WAVE / 2; o >= 1; o >>= 1) t += __shfl_xor(t, o, WAVE);
-        if (lane == 0 && t) {
-            atomicAdd(&lam2[pr.x], (unsigned long long)t);
-            atomicAdd(&lam2[pr.y], (unsigned long long)t);
+// Pairs of rows both longer than TRI_LANE, each counted by the endpoint of
+// larger (degree, id): one workgroup per such row L holds N_L in LDS (when
+// it has at most TRI_LDS entries, else it is searched in memory) for all of
+// its pairs; each wave takes a neighbour j and its lanes, striding over
+// N_j, binary-search N_L.
+constexpr int TRI_LDS = 8192;
+
+__global__ __launch_bounds__(PBLOCK) void k_triangles_hub(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                          const int32_t *__restrict__ col,
+                                                          unsigned long long *__restrict__ lam2) {
+    __shared__ int32_t lrow[TRI_LDS];
+    __shared__ unsigned long long wsum[PBLOCK / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
+    for (int64_t L = blockIdx.x; L < n; L += gridDim.x) {
+        const int64_t l0 = row_ptr[L], l1 = row_ptr[L + 1], dl = l1 - l0;
+        if (dl <= TRI_LANE) continue;                       // uniform over the workgroup
+        const bool in_lds = dl <= TRI_LDS;
+        if (in_lds)
+            for (int64_t q = threadIdx.x; q < dl; q += PBLOCK) lrow[q] = col[l0 + q];
+        __syncthreads();
+        unsigned long long own = 0;
+        for (int64_t p = l0 + wv; p < l1; p += PBLOCK / WAVE) {
+            const int32_t j = col[p];
+            const int64_t c0 = row_ptr[j], c1 = row_ptr[j + 1], dj = c1 - c0;
+            if (dj <= TRI_LANE || dj > dl || (dj == dl && j > L)) continue;     // uniform over the wave
+            int64_t t = 0;
+            for (int64_t q = c0 + lane; q < c1; q += WAVE) {
+                const int32_t x = col[q];
+                if (in_lds) {
+                    int lo = 0, hi = (int)dl;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (lrow[mid] < x) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    t += (lo < dl && lrow[lo] == x) ? 1 : 0;
+                } else {
+                    int64_t lo = l0, hi = l1;
+                    while (lo < hi) {
+                        const int64_t mid = (lo + hi) >> 1;
+                        if (col[mid] < x) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    t += (lo < l1 && col[lo] == x) ? 1 : 0;
+                }
+            }
+            for (int o = WAVE / 2; o >= 1; o >>= 1) t += __shfl_xor(t, o, WAVE);
+            if (lane == 0 && t) {
+                atomicAdd(&lam2[j], (unsigned long long)t);
+                own += (unsigned long long)t;
+            }
         }
+        if (lane == 0) wsum[wv] = own;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int q = 0; q < PBLOCK / WAVE; ++q) tot += wsum[q];
+            if (tot) atomicAdd(&lam2[L], tot);
+        }
+        __syncthreads();     // lrow and wsum are reused by the next row
     }
 }
 
@@ -329,7 +365,6 @@ static size_t sub_layout(const ad_graph *g, void *ws, size_t ws_bytes, SubLayout
 
 struct PropLayout {
     unsigned long long *lam2;     // [n]
-    int2 *big;                    // [m] listed long pairs
     unsigned int *flags;          // [4]: listed pairs, changed
     unsigned long long *roots;    // [1]
     double *part_sum;             // [PREDUCE_BLOCKS]
@@ -342,7 +377,6 @@ static size_t prop_layout(const ad_graph *g, void *ws, size_t ws_bytes, PropLayo
     const size_t m = (size_t)std::max<int64_t>(1, g->m), n = (size_t)std::max<int64_t>(1, g->n);
     PropLayout l;
     l.lam2 = c.take<unsigned long long>(n);
-    l.big = c.take<int2>(m);
     l.flags = c.take<unsigned int>(4);
     l.roots = c.take<unsigned long long>(1);
     l.part_sum = c.take<double>(PREDUCE_BLOCKS);
@@ -476,12 +510,11 @@ extern "C" ad_status ad_graph_properties(const ad_graph *g, int64_t *lambda, dou
     s = fill_i32((int32_t *)L.flags, 0, 4, stream);
     if (s != AD_OK) return s;
     if (g->m > 0) {
-        hipLaunchKernelGGL(k_triangles_lane, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, L.lam2, L.big,
-                           L.flags);
+        hipLaunchKernelGGL(k_triangles_lane, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, L.lam2);
         AD_LAUNCH_CHECK("k_triangles_lane");
-        hipLaunchKernelGGL(k_triangles_wave, dim3(4096), dim3(PBLOCK), 0, stream, g->row_ptr, g->col, L.big, L.flags,
-                           L.lam2);
-        AD_LAUNCH_CHECK("k_triangles_wave");
+        hipLaunchKernelGGL(k_triangles_hub, dim3((unsigned)std::min<int64_t>(4096, n)), dim3(PBLOCK), 0, stream, n,
+                           g->row_ptr, g->col, L.lam2);
+        AD_LAUNCH_CHECK("k_triangles_hub");
     }
     hipLaunchKernelGGL(k_clustering, dim3(PREDUCE_BLOCKS), dim3(PBLOCK), 0, stream, n, g->row_ptr, L.lam2, lambda, c,
                        L.part_sum, L.part_cnt);
