@@ -466,3 +466,45 @@ def test_validate_graph_accepts_valid(api):
     announce("validate graph")
     for g in [G.gnm(500, 2000, 1), G.chung_lu(3000, 20000, seed=1), G.grid_long_range(20, 5)]:
         api.validate_graph(_dg(api, g))
+
+
+def test_ranking_from_two_host_threads(api):
+    """Two host threads, each with its own stream and workspace, fit both
+    orientations on different graphs at the same time, repeatedly (the long
+    ranking classes fork onto shared helper streams); every result equals
+    the same call made alone."""
+    announce("ranking from two host threads")
+    import threading
+    gs = [G.chung_lu(40_000, 600_000, seed=41), G.chung_lu(30_000, 500_000, seed=42)]
+    dgs = [api.DeviceGraph.from_host(g, "cuda") for g in gs]
+    rhos = []
+    for dg in dgs:
+        res = api.relax(dg, 8, 10, seed=3)
+        rhos.append(api.edge_dist(dg, res.x, res.minmax))
+    torch.cuda.synchronize()
+    alone = []
+    for dg, rho in zip(dgs, rhos):
+        kl, kg, nk, e = api.sparsify_fit_both(dg, rho, 0.3)
+        alone.append((_np(kl).copy(), _np(kg).copy(), e))
+    errors = []
+
+    def work(q):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(6):
+                    kl, kg, nk, e = api.sparsify_fit_both(dgs[q], rhos[q], 0.3)
+                    s.synchronize()
+                    if not (np.array_equal(_np(kl), alone[q][0]) and np.array_equal(_np(kg), alone[q][1])
+                            and e == alone[q][2]):
+                        errors.append(q)
+        except Exception as ex:      # reported below
+            errors.append(repr(ex))
+
+    th = [threading.Thread(target=work, args=(q,)) for q in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in th)
+    assert errors == []
