@@ -288,6 +288,19 @@ def run_chung_lu(args, api, torch, dev):
                         "step's own distances; synchronises for the fit"))
     del ws_b
 
+    # Algorithm 1's normalised distance (weighted-degree form) on the step's
+    # distances, then the LOCAL fit on it
+    rho_n = torch.empty_like(rho)
+    norm_ms = timer.run(lambda: api.normalize_dist(dg, rho, by_strength=True, out=rho_n), 5)
+    keep_nl, keep_ng = torch.empty_like(keep_l), torch.empty_like(keep_g)
+    _, _, _, (e_nl, e_ng) = api.sparsify_fit_both(dg, rho_n, TARGET, ws=ws_s, keep_local=keep_nl,
+                                                  keep_global=keep_ng, n_kept=torch.empty_like(nk))
+    normalized = {"ms": norm_ms, "e_local_fit": e_nl, "e_global_fit": e_ng,
+                  "what": ("per-vertex weighted degrees (a wave per row, FP64) and rho_e * sqrt(s_i s_j) for every "
+                           "edge (eps 0); the fits: LOCAL and GLOBAL to the same retention on the normalised "
+                           "distances")}
+    del rho_n, keep_nl, keep_ng
+
     # the property comparisons of Section 6 for the step's LOCAL selection
     props = {}
 
@@ -360,6 +373,7 @@ def run_chung_lu(args, api, torch, dev):
         gather_ceiling=gather,
         vendor_spmm=spmm,
         binned_selection=binned,
+        normalized_distance=normalized,
         ingest=ingest,
         properties=props,
         traffic_over_algorithmic=(roof["traffic"] / sb) if roof["traffic"] else None,
