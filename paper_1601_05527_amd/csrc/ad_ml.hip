@@ -18,8 +18,8 @@
 //     order); any other vertex joins the seed neighbour of largest delta_ij,
 //     ties by smaller name;
 //   - Galerkin coarse graph P^T L P: the fine edges' aggregate pairs with
-//     repeats merged and weights summed (ad_ingest; unit weights count
-//     edges), coarse vertices named by their seeds;
+//     repeats merged, their weights summed exactly (ad_ingest; unit weights
+//     count edges), coarse vertices named by their seeds;
 //   - a level is the coarsest at n <= n_min, at level levels - 1, with no
 //     edges, or when coarsening would keep more than 90% of the vertices;
 //   - level l uses graph id graph_id + l (test vectors and bin order);
@@ -41,10 +41,6 @@
 // The call allocates its per-level graphs and buffers (their sizes are
 // known only as coarsening proceeds) and frees them before it returns.
 #include "ad_internal.h"
-
-#include <cstring>    // before rocPRIM: its host code calls memset
-
-#include <rocprim/rocprim.hpp>
 
 #include <algorithm>
 #include <cstdint>
