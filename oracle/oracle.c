@@ -546,14 +546,16 @@ double orc_fit_exponent_binned(int64_t n, const int64_t *row_ptr, const int32_t 
  * self-loops, no repeated pairs), as the symmetric CSR the other functions
  * read.  Readings: a listed pair (u, v) and (v, u) name the same edge;
  * self-loops are dropped; repeated pairs are merged into one edge whose
- * weight is the sum of the listed weights (added in double in list order,
- * then rounded to single precision); edge ids enumerate the edges in order
+ * weight is the exact sum of the listed weights rounded once to single
+ * precision (orc_exact_sum_f32); listed weights must be finite and
+ * positive (the graph model's w > 0); edge ids enumerate the edges in order
  * of (smaller endpoint, larger endpoint), which is the CSR order of their
  * upper entries; each row lists its neighbours in ascending order.  With
  * order == 1 the vertices are stored by decreasing degree, ties by their id
  * in the list, and orig_out[new id] names the listed vertex (through
- * orig_in when given).  Returns the number of edges m, or -1 when an
- * endpoint lies outside [0, n); n_dropped receives m_in - m.               */
+ * orig_in when given).  Returns the number of edges m, -1 when an endpoint
+ * lies outside [0, n), -2 for a weight that is not finite and positive;
+ * n_dropped receives m_in - m.                                             */
 
 typedef struct { int64_t a, b, idx; } orc_pair;
 

@@ -74,7 +74,7 @@ def test_ingest_bit_exact(api, by_degree, seed, weighted):
 
 
 def test_ingest_long_runs_and_hubs(api):
-    """One pair listed 5,000 times (a long merge run, summed in list order),
+    """One pair listed 5,000 times (a long merge run, summed by a workgroup),
     a star of degree 20,000 and isolated vertices."""
     announce("ingest long runs and hubs")
     rng = np.random.default_rng(7)
