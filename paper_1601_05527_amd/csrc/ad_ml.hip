@@ -124,11 +124,17 @@ __global__ __launch_bounds__(MBLOCK) void k_ml_strong(int64_t n, const int64_t *
 // One round of the seed traversal over the undecided vertices (state 0;
 // 1 = seed, 2 = not a seed): a vertex with a strongly coupled seed is not a
 // seed; one whose strongly coupled vertices ahead of it are all decided
-// becomes a seed; the others wait and are counted in *left.
+// becomes a seed; the others wait and are counted in *left.  Only the
+// strongly coupled vertices ahead of i matter while i is undecided (one
+// behind i cannot be decided a seed before i is decided), and a decided
+// state never changes, so a waiting vertex keeps in resume[i] the offset in
+// its row of its first undecided such neighbour (every one before it is
+// final and not a seed) and the next round reads its row from there.
 __global__ __launch_bounds__(MBLOCK) void k_ml_seed_round(int64_t n, const int64_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
                                                           const uint8_t *__restrict__ sflag,
                                                           uint8_t *__restrict__ state,
+                                                          uint32_t *__restrict__ resume,
                                                           unsigned long long *__restrict__ left) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = (int64_t)gridDim.x * (MBLOCK / WAVE);
@@ -144,20 +150,26 @@ __global__ __launch_bounds__(MBLOCK) void k_ml_seed_round(int64_t n, const int64
             const int t = __ffsll((long long)todo) - 1;
             todo &= todo - 1;
             const int64_t i = base + (int64_t)t * nw;
-            bool seed_nb = false, blocked = false;
-            for (int64_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += WAVE) {
-                const uint8_t f = sflag[p];
-                if (f == 0) continue;
-                const uint8_t sj = __hip_atomic_load(&state[col[p]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int64_t b0 = row_ptr[i];
+            const int len = (int)(row_ptr[i + 1] - b0);
+            bool seed_nb = false;
+            int wait_at = len;                               // first undecided neighbour ahead
+            for (int q = (int)resume[i] + lane; q < len; q += WAVE) {
+                if (sflag[b0 + q] != 2) continue;
+                const uint8_t sj =
+                    __hip_atomic_load(&state[col[b0 + q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (sj == 1) seed_nb = true;
-                else if (sj == 0 && f == 2) blocked = true;
+                else if (sj == 0) wait_at = min(wait_at, q);
             }
             const bool any_seed = __ballot(seed_nb) != 0ull;
-            const bool any_block = __ballot(blocked) != 0ull;
+            for (int o = WAVE / 2; o >= 1; o >>= 1) wait_at = min(wait_at, __shfl_xor(wait_at, o, WAVE));
+            const bool any_block = wait_at < len;
             if (lane == 0) {
                 if (any_seed) __hip_atomic_store(&state[i], (uint8_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 else if (!any_block)
                     __hip_atomic_store(&state[i], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else
+                    resume[i] = (uint32_t)wait_at;
             }
             if (!any_seed && any_block) ++waiting;
         }
@@ -298,6 +310,7 @@ constexpr int SEED_BATCH = 4;            // seed rounds per read-back
 struct AggLayout {
     double *smax;                 // [n]
     uint8_t *state;               // [n]
+    uint32_t *resume;             // [n] where a waiting vertex's next seed round reads its row from
     uint8_t *sflag;               // [nnz] coupling of every entry
     unsigned int *rank;           // [n] seed flags, scanned in place into aggregate ids
     unsigned int *total;          // [1] number of seeds
@@ -311,6 +324,7 @@ static size_t agg_layout(int64_t n, int64_t nnz, void *ws, size_t ws_bytes, AggL
     AggLayout l;
     l.smax = c.take<double>(nn);
     l.state = c.take<uint8_t>(nn);
+    l.resume = c.take<uint32_t>(nn);
     l.sflag = c.take<uint8_t>((size_t)std::max<int64_t>(1, nnz));
     l.rank = c.take<unsigned int>(nn);
     l.total = c.take<unsigned int>(1);
@@ -345,6 +359,8 @@ static ad_status aggregate_impl(const ad_graph *g, const Tr *rho, double eps, do
     AD_LAUNCH_CHECK("k_ml_strong");
     ad_status s = fill_u8(L.state, 0, n, st);
     if (s != AD_OK) return s;
+    s = fill_i32((int32_t *)L.resume, 0, n, st);
+    if (s != AD_OK) return s;
     // each round decides at least the undecided vertex of highest priority
     // rounds are enqueued SEED_BATCH at a time and only the last one's count
     // is read back (a round after the last undecided vertex changes nothing)
@@ -354,7 +370,7 @@ static ad_status aggregate_impl(const ad_graph *g, const Tr *rho, double eps, do
         if (s != AD_OK) return s;
         for (int b = 0; b < SEED_BATCH; ++b) {
             hipLaunchKernelGGL(k_ml_seed_round, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->col,
-                               L.sflag, L.state, L.left + b);
+                               L.sflag, L.state, L.resume, L.left + b);
             AD_LAUNCH_CHECK("k_ml_seed_round");
         }
         unsigned long long waiting = 0;
