@@ -346,7 +346,8 @@ ad_status ad_spearman(int64_t n, const double *x, const double *y, double *rho_h
 
 /* ----------------------------------------------------------- multilevel -- */
 
-/* Workspace bytes for ad_ml_aggregate (0 when n < 0 or n >= 2^31). */
+/* Workspace bytes for ad_ml_aggregate (0 when n or m is negative or at least
+ * 2^31). */
 size_t ad_ml_aggregate_workspace_size(const ad_graph *g);
 
 /* One coarsening step of Algorithm 6 (Section 5): the seeds and the

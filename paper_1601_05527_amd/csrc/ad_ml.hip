@@ -97,19 +97,21 @@ __global__ __launch_bounds__(MBLOCK) void k_ml_smax(int64_t n, const int64_t *__
 }
 
 // Coupling of every stored entry (i, j): 0 not strong, 1 strong with j
-// after i in the traversal, 2 strong with j ahead of i.
+// after i in the traversal, 2 strong with j ahead of i; acnt[i] = the number
+// of entries of row i coupled strongly to a vertex ahead.
 template <typename Tr>
 __global__ __launch_bounds__(MBLOCK) void k_ml_strong(int64_t n, const int64_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
                                                       const int32_t *__restrict__ orig_id, const Tr *__restrict__ rho,
                                                       double eps, double theta, const double *__restrict__ smax,
-                                                      uint8_t *__restrict__ sflag) {
+                                                      uint8_t *__restrict__ sflag, uint32_t *__restrict__ acnt) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = (int64_t)gridDim.x * (MBLOCK / WAVE);
     for (int64_t i = (int64_t)blockIdx.x * (MBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
         const int64_t b0 = row_ptr[i], b1 = row_ptr[i + 1];
         const int32_t ki = orig_id ? orig_id[i] : (int32_t)i;
         const double si = theta * smax[i];
+        int ahead = 0;
         for (int64_t p = b0 + lane; p < b1; p += WAVE) {
             const int32_t j = col[p];
             const double d = ml_strength(rho[eid[p]], eps);
@@ -117,6 +119,32 @@ __global__ __launch_bounds__(MBLOCK) void k_ml_strong(int64_t n, const int64_t *
             if (d >= si || d >= theta * smax[j])
                 f = ml_ahead(b1 - b0, ki, row_ptr[j + 1] - row_ptr[j], orig_id ? orig_id[j] : j) ? 2 : 1;
             sflag[p] = f;
+            ahead += f == 2;
+        }
+        for (int o = WAVE / 2; o >= 1; o >>= 1) ahead += __shfl_xor(ahead, o, WAVE);
+        if (lane == 0) acnt[i] = (uint32_t)ahead;
+    }
+}
+
+// The strongly coupled neighbours ahead of each vertex, in row order:
+// alist[aoff[i], aoff[i + 1]).
+__global__ __launch_bounds__(MBLOCK) void k_ml_ahead_list(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const uint8_t *__restrict__ sflag,
+                                                          const uint32_t *__restrict__ aoff,
+                                                          int32_t *__restrict__ alist) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (MBLOCK / WAVE);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int64_t i = (int64_t)blockIdx.x * (MBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        const int64_t b0 = row_ptr[i], b1 = row_ptr[i + 1];
+        uint32_t o = aoff[i];
+        for (int64_t p0 = b0; p0 < b1; p0 += WAVE) {            // the bound is the same for the whole wave
+            const int64_t p = p0 + lane;
+            const bool f2 = p < b1 && sflag[p] == 2;
+            const unsigned long long bal = __ballot(f2);
+            if (f2) alist[o + (uint32_t)__popcll(bal & below)] = col[p];
+            o += (uint32_t)__popcll(bal);
         }
     }
 }
@@ -126,13 +154,19 @@ __global__ __launch_bounds__(MBLOCK) void k_ml_strong(int64_t n, const int64_t *
 // seed; one whose strongly coupled vertices ahead of it are all decided
 // becomes a seed; the others wait and are counted in *left.  Only the
 // strongly coupled vertices ahead of i matter while i is undecided (one
-// behind i cannot be decided a seed before i is decided), and a decided
-// state never changes, so a waiting vertex keeps in resume[i] the offset in
-// its row of its first undecided such neighbour (every one before it is
-// final and not a seed) and the next round reads its row from there.
-__global__ __launch_bounds__(MBLOCK) void k_ml_seed_round(int64_t n, const int64_t *__restrict__ row_ptr,
-                                                          const int32_t *__restrict__ col,
-                                                          const uint8_t *__restrict__ sflag,
+// behind i cannot be decided a seed before i is decided), so a round reads
+// i's list of those; and since a decided state never changes, a waiting
+// vertex keeps in resume[i] the place in its list of its first undecided
+// neighbour (every one before it is final and not a seed) and the next round
+// reads the list from there.  States are read and written with device
+// scope, so a decision made during a round can already settle other
+// vertices in the same round (with workgroup scope the rounds were more and
+// no shorter).
+constexpr uint32_t SEED_LANE_MAX = 32;   // lists up to this length: one lane per vertex, longer: one wave
+constexpr int SEED_LOADS = 8;            // list entries a lane reads per step
+
+__global__ __launch_bounds__(MBLOCK) void k_ml_seed_round(int64_t n, const uint32_t *__restrict__ aoff,
+                                                          const int32_t *__restrict__ alist,
                                                           uint8_t *__restrict__ state,
                                                           uint32_t *__restrict__ resume,
                                                           unsigned long long *__restrict__ left) {
@@ -140,40 +174,74 @@ __global__ __launch_bounds__(MBLOCK) void k_ml_seed_round(int64_t n, const int64
     const int64_t nw = (int64_t)gridDim.x * (MBLOCK / WAVE);
     unsigned long long waiting = 0;
     // wave gw owns rows gw + k nw (the high-degree rows, stored first, spread
-    // over the waves); its lanes find 64 undecided ones at a time, then the
-    // wave works through them one row at a time
+    // over the waves), 64 at a time: short lists by their own lane, then
+    // long ones by the whole wave, one at a time
     const int64_t gw = (int64_t)blockIdx.x * (MBLOCK / WAVE) + (threadIdx.x >> 6);
     for (int64_t base = gw; base < n; base += nw * WAVE) {
         const int64_t mine = base + (int64_t)lane * nw;
-        unsigned long long todo = __ballot(mine < n && state[mine] == 0);
+        // the row's state (only this wave writes its rows' states), list
+        // bounds and resume point, loaded together
+        const bool in = mine < n;
+        const uint8_t own = in ? state[mine] : (uint8_t)1;
+        const uint32_t a = in ? aoff[mine] : 0u, len = in ? aoff[mine + 1] - a : 0u;
+        const uint32_t from = in ? resume[mine] : 0u;
+        const bool undecided = own == 0;
+        if (undecided && len <= SEED_LANE_MAX) {
+            bool seed_nb = false;
+            uint32_t wait_at = len;
+            for (uint32_t q0 = from; q0 < len && !seed_nb; q0 += SEED_LOADS) {
+                int32_t v[SEED_LOADS];
+                uint8_t sj[SEED_LOADS];
+#pragma unroll
+                for (int t = 0; t < SEED_LOADS; ++t) v[t] = q0 + t < len ? alist[a + q0 + t] : -1;
+#pragma unroll
+                for (int t = 0; t < SEED_LOADS; ++t)
+                    sj[t] = v[t] >= 0
+                                ? __hip_atomic_load(&state[v[t]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : (uint8_t)2;
+#pragma unroll
+                for (int t = 0; t < SEED_LOADS; ++t) {
+                    if (sj[t] == 1) seed_nb = true;
+                    else if (sj[t] == 0 && wait_at == len) wait_at = q0 + t;
+                }
+            }
+            if (seed_nb) __hip_atomic_store(&state[mine], (uint8_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else if (wait_at == len)
+                __hip_atomic_store(&state[mine], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else {
+                resume[mine] = wait_at;
+                ++waiting;
+            }
+        }
+        unsigned long long todo = __ballot(undecided && len > SEED_LANE_MAX);
         while (todo) {
             const int t = __ffsll((long long)todo) - 1;
             todo &= todo - 1;
             const int64_t i = base + (int64_t)t * nw;
-            const int64_t b0 = row_ptr[i];
-            const int len = (int)(row_ptr[i + 1] - b0);
+            const uint32_t ai = aoff[i], li = aoff[i + 1] - ai;
             bool seed_nb = false;
-            int wait_at = len;                               // first undecided neighbour ahead
-            for (int q = (int)resume[i] + lane; q < len; q += WAVE) {
-                if (sflag[b0 + q] != 2) continue;
+            uint32_t wait_at = li;
+            for (uint32_t q = resume[i] + (uint32_t)lane; q < li; q += WAVE) {
                 const uint8_t sj =
-                    __hip_atomic_load(&state[col[b0 + q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_load(&state[alist[ai + q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (sj == 1) seed_nb = true;
                 else if (sj == 0) wait_at = min(wait_at, q);
             }
             const bool any_seed = __ballot(seed_nb) != 0ull;
-            for (int o = WAVE / 2; o >= 1; o >>= 1) wait_at = min(wait_at, __shfl_xor(wait_at, o, WAVE));
-            const bool any_block = wait_at < len;
+            for (int o = WAVE / 2; o >= 1; o >>= 1)
+                wait_at = min(wait_at, (uint32_t)__shfl_xor((int)wait_at, o, WAVE));
             if (lane == 0) {
                 if (any_seed) __hip_atomic_store(&state[i], (uint8_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                else if (!any_block)
+                else if (wait_at == li)
                     __hip_atomic_store(&state[i], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                else
-                    resume[i] = (uint32_t)wait_at;
+                else {
+                    resume[i] = wait_at;
+                    ++waiting;
+                }
             }
-            if (!any_seed && any_block) ++waiting;
         }
     }
+    for (int o = WAVE / 2; o >= 1; o >>= 1) waiting += __shfl_xor(waiting, o, WAVE);
     if (lane == 0 && waiting) atomicAdd(left, waiting);
 }
 
@@ -312,6 +380,8 @@ struct AggLayout {
     uint8_t *state;               // [n]
     uint32_t *resume;             // [n] where a waiting vertex's next seed round reads its row from
     uint8_t *sflag;               // [nnz] coupling of every entry
+    uint32_t *aoff;               // [n + 1] offsets of the lists of strongly coupled neighbours ahead
+    int32_t *alist;               // [nnz / 2] those lists (a strong edge is ahead from one end only)
     unsigned int *rank;           // [n] seed flags, scanned in place into aggregate ids
     unsigned int *total;          // [1] number of seeds
     unsigned long long *left;     // [SEED_BATCH] vertices still undecided after each round of a batch
@@ -326,6 +396,8 @@ static size_t agg_layout(int64_t n, int64_t nnz, void *ws, size_t ws_bytes, AggL
     l.state = c.take<uint8_t>(nn);
     l.resume = c.take<uint32_t>(nn);
     l.sflag = c.take<uint8_t>((size_t)std::max<int64_t>(1, nnz));
+    l.aoff = c.take<uint32_t>(nn + 1);
+    l.alist = c.take<int32_t>((size_t)std::max<int64_t>(1, nnz / 2));
     l.rank = c.take<unsigned int>(nn);
     l.total = c.take<unsigned int>(1);
     l.left = c.take<unsigned long long>(SEED_BATCH);
@@ -355,9 +427,14 @@ static ad_status aggregate_impl(const ad_graph *g, const Tr *rho, double eps, do
     hipLaunchKernelGGL(k_ml_smax<Tr>, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->eid, rho, eps, L.smax);
     AD_LAUNCH_CHECK("k_ml_smax");
     hipLaunchKernelGGL(k_ml_strong<Tr>, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->col, g->eid,
-                       g->orig_id, rho, eps, theta, L.smax, L.sflag);
+                       g->orig_id, rho, eps, theta, L.smax, L.sflag, L.aoff);
     AD_LAUNCH_CHECK("k_ml_strong");
-    ad_status s = fill_u8(L.state, 0, n, st);
+    ad_status s = scan_exclusive(n, L.aoff, nullptr, L.aoff + n, nullptr, L.scan, st);
+    if (s != AD_OK) return s;
+    hipLaunchKernelGGL(k_ml_ahead_list, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->col, L.sflag,
+                       L.aoff, L.alist);
+    AD_LAUNCH_CHECK("k_ml_ahead_list");
+    s = fill_u8(L.state, 0, n, st);
     if (s != AD_OK) return s;
     s = fill_i32((int32_t *)L.resume, 0, n, st);
     if (s != AD_OK) return s;
@@ -369,8 +446,8 @@ static ad_status aggregate_impl(const ad_graph *g, const Tr *rho, double eps, do
         s = fill_u64(L.left, 0, SEED_BATCH, st);
         if (s != AD_OK) return s;
         for (int b = 0; b < SEED_BATCH; ++b) {
-            hipLaunchKernelGGL(k_ml_seed_round, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->col,
-                               L.sflag, L.state, L.resume, L.left + b);
+            hipLaunchKernelGGL(k_ml_seed_round, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, L.aoff, L.alist, L.state,
+                               L.resume, L.left + b);
             AD_LAUNCH_CHECK("k_ml_seed_round");
         }
         unsigned long long waiting = 0;
@@ -500,7 +577,7 @@ struct MlArenaScope {
     MlArena arena;
     MlArenaScope(hipStream_t st, int64_t n, int64_t m) : stream(st) {
         void *p = nullptr;
-        const size_t first = (size_t)(96 * std::max<int64_t>(1, m) + 96 * std::max<int64_t>(1, n)) + (64u << 20);
+        const size_t first = (size_t)(104 * std::max<int64_t>(1, m) + 104 * std::max<int64_t>(1, n)) + (64u << 20);
         if (hipMalloc(&p, first) == hipSuccess) arena.chunks.push_back(MlArena::Chunk{(char *)p, first, 0});
         else (void)hipGetLastError();
         ml_arena = &arena;
