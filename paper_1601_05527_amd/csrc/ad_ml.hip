@@ -82,17 +82,27 @@ __device__ __forceinline__ bool ml_ahead(int64_t da, int32_t ka, int64_t db, int
     return kb < ka;
 }
 
+// What a coupling test reads of a vertex, in one 16-byte record: theta
+// times its largest strength, its degree and its name.
+struct __align__(16) MlVert {
+    double tsmax;
+    uint32_t deg;
+    int32_t key;
+};
+
 template <typename Tr>
 __global__ __launch_bounds__(MBLOCK) void k_ml_smax(int64_t n, const int64_t *__restrict__ row_ptr,
-                                                     const int32_t *__restrict__ eid, const Tr *__restrict__ rho,
-                                                     double eps, double *__restrict__ smax) {
+                                                     const int32_t *__restrict__ eid,
+                                                     const int32_t *__restrict__ orig_id, const Tr *__restrict__ rho,
+                                                     double eps, double theta, MlVert *__restrict__ vert) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = (int64_t)gridDim.x * (MBLOCK / WAVE);
     for (int64_t i = (int64_t)blockIdx.x * (MBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        const int64_t b0 = row_ptr[i], b1 = row_ptr[i + 1];
         double mx = 0.0;
-        for (int64_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += WAVE) mx = fmax(mx, ml_strength(rho[eid[p]], eps));
+        for (int64_t p = b0 + lane; p < b1; p += WAVE) mx = fmax(mx, ml_strength(rho[eid[p]], eps));
         for (int o = WAVE / 2; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, WAVE));
-        if (lane == 0) smax[i] = mx;
+        if (lane == 0) vert[i] = MlVert{theta * mx, (uint32_t)(b1 - b0), orig_id ? orig_id[i] : (int32_t)i};
     }
 }
 
@@ -102,22 +112,21 @@ __global__ __launch_bounds__(MBLOCK) void k_ml_smax(int64_t n, const int64_t *__
 template <typename Tr>
 __global__ __launch_bounds__(MBLOCK) void k_ml_strong(int64_t n, const int64_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
-                                                      const int32_t *__restrict__ orig_id, const Tr *__restrict__ rho,
-                                                      double eps, double theta, const double *__restrict__ smax,
+                                                      const Tr *__restrict__ rho, double eps,
+                                                      const MlVert *__restrict__ vert,
                                                       uint8_t *__restrict__ sflag, uint32_t *__restrict__ acnt) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = (int64_t)gridDim.x * (MBLOCK / WAVE);
     for (int64_t i = (int64_t)blockIdx.x * (MBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
         const int64_t b0 = row_ptr[i], b1 = row_ptr[i + 1];
-        const int32_t ki = orig_id ? orig_id[i] : (int32_t)i;
-        const double si = theta * smax[i];
+        const MlVert vi = vert[i];
         int ahead = 0;
         for (int64_t p = b0 + lane; p < b1; p += WAVE) {
             const int32_t j = col[p];
             const double d = ml_strength(rho[eid[p]], eps);
+            const MlVert vj = vert[j];
             uint8_t f = 0;
-            if (d >= si || d >= theta * smax[j])
-                f = ml_ahead(b1 - b0, ki, row_ptr[j + 1] - row_ptr[j], orig_id ? orig_id[j] : j) ? 2 : 1;
+            if (d >= vi.tsmax || d >= vj.tsmax) f = ml_ahead(vi.deg, vi.key, vj.deg, vj.key) ? 2 : 1;
             sflag[p] = f;
             ahead += f == 2;
         }
@@ -376,7 +385,7 @@ __global__ void k_ml_count(int64_t m, const uint8_t *__restrict__ keep, unsigned
 constexpr int SEED_BATCH = 4;            // seed rounds per read-back
 
 struct AggLayout {
-    double *smax;                 // [n]
+    MlVert *vert;                 // [n] theta * largest strength, degree and name of every vertex
     uint8_t *state;               // [n]
     uint32_t *resume;             // [n] where a waiting vertex's next seed round reads its row from
     uint8_t *sflag;               // [nnz] coupling of every entry
@@ -392,7 +401,7 @@ static size_t agg_layout(int64_t n, int64_t nnz, void *ws, size_t ws_bytes, AggL
     Carver c(ws, ws_bytes);
     const size_t nn = (size_t)std::max<int64_t>(1, n);
     AggLayout l;
-    l.smax = c.take<double>(nn);
+    l.vert = c.take<MlVert>(nn);
     l.state = c.take<uint8_t>(nn);
     l.resume = c.take<uint32_t>(nn);
     l.sflag = c.take<uint8_t>((size_t)std::max<int64_t>(1, nnz));
@@ -424,10 +433,11 @@ static ad_status aggregate_impl(const ad_graph *g, const Tr *rho, double eps, do
     const int64_t n = g->n;
     *nc_host = 0;
     if (n == 0) return AD_OK;
-    hipLaunchKernelGGL(k_ml_smax<Tr>, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->eid, rho, eps, L.smax);
+    hipLaunchKernelGGL(k_ml_smax<Tr>, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->eid, g->orig_id, rho,
+                       eps, theta, L.vert);
     AD_LAUNCH_CHECK("k_ml_smax");
     hipLaunchKernelGGL(k_ml_strong<Tr>, dim3(mwgrid(n)), dim3(MBLOCK), 0, st, n, g->row_ptr, g->col, g->eid,
-                       g->orig_id, rho, eps, theta, L.smax, L.sflag, L.aoff);
+                       rho, eps, L.vert, L.sflag, L.aoff);
     AD_LAUNCH_CHECK("k_ml_strong");
     ad_status s = scan_exclusive(n, L.aoff, nullptr, L.aoff + n, nullptr, L.scan, st);
     if (s != AD_OK) return s;
