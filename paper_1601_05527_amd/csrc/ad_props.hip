@@ -29,45 +29,44 @@ __global__ void k_keep_u32(int64_t m, const uint8_t *__restrict__ keep, uint32_t
         k32[e] = keep[e] ? 1u : 0u;
 }
 
-// Kept entries per row (one wave per row).
-__global__ void k_kept_per_row(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ eid,
-                               const uint8_t *__restrict__ keep, uint64_t *__restrict__ cnt) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
-    for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
-        int64_t c = 0;
-        for (int64_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += WAVE) c += keep[eid[p]] ? 1 : 0;
-        for (int o = WAVE / 2; o >= 1; o >>= 1) c += __shfl_xor(c, o, WAVE);
-        if (lane == 0) cnt[i] = (uint64_t)c;
+// Kept flag of every stored entry, as the input of the entry scan.
+struct EntryKept {
+    const uint8_t *keep;
+    const int32_t *eid;
+    __device__ uint32_t operator()(int64_t p) const { return keep[eid[p]] ? 1u : 0u; }
+};
+using EntryKeptIt = rocprim::transform_iterator<rocprim::counting_iterator<int64_t>, EntryKept, uint32_t>;
+static EntryKeptIt entry_kept(const uint8_t *keep, const int32_t *eid) {
+    return EntryKeptIt(rocprim::counting_iterator<int64_t>(0), EntryKept{keep, eid});
+}
+
+// The subgraph keeps the stored order, so pos[p] (kept entries before p)
+// places entry p, and a row starts at pos of its first entry.
+__global__ void k_sub_rows(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr,
+                           const int32_t *__restrict__ eid, const uint8_t *__restrict__ keep,
+                           const uint32_t *__restrict__ pos, int64_t *__restrict__ sub_row_ptr) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = row_ptr[i];
+        int64_t v = 0;
+        if (p < nnz) v = pos[p];
+        else if (nnz > 0) v = (int64_t)pos[nnz - 1] + (keep[eid[nnz - 1]] ? 1 : 0);
+        sub_row_ptr[i] = v;
     }
 }
 
-// The kept entries of every row, in order (ballot compaction per 64 entries).
-__global__ void k_compact_rows(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                               const float *__restrict__ w, const int32_t *__restrict__ eid,
-                               const uint8_t *__restrict__ keep, const uint32_t *__restrict__ new_id,
-                               const int64_t *__restrict__ sub_row_ptr, int32_t *__restrict__ sub_col,
-                               float *__restrict__ sub_w, int32_t *__restrict__ sub_eid,
-                               int32_t *__restrict__ orig_edge) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
-    for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
-        int64_t out = sub_row_ptr[i];
-        for (int64_t base = row_ptr[i]; base < row_ptr[i + 1]; base += WAVE) {
-            const int64_t p = base + lane;
-            const bool on = p < row_ptr[i + 1];
-            const int32_t e = on ? eid[p] : 0;
-            const bool k = on && keep[e];
-            const unsigned long long mask = __ballot(k);
-            if (k) {
-                const int64_t q = out + __popcll(mask & ((1ull << lane) - 1ull));
-                sub_col[q] = col[p];
-                if (sub_w) sub_w[q] = w[p];
-                sub_eid[q] = (int32_t)new_id[e];
-                if (orig_edge) orig_edge[q] = e;
-            }
-            out += __popcll(mask);
-        }
+__global__ void k_compact_entries(int64_t nnz, const int32_t *__restrict__ col, const float *__restrict__ w,
+                                  const int32_t *__restrict__ eid, const uint8_t *__restrict__ keep,
+                                  const uint32_t *__restrict__ new_id, const uint32_t *__restrict__ pos,
+                                  int32_t *__restrict__ sub_col, float *__restrict__ sub_w,
+                                  int32_t *__restrict__ sub_eid, int32_t *__restrict__ orig_edge) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = eid[p];
+        if (!keep[e]) continue;
+        const uint32_t q = pos[p];
+        sub_col[q] = col[p];
+        if (sub_w) sub_w[q] = w[p];
+        sub_eid[q] = (int32_t)new_id[e];
+        if (orig_edge) orig_edge[q] = e;
     }
 }
 
@@ -338,24 +337,24 @@ __global__ void k_rank_diff2(int64_t n, const int64_t *__restrict__ rx2, const i
 
 struct SubLayout {
     uint32_t *k32, *new_id;   // [m]
-    uint64_t *cnt;            // [n + 1]
+    uint32_t *pos;            // [2m] kept entries before each stored entry
     void *temp;
     size_t temp_bytes;
 };
 
 static size_t sub_layout(const ad_graph *g, void *ws, size_t ws_bytes, SubLayout *L) {
     Carver c(ws, ws_bytes);
-    const size_t m = (size_t)std::max<int64_t>(1, g->m), n1 = (size_t)std::max<int64_t>(1, g->n) + 1;
+    const size_t m = (size_t)std::max<int64_t>(1, g->m);
     SubLayout l;
     l.k32 = c.take<uint32_t>(m);
     l.new_id = c.take<uint32_t>(m);
-    l.cnt = c.take<uint64_t>(n1);
+    l.pos = c.take<uint32_t>(2 * m);
     size_t t1 = 0, t2 = 0;
     if (rocprim::exclusive_scan(nullptr, t1, (uint32_t *)nullptr, (uint32_t *)nullptr, 0u, m,
                                 rocprim::plus<uint32_t>()) != hipSuccess)
         t1 = 0;
-    if (rocprim::exclusive_scan(nullptr, t2, (uint64_t *)nullptr, (uint64_t *)nullptr, (uint64_t)0, n1,
-                                rocprim::plus<uint64_t>()) != hipSuccess)
+    if (rocprim::exclusive_scan(nullptr, t2, entry_kept(nullptr, nullptr), (uint32_t *)nullptr, 0u, 2 * m,
+                                rocprim::plus<uint32_t>()) != hipSuccess)
         t2 = 0;
     l.temp_bytes = std::max(t1, t2);
     l.temp = c.take<char>(l.temp_bytes);
@@ -462,21 +461,18 @@ extern "C" ad_status ad_subgraph(const ad_graph *g, const uint8_t *keep, int64_t
         AD_HIP(hipMemcpyAsync(&last[0], L.new_id + (m - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
         AD_HIP(hipMemcpyAsync(&last[1], L.k32 + (m - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
     }
-    s = fill_i32((int32_t *)(L.cnt + n), 0, 2, stream);
-    if (s != AD_OK) return s;
-    const unsigned wgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, PBLOCK / WAVE)));
-    if (n > 0) {
-        hipLaunchKernelGGL(k_kept_per_row, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->eid, keep, L.cnt);
-        AD_LAUNCH_CHECK("k_kept_per_row");
+    if (m > 0) {
+        size_t tb = L.temp_bytes;
+        AD_RP(rocprim::exclusive_scan(L.temp, tb, entry_kept(keep, g->eid), L.pos, 0u, (size_t)(2 * m),
+                                      rocprim::plus<uint32_t>(), stream));
     }
-    size_t tb = L.temp_bytes;
-    AD_RP(rocprim::exclusive_scan(L.temp, tb, L.cnt, (uint64_t *)sub_row_ptr, (uint64_t)0, (size_t)n + 1,
-                                  rocprim::plus<uint64_t>(), stream));
-    if (n > 0 && m > 0) {
-        hipLaunchKernelGGL(k_compact_rows, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, g->w,
-                           g->eid, keep, L.new_id, (const int64_t *)sub_row_ptr, sub_col, g->w ? sub_w : nullptr,
-                           sub_eid, orig_edge);
-        AD_LAUNCH_CHECK("k_compact_rows");
+    hipLaunchKernelGGL(k_sub_rows, dim3(pgrid(n + 1)), dim3(PBLOCK), 0, stream, n, 2 * m, g->row_ptr, g->eid, keep,
+                       L.pos, sub_row_ptr);
+    AD_LAUNCH_CHECK("k_sub_rows");
+    if (m > 0) {
+        hipLaunchKernelGGL(k_compact_entries, dim3(pgrid(2 * m)), dim3(PBLOCK), 0, stream, 2 * m, g->col, g->w,
+                           g->eid, keep, L.new_id, L.pos, sub_col, g->w ? sub_w : nullptr, sub_eid, orig_edge);
+        AD_LAUNCH_CHECK("k_compact_entries");
     }
     AD_HIP(hipStreamSynchronize(stream));
     *m_sub_host = (int64_t)last[0] + (int64_t)last[1];
