@@ -236,18 +236,22 @@ __global__ void k_parent_init(int64_t n, int32_t *__restrict__ parent) {
 // decrease and hooks only join trees of one component, so each component
 // ends rooted at its smallest vertex.  `changed` is raised while any edge
 // still joins two trees (a hook can lose a race and leave its trees apart
-// for the next round), once per wave.
+// for the next round), once per wave.  A parent read late is still a vertex
+// of the same tree (trees only merge), so two equal parents always mean one
+// tree: parents are read with workgroup scope, i's once per row, and a
+// value read before another wave's hook only leaves work for the next round.
 __global__ void k_hook(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                        int32_t *__restrict__ parent, unsigned int *__restrict__ changed) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
     bool any = false;
     for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
-        for (int64_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += WAVE) {
+        const int64_t b1 = row_ptr[i + 1];
+        const int32_t pi = __hip_atomic_load(&parent[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (int64_t p = row_ptr[i] + lane; p < b1; p += WAVE) {
             const int32_t j = col[p];
             if (j <= i) continue;
-            const int32_t pi = __hip_atomic_load(&parent[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int32_t pj = __hip_atomic_load(&parent[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int32_t pj = __hip_atomic_load(&parent[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (pi == pj) continue;
             any = true;
             const int32_t lo = pi < pj ? pi : pj, hi = pi < pj ? pj : pi;
