@@ -187,6 +187,84 @@ __global__ __launch_bounds__(PBLOCK) void k_triangles_hub(int64_t n, const int64
     }
 }
 
+// The same pairs with N_L held as a bitmap over its id range [lo, hi]
+// (rows are sorted, so lo and hi are its first and last entries) when that
+// range has at most TRI_BITS ids: a lookup is one LDS read instead of a
+// binary search (used for graphs of at most TRI_BITS vertices; a row with
+// a wider range would search N_L in memory).  The bitmap
+// is cleared once per workgroup and, after each row, only in the words that
+// row set.  Needs TRI_BITS / 8 bytes of LDS per workgroup.
+constexpr int TRI_BT = 1024;
+constexpr int64_t TRI_BITS = (int64_t)1 << 20;
+
+__global__ __launch_bounds__(TRI_BT) void k_triangles_hub_bits(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                               const int32_t *__restrict__ col,
+                                                               unsigned long long *__restrict__ lam2) {
+    extern __shared__ uint32_t bm[];                       // TRI_BITS / 32 words
+    __shared__ unsigned long long wsum[TRI_BT / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
+    for (int64_t q = threadIdx.x; q < TRI_BITS / 32; q += TRI_BT) bm[q] = 0u;
+    __syncthreads();
+    for (int64_t L = blockIdx.x; L < n; L += gridDim.x) {
+        const int64_t l0 = row_ptr[L], l1 = row_ptr[L + 1], dl = l1 - l0;
+        if (dl <= TRI_LANE) continue;                       // uniform over the workgroup
+        const int64_t lo = col[l0], span = (int64_t)col[l1 - 1] - lo + 1;
+        const bool bits = span <= TRI_BITS;
+        if (bits) {
+            for (int64_t q = threadIdx.x; q < dl; q += TRI_BT) {
+                const int64_t r = (int64_t)col[l0 + q] - lo;
+                atomicOr(&bm[r >> 5], 1u << (r & 31));
+            }
+        }
+        __syncthreads();
+        unsigned long long own = 0;
+        for (int64_t p = l0 + wv; p < l1; p += TRI_BT / WAVE) {
+            const int32_t j = col[p];
+            const int64_t c0 = row_ptr[j], c1 = row_ptr[j + 1], dj = c1 - c0;
+            if (dj <= TRI_LANE || dj > dl || (dj == dl && j > L)) continue;     // uniform over the wave
+            int64_t t = 0;
+            for (int64_t q = c0 + lane; q < c1; q += WAVE) {
+                const int32_t x = col[q];
+                if (bits) {
+                    const int64_t r = (int64_t)x - lo;
+                    t += (r >= 0 && r < span) ? (int64_t)((bm[r >> 5] >> (r & 31)) & 1u) : 0;
+                } else {
+                    int64_t a = l0, b = l1;
+                    while (a < b) {
+                        const int64_t mid = (a + b) >> 1;
+                        if (col[mid] < x) a = mid + 1;
+                        else b = mid;
+                    }
+                    t += (a < l1 && col[a] == x) ? 1 : 0;
+                }
+            }
+            for (int o = WAVE / 2; o >= 1; o >>= 1) t += __shfl_xor(t, o, WAVE);
+            if (lane == 0 && t) {
+                atomicAdd(&lam2[j], (unsigned long long)t);
+                own += (unsigned long long)t;
+            }
+        }
+        if (lane == 0) wsum[wv] = own;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int q = 0; q < TRI_BT / WAVE; ++q) tot += wsum[q];
+            if (tot) atomicAdd(&lam2[L], tot);
+        }
+        if (bits)
+            for (int64_t q = threadIdx.x; q < dl; q += TRI_BT) bm[((int64_t)col[l0 + q] - lo) >> 5] = 0u;
+        __syncthreads();     // bm and wsum are reused by the next row
+    }
+}
+
+// Whether the current device gives a workgroup the bitmap's LDS.
+static bool tri_bits_fit() {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return false;
+    return (int64_t)lds >= TRI_BITS / 8 + (int64_t)sizeof(unsigned long long) * (TRI_BT / WAVE);
+}
+
 // lambda_i and c_i; per-block partial sums of c_i over d_i > 1 (and their
 // count), in a fixed order for the host to finish.
 __global__ void k_clustering(int64_t n, const int64_t *__restrict__ row_ptr, const unsigned long long *__restrict__ lam2,
@@ -512,9 +590,16 @@ extern "C" ad_status ad_graph_properties(const ad_graph *g, int64_t *lambda, dou
     if (g->m > 0) {
         hipLaunchKernelGGL(k_triangles_lane, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, L.lam2);
         AD_LAUNCH_CHECK("k_triangles_lane");
-        hipLaunchKernelGGL(k_triangles_hub, dim3((unsigned)std::min<int64_t>(4096, n)), dim3(PBLOCK), 0, stream, n,
-                           g->row_ptr, g->col, L.lam2);
-        AD_LAUNCH_CHECK("k_triangles_hub");
+        // with at most TRI_BITS vertices every row's id range fits the bitmap
+        if (n <= TRI_BITS && tri_bits_fit()) {
+            hipLaunchKernelGGL(k_triangles_hub_bits, dim3((unsigned)std::min<int64_t>(4096, n)), dim3(TRI_BT),
+                               (size_t)(TRI_BITS / 8), stream, n, g->row_ptr, g->col, L.lam2);
+            AD_LAUNCH_CHECK("k_triangles_hub_bits");
+        } else {
+            hipLaunchKernelGGL(k_triangles_hub, dim3((unsigned)std::min<int64_t>(4096, n)), dim3(PBLOCK), 0, stream,
+                               n, g->row_ptr, g->col, L.lam2);
+            AD_LAUNCH_CHECK("k_triangles_hub");
+        }
     }
     hipLaunchKernelGGL(k_clustering, dim3(PREDUCE_BLOCKS), dim3(PBLOCK), 0, stream, n, g->row_ptr, L.lam2, lambda, c,
                        L.part_sum, L.part_cnt);

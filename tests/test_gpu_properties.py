@@ -53,6 +53,19 @@ def test_properties_match_oracle(api, kind):
     _check_props(api, api.DeviceGraph.from_host(g, "cuda"), g.row_ptr, g.col)
 
 
+def test_properties_beyond_the_bitmap_range(api):
+    """More than 2^20 vertices: long rows are searched as sorted arrays (the
+    id-range bitmap covers at most 2^20 ids).  A dense Chung-Lu core of
+    4,000 vertices is spread over the whole id range; the rest is isolated."""
+    announce("properties n > 2^20")
+    core = G.chung_lu(4000, 120_000, seed=12)
+    n = (1 << 20) + 5000
+    ids = np.sort(np.random.default_rng(13).choice(n, size=core.n, replace=False))
+    g = G.from_edges(n, ids[core.edge_u], ids[core.edge_v])
+    assert int(np.diff(g.row_ptr).max()) > 64
+    _check_props(api, api.DeviceGraph.from_host(g, "cuda"), g.row_ptr, g.col)
+
+
 @pytest.mark.parametrize("frac", [0.0, 0.05, 0.4, 1.0])
 def test_subgraph_matches_oracle(api, frac):
     announce(f"subgraph frac={frac}")
