@@ -92,9 +92,11 @@ __device__ __forceinline__ int64_t common_count(const int32_t *__restrict__ col,
 
 // Every edge (i, j), i < j, adds |N_i ∩ N_j| to both ends (each triangle at i
 // is then counted once through each of its two edges at i).  Pairs whose
-// shorter row exceeds TRI_LANE are left to k_triangles_hub.
+// shorter row exceeds TRI_LANE are left to k_triangles_hub(_bits), and with
+// both_short also those whose longer row does (k_triangles_hub_bits takes
+// them from the long row's bitmap).
 __global__ void k_triangles_lane(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                                 unsigned long long *__restrict__ lam2) {
+                                 int both_short, unsigned long long *__restrict__ lam2) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
     for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
@@ -111,7 +113,8 @@ __global__ void k_triangles_lane(int64_t n, const int64_t *__restrict__ row_ptr,
             }
             const bool i_short = (b1 - b0) <= (c1 - c0);
             const int64_t shorter = i_short ? b1 - b0 : c1 - c0;
-            const bool is_big = up && shorter > TRI_LANE;
+            const int64_t longer = i_short ? c1 - c0 : b1 - b0;
+            const bool is_big = up && (shorter > TRI_LANE || (both_short && longer > TRI_LANE));
             if (up && !is_big) {
                 const int64_t t =
                     i_short ? common_count(col, b0, b1, c0, c1, 0, 1) : common_count(col, c0, c1, b0, b1, 0, 1);
@@ -187,7 +190,8 @@ __global__ __launch_bounds__(PBLOCK) void k_triangles_hub(int64_t n, const int64
     }
 }
 
-// The same pairs with N_L held as a bitmap over its id range [lo, hi]
+// The pairs of a long row L with every neighbour of no larger (degree, id),
+// short neighbours included, with N_L held as a bitmap over its id range [lo, hi]
 // (rows are sorted, so lo and hi are its first and last entries) when that
 // range has at most TRI_BITS ids: a lookup is one LDS read instead of a
 // binary search (used for graphs of at most TRI_BITS vertices; a row with
@@ -217,33 +221,55 @@ __global__ __launch_bounds__(TRI_BT) void k_triangles_hub_bits(int64_t n, const 
             }
         }
         __syncthreads();
+        // whether id x is in N_L
+        auto in_l = [&](int32_t x) -> int64_t {
+            if (bits) {
+                const int64_t r = (int64_t)x - lo;
+                return (r >= 0 && r < span) ? (int64_t)((bm[r >> 5] >> (r & 31)) & 1u) : 0;
+            }
+            int64_t a = l0, b = l1;
+            while (a < b) {
+                const int64_t mid = (a + b) >> 1;
+                if (col[mid] < x) a = mid + 1;
+                else b = mid;
+            }
+            return (a < l1 && col[a] == x) ? 1 : 0;
+        };
         unsigned long long own = 0;
+        // short neighbours: one lane each, over the whole of N_j
+        for (int64_t p0 = l0 + (int64_t)wv * WAVE; p0 < l1; p0 += TRI_BT) {
+            const int64_t p = p0 + lane;
+            if (p >= l1) continue;
+            const int32_t j = col[p];
+            const int64_t c0 = row_ptr[j], c1 = row_ptr[j + 1];
+            if (c1 - c0 > TRI_LANE) continue;
+            int64_t t = 0;
+            for (int64_t q0 = c0; q0 < c1; q0 += 8) {                  // eight loads in flight
+                int32_t x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = q0 + u < c1 ? col[q0 + u] : -1;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t += x[u] >= 0 ? in_l(x[u]) : 0;
+            }
+            if (t) {
+                atomicAdd(&lam2[j], (unsigned long long)t);
+                own += (unsigned long long)t;
+            }
+        }
+        // long neighbours: one wave each, lanes striding over N_j
         for (int64_t p = l0 + wv; p < l1; p += TRI_BT / WAVE) {
             const int32_t j = col[p];
             const int64_t c0 = row_ptr[j], c1 = row_ptr[j + 1], dj = c1 - c0;
             if (dj <= TRI_LANE || dj > dl || (dj == dl && j > L)) continue;     // uniform over the wave
             int64_t t = 0;
-            for (int64_t q = c0 + lane; q < c1; q += WAVE) {
-                const int32_t x = col[q];
-                if (bits) {
-                    const int64_t r = (int64_t)x - lo;
-                    t += (r >= 0 && r < span) ? (int64_t)((bm[r >> 5] >> (r & 31)) & 1u) : 0;
-                } else {
-                    int64_t a = l0, b = l1;
-                    while (a < b) {
-                        const int64_t mid = (a + b) >> 1;
-                        if (col[mid] < x) a = mid + 1;
-                        else b = mid;
-                    }
-                    t += (a < l1 && col[a] == x) ? 1 : 0;
-                }
-            }
+            for (int64_t q = c0 + lane; q < c1; q += WAVE) t += in_l(col[q]);
             for (int o = WAVE / 2; o >= 1; o >>= 1) t += __shfl_xor(t, o, WAVE);
             if (lane == 0 && t) {
                 atomicAdd(&lam2[j], (unsigned long long)t);
                 own += (unsigned long long)t;
             }
         }
+        for (int o = WAVE / 2; o >= 1; o >>= 1) own += __shfl_xor(own, o, WAVE);
         if (lane == 0) wsum[wv] = own;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -588,10 +614,12 @@ extern "C" ad_status ad_graph_properties(const ad_graph *g, int64_t *lambda, dou
     s = fill_i32((int32_t *)L.flags, 0, 4, stream);
     if (s != AD_OK) return s;
     if (g->m > 0) {
-        hipLaunchKernelGGL(k_triangles_lane, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, L.lam2);
-        AD_LAUNCH_CHECK("k_triangles_lane");
         // with at most TRI_BITS vertices every row's id range fits the bitmap
-        if (n <= TRI_BITS && tri_bits_fit()) {
+        const bool use_bits = n <= TRI_BITS && tri_bits_fit();
+        hipLaunchKernelGGL(k_triangles_lane, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col,
+                           use_bits ? 1 : 0, L.lam2);
+        AD_LAUNCH_CHECK("k_triangles_lane");
+        if (use_bits) {
             hipLaunchKernelGGL(k_triangles_hub_bits, dim3((unsigned)std::min<int64_t>(4096, n)), dim3(TRI_BT),
                                (size_t)(TRI_BITS / 8), stream, n, g->row_ptr, g->col, L.lam2);
             AD_LAUNCH_CHECK("k_triangles_hub_bits");
