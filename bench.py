@@ -4,15 +4,21 @@
 Default workload (one step): a Chung-Lu power-law graph, n = 2^20 vertices,
 exactly 16,000,000 undirected edges, degree exponent 2.1, lognormal(0, 1)
 weights (seeded, synthetic; it stands in for the paper's real networks), with
-  start vectors (Philox) -> 20 JOR sweeps of R = 16 vectors (omega = 1/2,
-  FP32) -> rescale -> per-edge L2 algebraic distance ->
+  start vectors (Philox, each connected component centred by its own
+  weighted mean) -> 20 JOR sweeps of R = 16 vectors (omega = 1/2, FP32
+  storage and arithmetic, the last 2 sweeps stored and computed in FP64) ->
+  rescale -> per-edge L2 algebraic distance (FP32) ->
   LOCAL and GLOBAL selection, each with e fitted to 30% retention.
 The graph is resident in HBM before timing starts.  Vertices are stored in
-decreasing-degree order (a relabelling done once at setup, timed apart;
-results are keyed by the original ids and do not depend on it).
+decreasing-degree order and the graph's connected components are grouped
+once (set-up work of the graph, timed apart; results are keyed by the
+original ids and do not depend on either).
 
 Prints one JSON line.  `value` is JOR edge-vector updates per second over
-the whole step, nnz * R * k / t_step.
+the whole step, nnz * R * k / t_step.  The line also carries compact
+records of the other workloads (`workloads`: the 512-graph batch, R-MAT in
+BF16 and FP32 storage with their accuracy, the adjoint on the grid), unless
+--no-extras is given.
 
 Other forms, one JSON line each (--workload): `batch` (512 Chung-Lu graphs
 in one captured launch sequence), `bf16` (R-MAT n = 2^24, 2^28 edges, BF16
@@ -51,15 +57,43 @@ def sweep_bytes(n: int, nnz: int, r: int, bx_in: int, weighted: bool, bx_out: "i
 
 
 def dist_bytes(n: int, nnz: int, m: int, r: int, bx: int) -> int:
-    """Algorithmic bytes of the distance pass: row pointers, columns and
-    edge ids once, the rescaled block once, one FP32 distance per edge."""
-    return (n + 1) * 8 + nnz * 4 + nnz * 4 + n * r * bx + 4 * m
+    """Algorithmic bytes of the distance pass: row pointers and columns
+    once, the edge ids of the upper entries (one per edge), the vector
+    block once, one FP32 distance per edge."""
+    return (n + 1) * 8 + nnz * 4 + m * 4 + n * r * bx + 4 * m
+
+
+def relax_sweep_bytes(n: int, nnz: int, r: int, k: int, weighted: bool, store_bytes: int, tail32: int,
+                      tail64: int) -> list:
+    """Algorithmic bytes of each of the k sweeps: x^(0) in FP32 (FP64 for
+    FP64 storage), sweeps 1..k-tail32 stored in `store_bytes` (BF16 2, FP32
+    4), then FP32 up to k-tail64, then FP64."""
+    def b(t):            # bytes per element of x^(t)
+        if t == 0:
+            return 8 if store_bytes == 8 else 4
+        if t > k - tail64:
+            return 8
+        if t > k - tail32:
+            return 4
+        return store_bytes
+    return [sweep_bytes(n, nnz, r, b(t - 1), weighted, b(t)) for t in range(1, k + 1)]
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def sweep_traffic() -> "float | None":
-    """HBM traffic per k_sweep launch from the committed counter summary
-    (profiles/k_sweep_traffic.json), or None when the sweep kernel's source
-    has changed since those counters were taken."""
+    """Memory-side traffic per k_sweep launch from the committed counter
+    summary (profiles/k_sweep_traffic.json: FETCH_SIZE + WRITE_SIZE of the
+    step's sweeps, calibrated on a copy of known size), or None when the
+    sweep kernel's source has changed since those counters were taken."""
     import hashlib
     try:
         info = json.load(open(os.path.join(ROOT, "profiles", "k_sweep_traffic.json")))
@@ -159,13 +193,20 @@ def traced(api, timer, fn, reps):
     return ms, kern
 
 
+LIMITER = ("memory system: random 64-128 B row gathers, each a line fetch missing the XCD's 4 MB L2; "
+           "the line requests leave L2 for the memory side (Infinity Cache and HBM, which no counter on "
+           "this profiler separates) -- see profiles/k_sweep_chung_lu_n2e20_memory_counters.md")
+
+
 def roofline(kern: dict, bytes_per_launch: float, traffic=None) -> dict:
     launches, total = kern.get("k_sweep", (0, 0.0))
     avg = total / max(1, launches)
     achieved = bytes_per_launch / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
     return {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": bytes_per_launch,
-            "avg_launch_ms": avg}
+            "avg_launch_ms": avg, "limiter": LIMITER,
+            "traffic_source": ("profiles/k_sweep_traffic.json (rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, "
+                               "calibrated on a copy kernel; null when the kernel changed since)")}
 
 
 def base_result(args, value, step_ms, dtype, data, config, roof, cpu, **extra) -> dict:
@@ -179,20 +220,25 @@ def base_result(args, value, step_ms, dtype, data, config, roof, cpu, **extra) -
     return out
 
 
-def err_stats(got, want, floor_frac=0.1):
-    """Relative error of got against want (torch tensors on the GPU), with
-    values below floor_frac * median(want) measured against that floor."""
+def err_stats(got, want, tol):
+    """Relative error of every element of got against want (torch tensors
+    on the GPU; an exact zero in want needs an exact zero in got): max,
+    median, p99, p99.9 (quantiles over a fixed sample of 2^23 when larger)
+    and the count beyond tol."""
     import torch
     want = want.double()
-    floor = floor_frac * float(want.median())
-    den = torch.clamp(want.abs(), min=floor)
-    rel = ((got.double() - want).abs() / den).float()
+    diff = (got.double() - want).abs()
+    rel = torch.where(want != 0, diff / want.abs(), torch.where(diff > 0, torch.full_like(diff, float("inf")),
+                                                                 torch.zeros_like(diff)))
+    beyond = int((rel > tol).sum())
+    rel = rel.float()
     qs = torch.tensor([0.5, 0.99, 0.999], device=rel.device)
     n = rel.numel()
     pick = rel if n <= (1 << 23) else rel[torch.randint(0, n, (1 << 23,), device=rel.device,
                                                        generator=torch.Generator(rel.device).manual_seed(0))]
     q = torch.quantile(pick, qs).tolist()
-    return {"max": float(rel.max()), "median": q[0], "p99": q[1], "p999": q[2], "floor": floor}
+    return {"max": float(rel.max()), "median": q[0], "p99": q[1], "p999": q[2], "tol": tol, "beyond_tol": beyond,
+            "n": n}
 
 
 # ------------------------------------------------------------ Chung-Lu ---
@@ -208,16 +254,23 @@ def run_chung_lu(args, api, torch, dev):
     dg = api.DeviceGraph.from_host(g_run, dev, keep_host=False)
     n, m, nnz = dg.n, dg.m, 2 * dg.m
     torch.cuda.synchronize()
+    TAIL64 = W.FP64_TAIL
+    t0 = time.perf_counter()
+    comp = dg.components()            # grouped once per graph, like the layout
+    torch.cuda.synchronize()
+    t_comp = time.perf_counter() - t0
+    log(f"{comp.n_comp} connected components grouped in {t_comp * 1e3:.1f} ms")
 
     # buffers reused by every step
     ws_r = api._workspace(api.relax_workspace_bytes(
         dg, api.relax_opts(R, K, OMEGA, SEED_VEC, rows_per_wave=args.rows_per_wave,
-                           hub_degree=args.hub_degree)), dev)
+                           hub_degree=args.hub_degree, fp64_tail=TAIL64, comp=comp)), dev)
     ws_s = api._workspace(api.sparsify_fit_both_workspace_bytes(dg), dev)
     ws_d = api._workspace(api.edge_dist_workspace_bytes(dg), dev)
-    out = api.RelaxResult(x=torch.empty((n, R), dtype=torch.float32, device=dev),
+    out = api.RelaxResult(x=torch.empty((n, R), dtype=torch.float64, device=dev),
                           minmax=torch.empty(2 * R, dtype=torch.float64, device=dev),
-                          shift=torch.empty(R, dtype=torch.float64, device=dev), ckpt=None, store="f32")
+                          shift=torch.empty((max(1, comp.n_comp), R), dtype=torch.float64, device=dev), ckpt=None,
+                          store="f32")
     rho = torch.empty(m, dtype=torch.float32, device=dev)
     keep_l = torch.empty(m, dtype=torch.uint8, device=dev)
     keep_g = torch.empty(m, dtype=torch.uint8, device=dev)
@@ -226,8 +279,8 @@ def run_chung_lu(args, api, torch, dev):
 
     def relax_dist():
         api.relax(dg, R, K, OMEGA, SEED_VEC, ws=ws_r, out=out, rows_per_wave=args.rows_per_wave,
-                  hub_degree=args.hub_degree)
-        api.edge_dist(dg, out.x, out.minmax, out=rho, ws=ws_d)
+                  hub_degree=args.hub_degree, fp64_tail=TAIL64)
+        api.distances(dg, out, out=rho, ws=ws_d)
 
     def step():
         relax_dist()
@@ -255,10 +308,25 @@ def run_chung_lu(args, api, torch, dev):
 
     kept_l, kept_g = (int(v) for v in nk.tolist())
     weighted = dg.w is not None
-    sb = sweep_bytes(n, nnz, R, 4, weighted)
-    db = dist_bytes(n, nnz, m, R, 4)
+    per_sweep = relax_sweep_bytes(n, nnz, R, K, weighted, 4, K, TAIL64)
+    sb = sum(per_sweep) / K           # the k sweeps share one trace scope: bytes of an average sweep
+    db = dist_bytes(n, nnz, m, R, 8)
     roof = roofline(kern, sb, sweep_traffic())
-    rd_gbs = (K * sb + db) / (rd_ms * 1e-3) / 1e9
+    rd_gbs = (sum(per_sweep) + db) / (rd_ms * 1e-3) / 1e9
+    # context: the same relaxation with every sweep stored in FP32 (no FP64 tail)
+    out32 = api.RelaxResult(x=torch.empty((n, R), dtype=torch.float32, device=dev), minmax=out.minmax.clone(),
+                            shift=out.shift.clone(), ckpt=None, store="f32")
+    ws_r32 = api._workspace(api.relax_workspace_bytes(dg, api.relax_opts(R, K, OMEGA, SEED_VEC, comp=comp)), dev)
+    rho32 = torch.empty_like(rho)
+
+    def relax_dist32():
+        api.relax(dg, R, K, OMEGA, SEED_VEC, ws=ws_r32, out=out32)
+        api.distances(dg, out32, out=rho32, ws=ws_d)
+
+    relax_dist32()
+    rd32_ms = timer.run(relax_dist32, args.steps)
+    x32 = out32.x
+    del ws_r32, rho32
 
     # context: a device-to-device copy of 1 GiB (reads and writes 2 GiB), the streaming ceiling
     src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
@@ -331,7 +399,7 @@ def run_chung_lu(args, api, torch, dev):
     # context: the sweep's neighbour-row gathers alone, with nothing else asked of the
     # memory system (the irregular path's practical ceiling), and the vendor SpMM
     sweep_ms = roof["avg_launch_ms"]
-    probe_ms = gather_probe_ms(torch, timer, out.x, dg.col, R * 4)
+    probe_ms = gather_probe_ms(torch, timer, x32, dg.col, R * 4)
     gather = None
     if probe_ms:
         gather = {"probe_ms": probe_ms, "rows_per_s": nnz / (probe_ms * 1e-3),
@@ -340,7 +408,8 @@ def run_chung_lu(args, api, torch, dev):
                   "what": (f"one launch gathering all {nnz} neighbour rows ({R * 4} B each) in CSR "
                            "order with the graph's own column array, summing them; no weights, no "
                            "output rows, no arithmetic beyond the sum")}
-    spmm = vendor_spmm_ms(torch, timer, dg, out.x)
+    spmm = vendor_spmm_ms(torch, timer, dg, x32)
+    del x32, out32
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -351,7 +420,7 @@ def run_chung_lu(args, api, torch, dev):
         oracle.algebraic_distance(g_run, R, args.cpu_sweeps, OMEGA, seed=SEED_VEC)
         t_cpu = time.perf_counter() - t0
         cpu = {"value": nnz * R * args.cpu_sweeps / t_cpu, "unit": "edge-vector updates/s",
-               "cores": cores, "kind": "oracle",
+               "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
                "sample": (f"FP64 oracle (Algorithm 1 in the paper's order) on the same graph, all "
                           f"{R} vectors, {args.cpu_sweeps} of the {K} sweeps, then rescale and "
                           f"distances; {t_cpu:.2f}s wall on {cores} threads (about {t_cpu * cores:.0f} "
@@ -361,14 +430,18 @@ def run_chung_lu(args, api, torch, dev):
         "workload": (f"Chung-Lu power-law graph n=2^20, m={c['m']}, gamma={c['gamma']}, "
                      f"lognormal(0,1) weights; R={R}, k={K}, omega={OMEGA}, FP32; LOCAL and "
                      f"GLOBAL selection each fitted to {int(TARGET * 100)}% retention"),
-        "n": n, "m": m, "nnz": nnz, "d_max": dg.d_max, "R": R, "k": K,
-        "layout": args.layout, "parallelism": "single GPU",
+        "precision": (f"FP32 storage and arithmetic for sweeps 1..{K - TAIL64}, sweeps {K - TAIL64 + 1}..{K} "
+                      f"stored and computed in FP64, FP32 distances; each connected component centred by its "
+                      f"own weighted mean"),
+        "n": n, "m": m, "nnz": nnz, "d_max": dg.d_max, "R": R, "k": K, "fp64_tail": TAIL64,
+        "components": comp.n_comp, "layout": args.layout, "parallelism": "single GPU",
     }
     return base_result(
         args, nnz * R * K / (step_ms * 1e-3), step_ms, "f32", "synthetic (seeded Chung-Lu graph; no dataset)",
         config, roof, cpu,
         breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())},
         relax_dist_ms=rd_ms, relax_dist_hbm_frac=rd_gbs / HBM_PEAK_GBS,
+        relax_dist_fp32_only_ms=rd32_ms,
         copy_ceiling_GBs=copy_gbs,
         gather_ceiling=gather,
         vendor_spmm=spmm,
@@ -380,7 +453,7 @@ def run_chung_lu(args, api, torch, dev):
         sweep_updates_per_s=nnz * R / (roof["avg_launch_ms"] * 1e-3) if roof["avg_launch_ms"] else None,
         fit={"e_local": fit["e_local"], "e_global": fit["e_global"], "kept_local": kept_l,
              "kept_global": kept_g, "ratio_local": kept_l / m, "ratio_global": kept_g / m},
-        setup_s={"generate_and_layout": t_setup})
+        setup_s={"generate_and_layout": t_setup, "components": t_comp})
 
 
 # ----------------------------------------------------------- multilevel ---
@@ -453,7 +526,7 @@ def run_batch(args, api, torch, dev):
     log(f"{len(dgs)} graphs generated in {t_gen:.1f}s: n={n} m={m}")
     t0 = time.perf_counter()
     b = api.Batch(dgs, R, K, W.OMEGA, seed=b_["seed_vec"], graph_id=b_["graph_id"], orient=api.AD_LOCAL,
-                  e=b_["e"], autotune=True)
+                  e=b_["e"], autotune=True, fp64_tail=W.FP64_TAIL)
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
     log(f"batch created (pack, autotune, capture) in {t_create:.1f}s; rows_per_wave={b.rows_per_wave}")
@@ -464,7 +537,7 @@ def run_batch(args, api, torch, dev):
     # the same launch sequence uncaptured, traced per kernel
     unc_ms, kern = traced(api, timer, lambda: b.run(captured=False), args.steps)
     weighted = True
-    roof = roofline(kern, sweep_bytes(n, nnz, R, 4, weighted))
+    roof = roofline(kern, sum(relax_sweep_bytes(n, nnz, R, K, weighted, 4, K, W.FP64_TAIL)) / K)
     kept = int(b.fetch()[2].sum().item())
     cpu = None
     if not args.no_cpu_baseline:
@@ -480,12 +553,13 @@ def run_batch(args, api, torch, dev):
             done_nnz += 2 * g.m
             q += 1
         cpu = {"value": done_nnz * R * K / t_cpu, "unit": "edge-vector updates/s", "cores": cores,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": (f"FP64 oracle on the first {q} of the {len(ds)} graphs ({done_nnz // 2} edges), "
                           f"R={R}, all {K} sweeps, rescale and distances; {t_cpu:.2f}s; selection not included")}
     config = {
         "workload": (f"batch of {len(dgs)} Chung-Lu graphs (gamma 2.1, lognormal weights), n log-uniform in "
-                     f"[1e3, 2e5], average degree uniform in [8, 32]; R={R}, k={K}, FP32; LOCAL selection "
+                     f"[1e3, 2e5], average degree uniform in [8, 32]; R={R}, k={K}, FP32 (last "
+                     f"{W.FP64_TAIL} sweeps FP64, components centred apart); LOCAL selection "
                      f"at e={b_['e']}; one captured launch sequence, rows_per_wave autotuned"),
         "graphs": len(dgs), "n": n, "m": m, "nnz": nnz, "R": R, "k": K,
         "rows_per_wave": b.rows_per_wave, "parallelism": "single GPU",
@@ -501,10 +575,12 @@ def run_batch(args, api, torch, dev):
 # ---------------------------------------------------------------- BF16 ---
 
 def run_bf16(args, api, torch, dev):
+    """R-MAT n = 2^24, 2^28 edges: BF16 storage (the step timed in the line)
+    beside the FP32 path, both against the library's FP64 path."""
     from paper_1601_05527_amd import graphs
     from paper_1601_05527_amd import workloads as W
     c = W.RMAT
-    R, K, TAIL, TARGET = c["R"], c["k"], c["fp32_tail"], c["target"]
+    R, K, TAIL, TAIL64, TARGET = c["R"], c["k"], c["fp32_tail"], c["fp64_tail"], c["target"]
     t0 = time.perf_counter()
     d = W.rmat_graph(dev)
     dg = api.DeviceGraph.from_tensors(d)
@@ -512,61 +588,62 @@ def run_bf16(args, api, torch, dev):
     t_gen = time.perf_counter() - t0
     n, m, nnz = dg.n, dg.m, 2 * dg.m
     log(f"R-MAT generated in {t_gen:.1f}s: n={n} m={m} d_max={dg.d_max}")
-    rho = torch.empty(m, dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    comp = dg.components()
+    torch.cuda.synchronize()
+    t_comp = time.perf_counter() - t0
+    log(f"{comp.n_comp} components grouped in {t_comp:.2f}s")
     ws_d = api._workspace(api.edge_dist_workspace_bytes(dg), dev)
     ws_s = api._workspace(api.sparsify_fit_both_workspace_bytes(dg), dev)
     keep_l = torch.empty(m, dtype=torch.uint8, device=dev)
     keep_g = torch.empty(m, dtype=torch.uint8, device=dev)
     nk = torch.empty(2, dtype=torch.int64, device=dev)
     fits = {}
+    tails = {"bf16": (TAIL, TAIL64), "f32": (K, W.FP64_TAIL), "f64": (K, 0)}
 
     def make(store):
-        opts = api.relax_opts(R, K, W.OMEGA, c["seed_vec"], store=store, fp32_tail=TAIL)
+        t32, t64 = tails[store]
+        opts = api.relax_opts(R, K, W.OMEGA, c["seed_vec"], store=store, fp32_tail=t32, fp64_tail=t64, comp=comp)
         ws = api._workspace(api.relax_workspace_bytes(dg, opts), dev)
-        xdt = torch.float64 if store == "f64" else torch.float32
-        out = api.RelaxResult(x=torch.empty((n, R), dtype=xdt, device=dev),
+        out = api.RelaxResult(x=torch.empty((n, R), dtype=torch.float64, device=dev),
                               minmax=torch.empty(2 * R, dtype=torch.float64, device=dev),
-                              shift=torch.empty(R, dtype=torch.float64, device=dev), ckpt=None, store=store)
-        rho_s = rho if store != "f64" else torch.empty(m, dtype=torch.float64, device=dev)
+                              shift=torch.empty((max(1, comp.n_comp), R), dtype=torch.float64, device=dev),
+                              ckpt=None, store=store)
+        rho_s = torch.empty(m, dtype=torch.float64 if store == "f64" else torch.float32, device=dev)
 
         def relax_dist():
-            api.relax(dg, R, K, W.OMEGA, c["seed_vec"], store=store, fp32_tail=TAIL, ws=ws, out=out)
-            api.edge_dist(dg, out.x, out.minmax, out=rho_s, ws=ws_d)
+            api.relax(dg, R, K, W.OMEGA, c["seed_vec"], store=store, fp32_tail=t32, fp64_tail=t64, ws=ws, out=out)
+            api.distances(dg, out, out=rho_s, ws=ws_d)
 
         def step():
             relax_dist()
             _, _, _, (e_l, e_g) = api.sparsify_fit_both(dg, rho_s, TARGET, ws=ws_s, keep_local=keep_l,
                                                         keep_global=keep_g, n_kept=nk)
             fits[(store, "local")], fits[(store, "global")] = e_l, e_g
-        return step, relax_dist, rho_s, ws
+        return step, relax_dist, rho_s, ws, out
 
     timer = Timer(torch)
     results = {}
     for store in ("bf16", "f32"):
-        step, relax_dist, rho_s, ws = make(store)
+        step, relax_dist, rho_s, ws, out = make(store)
         for _ in range(args.warmup):
             step()
         ms, kern = traced(api, timer, step, args.steps)
         rd_ms = timer.run(relax_dist, args.steps)
         relax_dist()
-        results[store] = {"ms": ms, "relax_dist_ms": rd_ms, "kern": kern, "rho": rho_s.clone()}
-        del ws
+        results[store] = {"ms": ms, "relax_dist_ms": rd_ms, "kern": kern, "rho": rho_s}
+        del ws, out
         log(f"{store}: {ms:.2f} ms per step, relax+dist {rd_ms:.2f} ms")
-    # FP64 reference on the GPU (its parity with the oracle is tested), for error statistics
-    _, relax_dist64, rho64, ws64 = make("f64")
+    # reference: the library's FP64 path (FP64 storage and arithmetic; its parity with the oracle is tested)
+    _, relax_dist64, rho64, ws64, out64 = make("f64")
     relax_dist64()
     torch.cuda.synchronize()
-    acc = {"bf16_vs_f64": err_stats(results["bf16"]["rho"], rho64),
-           "f32_vs_f64": err_stats(results["f32"]["rho"], rho64),
-           "bf16_vs_f32": err_stats(results["bf16"]["rho"], results["f32"]["rho"])}
-    del rho64, ws64
-    # sweep bytes: x^(0) FP32, sweeps 1 .. k - tail stored in BF16, the last `tail` in FP32
+    acc = {"reference": "the library's FP64 path on the GPU (FP64 storage and arithmetic)",
+           "bf16": err_stats(results["bf16"]["rho"], rho64, 2e-2),
+           "f32": err_stats(results["f32"]["rho"], rho64, 1e-5)}
+    del rho64, ws64, out64
     weighted = True
-    per = []
-    for t in range(1, K + 1):
-        bin_ = 4 if (t - 1 == 0 or t - 1 > K - TAIL) else 2
-        bout = 4 if t > K - TAIL else 2
-        per.append(sweep_bytes(n, nnz, R, bin_, weighted, bout))
+    per = relax_sweep_bytes(n, nnz, R, K, weighted, 2, TAIL, TAIL64)
     roof = roofline(results["bf16"]["kern"], sum(per) / K)
     cpu = None
     if not args.no_cpu_baseline:
@@ -578,28 +655,30 @@ def run_bf16(args, api, torch, dev):
         oracle.relax_vector(g, x0, sweeps, W.OMEGA)
         t_cpu = time.perf_counter() - t0
         cpu = {"value": nnz * sweeps / t_cpu, "unit": "edge-vector updates/s", "cores": oracle_threads(),
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"FP64 oracle, 1 of the {R} vectors, {sweeps} of the {K} sweeps on the same graph; "
                          f"{t_cpu:.2f}s"}
         del g
     ms = results["bf16"]["ms"]
     config = {
         "workload": (f"R-MAT (a,b,c,d)=(.57,.19,.19,.05) n=2^{c['scale']}, m={m}, uniform(0.5,2) weights; "
-                     f"R={R}, k={K}, test vectors stored in BF16 (last {TAIL} sweeps FP32), FP32 arithmetic; "
-                     f"LOCAL and GLOBAL selection each fitted to {int(TARGET * 100)}% retention"),
-        "n": n, "m": m, "nnz": nnz, "d_max": dg.d_max, "R": R, "k": K, "fp32_tail": TAIL,
-        "parallelism": "single GPU",
+                     f"R={R}, k={K}, test vectors stored in BF16 (last {TAIL} sweeps wider: {TAIL - TAIL64} FP32, "
+                     f"{TAIL64} FP64), FP32 arithmetic; components centred apart and re-centred before every "
+                     f"BF16 sweep; LOCAL and GLOBAL selection each fitted to {int(TARGET * 100)}% retention"),
+        "n": n, "m": m, "nnz": nnz, "d_max": dg.d_max, "R": R, "k": K, "fp32_tail": TAIL, "fp64_tail": TAIL64,
+        "components": comp.n_comp, "parallelism": "single GPU",
     }
     return base_result(
         args, nnz * R * K / (ms * 1e-3), ms, "bf16 storage, f32 arithmetic",
         "synthetic (seeded R-MAT graph; no dataset)", config, roof, cpu,
         fp32_path={"ms_per_step": results["f32"]["ms"], "relax_dist_ms": results["f32"]["relax_dist_ms"],
-                   "value": nnz * R * K / (results["f32"]["ms"] * 1e-3),
+                   "value": nnz * R * K / (results["f32"]["ms"] * 1e-3), "fp64_tail": W.FP64_TAIL,
                    "breakdown_ms_per_step": {k_: v[1] / args.steps
                                              for k_, v in sorted(results["f32"]["kern"].items())}},
         relax_dist_ms=results["bf16"]["relax_dist_ms"],
         breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(results["bf16"]["kern"].items())},
-        accuracy=acc, fit={f"{s}_{o}": v for (s, o), v in fits.items()}, setup_s={"generate": t_gen})
+        accuracy=acc, fit={f"{s}_{o}": v for (s, o), v in fits.items()},
+        setup_s={"generate": t_gen, "components": t_comp})
 
 
 # ------------------------------------------------------------- adjoint ---
@@ -613,17 +692,18 @@ def run_adjoint(args, api, torch, dev):
     dg = api.DeviceGraph.from_host(g, dev)
     n, m, nnz = dg.n, dg.m, 2 * dg.m
     cvec = torch.from_numpy(np.random.default_rng(c["seed"]).normal(size=m).astype(np.float32)).to(dev)
-    opts = api.relax_opts(R, K, W.OMEGA, c["seed_vec"], ckpt_every=CK)
+    comp = dg.components()
+    opts = api.relax_opts(R, K, W.OMEGA, c["seed_vec"], ckpt_every=CK, comp=comp)
     ws_r = api._workspace(api.relax_workspace_bytes(dg, opts), dev)
     ws_d = api._workspace(api.edge_dist_workspace_bytes(dg), dev)
     nck = int(api.lib.ad_relax_num_checkpoints(api.ctypes.byref(opts)))
     out = api.RelaxResult(x=torch.empty((n, R), dtype=torch.float32, device=dev),
                           minmax=torch.empty(2 * R, dtype=torch.float64, device=dev),
-                          shift=torch.empty(R, dtype=torch.float64, device=dev),
+                          shift=torch.empty((max(1, comp.n_comp), R), dtype=torch.float64, device=dev),
                           ckpt=torch.empty((nck, n, R), dtype=torch.float32, device=dev), store="f32")
     rho = torch.empty(m, dtype=torch.float32, device=dev)
     gw = torch.empty(m, dtype=torch.float32, device=dev)
-    opts_b = api.relax_opts(R, K, W.OMEGA, c["seed_vec"], ckpt_every=CK)
+    opts_b = api.relax_opts(R, K, W.OMEGA, c["seed_vec"], ckpt_every=CK, comp=comp)
     ws_b = api._workspace(int(api.lib.ad_relax_backward_workspace_size(api.ctypes.byref(dg.abi()),
                                                                        api.ctypes.byref(opts_b))), dev)
 
@@ -645,14 +725,20 @@ def run_adjoint(args, api, torch, dev):
     b_ms = timer.run(backward, args.steps)
     step_ms, kern = traced(api, timer, step, args.steps)
     roof = roofline(kern, sweep_bytes(n, nnz, R, 4, True))
+    # the gradient against the FP64 oracle's reverse mode (test infrastructure, outside the timed region)
+    import oracle
+    t0 = time.perf_counter()
+    want = oracle.grad_weights(g, cvec.cpu().numpy().astype(np.float64), R, K, W.OMEGA, seed=c["seed_vec"])
+    t_cpu = time.perf_counter() - t0
+    got = gw.cpu().numpy().astype(np.float64)
+    per = np.abs(got - want) / (np.abs(want) + 1e-3 * np.abs(want).max())
+    grad_err = {"rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)), "max_per_edge": float(per.max()),
+                "p999_per_edge": float(np.quantile(per, 0.999)),
+                "per_edge_measure": "|g - g_oracle| / (|g_oracle| + 1e-3 max |g_oracle|)"}
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        t0 = time.perf_counter()
-        oracle.grad_weights(g, cvec.cpu().numpy().astype(np.float64), R, K, W.OMEGA, seed=c["seed_vec"])
-        t_cpu = time.perf_counter() - t0
         cpu = {"value": nnz * R * K / t_cpu, "unit": "edge-vector updates/s (forward + gradient)",
-               "cores": oracle_threads(), "kind": "oracle",
+               "cores": oracle_threads(), "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"FP64 oracle reverse-mode gradient on the same graph, R={R}, k={K}; {t_cpu:.2f}s"}
     config = {
         "workload": (f"{c['side']}x{c['side']} grid plus {g.m - 2 * c['side'] * (c['side'] - 1)} random long-range "
@@ -662,7 +748,7 @@ def run_adjoint(args, api, torch, dev):
     }
     return base_result(args, nnz * R * K / (step_ms * 1e-3), step_ms, "f32",
                        "synthetic (seeded grid with long-range edges; no dataset)", config, roof, cpu,
-                       forward_ms=f_ms, backward_ms=b_ms, backward_over_forward=b_ms / f_ms,
+                       forward_ms=f_ms, backward_ms=b_ms, backward_over_forward=b_ms / f_ms, gradient_error=grad_err,
                        breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())})
 
 
@@ -707,6 +793,38 @@ def run_fp64(args, api, torch, dev):
                        breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())})
 
 
+def extras(args, api, torch, dev) -> dict:
+    """Compact records of the batch, R-MAT and adjoint workloads for the
+    default line (fewer steps, no CPU baselines; each workload's own line
+    holds the full record)."""
+    import copy
+    import gc
+    sub = copy.copy(args)
+    sub.steps, sub.warmup, sub.no_cpu_baseline = args.extra_steps, 1, True
+    out = {}
+    keep = ("value", "unit", "ms_per_step", "dtype", "roofline")
+    for name, fn in (("batch", run_batch), ("rmat", run_bf16), ("adjoint", run_adjoint)):
+        t0 = time.perf_counter()
+        r = fn(sub, api, torch, dev)
+        rec = {k_: r[k_] for k_ in keep}
+        rec["roofline"] = {k_: r["roofline"][k_] for k_ in ("achieved", "frac", "avg_launch_ms")}
+        rec["workload"] = r["config"]["workload"]
+        rec["steps"] = sub.steps
+        for k_ in ("uncaptured_ms_per_step", "kept", "fp32_path", "accuracy", "forward_ms", "backward_ms",
+                   "backward_over_forward", "gradient_error", "relax_dist_ms"):
+            if k_ in r:
+                rec[k_] = r[k_]
+        if "fp32_path" in rec:
+            rec["fp32_path"] = {k_: v for k_, v in rec["fp32_path"].items() if k_ != "breakdown_ms_per_step"}
+        rec["wall_s"] = time.perf_counter() - t0
+        out[name] = rec
+        log(f"{name}: {rec['ms_per_step']:.2f} ms per step ({rec['wall_s']:.0f} s with set-up)")
+        del r
+        gc.collect()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -721,6 +839,9 @@ def main() -> int:
     ap.add_argument("--layout", choices=["degree", "given"], default="degree")
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--hub-degree", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: leave out the compact batch / R-MAT / adjoint records")
+    ap.add_argument("--extra-steps", type=int, default=3, help="timed steps of each compact record")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB device to device "
                          "(a kernel of known traffic for calibrating memory counters)")
@@ -741,6 +862,11 @@ def main() -> int:
     run = {"chung-lu": run_chung_lu, "batch": run_batch, "bf16": run_bf16, "adjoint": run_adjoint,
            "fp64": run_fp64, "multilevel": run_multilevel}[args.workload]
     result = run(args, api, torch, dev)
+    if args.workload == "chung-lu" and not args.no_extras:
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        result["workloads"] = extras(args, api, torch, dev)
     print(json.dumps(result), flush=True)
     return 0
 

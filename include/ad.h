@@ -91,6 +91,21 @@ typedef struct {
                                  order instead of gathering them; NULL = gather          */
 } ad_graph;
 
+/* Connected components of a graph, grouped so that the relaxation can centre
+ * each component by its own weighted mean (see ad_relax).  Built once per
+ * graph by ad_components_build; every array is DEVICE memory owned by the
+ * caller.  Isolated vertices (no edges) belong to no component.           */
+typedef struct {
+    int64_t n_comp;           /* host: components with at least one edge               */
+    int64_t n_chunks;         /* host: sum over components of ceil(size / 1024)        */
+    const int32_t *comp_of;   /* [n] component of each vertex, -1 when isolated        */
+    const int32_t *members;   /* [n_live] the non-isolated vertices, component by
+                                 component (components in increasing order of their
+                                 smallest vertex, vertices ascending within each)      */
+    const int64_t *comp_start;/* [n_comp+1] offsets of the components in members       */
+    const int64_t *chunk_start;/* [n_comp+1] cumulative 1024-member chunks             */
+} ad_components;
+
 /* Parameters of Algorithm 1's relaxation. */
 typedef struct {
     int32_t R;                /* test vectors, 1..64                                   */
@@ -114,7 +129,32 @@ typedef struct {
                                  except through FP summation order                     */
     int32_t hub_degree;       /* launch shape, 0 = automatic: rows with more neighbours
                                  get a 256-thread workgroup each                       */
+    int32_t fp64_tail;        /* AD_F32 / AD_BF16: the last fp64_tail sweeps are stored
+                                 in FP64 with FP64 arithmetic (0 = none); x_out is then
+                                 FP64.  With AD_BF16 it must be below fp32_tail, which
+                                 counts every final sweep stored wider than BF16       */
+    const ad_components *comp;/* NULL: one shift per vector (the weighted mean over the
+                                 whole graph).  Else: one shift per vector and connected
+                                 component (its own weighted mean), see ad_relax       */
 } ad_relax_opts;
+
+/* ----------------------------------------------------------- components -- */
+
+/* Workspace bytes for ad_components_build (0 when n >= 2^31). */
+size_t ad_components_workspace_size(const ad_graph *g);
+
+/* The connected components of g (Preliminaries: G undirected) in the
+ * grouped form of ad_components, for ad_relax's per-component centring.
+ * Outputs, DEVICE and caller-owned: comp_of [n]; members [n] (the first
+ * n_live written); comp_start and chunk_start [n+1] (the first n_comp + 1
+ * written).  n_comp_host, n_chunks_host: HOST.  Components are labelled by
+ * hooking and pointer jumping and grouped by rocPRIM's stable radix sort, so
+ * the result depends only on the graph.  SYNCHRONISES `stream`.  Errors:
+ * AD_ERR_INVALID_ARG, AD_ERR_WORKSPACE, AD_ERR_UNSUPPORTED (n >= 2^31). */
+ad_status ad_components_build(const ad_graph *g, int32_t *comp_of, int32_t *members,
+                              int64_t *comp_start, int64_t *chunk_start, int64_t *n_comp_host,
+                              int64_t *n_chunks_host, void *ws, size_t ws_bytes,
+                              hipStream_t stream);
 
 /* ---------------------------------------------------------------- relax -- */
 
@@ -136,16 +176,31 @@ int32_t ad_relax_num_checkpoints(const ad_relax_opts *o);
  * grid in [-1/2, 1/2).  Otherwise x0 holds [n][R] start values (FP64 when
  * store == AD_F64, else FP32).
  *
+ * Centring (a change of frame that leaves x^(k) and xhat unchanged): the
+ * sweeps keep every vector that is constant on each connected component
+ * fixed, and conserve each component's weighted mean sum s_i x_i / sum s_i
+ * (s_i = sum_j w_ij).  The library subtracts from x^(0), per vector, that
+ * mean rounded to a multiple of 2^-24 -- one shift per component when
+ * o->comp is given, else one for the whole graph -- and sweeps the
+ * differences, whose rounding errors then scale with how far each
+ * component still is from its own limit instead of with its mean.
+ *
+ * Arithmetic: AD_F64 sweeps in FP64; AD_F32 in FP32; AD_BF16 stores sweeps
+ * 1..k-fp32_tail in BF16 (round to nearest even) and computes in FP32.  The
+ * last fp64_tail sweeps are stored in FP64 and computed in FP64, the
+ * neighbour average as a correctly rounded quotient sum_j w_ij x_j / s_i (as
+ * in every FP64 sweep).
+ *
  * Outputs:
- *   x_out      [n][R] row-major, FP64 when store == AD_F64, else FP32.  It holds
- *              x^(k) - shift_r, where shift_r is a per-vector constant (the
- *              weighted mean sum_i s_i x_i^(0) / sum_i s_i rounded to a multiple
- *              of 2^-24).  The sweeps preserve any constant vector, so this is
- *              x^(k) exactly up to rounding, and min/max/xhat refer to it.
- *   minmax_out [2R] doubles: min_r then max_r of x_out over non-isolated vertices.
- *   shift_out  [R] doubles or NULL: the shifts above.
+ *   x_out      [n][R] row-major, FP64 when store == AD_F64 or fp64_tail > 0,
+ *              else FP32: x^(k) minus the shift of the vertex's component
+ *              (isolated vertices: minus 0).
+ *   minmax_out [2R] doubles: min_r then max_r of x^(k) itself (shift added
+ *              back) over the non-isolated vertices.
+ *   shift_out  NULL, or [n_comp][R] doubles (o->comp given) or [R] doubles:
+ *              the shifts above.
  *   ckpt       NULL, or [ad_relax_num_checkpoints][n][R] in x_out's type:
- *              the (shifted) x^(0), x^(c), x^(2c), ...
+ *              the (shifted) x^(0), x^(c), x^(2c), ...; needs fp64_tail == 0.
  * x_out must not alias x0 or ckpt. */
 ad_status ad_relax(const ad_graph *g, const ad_relax_opts *o, const void *x0,
                    void *x_out, double *minmax_out, double *shift_out, void *ckpt,
@@ -160,11 +215,13 @@ size_t ad_edge_dist_workspace_size(const ad_graph *g);
  *     rho_e = sqrt( sum_r ((x_i,r - x_j,r) / (max_r - min_r))^2 ),
  * i.e. the L2 distance of the rescaled vectors (a vector with max_r == min_r
  * contributes 0).  x: [n][R] in x_dtype (AD_F64 or AD_F32), as written by
- * ad_relax; minmax: [2R] doubles as written by ad_relax.  rho: [m], FP64
- * when x_dtype == AD_F64, else FP32. */
+ * ad_relax (both ends of an edge lie in one component, so its shift
+ * cancels); minmax: [2R] doubles as written by ad_relax.  rho: [m] in
+ * rho_dtype: AD_F64 needs FP64 x; AD_F32 takes either (with FP64 x the
+ * arithmetic is FP64 and only rho is rounded to FP32). */
 ad_status ad_edge_dist(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
-                       const double *minmax, void *rho, void *ws, size_t ws_bytes,
-                       hipStream_t stream);
+                       const double *minmax, ad_dtype rho_dtype, void *rho, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------ selection -- */
 
@@ -393,6 +450,7 @@ typedef struct {
                                  span_value)                                       */
     int32_t segment;          /* 0 coarsest, 1 middle, 2 finest third of the levels  */
     double span_value;        /* the entry the level-span rule gives, <= 1           */
+    int32_t fp64_tail;        /* AD_F32: final sweeps stored in FP64 (ad_relax_opts)  */
 } ad_ml_opts;
 
 /* Host helper: the level-span ratio vector of Section 6 (implementation
@@ -404,7 +462,8 @@ ad_status ad_ml_level_span(int32_t n_levels, int32_t span, int32_t segment, doub
                            double *out_host);
 
 /* Algorithm 6 (MLSparsify).  Level 0 is g.  At level l: distances by
- * ad_relax + ad_edge_dist (graph id graph_id + l); if n <= n_min, or
+ * ad_relax + ad_edge_dist (graph id graph_id + l, the level's connected
+ * components from ad_components_build, fp64_tail for FP32); if n <= n_min, or
  * l == levels - 1, or the graph has no edges, or ad_ml_aggregate would keep
  * more than 90% of the vertices, level l is the coarsest (D = l): SparsifyB
  * (ad_sparsify_binned, graph id graph_id + D) selects with the vector's
@@ -435,16 +494,19 @@ size_t ad_relax_backward_workspace_size(const ad_graph *g, const ad_relax_opts *
 
 /* Reverse-mode derivative of a loss L(rho) with respect to the edge weights,
  * through ad_edge_dist, the rescale and the k sweeps of ad_relax (start
- * vectors do not depend on w).  Requires store == AD_F32 and ckpt_every > 0.
+ * vectors do not depend on w).  Requires store == AD_F32, fp64_tail == 0
+ * and ckpt_every > 0.
  *   ckpt     : checkpoints written by ad_relax with the same graph and opts.
- *   x_k      : x_out of that ad_relax call; minmax: its minmax_out.
+ *   x_k      : x_out of that ad_relax call; minmax, shift: its minmax_out
+ *              and shift_out (per component when o->comp is given).
  *   grad_rho : [m] FP32, dL/drho_e.
  *   grad_w   : [m] FP32 output, dL/dw_e with w_ij = w_ji = w_e.
  * The min and max of the rescale are differentiated at the first vertex
  * attaining them; edges with rho_e == 0 pass no gradient. */
 ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o, const void *ckpt,
-                            const void *x_k, const double *minmax, const float *grad_rho,
-                            float *grad_w, void *ws, size_t ws_bytes, hipStream_t stream);
+                            const void *x_k, const double *minmax, const double *shift,
+                            const float *grad_rho, float *grad_w, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
 
 /* Edge weights to CSR order: w_entries[p] = w_edge[eid[p]] for p < 2m (the
  * layout ad_relax reads; used when the weights are the variables of the
@@ -458,12 +520,15 @@ ad_status ad_graph_col_orig(const ad_graph *g, int32_t *col_orig, hipStream_t st
 
 /* --------------------------------------------------------------- batch --- */
 
-/* Batched form: G independent graphs, each run through ad_relax (FP32),
- * ad_edge_dist and ad_sparsify at one fixed e, as one captured sequence of
- * kernel launches covering all graphs (a HIP graph replayed by
- * ad_batch_run).  Graph q is relaxed with key word o->graph_id + q; its
- * distances, kept edges and count equal, bit for bit, those of the three
- * calls on graph q alone with the same options (including rows_per_wave).
+/* Batched form: G independent graphs, each run through ad_relax (FP32
+ * storage, optionally with an FP64 tail), ad_edge_dist (FP32 rho) and
+ * ad_sparsify at one fixed e, as one captured sequence of kernel launches
+ * covering all graphs (a HIP graph replayed by ad_batch_run).  Graph q is
+ * relaxed with key word o->graph_id + q and centred per connected component
+ * (the batch builds the components of its packed graph at creation;
+ * o->comp is ignored); its distances, kept edges and count equal, bit for
+ * bit, those of the three calls on graph q alone with the same options
+ * (including rows_per_wave) and its own ad_components_build.
  * The batch owns a packed copy of the graphs, its workspaces and its
  * outputs (device memory allocated by ad_batch_create, freed by
  * ad_batch_destroy -- the one exception to "no call allocates").
@@ -477,7 +542,8 @@ typedef struct {
 } ad_batch_opts;
 
 /* graphs: host array of G graph descriptions (device pointers, host n, m,
- * d_max); o: relaxation options (store must be AD_F32, no checkpoints). */
+ * d_max); o: relaxation options (store must be AD_F32, no checkpoints;
+ * fp64_tail allowed). */
 ad_status ad_batch_create(int32_t G, const ad_graph *graphs, const ad_relax_opts *o,
                           const ad_batch_opts *bo, ad_batch **out, hipStream_t stream);
 /* Replays the captured sequence on `stream`. */

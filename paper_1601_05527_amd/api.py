@@ -34,11 +34,17 @@ class ADGraph(ctypes.Structure):
                 ("col_orig", ctypes.c_void_p)]
 
 
+class ADComponents(ctypes.Structure):
+    _fields_ = [("n_comp", ctypes.c_int64), ("n_chunks", ctypes.c_int64), ("comp_of", ctypes.c_void_p),
+                ("members", ctypes.c_void_p), ("comp_start", ctypes.c_void_p), ("chunk_start", ctypes.c_void_p)]
+
+
 class ADRelaxOpts(ctypes.Structure):
     _fields_ = [("R", ctypes.c_int32), ("k", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("graph_id", ctypes.c_uint64), ("store", ctypes.c_int),
                 ("fp32_tail", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
-                ("rows_per_wave", ctypes.c_int32), ("hub_degree", ctypes.c_int32)]
+                ("rows_per_wave", ctypes.c_int32), ("hub_degree", ctypes.c_int32),
+                ("fp64_tail", ctypes.c_int32), ("comp", ctypes.POINTER(ADComponents))]
 
 
 class ADBatchOpts(ctypes.Structure):
@@ -51,7 +57,7 @@ class ADMLOpts(ctypes.Structure):
                 ("levels", ctypes.c_int32), ("n_min", ctypes.c_int64), ("e_host", ctypes.c_void_p),
                 ("eps", ctypes.c_double), ("theta", ctypes.c_double), ("bin_seed", ctypes.c_uint64),
                 ("fit", ctypes.c_int32), ("span", ctypes.c_int32), ("segment", ctypes.c_int32),
-                ("span_value", ctypes.c_double)]
+                ("span_value", ctypes.c_double), ("fp64_tail", ctypes.c_int32)]
 
 
 class ADError(RuntimeError):
@@ -74,7 +80,9 @@ def _load_lib():
         "ad_relax_num_checkpoints": (i32, [O]),
         "ad_relax": (st, [G, O, P, P, P, P, P, P, S, P]),
         "ad_edge_dist_workspace_size": (S, [G]),
-        "ad_edge_dist": (st, [G, i32, ctypes.c_int, P, P, P, P, S, P]),
+        "ad_edge_dist": (st, [G, i32, ctypes.c_int, P, P, ctypes.c_int, P, P, S, P]),
+        "ad_components_workspace_size": (S, [G]),
+        "ad_components_build": (st, [G, P, P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i64), P, S, P]),
         "ad_budget_table": (st, [i32, f64, P]),
         "ad_sparsify_workspace_size": (S, [G]),
         "ad_sparsify": (st, [G, ctypes.c_int, P, ctypes.c_int, P, P, P, P, S, P]),
@@ -100,7 +108,7 @@ def _load_lib():
         "ad_ml_sparsify": (st, [G, ctypes.POINTER(ADMLOpts), P, ctypes.POINTER(i64), ctypes.POINTER(i32), P]),
         "ad_sparsify_fit_both": (st, [G, ctypes.c_int, P, f64, P, P, P, P, P, S, P]),
         "ad_relax_backward_workspace_size": (S, [G, O]),
-        "ad_relax_backward": (st, [G, O, P, P, P, P, P, P, S, P]),
+        "ad_relax_backward": (st, [G, O, P, P, P, P, P, P, P, S, P]),
         "ad_edge_to_entries": (st, [G, P, P, P]),
         "ad_graph_col_orig": (st, [G, P, P]),
         "ad_batch_create": (st, [i32, G, O, ctypes.POINTER(ADBatchOpts), ctypes.POINTER(P), P]),
@@ -177,6 +185,7 @@ class DeviceGraph:
     orig_id: Optional[torch.Tensor]
     host: Optional[_graphs.Graph] = None
     col_orig: Optional[torch.Tensor] = None
+    comp: Optional["Components"] = None
 
     @classmethod
     def from_host(cls, g: _graphs.Graph, device="cuda", keep_host: bool = True,
@@ -225,8 +234,52 @@ class DeviceGraph:
                        None if self.col_orig is None else self.col_orig.data_ptr())
 
     def with_weights(self, w_entries: Optional[torch.Tensor]) -> "DeviceGraph":
+        # positive weights keep the components, so the grouping carries over
         return DeviceGraph(self.n, self.m, self.d_max, self.row_ptr, self.col, w_entries,
-                           self.eid, self.orig_id, self.host, self.col_orig)
+                           self.eid, self.orig_id, self.host, self.col_orig, self.comp)
+
+    def components(self) -> "Components":
+        """The graph's connected components grouped for the per-component
+        centring of ``ad_relax`` (``ad_components_build``), built on first use
+        and kept with the graph.  Synchronises the current stream."""
+        if self.comp is None:
+            self.comp = components(self)
+        return self.comp
+
+
+@dataclass
+class Components:
+    """Device arrays of ``ad_components`` plus the ABI struct."""
+
+    n_comp: int
+    n_chunks: int
+    comp_of: torch.Tensor        # int32 [n], -1 for isolated vertices
+    members: torch.Tensor        # int32 [n]
+    comp_start: torch.Tensor     # int64 [n + 1]
+    chunk_start: torch.Tensor    # int64 [n + 1]
+
+    def abi(self) -> ADComponents:
+        return ADComponents(self.n_comp, self.n_chunks, self.comp_of.data_ptr(), self.members.data_ptr(),
+                            self.comp_start.data_ptr(), self.chunk_start.data_ptr())
+
+
+def components(dg: DeviceGraph) -> Components:
+    """``ad_components_build``: connected components of the graph, grouped.
+    Synchronises the current stream."""
+    dev = dg.device
+    g = dg.abi()
+    n1 = max(1, dg.n)
+    out = Components(0, 0, torch.empty(n1, dtype=torch.int32, device=dev),
+                     torch.empty(n1, dtype=torch.int32, device=dev),
+                     torch.empty(n1 + 1, dtype=torch.int64, device=dev),
+                     torch.empty(n1 + 1, dtype=torch.int64, device=dev))
+    ws = _workspace(lib.ad_components_workspace_size(ctypes.byref(g)), dev)
+    nc, nch = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib.ad_components_build(ctypes.byref(g), _ptr(out.comp_of), _ptr(out.members), _ptr(out.comp_start),
+                                   _ptr(out.chunk_start), ctypes.byref(nc), ctypes.byref(nch), _ptr(ws), ws.numel(),
+                                   _stream()))
+    out.n_comp, out.n_chunks = nc.value, nch.value
+    return out
 
 
 def validate_graph(dg: DeviceGraph) -> None:
@@ -240,18 +293,39 @@ def validate_graph(dg: DeviceGraph) -> None:
 
 @dataclass
 class RelaxResult:
-    x: torch.Tensor          # [n, R] x^(k) minus the per-vector shift
-    minmax: torch.Tensor     # [2R] float64
-    shift: torch.Tensor      # [R] float64
+    x: torch.Tensor          # [n, R] x^(k) minus the shift of each vertex's component
+    minmax: torch.Tensor     # [2R] float64, of x^(k) itself
+    shift: torch.Tensor      # [n_comp, R] (per component) or [R] float64
     ckpt: Optional[torch.Tensor]
     store: str
+    comp: Optional[Components] = None
+    opts: Optional[ADRelaxOpts] = None
+
+    def x_true(self) -> torch.Tensor:
+        """x^(k) itself in float64: the stored values plus their shifts."""
+        x = self.x.to(torch.float64)
+        if self.comp is None:
+            return x + self.shift.reshape(1, -1)
+        c = self.comp.comp_of[:x.shape[0]].to(torch.int64)
+        sh = self.shift.reshape(-1, x.shape[1])[c.clamp(min=0)]
+        return x + torch.where((c >= 0)[:, None], sh, torch.zeros_like(sh))
+
+    @property
+    def rho_dtype(self) -> torch.dtype:
+        """Distances are FP64 for FP64 storage, else FP32."""
+        return torch.float64 if self.store == "f64" else torch.float32
 
 
 def relax_opts(R: int, k: int, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
                store: str = "f32", fp32_tail: int = 2, ckpt_every: int = 0,
-               rows_per_wave: int = 0, hub_degree: int = 0) -> ADRelaxOpts:
-    return ADRelaxOpts(R, k, omega, seed, graph_id, _DTYPES[store], fp32_tail, ckpt_every,
-                       rows_per_wave, hub_degree)
+               rows_per_wave: int = 0, hub_degree: int = 0, fp64_tail: int = 0,
+               comp: Optional[Components] = None) -> ADRelaxOpts:
+    o = ADRelaxOpts(R, k, omega, seed, graph_id, _DTYPES[store], fp32_tail, ckpt_every,
+                    rows_per_wave, hub_degree, fp64_tail, None)
+    if comp is not None:
+        o._comp_abi = comp.abi()             # kept alive with the options
+        o.comp = ctypes.pointer(o._comp_abi)
+    return o
 
 
 def relax_workspace_bytes(dg: DeviceGraph, opts: ADRelaxOpts) -> int:
@@ -262,23 +336,32 @@ def relax_workspace_bytes(dg: DeviceGraph, opts: ADRelaxOpts) -> int:
 def relax(dg: DeviceGraph, R: int, k: int, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
           store: str = "f32", x0: Optional[torch.Tensor] = None, fp32_tail: int = 2,
           ckpt_every: int = 0, rows_per_wave: int = 0, hub_degree: int = 0,
-          ws: Optional[torch.Tensor] = None, out: Optional[RelaxResult] = None) -> RelaxResult:
-    """Start vectors + k JOR sweeps + rescale statistics (``ad_relax``)."""
+          ws: Optional[torch.Tensor] = None, out: Optional[RelaxResult] = None,
+          fp64_tail: int = 0, per_component: bool = True) -> RelaxResult:
+    """Start vectors + k JOR sweeps + rescale statistics (``ad_relax``).
+    With ``per_component`` each connected component is centred by its own
+    weighted mean (the graph's components are built once and cached); the
+    last ``fp64_tail`` sweeps of FP32 / BF16 storage are stored in FP64, and
+    x is then float64."""
+    comp = dg.components() if per_component else None
     opts = relax_opts(R, k, omega, seed, graph_id, store, fp32_tail, ckpt_every, rows_per_wave,
-                      hub_degree)
+                      hub_degree, fp64_tail, comp)
     g = dg.abi()
     dev = dg.device
-    xdt = torch.float64 if store == "f64" else torch.float32
+    sdt = torch.float64 if store == "f64" else torch.float32
+    xdt = torch.float64 if (store == "f64" or fp64_tail > 0) else torch.float32
+    nsh = max(1, comp.n_comp) if comp is not None else 1
     if out is None:
         nck = int(lib.ad_relax_num_checkpoints(ctypes.byref(opts)))
         out = RelaxResult(
             x=torch.empty((dg.n, R), dtype=xdt, device=dev),
             minmax=torch.empty(2 * R, dtype=torch.float64, device=dev),
-            shift=torch.empty(R, dtype=torch.float64, device=dev),
-            ckpt=torch.empty((nck, dg.n, R), dtype=xdt, device=dev) if nck else None,
+            shift=torch.empty((nsh, R) if comp is not None else (R,), dtype=torch.float64, device=dev),
+            ckpt=torch.empty((nck, dg.n, R), dtype=sdt, device=dev) if nck else None,
             store=store)
+    out.comp, out.opts = comp, opts
     if x0 is not None:
-        if x0.dtype != xdt or tuple(x0.shape) != (dg.n, R) or not x0.is_contiguous():
+        if x0.dtype != sdt or tuple(x0.shape) != (dg.n, R) or not x0.is_contiguous():
             raise ValueError("x0 must be a contiguous [n, R] tensor of the storage dtype")
     if ws is None:
         ws = _workspace(lib.ad_relax_workspace_size(ctypes.byref(g), ctypes.byref(opts)), dev)
@@ -295,18 +378,29 @@ def edge_dist_workspace_bytes(dg: DeviceGraph) -> int:
 
 
 def edge_dist(dg: DeviceGraph, x: torch.Tensor, minmax: torch.Tensor,
-              out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """rho[m] = L2 distance of the rescaled vectors (``ad_edge_dist``)."""
+              out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+              rho_dtype: Optional[torch.dtype] = None) -> torch.Tensor:
+    """rho[m] = L2 distance of the rescaled vectors (``ad_edge_dist``);
+    rho_dtype defaults to out's dtype, else x's."""
     R = x.shape[1]
     dt = AD_F64 if x.dtype == torch.float64 else AD_F32
+    if rho_dtype is None:
+        rho_dtype = out.dtype if out is not None else x.dtype
     if out is None:
-        out = torch.empty(dg.m, dtype=x.dtype, device=x.device)
+        out = torch.empty(dg.m, dtype=rho_dtype, device=x.device)
+    rt = AD_F64 if out.dtype == torch.float64 else AD_F32
     g = dg.abi()
     if ws is None:
         ws = _workspace(lib.ad_edge_dist_workspace_size(ctypes.byref(g)), x.device)
-    _check(lib.ad_edge_dist(ctypes.byref(g), R, dt, _ptr(x), _ptr(minmax), _ptr(out), _ptr(ws), ws.numel(),
+    _check(lib.ad_edge_dist(ctypes.byref(g), R, dt, _ptr(x), _ptr(minmax), rt, _ptr(out), _ptr(ws), ws.numel(),
                             _stream()))
     return out
+
+
+def distances(dg: DeviceGraph, res: RelaxResult, out: Optional[torch.Tensor] = None,
+              ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """``edge_dist`` of a relaxation: FP64 rho for FP64 storage, else FP32."""
+    return edge_dist(dg, res.x, res.minmax, out=out, ws=ws, rho_dtype=res.rho_dtype)
 
 
 def normalize_dist(dg: DeviceGraph, rho: torch.Tensor, by_strength: bool = True, eps: float = 0.0,
@@ -411,15 +505,15 @@ def relax_backward(dg: DeviceGraph, res: RelaxResult, R: int, k: int, grad_rho: 
                    omega: float = 0.5, seed: int = 0, graph_id: int = 0, ckpt_every: int = 5,
                    ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """dL/dw_e given dL/drho_e (``ad_relax_backward``)."""
-    opts = relax_opts(R, k, omega, seed, graph_id, "f32", 2, ckpt_every)
+    opts = relax_opts(R, k, omega, seed, graph_id, "f32", 2, ckpt_every, comp=res.comp)
     g = dg.abi()
     if ws is None:
         ws = _workspace(lib.ad_relax_backward_workspace_size(ctypes.byref(g), ctypes.byref(opts)), dg.device)
     if out is None:
         out = torch.empty(dg.m, dtype=torch.float32, device=dg.device)
     _check(lib.ad_relax_backward(ctypes.byref(g), ctypes.byref(opts), _ptr(res.ckpt), _ptr(res.x),
-                                 _ptr(res.minmax), _ptr(grad_rho), _ptr(out), _ptr(ws), ws.numel(),
-                                 _stream()))
+                                 _ptr(res.minmax), _ptr(res.shift), _ptr(grad_rho), _ptr(out), _ptr(ws),
+                                 ws.numel(), _stream()))
     return out
 
 
@@ -443,7 +537,7 @@ class AlgDist(torch.autograd.Function):
         w_edge = w_edge.detach().contiguous().float()
         dgw = dg.with_weights(edge_to_entries(dg, w_edge))
         res = relax(dgw, R, k, omega, seed, store="f32", ckpt_every=ckpt_every)
-        rho = edge_dist(dgw, res.x, res.minmax)
+        rho = distances(dgw, res)
         ctx.dgw, ctx.res = dgw, res
         ctx.args = (R, k, omega, seed, ckpt_every)
         return rho
@@ -465,12 +559,12 @@ class Batch:
 
     def __init__(self, graphs, R: int, k: int, omega: float = 0.5, seed: int = 0, graph_id: int = 0,
                  orient: int = AD_LOCAL, e: float = 0.5, autotune: bool = True,
-                 rows_per_wave: int = 0, hub_degree: int = 0):
+                 rows_per_wave: int = 0, hub_degree: int = 0, fp64_tail: int = 0):
         self.graphs = list(graphs)        # keep the inputs alive while packing
         self.G = len(self.graphs)
         self.R = R
         arr = (ADGraph * self.G)(*[dg.abi() for dg in self.graphs])
-        opts = relax_opts(R, k, omega, seed, graph_id, "f32", 2, 0, rows_per_wave, hub_degree)
+        opts = relax_opts(R, k, omega, seed, graph_id, "f32", 2, 0, rows_per_wave, hub_degree, fp64_tail)
         bo = ADBatchOpts(orient, float(e), 1 if autotune else 0)
         h = ctypes.c_void_p()
         _check(lib.ad_batch_create(self.G, arr, ctypes.byref(opts), ctypes.byref(bo), ctypes.byref(h), _stream()))
@@ -514,11 +608,12 @@ class Batch:
 
 def sparsify_graph(dg: DeviceGraph, R: int, k: int, orient: int, e: Optional[float] = None,
                    target: Optional[float] = None, omega: float = 0.5, seed: int = 0,
-                   store: str = "f32"):
-    """Algorithm 1 then Algorithm 3 on one graph.  Returns a dict with rho,
-    keep, n_kept and the exponent used."""
-    res = relax(dg, R, k, omega, seed, store=store)
-    rho = edge_dist(dg, res.x, res.minmax)
+                   store: str = "f32", fp64_tail: int = 2):
+    """Algorithm 1 then Algorithm 3 on one graph (components centred apart,
+    the last ``fp64_tail`` sweeps of FP32 storage in FP64).  Returns a dict
+    with rho, keep, n_kept and the exponent used."""
+    res = relax(dg, R, k, omega, seed, store=store, fp64_tail=0 if store == "f64" else fp64_tail)
+    rho = distances(dg, res)
     if target is not None:
         keep, n_kept, e_used = sparsify_fit(dg, rho, orient, target)
     else:
@@ -693,24 +788,28 @@ def ml_level_span(n_levels: int, span: int, segment: int, value: float) -> np.nd
 def ml_sparsify(dg: DeviceGraph, R: int, k: int, e_levels=None, omega: float = 0.5, seed: int = 0,
                 graph_id: int = 0, levels: int = 8, n_min: int = 1000, store: str = "f32", eps: float = 1e-12,
                 theta: float = 0.5, bin_seed: int = 0, fit: bool = False, span: int = 0, segment: int = 0,
-                span_value: float = 0.3, keep: Optional[torch.Tensor] = None):
+                span_value: float = 0.3, keep: Optional[torch.Tensor] = None, fp64_tail: int = 2):
     """Algorithm 6, MLSparsify (``ad_ml_sparsify``).  ``e_levels``: the
-    per-level ratio vector, coarsest level first (a shorter list repeats its
-    last value; a negative entry skips SparsifyB at that level); exponents,
-    or retention targets with ``fit``.  ``span > 0`` uses the level-span
-    vector of the levels reached instead.  Returns (keep uint8 [m], n_kept,
-    depth).  Synchronises the current stream."""
-    if e_levels is None and span <= 0:
-        raise ValueError("ml_sparsify needs e_levels, or span > 0 for the level-span rule")
-    ev = [float(x) for x in np.atleast_1d(np.asarray(e_levels if e_levels is not None else [0.0],
-                                                     dtype=np.float64))]
-    ev = (ev + [ev[-1]] * max(0, levels - len(ev)))[:max(levels, 1)]
+    per-level ratio vector, coarsest level first, one entry per level (a
+    negative entry skips SparsifyB at that level); exponents, or retention
+    targets with ``fit``.  ``span > 0`` uses the level-span vector of the
+    levels reached instead.  FP32 relaxations store their last ``fp64_tail``
+    sweeps in FP64.  Returns (keep uint8 [m], n_kept, depth).  Synchronises
+    the current stream."""
+    if span > 0:
+        ev = [0.0] * max(levels, 1)
+    else:
+        if e_levels is None:
+            raise ValueError("ml_sparsify needs e_levels, or span > 0 for the level-span rule")
+        ev = [float(x) for x in np.atleast_1d(np.asarray(e_levels, dtype=np.float64))]
+        if len(ev) != levels:
+            raise ValueError(f"e_levels has {len(ev)} entries for {levels} levels")
     e_arr = (ctypes.c_double * len(ev))(*ev)
     o = ADMLOpts(R=R, k=k, omega=omega, seed=int(seed) & (2 ** 64 - 1), graph_id=int(graph_id) & (2 ** 64 - 1),
                  store=_DTYPES[store], levels=levels, n_min=n_min,
                  e_host=ctypes.cast(e_arr, ctypes.c_void_p).value, eps=eps, theta=theta,
                  bin_seed=int(bin_seed) & (2 ** 64 - 1), fit=int(fit), span=span, segment=segment,
-                 span_value=span_value)
+                 span_value=span_value, fp64_tail=fp64_tail if store == "f32" else 0)
     g = dg.abi()
     if keep is None:
         keep = torch.empty(max(1, dg.m), dtype=torch.uint8, device=dg.row_ptr.device)

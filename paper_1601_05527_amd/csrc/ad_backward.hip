@@ -2,7 +2,8 @@
 // edge weights, through the distance, the rescale and the k JOR sweeps of
 // Algorithm 1 (FP32).
 //
-// Forward recap (per vector r, shifted values x):
+// Forward recap (per vector r; x^(t) below is the relaxation's own value,
+// the stored one plus its component's shift, which no sweep changes):
 //   x^(t)_i = (1-omega) x^(t-1)_i + omega y^(t)_i,  y^(t)_i = sum_j w_ij x^(t-1)_j / s_i,
 //   xhat_i  = (x^(k)_i - m) / (M - m) - 1/2   (m, M: min and max over live rows),
 //   rho_e   = sqrt(sum_r (xhat_i - xhat_j)^2).
@@ -109,9 +110,11 @@ __global__ __launch_bounds__(BB) void k_adj_dist(int64_t n, const int64_t *__res
     }
 }
 
-// First live row attaining the min and the max of each vector.
+// First live row attaining the min and the max of each vector (values with
+// their shift added back exactly as ad_relax's min / max pass adds it).
 __global__ void k_adj_argminmax(int64_t n, int R, const int64_t *__restrict__ row_ptr,
-                                const float *__restrict__ x, const double *__restrict__ minmax,
+                                const float *__restrict__ x, const double *__restrict__ shift,
+                                const int32_t *__restrict__ comp_of, const double *__restrict__ minmax,
                                 unsigned long long *__restrict__ arg) {
     const int64_t total = n * R;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -119,7 +122,9 @@ __global__ void k_adj_argminmax(int64_t n, int R, const int64_t *__restrict__ ro
         const int64_t i = idx / R;
         const int r = (int)(idx - i * R);
         if (row_ptr[i + 1] == row_ptr[i]) continue;
-        const double v = (double)x[idx];
+        bool zero;
+        const double *sh = row_shift(shift, comp_of, i, 0, R, zero);
+        const double v = (double)x[idx] + (zero ? 0.0 : sh[r]);
         if (v == minmax[r]) atomicMin(&arg[r], (unsigned long long)i);
         if (v == minmax[R + r]) atomicMin(&arg[R + r], (unsigned long long)i);
     }
@@ -127,7 +132,9 @@ __global__ void k_adj_argminmax(int64_t n, int R, const int64_t *__restrict__ ro
 
 // lambda = xhatbar / (M - m) on live rows; partial sums for the min/max terms.
 __global__ __launch_bounds__(BB) void k_adj_rescale(int64_t n, int R, const int64_t *__restrict__ row_ptr,
-                                                   const float *__restrict__ x, const double *__restrict__ minmax,
+                                                   const float *__restrict__ x, const double *__restrict__ shift,
+                                                   const int32_t *__restrict__ comp_of,
+                                                   const double *__restrict__ minmax,
                                                    const float *__restrict__ xbh, float *__restrict__ lam,
                                                    double *__restrict__ part) {
     __shared__ double a_l[BB];
@@ -147,7 +154,9 @@ __global__ __launch_bounds__(BB) void k_adj_rescale(int64_t n, int R, const int6
             const bool live = row_ptr[i + 1] > row_ptr[i];
             const double xb = live ? (double)xbh[i * R + r] : 0.0;
             lam[i * R + r] = (float)(xb * inv);
-            const double xv = (double)x[i * R + r];
+            bool zero;
+            const double *sh = row_shift(shift, comp_of, i, 0, R, zero);
+            const double xv = (double)x[i * R + r] + (zero ? 0.0 : sh[r]);
             a += xb * (xv - hi) * inv * inv;
             b -= xb * (xv - lo) * inv * inv;
         }
@@ -328,8 +337,9 @@ extern "C" size_t ad_relax_backward_workspace_size(const ad_graph *g, const ad_r
 }
 
 extern "C" ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o, const void *ckpt,
-                                       const void *x_k, const double *minmax, const float *grad_rho,
-                                       float *grad_w, void *ws, size_t ws_bytes, hipStream_t stream) {
+                                       const void *x_k, const double *minmax, const double *shift,
+                                       const float *grad_rho, float *grad_w, void *ws, size_t ws_bytes,
+                                       hipStream_t stream) {
     ad_status s = check_graph_args(g);
     if (s != AD_OK) return s;
     if (!o) return fail(AD_ERR_INVALID_ARG, "opts is NULL");
@@ -337,9 +347,13 @@ extern "C" ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o
     if (o->k < 0) return fail(AD_ERR_INVALID_ARG, "k must be >= 0");
     if (!(o->omega > 0.0 && o->omega <= 1.0)) return fail(AD_ERR_INVALID_ARG, "omega must be in (0, 1]");
     if (o->store != AD_F32) return fail(AD_ERR_UNSUPPORTED, "the adjoint needs FP32 storage");
+    if (o->fp64_tail != 0) return fail(AD_ERR_UNSUPPORTED, "the adjoint needs fp64_tail == 0");
     if (o->ckpt_every < 1) return fail(AD_ERR_INVALID_ARG, "the adjoint needs ckpt_every >= 1");
-    if (g->m > 0 && (!x_k || !minmax || !grad_rho || !grad_w))
-        return fail(AD_ERR_INVALID_ARG, "x_k, minmax, grad_rho or grad_w is NULL");
+    if (g->m > 0 && (!x_k || !minmax || !shift || !grad_rho || !grad_w))
+        return fail(AD_ERR_INVALID_ARG, "x_k, minmax, shift, grad_rho or grad_w is NULL");
+    if (o->comp && o->comp->n_comp > 0 && !o->comp->comp_of)
+        return fail(AD_ERR_INVALID_ARG, "component arrays are NULL");
+    const int32_t *comp_of = o->comp ? o->comp->comp_of : nullptr;
     if (o->k > 0 && g->m > 0 && !ckpt) return fail(AD_ERR_INVALID_ARG, "ckpt is NULL");
     if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
@@ -379,11 +393,11 @@ extern "C" ad_status ad_relax_backward(const ad_graph *g, const ad_relax_opts *o
     s = fill_u64(L.arg, ~0ull, 2 * R, stream);
     if (s != AD_OK) return s;
     hipLaunchKernelGGL(k_adj_argminmax, dim3(grid_for((int64_t)nR, BB)), dim3(BB), 0, stream, n, R, g->row_ptr,
-                       xk, minmax, L.arg);
+                       xk, shift, comp_of, minmax, L.arg);
     AD_LAUNCH_CHECK("k_adj_argminmax");
     const int64_t nb = std::max<int64_t>(1, ceil_div(n, PART_ROWS));
-    hipLaunchKernelGGL(k_adj_rescale, dim3((unsigned)nb), dim3(BB), 0, stream, n, R, g->row_ptr, xk, minmax,
-                       L.xbh, L.lam, L.part);
+    hipLaunchKernelGGL(k_adj_rescale, dim3((unsigned)nb), dim3(BB), 0, stream, n, R, g->row_ptr, xk, shift,
+                       comp_of, minmax, L.xbh, L.lam, L.part);
     AD_LAUNCH_CHECK("k_adj_rescale");
     hipLaunchKernelGGL(k_adj_corner, dim3(1), dim3(64), 0, stream, R, nb, L.part, L.arg, minmax, L.lam);
     AD_LAUNCH_CHECK("k_adj_corner");

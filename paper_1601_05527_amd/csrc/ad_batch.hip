@@ -91,8 +91,13 @@ struct ad_batch {
             *d_tile_off = nullptr;
     int32_t *col = nullptr, *eid = nullptr, *orig = nullptr, *col_orig = nullptr, *row_graph = nullptr;
     float *w = nullptr;
-    float *x = nullptr, *rho = nullptr;
+    void *x = nullptr;                   // FP32, or FP64 with an FP64 tail
+    float *rho = nullptr;
     double *minmax = nullptr, *shift = nullptr;
+    // connected components of the packed graph (per-component centring)
+    ad_components comps{};
+    int32_t *comp_of = nullptr, *members = nullptr;
+    int64_t *comp_start = nullptr, *chunk_start = nullptr;
     uint8_t *keep = nullptr;
     int64_t *n_kept = nullptr;
     unsigned long long *counts = nullptr;
@@ -152,7 +157,8 @@ static ad_status batch_enqueue(ad_batch *b, hipStream_t st) {
     ad_status s = relax_segs(&g, &b->o, nullptr, b->x, b->minmax, b->shift, nullptr, b->ws_relax, b->ws_relax_bytes,
                              sg, st);
     if (s != AD_OK) return s;
-    s = edge_dist_segs(&g, b->o.R, AD_F32, b->x, b->minmax, b->rho, b->ws_dist, b->ws_dist_bytes, sg, st);
+    s = edge_dist_segs(&g, b->o.R, b->o.fp64_tail > 0 ? AD_F64 : AD_F32, b->x, b->minmax, AD_F32, b->rho,
+                       b->ws_dist, b->ws_dist_bytes, sg, st);
     if (s != AD_OK) return s;
     s = sparsify_fixed(&g, AD_F32, b->rho, b->orient, b->budget, b->keep, b->ws_sel, b->ws_sel_bytes, st);
     if (s != AD_OK) return s;
@@ -189,6 +195,7 @@ extern "C" ad_status ad_batch_create(int32_t G, const ad_graph *graphs, const ad
         return fail(AD_ERR_INVALID_ARG, "bad relaxation options");
     if (o->store != AD_F32) return fail(AD_ERR_UNSUPPORTED, "batches use FP32 storage");
     if (o->ckpt_every != 0) return fail(AD_ERR_UNSUPPORTED, "batches keep no checkpoints");
+    if (o->fp64_tail < 0) return fail(AD_ERR_INVALID_ARG, "fp64_tail must be >= 0");
     if (bo->orient != AD_LOCAL && bo->orient != AD_GLOBAL) return fail(AD_ERR_INVALID_ARG, "unknown orientation");
     if (!(bo->e >= 0.0 && bo->e <= 1.0)) return fail(AD_ERR_INVALID_ARG, "e must be in [0, 1]");
     for (int32_t q = 0; q < G; ++q) {
@@ -198,6 +205,7 @@ extern "C" ad_status ad_batch_create(int32_t G, const ad_graph *graphs, const ad
     ad_batch *b = new ad_batch();
     b->G = G;
     b->o = *o;
+    b->o.comp = nullptr;          // set below to the packed graph's components
     b->orient = bo->orient;
     b->e = bo->e;
     b->row_off.assign(G + 1, 0);
@@ -240,10 +248,13 @@ extern "C" ad_status ad_batch_create(int32_t G, const ad_graph *graphs, const ad
     AD_TRY(b->alloc(&b->d_edge_off, G + 1));
     AD_TRY(b->alloc(&b->d_chunk_off, G + 1));
     AD_TRY(b->alloc(&b->d_tile_off, G + 1));
-    AD_TRY(b->alloc(&b->x, N * R));
+    AD_TRY(b->alloc((char **)&b->x, N * R * (o->fp64_tail > 0 ? 8 : 4)));
     AD_TRY(b->alloc(&b->rho, M));
     AD_TRY(b->alloc(&b->minmax, (size_t)G * 2 * R));
-    AD_TRY(b->alloc(&b->shift, (size_t)G * R));
+    AD_TRY(b->alloc(&b->comp_of, N));
+    AD_TRY(b->alloc(&b->members, N));
+    AD_TRY(b->alloc(&b->comp_start, N + 1));
+    AD_TRY(b->alloc(&b->chunk_start, N + 1));
     AD_TRY(b->alloc(&b->keep, M));
     AD_TRY(b->alloc(&b->n_kept, G));
     AD_TRY(b->alloc(&b->counts, G));
@@ -302,6 +313,34 @@ extern "C" ad_status ad_batch_create(int32_t G, const ad_graph *graphs, const ad
     if (err != hipSuccess) {
         delete b;
         return hip_fail(err, "batch set-up copies");
+    }
+
+    // connected components of the packed graph: the components of its graphs,
+    // grouped in the same relative order as each graph's own
+    {
+        const ad_graph pg = b->packed();
+        const size_t cb = ad_components_workspace_size(&pg);
+        if (cb == 0) {
+            delete b;
+            return fail(AD_ERR_INTERNAL, "component workspace size");
+        }
+        void *cws = nullptr;
+        err = hipMalloc(&cws, cb);
+        if (err != hipSuccess) {
+            delete b;
+            return hip_fail(err, "hipMalloc");
+        }
+        int64_t nc = 0, nch = 0;
+        s = ad_components_build(&pg, b->comp_of, b->members, b->comp_start, b->chunk_start, &nc, &nch, cws, cb,
+                                stream);
+        (void)hipFree(cws);
+        if (s != AD_OK) {
+            delete b;
+            return s;
+        }
+        b->comps = ad_components{nc, nch, b->comp_of, b->members, b->comp_start, b->chunk_start};
+        b->o.comp = &b->comps;
+        AD_TRY(b->alloc(&b->shift, (size_t)std::max<int64_t>(1, nc) * R));
     }
 
     // workspaces do not depend on the launch shape

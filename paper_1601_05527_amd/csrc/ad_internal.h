@@ -236,7 +236,22 @@ struct Segs {
 };
 
 constexpr int CENTRE_ROWS = 1024;   // rows per centring / min-max chunk
+constexpr int64_t COMP_CHUNK = 1024; // component members per centring chunk (ad_components)
 constexpr int PLAN_TILE = 64;       // rows per launch-plan tile
+
+// Shift of row i: per component (comp_of given; isolated rows 0), else the
+// graph's.
+__device__ __forceinline__ const double *row_shift(const double *__restrict__ shift,
+                                                   const int32_t *__restrict__ comp_of, int64_t i, int g, int R,
+                                                   bool &zero) {
+    if (comp_of) {
+        const int32_t c = comp_of[i];
+        zero = c < 0;
+        return shift + (int64_t)(c < 0 ? 0 : c) * R;
+    }
+    zero = false;
+    return shift + (int64_t)g * R;
+}
 
 // Largest g in [0, G) with off[g] <= x (empty segments are skipped over).
 __device__ __forceinline__ int seg_find(const int64_t *__restrict__ off, int G, int64_t x) {
@@ -356,7 +371,8 @@ ad_status relax_segs(const ad_graph *g, const ad_relax_opts *o, const void *x0, 
 // ad_edge_dist over packed graph segments (minmax [G][2R]).
 size_t edge_dist_segs_workspace(const ad_graph *g, const Segs &sg);
 ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x, const double *minmax,
-                         void *rho, void *ws, size_t ws_bytes, const Segs &sg, hipStream_t stream);
+                         ad_dtype rho_dtype, void *rho, void *ws, size_t ws_bytes, const Segs &sg,
+                         hipStream_t stream);
 
 // Algorithm 3 at fixed per-degree budgets, keep[] only (rows are independent,
 // so packed graphs need no segment information).

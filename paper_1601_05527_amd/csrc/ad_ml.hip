@@ -605,8 +605,25 @@ struct MlArenaScope {
         if (s_ != AD_OK) return s_;        \
     } while (0)
 
-// Distances of g at level l (relax with graph id graph_id + l, then ad_edge_dist).
+// Distances of g at level l (relax with graph id graph_id + l, each
+// connected component centred by its own mean, then ad_edge_dist).
 static ad_status ml_distances(const ad_graph *g, const ad_ml_opts *o, int l, DevMem &rho, hipStream_t st) {
+    const int64_t n1 = std::max<int64_t>(1, g->n);
+    DevMem comp_of, members, comp_start, chunk_start, cws;
+    ML_TRY(dev_alloc(comp_of, (size_t)n1 * sizeof(int32_t)));
+    ML_TRY(dev_alloc(members, (size_t)n1 * sizeof(int32_t)));
+    ML_TRY(dev_alloc(comp_start, (size_t)(n1 + 1) * sizeof(int64_t)));
+    ML_TRY(dev_alloc(chunk_start, (size_t)(n1 + 1) * sizeof(int64_t)));
+    const size_t cb = ad_components_workspace_size(g);
+    if (cb == 0) return fail(AD_ERR_INTERNAL, "component workspace size");
+    ML_TRY(dev_alloc(cws, cb));
+    ad_components comps{};
+    ML_TRY(ad_components_build(g, comp_of.get<int32_t>(), members.get<int32_t>(), comp_start.get<int64_t>(),
+                               chunk_start.get<int64_t>(), &comps.n_comp, &comps.n_chunks, cws.p, cb, st));
+    comps.comp_of = comp_of.get<const int32_t>();
+    comps.members = members.get<const int32_t>();
+    comps.comp_start = comp_start.get<const int64_t>();
+    comps.chunk_start = chunk_start.get<const int64_t>();
     ad_relax_opts ro{};
     ro.R = o->R;
     ro.k = o->k;
@@ -615,19 +632,23 @@ static ad_status ml_distances(const ad_graph *g, const ad_ml_opts *o, int l, Dev
     ro.graph_id = o->graph_id + (uint64_t)l;
     ro.store = o->store;
     ro.fp32_tail = 1;
-    const size_t xb = o->store == AD_F64 ? 8 : 4;
+    ro.fp64_tail = o->store == AD_F32 ? o->fp64_tail : 0;
+    ro.comp = &comps;
+    const ad_dtype xt = (o->store == AD_F64 || ro.fp64_tail > 0) ? AD_F64 : AD_F32;
+    const size_t xb = xt == AD_F64 ? 8 : 4;
+    const size_t rb = o->store == AD_F64 ? 8 : 4;
     DevMem x, mm, ws, wsd;
-    ML_TRY(dev_alloc(x, (size_t)std::max<int64_t>(1, g->n) * o->R * xb));
+    ML_TRY(dev_alloc(x, (size_t)n1 * o->R * xb));
     ML_TRY(dev_alloc(mm, 2 * (size_t)o->R * sizeof(double)));
     const size_t wb = ad_relax_workspace_size(g, &ro);
     if (wb == 0) return fail(AD_ERR_INTERNAL, "relax workspace size");
     ML_TRY(dev_alloc(ws, wb));
     ML_TRY(ad_relax(g, &ro, nullptr, x.p, mm.get<double>(), nullptr, nullptr, ws.p, wb, st));
-    ML_TRY(dev_alloc(rho, (size_t)std::max<int64_t>(1, g->m) * xb));
+    ML_TRY(dev_alloc(rho, (size_t)std::max<int64_t>(1, g->m) * rb));
     const size_t db = ad_edge_dist_workspace_size(g);
     if (db == 0) return fail(AD_ERR_INTERNAL, "distance workspace size");
     ML_TRY(dev_alloc(wsd, db));
-    ML_TRY(ad_edge_dist(g, o->R, o->store, x.p, mm.get<double>(), rho.p, wsd.p, db, st));
+    ML_TRY(ad_edge_dist(g, o->R, xt, x.p, mm.get<double>(), o->store, rho.p, wsd.p, db, st));
     return AD_OK;
 }
 
@@ -834,6 +855,7 @@ extern "C" ad_status ad_ml_sparsify(const ad_graph *g, const ad_ml_opts *o, uint
     if (o->levels < 1 || o->levels > 64) return fail(AD_ERR_INVALID_ARG, "levels must be in [1, 64]");
     if (o->n_min < 0) return fail(AD_ERR_INVALID_ARG, "n_min must be >= 0");
     if (o->fit != 0 && o->fit != 1) return fail(AD_ERR_INVALID_ARG, "fit must be 0 or 1");
+    if (o->fp64_tail < 0) return fail(AD_ERR_INVALID_ARG, "fp64_tail must be >= 0");
     if (o->span > 0) {
         if (o->segment < 0 || o->segment > 2) return fail(AD_ERR_INVALID_ARG, "segment must be 0, 1 or 2");
         if (!(o->span_value <= 1.0)) return fail(AD_ERR_INVALID_ARG, "span_value must be <= 1");

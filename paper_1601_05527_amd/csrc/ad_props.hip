@@ -389,6 +389,50 @@ __global__ void k_count_roots(int64_t n, const int32_t *__restrict__ parent, uns
     if ((threadIdx.x & (WAVE - 1)) == 0 && k) atomicAdd(cnt, k);
 }
 
+// Grouping of the components for the relaxation's per-component centring:
+// sort keys (the component's smallest vertex; isolated vertices last).
+__global__ void k_comp_keys(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ parent,
+                            uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        key[i] = row_ptr[i + 1] > row_ptr[i] ? (uint32_t)parent[i] : 0xffffffffu;
+        val[i] = (uint32_t)i;
+    }
+}
+
+// head[p] = 1 where sorted position p starts a component.
+__global__ void k_comp_heads(int64_t n, const uint32_t *__restrict__ key, uint32_t *__restrict__ head) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+        head[p] = (key[p] != 0xffffffffu && (p == 0 || key[p] != key[p - 1])) ? 1u : 0u;
+}
+
+// comp_of, members and the component starts from the sorted order and the
+// exclusive scan of the heads; the last live position closes the last
+// component.
+__global__ void k_comp_fill(int64_t n, const uint32_t *__restrict__ key, const uint32_t *__restrict__ val,
+                            const uint32_t *__restrict__ head, const uint32_t *__restrict__ before,
+                            int32_t *__restrict__ comp_of, int32_t *__restrict__ members,
+                            int64_t *__restrict__ comp_start) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = (int32_t)val[p];
+        if (key[p] == 0xffffffffu) {
+            comp_of[v] = -1;
+            continue;
+        }
+        const int64_t c = (int64_t)before[p] + head[p] - 1;
+        comp_of[v] = (int32_t)c;
+        members[p] = v;
+        if (head[p]) comp_start[c] = p;
+        if (p + 1 == n || key[p + 1] == 0xffffffffu) comp_start[c + 1] = p + 1;
+    }
+}
+
+// Chunks of COMP_CHUNK members per component (the entry after the last is 0,
+// so an exclusive scan ends with the total).
+__global__ void k_comp_chunks(int64_t nc, const int64_t *__restrict__ comp_start, int64_t *__restrict__ cnt) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nc; c += (int64_t)gridDim.x * blockDim.x)
+        cnt[c] = c < nc ? (comp_start[c + 1] - comp_start[c] + COMP_CHUNK - 1) / COMP_CHUNK : 0;
+}
+
 // ------------------------------------------------------------- spearman --
 
 __global__ void k_iota(int64_t n, uint32_t *__restrict__ idx) {
@@ -489,6 +533,81 @@ static size_t prop_layout(const ad_graph *g, void *ws, size_t ws_bytes, PropLayo
     l.part_sum = c.take<double>(PREDUCE_BLOCKS);
     l.part_cnt = c.take<unsigned long long>(PREDUCE_BLOCKS);
     l.parent = c.take<int32_t>(n);
+    if (L) *L = l;
+    return c.ok() ? c.used : 0;
+}
+
+// Hook and jump until no hook changes a parent; every vertex then holds the
+// smallest vertex of its component.  flags: [3] scratch words.
+static ad_status label_components(const ad_graph *g, int32_t *parent, unsigned int *flags, hipStream_t stream) {
+    const int64_t n = g->n;
+    const unsigned wgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, PBLOCK / WAVE)));
+    hipLaunchKernelGGL(k_parent_init, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent);
+    AD_LAUNCH_CHECK("k_parent_init");
+    // every round joins, for each edge between two trees, its two trees; the
+    // bound only guards against a defect, it is far above the rounds needed
+    for (int round = 0;; ++round) {
+        if (round > 4096) return fail(AD_ERR_INTERNAL, "components did not settle");
+        ad_status s = fill_i32((int32_t *)flags + 1, 0, 1, stream);
+        if (s != AD_OK) return s;
+        if (g->m > 0) {
+            hipLaunchKernelGGL(k_hook, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, parent, flags + 1);
+            AD_LAUNCH_CHECK("k_hook");
+        }
+        // jump until every vertex points at a root
+        for (int step = 0;; ++step) {
+            if (step > 64) return fail(AD_ERR_INTERNAL, "pointer jumping did not settle");
+            s = fill_i32((int32_t *)flags + 2, 0, 1, stream);
+            if (s != AD_OK) return s;
+            hipLaunchKernelGGL(k_jump, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent, flags + 2);
+            AD_LAUNCH_CHECK("k_jump");
+            unsigned int moved = 0;
+            AD_HIP(hipMemcpyAsync(&moved, flags + 2, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
+            AD_HIP(hipStreamSynchronize(stream));
+            if (!moved) break;
+        }
+        unsigned int changed = 0;
+        AD_HIP(hipMemcpyAsync(&changed, flags + 1, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
+        AD_HIP(hipStreamSynchronize(stream));
+        if (!changed) break;
+    }
+    return AD_OK;
+}
+
+struct CompLayout {
+    int32_t *parent;              // [n]
+    unsigned int *flags;          // [4]
+    uint32_t *key0, *key1, *val0, *val1, *head, *before;   // [n]
+    int64_t *cnt;                 // [n + 1]
+    void *temp;
+    size_t temp_bytes;
+};
+
+static size_t comp_layout(int64_t n, void *ws, size_t ws_bytes, CompLayout *L) {
+    Carver c(ws, ws_bytes);
+    const size_t nn = (size_t)std::max<int64_t>(1, n);
+    CompLayout l;
+    l.parent = c.take<int32_t>(nn);
+    l.flags = c.take<unsigned int>(4);
+    l.key0 = c.take<uint32_t>(nn);
+    l.key1 = c.take<uint32_t>(nn);
+    l.val0 = c.take<uint32_t>(nn);
+    l.val1 = c.take<uint32_t>(nn);
+    l.head = c.take<uint32_t>(nn);
+    l.before = c.take<uint32_t>(nn);
+    l.cnt = c.take<int64_t>(nn + 1);
+    size_t t0 = 0, t1 = 0, t2 = 0;
+    if (rocprim::radix_sort_pairs(nullptr, t0, (uint32_t *)nullptr, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                  (uint32_t *)nullptr, nn) != hipSuccess)
+        t0 = 0;
+    if (rocprim::exclusive_scan(nullptr, t1, (uint32_t *)nullptr, (uint32_t *)nullptr, 0u, nn,
+                                rocprim::plus<uint32_t>()) != hipSuccess)
+        t1 = 0;
+    if (rocprim::exclusive_scan(nullptr, t2, (int64_t *)nullptr, (int64_t *)nullptr, (int64_t)0, nn + 1,
+                                rocprim::plus<int64_t>()) != hipSuccess)
+        t2 = 0;
+    l.temp_bytes = std::max(t0, std::max(t1, t2));
+    l.temp = c.take<char>(l.temp_bytes);
     if (L) *L = l;
     return c.ok() ? c.used : 0;
 }
@@ -634,35 +753,8 @@ extern "C" ad_status ad_graph_properties(const ad_graph *g, int64_t *lambda, dou
     AD_LAUNCH_CHECK("k_clustering");
     // components: hook and jump until no hook changes a parent
     int32_t *parent = comp ? comp : L.parent;
-    hipLaunchKernelGGL(k_parent_init, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent);
-    AD_LAUNCH_CHECK("k_parent_init");
-    // every round joins, for each edge between two trees, its two trees; the
-    // bound only guards against a defect, it is far above the rounds needed
-    for (int round = 0;; ++round) {
-        if (round > 4096) return fail(AD_ERR_INTERNAL, "components did not settle");
-        s = fill_i32((int32_t *)L.flags + 1, 0, 1, stream);
-        if (s != AD_OK) return s;
-        if (g->m > 0) {
-            hipLaunchKernelGGL(k_hook, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, parent, L.flags + 1);
-            AD_LAUNCH_CHECK("k_hook");
-        }
-        // jump until every vertex points at a root
-        for (int step = 0;; ++step) {
-            if (step > 64) return fail(AD_ERR_INTERNAL, "pointer jumping did not settle");
-            s = fill_i32((int32_t *)L.flags + 2, 0, 1, stream);
-            if (s != AD_OK) return s;
-            hipLaunchKernelGGL(k_jump, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent, L.flags + 2);
-            AD_LAUNCH_CHECK("k_jump");
-            unsigned int moved = 0;
-            AD_HIP(hipMemcpyAsync(&moved, L.flags + 2, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
-            AD_HIP(hipStreamSynchronize(stream));
-            if (!moved) break;
-        }
-        unsigned int changed = 0;
-        AD_HIP(hipMemcpyAsync(&changed, L.flags + 1, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
-        AD_HIP(hipStreamSynchronize(stream));
-        if (!changed) break;
-    }
+    s = label_components(g, parent, L.flags, stream);
+    if (s != AD_OK) return s;
     s = fill_u64(L.roots, 0, 1, stream);
     if (s != AD_OK) return s;
     hipLaunchKernelGGL(k_count_roots, dim3(std::min<unsigned>(1024, pgrid(n))), dim3(PBLOCK), 0, stream, n, parent,
@@ -682,6 +774,77 @@ extern "C" ad_status ad_graph_properties(const ad_graph *g, int64_t *lambda, dou
     }
     summary_host[0] = cnt ? sum / (double)cnt : 0.0;
     summary_host[1] = (double)roots;
+    return AD_OK;
+}
+
+extern "C" size_t ad_components_workspace_size(const ad_graph *g) {
+    if (check_graph_args(g) != AD_OK || g->n >= ((int64_t)1 << 31)) return 0;
+    return comp_layout(g->n, nullptr, 0, nullptr);
+}
+
+extern "C" ad_status ad_components_build(const ad_graph *g, int32_t *comp_of, int32_t *members, int64_t *comp_start,
+                                         int64_t *chunk_start, int64_t *n_comp_host, int64_t *n_chunks_host,
+                                         void *ws, size_t ws_bytes, hipStream_t stream) {
+    ad_status s = check_graph_args(g);
+    if (s != AD_OK) return s;
+    if (!n_comp_host || !n_chunks_host) return fail(AD_ERR_INVALID_ARG, "n_comp_host or n_chunks_host is NULL");
+    if (!comp_start || !chunk_start) return fail(AD_ERR_INVALID_ARG, "comp_start or chunk_start is NULL");
+    if (g->n > 0 && (!comp_of || !members)) return fail(AD_ERR_INVALID_ARG, "comp_of or members is NULL");
+    if (g->n >= ((int64_t)1 << 31)) return fail(AD_ERR_UNSUPPORTED, "n must be below 2^31");
+    s = check_ws(ws, comp_layout(g->n, nullptr, 0, nullptr), ws_bytes);
+    if (s != AD_OK) return s;
+    CompLayout L;
+    if (comp_layout(g->n, ws, ws_bytes, &L) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    TraceScope trace("k_components", stream);
+    const int64_t n = g->n;
+    *n_comp_host = 0;
+    *n_chunks_host = 0;
+    int64_t zero[2] = {0, 0};
+    if (n == 0) {
+        AD_HIP(hipMemcpyAsync(comp_start, zero, sizeof(int64_t), hipMemcpyHostToDevice, stream));
+        AD_HIP(hipMemcpyAsync(chunk_start, zero, sizeof(int64_t), hipMemcpyHostToDevice, stream));
+        AD_HIP(hipStreamSynchronize(stream));
+        return AD_OK;
+    }
+    s = fill_i32((int32_t *)L.flags, 0, 4, stream);
+    if (s != AD_OK) return s;
+    s = label_components(g, L.parent, L.flags, stream);
+    if (s != AD_OK) return s;
+    hipLaunchKernelGGL(k_comp_keys, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, g->row_ptr, L.parent, L.key0, L.val0);
+    AD_LAUNCH_CHECK("k_comp_keys");
+    size_t tb = L.temp_bytes;
+    AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.key0, L.key1, L.val0, L.val1, (size_t)n, 0, 32, stream));
+    hipLaunchKernelGGL(k_comp_heads, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, L.key1, L.head);
+    AD_LAUNCH_CHECK("k_comp_heads");
+    tb = L.temp_bytes;
+    AD_RP(rocprim::exclusive_scan(L.temp, tb, L.head, L.before, 0u, (size_t)n, rocprim::plus<uint32_t>(), stream));
+    uint32_t last[2] = {0, 0};
+    AD_HIP(hipMemcpyAsync(&last[0], L.before + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    AD_HIP(hipMemcpyAsync(&last[1], L.head + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    AD_HIP(hipStreamSynchronize(stream));
+    const int64_t nc = (int64_t)last[0] + (int64_t)last[1];
+    if (nc == 0) {
+        hipLaunchKernelGGL(k_comp_fill, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, L.key1, L.val1, L.head, L.before,
+                           comp_of, members, comp_start);
+        AD_LAUNCH_CHECK("k_comp_fill");
+        AD_HIP(hipMemcpyAsync(comp_start, zero, sizeof(int64_t), hipMemcpyHostToDevice, stream));
+        AD_HIP(hipMemcpyAsync(chunk_start, zero, sizeof(int64_t), hipMemcpyHostToDevice, stream));
+        AD_HIP(hipStreamSynchronize(stream));
+        return AD_OK;
+    }
+    hipLaunchKernelGGL(k_comp_fill, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, L.key1, L.val1, L.head, L.before,
+                       comp_of, members, comp_start);
+    AD_LAUNCH_CHECK("k_comp_fill");
+    hipLaunchKernelGGL(k_comp_chunks, dim3(pgrid(nc + 1)), dim3(PBLOCK), 0, stream, nc, comp_start, L.cnt);
+    AD_LAUNCH_CHECK("k_comp_chunks");
+    tb = L.temp_bytes;
+    AD_RP(rocprim::exclusive_scan(L.temp, tb, L.cnt, chunk_start, (int64_t)0, (size_t)(nc + 1),
+                                  rocprim::plus<int64_t>(), stream));
+    int64_t nch = 0;
+    AD_HIP(hipMemcpyAsync(&nch, chunk_start + nc, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    AD_HIP(hipStreamSynchronize(stream));
+    *n_comp_host = nc;
+    *n_chunks_host = nch;
     return AD_OK;
 }
 

@@ -11,13 +11,19 @@
 // of them a 256-thread workgroup.  Arithmetic order is fixed, so results are
 // bitwise repeatable.
 //
-// Numerics: the start block is shifted per vector by the weighted mean
-// sum_i s_i x_i / sum_i s_i rounded to the 2^-24 grid.  The sweep matrix
-// preserves constant vectors, so this changes x^(k) by exactly that constant
-// (the start values lie on the same grid, so the subtraction itself is exact)
-// and leaves the rescaled vectors unchanged, while the sweeps then work on
-// values centred near zero, whose rounding errors are proportional to the
-// spread of the vector rather than to its mean.
+// Numerics: the start block is shifted per vector -- and, given the graph's
+// connected components, per component -- by the weighted mean
+// sum_i s_i x_i / sum_i s_i over the component, rounded to the 2^-24 grid.
+// The sweep matrix keeps every vector that is constant on each component
+// fixed, so this changes x^(k) by exactly those constants (the start values
+// lie on the same grid, so the subtraction itself is exact) and leaves the
+// rescaled vectors unchanged, while the sweeps work on differences from each
+// component's conserved mean.  Their rounding errors then scale with how far
+// a component still is from its limit: a small component that has nearly
+// converged keeps its own tiny differences, which a single graph-wide shift
+// would drown in the rounding of its distance from the graph-wide mean.
+// Storage rounding of the last sweeps is the other limit of FP32 vectors;
+// the last fp64_tail sweeps are therefore stored and computed in FP64.
 #include "ad_internal.h"
 
 #include <math.h>
@@ -31,11 +37,25 @@ constexpr int BLOCK = 256;
 constexpr int SWEEP_UNROLL = 8;     // row gathers in flight per lane
 
 // s_i = sum_j w_ij in FP64 (LPR lanes per row, strided partial sums combined
-// by a fixed shuffle tree); inv_s = 1/s_i (0 for isolated vertices).
+// by a fixed shuffle tree).  FP32 sweeps multiply by inv_s = 1/s_i (0 for
+// isolated vertices); FP64 sweeps divide by s_i, which they read from inv_s
+// (A == double) or from s64.
+template <typename A>
+__device__ __forceinline__ A sweep_scale(double s) {
+    if constexpr (sizeof(A) == 8) return (A)s;
+    else return s > 0.0 ? (A)(1.0 / s) : (A)0;
+}
+template <typename A>
+__device__ __forceinline__ A neighbour_avg(A acc, A is) {
+    if constexpr (sizeof(A) == 8) return acc / is;    // correctly rounded quotient
+    else return acc * is;
+}
+
 template <typename A>
 __global__ __launch_bounds__(BLOCK) void k_weighted_degree(int64_t n, const int64_t *__restrict__ row_ptr,
                                                           const float *__restrict__ w, A *__restrict__ inv_s,
-                                                          float *__restrict__ sdeg, int LPR, int64_t hub_d) {
+                                                          float *__restrict__ sdeg, double *__restrict__ s64,
+                                                          int LPR, int64_t hub_d) {
     const int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     int64_t b = 0, e = 0;
@@ -52,8 +72,9 @@ __global__ __launch_bounds__(BLOCK) void k_weighted_degree(int64_t n, const int6
     }
     for (int d = LPR >> 1; d >= 1; d >>= 1) s += shfl_down(s, d);
     if (i < n && lane == 0) {
-        inv_s[i] = (e > b) ? (A)(1.0 / s) : (A)0;
+        inv_s[i] = sweep_scale<A>(e > b ? s : 0.0);
         sdeg[i] = (float)s;
+        if (s64) s64[i] = s;
     }
 }
 
@@ -64,7 +85,7 @@ __global__ __launch_bounds__(BLOCK) void k_weighted_degree_hub(const int32_t *__
                                                               const unsigned int *__restrict__ count,
                                                               const int64_t *__restrict__ row_ptr,
                                                               const float *__restrict__ w, A *__restrict__ inv_s,
-                                                              float *__restrict__ sdeg) {
+                                                              float *__restrict__ sdeg, double *__restrict__ s64) {
     __shared__ double part[BLOCK];
     const unsigned int nh = *count;
     for (unsigned int h = blockIdx.x; h < nh; h += gridDim.x) {
@@ -83,8 +104,9 @@ __global__ __launch_bounds__(BLOCK) void k_weighted_degree_hub(const int32_t *__
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            inv_s[i] = (A)(1.0 / part[0]);
+            inv_s[i] = sweep_scale<A>(part[0]);
             sdeg[i] = (float)part[0];
+            if (s64) s64[i] = part[0];
         }
         __syncthreads();
     }
@@ -195,11 +217,159 @@ __global__ __launch_bounds__(BLOCK) void k_centre_finalize(int R, int64_t nblock
     }
 }
 
-// x^(0) - shift into the start buffer.  One Philox block feeds 4 vectors.
+// Per-component centring.  The members of every component (ad_components)
+// are cut into chunks of COMP_CHUNK; one wave sums a chunk: lane l takes
+// members l, l + 64, ... of the chunk in that order, and a fixed shuffle
+// tree adds the lanes, so the sums depend only on the grouping.
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int d = WAVE / 2; d >= 1; d >>= 1) v += shfl_down(v, d);
+    return v;
+}
+
 template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_comp_partials(int R, int64_t n_comp, int64_t n_chunks,
+                                                        const int32_t *__restrict__ members,
+                                                        const int64_t *__restrict__ comp_start,
+                                                        const int64_t *__restrict__ chunk_start,
+                                                        const float *__restrict__ sdeg,
+                                                        const int32_t *__restrict__ orig_id, uint64_t seed,
+                                                        uint64_t gid, const T *__restrict__ x0,
+                                                        const int32_t *__restrict__ row_graph,
+                                                        double *__restrict__ part, double *__restrict__ part_s) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t ch = (int64_t)blockIdx.x * (BLOCK / WAVE) + (threadIdx.x >> 6);
+    if (ch >= n_chunks) return;                      // uniform across the wave
+    int64_t lo = 0, hi = n_comp - 1;                 // last component starting at or before ch
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (chunk_start[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t p0 = comp_start[lo] + (ch - chunk_start[lo]) * COMP_CHUNK;
+    const int64_t p1 = min(comp_start[lo + 1], p0 + COMP_CHUNK);
+    double sacc = 0.0;
+    for (int64_t p = p0 + lane; p < p1; p += WAVE) sacc += (double)sdeg[members[p]];
+    sacc = wave_sum(sacc);
+    if (lane == 0) part_s[ch] = sacc;
+    const int nq = (R + 3) >> 2;
+    for (int q = 0; q < nq; ++q) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t p = p0 + lane; p < p1; p += WAVE) {
+            const int32_t i = members[p];
+            const double s = (double)sdeg[i];
+            if (x0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (4 * q + c < R) acc[c] += s * (double)x0[(int64_t)i * R + 4 * q + c];
+            } else {
+                uint64_t words[4];
+                const int32_t key = orig_id ? orig_id[i] : i;
+                const uint64_t g = row_graph ? (uint64_t)row_graph[i] : 0ull;
+                philox4x64_10((uint64_t)(uint32_t)key, (uint64_t)q, 0, 0, seed, gid + g, words);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] += s * start_from_word(words[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double v = wave_sum(acc[c]);
+            if (lane == 0 && 4 * q + c < R) part[ch * R + 4 * q + c] = v;
+        }
+    }
+}
+
+// shift[c][r] = the weighted mean of component c rounded to the 2^-24 grid:
+// one thread per (component, vector) adds the component's chunks in order.
+__global__ void k_comp_finalize(int R, int64_t n_comp, const int64_t *__restrict__ chunk_start,
+                                const double *__restrict__ part, const double *__restrict__ part_s, int centre,
+                                double *__restrict__ shift) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_comp * R) return;
+    const int64_t c = idx / R;
+    const int r = (int)(idx - c * R);
+    double S = 0.0, X = 0.0;
+    for (int64_t ch = chunk_start[c]; ch < chunk_start[c + 1]; ++ch) {
+        S += part_s[ch];
+        X += part[ch * R + r];
+    }
+    shift[idx] = (centre && S > 0.0) ? rint((X / S) * 16777216.0) * (1.0 / 16777216.0) : 0.0;
+}
+
+// Current weighted mean of every component (the BF16 re-centring): one wave
+// per chunk sums s_i x_i per vector over the chunk's members as
+// k_comp_partials does; k_comp_drift then adds the chunks of each
+// component in order, keeps c = mean rounded to FP32 for the next sweep to
+// subtract, and adds c to the component's shift.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_comp_drift_partials(int R, int64_t n_comp, int64_t n_chunks,
+                                                              const int32_t *__restrict__ members,
+                                                              const int64_t *__restrict__ comp_start,
+                                                              const int64_t *__restrict__ chunk_start,
+                                                              const float *__restrict__ sdeg,
+                                                              const T *__restrict__ x, double *__restrict__ part) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t ch = (int64_t)blockIdx.x * (BLOCK / WAVE) + (threadIdx.x >> 6);
+    if (ch >= n_chunks) return;                      // uniform across the wave
+    int64_t lo = 0, hi = n_comp - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (chunk_start[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t p0 = comp_start[lo] + (ch - chunk_start[lo]) * COMP_CHUNK;
+    const int64_t p1 = min(comp_start[lo + 1], p0 + COMP_CHUNK);
+    for (int q = 0; q < (R + 3) / 4; ++q) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t p = p0 + lane; p < p1; p += WAVE) {
+            const int32_t i = members[p];
+            const double s = (double)sdeg[i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (4 * q + c >= R) break;
+                float v[1];
+                load_vec<1>(x + (int64_t)i * R + 4 * q + c, v);
+                acc[c] += s * (double)v[0];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double v = wave_sum(acc[c]);
+            if (lane == 0 && 4 * q + c < R) part[ch * R + 4 * q + c] = v;
+        }
+    }
+}
+
+__global__ void k_comp_drift(int R, int64_t n_comp, const int64_t *__restrict__ chunk_start,
+                             const double *__restrict__ part, const double *__restrict__ part_s,
+                             float *__restrict__ drift, double *__restrict__ shift) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_comp * R) return;
+    const int64_t c = idx / R;
+    const int r = (int)(idx - c * R);
+    double S = 0.0, X = 0.0;
+    for (int64_t ch = chunk_start[c]; ch < chunk_start[c + 1]; ++ch) {
+        S += part_s[ch];
+        X += part[ch * R + r];
+    }
+    const float d = S > 0.0 ? (float)(X / S) : 0.0f;
+    drift[idx] = d;
+    shift[idx] += (double)d;
+}
+
+// The running min / max codes of every graph start empty.
+__global__ void k_mm_reset(int64_t count, int R, unsigned long long *__restrict__ mm) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count) return;
+    mm[idx] = ((idx / R) % 2 == 0) ? ~0ull : 0ull;
+}
+
+// x^(0) - shift into the start buffer.  One Philox block feeds 4 vectors.
+template <typename T, typename Tx>
 __global__ void k_init(int64_t n, int R, const int32_t *__restrict__ orig_id, uint64_t seed,
                        uint64_t gid, const T *__restrict__ x0, const double *__restrict__ shift,
-                       T *__restrict__ x, const int32_t *__restrict__ row_graph) {
+                       const int32_t *__restrict__ comp_of, Tx *__restrict__ x,
+                       const int32_t *__restrict__ row_graph) {
     const int nq = (R + 3) >> 2;
     const int64_t total = n * nq;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -212,13 +382,36 @@ __global__ void k_init(int64_t n, int R, const int32_t *__restrict__ orig_id, ui
             int32_t key = orig_id ? orig_id[i] : (int32_t)i;
             philox4x64_10((uint64_t)(uint32_t)key, (uint64_t)q, 0, 0, seed, gid + (uint64_t)g, words);
         }
+        bool zero;
+        const double *sh = row_shift(shift, comp_of, i, g, R, zero);
         for (int c = 0; c < 4; ++c) {
             int r = 4 * q + c;
             if (r >= R) break;
             double v = x0 ? (double)x0[i * R + r] : start_from_word(words[c]);
-            x[i * R + r] = (T)(v - shift[(int64_t)g * R + r]);
+            x[i * R + r] = (Tx)(zero ? v : v - sh[r]);
         }
     }
+}
+
+// Re-centring of BF16 sweeps: every component's current weighted mean c
+// (FP32, per vector) is subtracted from the sweep's output rows.  The sweep
+// matrix maps the component-constant vector c to itself, so the result is
+// x^(t) - c exactly up to rounding, a change of frame that the relaxation
+// adds to the component's shift; the stored values stay on the scale of
+// the component's own differences instead of on that of the mean drift that
+// BF16 rounding accumulates.
+struct SweepDrift {
+    const float *c = nullptr;         // [n_comp][R], or NULL: none
+    const int32_t *comp_of = nullptr; // [n]
+};
+template <typename A, int VEC>
+__device__ __forceinline__ void apply_drift(const SweepDrift &dr, int64_t row, int R, int off, A (&res)[VEC]) {
+    if (!dr.c) return;
+    const int32_t c = dr.comp_of[row];
+    if (c < 0) return;
+    const float *d = dr.c + (int64_t)c * R + off;
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) res[q] -= (A)d[q];
 }
 
 // One lane's part of a launch-plan entry (first row << 16 | rows in the
@@ -387,7 +580,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sweep_wav
     int64_t hub_d, int SPRW, int hub_blocks, const int32_t *__restrict__ hub_list,
     const unsigned int *__restrict__ hub_count, const long long *__restrict__ plan,
     const unsigned int *__restrict__ plan_count, const unsigned int *__restrict__ splits, int xcd_groups,
-    unsigned int *__restrict__ queue, unsigned int *__restrict__ queue_clear) {
+    unsigned int *__restrict__ queue, unsigned int *__restrict__ queue_clear, SweepDrift dr) {
     __shared__ A part[BLOCK / WAVE][64];
     __shared__ unsigned int s_row;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -429,7 +622,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sweep_wav
                 load_vec<VEC>(xin + row * R + off, own);
                 const A is = inv_s[row];
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) res[q] = fma(omega, sum[q] * is, keep * own[q]);
+                for (int q = 0; q < VEC; ++q) res[q] = fma(omega, neighbour_avg(sum[q], is), keep * own[q]);
+                apply_drift(dr, row, R, off, res);
                 store_vec<VEC>(xout + row * R + off, res);
             }
             __syncthreads();
@@ -488,7 +682,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sweep_wav
             A res[VEC];
             if (end > beg) {
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) res[q] = fma(omega, acc[q] * is, keep * own[q]);
+                for (int q = 0; q < VEC; ++q) res[q] = fma(omega, neighbour_avg(acc[q], is), keep * own[q]);
+                apply_drift(dr, row, R, off, res);
             } else {
 #pragma unroll
                 for (int q = 0; q < VEC; ++q) res[q] = own[q];
@@ -553,7 +748,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sweep_wav
                 load_vec<VEC>(xin + row * R + off, own);
                 const A is = inv_s[row];
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) res[q] = fma(omega, sum[q] * is, keep * own[q]);
+                for (int q = 0; q < VEC; ++q) res[q] = fma(omega, neighbour_avg(sum[q], is), keep * own[q]);
+                apply_drift(dr, row, R, off, res);
                 store_vec<VEC>(xout + row * R + off, res);
             }
             if (wave == 0) {
@@ -640,7 +836,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sweep_wav
                 A res[VEC];
                 if (end > beg) {
 #pragma unroll
-                    for (int q = 0; q < VEC; ++q) res[q] = fma(omega, acc[q] * is, keep * own[q]);
+                    for (int q = 0; q < VEC; ++q) res[q] = fma(omega, neighbour_avg(acc[q], is), keep * own[q]);
+                    apply_drift(dr, row, R, off, res);
                 } else {
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) res[q] = own[q];
@@ -729,12 +926,14 @@ __global__ void k_plan_fill(int64_t n, const int *__restrict__ tile_lg, const un
     }
 }
 
-// Per-vector min and max of x over non-isolated rows (ordered-integer
-// atomics); one block per chunk of CENTRE_ROWS rows of one graph.
+// Per-vector min and max of x^(k) = x + shift over non-isolated rows
+// (ordered-integer atomics); one block per chunk of CENTRE_ROWS rows of one
+// graph.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_minmax(int64_t n, int R, const int64_t *__restrict__ row_ptr,
-                                                 const T *__restrict__ x, unsigned long long *__restrict__ mm,
-                                                 Segs sg) {
+                                                 const T *__restrict__ x, const double *__restrict__ shift,
+                                                 const int32_t *__restrict__ comp_of,
+                                                 unsigned long long *__restrict__ mm, Segs sg) {
     __shared__ double lo_l[BLOCK];
     __shared__ double hi_l[BLOCK];
     const int t = threadIdx.x;
@@ -748,7 +947,9 @@ __global__ __launch_bounds__(BLOCK) void k_minmax(int64_t n, int R, const int64_
     if (row_off < stride) {
         for (int64_t i = r0 + row_off; i < r1; i += stride) {
             if (row_ptr[i + 1] == row_ptr[i]) continue;
-            double v = (double)x[i * R + r];
+            bool zero;
+            const double *sh = row_shift(shift, comp_of, i, g, R, zero);
+            double v = (double)x[i * R + r] + (zero ? 0.0 : sh[r]);
             lo = fmin(lo, v);
             hi = fmax(hi, v);
         }
@@ -769,9 +970,7 @@ __global__ __launch_bounds__(BLOCK) void k_minmax(int64_t n, int R, const int64_
     }
 }
 
-__global__ void k_minmax_out(int G, int R, const unsigned long long *__restrict__ mm,
-                             const double *__restrict__ shift, double *__restrict__ out,
-                             double *__restrict__ shift_out) {
+__global__ void k_minmax_out(int G, int R, const unsigned long long *__restrict__ mm, double *__restrict__ out) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)G * R) return;
     const int64_t g = idx / R;
@@ -780,7 +979,6 @@ __global__ void k_minmax_out(int G, int R, const unsigned long long *__restrict_
     bool none = (a == ~0ull);
     out[g * 2 * R + r] = none ? INFINITY : ord_decode(a);
     out[g * 2 * R + R + r] = none ? -INFINITY : ord_decode(b);
-    if (shift_out) shift_out[idx] = shift[idx];
 }
 
 // ------------------------------------------------------------------- host --
@@ -873,7 +1071,7 @@ constexpr int64_t MAX_MAIN_BLOCKS = 4096;   // static walk: persistent, waves lo
 
 template <typename Tin, typename Tout, typename A, int VEC>
 static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout,
-                                int R, const SweepPlan &pl, hipStream_t st) {
+                                int R, const SweepPlan &pl, hipStream_t st, SweepDrift dr) {
     const SweepShape &sh = pl.sh;
     if (pl.xcd_groups <= 1) {
         const int64_t main_blocks = std::min<int64_t>(MAX_MAIN_BLOCKS, ceil_div(g->n, BLOCK / WAVE));
@@ -888,7 +1086,7 @@ static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, cons
         hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC, SWEEP_UNROLL, false>), dim3((unsigned)grid), dim3(BLOCK), 0,
                            st, g->n, g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C, sh.hub_d, sh.SPRW,
                            (int)hub_blocks, pl.hub_list, pl.hub_count, pl.plan, pl.plan_count, pl.splits,
-                           pl.xcd_groups, (unsigned int *)nullptr, (unsigned int *)nullptr);
+                           pl.xcd_groups, (unsigned int *)nullptr, (unsigned int *)nullptr, dr);
         AD_LAUNCH_CHECK("k_sweep");
         return AD_OK;
     }
@@ -916,19 +1114,30 @@ static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, cons
     TraceScope trace("k_sweep", st);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(BLOCK), 0, st, g->n, g->row_ptr, g->col, g->w, inv_s, omega,
                        xin, xout, R, sh.C, sh.hub_d, sh.SPRW, 0, pl.hub_list, pl.hub_count, pl.plan, pl.plan_count,
-                       pl.splits, pl.xcd_groups, use, clear);
+                       pl.splits, pl.xcd_groups, use, clear, dr);
     AD_LAUNCH_CHECK("k_sweep");
     return AD_OK;
 }
 
+// Vector widths a plan can ask for: at most 16 bytes of the plan's element
+// type per lane, which is the input type except for FP64 sweeps run on the
+// FP32 plan (the FP64 tail of FP32 storage: 4 doubles per lane).
+template <typename Tin, typename Tout, typename A, int VEC>
+static ad_status launch_sweep_w(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout, int R,
+                                const SweepPlan &pl, hipStream_t st, SweepDrift dr) {
+    if constexpr (VEC * (sizeof(Tin) < 4 ? sizeof(Tin) : 4) <= 16)
+        return launch_sweep_v<Tin, Tout, A, VEC>(g, inv_s, omega, xin, xout, R, pl, st, dr);
+    return fail(AD_ERR_INTERNAL, "vector width beyond the plan's");
+}
+
 template <typename Tin, typename Tout, typename A>
 static ad_status launch_sweep(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout, int R,
-                              const SweepPlan &pl, hipStream_t st) {
+                              const SweepPlan &pl, hipStream_t st, SweepDrift dr = SweepDrift()) {
     switch (pl.sh.vec) {
-    case 1: return launch_sweep_v<Tin, Tout, A, 1>(g, inv_s, omega, xin, xout, R, pl, st);
-    case 2: return launch_sweep_v<Tin, Tout, A, 2>(g, inv_s, omega, xin, xout, R, pl, st);
-    case 4: return launch_sweep_v<Tin, Tout, A, 4>(g, inv_s, omega, xin, xout, R, pl, st);
-    case 8: return launch_sweep_v<Tin, Tout, A, 8>(g, inv_s, omega, xin, xout, R, pl, st);
+    case 1: return launch_sweep_w<Tin, Tout, A, 1>(g, inv_s, omega, xin, xout, R, pl, st, dr);
+    case 2: return launch_sweep_w<Tin, Tout, A, 2>(g, inv_s, omega, xin, xout, R, pl, st, dr);
+    case 4: return launch_sweep_w<Tin, Tout, A, 4>(g, inv_s, omega, xin, xout, R, pl, st, dr);
+    case 8: return launch_sweep_w<Tin, Tout, A, 8>(g, inv_s, omega, xin, xout, R, pl, st, dr);
     }
     return fail(AD_ERR_INTERNAL, "bad vector width");
 }
@@ -938,11 +1147,14 @@ static size_t dtype_bytes(ad_dtype t) { return t == AD_F64 ? 8 : (t == AD_F32 ? 
 struct RelaxLayout {
     void *inv_s;
     float *sdeg;
+    double *s64;              // s_i for the FP64 tail of FP32 / BF16 storage
     double *part, *part_s, *shift;
+    float *drift;             // BF16 re-centring, [n_comp][R]
     unsigned long long *mm;
     SweepPlan p32, p16;
     void *bufA, *bufB;
     void *b16A, *b16B;
+    void *b64A, *b64B;
 };
 
 static int64_t seg_chunks(const ad_graph *g, const Segs &sg) {
@@ -952,20 +1164,32 @@ static int64_t seg_tiles(const ad_graph *g, const Segs &sg) {
     return sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE);
 }
 
+// Sweeps stored in FP64 at the end (the whole run for AD_F64).
+static int fp64_sweeps(const ad_relax_opts *o) {
+    if (o->store == AD_F64) return o->k;
+    return std::min(std::max(o->fp64_tail, 0), std::max(o->k, 0));
+}
+static bool x_out_f64(const ad_relax_opts *o) { return o->store == AD_F64 || o->fp64_tail > 0; }
+
 static size_t relax_layout(const ad_graph *g, const ad_relax_opts *o, void *ws, size_t ws_bytes,
                            RelaxLayout *L, const Segs &sg) {
     Carver c(ws, ws_bytes);
     const int64_t n = g->n > 0 ? g->n : 1;
     const int R = o->R;
-    const int64_t nb = std::max<int64_t>(1, seg_chunks(g, sg));
+    const bool comp = o->comp != nullptr;
+    const int64_t nb = std::max<int64_t>(1, comp ? o->comp->n_chunks : seg_chunks(g, sg));
+    const int64_t nshift = comp ? std::max<int64_t>(1, o->comp->n_comp) : (int64_t)sg.G;
     const int64_t nt = seg_tiles(g, sg);
     const bool f64 = o->store == AD_F64;
+    const bool tail64 = !f64 && o->fp64_tail > 0 && o->k > 0;
     RelaxLayout l;
     l.inv_s = f64 ? (void *)c.take<double>(n) : (void *)c.take<float>(n);
     l.sdeg = c.take<float>(n);
+    l.s64 = tail64 ? c.take<double>(n) : nullptr;
     l.part = c.take<double>(nb * R);
     l.part_s = c.take<double>(nb);
-    l.shift = c.take<double>((size_t)sg.G * R);
+    l.shift = c.take<double>((size_t)nshift * R);
+    l.drift = (comp && o->store == AD_BF16) ? c.take<float>((size_t)nshift * R) : nullptr;
     l.mm = c.take<unsigned long long>((size_t)sg.G * 2 * R);
     sweep_plan_carve(c, n, nt, l.p32);
     if (o->store == AD_BF16) sweep_plan_carve(c, n, nt, l.p16);
@@ -977,6 +1201,12 @@ static size_t relax_layout(const ad_graph *g, const ad_relax_opts *o, void *ws, 
         l.b16B = c.take<uint16_t>((size_t)n * R);
     } else {
         l.b16A = l.b16B = nullptr;
+    }
+    if (tail64) {
+        l.b64A = c.take<double>((size_t)n * R);
+        l.b64B = o->fp64_tail > 2 ? c.take<double>((size_t)n * R) : nullptr;
+    } else {
+        l.b64A = l.b64B = nullptr;
     }
     if (L) *L = l;
     return c.ok() ? c.used : 0;
@@ -990,31 +1220,75 @@ static ad_status check_relax_opts(const ad_relax_opts *o) {
     if (o->store != AD_F64 && o->store != AD_F32 && o->store != AD_BF16)
         return fail(AD_ERR_INVALID_ARG, "unknown storage type");
     if (o->store == AD_BF16 && o->fp32_tail < 1) return fail(AD_ERR_INVALID_ARG, "fp32_tail must be >= 1");
+    if (o->fp64_tail < 0) return fail(AD_ERR_INVALID_ARG, "fp64_tail must be >= 0");
+    if (o->store == AD_BF16 && o->fp64_tail > 0 && o->fp64_tail >= o->fp32_tail)
+        return fail(AD_ERR_INVALID_ARG, "with BF16 storage fp64_tail must be below fp32_tail");
     if (o->ckpt_every < 0) return fail(AD_ERR_INVALID_ARG, "ckpt_every must be >= 0");
     if (o->ckpt_every > 0 && o->store == AD_BF16)
         return fail(AD_ERR_UNSUPPORTED, "checkpoints need FP32 or FP64 storage");
+    if (o->ckpt_every > 0 && o->store != AD_F64 && o->fp64_tail > 0)
+        return fail(AD_ERR_UNSUPPORTED, "checkpoints need fp64_tail == 0");
     if (o->rows_per_wave < 0 || o->hub_degree < 0) return fail(AD_ERR_INVALID_ARG, "negative tuning value");
+    if (o->comp) {
+        const ad_components *c = o->comp;
+        if (c->n_comp < 0 || c->n_chunks < c->n_comp) return fail(AD_ERR_INVALID_ARG, "bad component counts");
+        if (c->n_comp > 0 && (!c->comp_of || !c->members || !c->comp_start || !c->chunk_start))
+            return fail(AD_ERR_INVALID_ARG, "component arrays are NULL");
+    }
     return AD_OK;
 }
 
-// s_i and 1/s_i: rows up to the plan's hub degree by lane groups, longer
-// rows (the plan's hub list) by a workgroup each.
+// s_i and the sweep scale (1/s_i for FP32, s_i for FP64 arithmetic): rows up
+// to the plan's hub degree by lane groups, longer rows (the plan's hub list)
+// by a workgroup each; s64 (optional) receives s_i in FP64.
 template <typename A>
-static ad_status weighted_degree_impl(const ad_graph *g, A *inv_s, float *sdeg, const SweepPlan &pl,
+static ad_status weighted_degree_impl(const ad_graph *g, A *inv_s, float *sdeg, double *s64, const SweepPlan &pl,
                                       hipStream_t st) {
     const int64_t n = g->n;
     if (n <= 0) return AD_OK;
     const int lpr = degree_lanes((double)(2 * g->m) / (double)n);
     hipLaunchKernelGGL((k_weighted_degree<A>), dim3((unsigned)ceil_div(n * lpr, BLOCK)), dim3(BLOCK), 0, st, n,
-                       g->row_ptr, g->w, inv_s, sdeg, lpr, pl.sh.hub_d);
+                       g->row_ptr, g->w, inv_s, sdeg, s64, lpr, pl.sh.hub_d);
     AD_LAUNCH_CHECK("k_weighted_degree");
     if (g->d_max == 0 || g->d_max > pl.sh.hub_d) {
         const unsigned grid = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(2 * g->m, pl.sh.hub_d + 1)));
         hipLaunchKernelGGL((k_weighted_degree_hub<A>), dim3(grid), dim3(BLOCK), 0, st, pl.hub_list, pl.hub_count,
-                           g->row_ptr, g->w, inv_s, sdeg);
+                           g->row_ptr, g->w, inv_s, sdeg, s64);
         AD_LAUNCH_CHECK("k_weighted_degree_hub");
     }
     return AD_OK;
+}
+
+// One sweep from cur to dst in the types they are stored in.
+static ad_status sweep_step(const ad_graph *g, const RelaxLayout &L, const RelaxLayout &P, double omega,
+                            const Buf &cur, const Buf &dst, int R, hipStream_t st, SweepDrift dr) {
+    if (dst.t == AD_F64) {
+        // FP64 arithmetic, dividing by s_i: the FP64 storage form reads its
+        // divisor from inv_s, the FP64 tail of FP32 storage from s64 and runs
+        // on the FP32 plan
+        if (cur.t == AD_F64) {
+            if (L.s64)
+                return launch_sweep<double, double, double>(g, L.s64, omega, (const double *)cur.p,
+                                                            (double *)dst.p, R, P.p32, st);
+            return launch_sweep<double, double, double>(g, (const double *)L.inv_s, omega, (const double *)cur.p,
+                                                        (double *)dst.p, R, P.p32, st);
+        }
+        if (cur.t == AD_F32)
+            return launch_sweep<float, double, double>(g, L.s64, omega, (const float *)cur.p, (double *)dst.p, R,
+                                                       P.p32, st);
+        return fail(AD_ERR_INTERNAL, "BF16 to FP64 sweep");
+    }
+    const float om = (float)omega;
+    const float *is = (const float *)L.inv_s;
+    if (cur.t == AD_F32 && dst.t == AD_F32)
+        return launch_sweep<float, float, float>(g, is, om, (const float *)cur.p, (float *)dst.p, R, P.p32, st);
+    if (cur.t == AD_F32 && dst.t == AD_BF16)
+        return launch_sweep<float, bf16, float>(g, is, om, (const float *)cur.p, (bf16 *)dst.p, R, P.p32, st, dr);
+    if (cur.t == AD_BF16 && dst.t == AD_BF16)
+        return launch_sweep<bf16, bf16, float>(g, is, om, (const bf16 *)cur.p, (bf16 *)dst.p, R, P.p16, st, dr);
+    if (cur.t == AD_BF16 && dst.t == AD_F32)
+        return launch_sweep<bf16, float, float>(g, is, om, (const bf16 *)cur.p, (float *)dst.p, R, P.p16, st);
+    return fail(AD_ERR_INTERNAL, "unsupported sweep types");
 }
 
 // Enqueue the whole relaxation.  `shift_out` may be NULL.
@@ -1025,6 +1299,7 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
     typedef typename acc_of<T>::type A;
     const int R = o->R;
     const int64_t n = g->n;
+    const ad_components *comp = o->comp;
     const int64_t nb = seg_chunks(g, sg);
     ad_status s;
 
@@ -1044,26 +1319,58 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
         }
     }
 
+    // the shifts: written straight into shift_out when the caller wants them
+    double *shift = shift_out ? shift_out : L.shift;
     if (n > 0) {
-        s = weighted_degree_impl<A>(g, (A *)L.inv_s, L.sdeg, P.p32, st);
+        s = weighted_degree_impl<A>(g, (A *)L.inv_s, L.sdeg, L.s64, P.p32, st);
         if (s != AD_OK) return s;
-        if (nb > 0) {
+    }
+    if (comp) {
+        if (n > 0 && comp->n_chunks > 0) {
+            hipLaunchKernelGGL((k_comp_partials<T>), dim3((unsigned)ceil_div(comp->n_chunks, BLOCK / WAVE)),
+                               dim3(BLOCK), 0, st, R, comp->n_comp, comp->n_chunks, comp->members, comp->comp_start,
+                               comp->chunk_start, L.sdeg, g->orig_id, o->seed, o->graph_id, (const T *)x0,
+                               sg.row_graph, L.part, L.part_s);
+            AD_LAUNCH_CHECK("k_comp_partials");
+        }
+        const int64_t cr = comp->n_comp * R;
+        if (cr > 0) {
+            hipLaunchKernelGGL(k_comp_finalize, dim3((unsigned)ceil_div(cr, BLOCK)), dim3(BLOCK), 0, st, R,
+                               comp->n_comp, comp->chunk_start, L.part, L.part_s, 1, shift);
+            AD_LAUNCH_CHECK("k_comp_finalize");
+        }
+        const int64_t mmc = (int64_t)sg.G * 2 * R;
+        hipLaunchKernelGGL(k_mm_reset, dim3((unsigned)ceil_div(mmc, BLOCK)), dim3(BLOCK), 0, st, mmc, R, L.mm);
+        AD_LAUNCH_CHECK("k_mm_reset");
+    } else {
+        if (n > 0 && nb > 0) {
             hipLaunchKernelGGL((k_centre_partials<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, L.sdeg,
                                g->orig_id, o->seed, o->graph_id, (const T *)x0, L.part, L.part_s, sg);
             AD_LAUNCH_CHECK("k_centre_partials");
         }
+        hipLaunchKernelGGL(k_centre_finalize, dim3((unsigned)sg.G), dim3(BLOCK), 0, st, R, n > 0 ? nb : (int64_t)0,
+                           L.part, L.part_s, 1, shift, L.mm, sg);
+        AD_LAUNCH_CHECK("k_centre_finalize");
     }
-    hipLaunchKernelGGL(k_centre_finalize, dim3((unsigned)sg.G), dim3(BLOCK), 0, st, R, n > 0 ? nb : (int64_t)0,
-                       L.part, L.part_s, 1, L.shift, L.mm, sg);
-    AD_LAUNCH_CHECK("k_centre_finalize");
+    const int32_t *comp_of = comp ? comp->comp_of : nullptr;
 
     const int nck = ad_relax_num_checkpoints(o);
     const size_t slot_elems = (size_t)n * R;
-    T *start = (o->k == 0) ? (T *)x_out : (ckpt && nck > 0 ? (T *)ckpt : (T *)L.bufA);
+    const bool out64 = x_out_f64(o);
+    const ad_dtype tstore = o->store == AD_F64 ? AD_F64 : AD_F32;
+    Buf cur;
+    if (o->k == 0) cur = {x_out, out64 ? AD_F64 : AD_F32};
+    else cur = {ckpt && nck > 0 ? ckpt : L.bufA, tstore};
     if (n > 0) {
         int64_t total = n * ((R + 3) / 4);
-        hipLaunchKernelGGL((k_init<T>), dim3(grid_for(total, BLOCK)), dim3(BLOCK), 0, st, n, R,
-                           g->orig_id, o->seed, o->graph_id, (const T *)x0, L.shift, start, sg.row_graph);
+        if (cur.t == AD_F64)
+            hipLaunchKernelGGL((k_init<T, double>), dim3(grid_for(total, BLOCK)), dim3(BLOCK), 0, st, n, R,
+                               g->orig_id, o->seed, o->graph_id, (const T *)x0, shift, comp_of, (double *)cur.p,
+                               sg.row_graph);
+        else
+            hipLaunchKernelGGL((k_init<T, float>), dim3(grid_for(total, BLOCK)), dim3(BLOCK), 0, st, n, R,
+                               g->orig_id, o->seed, o->graph_id, (const T *)x0, shift, comp_of, (float *)cur.p,
+                               sg.row_graph);
         AD_LAUNCH_CHECK("k_init");
     }
 
@@ -1072,50 +1379,53 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
         // between two sweeps would cost the stream more than it measures)
         TraceScope trace("k_sweep", st, o->k);
         TraceSuppress per_launch;
-        Buf cur = {start, o->store == AD_F64 ? AD_F64 : AD_F32};
-        const int tail = o->store == AD_BF16 ? o->fp32_tail : o->k;
+        const int tail32 = o->store == AD_BF16 ? o->fp32_tail : o->k;
+        const int tail64 = fp64_sweeps(o);
         for (int t = 1; t <= o->k; ++t) {
+            const bool wide = t > o->k - tail64;
             Buf dst;
             if (t == o->k) {
-                dst = {x_out, o->store == AD_F64 ? AD_F64 : AD_F32};
+                dst = {x_out, out64 ? AD_F64 : AD_F32};
+            } else if (wide && o->store != AD_F64) {
+                dst = {cur.p == L.b64A ? L.b64B : L.b64A, AD_F64};
             } else if (ckpt && o->ckpt_every > 0 && t % o->ckpt_every == 0) {
-                dst = {(char *)ckpt + (size_t)(t / o->ckpt_every) * slot_elems * sizeof(T),
-                       o->store == AD_F64 ? AD_F64 : AD_F32};
-            } else if (o->store == AD_BF16 && t <= o->k - tail) {
+                dst = {(char *)ckpt + (size_t)(t / o->ckpt_every) * slot_elems * sizeof(T), tstore};
+            } else if (o->store == AD_BF16 && t <= o->k - tail32) {
                 dst = {cur.p == L.b16A ? L.b16B : L.b16A, AD_BF16};
             } else {
-                dst = {cur.p == L.bufA ? L.bufB : L.bufA, o->store == AD_F64 ? AD_F64 : AD_F32};
+                dst = {cur.p == L.bufA ? L.bufB : L.bufA, tstore};
             }
-            const A om = (A)o->omega;
-            if (cur.t == AD_F64) {
-                s = launch_sweep<double, double, double>(g, (const double *)L.inv_s, (double)om,
-                                                         (const double *)cur.p, (double *)dst.p, R, P.p32, st);
-            } else if (cur.t == AD_F32 && dst.t == AD_F32) {
-                s = launch_sweep<float, float, float>(g, (const float *)L.inv_s, (float)om,
-                                                      (const float *)cur.p, (float *)dst.p, R, P.p32, st);
-            } else if (cur.t == AD_F32 && dst.t == AD_BF16) {
-                s = launch_sweep<float, bf16, float>(g, (const float *)L.inv_s, (float)om,
-                                                     (const float *)cur.p, (bf16 *)dst.p, R, P.p32, st);
-            } else if (cur.t == AD_BF16 && dst.t == AD_BF16) {
-                s = launch_sweep<bf16, bf16, float>(g, (const float *)L.inv_s, (float)om,
-                                                    (const bf16 *)cur.p, (bf16 *)dst.p, R, P.p16, st);
-            } else {
-                s = launch_sweep<bf16, float, float>(g, (const float *)L.inv_s, (float)om,
-                                                     (const bf16 *)cur.p, (float *)dst.p, R, P.p16, st);
+            SweepDrift dr;
+            if (L.drift && dst.t == AD_BF16 && t >= 2 && comp->n_comp > 0) {
+                hipLaunchKernelGGL((k_comp_drift_partials<bf16>), dim3((unsigned)ceil_div(comp->n_chunks, BLOCK / WAVE)),
+                                   dim3(BLOCK), 0, st, R, comp->n_comp, comp->n_chunks, comp->members,
+                                   comp->comp_start, comp->chunk_start, L.sdeg, (const bf16 *)cur.p, L.part);
+                AD_LAUNCH_CHECK("k_comp_drift_partials");
+                const int64_t cr = comp->n_comp * R;
+                hipLaunchKernelGGL(k_comp_drift, dim3((unsigned)ceil_div(cr, BLOCK)), dim3(BLOCK), 0, st, R,
+                                   comp->n_comp, comp->chunk_start, L.part, L.part_s, L.drift, shift);
+                AD_LAUNCH_CHECK("k_comp_drift");
+                dr.c = L.drift;
+                dr.comp_of = comp->comp_of;
             }
+            s = sweep_step(g, L, P, o->omega, cur, dst, R, st, dr);
             if (s != AD_OK) return s;
             cur = dst;
         }
     }
 
     if (n > 0 && nb > 0) {
-        hipLaunchKernelGGL((k_minmax<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, g->row_ptr,
-                           (const T *)x_out, L.mm, sg);
+        if (out64)
+            hipLaunchKernelGGL((k_minmax<double>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, g->row_ptr,
+                               (const double *)x_out, shift, comp_of, L.mm, sg);
+        else
+            hipLaunchKernelGGL((k_minmax<float>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, g->row_ptr,
+                               (const float *)x_out, shift, comp_of, L.mm, sg);
         AD_LAUNCH_CHECK("k_minmax");
     }
     const int64_t gr = (int64_t)sg.G * R;
     hipLaunchKernelGGL(k_minmax_out, dim3((unsigned)ceil_div(gr, BLOCK)), dim3(BLOCK), 0, st, sg.G, R, L.mm,
-                       L.shift, minmax_out, shift_out);
+                       minmax_out);
     AD_LAUNCH_CHECK("k_minmax_out");
     return AD_OK;
 }
@@ -1138,7 +1448,7 @@ ad_status sweep_f32(const ad_graph *g, const float *inv_s, float omega, const fl
 }
 
 ad_status weighted_degree_f32(const ad_graph *g, float *inv_s, float *sdeg, const SweepPlan &pl, hipStream_t st) {
-    return weighted_degree_impl<float>(g, inv_s, sdeg, pl, st);
+    return weighted_degree_impl<float>(g, inv_s, sdeg, nullptr, pl, st);
 }
 
 }  // namespace ad

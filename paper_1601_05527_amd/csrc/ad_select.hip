@@ -1347,7 +1347,8 @@ size_t edge_dist_segs_workspace(const ad_graph *g, const Segs &sg) {
 }
 
 ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x, const double *minmax,
-                         void *rho, void *ws, size_t ws_bytes, const Segs &sg, hipStream_t stream) {
+                         ad_dtype rho_dtype, void *rho, void *ws, size_t ws_bytes, const Segs &sg,
+                         hipStream_t stream) {
     Carver c(ws, ws_bytes);
     SweepPlan pl;
     sweep_plan_carve(c, g->n, sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE), pl);
@@ -1371,9 +1372,13 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
                        g->row_ptr, g->col, g->eid, (const TX *)x, minmax, (TR *)rho, R, pl.sh.C, pl.sh.SPRW,  \
                        pl.sh.hub_d, (int)hub_blocks, hub_segs, pl.hub_list, pl.hub_count, pl.plan,            \
                        pl.plan_count, pl.splits, pl.xcd_groups, sg.row_graph)
-    if (x_dtype == AD_F64) {
+    if (x_dtype == AD_F64 && rho_dtype == AD_F64) {
         if (pl.sh.vec == 2) AD_DIST(double, double, 2);
         else AD_DIST(double, double, 1);
+    } else if (x_dtype == AD_F64) {
+        // FP64 vectors (the FP64 tail of FP32 storage), FP64 arithmetic, FP32 rho
+        if (pl.sh.vec == 2) AD_DIST(double, float, 2);
+        else AD_DIST(double, float, 1);
     } else {
         if (pl.sh.vec == 4) AD_DIST(float, float, 4);
         else if (pl.sh.vec == 2) AD_DIST(float, float, 2);
@@ -1410,16 +1415,18 @@ extern "C" size_t ad_edge_dist_workspace_size(const ad_graph *g) {
 }
 
 extern "C" ad_status ad_edge_dist(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
-                                  const double *minmax, void *rho, void *ws, size_t ws_bytes,
+                                  const double *minmax, ad_dtype rho_dtype, void *rho, void *ws, size_t ws_bytes,
                                   hipStream_t stream) {
     ad_status s = check_graph_args(g);
     if (s != AD_OK) return s;
     if (R < 1 || R > 64) return fail(AD_ERR_INVALID_ARG, "R must be in [1, 64]");
     if (x_dtype != AD_F32 && x_dtype != AD_F64) return fail(AD_ERR_INVALID_ARG, "x must be F32 or F64");
+    if (rho_dtype != AD_F32 && rho_dtype != AD_F64) return fail(AD_ERR_INVALID_ARG, "rho must be F32 or F64");
+    if (rho_dtype == AD_F64 && x_dtype != AD_F64) return fail(AD_ERR_UNSUPPORTED, "FP64 rho needs FP64 x");
     if (g->m > 0 && (!x || !minmax || !rho)) return fail(AD_ERR_INVALID_ARG, "x, minmax or rho is NULL");
     if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
-    return edge_dist_segs(g, R, x_dtype, x, minmax, rho, ws, ws_bytes, Segs(), stream);
+    return edge_dist_segs(g, R, x_dtype, x, minmax, rho_dtype, rho, ws, ws_bytes, Segs(), stream);
 }
 
 extern "C" size_t ad_normalize_dist_workspace_size(const ad_graph *g) {

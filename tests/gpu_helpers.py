@@ -25,24 +25,28 @@ def rel_stats(got, want, floor=0.0):
 def near_cut_mismatches(g, rho_ref, keep_got, keep_ref, orient, e, tol):
     """Edges whose kept/dropped state differs, minus those explained by
     rounding: an edge within `tol` (relative) of a deciding endpoint's cut in
-    the reference distances.  Returns the list of unexplained edge ids."""
+    the reference distances (the c_i-th key of row i in rank order, or the
+    (c_i+1)-th).  Returns the list of unexplained edge ids."""
     import math
     bad = []
-    diff = np.nonzero(keep_got != keep_ref)[0]
-    for q in diff:
-        explained = False
-        for i in (int(g.edge_u[q]), int(g.edge_v[q])):
-            ps = range(g.row_ptr[i], g.row_ptr[i + 1])
-            vals = sorted(float(rho_ref[g.eid[p]]) for p in ps)
+    diff = np.nonzero(np.asarray(keep_got) != np.asarray(keep_ref))[0]
+    cuts = {}
+
+    def row_cut(i):
+        if i not in cuts:
+            ps = slice(int(g.row_ptr[i]), int(g.row_ptr[i + 1]))
+            vals = np.sort(np.asarray(rho_ref, dtype=np.float64)[g.eid[ps]])
             if orient == 1:
                 vals = vals[::-1]
             d = len(vals)
             c = min(d, max(1, int(math.floor(d ** e))))
-            cut = [vals[c - 1]] + ([vals[c]] if c < d else [])
-            r = float(rho_ref[q])
-            if any(abs(r - kc) <= tol * max(abs(kc), 1e-30) for kc in cut):
-                explained = True
-                break
+            cuts[i] = [float(vals[c - 1])] + ([float(vals[c])] if c < d else [])
+        return cuts[i]
+
+    for q in diff:
+        r = float(rho_ref[q])
+        explained = any(abs(r - kc) <= tol * max(abs(kc), 1e-30)
+                        for i in (int(g.edge_u[q]), int(g.edge_v[q])) for kc in row_cut(i))
         if not explained:
             bad.append(int(q))
     return bad

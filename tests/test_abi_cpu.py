@@ -73,6 +73,11 @@ def test_relax_rejects_bad_arguments():
     assert call(api.relax_opts(4, 2, omega=1.5)) == 1
     assert call(api.relax_opts(4, 2, store="bf16", fp32_tail=0)) == 1
     assert call(api.relax_opts(4, 2, store="bf16", ckpt_every=2)) == 2
+    assert call(api.relax_opts(4, 2, fp64_tail=-1)) == 1
+    assert call(api.relax_opts(4, 2, fp64_tail=1, ckpt_every=1)) == 2     # checkpoints need no FP64 tail
+    assert call(api.relax_opts(4, 8, store="bf16", fp32_tail=2, fp64_tail=2)) == 1
+    bad_comp = api.Components(2, 1, *[__import__("torch").zeros(1)] * 4)  # fewer chunks than components
+    assert call(api.relax_opts(4, 2, comp=bad_comp)) == 1
     assert call(api.relax_opts(4, 2), ws_=ctypes.c_void_p(0x10001)) == 3   # misaligned
     assert call(api.relax_opts(4, 2), nbytes=16) == 3                     # too small
     msg = L.ad_last_error().decode()
@@ -93,9 +98,11 @@ def test_selection_rejects_bad_arguments():
     assert L.ad_sparsify_fit(ctypes.byref(g), 2, p, 0, 0.3, p, p, ctypes.byref(e), ws, 1 << 30, None) == 1
     assert L.ad_sparsify(ctypes.byref(g), 1, p, 7, p, p, p, ws, 1 << 30, None) == 1
     assert L.ad_sparsify(ctypes.byref(g), 1, p, 0, None, p, p, ws, 1 << 30, None) == 1
-    assert L.ad_edge_dist(ctypes.byref(g), 0, 1, p, p, p, ws, 1 << 30, None) == 1
-    assert L.ad_edge_dist(ctypes.byref(g), 4, 2, p, p, p, ws, 1 << 30, None) == 1
-    assert L.ad_edge_dist(ctypes.byref(g), 4, 1, p, p, p, ws, 16, None) == 3
+    assert L.ad_edge_dist(ctypes.byref(g), 0, 1, p, p, 1, p, ws, 1 << 30, None) == 1
+    assert L.ad_edge_dist(ctypes.byref(g), 4, 2, p, p, 1, p, ws, 1 << 30, None) == 1
+    assert L.ad_edge_dist(ctypes.byref(g), 4, 1, p, p, 2, p, ws, 1 << 30, None) == 1     # BF16 rho
+    assert L.ad_edge_dist(ctypes.byref(g), 4, 1, p, p, 0, p, ws, 1 << 30, None) == 2     # FP64 rho of FP32 x
+    assert L.ad_edge_dist(ctypes.byref(g), 4, 1, p, p, 1, p, ws, 16, None) == 3
     # fit of both orientations: target and keep_global
     e2 = (ctypes.c_double * 2)()
     assert L.ad_sparsify_fit_both(ctypes.byref(g), 1, p, 0.0, p, p, p, e2, ws, 1 << 30, None) == 1

@@ -11,6 +11,13 @@ from gpu_helpers import announce
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
+# Per-edge bound on |g_gpu - g_oracle| / (|g_oracle| + 1e-3 max |g_oracle|):
+# the FP32 adjoint accumulates every sweep's contributions in single
+# precision, so an edge whose gradient is a small difference of large terms
+# carries an error on the scale of the largest gradients (hence the 1e-3
+# floor) and of k FP32 roundings.
+PER_EDGE = 1e-3
+
 
 @pytest.fixture(scope="module")
 def api():
@@ -40,6 +47,7 @@ def test_adjoint_small_grid(api, side, ckpt_every, k):
     per = np.abs(gw - want) / (np.abs(want) + 1e-3 * np.abs(want).max())
     print(f"rel L2 {err:.3e}  max per-edge {per.max():.3e}")
     assert err <= 1e-4
+    assert per.max() <= PER_EDGE
 
 
 def test_adjoint_full_grid_512(api):
@@ -50,8 +58,11 @@ def test_adjoint_full_grid_512(api):
     gw, rho = _grad_gpu(api, g, c, R, k, seed, 5)
     want = oracle.grad_weights(g, c, R, k, 0.5, x0=oracle.start_vectors(g.n, R, seed, 0, g.orig_id))
     err = np.linalg.norm(gw - want) / np.linalg.norm(want)
-    print(f"512x512 rel L2 {err:.3e}")
+    per = np.abs(gw - want) / (np.abs(want) + 1e-3 * np.abs(want).max())
+    print(f"512x512 rel L2 {err:.3e}  max per-edge {per.max():.3e}  "
+          f"p99.9 {np.quantile(per, 0.999):.3e}")
     assert err <= 1e-4
+    assert per.max() <= PER_EDGE
     # directional derivative of the FP64 oracle forward along a random direction
     v = np.random.default_rng(12).normal(size=g.m)
     h = 1e-6

@@ -1,12 +1,14 @@
 """BF16 storage of the test vectors (FP32 arithmetic, FP32 degree
 normalisation and distances) against the FP64 oracle.
 
-Bound: 2e-2 relative on rho, over edges whose oracle distance is at least
-a tenth of the median (smaller distances are measured against that floor:
-BF16 keeps 8 significant bits of x_i and x_j, so the error of x_i - x_j is
-absolute, on the scale of the vectors, not of their difference), with the
-last 8 sweeps stored in FP32 (they damp the rounding noise of the BF16
-sweeps, which is mostly high-frequency).  Kept-edge sets agree except on
+Bound: 2e-2 relative on every edge's rho.  Sweeps 1 .. k-8 are stored in
+BF16, the next 7 in FP32 and the last one in FP64 (TAIL = 8 counts every
+sweep stored wider than BF16; the FP64 sweep divides by s_i, which keeps the
+exact zeros of two-vertex components).  Each connected component is centred
+by its own weighted mean, and before every BF16 sweep by its current one:
+BF16 rounding moves a component's mean by about 2^-9 of its values per
+sweep, and without the re-centring a small component's tiny differences
+end up stored on the scale of that drift.  Kept-edge sets agree except on
 edges within 2e-2 of a deciding endpoint's cut.
 """
 import numpy as np
@@ -14,14 +16,16 @@ import pytest
 
 import oracle
 from paper_1601_05527_amd import graphs as G
+from paper_1601_05527_amd.workloads import FP64_TAIL
 
-from gpu_helpers import announce, check_fp32, near_cut_mismatches, rel_stats
+from gpu_helpers import announce, near_cut_mismatches, rel_stats
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 TOL = 2e-2
-TAIL = 8          # sweeps stored in FP32 at the end of the relaxation
+TAIL = 8          # sweeps stored wider than BF16 at the end of the relaxation
+TAIL64 = 1        # of those, the last ones stored in FP64
 
 
 @pytest.fixture(scope="module")
@@ -43,11 +47,10 @@ def _case(kind):
 
 
 def _stats(rho, rho_o):
-    floor = 0.1 * float(np.median(rho_o))
-    st = rel_stats(rho, rho_o, floor)
+    st = rel_stats(rho, rho_o)
     rel = st["rel"]
     return {"max": st["max"], "p999": st["p999"], "p99": float(np.quantile(rel, 0.99)),
-            "median": float(np.median(rel)), "floor": floor}
+            "median": float(np.median(rel)), "n_over": int((rel > TOL).sum())}
 
 
 @pytest.mark.parametrize("kind", ["rmat", "chung_lu", "grid"])
@@ -55,17 +58,16 @@ def test_bf16_distances_against_oracle(api, kind):
     announce(f"BF16 storage {kind}")
     g, R, k = _case(kind)
     dg = api.DeviceGraph.from_host(g, "cuda")
-    rho_o, xk_o, _, mm_o = oracle.algebraic_distance(g, R, k, 0.5, seed=9, want_vectors=True)
-    x0 = oracle.start_vectors(g.n, R, 9, 0, g.orig_id)
-    res16 = api.relax(dg, R, k, seed=9, store="bf16", fp32_tail=TAIL)
-    rho16 = _np(api.edge_dist(dg, res16.x, res16.minmax))
-    res32 = api.relax(dg, R, k, seed=9, store="f32")
-    rho32 = _np(api.edge_dist(dg, res32.x, res32.minmax))
+    rho_o = oracle.algebraic_distance(g, R, k, 0.5, seed=9)
+    res16 = api.relax(dg, R, k, seed=9, store="bf16", fp32_tail=TAIL, fp64_tail=TAIL64)
+    rho16 = _np(api.distances(dg, res16))
+    res32 = api.relax(dg, R, k, seed=9, store="f32", fp64_tail=FP64_TAIL)
+    rho32 = _np(api.distances(dg, res32))
     s16 = _stats(rho16, rho_o)
-    ratio32, s32 = check_fp32(g, x0, xk_o, mm_o, rho32, rho_o, k)
+    s32 = rel_stats(rho32, rho_o)
     print(f"{kind}: n={g.n} m={g.m} R={R} k={k}  BF16 rel err max {s16['max']:.2e} p99.9 {s16['p999']:.2e} "
-          f"p99 {s16['p99']:.2e} median {s16['median']:.2e}  |  FP32 {s32}, worst/bound {ratio32:.2f}")
-    assert ratio32 <= 1.0
+          f"p99 {s16['p99']:.2e} median {s16['median']:.2e}  |  FP32 max {s32['max']:.2e}")
+    assert s32["max"] <= 1e-5
     assert s16["max"] <= TOL
     # kept edges: BF16 distances against the oracle's, both orientations
     for orient in (0, 1):
@@ -78,17 +80,20 @@ def test_bf16_distances_against_oracle(api, kind):
 
 @pytest.mark.parametrize("tail", [1, 2, 4, 8, 12])
 def test_bf16_fp32_tail(api, tail):
-    """Every split between BF16 and FP32 sweeps runs; the error falls as
-    the FP32 tail (the last sweeps stored in FP32) grows, and from 8 tail
-    sweeps on it is within the bound."""
+    """Every split between BF16 and wider sweeps runs; the error falls as
+    the tail grows, and from 8 tail sweeps on it is within the bound on
+    every edge.  Shorter tails are reported with their count of edges
+    beyond the bound (the BF16 rounding noise of the last BF16 sweeps is
+    not yet damped)."""
     announce(f"BF16 tail={tail}")
     g, R, k = _case("rmat")
     dg = api.DeviceGraph.from_host(g, "cuda")
     rho_o = oracle.algebraic_distance(g, R, k, 0.5, seed=9)
-    res = api.relax(dg, R, k, seed=9, store="bf16", fp32_tail=tail)
-    rho = _np(api.edge_dist(dg, res.x, res.minmax))
+    res = api.relax(dg, R, k, seed=9, store="bf16", fp32_tail=tail, fp64_tail=TAIL64 if tail > TAIL64 else 0)
+    rho = _np(api.distances(dg, res))
     st = _stats(rho, rho_o)
-    print(f"tail {tail}: max {st['max']:.2e} p99.9 {st['p999']:.2e} p99 {st['p99']:.2e} median {st['median']:.2e}")
+    print(f"tail {tail}: max {st['max']:.2e} p99.9 {st['p999']:.2e} p99 {st['p99']:.2e} median {st['median']:.2e} "
+          f"beyond {TOL}: {st['n_over']}")
     assert st["median"] <= TOL
     if tail >= TAIL:
         assert st["max"] <= TOL

@@ -104,6 +104,7 @@ def test_ml_sparsify_matches_oracle(api, case):
     announce(f"ml sparsify {kind} levels={levels}")
     g = _graph(kind)
     dg = api.DeviceGraph.from_host(g, "cuda")
+    e = (list(e) + [e[-1]] * levels)[:levels]
     keep, kept, depth = api.ml_sparsify(dg, 8, 10, e, seed=3, graph_id=2, levels=levels, n_min=n_min,
                                         store="f64", bin_seed=11)
     keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, e, seed=3, graph_id=2, levels=levels, n_min=n_min,
@@ -115,17 +116,22 @@ def test_ml_sparsify_matches_oracle(api, case):
 
 
 def test_ml_sparsify_fp32_against_oracle(api):
-    """FP32 relaxation: the same depth and a kept count within 1% of the
-    FP64 oracle's (decisions near a cut may flip with the rounding)."""
+    """FP32 relaxation (each component centred apart, the last two sweeps
+    in FP64; every level's distances within 1e-5 of the FP64 oracle's):
+    the same depth and kept edges as the FP64 oracle, edge for edge -- on
+    these seeded inputs no seed, aggregate or selection decision lies within
+    that tolerance of its threshold."""
     announce("ml sparsify f32")
     g = _graph("chung_lu")
     dg = api.DeviceGraph.from_host(g, "cuda")
-    keep, kept, depth = api.ml_sparsify(dg, 8, 10, [0.5], seed=3, levels=3, n_min=300, store="f32", bin_seed=11)
-    keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, [0.5], seed=3, levels=3, n_min=300, bin_seed=11)
+    keep, kept, depth = api.ml_sparsify(dg, 8, 10, [0.5] * 3, seed=3, levels=3, n_min=300, store="f32", bin_seed=11)
+    keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, [0.5] * 3, seed=3, levels=3, n_min=300, bin_seed=11)
+    print(f"f32: kept {kept} oracle {kept_o}, depth {depth} oracle {depth_o}, "
+          f"{int((_np(keep) != keep_o).sum())} edges differ")
     assert depth == depth_o
-    assert abs(kept - kept_o) <= 0.01 * kept_o
     assert int(_np(keep).sum()) == kept
-    assert np.mean(_np(keep) == keep_o) > 0.97
+    assert kept == kept_o
+    np.testing.assert_array_equal(_np(keep), keep_o)
 
 
 def test_one_level_is_binned_and_exponent_one_keeps_all(api):
@@ -138,7 +144,7 @@ def test_one_level_is_binned_and_exponent_one_keeps_all(api):
     kb, nb, _ = api.sparsify_binned(dg, rho, 7, e=0.5)
     assert depth == 0 and kept == int(_np(nb)[0])
     np.testing.assert_array_equal(_np(keep), _np(kb))
-    keep, kept, depth = api.ml_sparsify(dg, 8, 10, [1.0], seed=4, levels=6, n_min=100, store="f32", bin_seed=7)
+    keep, kept, depth = api.ml_sparsify(dg, 8, 10, [1.0] * 6, seed=4, levels=6, n_min=100, store="f32", bin_seed=7)
     assert depth >= 2 and kept == g.m and bool(np.all(_np(keep) == 1))
 
 
@@ -146,18 +152,18 @@ def test_small_and_empty_graphs(api):
     announce("ml sparsify small and empty")
     g = G.from_edges(5, np.zeros(0, int), np.zeros(0, int))
     dg = api.DeviceGraph.from_host(g, "cuda")
-    keep, kept, depth = api.ml_sparsify(dg, 8, 10, [0.5], levels=3, n_min=0, store="f64")
+    keep, kept, depth = api.ml_sparsify(dg, 8, 10, [0.5] * 3, levels=3, n_min=0, store="f64")
     assert kept == 0 and depth == 0
     # a graph below n_min is one SparsifyB level
     g = G.clusters_with_bridges(4, 8)
     dg = api.DeviceGraph.from_host(g, "cuda")
-    keep, kept, depth = api.ml_sparsify(dg, 8, 10, [0.5], seed=1, levels=4, n_min=1000, store="f64", bin_seed=2)
-    keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, [0.5], seed=1, levels=4, n_min=1000, bin_seed=2)
+    keep, kept, depth = api.ml_sparsify(dg, 8, 10, [0.5] * 4, seed=1, levels=4, n_min=1000, store="f64", bin_seed=2)
+    keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, [0.5] * 4, seed=1, levels=4, n_min=1000, bin_seed=2)
     assert depth == depth_o == 0 and kept == kept_o
     np.testing.assert_array_equal(_np(keep), keep_o)
     # n_min = 0 coarsens a small graph until the 90% rule or the level cap stops it
-    keep, kept, depth = api.ml_sparsify(dg, 8, 10, [0.5], seed=1, levels=6, n_min=0, store="f64", bin_seed=2)
-    keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, [0.5], seed=1, levels=6, n_min=0, bin_seed=2)
+    keep, kept, depth = api.ml_sparsify(dg, 8, 10, [0.5] * 6, seed=1, levels=6, n_min=0, store="f64", bin_seed=2)
+    keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, [0.5] * 6, seed=1, levels=6, n_min=0, bin_seed=2)
     assert depth == depth_o and kept == kept_o
     np.testing.assert_array_equal(_np(keep), keep_o)
 
@@ -178,7 +184,7 @@ def test_ratio_vector_variants_match_oracle(api, variant):
     elif variant.startswith("span"):
         kw.update(span=1, segment=["span_coarsest", "span_middle", "span_finest"].index(variant), span_value=0.4)
     else:
-        kw.update(e_levels=[-1])
+        kw.update(e_levels=[-1] * 4)
     keep, kept, depth = api.ml_sparsify(dg, 8, 10, store="f64", **kw)
     keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, **kw)
     print(f"{variant}: kept {kept} of {g.m}, depth {depth}")
@@ -206,7 +212,7 @@ def test_degenerate_graphs_match_oracle(api, shape):
         u, v = np.triu_indices(12, 1)
         g = G.from_edges(12, u, v)
     dg = api.DeviceGraph.from_host(g, "cuda")
-    for e in ([0.5], [0.0], [-1.0, 0.7]):
+    for e in ([0.5] * 5, [0.0] * 5, [-1.0, 0.7, 0.7, 0.7, 0.7]):
         keep, kept, depth = api.ml_sparsify(dg, 8, 10, e, seed=2, levels=5, n_min=0, store="f64", bin_seed=3)
         keep_o, kept_o, depth_o = oracle.ml_sparsify(g, 8, 10, e, seed=2, levels=5, n_min=0, bin_seed=3)
         assert depth == depth_o and kept == kept_o, (shape, e)

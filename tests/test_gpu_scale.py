@@ -2,25 +2,26 @@
 benchmark times (same graphs, seeds and options, see
 paper_1601_05527_amd.workloads).
 
-  Chung-Lu n = 2^20, 16M edges, FP32: every distance against the FP64
-      oracle (1e-5 relative, or the edge's FP32 conditioning bound where
-      that is larger, gpu_helpers.fp32_tolerance); the fit on the oracle's distances equal to the oracle's
-      bisection bit for bit; the end-to-end kept set near-cut equal; the
-      selection with binning (fixed e and fitted) equal to the oracle's; the
-      graph as drawn ingested on the device equal to the oracle's ingest;
-      the sparsified subgraph and both graphs' component labels equal the
-      oracle's (triangle counts are checked at 30,000 vertices: the
-      oracle's pairwise count is quadratic in the hub degrees).
-  Batch of 512 Chung-Lu graphs, FP32: every graph's kept set equal to the
-      oracle's selection on the batch's distances, every graph's outputs
-      equal to a standalone run bit for bit, distances of sampled graphs
-      against the oracle.
-  R-MAT n = 2^24, 2^28 edges, BF16 storage: sampled test vectors (the
-      oracle relaxes one vector at a time) against the oracle; every kept
-      set equal to the oracle's selection on the same distances; the fitted
-      exponent is the bisection's end point (retention at e meets the
-      target, at e - 2^-40 it does not); distances of sampled edges equal to
-      their definition from the kernel's own rescaled vectors.
+  Chung-Lu n = 2^20, 16M edges, FP32 storage with the last three sweeps in
+      FP64 (workloads.FP64_TAIL): every distance within 1e-5 (relative) of the FP64 oracle's; the
+      counts beyond 1e-5 of the pure FP32 forms (no FP64 tail; also one
+      shift for the whole graph) are printed; the fit on the oracle's
+      distances equal to the oracle's bisection bit for bit; the end-to-end
+      kept set near-cut equal; the selection with binning (fixed e and
+      fitted) equal to the oracle's; the graph as drawn ingested on the
+      device equal to the oracle's ingest; the sparsified subgraph and both
+      graphs' component labels equal the oracle's.
+  Batch of 512 Chung-Lu graphs, FP32 with the FP64 tail: every distance of
+      every graph within 1e-5 of the oracle's; every graph's kept set equal
+      to the oracle's selection on the batch's distances and near-cut equal
+      to the oracle's selection on its own; every graph's outputs equal to a
+      standalone run bit for bit.
+  R-MAT n = 2^24, 2^28 edges: the oracle relaxes all 16 vectors; every
+      distance of the FP32 path within 1e-5 and of the BF16 path within 2e-2
+      of the oracle's; both orientations' kept sets at the fitted exponent
+      near-cut equal to the oracle's kept sets from its own distances; the
+      kept sets equal the oracle's selection on the same distances; the
+      fitted exponent is the bisection's end point.
 """
 import time
 
@@ -31,7 +32,7 @@ import oracle
 from paper_1601_05527_amd import graphs as G
 from paper_1601_05527_amd import workloads as W
 
-from gpu_helpers import announce, check_fp32, near_cut_mismatches, rel_stats
+from gpu_helpers import announce, near_cut_mismatches, rel_stats
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -51,6 +52,13 @@ def _log(msg):
     print(f"[fullsize] {time.strftime('%H:%M:%S')} {msg}", flush=True)
 
 
+def _report(name, got, want, tol):
+    st = rel_stats(got, want)
+    n_over = int((st["rel"] > tol).sum())
+    _log(f"{name}: max rel {st['max']:.3e} p99.9 {st['p999']:.3e}, {n_over} of {len(want)} beyond {tol:g}")
+    return st, n_over
+
+
 @pytest.mark.timeout(900)
 def test_full_chung_lu(api):
     announce("full size Chung-Lu n=2^20 m=16M FP32")
@@ -58,16 +66,17 @@ def test_full_chung_lu(api):
     _, g = W.chung_lu_graph("degree")
     _log(f"graph n={g.n} m={g.m} d_max={g.d_max}")
     dg = api.DeviceGraph.from_host(g, "cuda", keep_host=False)
-    res = api.relax(dg, c["R"], c["k"], W.OMEGA, c["seed_vec"])
-    rho = api.edge_dist(dg, res.x, res.minmax)
+    res = api.relax(dg, c["R"], c["k"], W.OMEGA, c["seed_vec"], fp64_tail=W.FP64_TAIL)
+    rho = api.distances(dg, res)
     rho_g = _np(rho)
-    rho_o, xk_o, _, mm_o = oracle.algebraic_distance(g, c["R"], c["k"], W.OMEGA, seed=c["seed_vec"],
-                                                     want_vectors=True)
-    x0 = oracle.start_vectors(g.n, c["R"], c["seed_vec"], 0, g.orig_id)
-    ratio, st = check_fp32(g, x0, xk_o, mm_o, rho_g, rho_o, c["k"])
-    _log(f"rho: {st}, worst error / bound {ratio:.3f}")
-    assert ratio <= 1.0
-    del xk_o, x0
+    rho_o = oracle.algebraic_distance(g, c["R"], c["k"], W.OMEGA, seed=c["seed_vec"])
+    _log(f"components: {dg.comp.n_comp}")
+    st, n_over = _report("FP32 + FP64 tail", rho_g, rho_o, 1e-5)
+    for name, kw in (("FP32 only", dict()), ("FP32 only, one graph-wide shift", dict(per_component=False))):
+        r0 = api.relax(dg, c["R"], c["k"], W.OMEGA, c["seed_vec"], **kw)
+        _report(name, _np(api.distances(dg, r0)), rho_o, 1e-5)
+        del r0
+    assert n_over == 0 and st["max"] <= 1e-5
     rho32 = rho_o.astype(np.float32)
     # both orders from one ranking pass, as the benchmark step runs them
     kl, kg, nk, es = api.sparsify_fit_both(dg, torch.from_numpy(rho32).cuda(), c["target"])
@@ -80,10 +89,12 @@ def test_full_chung_lu(api):
         assert e == e_o
         assert np.array_equal(_np(keep), keep_o)
         assert int(nk[orient]) == kept_o
-        # end to end on the kernel's own distances
+        # end to end: the kernel's own distances at the oracle's exponent
         assert abs(es_g[orient] - e_o) <= 1e-2
         keep_g, _ = api.sparsify(dg, rho, orient, e_o)
-        bad = near_cut_mismatches(g, rho_o, _np(keep_g), keep_o, orient, e_o, 1e-5)
+        keep_oo, _ = oracle.sparsify(g, rho_o, orient, e_o)
+        bad = near_cut_mismatches(g, rho_o, _np(keep_g), keep_oo, orient, e_o, 1e-5)
+        _log(f"orient {orient}: {int((_np(keep_g) != keep_oo).sum())} kept flags differ, all near a cut")
         assert not bad, bad[:10]
     # selection with binning (Algorithm 4) on the same distances: fixed e and the fit
     rt = torch.from_numpy(rho32).cuda()
@@ -133,6 +144,12 @@ def test_full_chung_lu_subgraph_and_components(api):
                                            oracle._p(np.ascontiguousarray(cl)), oracle._p(comp))
         _log(f"components {pr['n_components']} oracle {nc}, C_G {pr['C_G']:.6f}")
         assert pr["n_components"] == nc and np.array_equal(_np(pr["comp"]), comp)
+        # the grouping the relaxation centres by: the same components, isolated vertices apart
+        cp = d.components()
+        live = np.diff(np.asarray(rpp)) > 0
+        assert cp.n_comp == len(np.unique(comp[live]))
+        assert np.array_equal(np.unique(comp[live], return_inverse=True)[1],
+                              np.unique(_np(cp.comp_of)[:d.n][live], return_inverse=True)[1])
 
 
 def test_full_chung_lu_multilevel(api):
@@ -152,22 +169,22 @@ def test_full_chung_lu_multilevel(api):
     _log(f"aggregates: {nc} of {g.n}")
     assert nc == nc_o and np.array_equal(_np(is_seed), seeds_o) and np.array_equal(_np(agg), agg_o)
     kw = dict(omega=W.OMEGA, seed=c["seed_vec"], levels=c["ml_levels"], n_min=c["ml_n_min"], store="f32",
-              bin_seed=c["bin_seed"])
+              bin_seed=c["bin_seed"], fp64_tail=W.FP64_TAIL)
     keep, kept, depth = api.ml_sparsify(dg, c["R"], c["k"], fit=True, span=c["ml_span"], segment=2,
                                         span_value=c["target"], **kw)
     k = _np(keep)
     _log(f"multilevel: kept {kept} of {g.m}, depth {depth}")
     assert depth >= 2 and int(k.sum()) == kept and set(np.unique(k).tolist()) <= {0, 1}
     assert 0.05 * g.m < kept < 0.6 * g.m
-    keep, kept, depth2 = api.ml_sparsify(dg, c["R"], c["k"], [-1.0], **kw)
+    keep, kept, depth2 = api.ml_sparsify(dg, c["R"], c["k"], [-1.0] * c["ml_levels"], **kw)
     assert kept == g.m and depth2 == depth
     keep, kept, depth = api.ml_sparsify(dg, c["R"], c["k"], [0.5], **dict(kw, levels=1))
-    res = api.relax(dg, c["R"], c["k"], W.OMEGA, seed=c["seed_vec"])
-    kb, nb, _ = api.sparsify_binned(dg, api.edge_dist(dg, res.x, res.minmax), c["bin_seed"], e=0.5)
+    res = api.relax(dg, c["R"], c["k"], W.OMEGA, seed=c["seed_vec"], fp64_tail=W.FP64_TAIL)
+    kb, nb, _ = api.sparsify_binned(dg, api.distances(dg, res), c["bin_seed"], e=0.5)
     assert depth == 0 and kept == int(_np(nb)[0]) and torch.equal(keep, kb)
 
 
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(1100)
 def test_full_batch(api):
     announce("full size batch of 512 Chung-Lu graphs FP32")
     b_ = W.BATCH
@@ -175,17 +192,17 @@ def test_full_batch(api):
     dgs = [api.DeviceGraph.from_tensors(d) for d in ds]
     _log(f"{len(dgs)} graphs, n={sum(d.n for d in dgs)} m={sum(d.m for d in dgs)}")
     b = api.Batch(dgs, b_["R"], b_["k"], W.OMEGA, seed=b_["seed_vec"], graph_id=b_["graph_id"],
-                  orient=api.AD_LOCAL, e=b_["e"], autotune=True)
+                  orient=api.AD_LOCAL, e=b_["e"], autotune=True, fp64_tail=W.FP64_TAIL)
     b.run()
     rho, keep, n_kept, mm = [_np(t) for t in b.fetch()]
     _log(f"batch done, rows_per_wave {b.rows_per_wave}")
-    order = np.argsort([d.n for d in dgs])
-    sampled = set(order[np.linspace(0, len(dgs) - 1, 8).astype(int)].tolist())
+    worst, over, flips = 0.0, 0, 0
+    oracle.set_threads(16)
     for q, (d, dg) in enumerate(zip(ds, dgs)):
         e0, e1 = b.edge_off[q], b.edge_off[q + 1]
         res = api.relax(dg, b_["R"], b_["k"], W.OMEGA, seed=b_["seed_vec"], graph_id=b_["graph_id"] + q,
-                        rows_per_wave=b.rows_per_wave)
-        rho_s = api.edge_dist(dg, res.x, res.minmax)
+                        rows_per_wave=b.rows_per_wave, fp64_tail=W.FP64_TAIL)
+        rho_s = api.distances(dg, res)
         keep_s, nk_s = api.sparsify(dg, rho_s, api.AD_LOCAL, b_["e"])
         assert np.array_equal(rho[e0:e1], _np(rho_s)), q
         assert np.array_equal(keep[e0:e1], _np(keep_s)), q
@@ -195,54 +212,52 @@ def test_full_batch(api):
         keep_o, kept_o = oracle.sparsify(g, rho[e0:e1].astype(np.float64), api.AD_LOCAL, b_["e"])
         assert np.array_equal(keep[e0:e1], keep_o), q
         assert int(n_kept[q]) == kept_o, q
-        if q in sampled:
-            rho_o, xk_o, _, mm_o = oracle.algebraic_distance(g, b_["R"], b_["k"], W.OMEGA, seed=b_["seed_vec"],
-                                                             graph_id=b_["graph_id"] + q, want_vectors=True)
-            x0 = oracle.start_vectors(g.n, b_["R"], b_["seed_vec"], b_["graph_id"] + q, g.orig_id)
-            ratio, st = check_fp32(g, x0, xk_o, mm_o, rho[e0:e1], rho_o, b_["k"])
-            _log(f"graph {q}: n={g.n} m={g.m} rho {st}, worst error / bound {ratio:.3f}")
-            assert ratio <= 1.0, q
+        rho_o = oracle.algebraic_distance(g, b_["R"], b_["k"], W.OMEGA, seed=b_["seed_vec"],
+                                          graph_id=b_["graph_id"] + q)
+        st = rel_stats(rho[e0:e1], rho_o)
+        worst = max(worst, st["max"])
+        over += int((st["rel"] > 1e-5).sum())
+        keep_oo, _ = oracle.sparsify(g, rho_o, api.AD_LOCAL, b_["e"])
+        flips += int((keep[e0:e1] != keep_oo).sum())
+        assert not near_cut_mismatches(g, rho_o, keep[e0:e1], keep_oo, api.AD_LOCAL, b_["e"], 1e-5), q
+        if q % 64 == 0:
+            _log(f"graph {q}: n={g.n} m={g.m} max rel so far {worst:.3e}")
+    _log(f"batch: every graph, every edge: max rel {worst:.3e}, {over} edges beyond 1e-5; "
+         f"{flips} kept flags differ from the oracle's selection, all near a cut")
+    assert over == 0 and worst <= 1e-5
     b.close()
 
 
-@pytest.mark.timeout(900)
-def test_full_rmat_bf16(api):
-    announce("full size R-MAT n=2^24 m=2^28 BF16 storage")
+@pytest.mark.timeout(1100)
+def test_full_rmat(api):
+    announce("full size R-MAT n=2^24 m=2^28 FP32 and BF16 storage")
     c = W.RMAT
     R, k = c["R"], c["k"]
     d = W.rmat_graph("cuda")
     dg = api.DeviceGraph.from_tensors(d)
     _log(f"graph n={dg.n} m={dg.m} d_max={dg.d_max}")
-    res = api.relax(dg, R, k, W.OMEGA, c["seed_vec"], store="bf16", fp32_tail=c["fp32_tail"])
-    rho = api.edge_dist(dg, res.x, res.minmax)
+    res = api.relax(dg, R, k, W.OMEGA, c["seed_vec"], fp64_tail=W.FP64_TAIL)
+    rho32 = _np(api.distances(dg, res))
+    del res
+    res = api.relax(dg, R, k, W.OMEGA, c["seed_vec"], store="bf16", fp32_tail=c["fp32_tail"],
+                    fp64_tail=c["fp64_tail"])
+    rho = api.distances(dg, res)
+    del res
     torch.cuda.synchronize()
+    _log(f"components: {dg.comp.n_comp}")
     g = G.device_to_host(d)
     del d
     rho_g = _np(rho)
-    x = _np(res.x)
-    mm = _np(res.minmax)
-    live = np.diff(g.row_ptr) > 0
-    lo, hi = mm[:R], mm[R:]
-    # (1) sampled test vectors: the oracle relaxes vector r from the same start values
-    x0 = oracle.start_vectors(g.n, R, c["seed_vec"], 0, g.orig_id)
-    for r in (0, R - 1):
-        xk = oracle.relax_vector(g, np.ascontiguousarray(x0[:, r]), k, W.OMEGA)
-        xh_o, _, _ = oracle.rescale_vector(g, xk)
-        xh_g = (x[:, r].astype(np.float64) - lo[r]) / (hi[r] - lo[r]) - 0.5
-        err = np.abs(xh_g - xh_o)[live]
-        _log(f"vector {r}: rescaled value abs err max {err.max():.3e} p99 {np.quantile(err, 0.99):.3e}")
-        assert err.max() <= 2e-2
-    del x0
-    # (2) sampled distances equal their definition from the kernel's own vectors (FP32 arithmetic)
-    rng = np.random.default_rng(0)
-    es = rng.choice(g.m, size=1 << 20, replace=False)
-    xh = (x.astype(np.float64) - lo) / (hi - lo) - 0.5
-    want = np.sqrt(((xh[g.edge_u[es]] - xh[g.edge_v[es]]) ** 2).sum(axis=1))
-    st = rel_stats(rho_g[es], want, 1e-6)
-    _log(f"distance definition max rel {st['max']:.3e}")
-    assert st["max"] <= 1e-5
-    del xh, x
-    # (3) selection: kept sets equal the oracle's on the same distances; the fit is the bisection's end point
+    oracle.set_threads(16)
+    rho_o = oracle.algebraic_distance(g, R, k, W.OMEGA, seed=c["seed_vec"])
+    _log("oracle done")
+    st32, over32 = _report("FP32 + FP64 tail", rho32, rho_o, 1e-5)
+    st16, over16 = _report("BF16", rho_g, rho_o, 2e-2)
+    assert over32 == 0 and st32["max"] <= 1e-5
+    assert over16 == 0 and st16["max"] <= 2e-2
+    del rho32
+    # selection: kept sets equal the oracle's selection on the same distances,
+    # and near-cut equal to the oracle's kept sets from its own distances
     rho64 = rho_g.astype(np.float64)
     kl, kg, nk, es = api.sparsify_fit_both(dg, rho, c["target"])
     nk = _np(nk)
@@ -257,3 +272,8 @@ def test_full_rmat_bf16(api):
         if e > 0.0:
             _, kept_lo = oracle.sparsify(g, rho64, orient, e - 2.0 ** -40)
             assert kept_lo / g.m < c["target"]
+        keep_oo, _ = oracle.sparsify(g, rho_o, orient, e)
+        bad = near_cut_mismatches(g, rho_o, keep_o, keep_oo, orient, e, 2e-2)
+        _log(f"orient {orient}: {int((keep_o != keep_oo).sum())} kept flags differ from the oracle's own, "
+             f"{len(bad)} not near a cut")
+        assert not bad, bad[:10]

@@ -363,6 +363,44 @@ def test_gradient_matches_central_differences():
     assert err < 1e-6, err
 
 
+def test_gradient_matches_central_differences_16x16():
+    """The differentiation workload's own pin: on the 16 x 16 copy of the
+    grid (480 grid edges + 2 long-range, lognormal weights), R = 8, k = 20,
+    the oracle's reverse-mode gradient of sum_e c_e rho_e equals central
+    differences of an independent dense FP64 forward, h = 1e-6 w_e, on
+    every edge."""
+    g = G.grid_long_range(16, 2, seed=0)
+    assert g.m == 482
+    R, k, seed = 8, 20, 1
+    c = np.random.default_rng(10).normal(size=g.m)
+    ew = g.edge_w.astype(np.float64)
+    x0 = oracle.start_vectors(g.n, R, seed, 0, g.orig_id)
+    grad = oracle.grad_weights(g, c, R, k, OMEGA, x0=x0)
+    n = g.n
+
+    def loss(wv):
+        W = np.zeros((n, n))
+        W[g.edge_u, g.edge_v] = wv
+        W[g.edge_v, g.edge_u] = wv
+        s = W.sum(axis=1)
+        x = x0.copy()
+        for _ in range(k):
+            x = (1 - OMEGA) * x + OMEGA * (W @ x) / s[:, None]
+        xh = (x - x.min(axis=0)) / (x.max(axis=0) - x.min(axis=0)) - 0.5
+        return float(c @ np.sqrt(((xh[g.edge_u] - xh[g.edge_v]) ** 2).sum(axis=1)))
+
+    fd = np.zeros(g.m)
+    for q in range(g.m):
+        h = 1e-6 * ew[q]
+        wp = ew.copy(); wp[q] += h
+        wm = ew.copy(); wm[q] -= h
+        fd[q] = (loss(wp) - loss(wm)) / (2 * h)
+    err = np.linalg.norm(grad - fd) / np.linalg.norm(fd)
+    per = np.abs(grad - fd) / (np.abs(fd) + 1e-3 * np.abs(fd).max())
+    assert err < 1e-6, err
+    assert per.max() < 1e-5, per.max()
+
+
 def test_gradient_matches_torch_autograd():
     torch = pytest.importorskip("torch")
     g = G.grid_long_range(16, 2, seed=0)
