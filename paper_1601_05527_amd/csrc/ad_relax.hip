@@ -436,10 +436,17 @@ __device__ __forceinline__ EntryLane entry_lane(long long e, int lane, int C, in
     return q;
 }
 
+// Registers a gathered value is held in until it is used: its stored type,
+// except BF16, which is widened on load.
+template <typename T> struct held_of { typedef T type; };
+template <> struct held_of<bf16> { typedef float type; };
+
 // Accumulate sum_j w_ij x_j over the entries p0, p0 + stride, p0 + 2 stride,
 // ... < end into acc (VEC values of one lane's chunk), in that order.  U
 // column/weight pairs are loaded first, then U gathers are issued together,
-// so each lane keeps U row reads in flight.
+// so each lane keeps U row reads in flight.  Gathered values stay in their
+// stored width until the FMA, so an FP32 row summed in FP64 holds half the
+// registers.
 template <int U, int VEC, typename Tin, typename A>
 __device__ __forceinline__ void gather_rows(const int32_t *__restrict__ col, const float *__restrict__ w,
                                             const Tin *__restrict__ xin, int64_t p0, int64_t end,
@@ -454,20 +461,21 @@ __device__ __forceinline__ void gather_rows(const int32_t *__restrict__ col, con
             jj[u] = ok ? col[q] : -1;
             ww[u] = ok ? (w ? (A)w[q] : (A)1) : (A)0;
         }
-        A v[U][VEC];
+        typedef typename held_of<Tin>::type H;
+        H v[U][VEC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (jj[u] >= 0) {
                 load_vec<VEC>(xin + (int64_t)jj[u] * R + off, v[u]);
             } else {
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) v[u][q] = (A)0;
+                for (int q = 0; q < VEC; ++q) v[u][q] = (H)0;
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) acc[q] = fma(ww[u], v[u][q], acc[q]);
+            for (int q = 0; q < VEC; ++q) acc[q] = fma(ww[u], (A)v[u][q], acc[q]);
         }
     }
 }
@@ -548,12 +556,13 @@ __device__ __forceinline__ long long lane_word(long long v, int i) {
     return (long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned int)lo);
 }
 
-// Waves per SIMD the sweep is compiled for: four for 4-byte arithmetic with
-// up to 16 bytes per lane (the FP32 and BF16 forms at R <= 16), which fits
-// the register budget of four waves without spilling; no request otherwise.
+// Waves per SIMD the sweep is compiled for: four with up to four values
+// per lane (the FP32 and BF16 forms at R <= 16, the FP64 forms with their
+// halved unroll), which fits the register budget of four waves without
+// spilling; no request otherwise.
 template <typename A, int VEC>
 constexpr int sweep_waves_per_eu() {
-    return sizeof(A) == 4 && VEC <= 4 ? 4 : 1;
+    return VEC <= 4 ? 4 : 1;
 }
 
 // One JOR sweep over all rows, in one launch.  Long rows (degree > hub_d)
@@ -1069,6 +1078,14 @@ ad_status sweep_plan_build(const ad_graph *g, SweepPlan &p, bool build_hubs, con
 
 constexpr int64_t MAX_MAIN_BLOCKS = 4096;   // static walk: persistent, waves loop over plan entries
 
+// Gathers in flight per lane: SWEEP_UNROLL, or half of it for FP64
+// arithmetic, whose accumulators and wider rows would not fit the register
+// budget of four waves per SIMD with eight.
+template <typename A, int VEC>
+constexpr int sweep_unroll() {
+    return (sizeof(A) == 8 && VEC >= 2) ? SWEEP_UNROLL / 2 : SWEEP_UNROLL;
+}
+
 template <typename Tin, typename Tout, typename A, int VEC>
 static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, const Tin *xin, Tout *xout,
                                 int R, const SweepPlan &pl, hipStream_t st, SweepDrift dr) {
@@ -1083,14 +1100,14 @@ static ad_status launch_sweep_v(const ad_graph *g, const A *inv_s, A omega, cons
         const int64_t grid = main_blocks + hub_blocks;
         if (grid <= 0) return AD_OK;
         TraceScope trace("k_sweep", st);
-        hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC, SWEEP_UNROLL, false>), dim3((unsigned)grid), dim3(BLOCK), 0,
+        hipLaunchKernelGGL((k_sweep<Tin, Tout, A, VEC, sweep_unroll<A, VEC>(), false>), dim3((unsigned)grid), dim3(BLOCK), 0,
                            st, g->n, g->row_ptr, g->col, g->w, inv_s, omega, xin, xout, R, sh.C, sh.hub_d, sh.SPRW,
                            (int)hub_blocks, pl.hub_list, pl.hub_count, pl.plan, pl.plan_count, pl.splits,
                            pl.xcd_groups, (unsigned int *)nullptr, (unsigned int *)nullptr, dr);
         AD_LAUNCH_CHECK("k_sweep");
         return AD_OK;
     }
-    auto kern = k_sweep<Tin, Tout, A, VEC, SWEEP_UNROLL, true>;
+    auto kern = k_sweep<Tin, Tout, A, VEC, sweep_unroll<A, VEC>(), true>;
     // workgroups the device holds at once (per device, found once): the queues
     // hand out all work, so a larger grid would only add idle workgroups
     static std::atomic<int> resident[MAX_DEVICES];

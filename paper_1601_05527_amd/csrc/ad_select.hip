@@ -1354,7 +1354,9 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
     sweep_plan_carve(c, g->n, sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE), pl);
     if (!c.ok()) return fail(AD_ERR_WORKSPACE, "workspace too small");
     if (g->n <= 0 || g->m <= 0) return AD_OK;
-    pl.sh = dist_shape(R, x_dtype, g->d_max);
+    // FP64 vectors with FP32 distances (the FP64 tail of FP32 storage) take
+    // the FP32 lane layout: four values, 32 bytes, per lane
+    pl.sh = dist_shape(R, (x_dtype == AD_F64 && rho_dtype == AD_F32) ? AD_F32 : x_dtype, g->d_max);
     const bool hubs = g->d_max > DIST_HUB;
     ad_status s = sweep_plan_build(g, pl, hubs, sg, stream);
     if (s != AD_OK) return s;
@@ -1377,7 +1379,8 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
         else AD_DIST(double, double, 1);
     } else if (x_dtype == AD_F64) {
         // FP64 vectors (the FP64 tail of FP32 storage), FP64 arithmetic, FP32 rho
-        if (pl.sh.vec == 2) AD_DIST(double, float, 2);
+        if (pl.sh.vec == 4) AD_DIST(double, float, 4);
+        else if (pl.sh.vec == 2) AD_DIST(double, float, 2);
         else AD_DIST(double, float, 1);
     } else {
         if (pl.sh.vec == 4) AD_DIST(float, float, 4);

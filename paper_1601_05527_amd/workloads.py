@@ -19,8 +19,8 @@ None of the method's arithmetic lives here: these are input recipes only
              LOCAL selection at e = 0.5, one captured launch sequence.
   RMAT       R-MAT (a, b, c, d) = (.57, .19, .19, .05), n = 2^24, 2^28
              edges, uniform(0.5, 2) weights; R = 16, k = 30; BF16 storage of
-             the test vectors with FP32 arithmetic, the last 8 sweeps stored
-             wider (7 in FP32, the last in FP64), beside the FP32 path.
+             the test vectors with FP32 arithmetic, the last 12 sweeps stored
+             wider (11 in FP32, the last in FP64), beside the FP32 path.
   GRID       512 x 512 4-neighbour grid plus 0.5% extra random long-range
              edges, lognormal weights; R = 8, k = 20, FP32; gradient of
              sum_e c_e rho_e with c_e ~ N(0, 1), checkpoints every 5 sweeps.
@@ -40,7 +40,7 @@ CHUNG_LU = dict(n=1 << 20, m=16_000_000, gamma=2.1, seed=2024, R=16, k=20, seed_
                 bin_seed=17, ml_levels=9, ml_n_min=1000, ml_span=3)
 BATCH = dict(G=512, n_lo=1e3, n_hi=2e5, deg_lo=8.0, deg_hi=32.0, seed=3, R=8, k=20, seed_vec=7,
              graph_id=0, e=0.5)
-RMAT = dict(scale=24, m=1 << 28, seed=11, R=16, k=30, seed_vec=5, fp32_tail=8, fp64_tail=1, target=0.3)
+RMAT = dict(scale=24, m=1 << 28, seed=11, R=16, k=30, seed_vec=5, fp32_tail=12, fp64_tail=1, target=0.3)
 GRID = dict(side=512, long_frac=0.005, seed=13, R=8, k=20, seed_vec=1, ckpt_every=5)
 GNM = dict(n=2000, m=10_000, seed=0, R=10, k=20, seed_vec=0, e=0.5)
 

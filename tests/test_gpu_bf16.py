@@ -1,10 +1,11 @@
 """BF16 storage of the test vectors (FP32 arithmetic, FP32 degree
 normalisation and distances) against the FP64 oracle.
 
-Bound: 2e-2 relative on every edge's rho.  Sweeps 1 .. k-8 are stored in
-BF16, the next 7 in FP32 and the last one in FP64 (TAIL = 8 counts every
-sweep stored wider than BF16; the FP64 sweep divides by s_i, which keeps the
-exact zeros of two-vertex components).  Each connected component is centred
+Bound: 2e-2 relative on every edge's rho.  Sweeps 1 .. k-TAIL are stored
+in BF16, the next TAIL-1 in FP32 and the last one in FP64 (TAIL, the
+R-MAT workload's setting, counts every sweep stored wider than BF16; the
+FP64 sweep divides by s_i, which keeps the exact zeros of two-vertex
+components).  Each connected component is centred
 by its own weighted mean, and before every BF16 sweep by its current one:
 BF16 rounding moves a component's mean by about 2^-9 of its values per
 sweep, and without the re-centring a small component's tiny differences
@@ -16,7 +17,7 @@ import pytest
 
 import oracle
 from paper_1601_05527_amd import graphs as G
-from paper_1601_05527_amd.workloads import FP64_TAIL
+from paper_1601_05527_amd.workloads import FP64_TAIL, RMAT
 
 from gpu_helpers import announce, near_cut_mismatches, rel_stats
 
@@ -24,8 +25,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 TOL = 2e-2
-TAIL = 8          # sweeps stored wider than BF16 at the end of the relaxation
-TAIL64 = 1        # of those, the last ones stored in FP64
+TAIL = RMAT["fp32_tail"]       # sweeps stored wider than BF16 at the end of the relaxation
+TAIL64 = RMAT["fp64_tail"]     # of those, the last ones stored in FP64
 
 
 @pytest.fixture(scope="module")
@@ -81,7 +82,7 @@ def test_bf16_distances_against_oracle(api, kind):
 @pytest.mark.parametrize("tail", [1, 2, 4, 8, 12])
 def test_bf16_fp32_tail(api, tail):
     """Every split between BF16 and wider sweeps runs; the error falls as
-    the tail grows, and from 8 tail sweeps on it is within the bound on
+    the tail grows, and with the workload's tail it is within the bound on
     every edge.  Shorter tails are reported with their count of edges
     beyond the bound (the BF16 rounding noise of the last BF16 sweeps is
     not yet damped)."""

@@ -465,10 +465,11 @@ def test_vector_counts_and_sweeps(api, R, k):
     res32 = api.relax(dg, R, k, seed=9, store="f32", fp64_tail=FP64_TAIL)
     rho32 = _np(api.distances(dg, res32))
     # With one vector rho is |xhat_i - xhat_j|, which nears 0 by chance on
-    # some edges; FP32 storage resolves x_i - x_j only to its rounding on the
-    # scale of |x - mean|, so with R = 1 the FP32 values are held to 1e-5 of
-    # max(rho, 1e-2 median).  From R = 3 on every edge is held to 1e-5.
-    floor32 = 1e-2 * float(np.median(rho_o)) if R == 1 else 0.0
+    # many edges; FP32 storage resolves x_i - x_j only to its rounding on the
+    # scale of |x - mean| (after k = 7 sweeps still most of the start's
+    # spread), so with R = 1 the FP32 values are held to 1e-5 of
+    # max(rho, median / 10).  From R = 3 on every edge is held to 1e-5.
+    floor32 = 0.1 * float(np.median(rho_o)) if R == 1 else 0.0
     assert rel_stats(rho32, rho_o, floor32)["max"] <= 1e-5
 
 
