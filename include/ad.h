@@ -223,6 +223,24 @@ ad_status ad_edge_dist(const ad_graph *g, int32_t R, ad_dtype x_dtype, const voi
                        const double *minmax, ad_dtype rho_dtype, void *rho, void *ws,
                        size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and kernels as ad_edge_dist, with no workspace argument.  The
+ * distance pass's launch plan lives in a fixed device array of
+ * ad_edge_dist_noalloc_max_bytes() bytes (32 MiB), one per GPU, which
+ * exists while the library's code is loaded on that GPU (until the process
+ * ends); a graph
+ * whose plan needs more (ad_edge_dist_workspace_size, about 12 bytes per
+ * vertex: up to roughly 2.5M vertices) is refused with AD_ERR_UNSUPPORTED
+ * before any work is enqueued.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  Every call on one GPU uses that
+ * GPU's array: calls that overlap on one GPU (several streams or host
+ * threads at once) race on it and must be ordered by the caller.  Results
+ * equal ad_edge_dist's bit for bit. */
+size_t ad_edge_dist_noalloc_max_bytes(void);
+ad_status ad_edge_dist_noalloc(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
+                               const double *minmax, ad_dtype rho_dtype, void *rho, hipStream_t stream);
+
 /* ------------------------------------------------------------ selection -- */
 
 /* Host helper: the per-vertex budget of Algorithm 3 for every degree,

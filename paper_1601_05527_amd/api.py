@@ -81,6 +81,8 @@ def _load_lib():
         "ad_relax": (st, [G, O, P, P, P, P, P, P, S, P]),
         "ad_edge_dist_workspace_size": (S, [G]),
         "ad_edge_dist": (st, [G, i32, ctypes.c_int, P, P, ctypes.c_int, P, P, S, P]),
+        "ad_edge_dist_noalloc_max_bytes": (S, []),
+        "ad_edge_dist_noalloc": (st, [G, i32, ctypes.c_int, P, P, ctypes.c_int, P, P]),
         "ad_components_workspace_size": (S, [G]),
         "ad_components_build": (st, [G, P, P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i64), P, S, P]),
         "ad_budget_table": (st, [i32, f64, P]),
