@@ -36,6 +36,17 @@
  *     the device except in ad_validate_graph.
  *   - Calls that share a workspace must not overlap (same stream, or
  *     ordered by the caller).
+ *   - Library-owned state: the selection calls on FP32 distances
+ *     (ad_sparsify, ad_sparsify_fit, ad_sparsify_fit_both,
+ *     ad_sparsify_binned) rank rows longer than 64 on three helper streams
+ *     per device, of default priority, created on first use and kept until
+ *     the process ends; they are forked from the caller's stream with an
+ *     event after the call's first kernels and joined back into it with
+ *     events before the call returns, so the caller's stream orders all of
+ *     the call's work, and a per-device mutex serialises the forks of calls
+ *     made from several host threads.  Under stream capture the call stays
+ *     on the caller's stream.  The kernel trace (ad_trace_*) keeps a pool
+ *     of events per device.
  */
 #ifndef AD_H
 #define AD_H
@@ -418,6 +429,25 @@ size_t ad_spearman_workspace_size(int64_t n);
  * `stream`. */
 ad_status ad_spearman(int64_t n, const double *x, const double *y, double *rho_host, void *ws,
                       size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes for ad_compare_properties (0 when n or m >= 2^31). */
+size_t ad_compare_properties_workspace_size(const ad_graph *g);
+
+/* The comparisons of G_s = (V, {e : keep[e]}) with G that Section 6 makes
+ * and that need no external package, all on the device: out_host
+ * [AD_CMP_FIELDS] doubles, HOST:
+ *   [0] edges kept (m of G_s);
+ *   [1] C_G of G, [2] C_G of G_s (Eq. cc, as ad_graph_properties);
+ *   [3] components of G, [4] components of G_s, [5] their ratio [4] / [3];
+ *   [6] Spearman's rho of the degree sequences of G and G_s,
+ *   [7] Spearman's rho of the clustering coefficients c_i of G and G_s
+ *       (the Preliminaries' formula, tied scores at their mean rank).
+ * The properties read the structure only (weights play no part).  keep:
+ * DEVICE [m].  SYNCHRONISES `stream`.  Errors as ad_subgraph,
+ * ad_graph_properties and ad_spearman. */
+#define AD_CMP_FIELDS 8
+ad_status ad_compare_properties(const ad_graph *g, const uint8_t *keep, double *out_host, void *ws,
+                                size_t ws_bytes, hipStream_t stream);
 
 /* ----------------------------------------------------------- multilevel -- */
 

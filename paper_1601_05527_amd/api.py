@@ -84,6 +84,8 @@ def _load_lib():
         "ad_edge_dist_noalloc_max_bytes": (S, []),
         "ad_edge_dist_noalloc": (st, [G, i32, ctypes.c_int, P, P, ctypes.c_int, P, P]),
         "ad_components_workspace_size": (S, [G]),
+        "ad_compare_properties_workspace_size": (S, [G]),
+        "ad_compare_properties": (st, [G, P, P, P, S, P]),
         "ad_components_build": (st, [G, P, P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i64), P, S, P]),
         "ad_budget_table": (st, [i32, f64, P]),
         "ad_sparsify_workspace_size": (S, [G]),
@@ -748,18 +750,19 @@ def spearman(x: torch.Tensor, y: torch.Tensor) -> float:
 
 
 def compare_properties(dg: DeviceGraph, keep: torch.Tensor) -> dict:
-    """The comparisons of Section 6 that need no external package: the
-    sparsified graph's C_G and component count against the original's
-    (as ratios), and Spearman correlations of the degree and clustering
-    distributions."""
-    sg = subgraph(dg, keep, entry_ids=False)
-    po, ps = graph_properties(dg), graph_properties(sg)
-    deg_o = (dg.row_ptr[1:] - dg.row_ptr[:-1]).to(torch.float64)
-    deg_s = (sg.row_ptr[1:] - sg.row_ptr[:-1]).to(torch.float64)
-    return {"m": dg.m, "m_kept": sg.m, "C_G": po["C_G"], "C_G_sparse": ps["C_G"],
-            "components": po["n_components"], "components_sparse": ps["n_components"],
-            "comp_ratio": ps["n_components"] / max(1, po["n_components"]),
-            "degree_spearman": spearman(deg_o, deg_s), "clustering_spearman": spearman(po["c"], ps["c"])}
+    """The comparisons of Section 6 that need no external package
+    (``ad_compare_properties``): the sparsified graph's C_G and component
+    count against the original's (and their ratio), and Spearman
+    correlations of the degree and clustering distributions.  Synchronises
+    the current stream."""
+    g = dg.abi()
+    ws = _workspace(lib.ad_compare_properties_workspace_size(ctypes.byref(g)), dg.device)
+    out = (ctypes.c_double * 8)()
+    _check(lib.ad_compare_properties(ctypes.byref(g), _ptr(keep.to(torch.uint8).contiguous()),
+                                     ctypes.cast(out, ctypes.c_void_p), _ptr(ws), ws.numel(), _stream()))
+    return {"m": dg.m, "m_kept": int(out[0]), "C_G": out[1], "C_G_sparse": out[2],
+            "components": int(out[3]), "components_sparse": int(out[4]), "comp_ratio": out[5],
+            "degree_spearman": out[6], "clustering_spearman": out[7]}
 
 
 # ------------------------------------------------------------ multilevel ---

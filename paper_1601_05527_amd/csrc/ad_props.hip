@@ -889,3 +889,100 @@ extern "C" ad_status ad_spearman(int64_t n, const double *x, const double *y, do
     *rho_host = 1.0 - 6.0 * (sum4 / 4.0) / (dn * (dn * dn - 1.0));
     return AD_OK;
 }
+
+// ------------------------------------------------------------ comparison --
+
+namespace ad {
+
+// Degree of every vertex as a double (the score Spearman's formula ranks).
+__global__ void k_degree_f64(int64_t n, const int64_t *__restrict__ row_ptr, double *__restrict__ deg) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        deg[i] = (double)(row_ptr[i + 1] - row_ptr[i]);
+}
+
+struct CmpLayout {
+    int64_t *sub_row_ptr;
+    int32_t *sub_col, *sub_eid;
+    double *c_o, *c_s, *deg_o, *deg_s;
+    void *ws;                 // the largest of the subgraph, properties and Spearman workspaces
+    size_t ws_bytes;
+};
+
+static size_t cmp_layout(const ad_graph *g, void *ws, size_t ws_bytes, CmpLayout *L) {
+    Carver c(ws, ws_bytes);
+    const size_t n = (size_t)std::max<int64_t>(1, g->n), nnz = (size_t)std::max<int64_t>(1, 2 * g->m);
+    CmpLayout l;
+    l.sub_row_ptr = c.take<int64_t>(n + 1);
+    l.sub_col = c.take<int32_t>(nnz);
+    l.sub_eid = c.take<int32_t>(nnz);
+    l.c_o = c.take<double>(n);
+    l.c_s = c.take<double>(n);
+    l.deg_o = c.take<double>(n);
+    l.deg_s = c.take<double>(n);
+    ad_graph gu = *g;
+    gu.w = nullptr;
+    l.ws_bytes = std::max(sub_layout(&gu, nullptr, 0, nullptr),
+                          std::max(prop_layout(&gu, nullptr, 0, nullptr), rank_layout(g->n, nullptr, 0, nullptr)));
+    l.ws = c.take<char>(l.ws_bytes);
+    if (L) *L = l;
+    return c.ok() ? c.used : 0;
+}
+
+}  // namespace ad
+
+extern "C" size_t ad_compare_properties_workspace_size(const ad_graph *g) {
+    if (check_graph_args(g) != AD_OK || g->n >= ((int64_t)1 << 31) || g->m >= ((int64_t)1 << 31)) return 0;
+    return cmp_layout(g, nullptr, 0, nullptr);
+}
+
+extern "C" ad_status ad_compare_properties(const ad_graph *g, const uint8_t *keep, double *out_host, void *ws,
+                                           size_t ws_bytes, hipStream_t stream) {
+    ad_status s = check_graph_args(g);
+    if (s != AD_OK) return s;
+    if (!out_host) return fail(AD_ERR_INVALID_ARG, "out_host is NULL");
+    if (g->m > 0 && !keep) return fail(AD_ERR_INVALID_ARG, "keep is NULL");
+    if (g->n >= ((int64_t)1 << 31) || g->m >= ((int64_t)1 << 31))
+        return fail(AD_ERR_UNSUPPORTED, "n and m must be below 2^31");
+    s = check_ws(ws, cmp_layout(g, nullptr, 0, nullptr), ws_bytes);
+    if (s != AD_OK) return s;
+    CmpLayout L;
+    if (cmp_layout(g, ws, ws_bytes, &L) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    for (int q = 0; q < AD_CMP_FIELDS; ++q) out_host[q] = 0.0;
+    const int64_t n = g->n;
+    ad_graph go = *g;             // the properties read the structure only
+    go.w = nullptr;
+    go.col_orig = nullptr;
+    int64_t ms = 0;
+    s = ad_subgraph(&go, keep, L.sub_row_ptr, L.sub_col, nullptr, L.sub_eid, nullptr, &ms, L.ws, L.ws_bytes, stream);
+    if (s != AD_OK) return s;
+    ad_graph gs = go;
+    gs.m = ms;
+    gs.row_ptr = L.sub_row_ptr;
+    gs.col = L.sub_col;
+    gs.eid = L.sub_eid;
+    double sum_o[2] = {0.0, 0.0}, sum_s[2] = {0.0, 0.0};
+    s = ad_graph_properties(&go, nullptr, L.c_o, nullptr, sum_o, L.ws, L.ws_bytes, stream);
+    if (s != AD_OK) return s;
+    s = ad_graph_properties(&gs, nullptr, L.c_s, nullptr, sum_s, L.ws, L.ws_bytes, stream);
+    if (s != AD_OK) return s;
+    double rho_deg = 0.0, rho_c = 0.0;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_degree_f64, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, go.row_ptr, L.deg_o);
+        AD_LAUNCH_CHECK("k_degree_f64");
+        hipLaunchKernelGGL(k_degree_f64, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, gs.row_ptr, L.deg_s);
+        AD_LAUNCH_CHECK("k_degree_f64");
+        s = ad_spearman(n, L.deg_o, L.deg_s, &rho_deg, L.ws, L.ws_bytes, stream);
+        if (s != AD_OK) return s;
+        s = ad_spearman(n, L.c_o, L.c_s, &rho_c, L.ws, L.ws_bytes, stream);
+        if (s != AD_OK) return s;
+    }
+    out_host[0] = (double)ms;
+    out_host[1] = sum_o[0];
+    out_host[2] = sum_s[0];
+    out_host[3] = sum_o[1];
+    out_host[4] = sum_s[1];
+    out_host[5] = sum_o[1] > 0.0 ? sum_s[1] / sum_o[1] : 0.0;
+    out_host[6] = rho_deg;
+    out_host[7] = rho_c;
+    return AD_OK;
+}
