@@ -60,7 +60,16 @@
 extern "C" {
 #endif
 
-typedef enum {
+/* The enum types below have int32_t as their underlying type in C++ too, so
+ * that any 32-bit value a caller passes is a value of the type: an unknown
+ * one reaches the argument checks and is rejected with AD_ERR_INVALID_ARG. */
+#ifdef __cplusplus
+#define AD_ENUM_I32 : int32_t
+#else
+#define AD_ENUM_I32
+#endif
+
+typedef enum AD_ENUM_I32 {
     AD_OK = 0,
     AD_ERR_INVALID_ARG = 1,   /* a null pointer, a size or a parameter out of range  */
     AD_ERR_UNSUPPORTED = 2,   /* a valid but unimplemented combination               */
@@ -70,7 +79,7 @@ typedef enum {
     AD_ERR_INTERNAL = 6       /* an internal consistency check failed                */
 } ad_status;
 
-typedef enum { AD_F64 = 0, AD_F32 = 1, AD_BF16 = 2 } ad_dtype;
+typedef enum AD_ENUM_I32 { AD_F64 = 0, AD_F32 = 1, AD_BF16 = 2 } ad_dtype;
 
 /* Orientation of the per-vertex ranking (Algorithm 3 sorts N_i by delta in
  * ascending or descending order; Section 4 names the two uses):
@@ -79,7 +88,7 @@ typedef enum { AD_F64 = 0, AD_F32 = 1, AD_BF16 = 2 } ad_dtype;
  *   AD_GLOBAL keeps the delta-weak edges   = largest rho first
  *             ("preserve global structure").
  * Ties in rho go to the neighbour with the smaller orig_id in both. */
-typedef enum { AD_LOCAL = 0, AD_GLOBAL = 1 } ad_orient;
+typedef enum AD_ENUM_I32 { AD_LOCAL = 0, AD_GLOBAL = 1 } ad_orient;
 
 /* Symmetric CSR of an undirected simple weighted graph G = (V, E, w)
  * (Preliminaries: undirected, no self-loops, no multi-edges, w >= 0; this

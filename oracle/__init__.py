@@ -43,16 +43,22 @@ LOCAL = 0
 GLOBAL = 1
 
 
-def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` with gcc (-O2, OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call([
-            "gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-            "-Wall", "-Wextra", "-Wno-unused-parameter",
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile ``liboracle.so`` with gcc (-O2, OpenMP).  With ``sanitize``
+    compile ``liboracle_san.so`` instead: -O1 with AddressSanitizer and
+    UndefinedBehaviorSanitizer (gcc's runtimes, to be preloaded into the
+    process), no OpenMP, so that the checks see one thread's accesses."""
+    out = os.path.join(_HERE, "liboracle_san.so") if sanitize else _LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        flags = (["-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                  "-fno-sanitize-recover=undefined", "-Wno-unknown-pragmas"]
+                 if sanitize else ["-O2", "-fopenmp"])
+        subprocess.check_call(["gcc"] + flags + [
+            "-fPIC", "-shared", "-std=c11", "-Wall", "-Wextra", "-Wno-unused-parameter",
             _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -62,9 +68,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build(force=True)
-    lib = ctypes.CDLL(_LIB)
+    path = os.environ.get("ORACLE_LIBRARY")      # another build, e.g. the sanitized one
+    if not path:
+        path = _LIB
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i64, i32, u64, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
     lib.orc_philox4x64_10.argtypes = [P, P, P]

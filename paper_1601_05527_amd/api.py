@@ -18,7 +18,9 @@ import torch
 from . import graphs as _graphs
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libad.so")
+# AD_LIBRARY names another build of the library (the host-sanitized one of
+# build_lib.build_sanitized()); by default the in-tree libad.so.
+LIB_PATH = os.environ.get("AD_LIBRARY") or os.path.join(_HERE, "libad.so")
 
 AD_F64, AD_F32, AD_BF16 = 0, 1, 2
 AD_LOCAL, AD_GLOBAL = 0, 1

@@ -10,7 +10,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ad.h")
-LIB = os.path.join(ROOT, "paper_1601_05527_amd", "libad.so")
+LIB = os.environ.get("AD_LIBRARY") or os.path.join(ROOT, "paper_1601_05527_amd", "libad.so")
 
 
 def _declared():
