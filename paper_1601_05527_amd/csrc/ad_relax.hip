@@ -279,29 +279,62 @@ __global__ __launch_bounds__(BLOCK) void k_comp_partials(int R, int64_t n_comp, 
     }
 }
 
-// shift[c][r] = the weighted mean of component c rounded to the 2^-24 grid:
-// one thread per (component, vector) adds the component's chunks in order.
-__global__ void k_comp_finalize(int R, int64_t n_comp, const int64_t *__restrict__ chunk_start,
-                                const double *__restrict__ part, const double *__restrict__ part_s, int centre,
-                                double *__restrict__ shift) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n_comp * R) return;
-    const int64_t c = idx / R;
-    const int r = (int)(idx - c * R);
-    double S = 0.0, X = 0.0;
-    for (int64_t ch = chunk_start[c]; ch < chunk_start[c + 1]; ++ch) {
-        S += part_s[ch];
-        X += part[ch * R + r];
+// Sums over the chunks of component c (chunk partials part[ch][r] and
+// part_s[ch]) for one wave: lane l adds chunks c0 + l, c0 + l + 64, ... in
+// that order (eight loads in flight per lane), then a fixed shuffle tree
+// adds the lanes.  The order depends only on the component's chunk range.
+__device__ __forceinline__ void comp_chunk_sums(int64_t c0, int64_t c1, int R, int r,
+                                                const double *__restrict__ part,
+                                                const double *__restrict__ part_s, double &S, double &X) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    constexpr int B = 8;
+    double s = 0.0, x = 0.0;
+    int64_t ch = c0 + lane;
+    for (; ch + (int64_t)(B - 1) * WAVE < c1; ch += (int64_t)B * WAVE) {
+        double a[B], b[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            b[u] = part_s[ch + (int64_t)u * WAVE];
+            a[u] = part[(ch + (int64_t)u * WAVE) * R + r];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            s += b[u];
+            x += a[u];
+        }
     }
-    shift[idx] = (centre && S > 0.0) ? rint((X / S) * 16777216.0) * (1.0 / 16777216.0) : 0.0;
+    for (; ch < c1; ch += WAVE) {
+        s += part_s[ch];
+        x += part[ch * R + r];
+    }
+    S = wave_sum(s);
+    X = wave_sum(x);
+}
+
+// shift[c][r] = the weighted mean of component c rounded to the 2^-24 grid:
+// one wave per (component, vector).
+__global__ __launch_bounds__(BLOCK) void k_comp_finalize(int R, int64_t n_comp, const int64_t *__restrict__ chunk_start,
+                                                        const double *__restrict__ part,
+                                                        const double *__restrict__ part_s, int centre,
+                                                        double *__restrict__ shift) {
+    const int64_t pairs = n_comp * R;
+    for (int64_t idx = (int64_t)blockIdx.x * (BLOCK / WAVE) + (threadIdx.x >> 6); idx < pairs;
+         idx += (int64_t)gridDim.x * (BLOCK / WAVE)) {     // uniform across the wave
+        const int64_t c = idx / R;
+        const int r = (int)(idx - c * R);
+        double S, X;
+        comp_chunk_sums(chunk_start[c], chunk_start[c + 1], R, r, part, part_s, S, X);
+        if ((threadIdx.x & (WAVE - 1)) == 0)
+            shift[idx] = (centre && S > 0.0) ? rint((X / S) * 16777216.0) * (1.0 / 16777216.0) : 0.0;
+    }
 }
 
 // Current weighted mean of every component (the BF16 re-centring): one wave
 // per chunk sums s_i x_i per vector over the chunk's members as
-// k_comp_partials does; k_comp_drift then adds the chunks of each
-// component in order, keeps c = mean rounded to FP32 for the next sweep to
-// subtract, and adds c to the component's shift.
-template <typename T>
+// k_comp_partials does (G vectors per pass); k_comp_drift then adds the
+// chunks of each component as comp_chunk_sums does, keeps c = mean rounded
+// to FP32 for the next sweep to subtract, and adds c to the component's shift.
+template <typename T, int G>
 __global__ __launch_bounds__(BLOCK) void k_comp_drift_partials(int R, int64_t n_comp, int64_t n_chunks,
                                                               const int32_t *__restrict__ members,
                                                               const int64_t *__restrict__ comp_start,
@@ -319,42 +352,44 @@ __global__ __launch_bounds__(BLOCK) void k_comp_drift_partials(int R, int64_t n_
     }
     const int64_t p0 = comp_start[lo] + (ch - chunk_start[lo]) * COMP_CHUNK;
     const int64_t p1 = min(comp_start[lo + 1], p0 + COMP_CHUNK);
-    for (int q = 0; q < (R + 3) / 4; ++q) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    // G vectors per pass (G divides R), read with one load per member
+    for (int q0 = 0; q0 < R; q0 += G) {
+        double acc[G];
+#pragma unroll
+        for (int c = 0; c < G; ++c) acc[c] = 0.0;
         for (int64_t p = p0 + lane; p < p1; p += WAVE) {
             const int32_t i = members[p];
             const double s = (double)sdeg[i];
+            float v[G];
+            load_vec<G>(x + (int64_t)i * R + q0, v);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (4 * q + c >= R) break;
-                float v[1];
-                load_vec<1>(x + (int64_t)i * R + 4 * q + c, v);
-                acc[c] += s * (double)v[0];
-            }
+            for (int c = 0; c < G; ++c) acc[c] += s * (double)v[c];
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < G; ++c) {
             const double v = wave_sum(acc[c]);
-            if (lane == 0 && 4 * q + c < R) part[ch * R + 4 * q + c] = v;
+            if (lane == 0) part[ch * R + q0 + c] = v;
         }
     }
 }
 
-__global__ void k_comp_drift(int R, int64_t n_comp, const int64_t *__restrict__ chunk_start,
-                             const double *__restrict__ part, const double *__restrict__ part_s,
-                             float *__restrict__ drift, double *__restrict__ shift) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n_comp * R) return;
-    const int64_t c = idx / R;
-    const int r = (int)(idx - c * R);
-    double S = 0.0, X = 0.0;
-    for (int64_t ch = chunk_start[c]; ch < chunk_start[c + 1]; ++ch) {
-        S += part_s[ch];
-        X += part[ch * R + r];
+__global__ __launch_bounds__(BLOCK) void k_comp_drift(int R, int64_t n_comp, const int64_t *__restrict__ chunk_start,
+                                                     const double *__restrict__ part,
+                                                     const double *__restrict__ part_s, float *__restrict__ drift,
+                                                     double *__restrict__ shift) {
+    const int64_t pairs = n_comp * R;
+    for (int64_t idx = (int64_t)blockIdx.x * (BLOCK / WAVE) + (threadIdx.x >> 6); idx < pairs;
+         idx += (int64_t)gridDim.x * (BLOCK / WAVE)) {     // uniform across the wave
+        const int64_t c = idx / R;
+        const int r = (int)(idx - c * R);
+        double S, X;
+        comp_chunk_sums(chunk_start[c], chunk_start[c + 1], R, r, part, part_s, S, X);
+        if ((threadIdx.x & (WAVE - 1)) == 0) {
+            const float d = S > 0.0 ? (float)(X / S) : 0.0f;
+            drift[idx] = d;
+            shift[idx] += (double)d;
+        }
     }
-    const float d = S > 0.0 ? (float)(X / S) : 0.0f;
-    drift[idx] = d;
-    shift[idx] += (double)d;
 }
 
 // The running min / max codes of every graph start empty.
@@ -1352,7 +1387,7 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
         }
         const int64_t cr = comp->n_comp * R;
         if (cr > 0) {
-            hipLaunchKernelGGL(k_comp_finalize, dim3((unsigned)ceil_div(cr, BLOCK)), dim3(BLOCK), 0, st, R,
+            hipLaunchKernelGGL(k_comp_finalize, dim3((unsigned)std::min<int64_t>(ceil_div(cr, BLOCK / WAVE), 1 << 16)), dim3(BLOCK), 0, st, R,
                                comp->n_comp, comp->chunk_start, L.part, L.part_s, 1, shift);
             AD_LAUNCH_CHECK("k_comp_finalize");
         }
@@ -1414,12 +1449,19 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
             }
             SweepDrift dr;
             if (L.drift && dst.t == AD_BF16 && t >= 2 && comp->n_comp > 0) {
-                hipLaunchKernelGGL((k_comp_drift_partials<bf16>), dim3((unsigned)ceil_div(comp->n_chunks, BLOCK / WAVE)),
-                                   dim3(BLOCK), 0, st, R, comp->n_comp, comp->n_chunks, comp->members,
-                                   comp->comp_start, comp->chunk_start, L.sdeg, (const bf16 *)cur.p, L.part);
+                const dim3 dgrid((unsigned)ceil_div(comp->n_chunks, BLOCK / WAVE));
+#define AD_DRIFT_ARGS R, comp->n_comp, comp->n_chunks, comp->members, comp->comp_start, comp->chunk_start, L.sdeg, \
+                      (const bf16 *)cur.p, L.part
+                if (R % 8 == 0)
+                    hipLaunchKernelGGL((k_comp_drift_partials<bf16, 8>), dgrid, dim3(BLOCK), 0, st, AD_DRIFT_ARGS);
+                else if (R % 4 == 0)
+                    hipLaunchKernelGGL((k_comp_drift_partials<bf16, 4>), dgrid, dim3(BLOCK), 0, st, AD_DRIFT_ARGS);
+                else
+                    hipLaunchKernelGGL((k_comp_drift_partials<bf16, 1>), dgrid, dim3(BLOCK), 0, st, AD_DRIFT_ARGS);
+#undef AD_DRIFT_ARGS
                 AD_LAUNCH_CHECK("k_comp_drift_partials");
                 const int64_t cr = comp->n_comp * R;
-                hipLaunchKernelGGL(k_comp_drift, dim3((unsigned)ceil_div(cr, BLOCK)), dim3(BLOCK), 0, st, R,
+                hipLaunchKernelGGL(k_comp_drift, dim3((unsigned)std::min<int64_t>(ceil_div(cr, BLOCK / WAVE), 1 << 16)), dim3(BLOCK), 0, st, R,
                                    comp->n_comp, comp->chunk_start, L.part, L.part_s, L.drift, shift);
                 AD_LAUNCH_CHECK("k_comp_drift");
                 dr.c = L.drift;

@@ -11,9 +11,11 @@
 // Keys are unique inside a row, so ranks are well defined.  Rows of degree
 // <= 64 are packed several to a wave, one entry per lane, and rank by
 // counting through shuffles; rows of degree <= 512 rank by counting inside
-// one wave with 2, 4 or 8 keys per lane; rows of degree <= 8192 sort their
-// keys with a bitonic network in LDS sized to the row; longer rows count
-// against keys read from memory.
+// one wave with 2, 4 or 8 keys per lane; rows of degree <= 8192 sort in LDS,
+// one workgroup per row (a radix sort of the distance bits, or a bitonic
+// network over a caller's own 64-bit keys); longer rows are cut into
+// buckets by a sorted sample and rank inside their bucket (FP64 distances
+// above 64 count against keys read from memory).
 //
 // Selection at fixed e: entry (i, j) selects its edge when rank < budget[d_i];
 // keep[e] = 1 is written by any selecting entry (all writers store the same
@@ -34,6 +36,8 @@
 #include <algorithm>
 #include <mutex>
 #include <vector>
+
+#include <rocprim/block/block_radix_sort.hpp>
 
 namespace ad {
 
@@ -626,6 +630,98 @@ __global__ __launch_bounds__(TB) void k_rank_bitonic(
                 rank_global = (int64_t)(d - b) + (t - a);
             }
             emit_ranks(em, row, col[p], eid[p], d, t, rank_global);
+        }
+        __syncthreads();
+    }
+}
+
+// Listed rows with d <= TB * IPT (FP32 distances, no caller keys): one
+// workgroup per row sorts the row's distance bits (rho >= 0, so the bits
+// order as the values) with the entry's place in the row as payload, by a
+// block radix sort in LDS (8-bit digits, four passes).  A distance shared by
+// several entries forms a run [a, b) of the sorted row; its entries take
+// their order inside the run from the neighbour ids (distinct within a row),
+// counted against the run.  LOCAL rank = a + place in run, GLOBAL rank =
+// (d - b) + place in run, as Algorithm 3 orders the row both ways.
+template <int TB, int IPT>
+__global__ __launch_bounds__(TB) void k_rank_radix(
+    const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, Emit em) {
+    constexpr int P = TB * IPT;
+    static_assert(P <= 65536, "places are 16-bit");
+    using Sorter = rocprim::block_radix_sort<uint32_t, TB, IPT, uint16_t>;
+    __shared__ union {
+        typename Sorter::storage_type sort;
+        struct {
+            uint32_t key[P];
+            uint16_t place[P];
+        } row;
+    } sh;
+    const unsigned int nr = *count;
+    for (unsigned int h = blockIdx.x; h < nr; h += gridDim.x) {
+        const int64_t row = list[h];
+        const int64_t beg = row_ptr[row];
+        const int d = (int)(row_ptr[row + 1] - beg);
+        // striped load (item s of thread t is entry s * TB + t); places past d
+        // carry the largest key and sort last
+        int32_t e[IPT];
+        uint32_t k[IPT];
+        uint16_t v[IPT];
+#pragma unroll
+        for (int s = 0; s < IPT; ++s) {
+            const int q = s * TB + (int)threadIdx.x;
+            e[s] = q < d ? eid[beg + q] : 0;
+        }
+#pragma unroll
+        for (int s = 0; s < IPT; ++s) {
+            const int q = s * TB + (int)threadIdx.x;
+            k[s] = q < d ? __float_as_uint(rho[e[s]]) : 0xffffffffu;
+            v[s] = (uint16_t)q;
+        }
+        Sorter().sort(k, v, sh.sort);                // blocked: thread t holds sorted places t * IPT + s
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < IPT; ++s) {
+            const int q = (int)threadIdx.x * IPT + s;
+            sh.row.key[q] = k[s];
+            sh.row.place[q] = v[s];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < IPT; ++s) {
+            const int q = (int)threadIdx.x * IPT + s;
+            if (q >= d) continue;
+            const uint32_t key = k[s];
+            const int64_t p = beg + v[s];
+            const int32_t j = col[p];
+            int64_t rl = q, rg = d - 1 - q;
+            const bool tie = (q > 0 && sh.row.key[q - 1] == key) || (q + 1 < d && sh.row.key[q + 1] == key);
+            if (tie) {
+                int a = 0, hi = q;                        // first place with this key
+                while (a < hi) {
+                    const int mid = (a + hi) >> 1;
+                    if (sh.row.key[mid] < key) a = mid + 1;
+                    else hi = mid;
+                }
+                int b = q + 1;                            // first place past the run
+                hi = d;
+                while (b < hi) {
+                    const int mid = (b + hi) >> 1;
+                    if (sh.row.key[mid] <= key) b = mid + 1;
+                    else hi = mid;
+                }
+                const int32_t id = nbr_id(p, j, col_orig, orig_id);
+                int before = 0;
+                for (int r = a; r < b; ++r) {
+                    const int64_t pr = beg + sh.row.place[r];
+                    before += nbr_id(pr, col[pr], col_orig, orig_id) < id ? 1 : 0;
+                }
+                rl = a + before;
+                rg = (int64_t)(d - b) + before;
+            }
+            emit_ranks(em, row, j, eid[p], d, rl, rg);
         }
         __syncthreads();
     }
@@ -1224,20 +1320,40 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
     if (sizeof(Tr) == 4) {
         const float *rf = (const float *)rho;
 #define AD_RANK_ARGS_F g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, em
-        // the longest rows first on their streams: their latency is the tail
-        if (g->d_max > 4096)
-            hipLaunchKernelGGL((k_rank_bitonic<8192, 1024>), dim3(grid), dim3(1024), 0, cls[0], lst[6], &L.cnt[6],
-                               AD_RANK_ARGS_F);
-        if (g->d_max > 2048)
-            hipLaunchKernelGGL((k_rank_bitonic<4096, 512>), dim3(grid), dim3(512), 0, cls[1], lst[5], &L.cnt[5],
-                               AD_RANK_ARGS_F);
-        if (g->d_max > 1024)
-            hipLaunchKernelGGL((k_rank_bitonic<2048, 256>), dim3(grid), dim3(256), 0, cls[2], lst[4], &L.cnt[4],
-                               AD_RANK_ARGS_F);
-        if (g->d_max > 512)
-            hipLaunchKernelGGL((k_rank_bitonic<1024, 256>), dim3(grid), dim3(256), 0, cls[1], lst[3], &L.cnt[3],
-                               AD_RANK_ARGS_F);
-        AD_LAUNCH_CHECK("k_rank_bitonic");
+        // the longest rows first on their streams: their latency is the tail.
+        // Distance keys: radix sorts of the 32-bit distance bits; the caller's
+        // own 64-bit keys: bitonic sorts of the keys.
+        if (!keys) {
+#define AD_RANK_ARGS_R g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, em
+            if (g->d_max > 4096)
+                hipLaunchKernelGGL((k_rank_radix<512, 16>), dim3(grid), dim3(512), 0, cls[0], lst[6], &L.cnt[6],
+                                   AD_RANK_ARGS_R);
+            if (g->d_max > 2048)
+                hipLaunchKernelGGL((k_rank_radix<512, 8>), dim3(grid), dim3(512), 0, cls[1], lst[5], &L.cnt[5],
+                                   AD_RANK_ARGS_R);
+            if (g->d_max > 1024)
+                hipLaunchKernelGGL((k_rank_radix<256, 8>), dim3(grid), dim3(256), 0, cls[2], lst[4], &L.cnt[4],
+                                   AD_RANK_ARGS_R);
+            if (g->d_max > 512)
+                hipLaunchKernelGGL((k_rank_radix<256, 4>), dim3(grid), dim3(256), 0, cls[1], lst[3], &L.cnt[3],
+                                   AD_RANK_ARGS_R);
+            AD_LAUNCH_CHECK("k_rank_radix");
+#undef AD_RANK_ARGS_R
+        } else {
+            if (g->d_max > 4096)
+                hipLaunchKernelGGL((k_rank_bitonic<8192, 1024>), dim3(grid), dim3(1024), 0, cls[0], lst[6], &L.cnt[6],
+                                   AD_RANK_ARGS_F);
+            if (g->d_max > 2048)
+                hipLaunchKernelGGL((k_rank_bitonic<4096, 512>), dim3(grid), dim3(512), 0, cls[1], lst[5], &L.cnt[5],
+                                   AD_RANK_ARGS_F);
+            if (g->d_max > 1024)
+                hipLaunchKernelGGL((k_rank_bitonic<2048, 256>), dim3(grid), dim3(256), 0, cls[2], lst[4], &L.cnt[4],
+                                   AD_RANK_ARGS_F);
+            if (g->d_max > 512)
+                hipLaunchKernelGGL((k_rank_bitonic<1024, 256>), dim3(grid), dim3(256), 0, cls[1], lst[3], &L.cnt[3],
+                                   AD_RANK_ARGS_F);
+            AD_LAUNCH_CHECK("k_rank_bitonic");
+        }
         if (g->d_max > 256)
             hipLaunchKernelGGL((k_rank_wave<8>), dim3(grid), dim3(SBLOCK), 0, cls[2], lst[2], &L.cnt[2],
                                AD_RANK_ARGS_F);

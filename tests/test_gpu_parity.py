@@ -245,6 +245,41 @@ def test_selection_bit_exact_on_oracle_rho(api, mixed, prec, orient, e):
     assert int(_np(n_kept)[0]) == kept_o
 
 
+@pytest.mark.parametrize("run", ["all_equal", "two_values", "equal_pairs"])
+def test_selection_tie_runs_in_sorted_rows(api, mixed, run):
+    """Rows ranked by the in-LDS sorts (512 < d <= 8192) with long runs of
+    equal distances: every entry of the hub rows equal, two values, or
+    pairs of equal values.  Runs take the neighbour-id order in both
+    orientations; masks, counts and fitted exponents are those of the
+    oracle on the same distances."""
+    announce(f"tie runs {run}")
+    g, rho = mixed
+    rho_in = rho.astype(np.float32).copy()
+    for hub in (9, 10, 12, 13, 14, 19, 20, 21, 22, 23, 24):
+        ids = g.eid[g.row_ptr[hub]:g.row_ptr[hub + 1]]
+        if run == "all_equal":
+            rho_in[ids] = np.float32(0.375)
+        elif run == "two_values":
+            rho_in[ids] = np.where(np.arange(ids.size) % 3 == 0, np.float32(0.25), np.float32(0.5))
+        else:
+            rho_in[ids] = np.repeat(rho_in[ids[::2]], 2)[: ids.size]
+    rho_ref = rho_in.astype(np.float64)
+    dg = _dg(api, g)
+    rt = torch.from_numpy(rho_in).cuda()
+    for orient in (0, 1):
+        for e in (0.4, 0.8):
+            keep, n_kept = api.sparsify(dg, rt, orient, e)
+            keep_o, kept_o = oracle.sparsify(g, rho_ref, orient, e)
+            assert np.array_equal(_np(keep), keep_o), (orient, e)
+            assert int(_np(n_kept)[0]) == kept_o
+    kl, kg, nk, (el, eg) = api.sparsify_fit_both(dg, rt, 0.3)
+    for o, (keep, e) in enumerate([(kl, el), (kg, eg)]):
+        e_o, keep_o, kept_o = oracle.fit_exponent(g, rho_ref, o, 0.3)
+        assert e == e_o
+        assert np.array_equal(_np(keep), keep_o)
+        assert int(_np(nk)[o]) == kept_o
+
+
 def _long_row_graph():
     """Stars of degree 8193 .. 70000 over a random base graph, so that the
     rows longer than the in-LDS sort take the bucket-partition path."""
