@@ -10,12 +10,12 @@
 // (rho ascending for LOCAL, descending for GLOBAL; ties by orig_id[j]).
 // Keys are unique inside a row, so ranks are well defined.  Rows of degree
 // <= 64 are packed several to a wave, one entry per lane, and rank by
-// counting through shuffles; rows of degree <= 512 rank by counting inside
-// one wave with 2, 4 or 8 keys per lane; rows of degree <= 8192 sort in LDS,
-// one workgroup per row (a radix sort of the distance bits, or a bitonic
-// network over a caller's own 64-bit keys); longer rows are cut into
-// buckets by a sorted sample and rank inside their bucket (FP64 distances
-// above 64 count against keys read from memory).
+// counting through shuffles.  Rows of degree <= 8192 sort in LDS, one
+// workgroup per row sized to the row: a radix sort of the distance bits, or,
+// for a caller's own 64-bit keys, counting inside one wave (<= 512) and a
+// bitonic network (<= 8192).  Longer rows are cut into buckets by a sorted
+// sample and rank inside their bucket.  FP64 distances above 64 count
+// against keys read from memory.
 //
 // Selection at fixed e: entry (i, j) selects its edge when rank < budget[d_i];
 // keep[e] = 1 is written by any selecting entry (all writers store the same
@@ -45,17 +45,54 @@ constexpr int SBLOCK = 256;
 constexpr int NCLASS = 8;            // degree classes above 64 (see CLASS_LO)
 constexpr int HUB_CLASS = 7;         // FP32 rows of class >= HUB_CLASS take the bucket partition
 constexpr int SORT_CAP = 8192;       // longest FP32 row ranked in one wave or one LDS sort
-constexpr int DIST_UNROLL = 8;       // entries per slot in flight in the distance pass
+constexpr int DIST_UNROLL = 8;       // entries per slot in flight in the distance pass (FP32 vectors)
+
+// Entries per slot in flight: FP64 vectors hold twice the registers per entry.
+template <typename Tx>
+constexpr int dist_unroll() { return sizeof(Tx) == 8 ? DIST_UNROLL / 2 : DIST_UNROLL; }
 
 // ---------------------------------------------------------------- distance --
+
+// The value of a butterfly partner at distance off within rows of 16 lanes,
+// through DPP: quad permutations for off = 1 and 2 (lane ^ off), the
+// half-row mirror for 4 and the row mirror for 8.  The mirrors pair a lane
+// with a lane of the other half of its block of 2 * off lanes; after the
+// earlier butterfly steps every lane of that half holds the same partial,
+// so the sums equal those of lane ^ off.
+template <int CTRL>
+__device__ __forceinline__ float dpp_take(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_take(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+template <typename A>
+__device__ __forceinline__ A butterfly_partner(A v, int off) {
+    switch (off) {
+        case 1: return dpp_take<0xB1>(v);      // quad_perm [1, 0, 3, 2]
+        case 2: return dpp_take<0x4E>(v);      // quad_perm [2, 3, 0, 1]
+        case 4: return dpp_take<0x141>(v);     // row_half_mirror
+        case 8: return dpp_take<0x140>(v);     // row_mirror
+        default: return __shfl_xor(v, off, WAVE);
+    }
+}
 
 // Sum over the C lanes of one entry's group (lanes base .. base + C - 1):
 // a butterfly when C is a power of two, ((c0 + c1) + (c2 + c3)) ..., else
 // c0 + c1 + ... in order.  Every lane of the group gets the same value.
 template <typename A>
 __device__ __forceinline__ A group_sum(A v, int C, int base) {
+    if (C == 4) {
+        v += dpp_take<0xB1>(v);
+        return v + dpp_take<0x4E>(v);
+    }
+    if (C == 2) return v + dpp_take<0xB1>(v);
     if ((C & (C - 1)) == 0) {
-        for (int off = 1; off < C; off <<= 1) v += __shfl_xor(v, off, WAVE);
+        for (int off = 1; off < C; off <<= 1) v += butterfly_partner(v, off);
         return v;
     }
     A t = shfl(v, base);
@@ -261,7 +298,7 @@ __global__ __launch_bounds__(SBLOCK) void k_normalize(int64_t n, int64_t nnz, co
 
 // ------------------------------------------------------------------ ranking --
 
-enum { MODE_FIXED = 0, MODE_SIDES = 1 };
+enum { MODE_FIXED = 0, MODE_REC = 1, MODE_REC_L = 2, MODE_REC_G = 3 };
 
 // Original id of the neighbour of entry p (tie-break key): the per-entry
 // copy when the graph carries one, else a gather through orig_id.
@@ -270,27 +307,20 @@ __device__ __forceinline__ int32_t nbr_id(int64_t p, int32_t j, const int32_t *_
     return col_orig ? col_orig[p] : (orig_id ? orig_id[j] : j);
 }
 
-// Where ranks go.  MODE_FIXED marks keep[e] when rank < budget[d];
-// MODE_SIDES stores (d << 32 | rank) at sides[2e + (row > j)].  With `both`
-// the LOCAL rank goes to (budget, keep, sides) and the GLOBAL rank to
-// (budget2, keep2, sides2); otherwise the rank of `orient` goes to the first.
+// Where ranks go.  MODE_FIXED marks keep[e] when rank < budget[d] (with
+// `both`, the LOCAL rank against (budget, keep) and the GLOBAL rank against
+// (budget2, keep2); otherwise the rank of `orient`).  MODE_REC stores the
+// side record {d, first rank, second rank, 0} at recs[2e + (row > j)]: with
+// `both` the LOCAL and the GLOBAL rank, otherwise the rank of `orient` in
+// both places; one 16-byte store per entry.  The bucketed rows rank one
+// orientation per pass: MODE_REC_L stores {d, rank} in words 0 and 1,
+// MODE_REC_G stores d and the rank in words 0 and 2.
 struct Emit {
     int mode, orient, both;
     const int32_t *budget, *budget2;
     uint8_t *keep, *keep2;
-    unsigned long long *sides, *sides2;
+    uint4 *recs;
 };
-
-__device__ __forceinline__ void emit_one(int mode, int64_t row, int32_t j, int32_t e, int64_t d, int64_t rank,
-                                         const int32_t *__restrict__ budget, uint8_t *__restrict__ keep,
-                                         unsigned long long *__restrict__ sides) {
-    if (mode == MODE_FIXED) {
-        if (rank < budget[d]) keep[e] = 1;
-    } else {
-        sides[2 * (int64_t)e + (row > j ? 1 : 0)] =
-            ((unsigned long long)d << 32) | (unsigned long long)rank;
-    }
-}
 
 // Order-preserving 64-bit key of (rho, orig_id) for the row's order
 // (FP32 distances); the GLOBAL key is the LOCAL key with the rho half
@@ -318,12 +348,25 @@ __device__ __forceinline__ unsigned long long entry_key(const unsigned long long
 //   rank_local = lt + eqlt,   rank_global = (d - lt - eq) + eqlt.
 __device__ __forceinline__ void emit_ranks(const Emit &em, int64_t row, int32_t j, int32_t e, int64_t d,
                                            int64_t rank_local, int64_t rank_global) {
-    if (em.both) {
-        emit_one(em.mode, row, j, e, d, rank_local, em.budget, em.keep, em.sides);
-        emit_one(em.mode, row, j, e, d, rank_global, em.budget2, em.keep2, em.sides2);
+    const int64_t rank_o = em.orient == AD_LOCAL ? rank_local : rank_global;
+    if (em.mode == MODE_FIXED) {
+        if (em.both) {
+            if (rank_local < em.budget[d]) em.keep[e] = 1;
+            if (rank_global < em.budget2[d]) em.keep2[e] = 1;
+        } else if (rank_o < em.budget[d]) {
+            em.keep[e] = 1;
+        }
+        return;
+    }
+    uint4 *r = em.recs + 2 * (int64_t)e + (row > j ? 1 : 0);
+    if (em.mode == MODE_REC) {
+        *r = make_uint4((uint32_t)d, (uint32_t)(em.both ? rank_local : rank_o),
+                        (uint32_t)(em.both ? rank_global : rank_o), 0u);
+    } else if (em.mode == MODE_REC_L) {
+        *reinterpret_cast<uint2 *>(r) = make_uint2((uint32_t)d, (uint32_t)rank_o);
     } else {
-        emit_one(em.mode, row, j, e, d, em.orient == AD_LOCAL ? rank_local : rank_global, em.budget, em.keep,
-                 em.sides);
+        reinterpret_cast<uint32_t *>(r)[0] = (uint32_t)d;
+        reinterpret_cast<uint32_t *>(r)[2] = (uint32_t)rank_o;
     }
 }
 
@@ -993,33 +1036,30 @@ __global__ void k_log_table(int64_t count, double *__restrict__ logs) {
         logs[v] = v > 0 ? log((double)v) : 0.0;
 }
 
-// Estimated grid index of each edge's threshold (0: kept at every e): the
-// side (d, r) selects once d^e >= r + 1, i.e. e >= log(r + 1) / log(d).
-__device__ __forceinline__ unsigned long long side_grid(unsigned long long v, const double *__restrict__ logs) {
-    const unsigned long long d = v >> 32, r = v & 0xffffffffull;
+// Estimated grid index of a side's threshold (0: kept at every e): the side
+// (d, r) selects once d^e >= r + 1, i.e. e >= log(r + 1) / log(d).
+__device__ __forceinline__ unsigned long long side_grid(uint32_t d, uint32_t r, const double *__restrict__ logs) {
     if (r == 0 || d < 2) return 0ull;
     const double gi = ceil(logs[r + 1] / logs[d] * GRID);
     return gi <= 0.0 ? 0ull : (unsigned long long)gi;
 }
 
-// G[e] = the smaller of its two sides' grid indices, and the histogram of
-// the first radix digit of G (bits 3 * DIGIT .. 4 * DIGIT - 1).
-__global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const unsigned long long *__restrict__ sides,
-                                                    const double *__restrict__ logs,
-                                                    unsigned long long *__restrict__ G,
-                                                    unsigned int *__restrict__ hist) {
-    __shared__ unsigned int h[NBINS];
-    for (int b = threadIdx.x; b < NBINS; b += SBLOCK) h[b] = 0;
-    __syncthreads();
+// Rank of fitted orientation o in a side record: the first rank, or the
+// second when both orientations are fitted.
+__device__ __forceinline__ uint32_t rec_rank(const uint4 &v, int o) { return o == 0 ? v.y : v.z; }
+
+// Per fitted orientation (at most two): the edges' grid indices and the
+// current radix histogram.
+struct FitArrays {
+    unsigned long long *G[2];
+    unsigned int *hist[2];
+};
+
+// Histogram of a thread's sequence of bins: runs of equal bins are added at once.
+struct BinRun {
     int last = -1;
     unsigned int run = 0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const ulonglong2 ab = reinterpret_cast<const ulonglong2 *>(sides)[e];
-        const unsigned long long a = side_grid(ab.x, logs), b = side_grid(ab.y, logs);
-        const unsigned long long g = a < b ? a : b;
-        G[e] = g;
-        const int bin = (int)((g >> (3 * DIGIT)) & (NBINS - 1));
+    __device__ __forceinline__ void add(unsigned int *h, int bin) {
         if (bin == last) {
             ++run;
         } else {
@@ -1028,52 +1068,81 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const unsigned l
             run = 1;
         }
     }
-    if (run) atomicAdd(&h[last], run);
-    __syncthreads();
-    for (int b = threadIdx.x; b < NBINS; b += SBLOCK)
-        if (h[b]) atomicAdd(&hist[b], h[b]);
-}
+    __device__ __forceinline__ void flush(unsigned int *h) {
+        if (run) atomicAdd(&h[last], run);
+    }
+};
 
-// state[0] = prefix of selected digits, state[1] = rank still to skip (K-1 based).
-__global__ void k_select_init(unsigned long long *state, unsigned long long K) {
-    state[0] = 0;
-    state[1] = K;
-}
-
-__global__ __launch_bounds__(SBLOCK) void k_radix_hist(int64_t m, const unsigned long long *__restrict__ G,
-                                                      int shift, int pass,
-                                                      const unsigned long long *__restrict__ state,
-                                                      unsigned int *__restrict__ hist) {
-    __shared__ unsigned int h[NBINS];
-    for (int b = threadIdx.x; b < NBINS; b += SBLOCK) h[b] = 0;
+// G_o[e] = the smaller of edge e's two sides' grid indices, and the
+// histogram of the first radix digit of G_o (bits 3 * DIGIT .. 4 * DIGIT - 1),
+// for every fitted orientation o < nfit from one read of the side records.
+__global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const uint4 *__restrict__ recs,
+                                                    const double *__restrict__ logs, int nfit, FitArrays fa) {
+    __shared__ unsigned int h[2][NBINS];
+    for (int b = threadIdx.x; b < 2 * NBINS; b += SBLOCK) h[b / NBINS][b % NBINS] = 0;
     __syncthreads();
-    const unsigned long long prefix = state[0];
-    // runs of equal bins in one thread's sequence are added at once
-    int last = -1;
-    unsigned int run = 0;
+    BinRun run[2];
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        unsigned long long g = G[e];
-        if (pass > 0 && (g >> (shift + DIGIT)) != prefix) continue;
-        const int b = (int)((g >> shift) & (NBINS - 1));
-        if (b == last) {
-            ++run;
-        } else {
-            if (run) atomicAdd(&h[last], run);
-            last = b;
-            run = 1;
+        const uint4 a = recs[2 * e], b = recs[2 * e + 1];
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+            if (o >= nfit) break;
+            const unsigned long long ga = side_grid(a.x, rec_rank(a, o), logs);
+            const unsigned long long gb = side_grid(b.x, rec_rank(b, o), logs);
+            const unsigned long long g = ga < gb ? ga : gb;
+            fa.G[o][e] = g;
+            run[o].add(h[o], (int)((g >> (3 * DIGIT)) & (NBINS - 1)));
         }
     }
-    if (run) atomicAdd(&h[last], run);
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+        if (o < nfit) run[o].flush(h[o]);
     __syncthreads();
-    for (int b = threadIdx.x; b < NBINS; b += SBLOCK)
-        if (h[b]) atomicAdd(&hist[b], h[b]);
+    for (int o = 0; o < nfit; ++o)
+        for (int b = threadIdx.x; b < NBINS; b += SBLOCK)
+            if (h[o][b]) atomicAdd(&fa.hist[o][b], h[o][b]);
 }
 
-__global__ __launch_bounds__(SBLOCK) void k_radix_pick(const unsigned int *__restrict__ hist,
-                                                      unsigned long long *state) {
+// state[2o] = prefix of selected digits, state[2o + 1] = rank still to skip
+// (1-based inside the prefix), for o < nfit.
+__global__ void k_select_init(unsigned long long *state, unsigned long long K, int nfit) {
+    for (int o = 0; o < nfit; ++o) {
+        state[2 * o] = 0;
+        state[2 * o + 1] = K;
+    }
+}
+
+// Histogram of the next digit of G_o among the edges that match the selected
+// prefix; orientation o = blockIdx.y.
+__global__ __launch_bounds__(SBLOCK) void k_radix_hist(int64_t m, FitArrays fa, int shift, int pass,
+                                                      const unsigned long long *__restrict__ state) {
+    __shared__ unsigned int h[NBINS];
+    const int o = blockIdx.y;
+    const unsigned long long *__restrict__ G = fa.G[o];
+    for (int b = threadIdx.x; b < NBINS; b += SBLOCK) h[b] = 0;
+    __syncthreads();
+    const unsigned long long prefix = state[2 * o];
+    BinRun run;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long g = G[e];
+        if (pass > 0 && (g >> (shift + DIGIT)) != prefix) continue;
+        run.add(h, (int)((g >> shift) & (NBINS - 1)));
+    }
+    run.flush(h);
+    __syncthreads();
+    for (int b = threadIdx.x; b < NBINS; b += SBLOCK)
+        if (h[b]) atomicAdd(&fa.hist[o][b], h[b]);
+}
+
+// The bin holding the state's rank, appended to the prefix; orientation
+// o = blockIdx.x.
+__global__ __launch_bounds__(SBLOCK) void k_radix_pick(FitArrays fa, unsigned long long *state_all) {
     __shared__ unsigned long long part[SBLOCK];
     constexpr int PER = NBINS / SBLOCK;
+    const unsigned int *__restrict__ hist = fa.hist[blockIdx.x];
+    unsigned long long *state = state_all + 2 * blockIdx.x;
     unsigned long long c = 0;
     for (int q = 0; q < PER; ++q) c += hist[threadIdx.x * PER + q];
     part[threadIdx.x] = c;
@@ -1090,26 +1159,40 @@ __global__ __launch_bounds__(SBLOCK) void k_radix_pick(const unsigned int *__res
     }
 }
 
-// Exact counts at two grid points from host budget tables; keep[] for the first.
-__global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const unsigned long long *__restrict__ sides,
-                            const int32_t *__restrict__ tab_hi, const int32_t *__restrict__ tab_lo,
-                            int use_lo, uint8_t *__restrict__ keep,
-                            unsigned long long *__restrict__ counts) {
-    unsigned long long c_hi = 0, c_lo = 0;
+// The exact check of a candidate grid point per orientation: budget tables
+// from the host at the point (hi) and one grid step lower (lo).
+struct CountArgs {
+    const int32_t *tab_hi[2], *tab_lo[2];
+    int use_lo[2], active[2];
+    uint8_t *keep[2];
+};
+
+// Exact kept counts at the two grid points of every active orientation (one
+// read of the side records), and keep[] at the upper point.
+__global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__restrict__ recs, int nfit,
+                                                     CountArgs ca, unsigned long long *__restrict__ counts) {
+    unsigned long long c[2][2] = {{0, 0}, {0, 0}};
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const ulonglong2 ab = reinterpret_cast<const ulonglong2 *>(sides)[e];
-        const unsigned long long a = ab.x, b = ab.y;
-        unsigned long long da = a >> 32, ra = a & 0xffffffffull;
-        unsigned long long db = b >> 32, rb = b & 0xffffffffull;
-        bool k_hi = ra < (unsigned long long)tab_hi[da] || rb < (unsigned long long)tab_hi[db];
-        keep[e] = k_hi ? 1 : 0;
-        c_hi += k_hi;
-        if (use_lo) c_lo += (ra < (unsigned long long)tab_lo[da] || rb < (unsigned long long)tab_lo[db]);
+        const uint4 a = recs[2 * e], b = recs[2 * e + 1];
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+            if (o >= nfit || !ca.active[o]) continue;
+            const uint32_t ra = rec_rank(a, o), rb = rec_rank(b, o);
+            const bool k_hi = ra < (uint32_t)ca.tab_hi[o][a.x] || rb < (uint32_t)ca.tab_hi[o][b.x];
+            ca.keep[o][e] = k_hi ? 1 : 0;
+            c[o][0] += k_hi;
+            if (ca.use_lo[o]) c[o][1] += (ra < (uint32_t)ca.tab_lo[o][a.x] || rb < (uint32_t)ca.tab_lo[o][b.x]);
+        }
     }
-    block_add(c_hi, &counts[0]);
-    __syncthreads();
-    block_add(c_lo, &counts[1]);
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        if (o >= nfit || !ca.active[o]) continue;
+        block_add(c[o][0], &counts[2 * o]);
+        __syncthreads();
+        block_add(c[o][1], &counts[2 * o + 1]);
+        __syncthreads();
+    }
 }
 
 __global__ void k_store_count(const unsigned long long *__restrict__ c, int64_t *__restrict__ out) {
@@ -1125,10 +1208,9 @@ struct SelLayout {
     long long *plan;              // packed small-row waves
     unsigned int *tile_waves, *plan_count;
     ScanScratch scan;
-    unsigned long long *sides;    // [2m]
-    unsigned long long *sides2;   // [2m] GLOBAL sides when both orientations are fitted
-    unsigned long long *G;        // [m]
-    unsigned int *hist;           // [NBINS]
+    uint4 *recs;                  // [2m] side records (Emit, MODE_REC*)
+    unsigned long long *G, *G2;   // [m] grid indices per fitted orientation (G2 when both)
+    unsigned int *hist;           // [2][NBINS]
     unsigned long long *state;    // [4]: two words per fitted orientation
     unsigned long long *counts;   // [4]: counts at the upper and lower grid point, per orientation
     int32_t *tabs;                // [4][d_max + 1]: upper and lower budget tables, per orientation
@@ -1163,10 +1245,10 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     l.scan.blk_v = c.take<unsigned int>(nblk);
     l.scan.blk_w = c.take<unsigned long long>(nblk);
     l.scan.total_w = c.take<unsigned long long>(1);
-    l.sides = c.take<unsigned long long>(2 * m);
-    l.sides2 = both ? c.take<unsigned long long>(2 * m) : nullptr;
+    l.recs = c.take<uint4>(2 * m);
     l.G = c.take<unsigned long long>(m);
-    l.hist = c.take<unsigned int>(NBINS);
+    l.G2 = both ? c.take<unsigned long long>(m) : nullptr;
+    l.hist = c.take<unsigned int>(2 * NBINS);
     l.state = c.take<unsigned long long>(4);
     l.counts = c.take<unsigned long long>(4);
     l.tabs = c.take<int32_t>(4 * ((size_t)g->d_max + 1));
@@ -1231,7 +1313,7 @@ static void budget_table(int32_t d_max, double e, std::vector<int32_t> &t) {
 
 // Rank every entry of every row and emit per `em`.
 // Helper streams for the ranking classes.  The classes rank disjoint rows
-// (their outputs are distinct sides or set-only keep flags), and the long
+// (their outputs are distinct side records or set-only keep flags), and the long
 // classes are latency-bound (one workgroup sorts one row), so outside stream
 // capture they run beside the short rows on three more streams of the same
 // (default) priority, forked from and joined back into the caller's stream
@@ -1324,6 +1406,8 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
         // Distance keys: radix sorts of the 32-bit distance bits; the caller's
         // own 64-bit keys: bitonic sorts of the keys.
         if (!keys) {
+            // one-wave workgroups for rows up to 512: more of them in flight
+            const unsigned grid_w = (unsigned)std::min<int64_t>(8192, n);
 #define AD_RANK_ARGS_R g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, em
             if (g->d_max > 4096)
                 hipLaunchKernelGGL((k_rank_radix<512, 16>), dim3(grid), dim3(512), 0, cls[0], lst[6], &L.cnt[6],
@@ -1336,6 +1420,15 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                                    AD_RANK_ARGS_R);
             if (g->d_max > 512)
                 hipLaunchKernelGGL((k_rank_radix<256, 4>), dim3(grid), dim3(256), 0, cls[1], lst[3], &L.cnt[3],
+                                   AD_RANK_ARGS_R);
+            if (g->d_max > 256)
+                hipLaunchKernelGGL((k_rank_radix<64, 8>), dim3(grid_w), dim3(64), 0, cls[2], lst[2], &L.cnt[2],
+                                   AD_RANK_ARGS_R);
+            if (g->d_max > 128)
+                hipLaunchKernelGGL((k_rank_radix<64, 4>), dim3(grid_w), dim3(64), 0, cls[0], lst[1], &L.cnt[1],
+                                   AD_RANK_ARGS_R);
+            if (g->d_max > 64)
+                hipLaunchKernelGGL((k_rank_radix<64, 2>), dim3(grid_w), dim3(64), 0, cls[2], lst[0], &L.cnt[0],
                                    AD_RANK_ARGS_R);
             AD_LAUNCH_CHECK("k_rank_radix");
 #undef AD_RANK_ARGS_R
@@ -1353,17 +1446,17 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                 hipLaunchKernelGGL((k_rank_bitonic<1024, 256>), dim3(grid), dim3(256), 0, cls[1], lst[3], &L.cnt[3],
                                    AD_RANK_ARGS_F);
             AD_LAUNCH_CHECK("k_rank_bitonic");
+            if (g->d_max > 256)
+                hipLaunchKernelGGL((k_rank_wave<8>), dim3(grid), dim3(SBLOCK), 0, cls[2], lst[2], &L.cnt[2],
+                                   AD_RANK_ARGS_F);
+            if (g->d_max > 128)
+                hipLaunchKernelGGL((k_rank_wave<4>), dim3(grid), dim3(SBLOCK), 0, cls[0], lst[1], &L.cnt[1],
+                                   AD_RANK_ARGS_F);
+            if (g->d_max > 64)
+                hipLaunchKernelGGL((k_rank_wave<2>), dim3(grid), dim3(SBLOCK), 0, cls[2], lst[0], &L.cnt[0],
+                                   AD_RANK_ARGS_F);
+            AD_LAUNCH_CHECK("k_rank_wave");
         }
-        if (g->d_max > 256)
-            hipLaunchKernelGGL((k_rank_wave<8>), dim3(grid), dim3(SBLOCK), 0, cls[2], lst[2], &L.cnt[2],
-                               AD_RANK_ARGS_F);
-        if (g->d_max > 128)
-            hipLaunchKernelGGL((k_rank_wave<4>), dim3(grid), dim3(SBLOCK), 0, cls[0], lst[1], &L.cnt[1],
-                               AD_RANK_ARGS_F);
-        if (g->d_max > 64)
-            hipLaunchKernelGGL((k_rank_wave<2>), dim3(grid), dim3(SBLOCK), 0, cls[2], lst[0], &L.cnt[0],
-                               AD_RANK_ARGS_F);
-        AD_LAUNCH_CHECK("k_rank_wave");
         // (the bucket partition runs once per orientation, a sort serves both: sorts up to SORT_CAP)
         static_assert(HUB_CLASS == 7 && SORT_CAP == 8192, "bitonic classes end where the bucket partition starts");
 #undef AD_RANK_ARGS_F
@@ -1377,9 +1470,9 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                     if (pass == 1) {
                         one.budget = em.budget2;
                         one.keep = em.keep2;
-                        one.sides = em.sides2;
                     }
                 }
+                if (em.mode != MODE_FIXED) one.mode = (em.both && pass == 1) ? MODE_REC_G : MODE_REC_L;
                 s = fill_i32((int32_t *)L.hub.nbk, 0, 1, cls[0]);
                 if (s != AD_OK) return s;
                 for (int k = HUB_CLASS; k < NCLASS; ++k) {
@@ -1412,14 +1505,14 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
     return AD_OK;
 }
 
-static Emit emit_single(int mode, int orient, const int32_t *budget, uint8_t *keep, unsigned long long *sides) {
+static Emit emit_single(int mode, int orient, const int32_t *budget, uint8_t *keep, uint4 *recs) {
     Emit em{};
     em.mode = mode;
     em.orient = orient;
     em.both = 0;
     em.budget = budget;
     em.keep = keep;
-    em.sides = sides;
+    em.recs = recs;
     return em;
 }
 
@@ -1486,7 +1579,7 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
     const unsigned nb = (unsigned)(std::min<int64_t>(4096, ceil_div(g->n, SBLOCK / WAVE)) + hub_blocks);
     TraceScope trace("k_edge_dist", stream);
 #define AD_DIST(TX, TR, V)                                                                                   \
-    hipLaunchKernelGGL((k_edge_dist<TX, TR, V, DIST_UNROLL>), dim3(nb), dim3(SBLOCK), 0, stream, g->n,      \
+    hipLaunchKernelGGL((k_edge_dist<TX, TR, V, dist_unroll<TX>()>), dim3(nb), dim3(SBLOCK), 0, stream, g->n, \
                        g->row_ptr, g->col, g->eid, (const TX *)x, minmax, (TR *)rho, R, pl.sh.C, pl.sh.SPRW,  \
                        pl.sh.hub_d, (int)hub_blocks, hub_segs, pl.hub_list, pl.hub_count, pl.plan,            \
                        pl.plan_count, pl.splits, pl.xcd_groups, sg.row_graph)
@@ -1652,40 +1745,38 @@ static ad_status stage_reserve(size_t count) {
     return AD_OK;
 }
 
-// From ranked sides (one array per fitted orientation, nfit <= 2): the
-// per-edge threshold grid index, the radix select of the K-th smallest, and
-// the exact confirmation with budget tables (count at the grid point >= K,
-// count one grid step lower < K).  The orientations share each read-back:
-// one after the selects, one per confirmation round.  Writes keep[o], the
-// device counts n_kept[o] and the exponents.  L.logs must hold the log table.
-static ad_status fit_from_sides(const ad_graph *g, const SelLayout &L, int nfit,
-                                unsigned long long *const *sides, int64_t K, uint8_t *const *keep,
-                                int64_t *n_kept, double *e_used_host, hipStream_t stream) {
+// From the side records (nfit <= 2 fitted orientations: the first rank, and
+// the second when both are fitted): the per-edge threshold grid index, the
+// radix select of the K-th smallest, and the exact confirmation with budget
+// tables (count at the grid point >= K, count one grid step lower < K).  The
+// orientations share every launch and every read-back: one after the
+// selects, one per confirmation round.  Writes keep[o], the device counts
+// n_kept[o] and the exponents.  L.logs must hold the log table.
+static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, int64_t K, uint8_t *const *keep,
+                               int64_t *n_kept, double *e_used_host, hipStream_t stream) {
     const int64_t m = g->m;
     const size_t tl = (size_t)g->d_max + 1;
     ad_status s;
     const unsigned hist_blocks = (unsigned)std::min<int64_t>(HIST_BLOCKS, ceil_div(m, SBLOCK));
     const unsigned count_blocks = (unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, SBLOCK));
-    for (int o = 0; o < nfit; ++o) {
-        unsigned long long *state = L.state + 2 * o;
-        hipLaunchKernelGGL(k_select_init, dim3(1), dim3(1), 0, stream, state, (unsigned long long)K);
-        AD_LAUNCH_CHECK("k_select_init");
-        s = fill_i32((int32_t *)L.hist, 0, NBINS, stream);
+    const FitArrays fa{{L.G, L.G2}, {L.hist, L.hist + NBINS}};
+    hipLaunchKernelGGL(k_select_init, dim3(1), dim3(1), 0, stream, L.state, (unsigned long long)K, nfit);
+    AD_LAUNCH_CHECK("k_select_init");
+    s = fill_i32((int32_t *)L.hist, 0, 2 * NBINS, stream);
+    if (s != AD_OK) return s;
+    hipLaunchKernelGGL(k_fit_grid, dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, L.recs, L.logs, nfit, fa);
+    AD_LAUNCH_CHECK("k_fit_grid");
+    hipLaunchKernelGGL(k_radix_pick, dim3(nfit), dim3(SBLOCK), 0, stream, fa, L.state);
+    AD_LAUNCH_CHECK("k_radix_pick");
+    for (int pass = 1; pass < 4; ++pass) {
+        const int shift = (3 - pass) * DIGIT;
+        s = fill_i32((int32_t *)L.hist, 0, 2 * NBINS, stream);
         if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_fit_grid, dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, sides[o], L.logs, L.G, L.hist);
-        AD_LAUNCH_CHECK("k_fit_grid");
-        hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(SBLOCK), 0, stream, L.hist, state);
+        hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks, nfit), dim3(SBLOCK), 0, stream, m, fa, shift, pass,
+                           L.state);
+        AD_LAUNCH_CHECK("k_radix_hist");
+        hipLaunchKernelGGL(k_radix_pick, dim3(nfit), dim3(SBLOCK), 0, stream, fa, L.state);
         AD_LAUNCH_CHECK("k_radix_pick");
-        for (int pass = 1; pass < 4; ++pass) {
-            const int shift = (3 - pass) * DIGIT;
-            s = fill_i32((int32_t *)L.hist, 0, NBINS, stream);
-            if (s != AD_OK) return s;
-            hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, L.G, shift, pass, state,
-                               L.hist);
-            AD_LAUNCH_CHECK("k_radix_hist");
-            hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(SBLOCK), 0, stream, L.hist, state);
-            AD_LAUNCH_CHECK("k_radix_pick");
-        }
     }
     unsigned long long st_host[4] = {0, 0, 0, 0};
     AD_HIP(hipMemcpyAsync(st_host, L.state, sizeof(st_host), hipMemcpyDeviceToHost, stream));
@@ -1701,7 +1792,13 @@ static ad_status fit_from_sides(const ad_graph *g, const SelLayout &L, int nfit,
     std::vector<int32_t> t;
     for (int attempt = 0; attempt < 64; ++attempt) {
         // budget tables at the candidate grid point and one step below
+        CountArgs ca{};
         for (int o = 0; o < nfit; ++o) {
+            ca.tab_hi[o] = L.tabs + (2 * o) * tl;
+            ca.tab_lo[o] = L.tabs + (2 * o + 1) * tl;
+            ca.keep[o] = keep[o];
+            ca.active[o] = done[o] ? 0 : 1;
+            ca.use_lo[o] = g_try[o] > 0 ? 1 : 0;
             if (done[o]) continue;
             budget_table(g->d_max, (double)g_try[o] / GRID, t);
             std::copy(t.begin(), t.end(), g_stage + (2 * o) * tl);
@@ -1711,13 +1808,8 @@ static ad_status fit_from_sides(const ad_graph *g, const SelLayout &L, int nfit,
         AD_HIP(hipMemcpyAsync(L.tabs, g_stage, 2 * nfit * tl * sizeof(int32_t), hipMemcpyHostToDevice, stream));
         s = fill_u64(L.counts, 0, 4, stream);
         if (s != AD_OK) return s;
-        for (int o = 0; o < nfit; ++o) {
-            if (done[o]) continue;
-            hipLaunchKernelGGL(k_fit_count, dim3(count_blocks), dim3(SBLOCK), 0, stream, m, sides[o],
-                               L.tabs + (2 * o) * tl, L.tabs + (2 * o + 1) * tl, g_try[o] > 0 ? 1 : 0, keep[o],
-                               L.counts + 2 * o);
-            AD_LAUNCH_CHECK("k_fit_count");
-        }
+        hipLaunchKernelGGL(k_fit_count, dim3(count_blocks), dim3(SBLOCK), 0, stream, m, L.recs, nfit, ca, L.counts);
+        AD_LAUNCH_CHECK("k_fit_count");
         unsigned long long hc[4];
         AD_HIP(hipMemcpyAsync(hc, L.counts, sizeof(hc), hipMemcpyDeviceToHost, stream));
         AD_HIP(hipStreamSynchronize(stream));
@@ -1747,7 +1839,7 @@ static ad_status fit_from_sides(const ad_graph *g, const SelLayout &L, int nfit,
 }
 
 // Both halves of the fitted sparsify: rank (one or both orientations) into
-// sides, then the fits.
+// side records, then the fits.
 static ad_status sparsify_fit_impl(const ad_graph *g, ad_dtype rho_dtype, const void *rho, int orient, bool both,
                                    double target, uint8_t *keep, uint8_t *keep2, int64_t *n_kept,
                                    double *e_used_host, const SelLayout &L, hipStream_t stream) {
@@ -1766,11 +1858,10 @@ static ad_status sparsify_fit_impl(const ad_graph *g, ad_dtype rho_dtype, const 
         return AD_OK;
     }
     const int64_t K = fit_count_target(m, target);
-    Emit em = emit_single(MODE_SIDES, orient, nullptr, nullptr, L.sides);
+    Emit em = emit_single(MODE_REC, orient, nullptr, nullptr, L.recs);
     if (both) {
         em.orient = AD_LOCAL;
         em.both = 1;
-        em.sides2 = L.sides2;
     }
     if (rho_dtype == AD_F32)
         s = rank_all<float>(g, (const float *)rho, em, L, stream);
@@ -1781,9 +1872,8 @@ static ad_status sparsify_fit_impl(const ad_graph *g, ad_dtype rho_dtype, const 
     hipLaunchKernelGGL(k_log_table, dim3(grid_for((int64_t)g->d_max + 2, SBLOCK)), dim3(SBLOCK), 0, stream,
                        (int64_t)g->d_max + 2, L.logs);
     AD_LAUNCH_CHECK("k_log_table");
-    unsigned long long *sd[2] = {L.sides, L.sides2};
     uint8_t *kp[2] = {keep, keep2};
-    return fit_from_sides(g, L, nfit, sd, K, kp, n_kept, e_used_host, stream);
+    return fit_from_recs(g, L, nfit, K, kp, n_kept, e_used_host, stream);
 }
 
 }  // namespace ad
@@ -1969,11 +2059,10 @@ __global__ __launch_bounds__(SBLOCK) void k_bin_keys(int64_t n, BinKeys<Tr> body
     for_bin_rows(n, body.row_ptr, body);
 }
 
-// Rank in the (bin, priority) order of an entry, from the sides written by
-// the first ranking (low half of sides[2e + (i > j)]).
-__device__ __forceinline__ uint32_t side_rank(const unsigned long long *__restrict__ sides, int32_t e, int64_t i,
-                                              int32_t j) {
-    return (uint32_t)sides[2 * (int64_t)e + (i > j ? 1 : 0)];
+// Rank in the (bin, priority) order of an entry, from the side records
+// written by the first ranking (word 1 of recs[2e + (i > j)]).
+__device__ __forceinline__ uint32_t side_rank(const uint4 *__restrict__ recs, int32_t e, int64_t i, int32_t j) {
+    return recs[2 * (int64_t)e + (i > j ? 1 : 0)].y;
 }
 
 // The row in (bin, priority) order: order[beg + rank] = entry offset, and
@@ -1981,14 +2070,14 @@ __device__ __forceinline__ uint32_t side_rank(const unsigned long long *__restri
 struct BinOrder {
     const int64_t *row_ptr;
     const int32_t *col, *eid;
-    const unsigned long long *sides;
+    const uint4 *recs;
     uint32_t *order, *rank;
     template <int G>
     __device__ __forceinline__ void run(int64_t i, int lane, bool on) const {
         if (!on) return;
         const int64_t beg = row_ptr[i], d = row_ptr[i + 1] - beg;
         for (int64_t q = lane; q < d; q += G) {
-            const uint32_t r = side_rank(sides, eid[beg + q], i, col[beg + q]);
+            const uint32_t r = side_rank(recs, eid[beg + q], i, col[beg + q]);
             order[beg + r] = (uint32_t)q;
             rank[beg + q] = r;
         }
@@ -2042,7 +2131,7 @@ __global__ __launch_bounds__(SBLOCK) void k_bin_rows(int64_t n, Body body) {
 }
 
 struct BinLayout {
-    SelLayout sel;                // sides2 holds the first ranking's ranks
+    SelLayout sel;                // recs hold the first ranking's ranks, then the second's
     unsigned long long *keys;     // [2m]
     uint32_t *first_u, *first_pos;  // [2m]: per-row bin slots
     uint32_t *order, *rank;         // [2m]: the row in the first order, and each entry's rank in it
@@ -2113,13 +2202,13 @@ static ad_status sparsify_binned_impl(const ad_graph *g, ad_dtype rho_dtype, con
         }
         AD_LAUNCH_CHECK("k_bin_keys");
     }
-    // first ranking: (bin, priority); ranks into sides2
-    s = rank_all<float>(g, nullptr, emit_single(MODE_SIDES, AD_LOCAL, nullptr, nullptr, L.sides2), L, stream, B.keys);
+    // first ranking: (bin, priority); ranks into the side records
+    s = rank_all<float>(g, nullptr, emit_single(MODE_REC, AD_LOCAL, nullptr, nullptr, L.recs), L, stream, B.keys);
     if (s != AD_OK) return s;
     {
         TraceScope trace("k_bin", stream);
         hipLaunchKernelGGL(k_bin_rows<BinOrder>, dim3(grid), dim3(SBLOCK), 0, stream, n,
-                           BinOrder{g->row_ptr, g->col, g->eid, L.sides2, B.order, B.rank});
+                           BinOrder{g->row_ptr, g->col, g->eid, L.recs, B.order, B.rank});
         AD_LAUNCH_CHECK("k_bin_order");
         hipLaunchKernelGGL(k_bin_rows<BinFirsts>, dim3(grid), dim3(SBLOCK), 0, stream, n,
                            BinFirsts{g->row_ptr, B.keys, B.order, B.first_u, B.first_pos});
@@ -2129,17 +2218,16 @@ static ad_status sparsify_binned_impl(const ad_graph *g, ad_dtype rho_dtype, con
         AD_LAUNCH_CHECK("k_bin_rounds");
     }
     if (target > 0.0) {
-        // second ranking (round, bin order) into sides, then the retention fit
-        s = rank_all<float>(g, nullptr, emit_single(MODE_SIDES, AD_LOCAL, nullptr, nullptr, L.sides), L, stream,
+        // second ranking (round, bin order) over the first's records, then the retention fit
+        s = rank_all<float>(g, nullptr, emit_single(MODE_REC, AD_LOCAL, nullptr, nullptr, L.recs), L, stream,
                             B.keys);
         if (s != AD_OK) return s;
         TraceScope trace_fit("k_fit_select", stream);
         hipLaunchKernelGGL(k_log_table, dim3(grid_for((int64_t)g->d_max + 2, SBLOCK)), dim3(SBLOCK), 0, stream,
                            (int64_t)g->d_max + 2, L.logs);
         AD_LAUNCH_CHECK("k_log_table");
-        unsigned long long *sd[1] = {L.sides};
         uint8_t *kp[1] = {keep};
-        return fit_from_sides(g, L, 1, sd, fit_count_target(m, target), kp, n_kept, e_used_host, stream);
+        return fit_from_recs(g, L, 1, fit_count_target(m, target), kp, n_kept, e_used_host, stream);
     }
     // second ranking straight into keep at the fixed exponent
     s = fill_u64(L.counts, 0, 1, stream);
