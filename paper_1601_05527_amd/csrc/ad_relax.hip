@@ -1030,6 +1030,7 @@ __global__ void k_minmax_out(int G, int R, const unsigned long long *__restrict_
 struct Buf {
     void *p;
     ad_dtype t;
+    bool f32 = false;     // FP64 storage holding the results of FP32 arithmetic
 };
 
 static int pick_vec(int R, size_t elem_bytes) {
@@ -1256,7 +1257,7 @@ static size_t relax_layout(const ad_graph *g, const ad_relax_opts *o, void *ws, 
     }
     if (tail64) {
         l.b64A = c.take<double>((size_t)n * R);
-        l.b64B = o->fp64_tail > 2 ? c.take<double>((size_t)n * R) : nullptr;
+        l.b64B = o->fp64_tail >= 2 ? c.take<double>((size_t)n * R) : nullptr;
     } else {
         l.b64A = l.b64B = nullptr;
     }
@@ -1314,6 +1315,17 @@ static ad_status weighted_degree_impl(const ad_graph *g, A *inv_s, float *sdeg, 
 // One sweep from cur to dst in the types they are stored in.
 static ad_status sweep_step(const ad_graph *g, const RelaxLayout &L, const RelaxLayout &P, double omega,
                             const Buf &cur, const Buf &dst, int R, hipStream_t st, SweepDrift dr) {
+    if (dst.t == AD_F64 && dst.f32) {
+        // the last sweep before the FP64 tail: FP32 arithmetic as the sweeps
+        // before it, its results stored widened, so that the tail reads FP64 rows
+        const float om = (float)omega;
+        const float *is = (const float *)L.inv_s;
+        if (cur.t == AD_F32)
+            return launch_sweep<float, double, float>(g, is, om, (const float *)cur.p, (double *)dst.p, R, P.p32, st);
+        if (cur.t == AD_BF16)
+            return launch_sweep<bf16, double, float>(g, is, om, (const bf16 *)cur.p, (double *)dst.p, R, P.p16, st);
+        return fail(AD_ERR_INTERNAL, "widened sweep from FP64");
+    }
     if (dst.t == AD_F64) {
         // FP64 arithmetic, dividing by s_i: the FP64 storage form reads its
         // divisor from inv_s, the FP64 tail of FP32 storage from s64 and runs
@@ -1440,6 +1452,8 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
                 dst = {x_out, out64 ? AD_F64 : AD_F32};
             } else if (wide && o->store != AD_F64) {
                 dst = {cur.p == L.b64A ? L.b64B : L.b64A, AD_F64};
+            } else if (tail64 > 0 && t == o->k - tail64 && o->store != AD_F64) {
+                dst = {L.b64A, AD_F64, true};
             } else if (ckpt && o->ckpt_every > 0 && t % o->ckpt_every == 0) {
                 dst = {(char *)ckpt + (size_t)(t / o->ckpt_every) * slot_elems * sizeof(T), tstore};
             } else if (o->store == AD_BF16 && t <= o->k - tail32) {

@@ -1029,18 +1029,25 @@ constexpr int DIGIT = 11;
 constexpr int NBINS = 1 << DIGIT;
 constexpr double GRID = 1099511627776.0;   // 2^40
 
-// logs[v] = log(v) for v = 1 .. d_max + 1 (logs[0] unused).
+// logs[v] = log(v) for v = 1 .. count - 1 (logs[0] unused), and
+// logs[count + v] = 1 / log(v) for v >= 2.
 __global__ void k_log_table(int64_t count, double *__restrict__ logs) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < count;
-         v += (int64_t)gridDim.x * blockDim.x)
-        logs[v] = v > 0 ? log((double)v) : 0.0;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const double l = v > 0 ? log((double)v) : 0.0;
+        logs[v] = l;
+        logs[count + v] = v > 1 ? 1.0 / l : 0.0;
+    }
 }
 
 // Estimated grid index of a side's threshold (0: kept at every e): the side
-// (d, r) selects once d^e >= r + 1, i.e. e >= log(r + 1) / log(d).
-__device__ __forceinline__ unsigned long long side_grid(uint32_t d, uint32_t r, const double *__restrict__ logs) {
+// (d, r) selects once d^e >= r + 1, i.e. e >= log(r + 1) / log(d); inv_ld =
+// 1 / log(d) from the table.  The estimate is within a small fraction of a
+// grid step of the index the exact check finds (see FIT_MARGIN).
+__device__ __forceinline__ unsigned long long side_grid(uint32_t d, uint32_t r, double inv_ld,
+                                                        const double *__restrict__ logs) {
     if (r == 0 || d < 2) return 0ull;
-    const double gi = ceil(logs[r + 1] / logs[d] * GRID);
+    const double gi = ceil(logs[r + 1] * inv_ld * GRID);
     return gi <= 0.0 ? 0ull : (unsigned long long)gi;
 }
 
@@ -1077,7 +1084,8 @@ struct BinRun {
 // histogram of the first radix digit of G_o (bits 3 * DIGIT .. 4 * DIGIT - 1),
 // for every fitted orientation o < nfit from one read of the side records.
 __global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const uint4 *__restrict__ recs,
-                                                    const double *__restrict__ logs, int nfit, FitArrays fa) {
+                                                    const double *__restrict__ logs, int64_t nlogs, int nfit,
+                                                    FitArrays fa) {
     __shared__ unsigned int h[2][NBINS];
     for (int b = threadIdx.x; b < 2 * NBINS; b += SBLOCK) h[b / NBINS][b % NBINS] = 0;
     __syncthreads();
@@ -1085,11 +1093,12 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const uint4 *__r
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
         const uint4 a = recs[2 * e], b = recs[2 * e + 1];
+        const double ia = logs[nlogs + a.x], ib = logs[nlogs + b.x];
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
             if (o >= nfit) break;
-            const unsigned long long ga = side_grid(a.x, rec_rank(a, o), logs);
-            const unsigned long long gb = side_grid(b.x, rec_rank(b, o), logs);
+            const unsigned long long ga = side_grid(a.x, rec_rank(a, o), ia, logs);
+            const unsigned long long gb = side_grid(b.x, rec_rank(b, o), ib, logs);
             const unsigned long long g = ga < gb ? ga : gb;
             fa.G[o][e] = g;
             run[o].add(h[o], (int)((g >> (3 * DIGIT)) & (NBINS - 1)));
@@ -1159,30 +1168,49 @@ __global__ __launch_bounds__(SBLOCK) void k_radix_pick(FitArrays fa, unsigned lo
     }
 }
 
-// The exact check of a candidate grid point per orientation: budget tables
-// from the host at the point (hi) and one grid step lower (lo).
+// The exact check of a candidate grid point g_hi per orientation (and of
+// g_hi - 1 when use_lo): budget tables from the host at both points.
 struct CountArgs {
     const int32_t *tab_hi[2], *tab_lo[2];
+    const unsigned long long *G[2];
+    unsigned long long g_hi[2];
     int use_lo[2], active[2];
     uint8_t *keep[2];
 };
 
-// Exact kept counts at the two grid points of every active orientation (one
-// read of the side records), and keep[] at the upper point.
+// An edge is kept at grid point p exactly when its threshold index is <= p.
+// G holds that index estimated from the log ratio in FP64, within a small
+// fraction of one grid step of the index the host's pow tables give; edges
+// whose estimate lies more than FIT_MARGIN steps from both candidate points
+// are classified by the estimate, the rest by the budget tables.
+constexpr unsigned long long FIT_MARGIN = 1ull << 16;
+
+// Exact kept counts at the two grid points of every active orientation, and
+// keep[] at the upper point.
 __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__restrict__ recs, int nfit,
                                                      CountArgs ca, unsigned long long *__restrict__ counts) {
     unsigned long long c[2][2] = {{0, 0}, {0, 0}};
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const uint4 a = recs[2 * e], b = recs[2 * e + 1];
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
             if (o >= nfit || !ca.active[o]) continue;
-            const uint32_t ra = rec_rank(a, o), rb = rec_rank(b, o);
-            const bool k_hi = ra < (uint32_t)ca.tab_hi[o][a.x] || rb < (uint32_t)ca.tab_hi[o][b.x];
+            const unsigned long long g = ca.G[o][e], hi = ca.g_hi[o];
+            const unsigned long long lo = hi > 0 ? hi - 1 : 0;
+            bool k_hi, k_lo;
+            if (g + FIT_MARGIN < lo) {
+                k_hi = k_lo = true;
+            } else if (g > hi + FIT_MARGIN) {
+                k_hi = k_lo = false;
+            } else {
+                const uint4 a = recs[2 * e], b = recs[2 * e + 1];
+                const uint32_t ra = rec_rank(a, o), rb = rec_rank(b, o);
+                k_hi = ra < (uint32_t)ca.tab_hi[o][a.x] || rb < (uint32_t)ca.tab_hi[o][b.x];
+                k_lo = ca.use_lo[o] && (ra < (uint32_t)ca.tab_lo[o][a.x] || rb < (uint32_t)ca.tab_lo[o][b.x]);
+            }
             ca.keep[o][e] = k_hi ? 1 : 0;
             c[o][0] += k_hi;
-            if (ca.use_lo[o]) c[o][1] += (ra < (uint32_t)ca.tab_lo[o][a.x] || rb < (uint32_t)ca.tab_lo[o][b.x]);
+            if (ca.use_lo[o]) c[o][1] += k_lo;
         }
     }
 #pragma unroll
@@ -1214,7 +1242,7 @@ struct SelLayout {
     unsigned long long *state;    // [4]: two words per fitted orientation
     unsigned long long *counts;   // [4]: counts at the upper and lower grid point, per orientation
     int32_t *tabs;                // [4][d_max + 1]: upper and lower budget tables, per orientation
-    double *logs;                 // [d_max + 2]
+    double *logs;                 // [2][d_max + 2]: log(v), then 1 / log(v)
     HubScratch hub;               // rows longer than SORT_CAP (d_max > SORT_CAP only)
 };
 
@@ -1252,7 +1280,7 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     l.state = c.take<unsigned long long>(4);
     l.counts = c.take<unsigned long long>(4);
     l.tabs = c.take<int32_t>(4 * ((size_t)g->d_max + 1));
-    l.logs = c.take<double>((size_t)g->d_max + 2);
+    l.logs = c.take<double>(2 * ((size_t)g->d_max + 2));
     l.hub = HubScratch{};
     if (g->d_max > SORT_CAP) {
         // at most 2m entries lie in long rows; a row of degree d has at most
@@ -1764,7 +1792,8 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
     AD_LAUNCH_CHECK("k_select_init");
     s = fill_i32((int32_t *)L.hist, 0, 2 * NBINS, stream);
     if (s != AD_OK) return s;
-    hipLaunchKernelGGL(k_fit_grid, dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, L.recs, L.logs, nfit, fa);
+    hipLaunchKernelGGL(k_fit_grid, dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, L.recs, L.logs,
+                       (int64_t)g->d_max + 2, nfit, fa);
     AD_LAUNCH_CHECK("k_fit_grid");
     hipLaunchKernelGGL(k_radix_pick, dim3(nfit), dim3(SBLOCK), 0, stream, fa, L.state);
     AD_LAUNCH_CHECK("k_radix_pick");
@@ -1796,6 +1825,8 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
         for (int o = 0; o < nfit; ++o) {
             ca.tab_hi[o] = L.tabs + (2 * o) * tl;
             ca.tab_lo[o] = L.tabs + (2 * o + 1) * tl;
+            ca.G[o] = o == 0 ? L.G : L.G2;
+            ca.g_hi[o] = (unsigned long long)g_try[o];
             ca.keep[o] = keep[o];
             ca.active[o] = done[o] ? 0 : 1;
             ca.use_lo[o] = g_try[o] > 0 ? 1 : 0;
