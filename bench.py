@@ -811,11 +811,9 @@ def extras(args, api, torch, dev) -> dict:
         rec["workload"] = r["config"]["workload"]
         rec["steps"] = sub.steps
         for k_ in ("uncaptured_ms_per_step", "kept", "fp32_path", "accuracy", "forward_ms", "backward_ms",
-                   "backward_over_forward", "gradient_error", "relax_dist_ms"):
+                   "backward_over_forward", "gradient_error", "relax_dist_ms", "breakdown_ms_per_step"):
             if k_ in r:
                 rec[k_] = r[k_]
-        if "fp32_path" in rec:
-            rec["fp32_path"] = {k_: v for k_, v in rec["fp32_path"].items() if k_ != "breakdown_ms_per_step"}
         rec["wall_s"] = time.perf_counter() - t0
         out[name] = rec
         log(f"{name}: {rec['ms_per_step']:.2f} ms per step ({rec['wall_s']:.0f} s with set-up)")

@@ -117,13 +117,13 @@ typedef struct {
  * caller.  Isolated vertices (no edges) belong to no component.           */
 typedef struct {
     int64_t n_comp;           /* host: components with at least one edge               */
-    int64_t n_chunks;         /* host: sum over components of ceil(size / 1024)        */
+    int64_t n_chunks;         /* host: sum over components of ceil(size / 256)         */
     const int32_t *comp_of;   /* [n] component of each vertex, -1 when isolated        */
     const int32_t *members;   /* [n_live] the non-isolated vertices, component by
                                  component (components in increasing order of their
                                  smallest vertex, vertices ascending within each)      */
     const int64_t *comp_start;/* [n_comp+1] offsets of the components in members       */
-    const int64_t *chunk_start;/* [n_comp+1] cumulative 1024-member chunks             */
+    const int64_t *chunk_start;/* [n_comp+1] cumulative 256-member chunks              */
 } ad_components;
 
 /* Parameters of Algorithm 1's relaxation. */

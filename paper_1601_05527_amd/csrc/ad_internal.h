@@ -236,7 +236,7 @@ struct Segs {
 };
 
 constexpr int CENTRE_ROWS = 1024;   // rows per centring / min-max chunk
-constexpr int64_t COMP_CHUNK = 1024; // component members per centring chunk (ad_components)
+constexpr int64_t COMP_CHUNK = 256;  // component members per centring chunk (ad_components)
 constexpr int PLAN_TILE = 64;       // rows per launch-plan tile
 
 // Shift of row i: per component (comp_of given; isolated rows 0), else the

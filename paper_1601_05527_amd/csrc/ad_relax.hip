@@ -66,7 +66,16 @@ __global__ __launch_bounds__(BLOCK) void k_weighted_degree(int64_t n, const int6
     if (e - b > hub_d) return;      // whole row group is one hub row: k_weighted_degree_hub
     double s = 0.0;
     if (w) {
-        for (int64_t p = b + lane; p < e; p += LPR) s += (double)w[p];
+        // four loads in flight per lane, added in entry order
+        int64_t p = b + lane;
+        for (; p + 3 * LPR < e; p += 4 * (int64_t)LPR) {
+            const float w0 = w[p], w1 = w[p + LPR], w2 = w[p + 2 * LPR], w3 = w[p + 3 * LPR];
+            s += (double)w0;
+            s += (double)w1;
+            s += (double)w2;
+            s += (double)w3;
+        }
+        for (; p < e; p += LPR) s += (double)w[p];
     } else if (lane == 0) {
         s = (double)(e - b);
     }
@@ -93,7 +102,15 @@ __global__ __launch_bounds__(BLOCK) void k_weighted_degree_hub(const int32_t *__
         const int64_t b = row_ptr[i], e = row_ptr[i + 1];
         double s = 0.0;
         if (w) {
-            for (int64_t p = b + threadIdx.x; p < e; p += BLOCK) s += (double)w[p];
+            int64_t p = b + threadIdx.x;
+            for (; p + 3 * BLOCK < e; p += 4 * BLOCK) {
+                const float w0 = w[p], w1 = w[p + BLOCK], w2 = w[p + 2 * BLOCK], w3 = w[p + 3 * BLOCK];
+                s += (double)w0;
+                s += (double)w1;
+                s += (double)w2;
+                s += (double)w3;
+            }
+            for (; p < e; p += BLOCK) s += (double)w[p];
         } else if (threadIdx.x == 0) {
             s = (double)(e - b);
         }
@@ -989,13 +1006,29 @@ __global__ __launch_bounds__(BLOCK) void k_minmax(int64_t n, int R, const int64_
     seg_span(sg, sg.chunk_off, n, blockIdx.x, CENTRE_ROWS, g, r0, r1);
     double lo = INFINITY, hi = -INFINITY;
     if (row_off < stride) {
-        for (int64_t i = r0 + row_off; i < r1; i += stride) {
-            if (row_ptr[i + 1] == row_ptr[i]) continue;
-            bool zero;
-            const double *sh = row_shift(shift, comp_of, i, g, R, zero);
-            double v = (double)x[i * R + r] + (zero ? 0.0 : sh[r]);
-            lo = fmin(lo, v);
-            hi = fmax(hi, v);
+        // four rows per step, their loads issued together (min and max do not
+        // depend on the order)
+        constexpr int RU = 4;
+        for (int64_t i0 = r0 + row_off; i0 < r1; i0 += (int64_t)RU * stride) {
+            double v[RU];
+            bool live[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int64_t i = i0 + (int64_t)u * stride;
+                live[u] = i < r1 && row_ptr[i + 1] != row_ptr[i];
+                v[u] = 0.0;
+                if (live[u]) {
+                    bool zero;
+                    const double *sh = row_shift(shift, comp_of, i, g, R, zero);
+                    v[u] = (double)x[i * R + r] + (zero ? 0.0 : sh[r]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!live[u]) continue;
+                lo = fmin(lo, v[u]);
+                hi = fmax(hi, v[u]);
+            }
         }
     }
     lo_l[t] = lo;

@@ -420,8 +420,31 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_packed(
         // every lane walks its own row: as many steps as the wave's longest row
         int dmax = d;
         for (int o = WAVE / 2; o >= 1; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, WAVE));
-        if constexpr (sizeof(Tr) == 4) {
-            // FP32: the row orders are those of 64-bit keys; GLOBAL flips the rho half
+        if (sizeof(Tr) == 4 && !keys) {
+            // FP32 distances: count on the 32-bit distance bits (rho >= 0, so
+            // the bits order as the values): lt = #{rho' < rho}, eq = #{rho' ==
+            // rho}; only when some row of the wave has a tie, a second pass
+            // counts the tied neighbours with smaller ids (eqlt)
+            const uint32_t mine = __float_as_uint((float)my_rho);
+            int lt = 0, eq = 0, eqlt = 0;
+            for (int t = 0; t < dmax; ++t) {
+                const uint32_t kb = (uint32_t)shfl((int)mine, min(s0 + t, WAVE - 1));
+                if (t < d) {
+                    lt += (kb < mine) ? 1 : 0;
+                    eq += (kb == mine) ? 1 : 0;
+                }
+            }
+            if (__any(on && eq > 1)) {                 // uniform across the wave
+                for (int t = 0; t < dmax; ++t) {
+                    const int src = min(s0 + t, WAVE - 1);
+                    const uint32_t kb = (uint32_t)shfl((int)mine, src);
+                    const int32_t id = shfl(my_id, src);
+                    if (t < d) eqlt += (kb == mine && id < my_id) ? 1 : 0;
+                }
+            }
+            if (on) emit_ranks(em, first + k, my_j, my_e, d, lt + eqlt, d - lt - eq + eqlt);
+        } else if constexpr (sizeof(Tr) == 4) {
+            // caller keys: the row orders are those of 64-bit keys
             const unsigned long long key =
                 keys ? (on ? keys[e] : 0ull) : sort_key((float)my_rho, my_id, em.both ? AD_LOCAL : em.orient);
             const unsigned long long keyg = key ^ KEY_FLIP;
