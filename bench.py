@@ -91,9 +91,10 @@ def cpu_model() -> str:
 
 def sweep_traffic() -> "float | None":
     """Memory-side traffic per k_sweep launch from the committed counter
-    summary (profiles/k_sweep_traffic.json: FETCH_SIZE + WRITE_SIZE of the
-    step's sweeps, calibrated on a copy of known size), or None when the
-    sweep kernel's source has changed since those counters were taken."""
+    summary (profiles/k_sweep_traffic.json: the step's sweeps' read requests
+    by size, TCC_EA0_RDREQ_128B and _64B, plus WRITE_SIZE, checked on a copy
+    of known size), or None when the sweep kernel's source has changed since
+    those counters were taken."""
     import hashlib
     try:
         info = json.load(open(os.path.join(ROOT, "profiles", "k_sweep_traffic.json")))
@@ -205,8 +206,9 @@ def roofline(kern: dict, bytes_per_launch: float, traffic=None) -> dict:
     return {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg, "limiter": LIMITER,
-            "traffic_source": ("profiles/k_sweep_traffic.json (rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, "
-                               "calibrated on a copy kernel; null when the kernel changed since)")}
+            "traffic_source": ("profiles/k_sweep_traffic.json (rocprofv3: read requests x their size from "
+                               "TCC_EA0_RDREQ_128B/_64B, plus WRITE_SIZE, per launch, averaged over a step's "
+                               "sweeps; a 1 GiB copy checks both; null when the kernel changed since)")}
 
 
 def base_result(args, value, step_ms, dtype, data, config, roof, cpu, **extra) -> dict:
