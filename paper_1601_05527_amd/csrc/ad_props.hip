@@ -335,50 +335,57 @@ __global__ void k_parent_init(int64_t n, int32_t *__restrict__ parent) {
         parent[i] = (int32_t)i;
 }
 
-// For every edge whose ends have different parents (roots, after the last
-// jump): hook the larger parent under the smaller (atomicMin).  Parents only
-// decrease and hooks only join trees of one component, so each component
-// ends rooted at its smallest vertex.  `changed` is raised while any edge
-// still joins two trees (a hook can lose a race and leave its trees apart
-// for the next round), once per wave.  A parent read late is still a vertex
-// of the same tree (trees only merge), so two equal parents always mean one
-// tree: parents are read with workgroup scope, i's once per row, and a
-// value read before another wave's hook only leaves work for the next round.
-__global__ void k_hook(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                       int32_t *__restrict__ parent, unsigned int *__restrict__ changed) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
-    bool any = false;
-    for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
-        const int64_t b1 = row_ptr[i + 1];
-        const int32_t pi = __hip_atomic_load(&parent[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        for (int64_t p = row_ptr[i] + lane; p < b1; p += WAVE) {
-            const int32_t j = col[p];
-            if (j <= i) continue;
-            const int32_t pj = __hip_atomic_load(&parent[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (pi == pj) continue;
-            any = true;
-            const int32_t lo = pi < pj ? pi : pj, hi = pi < pj ? pj : pi;
-            atomicMin(&parent[hi], lo);
-        }
+// Root of x, halving the path on the way: x is pointed at its grandparent
+// with atomicMin.  Ids decrease along every path, so the smaller of two
+// ancestors is the one nearer the root: a halving never moves a vertex away
+// from its root, whatever other halvings or final writes it races with.
+__device__ __forceinline__ int32_t uf_root(int32_t *parent, int32_t x) {
+    int32_t px = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (px != x) {
+        const int32_t ppx = __hip_atomic_load(&parent[px], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ppx != px) atomicMin(&parent[x], ppx);
+        x = px;
+        px = ppx;
     }
-    if (__ballot(any) != 0ull && lane == 0) atomicOr(changed, 1u);
+    return x;
 }
 
-// One pointer-jumping step, parent[i] <- parent[parent[i]]; `changed` is
-// raised (once per wave) while any parent moved.  Repeated, every vertex
-// points at its tree's root after log2 of the longest chain steps.
-__global__ void k_jump(int64_t n, int32_t *__restrict__ parent, unsigned int *__restrict__ changed) {
-    bool moved = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t p = parent[i];
-        const int32_t pp = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (pp != p) {
-            parent[i] = pp;
-            moved = true;
+// Join the trees of a and b: the larger root goes under the smaller; a
+// failed compare-and-swap means that root was just joined elsewhere, and
+// the roots are looked up again.
+__device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) {
+    for (;;) {
+        a = uf_root(parent, a);
+        b = uf_root(parent, b);
+        if (a == b) return;
+        if (a > b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(&parent[b], b, a) == b) return;
+    }
+}
+
+// One wave per row: every upper entry joins its two trees.
+__global__ void k_union(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                        int32_t *__restrict__ parent) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
+        const int64_t b1 = row_ptr[i + 1];
+        for (int64_t p = row_ptr[i] + lane; p < b1; p += WAVE) {
+            const int32_t j = col[p];
+            if (j > i) uf_union(parent, (int32_t)i, j);
         }
     }
-    if (__ballot(moved) != 0ull && (threadIdx.x & (WAVE - 1)) == 0) atomicOr(changed, 1u);
+}
+
+// Every vertex points at the root of its tree (atomicMin: the root is the
+// smallest ancestor, so a late halving by another thread cannot replace it).
+__global__ void k_flatten(int64_t n, int32_t *__restrict__ parent) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        atomicMin(&parent[i], uf_root(parent, (int32_t)i));
 }
 
 __global__ void k_count_roots(int64_t n, const int32_t *__restrict__ parent, unsigned long long *__restrict__ cnt) {
@@ -394,7 +401,7 @@ __global__ void k_count_roots(int64_t n, const int32_t *__restrict__ parent, uns
 __global__ void k_comp_keys(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ parent,
                             uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        key[i] = row_ptr[i + 1] > row_ptr[i] ? (uint32_t)parent[i] : 0xffffffffu;
+        key[i] = row_ptr[i + 1] > row_ptr[i] ? (uint32_t)parent[i] : (uint32_t)n;   // isolated: n, sorted last
         val[i] = (uint32_t)i;
     }
 }
@@ -402,7 +409,7 @@ __global__ void k_comp_keys(int64_t n, const int64_t *__restrict__ row_ptr, cons
 // head[p] = 1 where sorted position p starts a component.
 __global__ void k_comp_heads(int64_t n, const uint32_t *__restrict__ key, uint32_t *__restrict__ head) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
-        head[p] = (key[p] != 0xffffffffu && (p == 0 || key[p] != key[p - 1])) ? 1u : 0u;
+        head[p] = (key[p] != (uint32_t)n && (p == 0 || key[p] != key[p - 1])) ? 1u : 0u;
 }
 
 // comp_of, members and the component starts from the sorted order and the
@@ -414,7 +421,7 @@ __global__ void k_comp_fill(int64_t n, const uint32_t *__restrict__ key, const u
                             int64_t *__restrict__ comp_start) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = (int32_t)val[p];
-        if (key[p] == 0xffffffffu) {
+        if (key[p] == (uint32_t)n) {
             comp_of[v] = -1;
             continue;
         }
@@ -422,7 +429,7 @@ __global__ void k_comp_fill(int64_t n, const uint32_t *__restrict__ key, const u
         comp_of[v] = (int32_t)c;
         members[p] = v;
         if (head[p]) comp_start[c] = p;
-        if (p + 1 == n || key[p + 1] == 0xffffffffu) comp_start[c + 1] = p + 1;
+        if (p + 1 == n || key[p + 1] == (uint32_t)n) comp_start[c + 1] = p + 1;
     }
 }
 
@@ -539,38 +546,25 @@ static size_t prop_layout(const ad_graph *g, void *ws, size_t ws_bytes, PropLayo
 
 // Hook and jump until no hook changes a parent; every vertex then holds the
 // smallest vertex of its component.  flags: [3] scratch words.
+// Connected components by union-find: every upper entry (i, j) joins the
+// trees of i and j, hanging the larger root under the smaller with a
+// compare-and-swap, then every vertex is pointed at its root.  Parent ids
+// only ever decrease (a parent is always smaller than its child), so the
+// trees have no cycles, every root search ends, and each component's root
+// is its smallest vertex whatever the order of the joins.  No host round
+// trips.
 static ad_status label_components(const ad_graph *g, int32_t *parent, unsigned int *flags, hipStream_t stream) {
+    (void)flags;
     const int64_t n = g->n;
     const unsigned wgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, PBLOCK / WAVE)));
     hipLaunchKernelGGL(k_parent_init, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent);
     AD_LAUNCH_CHECK("k_parent_init");
-    // every round joins, for each edge between two trees, its two trees; the
-    // bound only guards against a defect, it is far above the rounds needed
-    for (int round = 0;; ++round) {
-        if (round > 4096) return fail(AD_ERR_INTERNAL, "components did not settle");
-        ad_status s = fill_i32((int32_t *)flags + 1, 0, 1, stream);
-        if (s != AD_OK) return s;
-        if (g->m > 0) {
-            hipLaunchKernelGGL(k_hook, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, parent, flags + 1);
-            AD_LAUNCH_CHECK("k_hook");
-        }
-        // jump until every vertex points at a root
-        for (int step = 0;; ++step) {
-            if (step > 64) return fail(AD_ERR_INTERNAL, "pointer jumping did not settle");
-            s = fill_i32((int32_t *)flags + 2, 0, 1, stream);
-            if (s != AD_OK) return s;
-            hipLaunchKernelGGL(k_jump, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent, flags + 2);
-            AD_LAUNCH_CHECK("k_jump");
-            unsigned int moved = 0;
-            AD_HIP(hipMemcpyAsync(&moved, flags + 2, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
-            AD_HIP(hipStreamSynchronize(stream));
-            if (!moved) break;
-        }
-        unsigned int changed = 0;
-        AD_HIP(hipMemcpyAsync(&changed, flags + 1, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
-        AD_HIP(hipStreamSynchronize(stream));
-        if (!changed) break;
+    if (g->m > 0) {
+        hipLaunchKernelGGL(k_union, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, parent);
+        AD_LAUNCH_CHECK("k_union");
     }
+    hipLaunchKernelGGL(k_flatten, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent);
+    AD_LAUNCH_CHECK("k_flatten");
     return AD_OK;
 }
 
@@ -813,7 +807,10 @@ extern "C" ad_status ad_components_build(const ad_graph *g, int32_t *comp_of, in
     hipLaunchKernelGGL(k_comp_keys, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, g->row_ptr, L.parent, L.key0, L.val0);
     AD_LAUNCH_CHECK("k_comp_keys");
     size_t tb = L.temp_bytes;
-    AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.key0, L.key1, L.val0, L.val1, (size_t)n, 0, 32, stream));
+    // keys are at most n (< 2^31): only their low bit_width(n) bits are sorted
+    int key_bits = 1;
+    while (key_bits < 32 && ((uint64_t)n >> key_bits) != 0) ++key_bits;
+    AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.key0, L.key1, L.val0, L.val1, (size_t)n, 0, key_bits, stream));
     hipLaunchKernelGGL(k_comp_heads, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, L.key1, L.head);
     AD_LAUNCH_CHECK("k_comp_heads");
     tb = L.temp_bytes;

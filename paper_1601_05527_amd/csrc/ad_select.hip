@@ -888,7 +888,8 @@ __device__ void hub_scan(uint32_t *a, int B, uint32_t *wsum) {
 }
 
 // Number of samples <= k in the sorted samp[0 .. S).
-__device__ __forceinline__ int hub_upper(const unsigned long long *samp, int S, unsigned long long k) {
+template <typename K>
+__device__ __forceinline__ int hub_upper(const K *samp, int S, K k) {
     int lo = 0, hi = S;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -898,13 +899,25 @@ __device__ __forceinline__ int hub_upper(const unsigned long long *samp, int S, 
     return lo;
 }
 
+// Key of entry p for the bucket partition: 64-bit (rho, id) or caller keys
+// of one orientation, or, with K = uint32_t, the 32-bit distance bits alone
+// (both orientations from one partition: equal distances share a bucket).
+template <typename K>
+__device__ __forceinline__ K hub_key(const unsigned long long *__restrict__ keys, const float *__restrict__ rho,
+                                     int64_t p, int32_t e, int32_t j, const int32_t *__restrict__ col_orig,
+                                     const int32_t *__restrict__ orig_id, int orient) {
+    if constexpr (sizeof(K) == 4) return __float_as_uint(rho[e]);
+    else return entry_key(keys, rho, p, e, nbr_id(p, j, col_orig, orig_id), orient);
+}
+
+template <typename K>
 __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
     const int32_t *__restrict__ col_orig, const float *__restrict__ rho,
     const unsigned long long *__restrict__ keys, int orient, HubScratch hs) {
-    __shared__ unsigned long long samp[HUB_SAMPLE];
+    __shared__ K samp[HUB_SAMPLE];
     __shared__ uint32_t cnt[HUB_MAX_B];
     __shared__ uint32_t wsum[HUB_TB / WAVE];
     __shared__ uint32_t base_s;
@@ -920,7 +933,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         const int B = (int)min((int64_t)(S / HUB_MIN_SP), (d + HUB_BUCKET - 1) / HUB_BUCKET);
         for (int t = threadIdx.x; t < S; t += HUB_TB) {
             const int64_t p = beg + ((int64_t)t * d) / S;
-            samp[t] = entry_key(keys, rho, p, eid[p], nbr_id(p, col[p], col_orig, orig_id), orient);
+            samp[t] = hub_key<K>(keys, rho, p, eid[p], col[p], col_orig, orig_id, orient);
         }
         for (int b = threadIdx.x; b < B; b += HUB_TB) cnt[b] = 0;
         __syncthreads();
@@ -930,7 +943,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
                     const int a = 2 * t - (t & (stride - 1));
                     const int b = a + stride;
                     const bool up = ((a & size) == 0);
-                    const unsigned long long ka = samp[a], kb = samp[b];
+                    const K ka = samp[a], kb = samp[b];
                     if ((ka > kb) == up) {
                         samp[a] = kb;
                         samp[b] = ka;
@@ -941,7 +954,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         }
         for (int64_t q = threadIdx.x; q < d; q += HUB_TB) {
             const int64_t p = beg + q;
-            const unsigned long long k = entry_key(keys, rho, p, eid[p], nbr_id(p, col[p], col_orig, orig_id), orient);
+            const K k = hub_key<K>(keys, rho, p, eid[p], col[p], col_orig, orig_id, orient);
             atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
         }
         __syncthreads();
@@ -963,9 +976,9 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         __syncthreads();
         for (int64_t q = threadIdx.x; q < d; q += HUB_TB) {
             const int64_t p = beg + q;
-            const unsigned long long k = entry_key(keys, rho, p, eid[p], nbr_id(p, col[p], col_orig, orig_id), orient);
+            const K k = hub_key<K>(keys, rho, p, eid[p], col[p], col_orig, orig_id, orient);
             const uint32_t at = atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
-            hs.key[beg + at] = k;
+            hs.key[beg + at] = (unsigned long long)k;
             hs.pos[beg + at] = (uint32_t)q;
         }
         __syncthreads();
@@ -1013,6 +1026,91 @@ __global__ __launch_bounds__(SBLOCK) void k_hub_rank(
                     const int64_t p = beg + bp[q];
                     const int64_t r = (int64_t)off + rank[t];
                     emit_ranks(em, row, col[p], eid[p], d, r, r);
+                }
+            }
+        }
+    }
+}
+
+// One wave per bucket of a partition on 32-bit distance bits: every entry's
+// ranks in both orders from counts inside its bucket (equal distances share
+// a bucket, so every entry of an earlier bucket is smaller and of a later
+// one larger): LOCAL = off + smaller + tied with smaller id, GLOBAL = d - off -
+// smaller - equal + tied with smaller id.  The ids are read only when the
+// wave's keys have a tie in their bucket.
+__global__ __launch_bounds__(SBLOCK) void k_hub_rank32(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
+    const int32_t *__restrict__ orig_id, const int32_t *__restrict__ col_orig, Emit em, HubScratch hs) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned int nb = (unsigned int)min((int64_t)(*hs.nbk), hs.cap);
+    const unsigned int waves = gridDim.x * (SBLOCK / WAVE);
+    for (unsigned int w = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); w < nb; w += waves) {
+        const int64_t row = hs.bk_row[w];
+        const int64_t beg = row_ptr[row];
+        const int64_t d = row_ptr[row + 1] - beg;
+        const uint32_t off = hs.bk_off[w], c = hs.bk_cnt[w];
+        const unsigned long long *bk = hs.key + beg + off;
+        const uint32_t *bp = hs.pos + beg + off;
+        for (uint32_t c0 = 0; c0 < c; c0 += HUB_KPL * WAVE) {
+            uint32_t key[HUB_KPL];
+            int lt[HUB_KPL], eq[HUB_KPL], eqlt[HUB_KPL];
+#pragma unroll
+            for (int t = 0; t < HUB_KPL; ++t) {
+                const uint32_t q = c0 + t * WAVE + lane;
+                key[t] = q < c ? (uint32_t)bk[q] : 0u;
+                lt[t] = eq[t] = eqlt[t] = 0;
+            }
+            for (uint32_t s0 = 0; s0 < c; s0 += WAVE) {
+                const uint32_t mine = (s0 + lane < c) ? (uint32_t)bk[s0 + lane] : 0u;
+                const int lim = (int)min((uint32_t)WAVE, c - s0);
+                for (int src = 0; src < lim; ++src) {
+                    const uint32_t kb = (uint32_t)shfl((int)mine, src);
+#pragma unroll
+                    for (int t = 0; t < HUB_KPL; ++t) {
+                        lt[t] += (kb < key[t]) ? 1 : 0;
+                        eq[t] += (kb == key[t]) ? 1 : 0;
+                    }
+                }
+            }
+            bool tie = false;
+#pragma unroll
+            for (int t = 0; t < HUB_KPL; ++t) tie = tie || (c0 + t * WAVE + lane < c && eq[t] > 1);
+            if (__any(tie)) {                          // uniform across the wave
+                int32_t id[HUB_KPL];
+#pragma unroll
+                for (int t = 0; t < HUB_KPL; ++t) {
+                    const uint32_t q = c0 + t * WAVE + lane;
+                    id[t] = 0;
+                    if (q < c) {
+                        const int64_t p = beg + bp[q];
+                        id[t] = nbr_id(p, col[p], col_orig, orig_id);
+                    }
+                }
+                for (uint32_t s0 = 0; s0 < c; s0 += WAVE) {
+                    uint32_t mine = 0u;
+                    int32_t mid = 0;
+                    if (s0 + lane < c) {
+                        mine = (uint32_t)bk[s0 + lane];
+                        const int64_t p = beg + bp[s0 + lane];
+                        mid = nbr_id(p, col[p], col_orig, orig_id);
+                    }
+                    const int lim = (int)min((uint32_t)WAVE, c - s0);
+                    for (int src = 0; src < lim; ++src) {
+                        const uint32_t kb = (uint32_t)shfl((int)mine, src);
+                        const int32_t ib = shfl(mid, src);
+#pragma unroll
+                        for (int t = 0; t < HUB_KPL; ++t) eqlt[t] += (kb == key[t] && ib < id[t]) ? 1 : 0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < HUB_KPL; ++t) {
+                const uint32_t q = c0 + t * WAVE + lane;
+                if (q < c) {
+                    const int64_t p = beg + bp[q];
+                    const int64_t rl = (int64_t)off + lt[t] + eqlt[t];
+                    const int64_t rg = d - (int64_t)off - lt[t] - eq[t] + eqlt[t];
+                    emit_ranks(em, row, col[p], eid[p], d, rl, rg);
                 }
             }
         }
@@ -1508,11 +1606,25 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                                    AD_RANK_ARGS_F);
             AD_LAUNCH_CHECK("k_rank_wave");
         }
-        // (the bucket partition runs once per orientation, a sort serves both: sorts up to SORT_CAP)
+        // (the bucket partition runs once per orientation, a sort serves both: sorts up to SORT_CAP);
+        // on its own stream beside the longest sorted class, whose rows it would otherwise follow
         static_assert(HUB_CLASS == 7 && SORT_CAP == 8192, "bitonic classes end where the bucket partition starts");
 #undef AD_RANK_ARGS_F
-        if (g->d_max > SORT_CAP) {
-            // the bucket keys carry one orientation: one partition per orientation asked for
+        if (g->d_max > SORT_CAP && !keys) {
+            // distance keys: one partition on the 32-bit distance bits serves both orders
+            s = fill_i32((int32_t *)L.hub.nbk, 0, 1, cls[2]);
+            if (s != AD_OK) return s;
+            for (int k = HUB_CLASS; k < NCLASS; ++k) {
+                if (g->d_max <= CLASS_LO[k]) break;
+                hipLaunchKernelGGL(k_hub_partition<uint32_t>, dim3(512), dim3(HUB_TB), 0, cls[2], lst[k], &L.cnt[k],
+                                   g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, em.orient, L.hub);
+                AD_LAUNCH_CHECK("k_hub_partition");
+            }
+            hipLaunchKernelGGL(k_hub_rank32, dim3(2048), dim3(SBLOCK), 0, cls[2], g->row_ptr, g->col, g->eid,
+                               g->orig_id, g->col_orig, em, L.hub);
+            AD_LAUNCH_CHECK("k_hub_rank32");
+        } else if (g->d_max > SORT_CAP) {
+            // caller keys carry one orientation: one partition per orientation asked for
             for (int pass = 0; pass < (em.both ? 2 : 1); ++pass) {
                 Emit one = em;
                 one.both = 0;
@@ -1524,16 +1636,16 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                     }
                 }
                 if (em.mode != MODE_FIXED) one.mode = (em.both && pass == 1) ? MODE_REC_G : MODE_REC_L;
-                s = fill_i32((int32_t *)L.hub.nbk, 0, 1, cls[0]);
+                s = fill_i32((int32_t *)L.hub.nbk, 0, 1, cls[2]);
                 if (s != AD_OK) return s;
                 for (int k = HUB_CLASS; k < NCLASS; ++k) {
                     if (g->d_max <= CLASS_LO[k]) break;
-                    hipLaunchKernelGGL(k_hub_partition, dim3(512), dim3(HUB_TB), 0, cls[0], lst[k], &L.cnt[k],
+                    hipLaunchKernelGGL(k_hub_partition<unsigned long long>, dim3(512), dim3(HUB_TB), 0, cls[2], lst[k], &L.cnt[k],
                                        g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, one.orient,
                                        L.hub);
                     AD_LAUNCH_CHECK("k_hub_partition");
                 }
-                hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, cls[0], g->row_ptr, g->col, g->eid, one,
+                hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, cls[2], g->row_ptr, g->col, g->eid, one,
                                    L.hub);
                 AD_LAUNCH_CHECK("k_hub_rank");
             }
