@@ -714,7 +714,7 @@ __global__ __launch_bounds__(TB) void k_rank_radix(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, Emit em) {
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, Emit em, int slice, int nslices) {
     constexpr int P = TB * IPT;
     static_assert(P <= 65536, "places are 16-bit");
     using Sorter = rocprim::block_radix_sort<uint32_t, TB, IPT, uint16_t>;
@@ -726,7 +726,8 @@ __global__ __launch_bounds__(TB) void k_rank_radix(
         } row;
     } sh;
     const unsigned int nr = *count;
-    for (unsigned int h = blockIdx.x; h < nr; h += gridDim.x) {
+    // this launch takes rows slice, slice + nslices, ... of the list
+    for (unsigned int h = blockIdx.x * nslices + slice; h < nr; h += gridDim.x * nslices) {
         const int64_t row = list[h];
         const int64_t beg = row_ptr[row];
         const int d = (int)(row_ptr[row + 1] - beg);
@@ -1558,27 +1559,40 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
             // one-wave workgroups for rows up to 512: more of them in flight
             const unsigned grid_w = (unsigned)std::min<int64_t>(8192, n);
 #define AD_RANK_ARGS_R g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, em
-            if (g->d_max > 4096)
+            // The classes' costs follow their entry counts, which differ by
+            // graph (a power-law graph holds most long-row entries in its few
+            // hundred longest rows, R-MAT spreads them over every class); the
+            // two longest sorted classes are split in two slices on different
+            // streams, and the rest spread so that neither kind of graph piles
+            // its work on one stream (the bucket partition follows the packed
+            // short rows on the caller's stream).
+            if (g->d_max > 4096) {
                 hipLaunchKernelGGL((k_rank_radix<512, 16>), dim3(grid), dim3(512), 0, cls[0], lst[6], &L.cnt[6],
-                                   AD_RANK_ARGS_R);
-            if (g->d_max > 2048)
-                hipLaunchKernelGGL((k_rank_radix<512, 8>), dim3(grid), dim3(512), 0, cls[1], lst[5], &L.cnt[5],
-                                   AD_RANK_ARGS_R);
+                                   AD_RANK_ARGS_R, 0, 2);
+                hipLaunchKernelGGL((k_rank_radix<512, 16>), dim3(grid), dim3(512), 0, cls[1], lst[6], &L.cnt[6],
+                                   AD_RANK_ARGS_R, 1, 2);
+            }
+            if (g->d_max > 2048) {
+                hipLaunchKernelGGL((k_rank_radix<512, 8>), dim3(grid), dim3(512), 0, cls[0], lst[5], &L.cnt[5],
+                                   AD_RANK_ARGS_R, 0, 2);
+                hipLaunchKernelGGL((k_rank_radix<512, 8>), dim3(grid), dim3(512), 0, cls[2], lst[5], &L.cnt[5],
+                                   AD_RANK_ARGS_R, 1, 2);
+            }
             if (g->d_max > 1024)
-                hipLaunchKernelGGL((k_rank_radix<256, 8>), dim3(grid), dim3(256), 0, cls[2], lst[4], &L.cnt[4],
-                                   AD_RANK_ARGS_R);
+                hipLaunchKernelGGL((k_rank_radix<256, 8>), dim3(grid), dim3(256), 0, cls[0], lst[4], &L.cnt[4],
+                                   AD_RANK_ARGS_R, 0, 1);
+            if (g->d_max > 64)
+                hipLaunchKernelGGL((k_rank_radix<64, 2>), dim3(grid_w), dim3(64), 0, cls[1], lst[0], &L.cnt[0],
+                                   AD_RANK_ARGS_R, 0, 1);
             if (g->d_max > 512)
-                hipLaunchKernelGGL((k_rank_radix<256, 4>), dim3(grid), dim3(256), 0, cls[1], lst[3], &L.cnt[3],
-                                   AD_RANK_ARGS_R);
+                hipLaunchKernelGGL((k_rank_radix<256, 4>), dim3(grid), dim3(256), 0, cls[2], lst[3], &L.cnt[3],
+                                   AD_RANK_ARGS_R, 0, 1);
             if (g->d_max > 256)
                 hipLaunchKernelGGL((k_rank_radix<64, 8>), dim3(grid_w), dim3(64), 0, cls[2], lst[2], &L.cnt[2],
-                                   AD_RANK_ARGS_R);
+                                   AD_RANK_ARGS_R, 0, 1);
             if (g->d_max > 128)
-                hipLaunchKernelGGL((k_rank_radix<64, 4>), dim3(grid_w), dim3(64), 0, cls[0], lst[1], &L.cnt[1],
-                                   AD_RANK_ARGS_R);
-            if (g->d_max > 64)
-                hipLaunchKernelGGL((k_rank_radix<64, 2>), dim3(grid_w), dim3(64), 0, cls[2], lst[0], &L.cnt[0],
-                                   AD_RANK_ARGS_R);
+                hipLaunchKernelGGL((k_rank_radix<64, 4>), dim3(grid_w), dim3(64), 0, cls[2], lst[1], &L.cnt[1],
+                                   AD_RANK_ARGS_R, 0, 1);
             AD_LAUNCH_CHECK("k_rank_radix");
 #undef AD_RANK_ARGS_R
         } else {
@@ -1606,21 +1620,21 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                                    AD_RANK_ARGS_F);
             AD_LAUNCH_CHECK("k_rank_wave");
         }
-        // (the bucket partition runs once per orientation, a sort serves both: sorts up to SORT_CAP);
-        // on its own stream beside the longest sorted class, whose rows it would otherwise follow
+        // rows above SORT_CAP: the bucket partition (for caller keys once per
+        // orientation, on a helper stream; for distance keys once, on the caller's stream)
         static_assert(HUB_CLASS == 7 && SORT_CAP == 8192, "bitonic classes end where the bucket partition starts");
 #undef AD_RANK_ARGS_F
         if (g->d_max > SORT_CAP && !keys) {
             // distance keys: one partition on the 32-bit distance bits serves both orders
-            s = fill_i32((int32_t *)L.hub.nbk, 0, 1, cls[2]);
+            s = fill_i32((int32_t *)L.hub.nbk, 0, 1, st);
             if (s != AD_OK) return s;
             for (int k = HUB_CLASS; k < NCLASS; ++k) {
                 if (g->d_max <= CLASS_LO[k]) break;
-                hipLaunchKernelGGL(k_hub_partition<uint32_t>, dim3(512), dim3(HUB_TB), 0, cls[2], lst[k], &L.cnt[k],
+                hipLaunchKernelGGL(k_hub_partition<uint32_t>, dim3(512), dim3(HUB_TB), 0, st, lst[k], &L.cnt[k],
                                    g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, em.orient, L.hub);
                 AD_LAUNCH_CHECK("k_hub_partition");
             }
-            hipLaunchKernelGGL(k_hub_rank32, dim3(2048), dim3(SBLOCK), 0, cls[2], g->row_ptr, g->col, g->eid,
+            hipLaunchKernelGGL(k_hub_rank32, dim3(2048), dim3(SBLOCK), 0, st, g->row_ptr, g->col, g->eid,
                                g->orig_id, g->col_orig, em, L.hub);
             AD_LAUNCH_CHECK("k_hub_rank32");
         } else if (g->d_max > SORT_CAP) {
