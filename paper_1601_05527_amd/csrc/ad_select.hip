@@ -35,6 +35,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include <rocprim/block/block_radix_sort.hpp>
@@ -722,6 +723,7 @@ __global__ __launch_bounds__(TB) void k_rank_radix(
         typename Sorter::storage_type sort;
         struct {
             uint32_t key[P];
+            uint32_t rank[P];                        // both ranks of entry q of the row, 16 bits each
             uint16_t place[P];
         } row;
     } sh;
@@ -756,14 +758,16 @@ __global__ __launch_bounds__(TB) void k_rank_radix(
             sh.row.place[q] = v[s];
         }
         __syncthreads();
+        // both ranks of sorted place q (each below d <= 65536: 16 bits each),
+        // stored at the entry's place in the row, so that the records are
+        // written by consecutive entries of the row (its upper entries hold
+        // consecutive edge ids)
 #pragma unroll
         for (int s = 0; s < IPT; ++s) {
             const int q = (int)threadIdx.x * IPT + s;
             if (q >= d) continue;
+            uint32_t rk = (uint32_t)q | ((uint32_t)(d - 1 - q) << 16);
             const uint32_t key = k[s];
-            const int64_t p = beg + v[s];
-            const int32_t j = col[p];
-            int64_t rl = q, rg = d - 1 - q;
             const bool tie = (q > 0 && sh.row.key[q - 1] == key) || (q + 1 < d && sh.row.key[q + 1] == key);
             if (tie) {
                 int a = 0, hi = q;                        // first place with this key
@@ -779,16 +783,25 @@ __global__ __launch_bounds__(TB) void k_rank_radix(
                     if (sh.row.key[mid] <= key) b = mid + 1;
                     else hi = mid;
                 }
-                const int32_t id = nbr_id(p, j, col_orig, orig_id);
+                const int64_t p = beg + v[s];
+                const int32_t id = nbr_id(p, col[p], col_orig, orig_id);
                 int before = 0;
                 for (int r = a; r < b; ++r) {
                     const int64_t pr = beg + sh.row.place[r];
                     before += nbr_id(pr, col[pr], col_orig, orig_id) < id ? 1 : 0;
                 }
-                rl = a + before;
-                rg = (int64_t)(d - b) + before;
+                rk = (uint32_t)(a + before) | ((uint32_t)(d - b + before) << 16);
             }
-            emit_ranks(em, row, j, eid[p], d, rl, rg);
+            sh.row.rank[v[s]] = rk;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int s = 0; s < IPT; ++s) {
+            const int q = s * TB + (int)threadIdx.x;
+            if (q < d) {
+                const uint32_t r = sh.row.rank[q];
+                emit_ranks(em, row, col[beg + q], eid[beg + q], d, r & 0xffffu, r >> 16);
+            }
         }
         __syncthreads();
     }
@@ -841,10 +854,14 @@ constexpr int HUB_BUCKET = 256;         // target bucket size
 constexpr int HUB_MIN_SP = 4;           // fewest samples per bucket
 constexpr int HUB_MAX_B = HUB_SAMPLE / HUB_MIN_SP;
 constexpr int HUB_KPL = 8;              // bucket keys per lane held in registers
+constexpr uint32_t HUB_EMITTED = 0x80000000u;  // place already emitted (above any rank: d < 2^31)
 
 struct HubScratch {
-    unsigned long long *key;   // [2m] bucketed keys, at the row's own entry range
-    uint32_t *pos;             // [2m] offset in the row of each bucketed key
+    unsigned long long *key;   // [2m] bucketed keys, at the row's own entry range (32-bit
+                               // distance keys: key << 32 | offset of the entry in its row)
+    uint32_t *pos;             // [2m] offset in the row of each bucketed 64-bit key (32-bit
+                               // keys: each entry's key at its own place between the passes,
+                               // then its LOCAL rank or HUB_EMITTED)
     int32_t *bk_row;           // [cap] the bucket's row
     uint32_t *bk_off;          // [cap] bucket offset within its row
     uint32_t *bk_cnt;          // [cap] bucket size
@@ -957,6 +974,9 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
             const int64_t p = beg + q;
             const K k = hub_key<K>(keys, rho, p, eid[p], col[p], col_orig, orig_id, orient);
             atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
+            // 32-bit keys: kept at the entry's own place for the scatter pass
+            // (one gather of the distance per entry instead of two)
+            if constexpr (sizeof(K) == 4) hs.pos[p] = k;
         }
         __syncthreads();
         if (threadIdx.x == 0) base_s = atomicAdd(hs.nbk, (unsigned int)B);
@@ -977,10 +997,17 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         __syncthreads();
         for (int64_t q = threadIdx.x; q < d; q += HUB_TB) {
             const int64_t p = beg + q;
-            const K k = hub_key<K>(keys, rho, p, eid[p], col[p], col_orig, orig_id, orient);
-            const uint32_t at = atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
-            hs.key[beg + at] = (unsigned long long)k;
-            hs.pos[beg + at] = (uint32_t)q;
+            if constexpr (sizeof(K) == 4) {
+                // bucketed as (key << 32 | place in row): one 8-byte entry
+                const uint32_t k = hs.pos[p];
+                const uint32_t at = atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
+                hs.key[beg + at] = ((unsigned long long)k << 32) | (uint32_t)q;
+            } else {
+                const K k = hub_key<K>(keys, rho, p, eid[p], col[p], col_orig, orig_id, orient);
+                const uint32_t at = atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
+                hs.key[beg + at] = (unsigned long long)k;
+                hs.pos[beg + at] = (uint32_t)q;
+            }
         }
         __syncthreads();
     }
@@ -1033,36 +1060,38 @@ __global__ __launch_bounds__(SBLOCK) void k_hub_rank(
     }
 }
 
-// One wave per bucket of a partition on 32-bit distance bits: every entry's
-// ranks in both orders from counts inside its bucket (equal distances share
+// One wave per bucket (of more than c_min entries) of a partition on 32-bit
+// distance bits: every entry's ranks in both orders from counts inside its bucket (equal distances share
 // a bucket, so every entry of an earlier bucket is smaller and of a later
 // one larger): LOCAL = off + smaller + tied with smaller id, GLOBAL = d - off -
 // smaller - equal + tied with smaller id.  The ids are read only when the
 // wave's keys have a tie in their bucket.
 __global__ __launch_bounds__(SBLOCK) void k_hub_rank32(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
-    const int32_t *__restrict__ orig_id, const int32_t *__restrict__ col_orig, Emit em, HubScratch hs) {
+    const int32_t *__restrict__ orig_id, const int32_t *__restrict__ col_orig, Emit em, HubScratch hs,
+    uint32_t c_min) {
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned int nb = (unsigned int)min((int64_t)(*hs.nbk), hs.cap);
     const unsigned int waves = gridDim.x * (SBLOCK / WAVE);
     for (unsigned int w = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); w < nb; w += waves) {
+        const uint32_t c = hs.bk_cnt[w];
+        if (c <= c_min) continue;                    // sorted by k_hub_sort
         const int64_t row = hs.bk_row[w];
         const int64_t beg = row_ptr[row];
         const int64_t d = row_ptr[row + 1] - beg;
-        const uint32_t off = hs.bk_off[w], c = hs.bk_cnt[w];
+        const uint32_t off = hs.bk_off[w];
         const unsigned long long *bk = hs.key + beg + off;
-        const uint32_t *bp = hs.pos + beg + off;
         for (uint32_t c0 = 0; c0 < c; c0 += HUB_KPL * WAVE) {
             uint32_t key[HUB_KPL];
             int lt[HUB_KPL], eq[HUB_KPL], eqlt[HUB_KPL];
 #pragma unroll
             for (int t = 0; t < HUB_KPL; ++t) {
                 const uint32_t q = c0 + t * WAVE + lane;
-                key[t] = q < c ? (uint32_t)bk[q] : 0u;
+                key[t] = q < c ? (uint32_t)(bk[q] >> 32) : 0u;
                 lt[t] = eq[t] = eqlt[t] = 0;
             }
             for (uint32_t s0 = 0; s0 < c; s0 += WAVE) {
-                const uint32_t mine = (s0 + lane < c) ? (uint32_t)bk[s0 + lane] : 0u;
+                const uint32_t mine = (s0 + lane < c) ? (uint32_t)(bk[s0 + lane] >> 32) : 0u;
                 const int lim = (int)min((uint32_t)WAVE, c - s0);
                 for (int src = 0; src < lim; ++src) {
                     const uint32_t kb = (uint32_t)shfl((int)mine, src);
@@ -1083,7 +1112,7 @@ __global__ __launch_bounds__(SBLOCK) void k_hub_rank32(
                     const uint32_t q = c0 + t * WAVE + lane;
                     id[t] = 0;
                     if (q < c) {
-                        const int64_t p = beg + bp[q];
+                        const int64_t p = beg + (uint32_t)bk[q];
                         id[t] = nbr_id(p, col[p], col_orig, orig_id);
                     }
                 }
@@ -1091,8 +1120,9 @@ __global__ __launch_bounds__(SBLOCK) void k_hub_rank32(
                     uint32_t mine = 0u;
                     int32_t mid = 0;
                     if (s0 + lane < c) {
-                        mine = (uint32_t)bk[s0 + lane];
-                        const int64_t p = beg + bp[s0 + lane];
+                        const unsigned long long kp = bk[s0 + lane];
+                        mine = (uint32_t)(kp >> 32);
+                        const int64_t p = beg + (uint32_t)kp;
                         mid = nbr_id(p, col[p], col_orig, orig_id);
                     }
                     const int lim = (int)min((uint32_t)WAVE, c - s0);
@@ -1104,16 +1134,129 @@ __global__ __launch_bounds__(SBLOCK) void k_hub_rank32(
                     }
                 }
             }
+            // an untied entry's LOCAL rank goes to its place in the row (its
+            // GLOBAL rank is d - 1 - LOCAL) for k_hub_emit, which writes the
+            // records in row order; tied entries are emitted here
 #pragma unroll
             for (int t = 0; t < HUB_KPL; ++t) {
                 const uint32_t q = c0 + t * WAVE + lane;
                 if (q < c) {
-                    const int64_t p = beg + bp[q];
+                    const int64_t p = beg + (uint32_t)bk[q];
                     const int64_t rl = (int64_t)off + lt[t] + eqlt[t];
-                    const int64_t rg = d - (int64_t)off - lt[t] - eq[t] + eqlt[t];
-                    emit_ranks(em, row, col[p], eid[p], d, rl, rg);
+                    if (eq[t] > 1) {
+                        const int64_t rg = d - (int64_t)off - lt[t] - eq[t] + eqlt[t];
+                        emit_ranks(em, row, col[p], eid[p], d, rl, rg);
+                        hs.pos[p] = HUB_EMITTED;
+                    } else {
+                        hs.pos[p] = (uint32_t)rl;
+                    }
                 }
             }
+        }
+    }
+}
+
+// Buckets of c_lo < c <= 64 * IPT entries of a partition on 32-bit distance
+// bits, one per one-wave workgroup: the bucket's keys sorted by a block radix
+// sort in LDS (bucket index as payload), so that an untied key's LOCAL rank is
+// the bucket offset + its sorted place.  Tied keys (adjacent after the sort)
+// take their order inside the run from the neighbour ids, as in k_rank_radix,
+// and are emitted here.
+template <int IPT>
+__global__ __launch_bounds__(WAVE) void k_hub_sort(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
+    const int32_t *__restrict__ orig_id, const int32_t *__restrict__ col_orig, Emit em, HubScratch hs,
+    uint32_t c_lo) {
+    constexpr int P = WAVE * IPT;
+    using Sorter = rocprim::block_radix_sort<uint32_t, WAVE, IPT, uint16_t>;
+    __shared__ union {
+        typename Sorter::storage_type sort;
+        struct {
+            uint32_t key[P];
+            uint32_t place[P];                       // offset in the row of sorted place q
+        } b;
+    } sh;
+    const unsigned int nb = (unsigned int)min((int64_t)(*hs.nbk), hs.cap);
+    for (unsigned int w = blockIdx.x; w < nb; w += gridDim.x) {
+        const uint32_t c = hs.bk_cnt[w];
+        if (c <= c_lo || c > (uint32_t)P) continue;  // uniform over the workgroup
+        const int64_t row = hs.bk_row[w];
+        const int64_t beg = row_ptr[row];
+        const int64_t d = row_ptr[row + 1] - beg;
+        const uint32_t off = hs.bk_off[w];
+        const unsigned long long *bk = hs.key + beg + off;
+        uint32_t k[IPT];
+        uint16_t v[IPT];
+#pragma unroll
+        for (int s = 0; s < IPT; ++s) {
+            const uint32_t q = (uint32_t)(s * WAVE) + threadIdx.x;
+            k[s] = q < c ? (uint32_t)(bk[q] >> 32) : 0xffffffffu;
+            v[s] = (uint16_t)q;
+        }
+        Sorter().sort(k, v, sh.sort);                // blocked: thread t holds sorted places t * IPT + s
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < IPT; ++s) {
+            const uint32_t q = threadIdx.x * IPT + s;
+            sh.b.key[q] = k[s];
+            sh.b.place[q] = q < c ? (uint32_t)bk[v[s]] : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < IPT; ++s) {
+            const int q = (int)(threadIdx.x * IPT + s);
+            if (q >= (int)c) continue;
+            const uint32_t key = k[s];
+            const int64_t p = beg + sh.b.place[q];
+            const bool tie = (q > 0 && sh.b.key[q - 1] == key) || (q + 1 < (int)c && sh.b.key[q + 1] == key);
+            if (!tie) {
+                hs.pos[p] = off + (uint32_t)q;
+                continue;
+            }
+            int a = 0, hi = q;                            // first place with this key
+            while (a < hi) {
+                const int mid = (a + hi) >> 1;
+                if (sh.b.key[mid] < key) a = mid + 1;
+                else hi = mid;
+            }
+            int b = q + 1;                                // first place past the run
+            hi = (int)c;
+            while (b < hi) {
+                const int mid = (b + hi) >> 1;
+                if (sh.b.key[mid] <= key) b = mid + 1;
+                else hi = mid;
+            }
+            const int32_t j = col[p];
+            const int32_t id = nbr_id(p, j, col_orig, orig_id);
+            int before = 0;
+            for (int r = a; r < b; ++r) {
+                const int64_t pr = beg + sh.b.place[r];
+                before += nbr_id(pr, col[pr], col_orig, orig_id) < id ? 1 : 0;
+            }
+            emit_ranks(em, row, j, eid[p], d, (int64_t)off + a + before, d - (int64_t)off - b + before);
+            hs.pos[p] = HUB_EMITTED;
+        }
+        __syncthreads();
+    }
+}
+
+// Records of the untied entries of the partitioned rows, in row order: the
+// buckets' offsets and sizes tile each row's places [0, d) into consecutive
+// ranges, one wave per range.
+__global__ __launch_bounds__(SBLOCK) void k_hub_emit(const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const int32_t *__restrict__ eid, Emit em, HubScratch hs) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned int nb = (unsigned int)min((int64_t)(*hs.nbk), hs.cap);
+    const unsigned int waves = gridDim.x * (SBLOCK / WAVE);
+    for (unsigned int w = blockIdx.x * (SBLOCK / WAVE) + (threadIdx.x >> 6); w < nb; w += waves) {
+        const int64_t row = hs.bk_row[w];
+        const int64_t beg = row_ptr[row];
+        const int64_t d = row_ptr[row + 1] - beg;
+        const int64_t a = beg + hs.bk_off[w], b = a + hs.bk_cnt[w];
+        for (int64_t p = a + lane; p < b; p += WAVE) {
+            const uint32_t r = hs.pos[p];
+            if (r != HUB_EMITTED) emit_ranks(em, row, col[p], eid[p], d, r, d - 1 - (int64_t)r);
         }
     }
 }
@@ -1436,19 +1579,26 @@ static inline int64_t budget_of(int64_t d, double e) {
 // by step: the end of the step at value c is predicted from (c + 1)^(1/e)
 // and confirmed with budget_of itself around the prediction.  Every entry
 // equals budget_of(d, e) under that monotonicity.
-static void budget_table(int32_t d_max, double e, std::vector<int32_t> &t) {
-    t.assign((size_t)d_max + 1, 0);
+static void budget_fill(int32_t d_max, double e, int32_t *t) {
+    t[0] = 0;
     int64_t d = 1;
+    int64_t c = d_max >= 1 ? budget_of(1, e) : 0;
     while (d <= d_max) {
-        const int64_t c = budget_of(d, e);
-        int64_t last = d;
+        int64_t last = d, next = -1;          // next: budget_of(last + 1) when already known
         if (c < d && e > 0.0) {
             const double edge = pow((double)(c + 1), 1.0 / e);
             int64_t guess = edge >= (double)d_max ? (int64_t)d_max : (int64_t)edge;
             if (guess < d) guess = d;
             if (budget_of(guess, e) == c) {
                 last = guess;
-                while (last < d_max && budget_of(last + 1, e) == c) ++last;
+                while (last < d_max) {
+                    const int64_t b = budget_of(last + 1, e);
+                    if (b != c) {
+                        next = b;
+                        break;
+                    }
+                    ++last;
+                }
             } else {
                 last = guess - 1;
                 while (last > d && budget_of(last, e) != c) --last;
@@ -1456,9 +1606,15 @@ static void budget_table(int32_t d_max, double e, std::vector<int32_t> &t) {
         } else if (c < d) {                 // e == 0: every budget is 1
             last = d_max;
         }
-        for (int64_t q = d; q <= last; ++q) t[(size_t)q] = (int32_t)c;
+        for (int64_t q = d; q <= last; ++q) t[q] = (int32_t)c;
         d = last + 1;
+        if (d <= d_max) c = next >= 0 ? next : budget_of(d, e);
     }
+}
+
+static void budget_table(int32_t d_max, double e, std::vector<int32_t> &t) {
+    t.assign((size_t)d_max + 1, 0);
+    budget_fill(d_max, e, t.data());
 }
 
 // Rank every entry of every row and emit per `em`.
@@ -1634,9 +1790,17 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                                    g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, em.orient, L.hub);
                 AD_LAUNCH_CHECK("k_hub_partition");
             }
+            // buckets of up to 256 / 512 entries by sorts, larger ones by counting
+            hipLaunchKernelGGL((k_hub_sort<4>), dim3(8192), dim3(WAVE), 0, st, g->row_ptr, g->col, g->eid,
+                               g->orig_id, g->col_orig, em, L.hub, 0u);
+            hipLaunchKernelGGL((k_hub_sort<8>), dim3(8192), dim3(WAVE), 0, st, g->row_ptr, g->col, g->eid,
+                               g->orig_id, g->col_orig, em, L.hub, 4u * WAVE);
+            AD_LAUNCH_CHECK("k_hub_sort");
             hipLaunchKernelGGL(k_hub_rank32, dim3(2048), dim3(SBLOCK), 0, st, g->row_ptr, g->col, g->eid,
-                               g->orig_id, g->col_orig, em, L.hub);
+                               g->orig_id, g->col_orig, em, L.hub, 8u * WAVE);
             AD_LAUNCH_CHECK("k_hub_rank32");
+            hipLaunchKernelGGL(k_hub_emit, dim3(2048), dim3(SBLOCK), 0, st, g->row_ptr, g->col, g->eid, em, L.hub);
+            AD_LAUNCH_CHECK("k_hub_emit");
         } else if (g->d_max > SORT_CAP) {
             // caller keys carry one orientation: one partition per orientation asked for
             for (int pass = 0; pass < (em.both ? 2 : 1); ++pass) {
@@ -1967,10 +2131,11 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
     std::lock_guard<std::mutex> lock(g_stage_mu);
     s = stage_reserve(4 * tl);
     if (s != AD_OK) return s;
-    std::vector<int32_t> t;
     for (int attempt = 0; attempt < 64; ++attempt) {
-        // budget tables at the candidate grid point and one step below
+        // budget tables at the candidate grid point and one step below, filled
+        // in the pinned staging buffer (one host thread per table for long rows)
         CountArgs ca{};
+        std::vector<std::pair<int32_t *, double>> fills;
         for (int o = 0; o < nfit; ++o) {
             ca.tab_hi[o] = L.tabs + (2 * o) * tl;
             ca.tab_lo[o] = L.tabs + (2 * o + 1) * tl;
@@ -1980,11 +2145,24 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
             ca.active[o] = done[o] ? 0 : 1;
             ca.use_lo[o] = g_try[o] > 0 ? 1 : 0;
             if (done[o]) continue;
-            budget_table(g->d_max, (double)g_try[o] / GRID, t);
-            std::copy(t.begin(), t.end(), g_stage + (2 * o) * tl);
-            if (g_try[o] > 0) budget_table(g->d_max, (double)(g_try[o] - 1) / GRID, t);
-            std::copy(t.begin(), t.end(), g_stage + (2 * o + 1) * tl);
+            fills.emplace_back(g_stage + (2 * o) * tl, (double)g_try[o] / GRID);
+            if (g_try[o] > 0) fills.emplace_back(g_stage + (2 * o + 1) * tl, (double)(g_try[o] - 1) / GRID);
         }
+        std::vector<std::thread> th;
+        size_t started = 0;                  // tables 1 .. started on their own threads
+        if (g->d_max >= (1 << 16)) {
+            try {
+                while (started + 1 < fills.size()) {
+                    const auto &f = fills[started + 1];
+                    th.emplace_back(budget_fill, g->d_max, f.second, f.first);
+                    ++started;
+                }
+            } catch (...) {                  // no thread: the rest on this one
+            }
+        }
+        for (size_t f = 0; f < fills.size(); ++f)
+            if (f == 0 || f > started) budget_fill(g->d_max, fills[f].second, fills[f].first);
+        for (auto &x : th) x.join();
         AD_HIP(hipMemcpyAsync(L.tabs, g_stage, 2 * nfit * tl * sizeof(int32_t), hipMemcpyHostToDevice, stream));
         s = fill_u64(L.counts, 0, 4, stream);
         if (s != AD_OK) return s;
