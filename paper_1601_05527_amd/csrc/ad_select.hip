@@ -1717,23 +1717,21 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
 #define AD_RANK_ARGS_R g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, em
             // The classes' costs follow their entry counts, which differ by
             // graph (a power-law graph holds most long-row entries in its few
-            // hundred longest rows, R-MAT spreads them over every class); the
-            // two longest sorted classes are split in two slices on different
-            // streams, and the rest spread so that neither kind of graph piles
-            // its work on one stream (the bucket partition follows the packed
-            // short rows on the caller's stream).
+            // hundred longest rows, R-MAT spreads them over every class).  The
+            // longest sorted class is split in two slices on two streams (its
+            // 512-thread workgroups need most of a compute unit and wait for
+            // room beside the other classes' work), and the rest spread so that
+            // neither kind of graph piles its work on one stream; the bucket
+            // partition follows the packed short rows on the caller's stream.
             if (g->d_max > 4096) {
                 hipLaunchKernelGGL((k_rank_radix<512, 16>), dim3(grid), dim3(512), 0, cls[0], lst[6], &L.cnt[6],
                                    AD_RANK_ARGS_R, 0, 2);
                 hipLaunchKernelGGL((k_rank_radix<512, 16>), dim3(grid), dim3(512), 0, cls[1], lst[6], &L.cnt[6],
                                    AD_RANK_ARGS_R, 1, 2);
             }
-            if (g->d_max > 2048) {
-                hipLaunchKernelGGL((k_rank_radix<512, 8>), dim3(grid), dim3(512), 0, cls[0], lst[5], &L.cnt[5],
-                                   AD_RANK_ARGS_R, 0, 2);
+            if (g->d_max > 2048)
                 hipLaunchKernelGGL((k_rank_radix<512, 8>), dim3(grid), dim3(512), 0, cls[2], lst[5], &L.cnt[5],
-                                   AD_RANK_ARGS_R, 1, 2);
-            }
+                                   AD_RANK_ARGS_R, 0, 1);
             if (g->d_max > 1024)
                 hipLaunchKernelGGL((k_rank_radix<256, 8>), dim3(grid), dim3(256), 0, cls[0], lst[4], &L.cnt[4],
                                    AD_RANK_ARGS_R, 0, 1);
@@ -1747,7 +1745,7 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                 hipLaunchKernelGGL((k_rank_radix<64, 8>), dim3(grid_w), dim3(64), 0, cls[2], lst[2], &L.cnt[2],
                                    AD_RANK_ARGS_R, 0, 1);
             if (g->d_max > 128)
-                hipLaunchKernelGGL((k_rank_radix<64, 4>), dim3(grid_w), dim3(64), 0, cls[2], lst[1], &L.cnt[1],
+                hipLaunchKernelGGL((k_rank_radix<64, 4>), dim3(grid_w), dim3(64), 0, cls[0], lst[1], &L.cnt[1],
                                    AD_RANK_ARGS_R, 0, 1);
             AD_LAUNCH_CHECK("k_rank_radix");
 #undef AD_RANK_ARGS_R
