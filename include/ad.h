@@ -38,8 +38,9 @@
  *     ordered by the caller).
  *   - Library-owned state: the selection calls on FP32 distances
  *     (ad_sparsify, ad_sparsify_fit, ad_sparsify_fit_both,
- *     ad_sparsify_binned) rank rows longer than 64 on three helper streams
- *     per device, of default priority, created on first use and kept until
+ *     ad_edge_dist_sparsify, ad_edge_dist_fit_both, ad_sparsify_binned)
+ *     rank rows longer than 64 on three helper streams per device, of
+ *     default priority, created on first use and kept until
  *     the process ends; they are forked from the caller's stream with an
  *     event after the call's first kernels and joined back into it with
  *     events before the call returns, so the caller's stream orders all of
@@ -308,6 +309,29 @@ ad_status ad_sparsify_fit_both(const ad_graph *g, ad_dtype rho_dtype, const void
                                double target, uint8_t *keep_local, uint8_t *keep_global,
                                int64_t *n_kept, double *e_used_host, void *ws,
                                size_t ws_bytes, hipStream_t stream);
+
+/* Distances and selection in one call: Algorithm 1's distances (as
+ * ad_edge_dist writes them, FP32 rho) and Algorithm 3 on them, with results
+ * equal to ad_edge_dist followed by ad_sparsify or ad_sparsify_fit_both.
+ * The distance pass visits whole rows and also writes every CSR entry's
+ * distance in entry order into the workspace (an edge's two entries get
+ * equal values: the squared differences and their summation order are the
+ * same from either end); the ranking reads its keys from there, contiguously,
+ * instead of gathering rho by edge id.  R in [1, 64]; x: [n][R] in x_dtype
+ * (AD_F64 or AD_F32) and minmax [2R] as ad_relax writes them; rho: [m] FP32
+ * output.  Workspace: ad_edge_dist_select_workspace_size bytes (the
+ * distance plan, 4 bytes per CSR entry, and the selection workspace of both
+ * orders).  The other arguments are those of ad_sparsify and
+ * ad_sparsify_fit_both; the fit SYNCHRONISES `stream`. */
+size_t ad_edge_dist_select_workspace_size(const ad_graph *g);
+ad_status ad_edge_dist_sparsify(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
+                                const double *minmax, float *rho, ad_orient orient,
+                                const int32_t *budget, uint8_t *keep, int64_t *n_kept, void *ws,
+                                size_t ws_bytes, hipStream_t stream);
+ad_status ad_edge_dist_fit_both(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
+                                const double *minmax, float *rho, double target,
+                                uint8_t *keep_local, uint8_t *keep_global, int64_t *n_kept,
+                                double *e_used_host, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Workspace bytes for ad_normalize_dist. */
 size_t ad_normalize_dist_workspace_size(const ad_graph *g);

@@ -113,6 +113,9 @@ def _load_lib():
         "ad_ml_level_span": (st, [i32, i32, i32, f64, P]),
         "ad_ml_sparsify": (st, [G, ctypes.POINTER(ADMLOpts), P, ctypes.POINTER(i64), ctypes.POINTER(i32), P]),
         "ad_sparsify_fit_both": (st, [G, ctypes.c_int, P, f64, P, P, P, P, P, S, P]),
+        "ad_edge_dist_select_workspace_size": (S, [G]),
+        "ad_edge_dist_sparsify": (st, [G, i32, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, P, S, P]),
+        "ad_edge_dist_fit_both": (st, [G, i32, ctypes.c_int, P, P, P, f64, P, P, P, P, P, S, P]),
         "ad_relax_backward_workspace_size": (S, [G, O]),
         "ad_relax_backward": (st, [G, O, P, P, P, P, P, P, P, S, P]),
         "ad_edge_to_entries": (st, [G, P, P, P]),
@@ -503,6 +506,67 @@ def sparsify_fit_both(dg: DeviceGraph, rho: torch.Tensor, target: float,
     _check(lib.ad_sparsify_fit_both(ctypes.byref(g), dt, _ptr(rho), float(target), _ptr(keep_local),
                                     _ptr(keep_global), _ptr(n_kept), e_used, _ptr(ws), ws.numel(), _stream()))
     return keep_local, keep_global, n_kept, (e_used[0], e_used[1])
+
+
+# ------------------------------------------- distance and selection, fused --
+
+def edge_dist_select_workspace_bytes(dg: DeviceGraph) -> int:
+    g = dg.abi()
+    return int(lib.ad_edge_dist_select_workspace_size(ctypes.byref(g)))
+
+
+def _fused_prep(dg, x, rho, ws):
+    if rho is None:
+        rho = torch.empty(dg.m, dtype=torch.float32, device=x.device)
+    if rho.dtype != torch.float32:
+        raise ValueError("the fused calls write FP32 distances")
+    g = dg.abi()
+    if ws is None:
+        ws = _workspace(lib.ad_edge_dist_select_workspace_size(ctypes.byref(g)), x.device)
+    dt = AD_F64 if x.dtype == torch.float64 else AD_F32
+    return g, rho, ws, dt
+
+
+def edge_dist_sparsify(dg: DeviceGraph, res: RelaxResult, orient: int, e: Optional[float] = None,
+                       budget: Optional[torch.Tensor] = None, rho: Optional[torch.Tensor] = None,
+                       ws: Optional[torch.Tensor] = None, keep: Optional[torch.Tensor] = None,
+                       n_kept: Optional[torch.Tensor] = None):
+    """Distances and Algorithm 3 at a fixed exponent in one call
+    (``ad_edge_dist_sparsify``); returns (rho, keep, n_kept)."""
+    x = res.x
+    dev = x.device
+    g, rho, ws, dt = _fused_prep(dg, x, rho, ws)
+    if budget is None:
+        budget = torch.from_numpy(budget_table(dg.d_max, e)).to(dev)
+    if keep is None:
+        keep = torch.empty(dg.m, dtype=torch.uint8, device=dev)
+    if n_kept is None:
+        n_kept = torch.empty(1, dtype=torch.int64, device=dev)
+    _check(lib.ad_edge_dist_sparsify(ctypes.byref(g), x.shape[1], dt, _ptr(x), _ptr(res.minmax), _ptr(rho), orient,
+                                     _ptr(budget), _ptr(keep), _ptr(n_kept), _ptr(ws), ws.numel(), _stream()))
+    return rho, keep, n_kept
+
+
+def edge_dist_fit_both(dg: DeviceGraph, res: RelaxResult, target: float, rho: Optional[torch.Tensor] = None,
+                       ws: Optional[torch.Tensor] = None, keep_local: Optional[torch.Tensor] = None,
+                       keep_global: Optional[torch.Tensor] = None, n_kept: Optional[torch.Tensor] = None):
+    """Distances and both fitted orders in one call (``ad_edge_dist_fit_both``);
+    returns (rho, keep_local, keep_global, n_kept[2], (e_local, e_global)).
+    Synchronises the current stream."""
+    x = res.x
+    dev = x.device
+    g, rho, ws, dt = _fused_prep(dg, x, rho, ws)
+    if keep_local is None:
+        keep_local = torch.empty(dg.m, dtype=torch.uint8, device=dev)
+    if keep_global is None:
+        keep_global = torch.empty(dg.m, dtype=torch.uint8, device=dev)
+    if n_kept is None:
+        n_kept = torch.empty(2, dtype=torch.int64, device=dev)
+    e_used = (ctypes.c_double * 2)(-1.0, -1.0)
+    _check(lib.ad_edge_dist_fit_both(ctypes.byref(g), x.shape[1], dt, _ptr(x), _ptr(res.minmax), _ptr(rho),
+                                     float(target), _ptr(keep_local), _ptr(keep_global), _ptr(n_kept), e_used,
+                                     _ptr(ws), ws.numel(), _stream()))
+    return rho, keep_local, keep_global, n_kept, (e_used[0], e_used[1])
 
 
 # --------------------------------------------------------------- adjoint ---

@@ -368,11 +368,13 @@ size_t relax_segs_workspace(const ad_graph *g, const ad_relax_opts *o, const Seg
 ad_status relax_segs(const ad_graph *g, const ad_relax_opts *o, const void *x0, void *x_out, double *minmax_out,
                      double *shift_out, void *ckpt, void *ws, size_t ws_bytes, const Segs &sg, hipStream_t st);
 
-// ad_edge_dist over packed graph segments (minmax [G][2R]).
+// ad_edge_dist over packed graph segments (minmax [G][2R]).  With rho_ent
+// (FP32 rho only) every CSR entry's distance is also written there, in
+// entry order, from a pass over whole rows.
 size_t edge_dist_segs_workspace(const ad_graph *g, const Segs &sg);
 ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x, const double *minmax,
                          ad_dtype rho_dtype, void *rho, void *ws, size_t ws_bytes, const Segs &sg,
-                         hipStream_t stream);
+                         hipStream_t stream, float *rho_ent = nullptr);
 
 // Algorithm 3 at fixed per-degree budgets, keep[] only (rows are independent,
 // so packed graphs need no segment information).

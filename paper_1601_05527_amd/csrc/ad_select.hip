@@ -105,12 +105,16 @@ __device__ __forceinline__ A group_sum(A v, int C, int base) {
 // (one lane group of C lanes per slot, SPR slots, U entries per slot in
 // flight).  Lane chunk c sums ((x_i - x_j) * inv)^2 over its VEC values in
 // order; group_sum adds the chunks.  `len` is the wave's common trip bound.
-template <typename Tx, typename Tr, int VEC, int U>
+// With ALL, every entry p of the span gets its value in rho_ent[p] (the
+// entry order of the CSR), and the upper ones also in rho[eid[p]]: an edge's
+// two entries get equal values, since x_j - x_i = -(x_i - x_j) exactly and
+// both are summed in the same order.
+template <typename Tx, typename Tr, int VEC, int U, bool ALL = false>
 __device__ __forceinline__ void dist_span(const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
                                           const Tx *__restrict__ x, const double *__restrict__ minmax,
-                                          Tr *__restrict__ rho, int R, int C, int SPR, int slot, int chunk,
-                                          int base, bool active, int64_t row, int64_t beg, int64_t end,
-                                          int64_t len, int64_t gb) {
+                                          Tr *__restrict__ rho, Tr *__restrict__ rho_ent, int R, int C, int SPR,
+                                          int slot, int chunk, int base, bool active, int64_t row, int64_t beg,
+                                          int64_t end, int64_t len, int64_t gb) {
     typedef typename acc_of<Tx>::type A;
     const int off = chunk * VEC;
     A xi[VEC], iv[VEC];
@@ -134,7 +138,7 @@ __device__ __forceinline__ void dist_span(const int32_t *__restrict__ col, const
             const int64_t p = beg + k0 + (int64_t)u * SPR;
             ok[u] = active && p < end;
             jj[u] = ok[u] ? col[p] : 0;
-            ok[u] = ok[u] && jj[u] > row;
+            if (!ALL) ok[u] = ok[u] && jj[u] > row;
         }
         A part[U];
 #pragma unroll
@@ -157,7 +161,12 @@ __device__ __forceinline__ void dist_span(const int32_t *__restrict__ col, const
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const A tot = group_sum(part[u], C, base);
-            if (ok[u] && chunk == 0) rho[eid[beg + k0 + (int64_t)u * SPR]] = (Tr)sqrt(tot);
+            if (ok[u] && chunk == 0) {
+                const int64_t p = beg + k0 + (int64_t)u * SPR;
+                const Tr r = (Tr)sqrt(tot);
+                if (ALL) rho_ent[p] = r;
+                if (!ALL || jj[u] > row) rho[eid[p]] = r;
+            }
         }
     }
 }
@@ -166,17 +175,18 @@ __device__ __forceinline__ void dist_span(const int32_t *__restrict__ col, const
 constexpr int64_t DIST_SEG = 4096;
 
 // rho for every edge, visited from its upper entry (j > i; the suffix of the
-// row after upper_start).  The first hub_blocks workgroups take the rows
+// row after upper_start); with ALL, from both of its entries (whole rows),
+// every entry's value also in rho_ent in CSR order.  The first hub_blocks workgroups take the rows
 // longer than hub_d, their upper suffix cut into work items of DIST_SEG
 // entries (row h of the hub list, segment s < hub_segs; items past the row's
 // end are skipped), one wave per item.  The other waves walk the launch plan (first row, rows in the tile,
 // log2 rows per wave) as the sweep does, with SPRW / rpw slots per row.
 // Every edge's value is computed by the same lane arithmetic on either path.
-template <typename Tx, typename Tr, int VEC, int U>
+template <typename Tx, typename Tr, int VEC, int U, bool ALL>
 __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
     int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const Tx *__restrict__ x, const double *__restrict__ minmax,
-    Tr *__restrict__ rho, int R, int C, int SPRW, int64_t hub_d, int hub_blocks, int64_t hub_segs,
+    Tr *__restrict__ rho, Tr *__restrict__ rho_ent, int R, int C, int SPRW, int64_t hub_d, int hub_blocks, int64_t hub_segs,
     const int32_t *__restrict__ hub_list, const unsigned int *__restrict__ hub_count,
     const long long *__restrict__ plan, const unsigned int *__restrict__ plan_count,
     const unsigned int *__restrict__ splits, int xcd_groups, const int32_t *__restrict__ row_graph) {
@@ -193,13 +203,13 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
              it += stride) {
             const int64_t row = hub_list[it / hub_segs];
             const int64_t re = row_ptr[row + 1];
-            const int64_t rb = upper_start(col, row_ptr[row], re, row);
+            const int64_t rb = ALL ? row_ptr[row] : upper_start(col, row_ptr[row], re, row);
             const int64_t b0 = rb + (int64_t)(it % hub_segs) * DIST_SEG;
             if (b0 >= re) continue;                       // uniform across the wave
             const int64_t e0 = min(re, b0 + DIST_SEG);
             const int64_t gb = (int64_t)(row_graph ? row_graph[row] : 0) * 2 * R;
-            dist_span<Tx, Tr, VEC, U>(col, eid, x, minmax, rho, R, C, SPRW, slot, chunk, lane - chunk, active,
-                                      row, b0, e0, e0 - b0, gb);
+            dist_span<Tx, Tr, VEC, U, ALL>(col, eid, x, minmax, rho, rho_ent, R, C, SPRW, slot, chunk,
+                                           lane - chunk, active, row, b0, e0, e0 - b0, gb);
         }
         return;
     }
@@ -223,7 +233,7 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
             beg = row_ptr[row];
             end = row_ptr[row + 1];
             if (end - beg > hub_d) active = false;        // taken by the hub workgroups
-            else beg = upper_start(col, beg, end, row);
+            else if (!ALL) beg = upper_start(col, beg, end, row);
         }
         if (!active) beg = end = 0;
         // uniform trip count across the wave: the longest row of the wave
@@ -231,8 +241,8 @@ __global__ __launch_bounds__(SBLOCK) void k_edge_dist(
         for (int d = WAVE / 2; d >= 1; d >>= 1) len = max(len, shfl_down(len, d));
         len = shfl(len, 0);
         const int64_t gb = (int64_t)(row_graph ? row_graph[row0] : 0) * 2 * R;
-        dist_span<Tx, Tr, VEC, U>(col, eid, x, minmax, rho, R, C, SPR, slot, chunk, lane - chunk, active, row, beg,
-                                  end, len, gb);
+        dist_span<Tx, Tr, VEC, U, ALL>(col, eid, x, minmax, rho, rho_ent, R, C, SPR, slot, chunk, lane - chunk,
+                                       active, row, beg, end, len, gb);
     }
 }
 
@@ -384,7 +394,7 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_packed(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
     const int32_t *__restrict__ col_orig, const Tr *__restrict__ rho,
-    const unsigned long long *__restrict__ keys, Emit em) {
+    const unsigned long long *__restrict__ keys, Emit em, const float *__restrict__ rho_ent) {
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned int np = *plan_count;
     const unsigned int nwaves = gridDim.x * (SBLOCK / WAVE);
@@ -415,7 +425,7 @@ __global__ __launch_bounds__(SBLOCK) void k_rank_packed(
         if (on) {
             my_j = col[e];
             my_e = eid[e];
-            if (!keys) my_rho = rho[my_e];
+            if (!keys) my_rho = rho_ent ? (Tr)rho_ent[e] : rho[my_e];
             my_id = nbr_id(e, my_j, col_orig, orig_id);
         }
         // every lane walks its own row: as many steps as the wave's longest row
@@ -715,7 +725,8 @@ __global__ __launch_bounds__(TB) void k_rank_radix(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, Emit em, int slice, int nslices) {
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, const float *__restrict__ rho_ent, Emit em,
+    int slice, int nslices) {
     constexpr int P = TB * IPT;
     static_assert(P <= 65536, "places are 16-bit");
     using Sorter = rocprim::block_radix_sort<uint32_t, TB, IPT, uint16_t>;
@@ -735,19 +746,28 @@ __global__ __launch_bounds__(TB) void k_rank_radix(
         const int d = (int)(row_ptr[row + 1] - beg);
         // striped load (item s of thread t is entry s * TB + t); places past d
         // carry the largest key and sort last
-        int32_t e[IPT];
         uint32_t k[IPT];
         uint16_t v[IPT];
+        if (rho_ent) {                               // distances in entry order: contiguous
 #pragma unroll
-        for (int s = 0; s < IPT; ++s) {
-            const int q = s * TB + (int)threadIdx.x;
-            e[s] = q < d ? eid[beg + q] : 0;
-        }
+            for (int s = 0; s < IPT; ++s) {
+                const int q = s * TB + (int)threadIdx.x;
+                k[s] = q < d ? __float_as_uint(rho_ent[beg + q]) : 0xffffffffu;
+                v[s] = (uint16_t)q;
+            }
+        } else {
+            int32_t e[IPT];
 #pragma unroll
-        for (int s = 0; s < IPT; ++s) {
-            const int q = s * TB + (int)threadIdx.x;
-            k[s] = q < d ? __float_as_uint(rho[e[s]]) : 0xffffffffu;
-            v[s] = (uint16_t)q;
+            for (int s = 0; s < IPT; ++s) {
+                const int q = s * TB + (int)threadIdx.x;
+                e[s] = q < d ? eid[beg + q] : 0;
+            }
+#pragma unroll
+            for (int s = 0; s < IPT; ++s) {
+                const int q = s * TB + (int)threadIdx.x;
+                k[s] = q < d ? __float_as_uint(rho[e[s]]) : 0xffffffffu;
+                v[s] = (uint16_t)q;
+            }
         }
         Sorter().sort(k, v, sh.sort);                // blocked: thread t holds sorted places t * IPT + s
         __syncthreads();
@@ -922,10 +942,11 @@ __device__ __forceinline__ int hub_upper(const K *samp, int S, K k) {
 // (both orientations from one partition: equal distances share a bucket).
 template <typename K>
 __device__ __forceinline__ K hub_key(const unsigned long long *__restrict__ keys, const float *__restrict__ rho,
-                                     int64_t p, int32_t e, int32_t j, const int32_t *__restrict__ col_orig,
+                                     const float *__restrict__ rho_ent, int64_t p, const int32_t *__restrict__ eid,
+                                     const int32_t *__restrict__ col, const int32_t *__restrict__ col_orig,
                                      const int32_t *__restrict__ orig_id, int orient) {
-    if constexpr (sizeof(K) == 4) return __float_as_uint(rho[e]);
-    else return entry_key(keys, rho, p, e, nbr_id(p, j, col_orig, orig_id), orient);
+    if constexpr (sizeof(K) == 4) return __float_as_uint(rho_ent ? rho_ent[p] : rho[eid[p]]);
+    else return entry_key(keys, rho, p, eid[p], nbr_id(p, col[p], col_orig, orig_id), orient);
 }
 
 template <typename K>
@@ -933,7 +954,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const int32_t *__restrict__ orig_id,
-    const int32_t *__restrict__ col_orig, const float *__restrict__ rho,
+    const int32_t *__restrict__ col_orig, const float *__restrict__ rho, const float *__restrict__ rho_ent,
     const unsigned long long *__restrict__ keys, int orient, HubScratch hs) {
     __shared__ K samp[HUB_SAMPLE];
     __shared__ uint32_t cnt[HUB_MAX_B];
@@ -951,7 +972,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         const int B = (int)min((int64_t)(S / HUB_MIN_SP), (d + HUB_BUCKET - 1) / HUB_BUCKET);
         for (int t = threadIdx.x; t < S; t += HUB_TB) {
             const int64_t p = beg + ((int64_t)t * d) / S;
-            samp[t] = hub_key<K>(keys, rho, p, eid[p], col[p], col_orig, orig_id, orient);
+            samp[t] = hub_key<K>(keys, rho, rho_ent, p, eid, col, col_orig, orig_id, orient);
         }
         for (int b = threadIdx.x; b < B; b += HUB_TB) cnt[b] = 0;
         __syncthreads();
@@ -972,7 +993,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
         }
         for (int64_t q = threadIdx.x; q < d; q += HUB_TB) {
             const int64_t p = beg + q;
-            const K k = hub_key<K>(keys, rho, p, eid[p], col[p], col_orig, orig_id, orient);
+            const K k = hub_key<K>(keys, rho, rho_ent, p, eid, col, col_orig, orig_id, orient);
             atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
             // 32-bit keys: kept at the entry's own place for the scatter pass
             // (one gather of the distance per entry instead of two)
@@ -1003,7 +1024,7 @@ __global__ __launch_bounds__(HUB_TB) void k_hub_partition(
                 const uint32_t at = atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
                 hs.key[beg + at] = ((unsigned long long)k << 32) | (uint32_t)q;
             } else {
-                const K k = hub_key<K>(keys, rho, p, eid[p], col[p], col_orig, orig_id, orient);
+                const K k = hub_key<K>(keys, rho, rho_ent, p, eid, col, col_orig, orig_id, orient);
                 const uint32_t at = atomicAdd(&cnt[min(B - 1, hub_upper(samp, S, k) * B / S)], 1u);
                 hs.key[beg + at] = (unsigned long long)k;
                 hs.pos[beg + at] = (uint32_t)q;
@@ -1652,7 +1673,7 @@ static RankFork *rank_fork() {
 
 template <typename Tr>
 static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, const SelLayout &L, hipStream_t st,
-                          const unsigned long long *keys = nullptr) {
+                          const unsigned long long *keys = nullptr, const float *rho_ent = nullptr) {
     const int64_t n = g->n;
     if (n <= 0 || g->m <= 0) return AD_OK;
     TraceScope trace("k_rank", st);
@@ -1691,7 +1712,7 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
     AD_LAUNCH_CHECK("k_rank_plan");
     const unsigned packed_blocks = (unsigned)std::min<int64_t>(4096, ceil_div(n, SBLOCK / WAVE));
     hipLaunchKernelGGL((k_rank_packed<Tr>), dim3(packed_blocks), dim3(SBLOCK), 0, st, L.plan, L.plan_count,
-                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rho, keys, em);
+                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rho, keys, em, rho_ent);
     AD_LAUNCH_CHECK("k_rank_packed");
     if (g->d_max <= 64) return AD_OK;
 
@@ -1714,7 +1735,7 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
         if (!keys) {
             // one-wave workgroups for rows up to 512: more of them in flight
             const unsigned grid_w = (unsigned)std::min<int64_t>(8192, n);
-#define AD_RANK_ARGS_R g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, em
+#define AD_RANK_ARGS_R g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, rho_ent, em
             // The classes' costs follow their entry counts, which differ by
             // graph (a power-law graph holds most long-row entries in its few
             // hundred longest rows, R-MAT spreads them over every class).  The
@@ -1785,7 +1806,8 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
             for (int k = HUB_CLASS; k < NCLASS; ++k) {
                 if (g->d_max <= CLASS_LO[k]) break;
                 hipLaunchKernelGGL(k_hub_partition<uint32_t>, dim3(512), dim3(HUB_TB), 0, st, lst[k], &L.cnt[k],
-                                   g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, em.orient, L.hub);
+                                   g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, rho_ent, keys, em.orient,
+                                   L.hub);
                 AD_LAUNCH_CHECK("k_hub_partition");
             }
             // buckets of up to 256 / 512 entries by sorts, larger ones by counting
@@ -1817,8 +1839,8 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
                 for (int k = HUB_CLASS; k < NCLASS; ++k) {
                     if (g->d_max <= CLASS_LO[k]) break;
                     hipLaunchKernelGGL(k_hub_partition<unsigned long long>, dim3(512), dim3(HUB_TB), 0, cls[2], lst[k], &L.cnt[k],
-                                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, keys, one.orient,
-                                       L.hub);
+                                       g->row_ptr, g->col, g->eid, g->orig_id, g->col_orig, rf, nullptr, keys,
+                                       one.orient, L.hub);
                     AD_LAUNCH_CHECK("k_hub_partition");
                 }
                 hipLaunchKernelGGL(k_hub_rank, dim3(2048), dim3(SBLOCK), 0, cls[2], g->row_ptr, g->col, g->eid, one,
@@ -1880,13 +1902,13 @@ namespace ad {
 // Rows longer than this are cut into DIST_SEG-entry work items.
 constexpr int64_t DIST_HUB = 4096;
 
-static SweepShape dist_shape(int R, ad_dtype x_dtype, int64_t d_max) {
+static SweepShape dist_shape(int R, ad_dtype x_dtype, int64_t d_max, bool whole_rows) {
     // the sweep's lane layout for this vector width, rows per wave sized by
-    // the upper entries; rows longer than DIST_HUB (when the graph has any)
-    // go to the hub workgroups
+    // the upper entries (or the whole rows); rows longer than DIST_HUB (when
+    // the graph has any) go to the hub workgroups
     SweepShape sh = sweep_shape(R, x_dtype == AD_F64 ? 8 : 4, 0, 0);
     sh.hub_d = (d_max > DIST_HUB) ? DIST_HUB : ((int64_t)1 << 62);
-    sh.upper_only = 1;
+    sh.upper_only = whole_rows ? 0 : 1;
     return sh;
 }
 
@@ -1896,7 +1918,7 @@ size_t edge_dist_segs_workspace(const ad_graph *g, const Segs &sg) {
 
 ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x, const double *minmax,
                          ad_dtype rho_dtype, void *rho, void *ws, size_t ws_bytes, const Segs &sg,
-                         hipStream_t stream) {
+                         hipStream_t stream, float *rho_ent) {
     Carver c(ws, ws_bytes);
     SweepPlan pl;
     sweep_plan_carve(c, g->n, sg.tile_off ? sg.ntiles : ceil_div(g->n, PLAN_TILE), pl);
@@ -1904,7 +1926,8 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
     if (g->n <= 0 || g->m <= 0) return AD_OK;
     // FP64 vectors with FP32 distances (the FP64 tail of FP32 storage) take
     // the FP32 lane layout: four values, 32 bytes, per lane
-    pl.sh = dist_shape(R, (x_dtype == AD_F64 && rho_dtype == AD_F32) ? AD_F32 : x_dtype, g->d_max);
+    if (rho_ent && rho_dtype != AD_F32) return fail(AD_ERR_INTERNAL, "entry-ordered distances are FP32");
+    pl.sh = dist_shape(R, (x_dtype == AD_F64 && rho_dtype == AD_F32) ? AD_F32 : x_dtype, g->d_max, rho_ent != nullptr);
     const bool hubs = g->d_max > DIST_HUB;
     ad_status s = sweep_plan_build(g, pl, hubs, sg, stream);
     if (s != AD_OK) return s;
@@ -1917,14 +1940,19 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
     }
     const unsigned nb = (unsigned)(std::min<int64_t>(4096, ceil_div(g->n, SBLOCK / WAVE)) + hub_blocks);
     TraceScope trace("k_edge_dist", stream);
-#define AD_DIST(TX, TR, V)                                                                                   \
-    hipLaunchKernelGGL((k_edge_dist<TX, TR, V, dist_unroll<TX>()>), dim3(nb), dim3(SBLOCK), 0, stream, g->n, \
-                       g->row_ptr, g->col, g->eid, (const TX *)x, minmax, (TR *)rho, R, pl.sh.C, pl.sh.SPRW,  \
-                       pl.sh.hub_d, (int)hub_blocks, hub_segs, pl.hub_list, pl.hub_count, pl.plan,            \
-                       pl.plan_count, pl.splits, pl.xcd_groups, sg.row_graph)
+#define AD_DIST_ALL(TX, TR, V, ALL)                                                                         \
+    hipLaunchKernelGGL((k_edge_dist<TX, TR, V, dist_unroll<TX>(), ALL>), dim3(nb), dim3(SBLOCK), 0, stream,  \
+                       g->n, g->row_ptr, g->col, g->eid, (const TX *)x, minmax, (TR *)rho, (TR *)rho_ent, R,  \
+                       pl.sh.C, pl.sh.SPRW, pl.sh.hub_d, (int)hub_blocks, hub_segs, pl.hub_list, pl.hub_count, \
+                       pl.plan, pl.plan_count, pl.splits, pl.xcd_groups, sg.row_graph)
+#define AD_DIST(TX, TR, V)                   \
+    do {                                     \
+        if (rho_ent) AD_DIST_ALL(TX, TR, V, true); \
+        else AD_DIST_ALL(TX, TR, V, false);  \
+    } while (0)
     if (x_dtype == AD_F64 && rho_dtype == AD_F64) {
-        if (pl.sh.vec == 2) AD_DIST(double, double, 2);
-        else AD_DIST(double, double, 1);
+        if (pl.sh.vec == 2) AD_DIST_ALL(double, double, 2, false);   // rho_ent is FP32 only
+        else AD_DIST_ALL(double, double, 1, false);
     } else if (x_dtype == AD_F64) {
         // FP64 vectors (the FP64 tail of FP32 storage), FP64 arithmetic, FP32 rho
         if (pl.sh.vec == 4) AD_DIST(double, float, 4);
@@ -1936,6 +1964,7 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
         else AD_DIST(float, float, 1);
     }
 #undef AD_DIST
+#undef AD_DIST_ALL
     AD_LAUNCH_CHECK("k_edge_dist");
     return AD_OK;
 }
@@ -2027,21 +2056,19 @@ extern "C" size_t ad_sparsify_workspace_size(const ad_graph *g) {
     return sel_layout(g, nullptr, 0, nullptr);
 }
 
-extern "C" ad_status ad_sparsify(const ad_graph *g, ad_dtype rho_dtype, const void *rho, ad_orient orient,
-                                 const int32_t *budget, uint8_t *keep, int64_t *n_kept, void *ws,
-                                 size_t ws_bytes, hipStream_t stream) {
-    SelLayout L;
-    ad_status s = check_sel_args(g, rho_dtype, rho, orient, keep, n_kept, ws, ws_bytes, &L);
-    if (s != AD_OK) return s;
-    if (g->m > 0 && !budget) return fail(AD_ERR_INVALID_ARG, "budget is NULL");
-    s = fill_u64(L.counts, 0, 1, stream);
+// Algorithm 3 at fixed budgets with the count (ad_sparsify's work); rho_ent,
+// when given, holds the FP32 distances in CSR entry order.
+static ad_status sparsify_count(const ad_graph *g, ad_dtype rho_dtype, const void *rho, ad_orient orient,
+                                const int32_t *budget, uint8_t *keep, int64_t *n_kept, const SelLayout &L,
+                                hipStream_t stream, const float *rho_ent = nullptr) {
+    ad_status s = fill_u64(L.counts, 0, 1, stream);
     if (s != AD_OK) return s;
     if (g->m > 0) {
         s = fill_u8(keep, 0, g->m, stream);
         if (s != AD_OK) return s;
         const Emit em = emit_single(MODE_FIXED, orient, budget, keep, nullptr);
         if (rho_dtype == AD_F32)
-            s = rank_all<float>(g, (const float *)rho, em, L, stream);
+            s = rank_all<float>(g, (const float *)rho, em, L, stream, nullptr, rho_ent);
         else
             s = rank_all<double>(g, (const double *)rho, em, L, stream);
         if (s != AD_OK) return s;
@@ -2053,6 +2080,16 @@ extern "C" ad_status ad_sparsify(const ad_graph *g, ad_dtype rho_dtype, const vo
     hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, stream, L.counts, n_kept);
     AD_LAUNCH_CHECK("k_store_count");
     return AD_OK;
+}
+
+extern "C" ad_status ad_sparsify(const ad_graph *g, ad_dtype rho_dtype, const void *rho, ad_orient orient,
+                                 const int32_t *budget, uint8_t *keep, int64_t *n_kept, void *ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+    SelLayout L;
+    ad_status s = check_sel_args(g, rho_dtype, rho, orient, keep, n_kept, ws, ws_bytes, &L);
+    if (s != AD_OK) return s;
+    if (g->m > 0 && !budget) return fail(AD_ERR_INVALID_ARG, "budget is NULL");
+    return sparsify_count(g, rho_dtype, rho, orient, budget, keep, n_kept, L, stream);
 }
 
 // Fewest kept edges meeting the target, in the bisection's own test
@@ -2198,7 +2235,8 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
 // side records, then the fits.
 static ad_status sparsify_fit_impl(const ad_graph *g, ad_dtype rho_dtype, const void *rho, int orient, bool both,
                                    double target, uint8_t *keep, uint8_t *keep2, int64_t *n_kept,
-                                   double *e_used_host, const SelLayout &L, hipStream_t stream) {
+                                   double *e_used_host, const SelLayout &L, hipStream_t stream,
+                                   const float *rho_ent = nullptr) {
     const int64_t m = g->m;
     const int nfit = both ? 2 : 1;
     ad_status s;
@@ -2220,7 +2258,7 @@ static ad_status sparsify_fit_impl(const ad_graph *g, ad_dtype rho_dtype, const 
         em.both = 1;
     }
     if (rho_dtype == AD_F32)
-        s = rank_all<float>(g, (const float *)rho, em, L, stream);
+        s = rank_all<float>(g, (const float *)rho, em, L, stream, nullptr, rho_ent);
     else
         s = rank_all<double>(g, (const double *)rho, em, L, stream);
     if (s != AD_OK) return s;
@@ -2262,6 +2300,93 @@ extern "C" ad_status ad_sparsify_fit_both(const ad_graph *g, ad_dtype rho_dtype,
     if (!e_used_host) return fail(AD_ERR_INVALID_ARG, "e_used_host is NULL");
     return sparsify_fit_impl(g, rho_dtype, rho, AD_LOCAL, true, target, keep_local, keep_global, n_kept,
                              e_used_host, L, stream);
+}
+
+// ------------------------------------------- distance and selection, fused --
+// One call for Algorithm 1's distances and Algorithm 3's selection: the
+// distance pass visits whole rows and writes every CSR entry's distance in
+// entry order beside rho (each edge's two entries get equal values), and the
+// ranking reads its keys from that array, contiguously, instead of gathering
+// rho by edge id.  Workspace: the distance plan, the entry-ordered distances
+// and the selection workspace of both orders, each 256-byte aligned.
+struct FusedLayout {
+    void *dist_ws = nullptr;
+    size_t dist_bytes = 0;
+    float *rho_ent = nullptr;
+    void *sel_ws = nullptr;
+    size_t sel_bytes = 0;
+};
+
+static size_t fused_layout(const ad_graph *g, void *ws, FusedLayout *F) {
+    const size_t dist = edge_dist_segs_workspace(g, Segs());
+    const size_t ent = (size_t)std::max<int64_t>(1, 2 * g->m) * sizeof(float);
+    const size_t sel = sel_layout(g, nullptr, 0, nullptr, true);
+    if (dist == 0 || sel == 0) return 0;
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t o1 = up(dist), o2 = up(o1 + ent);
+    if (F) {
+        F->dist_ws = ws;
+        F->dist_bytes = dist;
+        F->rho_ent = (float *)((char *)ws + o1);
+        F->sel_ws = (char *)ws + o2;
+        F->sel_bytes = sel;
+    }
+    return o2 + sel;
+}
+
+static ad_status check_fused_args(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
+                                  const double *minmax, void *rho, uint8_t *keep, int64_t *n_kept, void *ws,
+                                  size_t ws_bytes, FusedLayout *F, SelLayout *L) {
+    ad_status s = check_graph_args(g);
+    if (s != AD_OK) return s;
+    if (R < 1 || R > 64) return fail(AD_ERR_INVALID_ARG, "R must be in [1, 64]");
+    if (x_dtype != AD_F32 && x_dtype != AD_F64) return fail(AD_ERR_INVALID_ARG, "x must be F32 or F64");
+    if (g->m > 0 && (!x || !minmax || !rho || !keep)) return fail(AD_ERR_INVALID_ARG, "x, minmax, rho or keep is NULL");
+    if (!n_kept) return fail(AD_ERR_INVALID_ARG, "n_kept is NULL");
+    if (g->m > 0 && g->d_max <= 0) return fail(AD_ERR_INVALID_ARG, "d_max must be set for selection");
+    if (!ws) return fail(AD_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(AD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    const size_t need = fused_layout(g, ws, F);
+    if (need == 0 || ws_bytes < need) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    if (sel_layout(g, F->sel_ws, F->sel_bytes, L, true) == 0) return fail(AD_ERR_WORKSPACE, "workspace too small");
+    return AD_OK;
+}
+
+extern "C" size_t ad_edge_dist_select_workspace_size(const ad_graph *g) {
+    if (check_graph_args(g) != AD_OK) return 0;
+    return fused_layout(g, nullptr, nullptr);
+}
+
+extern "C" ad_status ad_edge_dist_sparsify(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
+                                           const double *minmax, float *rho, ad_orient orient,
+                                           const int32_t *budget, uint8_t *keep, int64_t *n_kept, void *ws,
+                                           size_t ws_bytes, hipStream_t stream) {
+    FusedLayout F;
+    SelLayout L;
+    ad_status s = check_fused_args(g, R, x_dtype, x, minmax, rho, keep, n_kept, ws, ws_bytes, &F, &L);
+    if (s != AD_OK) return s;
+    if (orient != AD_LOCAL && orient != AD_GLOBAL) return fail(AD_ERR_INVALID_ARG, "unknown orientation");
+    if (g->m > 0 && !budget) return fail(AD_ERR_INVALID_ARG, "budget is NULL");
+    s = edge_dist_segs(g, R, x_dtype, x, minmax, AD_F32, rho, F.dist_ws, F.dist_bytes, Segs(), stream, F.rho_ent);
+    if (s != AD_OK) return s;
+    return sparsify_count(g, AD_F32, rho, orient, budget, keep, n_kept, L, stream, F.rho_ent);
+}
+
+extern "C" ad_status ad_edge_dist_fit_both(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
+                                           const double *minmax, float *rho, double target, uint8_t *keep_local,
+                                           uint8_t *keep_global, int64_t *n_kept, double *e_used_host, void *ws,
+                                           size_t ws_bytes, hipStream_t stream) {
+    FusedLayout F;
+    SelLayout L;
+    ad_status s = check_fused_args(g, R, x_dtype, x, minmax, rho, keep_local, n_kept, ws, ws_bytes, &F, &L);
+    if (s != AD_OK) return s;
+    if (g->m > 0 && !keep_global) return fail(AD_ERR_INVALID_ARG, "keep_global is NULL");
+    if (!(target > 0.0 && target <= 1.0)) return fail(AD_ERR_INVALID_ARG, "target must be in (0, 1]");
+    if (!e_used_host) return fail(AD_ERR_INVALID_ARG, "e_used_host is NULL");
+    s = edge_dist_segs(g, R, x_dtype, x, minmax, AD_F32, rho, F.dist_ws, F.dist_bytes, Segs(), stream, F.rho_ent);
+    if (s != AD_OK) return s;
+    return sparsify_fit_impl(g, AD_F32, rho, AD_LOCAL, true, target, keep_local, keep_global, n_kept, e_used_host,
+                             L, stream, F.rho_ent);
 }
 
 // ---------------------------------------------------------------------------

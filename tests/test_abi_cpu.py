@@ -120,6 +120,25 @@ def test_selection_rejects_bad_arguments():
     assert L.ad_sparsify_binned(ctypes.byref(g), 1, p, 7, 0, 0.5, 0.0, p, p, eb, ws, need - 256, None) == 3
     assert L.ad_sparsify_binned(ctypes.byref(g), 1, p, 7, 0, 0.5, 0.0, p, p, eb, ctypes.c_void_p(0x10008),
                                 need, None) == 3
+    # distances and selection in one call: R, x dtype, orientation, budget,
+    # n_kept, target, keep_global, e_used_host, workspace size and alignment
+    gb = ctypes.byref(g)
+    need = L.ad_edge_dist_select_workspace_size(gb)
+    assert need >= (L.ad_sparsify_fit_both_workspace_size(gb) + L.ad_edge_dist_workspace_size(gb)
+                    + 4 * 2 * g.m)
+    assert L.ad_edge_dist_sparsify(gb, 0, 1, p, p, p, 0, p, p, p, ws, need, None) == 1
+    assert L.ad_edge_dist_sparsify(gb, 4, 2, p, p, p, 0, p, p, p, ws, need, None) == 1      # BF16 x
+    assert L.ad_edge_dist_sparsify(gb, 4, 1, p, p, p, 7, p, p, p, ws, need, None) == 1
+    assert L.ad_edge_dist_sparsify(gb, 4, 1, p, p, p, 0, None, p, p, ws, need, None) == 1
+    assert L.ad_edge_dist_sparsify(gb, 4, 1, p, p, p, 0, p, p, None, ws, need, None) == 1
+    assert L.ad_edge_dist_sparsify(gb, 4, 1, p, p, None, 0, p, p, p, ws, need, None) == 1    # rho
+    assert L.ad_edge_dist_sparsify(gb, 4, 1, p, p, p, 0, p, p, p, ws, need - 1, None) == 3
+    assert L.ad_edge_dist_sparsify(gb, 4, 1, p, p, p, 0, p, p, p, ctypes.c_void_p(0x10008), need, None) == 3
+    assert L.ad_edge_dist_fit_both(gb, 4, 1, p, p, p, 0.0, p, p, p, e2, ws, need, None) == 1
+    assert L.ad_edge_dist_fit_both(gb, 4, 1, p, p, p, 0.3, p, None, p, e2, ws, need, None) == 1
+    assert L.ad_edge_dist_fit_both(gb, 4, 1, p, p, p, 0.3, p, p, p, None, ws, need, None) == 1
+    assert L.ad_edge_dist_fit_both(gb, 65, 0, p, p, p, 0.3, p, p, p, e2, ws, need, None) == 1
+    assert L.ad_edge_dist_fit_both(gb, 4, 0, p, p, p, 0.3, p, p, p, e2, ws, need - 256, None) == 3
     # normalization: dtype, eps, workspace
     assert L.ad_normalize_dist(ctypes.byref(g), 2, p, 1, 0.0, p, ws, 1 << 30, None) == 1
     assert L.ad_normalize_dist(ctypes.byref(g), 1, p, 1, -1.0, p, ws, 1 << 30, None) == 1

@@ -305,18 +305,23 @@ def _long_row_graph():
     return G.from_edges(n, np.concatenate(us), np.concatenate(vs))
 
 
-@pytest.mark.parametrize("pattern", ["random", "ties", "clustered"])
+@pytest.mark.parametrize("pattern", ["random", "ties", "small_ties", "clustered"])
 def test_long_rows_bit_exact(api, pattern):
     """Selection and fit on rows longer than 8192, FP32 distances, against
-    the oracle.  'clustered' puts every unsampled entry of the 20000-row
-    between two adjacent sample keys of the partition (1024 <= sample size
-    S = 2048 for that degree), so one bucket holds almost the whole row."""
+    the oracle.  'ties' leaves about ten distinct values (runs of thousands:
+    buckets ranked by counting); 'small_ties' about ten thousand (runs of a
+    few entries inside buckets of a few hundred: the bucket sorts' tie
+    path).  'clustered' puts every unsampled entry of the 20000-row between
+    two adjacent sample keys of the partition (1024 <= sample size S = 2048
+    for that degree), so one bucket holds almost the whole row."""
     announce(f"long rows {pattern}")
     g = _long_row_graph()
     rng = np.random.default_rng(43)
     rho = rng.uniform(0.01, 1.0, g.m).astype(np.float32)
     if pattern == "ties":
         rho = np.round(rho, 1).astype(np.float32)
+    elif pattern == "small_ties":
+        rho = np.round(rho, 4).astype(np.float32)
     elif pattern == "clustered":
         i = 300
         beg, end = int(g.row_ptr[i]), int(g.row_ptr[i + 1])
