@@ -305,7 +305,7 @@ def fit_exponent_binned(g, rho: np.ndarray, target: float, seed: int, graph_id: 
 def ingest(n: int, u, v, w=None, orig_id=None, order: int = 0):
     """An edge list into the symmetric CSR of the graph model (self-loops
     dropped, repeated pairs merged with summed weights; order 1 stores the
-    vertices by decreasing degree).  Returns (row_ptr, col, w_entries or
+    vertices by decreasing degree, order 2 in reverse Cuthill-McKee order).  Returns (row_ptr, col, w_entries or
     None, eid, orig_id, m, n_dropped); raises ValueError for an endpoint out
     of range."""
     lib = _load()

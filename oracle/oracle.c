@@ -552,8 +552,8 @@ double orc_fit_exponent_binned(int64_t n, const int64_t *row_ptr, const int32_t 
  * of (smaller endpoint, larger endpoint), which is the CSR order of their
  * upper entries; each row lists its neighbours in ascending order.  With
  * order == 1 the vertices are stored by decreasing degree, ties by their id
- * in the list, and orig_out[new id] names the listed vertex (through
- * orig_in when given).  Returns the number of edges m, -1 when an endpoint
+ * in the list; with order == 2 in reverse Cuthill-McKee order (orc_rcm);
+ * orig_out[new id] names the listed vertex (through orig_in when given).  Returns the number of edges m, -1 when an endpoint
  * lies outside [0, n), -2 for a weight that is not finite and positive;
  * n_dropped receives m_in - m.                                             */
 
@@ -630,6 +630,78 @@ float orc_exact_sum_f32(const float *x, int64_t cnt)
     return ldexpf((float)mant, top - 23 - 149);
 }
 
+/* Reverse Cuthill-McKee order of the merged graph (ea[e] < eb[e], m
+ * edges), the bandwidth-reducing layout named beside the degree order.
+ * Readings (the layout is only named): the connected components are taken
+ * in increasing order of their smallest id (an isolated vertex is a
+ * component of its own); each is searched breadth first from its vertex of
+ * least degree (ties: the smallest id); when a vertex leaves the queue, its
+ * not yet queued neighbours join it in increasing (degree, id) order; the
+ * order of all components, concatenated, is reversed: the vertex at place q
+ * gets the id n - 1 - q.                                                   */
+typedef struct { int64_t deg, id; } orc_dv;
+
+static int orc_cmp_dv(const void *x, const void *y)
+{
+    const orc_dv *p = (const orc_dv *)x, *q = (const orc_dv *)y;
+    if (p->deg != q->deg) return p->deg < q->deg ? -1 : 1;     /* increasing degree */
+    return (p->id > q->id) - (p->id < q->id);
+}
+
+static void orc_rcm(int64_t n, int64_t m, const int64_t *ea, const int64_t *eb, int64_t *new_of)
+{
+    size_t nn = (size_t)(n > 0 ? n : 1), mm = (size_t)(m > 0 ? 2 * m : 1);
+    int64_t *deg = (int64_t *)calloc(nn, sizeof(int64_t));
+    int64_t *ptr = (int64_t *)calloc(nn + 1, sizeof(int64_t));
+    int64_t *adj = (int64_t *)malloc(sizeof(int64_t) * mm);
+    int64_t *at = (int64_t *)malloc(sizeof(int64_t) * nn);
+    for (int64_t e = 0; e < m; ++e) { deg[ea[e]]++; deg[eb[e]]++; }
+    for (int64_t i = 0; i < n; ++i) ptr[i + 1] = ptr[i] + deg[i];
+    for (int64_t i = 0; i < n; ++i) at[i] = ptr[i];
+    for (int64_t e = 0; e < m; ++e) { adj[at[ea[e]]++] = eb[e]; adj[at[eb[e]]++] = ea[e]; }
+    /* components in order of their smallest id, each with its start vertex */
+    int64_t *comp = (int64_t *)malloc(sizeof(int64_t) * nn);
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * nn);
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * nn);
+    for (int64_t i = 0; i < n; ++i) comp[i] = -1;
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (comp[i] >= 0) continue;
+        int64_t head = 0, tail = 0, best = i;
+        comp[i] = nc;
+        queue[tail++] = i;
+        while (head < tail) {
+            int64_t x = queue[head++];
+            if (deg[x] < deg[best] || (deg[x] == deg[best] && x < best)) best = x;
+            for (int64_t p = ptr[x]; p < ptr[x + 1]; ++p)
+                if (comp[adj[p]] < 0) { comp[adj[p]] = nc; queue[tail++] = adj[p]; }
+        }
+        start[nc++] = best;
+    }
+    /* Cuthill-McKee: breadth first from each start, neighbours by (degree, id) */
+    char *queued = (char *)calloc(nn, 1);
+    orc_dv *nb = (orc_dv *)malloc(sizeof(orc_dv) * nn);
+    int64_t place = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t head = place, tail = place;
+        queue[tail++] = start[c];
+        queued[start[c]] = 1;
+        while (head < tail) {
+            int64_t x = queue[head++];
+            int64_t k = 0;
+            for (int64_t p = ptr[x]; p < ptr[x + 1]; ++p) {
+                int64_t y = adj[p];
+                if (!queued[y]) { queued[y] = 1; nb[k].deg = deg[y]; nb[k].id = y; ++k; }
+            }
+            qsort(nb, (size_t)k, sizeof(orc_dv), orc_cmp_dv);
+            for (int64_t j = 0; j < k; ++j) queue[tail++] = nb[j].id;
+        }
+        place = tail;
+    }
+    for (int64_t q = 0; q < n; ++q) new_of[queue[q]] = n - 1 - q;
+    free(deg); free(ptr); free(adj); free(at); free(comp); free(start); free(queue); free(queued); free(nb);
+}
+
 int64_t orc_ingest(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v, const float *w,
                    const int32_t *orig_in, int32_t order, int64_t *row_ptr, int32_t *col, float *w_out,
                    int32_t *eid, int32_t *orig_out, int64_t *n_dropped)
@@ -673,13 +745,17 @@ int64_t orc_ingest(int64_t n, int64_t m_in, const int32_t *u, const int32_t *v, 
     /* vertex storage order */
     int64_t *new_of = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) new_of[i] = i;
-    if (order == 1 && n > 0) {
-        orc_vdeg *vd = (orc_vdeg *)malloc(sizeof(orc_vdeg) * (size_t)n);
-        for (int64_t i = 0; i < n; ++i) { vd[i].deg = 0; vd[i].id = i; }
-        for (int64_t e = 0; e < m; ++e) { vd[ea[e]].deg++; vd[eb[e]].deg++; }
-        qsort(vd, (size_t)n, sizeof(orc_vdeg), orc_cmp_vdeg);
-        for (int64_t r = 0; r < n; ++r) new_of[vd[r].id] = r;
-        free(vd);
+    if ((order == 1 || order == 2) && n > 0) {
+        if (order == 1) {
+            orc_vdeg *vd = (orc_vdeg *)malloc(sizeof(orc_vdeg) * (size_t)n);
+            for (int64_t i = 0; i < n; ++i) { vd[i].deg = 0; vd[i].id = i; }
+            for (int64_t e = 0; e < m; ++e) { vd[ea[e]].deg++; vd[eb[e]].deg++; }
+            qsort(vd, (size_t)n, sizeof(orc_vdeg), orc_cmp_vdeg);
+            for (int64_t r = 0; r < n; ++r) new_of[vd[r].id] = r;
+            free(vd);
+        } else {
+            orc_rcm(n, m, ea, eb, new_of);
+        }
         /* relabel, then number the edges again in (smaller, larger) order */
         orc_pair *rp = (orc_pair *)malloc(sizeof(orc_pair) * (size_t)(m > 0 ? m : 1));
         for (int64_t e = 0; e < m; ++e) {

@@ -11,6 +11,13 @@ model of Section 2) by brute force on small lists and by invariants:
     (smaller, larger) order; feeding its own edge list back is a fixed point;
   - the decreasing-degree order really is one, ties by listed id, and keeps
     the edge set (through orig_id);
+  - the reverse Cuthill-McKee order: a hand-worked graph with a degree tie;
+    bandwidth 1 on a scrambled path and at most 2k on a scrambled k x k
+    grid; and on random graphs with several components, checked by brute
+    force against breadth-first distances from scipy: components contiguous
+    in increasing order of their smallest id, each starting at its vertex of
+    least (degree, id), levels non-decreasing, and each level ordered by
+    (place of the first-placed neighbour one level up, degree, id);
   - out-of-range endpoints are refused; the empty list gives an empty graph.
 """
 from fractions import Fraction
@@ -110,7 +117,7 @@ def _check_csr(n, row_ptr, col, eid, m):
     assert pairs == sorted(pairs)          # ids follow (smaller, larger) order
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2])
 def test_ingest_structure_and_fixed_point(order):
     n = 200
     u, v, w = _random_list(n, 2000, 11)
@@ -157,6 +164,96 @@ def test_decreasing_degree_order_matches_relabel():
     np.testing.assert_array_equal(out[2], h.w)
     np.testing.assert_array_equal(out[3], h.eid)
     np.testing.assert_array_equal(out[4], h.orig_id)
+
+
+def test_rcm_hand_worked():
+    """Edges 0-1, 0-2, 0-3, 1-4, 2-4, 3-5 and the isolated vertex 6.
+    Component {0..5} starts at 5 (the only degree-1 vertex): 5; 3; 0; then
+    0's neighbours 1 and 2 (both degree 2: by id); then 4.  Component {6}
+    follows.  Cuthill-McKee order 5 3 0 1 2 4 6, reversed: new ids
+    6 <- 5, 5 <- 3, 4 <- 0, 3 <- 1, 2 <- 2, 1 <- 4, 0 <- 6."""
+    u = np.array([0, 0, 0, 1, 2, 3], dtype=np.int32)
+    v = np.array([1, 2, 3, 4, 4, 5], dtype=np.int32)
+    row_ptr, col, _, eid, orig, m, _ = oracle.ingest(7, u, v, order=2)
+    assert m == 6
+    assert orig.tolist() == [6, 4, 2, 1, 0, 3, 5]
+    _check_csr(7, row_ptr, col, eid, m)
+
+
+def _bandwidth(row_ptr, col):
+    rows = np.repeat(np.arange(row_ptr.size - 1), np.diff(row_ptr))
+    return int(np.abs(rows - col).max()) if col.size else 0
+
+
+def test_rcm_bandwidth_of_path_and_grid():
+    rng = np.random.default_rng(21)
+    n = 500
+    perm = rng.permutation(n)
+    u, v = perm[:-1], perm[1:]
+    row_ptr, col, *_ = oracle.ingest(n, u, v, order=2)
+    assert _bandwidth(row_ptr, col) == 1
+    k = 30
+    ii, jj = np.meshgrid(np.arange(k), np.arange(k), indexing="ij")
+    idx = (ii * k + jj).ravel()
+    right = np.stack([idx.reshape(k, k)[:, :-1].ravel(), idx.reshape(k, k)[:, 1:].ravel()])
+    down = np.stack([idx.reshape(k, k)[:-1, :].ravel(), idx.reshape(k, k)[1:, :].ravel()])
+    e = np.concatenate([right, down], axis=1)
+    scr = rng.permutation(k * k)
+    base = oracle.ingest(k * k, scr[e[0]], scr[e[1]])
+    assert _bandwidth(base[0], base[1]) > 10 * k           # scrambled
+    row_ptr, col, *_ = oracle.ingest(k * k, scr[e[0]], scr[e[1]], order=2)
+    assert _bandwidth(row_ptr, col) <= 2 * k
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33])
+def test_rcm_is_the_stated_breadth_first_order(seed):
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components, shortest_path
+    rng = np.random.default_rng(seed)
+    n = 400
+    # a few dense blocks, sparse links, isolated vertices, repeated pairs
+    u = rng.integers(0, 300, 700)
+    v = (u + rng.integers(1, 12, 700)) % 300
+    u = np.concatenate([u, rng.integers(300, 380, 90)])
+    v = np.concatenate([v, rng.integers(300, 380, 90)])
+    w = rng.uniform(0.5, 2.0, u.size).astype(np.float32)
+    listed = oracle.ingest(n, u, v, w)                 # the graph under the listed ids
+    lrp, lcol = listed[0], listed[1]
+    deg = np.diff(lrp)
+    a = sp.csr_matrix((np.ones(lcol.size), lcol, lrp), shape=(n, n))
+    nc, lab = connected_components(a, directed=False)
+    row_ptr, col, we, eid, orig, m, _ = oracle.ingest(n, u, v, w, order=2)
+    _check_csr(n, row_ptr, col, eid, m)
+    assert sorted(orig.tolist()) == list(range(n))
+    cm = orig[::-1]                                    # listed vertex at each Cuthill-McKee place
+    place = np.empty(n, dtype=np.int64)
+    place[cm] = np.arange(n)
+    # components contiguous, in increasing order of their smallest id
+    comp_seq = lab[cm]
+    runs = [comp_seq[0]] + [c for p, c in zip(comp_seq[:-1], comp_seq[1:]) if c != p]
+    assert len(runs) == nc
+    smallest = {c: int(np.nonzero(lab == c)[0].min()) for c in range(nc)}
+    assert [smallest[c] for c in runs] == sorted(smallest[c] for c in runs)
+    start = 0
+    for c in runs:
+        members = np.nonzero(lab == c)[0]
+        seq = cm[start:start + members.size]
+        s0 = min(members, key=lambda x: (deg[x], x))
+        assert seq[0] == s0
+        dist = shortest_path(a, unweighted=True, indices=[s0])[0]
+        lev = dist[seq]
+        assert np.all(np.diff(lev) >= 0)
+        key = []
+        for x in seq[1:]:
+            ups = [y for y in lcol[lrp[x]:lrp[x + 1]] if dist[y] == dist[x] - 1]
+            key.append((dist[x], min(place[y] for y in ups), deg[x], x))
+        assert key == sorted(key)
+        start += members.size
+    # the same weighted edge set, named by listed ids
+    def edge_set(rp, cl, ww, oid):
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        return {(int(min(oid[p], oid[q])), int(max(oid[p], oid[q]))): float(x) for p, q, x in zip(rows, cl, ww)}
+    assert edge_set(row_ptr, col, we, orig) == edge_set(listed[0], listed[1], listed[2], listed[4])
 
 
 def test_orig_ids_pass_through():
