@@ -395,8 +395,14 @@ def run_chung_lu(args, api, torch, dev):
     ingest = {"ms": ing_ms, "pairs_per_s": g_orig.m / (ing_ms * 1e-3), "equals_step_layout": same,
               "what": (f"ad_ingest of the {g_orig.m} drawn pairs (random labels, lognormal weights) into the "
                        "symmetric CSR stored by decreasing degree, outputs allocated per call; "
-                       f"(host generation and layout of the graph: {t_setup:.1f} s)")}
-    del gu, gv, gw
+                       f"(host generation and layout of the graph: {t_setup:.1f} s); rcm_ms: the same pairs "
+                       "into reverse Cuthill-McKee order; rcm_gather_probe_ms: the gather probe over that "
+                       "layout's column array (the degree order's: gather_ceiling.probe_ms)")}
+    # the same pairs in reverse Cuthill-McKee order, and the sweep's gather floor in that layout
+    dr = api.ingest(n, gu, gv, gw, order="rcm", entry_ids=False)
+    ingest["rcm_ms"] = timer.run(lambda: api.ingest(n, gu, gv, gw, order="rcm", entry_ids=False), 2)
+    ingest["rcm_gather_probe_ms"] = gather_probe_ms(torch, timer, x32, dr.col, R * 4)
+    del dr, gu, gv, gw
 
     # context: the sweep's neighbour-row gathers alone, with nothing else asked of the
     # memory system (the irregular path's practical ceiling), and the vendor SpMM

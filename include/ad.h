@@ -400,7 +400,13 @@ size_t ad_ingest_workspace_size(int64_t n, int64_t m_in);
  *   w: DEVICE [m_in] or NULL (unweighted: w_out unused, may be NULL).
  *   orig_id: DEVICE [n] names of the listed vertices or NULL (identity).
  *   order: 0 keeps the listed ids; 1 stores vertices by decreasing degree,
- *          ties by listed id (the layout the sweeps prefer).
+ *          ties by listed id (the layout the sweeps prefer); 2 stores them
+ *          in reverse Cuthill-McKee order (the bandwidth-reducing layout):
+ *          components by increasing smallest listed id, each searched
+ *          breadth first from its vertex of least (degree, listed id), the
+ *          unqueued neighbours of each dequeued vertex queued by increasing
+ *          (degree, listed id), the whole order reversed (one host
+ *          read-back per level of the search).
  *   Outputs (DEVICE, caller-owned): row_ptr [n+1]; col, eid and w_out
  *   [2*m_in] (the first 2*m entries written); orig_id_out [n], the name of
  *   every stored vertex (orig_id of its listed vertex, or the listed id).

@@ -721,13 +721,18 @@ def sparsify_binned(dg: DeviceGraph, rho: torch.Tensor, seed: int, e: float = 0.
 
 # ---------------------------------------------------------------- ingest ---
 
+_ORDERS = {"listed": 0, "degree": 1, "rcm": 2}
+
+
 def ingest(n: int, u: torch.Tensor, v: torch.Tensor, w: Optional[torch.Tensor] = None,
            orig_id: Optional[torch.Tensor] = None, by_degree: bool = True,
-           entry_ids: bool = True) -> DeviceGraph:
+           entry_ids: bool = True, order: Optional[str] = None) -> DeviceGraph:
     """An undirected edge list on the device into a ``DeviceGraph``
     (``ad_ingest``): self-loops dropped, repeated pairs merged (weights
     summed), vertices stored by decreasing degree unless ``by_degree`` is
-    False.  Synchronises the current stream."""
+    False; ``order`` ("listed", "degree" or "rcm", reverse Cuthill-McKee)
+    overrides ``by_degree``.  Synchronises the current stream."""
+    code = _ORDERS[order] if order is not None else (1 if by_degree else 0)
     dev = u.device
     m_in = int(u.numel())
     u = u.to(torch.int32).contiguous()
@@ -743,7 +748,7 @@ def ingest(n: int, u: torch.Tensor, v: torch.Tensor, w: Optional[torch.Tensor] =
     m = ctypes.c_int64(0)
     d_max = ctypes.c_int32(0)
     dropped = ctypes.c_int64(0)
-    _check(lib.ad_ingest(n, m_in, _ptr(u), _ptr(v), _ptr(w), _ptr(orig_id), 1 if by_degree else 0, _ptr(row_ptr),
+    _check(lib.ad_ingest(n, m_in, _ptr(u), _ptr(v), _ptr(w), _ptr(orig_id), code, _ptr(row_ptr),
                          _ptr(col), _ptr(w_out), _ptr(eid), _ptr(orig), ctypes.byref(m), ctypes.byref(d_max),
                          ctypes.byref(dropped), _ptr(ws), ws.numel(), _stream()))
     nnz = 2 * m.value

@@ -9,14 +9,20 @@
 // graph model requires); edge ids enumerate the edges
 // in (smaller endpoint, larger endpoint) order, the CSR order of their upper
 // entries; rows list neighbours in ascending order; the decreasing-degree
-// order breaks ties by listed id, and orig_id names the listed vertex.
+// order breaks ties by listed id, and orig_id names the listed vertex.  The
+// reverse Cuthill-McKee order: components by increasing smallest id, each
+// searched breadth first from its vertex of least (degree, id), the
+// neighbours of a dequeued vertex queued by increasing (degree, id), the
+// whole order reversed.
 //
 // The pipeline: canonical 64-bit pair keys, a stable radix sort (rocPRIM) of
 // (key, list index), run heads and their scan (edge ids), run bounds, and
 // the exact weight sum of every run (one thread per short run, one wave per
 // long run); for
 // the degree order a sort of (degree, id) vertex keys and a second pair sort
-// under the new labels; then per-row counts from the run lengths of the
+// under the new labels (for reverse Cuthill-McKee, the graph placed under
+// the listed ids, its components, and a level-by-level search with two
+// sorts per level, then the same relabelling); then per-row counts from the run lengths of the
 // sorted endpoints (no atomics, so hub vertices cost nothing extra), their
 // scans and the placement of the upper entries (edge order) and of the
 // lower entries (a stable sort of the edges by larger endpoint).
@@ -429,6 +435,108 @@ __global__ void k_u32_to_u64(int64_t n, const uint32_t *__restrict__ a, uint64_t
         b[i] = a[i];
 }
 
+// ------------------------------------------------ reverse Cuthill-McKee --
+// The order of the oracle's reading, built level by level: a breadth-first
+// search visits a level in queue order, and each vertex of the next level
+// is queued by its first-visited neighbour in the level, its siblings in
+// increasing (degree, id) order, so the next level is the set of unplaced
+// neighbours ordered by (smallest place among their placed neighbours,
+// degree, id).  Every component is searched at once, each in its own range
+// of places (components in increasing order of their smallest id, each
+// starting at its vertex of least (degree, id)).
+constexpr uint32_t RC_UNSET = 0xffffffffu;
+
+__global__ void k_rc_init(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ root,
+                          uint32_t *__restrict__ size, unsigned long long *__restrict__ start,
+                          uint32_t *__restrict__ pos, uint32_t *__restrict__ par) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = root[i];
+        const unsigned long long d = (unsigned long long)(row_ptr[i + 1] - row_ptr[i]);
+        atomicAdd(&size[r], 1u);
+        atomicMin(&start[r], (d << 32) | (unsigned long long)i);
+        pos[i] = RC_UNSET;
+        par[i] = RC_UNSET;
+    }
+}
+
+// Each component's start takes the component's first place and joins the
+// first frontier.
+__global__ void k_rc_seed(int64_t n, const uint32_t *__restrict__ size, const uint32_t *__restrict__ off,
+                          const unsigned long long *__restrict__ start, uint32_t *__restrict__ pos,
+                          uint32_t *__restrict__ fill, uint32_t *__restrict__ front, unsigned int *__restrict__ cnt) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        if (size[r] == 0) continue;
+        const uint32_t v = (uint32_t)(start[r] & 0xffffffffull);
+        pos[v] = off[r];
+        fill[r] = off[r] + 1u;
+        front[atomicAdd(&cnt[0], 1u)] = v;
+    }
+}
+
+// One wave per frontier vertex: every unplaced neighbour keeps the smallest
+// place among its frontier neighbours; the first to reach it lists it.
+__global__ void k_rc_expand(unsigned int nf, const uint32_t *__restrict__ front, const int64_t *__restrict__ row_ptr,
+                            const int32_t *__restrict__ col, const uint32_t *__restrict__ pos,
+                            uint32_t *__restrict__ par, uint32_t *__restrict__ cand, unsigned int *__restrict__ ncand) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned int nw = gridDim.x * (IBLOCK / WAVE);
+    for (unsigned int f = blockIdx.x * (IBLOCK / WAVE) + (threadIdx.x >> 6); f < nf; f += nw) {
+        const uint32_t v = front[f];
+        const uint32_t pv = pos[v];
+        const int64_t b1 = row_ptr[v + 1];
+        for (int64_t p = row_ptr[v] + lane; p < b1; p += WAVE) {
+            const int32_t u = col[p];
+            if (pos[u] != RC_UNSET) continue;
+            if (atomicMin(&par[u], pv) == RC_UNSET) cand[atomicAdd(ncand, 1u)] = (uint32_t)u;
+        }
+    }
+}
+
+// Sort key of a candidate: (smallest neighbour place, degree); its id breaks
+// ties through the stable sort of candidates already in id order.
+__global__ void k_rc_keys(unsigned int nc, const uint32_t *__restrict__ cand, const uint32_t *__restrict__ par,
+                          const int64_t *__restrict__ row_ptr, unsigned long long *__restrict__ key) {
+    for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+        const uint32_t u = cand[i];
+        key[i] = ((unsigned long long)par[u] << 32) | (unsigned long long)(row_ptr[u + 1] - row_ptr[u]);
+    }
+}
+
+// A component's candidates are contiguous in the sorted level (their
+// parents' places lie in the component's range): first index of each run,
+// the places, then the component's next free place.
+__global__ void k_rc_first(unsigned int nc, const uint32_t *__restrict__ vert, const int32_t *__restrict__ root,
+                           uint32_t *__restrict__ first) {
+    for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+        const int32_t r = root[vert[i]];
+        if (i == 0 || root[vert[i - 1]] != r) first[r] = i;
+    }
+}
+
+__global__ void k_rc_place(unsigned int nc, const uint32_t *__restrict__ vert, const int32_t *__restrict__ root,
+                           const uint32_t *__restrict__ first, const uint32_t *__restrict__ fill,
+                           uint32_t *__restrict__ pos) {
+    for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+        const uint32_t u = vert[i];
+        const int32_t r = root[u];
+        pos[u] = fill[r] + (i - first[r]);
+    }
+}
+
+__global__ void k_rc_advance(unsigned int nc, const uint32_t *__restrict__ vert, const int32_t *__restrict__ root,
+                             const uint32_t *__restrict__ first, uint32_t *__restrict__ fill) {
+    for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+        const int32_t r = root[vert[i]];
+        if (i + 1 == nc || root[vert[i + 1]] != r) fill[r] += i - first[r] + 1u;
+    }
+}
+
+// Reversed: the vertex at Cuthill-McKee place q is stored as n - 1 - q.
+__global__ void k_rc_order(int64_t n, const uint32_t *__restrict__ pos, uint32_t *__restrict__ vid_sorted) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        vid_sorted[n - 1 - (int64_t)pos[v]] = (uint32_t)v;
+}
+
 struct IngestLayout {
     unsigned long long *key0, *key1;     // [m_in] pair keys (sort double buffer)
     uint32_t *idx0, *idx1;               // [m_in] list indices / edge ids
@@ -440,6 +548,16 @@ struct IngestLayout {
     unsigned long long *vkey0, *vkey1;   // [n]
     uint32_t *vid0, *vid1;               // [n]
     unsigned int *flags;                 // [4]: error bits, d_max, runs for a workgroup, runs for a wave
+    // reverse Cuthill-McKee order ([n] each)
+    int32_t *rc_root;                    // component of every vertex (its smallest id)
+    uint32_t *rc_pos;                    // place in the Cuthill-McKee order (RC_UNSET before)
+    uint32_t *rc_par;                    // smallest place among a candidate's placed neighbours
+    uint32_t *rc_size, *rc_off, *rc_fill, *rc_first;  // per component root: size, first place, next place,
+                                                      // first index in the sorted candidates
+    unsigned long long *rc_start;        // per component root: (degree << 32 | id) of its start
+    uint32_t *rc_front, *rc_cand, *rc_cand2, *rc_vert;
+    unsigned long long *rc_key0, *rc_key1;
+    unsigned int *rc_cnt;                // [2]: frontier size, candidates
     void *temp;                          // rocPRIM temporary storage
     size_t temp_bytes;
 };
@@ -464,6 +582,11 @@ static size_t rocprim_temp_bytes(int64_t m_in, int64_t n) {
     need = std::max(need, e == hipSuccess ? t : 0);
     e = rocprim::exclusive_scan(nullptr, t, (uint64_t *)nullptr, (uint64_t *)nullptr, (uint64_t)0, nn + 1,
                                 rocprim::plus<uint64_t>());
+    need = std::max(need, e == hipSuccess ? t : 0);
+    e = rocprim::exclusive_scan(nullptr, t, (uint32_t *)nullptr, (uint32_t *)nullptr, 0u, nn,
+                                rocprim::plus<uint32_t>());
+    need = std::max(need, e == hipSuccess ? t : 0);
+    e = rocprim::radix_sort_keys(nullptr, t, (uint32_t *)nullptr, (uint32_t *)nullptr, nn, 0, 32);
     need = std::max(need, e == hipSuccess ? t : 0);
     return need;
 }
@@ -494,6 +617,21 @@ static size_t ingest_layout(int64_t n, int64_t m_in, void *ws, size_t ws_bytes, 
     l.vid0 = c.take<uint32_t>(nn);
     l.vid1 = c.take<uint32_t>(nn);
     l.flags = c.take<unsigned int>(4);
+    l.rc_root = c.take<int32_t>(nn);
+    l.rc_pos = c.take<uint32_t>(nn);
+    l.rc_par = c.take<uint32_t>(nn);
+    l.rc_size = c.take<uint32_t>(nn);
+    l.rc_off = c.take<uint32_t>(nn);
+    l.rc_fill = c.take<uint32_t>(nn);
+    l.rc_first = c.take<uint32_t>(nn);
+    l.rc_start = c.take<unsigned long long>(nn);
+    l.rc_front = c.take<uint32_t>(nn);
+    l.rc_cand = c.take<uint32_t>(nn);
+    l.rc_cand2 = c.take<uint32_t>(nn);
+    l.rc_vert = c.take<uint32_t>(nn);
+    l.rc_key0 = c.take<unsigned long long>(nn);
+    l.rc_key1 = c.take<unsigned long long>(nn);
+    l.rc_cnt = c.take<unsigned int>(2);
     l.temp_bytes = rocprim_temp_bytes(m_in, n);
     l.temp = c.take<char>(l.temp_bytes);
     if (L) *L = l;
@@ -535,6 +673,147 @@ static ad_status edge_counts(int64_t n, int64_t m, const int32_t *ea, const int3
     hipLaunchKernelGGL(k_count_finish, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.vid1, L.lower_cnt, L.upper_cnt,
                        L.deg);
     AD_LAUNCH_CHECK("k_count_finish");
+    return AD_OK;
+}
+
+// The edges (ea < eb, sorted by (ea, eb); weights ew or NULL) as the
+// symmetric CSR: per-row counts (upper_cnt: edges whose smaller endpoint is
+// the row, lower_cnt: larger), the edges sorted by larger endpoint
+// (idx1 / edge_of), the degrees and their maximum (flags[1]), row_ptr, then
+// the upper entries in edge order and the lower ones.  w_out NULL: no weights.
+static ad_status place_csr(int64_t n, int64_t m, const int32_t *ea, const int32_t *eb, const float *ew,
+                           int64_t *row_ptr, int32_t *col, float *w_out, int32_t *eid, const IngestLayout &L,
+                           hipStream_t st) {
+    ad_status s;
+    if (n > 0) {
+        s = fill_i32((int32_t *)L.deg, 0, n, st);
+        if (s != AD_OK) return s;
+        if (m > 0) {
+            s = edge_counts(n, m, ea, eb, L, st);
+            if (s != AD_OK) return s;
+        } else {
+            s = fill_i32((int32_t *)L.lower_cnt, 0, n, st);
+            if (s != AD_OK) return s;
+            s = fill_i32((int32_t *)L.upper_cnt, 0, n, st);
+            if (s != AD_OK) return s;
+        }
+        hipLaunchKernelGGL(k_degree_max, dim3(std::min<unsigned>(1024, igrid(n))), dim3(IBLOCK), 0, st, n, L.deg,
+                           L.flags + 1);
+        AD_LAUNCH_CHECK("k_degree_max");
+    }
+    // row_ptr = exclusive scan of the degrees over n + 1 entries (the last one 0)
+    s = fill_i32((int32_t *)(L.deg64 + n), 0, 2, st);
+    if (s != AD_OK) return s;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_u32_to_u64, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.deg, L.deg64);
+        AD_LAUNCH_CHECK("k_u32_to_u64");
+    }
+    size_t tb = L.temp_bytes;
+    AD_RP(rocprim::exclusive_scan(L.temp, tb, L.deg64, (uint64_t *)row_ptr, (uint64_t)0, (size_t)n + 1,
+                                  rocprim::plus<uint64_t>(), st));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_u32_to_u64, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.upper_cnt, L.deg64);
+        AD_LAUNCH_CHECK("k_u32_to_u64");
+        tb = L.temp_bytes;
+        AD_RP(rocprim::exclusive_scan(L.temp, tb, L.deg64, L.upper_start, (uint64_t)0, (size_t)n,
+                                      rocprim::plus<uint64_t>(), st));
+        hipLaunchKernelGGL(k_u32_to_u64, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.lower_cnt, L.deg64);
+        AD_LAUNCH_CHECK("k_u32_to_u64");
+        tb = L.temp_bytes;
+        AD_RP(rocprim::exclusive_scan(L.temp, tb, L.deg64, L.lower_start, (uint64_t)0, (size_t)n,
+                                      rocprim::plus<uint64_t>(), st));
+        hipLaunchKernelGGL(k_place_upper, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, ew, row_ptr, L.lower_cnt,
+                           L.upper_start, col, w_out, eid);
+        AD_LAUNCH_CHECK("k_place_upper");
+        // lower entries from the edges sorted (stably) by their larger endpoint
+        hipLaunchKernelGGL(k_place_lower, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, L.idx1, L.edge_of, ea, ew, row_ptr,
+                           L.lower_start, col, w_out, eid);
+        AD_LAUNCH_CHECK("k_place_lower");
+    }
+    return AD_OK;
+}
+
+// Relabel the edges by new_of and number them again in (smaller, larger)
+// order: ea, eb rewritten, the weights (when given) permuted into ew2.
+static ad_status relabel_edges(int64_t m, const int32_t *ea, const int32_t *eb, const float *ew,
+                               const IngestLayout &L, hipStream_t st) {
+    if (m <= 0) return AD_OK;
+    hipLaunchKernelGGL(k_relabel_keys, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, L.new_of, L.key0, L.idx0);
+    AD_LAUNCH_CHECK("k_relabel_keys");
+    size_t tb = L.temp_bytes;
+    AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.key0, L.key1, L.idx0, L.idx1, (size_t)m, 0, 64, st));
+    hipLaunchKernelGGL(k_unpack_edges, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, L.key1, L.idx1, ew, L.ea, L.eb,
+                       L.ew2);
+    AD_LAUNCH_CHECK("k_unpack_edges");
+    return AD_OK;
+}
+
+// Reverse Cuthill-McKee order of the CSR (n vertices, m edges): vid_sorted[r]
+// is the vertex stored at r.  One host read-back per level of the search.
+static ad_status rcm_order(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, const int32_t *eid,
+                           const IngestLayout &L, uint32_t *vid_sorted, hipStream_t st) {
+    ad_graph g{};
+    g.n = n;
+    g.m = m;
+    g.row_ptr = row_ptr;
+    g.col = m > 0 ? col : nullptr;
+    g.eid = m > 0 ? eid : nullptr;
+    ad_status s = label_components(&g, L.rc_root, nullptr, st);
+    if (s != AD_OK) return s;
+    s = fill_i32((int32_t *)L.rc_size, 0, n, st);
+    if (s != AD_OK) return s;
+    s = fill_u64(L.rc_start, ~0ull, n, st);
+    if (s != AD_OK) return s;
+    s = fill_i32((int32_t *)L.rc_cnt, 0, 2, st);
+    if (s != AD_OK) return s;
+    hipLaunchKernelGGL(k_rc_init, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, row_ptr, L.rc_root, L.rc_size, L.rc_start,
+                       L.rc_pos, L.rc_par);
+    AD_LAUNCH_CHECK("k_rc_init");
+    size_t tb = L.temp_bytes;
+    AD_RP(rocprim::exclusive_scan(L.temp, tb, L.rc_size, L.rc_off, 0u, (size_t)n, rocprim::plus<uint32_t>(), st));
+    hipLaunchKernelGGL(k_rc_seed, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.rc_size, L.rc_off, L.rc_start, L.rc_pos,
+                       L.rc_fill, L.rc_front, L.rc_cnt);
+    AD_LAUNCH_CHECK("k_rc_seed");
+    unsigned int nf = 0;
+    AD_HIP(hipMemcpyAsync(&nf, L.rc_cnt, sizeof(nf), hipMemcpyDeviceToHost, st));
+    AD_HIP(hipStreamSynchronize(st));
+    uint32_t *front = L.rc_front, *next = L.rc_vert;
+    const unsigned wgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, IBLOCK / WAVE)));
+    int64_t placed = nf;
+    while (nf > 0 && placed < n) {
+        s = fill_i32((int32_t *)L.rc_cnt + 1, 0, 1, st);
+        if (s != AD_OK) return s;
+        hipLaunchKernelGGL(k_rc_expand, dim3(wgrid), dim3(IBLOCK), 0, st, nf, front, row_ptr, col, L.rc_pos, L.rc_par,
+                           L.rc_cand, L.rc_cnt + 1);
+        AD_LAUNCH_CHECK("k_rc_expand");
+        unsigned int nc = 0;
+        AD_HIP(hipMemcpyAsync(&nc, L.rc_cnt + 1, sizeof(nc), hipMemcpyDeviceToHost, st));
+        AD_HIP(hipStreamSynchronize(st));
+        if (nc == 0) break;
+        if ((int64_t)nc > n - placed) return fail(AD_ERR_INTERNAL, "search listed a vertex twice");
+        // candidates by id, then stably by (parent place, degree)
+        tb = L.temp_bytes;
+        AD_RP(rocprim::radix_sort_keys(L.temp, tb, L.rc_cand, L.rc_cand2, (size_t)nc, 0, bits_for(n), st));
+        hipLaunchKernelGGL(k_rc_keys, dim3(igrid(nc)), dim3(IBLOCK), 0, st, nc, L.rc_cand2, L.rc_par, row_ptr,
+                           L.rc_key0);
+        AD_LAUNCH_CHECK("k_rc_keys");
+        tb = L.temp_bytes;
+        AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.rc_key0, L.rc_key1, L.rc_cand2, next, (size_t)nc, 0, 64, st));
+        hipLaunchKernelGGL(k_rc_first, dim3(igrid(nc)), dim3(IBLOCK), 0, st, nc, next, L.rc_root, L.rc_first);
+        AD_LAUNCH_CHECK("k_rc_first");
+        hipLaunchKernelGGL(k_rc_place, dim3(igrid(nc)), dim3(IBLOCK), 0, st, nc, next, L.rc_root, L.rc_first,
+                           L.rc_fill, L.rc_pos);
+        AD_LAUNCH_CHECK("k_rc_place");
+        hipLaunchKernelGGL(k_rc_advance, dim3(igrid(nc)), dim3(IBLOCK), 0, st, nc, next, L.rc_root, L.rc_first,
+                           L.rc_fill);
+        AD_LAUNCH_CHECK("k_rc_advance");
+        std::swap(front, next);
+        nf = nc;
+        placed += nc;
+    }
+    if (placed != n) return fail(AD_ERR_INTERNAL, "search did not place every vertex");
+    hipLaunchKernelGGL(k_rc_order, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.rc_pos, vid_sorted);
+    AD_LAUNCH_CHECK("k_rc_order");
     return AD_OK;
 }
 
@@ -603,69 +882,26 @@ static ad_status ingest_impl(int64_t n, int64_t m_in, const int32_t *u, const in
         AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.vkey0, L.vkey1, L.vid0, L.vid1, (size_t)n, 0, 64, st));
         hipLaunchKernelGGL(k_new_ids, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.vid1, L.new_of, orig_in, orig_out);
         AD_LAUNCH_CHECK("k_new_ids");
-        if (m > 0) {
-            hipLaunchKernelGGL(k_relabel_keys, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, L.new_of, L.key0,
-                               L.idx0);
-            AD_LAUNCH_CHECK("k_relabel_keys");
-            tb = L.temp_bytes;
-            AD_RP(rocprim::radix_sort_pairs(L.temp, tb, L.key0, L.key1, L.idx0, L.idx1, (size_t)m, 0, 64, st));
-            hipLaunchKernelGGL(k_unpack_edges, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, L.key1, L.idx1,
-                               w ? L.ew : (const float *)nullptr, L.ea, L.eb, L.ew2);
-            AD_LAUNCH_CHECK("k_unpack_edges");
-            ew = L.ew2;
-        }
+        s = relabel_edges(m, ea, eb, w ? ew : nullptr, L, st);
+        if (s != AD_OK) return s;
+        if (m > 0) ew = L.ew2;
+    } else if (order == 2 && n > 0) {
+        // the graph under the listed ids (in the outputs, rewritten below) for the search
+        s = place_csr(n, m, ea, eb, nullptr, row_ptr, col, nullptr, eid, L, st);
+        if (s != AD_OK) return s;
+        s = rcm_order(n, m, row_ptr, col, eid, L, L.vid1, st);
+        if (s != AD_OK) return s;
+        hipLaunchKernelGGL(k_new_ids, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.vid1, L.new_of, orig_in, orig_out);
+        AD_LAUNCH_CHECK("k_new_ids");
+        s = relabel_edges(m, ea, eb, w ? ew : nullptr, L, st);
+        if (s != AD_OK) return s;
+        if (m > 0) ew = L.ew2;
     } else if (n > 0) {
         hipLaunchKernelGGL(k_orig_identity, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, orig_in, orig_out);
         AD_LAUNCH_CHECK("k_orig_identity");
     }
-    // per-row counts under the final labels (upper_cnt: edges whose smaller
-    // endpoint is the row, lower_cnt: larger), the edges sorted by larger
-    // endpoint (idx1 / edge_of), and the degrees
-    if (n > 0) {
-        s = fill_i32((int32_t *)L.deg, 0, n, st);
-        if (s != AD_OK) return s;
-        if (m > 0) {
-            s = edge_counts(n, m, ea, eb, L, st);
-            if (s != AD_OK) return s;
-        } else {
-            s = fill_i32((int32_t *)L.lower_cnt, 0, n, st);
-            if (s != AD_OK) return s;
-            s = fill_i32((int32_t *)L.upper_cnt, 0, n, st);
-            if (s != AD_OK) return s;
-        }
-        hipLaunchKernelGGL(k_degree_max, dim3(std::min<unsigned>(1024, igrid(n))), dim3(IBLOCK), 0, st, n, L.deg,
-                           L.flags + 1);
-        AD_LAUNCH_CHECK("k_degree_max");
-    }
-    // row_ptr = exclusive scan of the degrees over n + 1 entries (the last one 0)
-    s = fill_i32((int32_t *)(L.deg64 + n), 0, 2, st);
+    s = place_csr(n, m, ea, eb, w ? ew : nullptr, row_ptr, col, w ? w_out : nullptr, eid, L, st);
     if (s != AD_OK) return s;
-    if (n > 0) {
-        hipLaunchKernelGGL(k_u32_to_u64, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.deg, L.deg64);
-        AD_LAUNCH_CHECK("k_u32_to_u64");
-    }
-    size_t tb = L.temp_bytes;
-    AD_RP(rocprim::exclusive_scan(L.temp, tb, L.deg64, (uint64_t *)row_ptr, (uint64_t)0, (size_t)n + 1,
-                                  rocprim::plus<uint64_t>(), st));
-    if (m > 0) {
-        hipLaunchKernelGGL(k_u32_to_u64, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.upper_cnt, L.deg64);
-        AD_LAUNCH_CHECK("k_u32_to_u64");
-        tb = L.temp_bytes;
-        AD_RP(rocprim::exclusive_scan(L.temp, tb, L.deg64, L.upper_start, (uint64_t)0, (size_t)n,
-                                      rocprim::plus<uint64_t>(), st));
-        hipLaunchKernelGGL(k_u32_to_u64, dim3(igrid(n)), dim3(IBLOCK), 0, st, n, L.lower_cnt, L.deg64);
-        AD_LAUNCH_CHECK("k_u32_to_u64");
-        tb = L.temp_bytes;
-        AD_RP(rocprim::exclusive_scan(L.temp, tb, L.deg64, L.lower_start, (uint64_t)0, (size_t)n,
-                                      rocprim::plus<uint64_t>(), st));
-        hipLaunchKernelGGL(k_place_upper, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, ea, eb, ew, row_ptr, L.lower_cnt,
-                           L.upper_start, col, w ? w_out : (float *)nullptr, eid);
-        AD_LAUNCH_CHECK("k_place_upper");
-        // lower entries from the edges sorted (stably) by their larger endpoint
-        hipLaunchKernelGGL(k_place_lower, dim3(igrid(m)), dim3(IBLOCK), 0, st, m, L.idx1, L.edge_of, ea, ew, row_ptr,
-                           L.lower_start, col, w ? w_out : (float *)nullptr, eid);
-        AD_LAUNCH_CHECK("k_place_lower");
-    }
     unsigned int dmax = 0;
     if (n > 0) AD_HIP(hipMemcpyAsync(&dmax, L.flags + 1, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
     AD_HIP(hipStreamSynchronize(st));
@@ -691,7 +927,8 @@ extern "C" ad_status ad_ingest(int64_t n, int64_t m_in, const int32_t *u, const 
     if (n < 0 || m_in < 0) return fail(AD_ERR_INVALID_ARG, "negative n or edge count");
     if (n >= ((int64_t)1 << 31) || m_in >= ((int64_t)1 << 31))
         return fail(AD_ERR_UNSUPPORTED, "n and the edge count must be below 2^31");
-    if (order != 0 && order != 1) return fail(AD_ERR_INVALID_ARG, "order must be 0 (as listed) or 1 (by degree)");
+    if (order < 0 || order > 2)
+        return fail(AD_ERR_INVALID_ARG, "order must be 0 (as listed), 1 (by degree) or 2 (reverse Cuthill-McKee)");
     if (m_in > 0 && (!u || !v)) return fail(AD_ERR_INVALID_ARG, "u or v is NULL");
     if (!row_ptr || !m_host) return fail(AD_ERR_INVALID_ARG, "row_ptr or m_host is NULL");
     if (m_in > 0 && (!col || !eid)) return fail(AD_ERR_INVALID_ARG, "col or eid is NULL");

@@ -376,6 +376,10 @@ ad_status edge_dist_segs(const ad_graph *g, int32_t R, ad_dtype x_dtype, const v
                          ad_dtype rho_dtype, void *rho, void *ws, size_t ws_bytes, const Segs &sg,
                          hipStream_t stream, float *rho_ent = nullptr);
 
+// Connected components by union-find: parent[i] = the smallest vertex of
+// i's component (flags unused, may be NULL).
+ad_status label_components(const ad_graph *g, int32_t *parent, unsigned int *flags, hipStream_t stream);
+
 // Algorithm 3 at fixed per-degree budgets, keep[] only (rows are independent,
 // so packed graphs need no segment information).
 size_t sparsify_workspace(const ad_graph *g);

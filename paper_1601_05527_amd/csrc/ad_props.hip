@@ -553,7 +553,7 @@ static size_t prop_layout(const ad_graph *g, void *ws, size_t ws_bytes, PropLayo
 // trees have no cycles, every root search ends, and each component's root
 // is its smallest vertex whatever the order of the joins.  No host round
 // trips.
-static ad_status label_components(const ad_graph *g, int32_t *parent, unsigned int *flags, hipStream_t stream) {
+ad_status label_components(const ad_graph *g, int32_t *parent, unsigned int *flags, hipStream_t stream) {
     (void)flags;
     const int64_t n = g->n;
     const unsigned wgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, PBLOCK / WAVE)));

@@ -226,7 +226,8 @@ def test_ingest_rejects_bad_arguments():
     assert call(n=-1) == 1
     assert call(m_in=-2) == 1
     assert call(n=1 << 31) == 2
-    assert call(order=2) == 1
+    assert call(order=3) == 1
+    assert call(order=-1) == 1
     assert call(u=None) == 1
     assert call(rp=None) == 1
     assert call(col=None) == 1

@@ -42,9 +42,9 @@ def _list(n, m_in, seed, dup_frac=0.2, loop_frac=0.02):
     return u[perm].astype(np.int32), v[perm].astype(np.int32), w
 
 
-def _run(api, n, u, v, w=None, orig=None, by_degree=True):
+def _run(api, n, u, v, w=None, orig=None, by_degree=True, order=None):
     cu = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    return api.ingest(n, cu(u), cu(v), cu(w), cu(orig), by_degree=by_degree)
+    return api.ingest(n, cu(u), cu(v), cu(w), cu(orig), by_degree=by_degree, order=order)
 
 
 def _compare(dg, ref):
@@ -170,6 +170,61 @@ def test_ingest_orig_ids_and_reuse(api):
     assert torch.equal(a.x, b.x) and torch.equal(a.minmax, b.minmax)
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_ingest_rcm_bit_exact(api, seed, weighted):
+    """Reverse Cuthill-McKee order (order 2) against the oracle on random
+    lists with repeats and loops (one large component, isolated vertices)."""
+    announce(f"ingest rcm seed={seed} weighted={weighted}")
+    n = [300, 5000, 70_000][seed]
+    u, v, w = _list(n, 8 * n, seed)
+    w = w if weighted else None
+    dg = _run(api, n, u, v, w, order="rcm")
+    _compare(dg, oracle.ingest(n, u, v, w, order=2))
+
+
+@pytest.mark.parametrize("kind", ["components", "grid", "path", "power_law"])
+def test_ingest_rcm_shapes(api, kind):
+    """Many components of different sizes searched at once; a grid (a few
+    hundred levels, many degree ties); a path (one level per vertex); a
+    power-law graph (hub rows, many equal degrees)."""
+    announce(f"ingest rcm {kind}")
+    rng = np.random.default_rng(7)
+    if kind == "components":
+        us, vs, base = [], [], 0
+        for size in [1, 2, 3, 10, 50, 400, 2000, 1, 7, 300]:
+            if size > 1:
+                a = rng.integers(0, size, 3 * size)
+                b = (a + rng.integers(1, size, 3 * size)) % size
+                us.append(a + base)
+                vs.append(b + base)
+            base += size
+        n = base + 100                                     # 100 isolated vertices at the end
+        perm = rng.permutation(n)
+        u, v = perm[np.concatenate(us)], perm[np.concatenate(vs)]
+    elif kind == "grid":
+        k = 120
+        idx = np.arange(k * k).reshape(k, k)
+        u = np.concatenate([idx[:, :-1].ravel(), idx[:-1, :].ravel()])
+        v = np.concatenate([idx[:, 1:].ravel(), idx[1:, :].ravel()])
+        n = k * k
+        perm = rng.permutation(n)
+        u, v = perm[u], perm[v]
+    elif kind == "path":
+        n = 3000
+        perm = rng.permutation(n)
+        u, v = perm[:-1], perm[1:]
+    else:
+        g = G.chung_lu(20_000, 150_000, seed=5)
+        rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+        up = g.col > rows
+        n, u, v = g.n, rows[up], g.col[up]
+    u, v = u.astype(np.int32), v.astype(np.int32)
+    w = rng.uniform(0.5, 2.0, u.size).astype(np.float32)
+    dg = _run(api, n, u, v, w, order="rcm")
+    _compare(dg, oracle.ingest(n, u, v, w, order=2))
+
+
 def test_ingest_edge_cases(api):
     announce("ingest edge cases")
     z = np.zeros(0, dtype=np.int32)
@@ -182,6 +237,11 @@ def test_ingest_edge_cases(api):
     one = _run(api, 2, np.array([1], dtype=np.int32), np.array([0], dtype=np.int32),
                np.array([2.5], dtype=np.float32), by_degree=False)
     _compare(one, oracle.ingest(2, [1], [0], [2.5], order=0))
+    # reverse Cuthill-McKee with no edges (every vertex a component of its own),
+    # only loops, and one edge among isolated vertices
+    for n, uu, vv in [(5, z, z), (4, only_loops, only_loops), (6, np.array([4], np.int32), np.array([1], np.int32))]:
+        dg = _run(api, n, uu, vv, order="rcm")
+        _compare(dg, oracle.ingest(n, uu, vv, order=2))
     with pytest.raises(api.ADError) as ex:
         _run(api, 4, np.array([0, 4], dtype=np.int32), np.array([1, 1], dtype=np.int32))
     assert ex.value.status == 4       # AD_ERR_GRAPH
