@@ -307,6 +307,21 @@ def run_chung_lu(args, api, torch, dev):
     torch.cuda.synchronize()
     step_ms, kern = traced(api, timer, step, args.steps)
     rd_ms = timer.run(relax_dist, args.steps)     # relax + distance alone, the bandwidth path
+    # the step without the e-fit: both selections at the fitted exponents
+    bud_l = torch.from_numpy(api.budget_table(dg.d_max, fit["e_local"])).to(dev)
+    bud_g = torch.from_numpy(api.budget_table(dg.d_max, fit["e_global"])).to(dev)
+    keep_fl, keep_fg = torch.empty_like(keep_l), torch.empty_like(keep_g)
+    nk_f = torch.empty(2, dtype=torch.int64, device=dev)
+
+    def step_fixed():
+        relax_dist()
+        api.sparsify(dg, rho, 0, budget=bud_l, ws=ws_s, keep=keep_fl, n_kept=nk_f[0:1])
+        api.sparsify(dg, rho, 1, budget=bud_g, ws=ws_s, keep=keep_fg, n_kept=nk_f[1:2])
+
+    step_fixed()
+    fixed_ms = timer.run(step_fixed, args.steps)
+    fixed_same = bool(torch.equal(keep_fl, keep_l) and torch.equal(keep_fg, keep_g) and torch.equal(nk_f, nk))
+    del bud_l, bud_g, keep_fl, keep_fg
 
     kept_l, kept_g = (int(v) for v in nk.tolist())
     weighted = dg.w is not None
@@ -449,6 +464,9 @@ def run_chung_lu(args, api, torch, dev):
         config, roof, cpu,
         breakdown_ms_per_step={k_: v[1] / args.steps for k_, v in sorted(kern.items())},
         relax_dist_ms=rd_ms, relax_dist_hbm_frac=rd_gbs / HBM_PEAK_GBS,
+        step_fixed_e={"ms": fixed_ms, "equals_fitted_masks": fixed_same,
+                      "what": "relax + distances + LOCAL and GLOBAL selection at the fitted exponents "
+                              "(ad_sparsify twice, budget tables already on the device): the step without the e-fit"},
         relax_dist_fp32_only_ms=rd32_ms,
         copy_ceiling_GBs=copy_gbs,
         gather_ceiling=gather,
