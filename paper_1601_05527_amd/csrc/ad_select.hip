@@ -720,6 +720,11 @@ __global__ __launch_bounds__(TB) void k_rank_bitonic(
 // their order inside the run from the neighbour ids (distinct within a row),
 // counted against the run.  LOCAL rank = a + place in run, GLOBAL rank =
 // (d - b) + place in run, as Algorithm 3 orders the row both ways.
+// Largest sort key of a real entry: padding (0xffffffff) must sort after
+// every entry, so the one bit pattern that could equal it (a negative NaN)
+// is clamped below it; valid distances (>= 0) are far below.
+constexpr uint32_t KEY_LAST = 0xfffffffeu;
+
 template <int TB, int IPT>
 __global__ __launch_bounds__(TB) void k_rank_radix(
     const int32_t *__restrict__ list, const unsigned int *__restrict__ count,
@@ -752,7 +757,7 @@ __global__ __launch_bounds__(TB) void k_rank_radix(
 #pragma unroll
             for (int s = 0; s < IPT; ++s) {
                 const int q = s * TB + (int)threadIdx.x;
-                k[s] = q < d ? __float_as_uint(rho_ent[beg + q]) : 0xffffffffu;
+                k[s] = q < d ? min(__float_as_uint(rho_ent[beg + q]), KEY_LAST) : 0xffffffffu;
                 v[s] = (uint16_t)q;
             }
         } else {
@@ -765,7 +770,7 @@ __global__ __launch_bounds__(TB) void k_rank_radix(
 #pragma unroll
             for (int s = 0; s < IPT; ++s) {
                 const int q = s * TB + (int)threadIdx.x;
-                k[s] = q < d ? __float_as_uint(rho[e[s]]) : 0xffffffffu;
+                k[s] = q < d ? min(__float_as_uint(rho[e[s]]), KEY_LAST) : 0xffffffffu;
                 v[s] = (uint16_t)q;
             }
         }
@@ -1211,7 +1216,7 @@ __global__ __launch_bounds__(WAVE) void k_hub_sort(
 #pragma unroll
         for (int s = 0; s < IPT; ++s) {
             const uint32_t q = (uint32_t)(s * WAVE) + threadIdx.x;
-            k[s] = q < c ? (uint32_t)(bk[q] >> 32) : 0xffffffffu;
+            k[s] = q < c ? min((uint32_t)(bk[q] >> 32), KEY_LAST) : 0xffffffffu;
             v[s] = (uint16_t)q;
         }
         Sorter().sort(k, v, sh.sort);                // blocked: thread t holds sorted places t * IPT + s

@@ -582,3 +582,26 @@ def test_ranking_from_two_host_threads(api):
         t.join(timeout=120)
     assert not any(t.is_alive() for t in th)
     assert errors == []
+
+
+def test_sorted_rows_with_the_padding_bit_pattern(api, mixed):
+    """Distances carrying the bit pattern 0xffffffff (a negative NaN, which
+    no distance pass produces but a caller could pass) in rows ranked by the
+    LDS sorts and in rows above 8,192: the sort padding still sorts last, so
+    every rank stays inside its row, the calls succeed, and the counts equal
+    the masks."""
+    announce("padding bit pattern in sorted rows")
+    for g in (mixed[0], _long_row_graph()):
+        rho = np.random.default_rng(47).uniform(0.01, 1.0, g.m).astype(np.float32)
+        bad = np.random.default_rng(48).choice(g.m, max(1, g.m // 50), replace=False)
+        rho.view(np.uint32)[bad] = 0xFFFFFFFF
+        dg = _dg(api, g)
+        rt = torch.from_numpy(rho).cuda()
+        for orient in (0, 1):
+            keep, n_kept = api.sparsify(dg, rt, orient, 0.5)
+            k = _np(keep)
+            assert set(np.unique(k).tolist()) <= {0, 1}
+            assert int(_np(n_kept)[0]) == int(k.sum())
+        kl, kg, nk, (el, eg) = api.sparsify_fit_both(dg, rt, 0.3)
+        assert 0.0 <= el <= 1.0 and 0.0 <= eg <= 1.0
+        assert _np(nk).tolist() == [int(_np(kl).sum()), int(_np(kg).sum())]
