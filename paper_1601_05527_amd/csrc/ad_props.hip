@@ -367,17 +367,36 @@ __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) 
     }
 }
 
-// One wave per row: every upper entry joins its two trees.
-__global__ void k_union(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                        int32_t *__restrict__ parent) {
+// Joins in two passes (the sampling idea of Afforest, Sutton et al., 2018):
+// first the first UF_FIRST entries of every row, which in a connected
+// power-law graph already gather most vertices under the root of vertex 0
+// (its component's smallest id); then the remaining entries of every row
+// whose root is not 0 at that moment.  A skipped row's vertex is joined to
+// 0, and any edge from it to a vertex outside 0's tree is taken from that
+// vertex's own row, which is not skipped, so every component is found.
+constexpr int UF_FIRST = 2;
+
+__global__ void k_union_first(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                              int32_t *__restrict__ parent) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = row_ptr[i], e = min(row_ptr[i + 1], b + UF_FIRST);
+        for (int64_t p = b; p < e; ++p) uf_union(parent, (int32_t)i, col[p]);
+    }
+}
+
+// One wave per row: the entries after the first UF_FIRST, unless the row's
+// vertex already hangs under 0.
+__global__ void k_union_rest(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                             int32_t *__restrict__ parent) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = (int64_t)gridDim.x * (PBLOCK / WAVE);
     for (int64_t i = (int64_t)blockIdx.x * (PBLOCK / WAVE) + (threadIdx.x >> 6); i < n; i += nw) {
-        const int64_t b1 = row_ptr[i + 1];
-        for (int64_t p = row_ptr[i] + lane; p < b1; p += WAVE) {
-            const int32_t j = col[p];
-            if (j > i) uf_union(parent, (int32_t)i, j);
-        }
+        const int64_t b = row_ptr[i] + UF_FIRST, b1 = row_ptr[i + 1];
+        if (b >= b1) continue;                                    // uniform across the wave
+        int32_t r = 0;
+        if (lane == 0) r = uf_root(parent, (int32_t)i);
+        if (shfl(r, 0) == 0) continue;
+        for (int64_t p = b + lane; p < b1; p += WAVE) uf_union(parent, (int32_t)i, col[p]);
     }
 }
 
@@ -544,15 +563,13 @@ static size_t prop_layout(const ad_graph *g, void *ws, size_t ws_bytes, PropLayo
     return c.ok() ? c.used : 0;
 }
 
-// Hook and jump until no hook changes a parent; every vertex then holds the
-// smallest vertex of its component.  flags: [3] scratch words.
-// Connected components by union-find: every upper entry (i, j) joins the
-// trees of i and j, hanging the larger root under the smaller with a
-// compare-and-swap, then every vertex is pointed at its root.  Parent ids
-// only ever decrease (a parent is always smaller than its child), so the
-// trees have no cycles, every root search ends, and each component's root
-// is its smallest vertex whatever the order of the joins.  No host round
-// trips.
+// Connected components by union-find: the entries (i, j) join the trees of
+// i and j (k_union_first, then k_union_rest for the rows not yet under 0),
+// hanging the larger root under the smaller with a compare-and-swap, then
+// every vertex is pointed at its root.  Parent ids only ever decrease (a
+// parent is always smaller than its child), so the trees have no cycles,
+// every root search ends, and each component's root is its smallest vertex
+// whatever the order of the joins.  flags is unused.  No host round trips.
 ad_status label_components(const ad_graph *g, int32_t *parent, unsigned int *flags, hipStream_t stream) {
     (void)flags;
     const int64_t n = g->n;
@@ -560,8 +577,10 @@ ad_status label_components(const ad_graph *g, int32_t *parent, unsigned int *fla
     hipLaunchKernelGGL(k_parent_init, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent);
     AD_LAUNCH_CHECK("k_parent_init");
     if (g->m > 0) {
-        hipLaunchKernelGGL(k_union, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, parent);
-        AD_LAUNCH_CHECK("k_union");
+        hipLaunchKernelGGL(k_union_first, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, parent);
+        AD_LAUNCH_CHECK("k_union_first");
+        hipLaunchKernelGGL(k_union_rest, dim3(wgrid), dim3(PBLOCK), 0, stream, n, g->row_ptr, g->col, parent);
+        AD_LAUNCH_CHECK("k_union_rest");
     }
     hipLaunchKernelGGL(k_flatten, dim3(pgrid(n)), dim3(PBLOCK), 0, stream, n, parent);
     AD_LAUNCH_CHECK("k_flatten");
