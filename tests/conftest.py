@@ -13,7 +13,7 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests run on the GPU machine; here they would only fail to find a device.
+    # GPU tests need a device; on a host without one they are skipped.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
