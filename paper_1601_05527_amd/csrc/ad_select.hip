@@ -1770,9 +1770,12 @@ static ad_status rank_all(const ad_graph *g, const Tr *rho, const Emit &em, cons
             if (g->d_max > 256)
                 hipLaunchKernelGGL((k_rank_radix<64, 8>), dim3(grid_w), dim3(64), 0, cls[2], lst[2], &L.cnt[2],
                                    AD_RANK_ARGS_R, 0, 1);
+            // 128..256 after the first half of the longest class, or, with no
+            // rows for the bucket partition, after the short rows on the
+            // caller's stream
             if (g->d_max > 128)
-                hipLaunchKernelGGL((k_rank_radix<64, 4>), dim3(grid_w), dim3(64), 0, cls[0], lst[1], &L.cnt[1],
-                                   AD_RANK_ARGS_R, 0, 1);
+                hipLaunchKernelGGL((k_rank_radix<64, 4>), dim3(grid_w), dim3(64), 0,
+                                   g->d_max > SORT_CAP ? cls[0] : st, lst[1], &L.cnt[1], AD_RANK_ARGS_R, 0, 1);
             AD_LAUNCH_CHECK("k_rank_radix");
 #undef AD_RANK_ARGS_R
         } else {
