@@ -194,9 +194,10 @@ def traced(api, timer, fn, reps):
     return ms, kern
 
 
-LIMITER = ("memory system: random 64-128 B row gathers, each a line fetch missing the XCD's 4 MB L2; "
-           "the line requests leave L2 for the memory side (Infinity Cache and HBM, which no counter on "
-           "this profiler separates) -- see profiles/k_sweep_chung_lu_n2e20_memory_counters.md")
+LIMITER = ("memory-side line-request rate: random 64-128 B row gathers, each a 128 B line request "
+           "when it misses the XCD's 4 MB L2; random line requests are served at about 55 G/s whether "
+           "the lines sit in the Infinity Cache or in HBM, and the FP32 sweep issues about 20.7M per launch "
+           "(about 56 G/s) -- see profiles/k_sweep_chung_lu_n2e20_memory_counters.md")
 
 
 def roofline(kern: dict, bytes_per_launch: float, traffic=None) -> dict:
