@@ -631,8 +631,9 @@ float orc_exact_sum_f32(const float *x, int64_t cnt)
 }
 
 /* Reverse Cuthill-McKee order of the merged graph (ea[e] < eb[e], m
- * edges), the bandwidth-reducing layout named beside the degree order.
- * Readings (the layout is only named): the connected components are taken
+ * edges): a storage layout offered beside the degree order (the paper takes
+ * its graphs as given and discusses no layout; this is the classic
+ * bandwidth-reducing one).  Readings: the connected components are taken
  * in increasing order of their smallest id (an isolated vertex is a
  * component of its own); each is searched breadth first from its vertex of
  * least degree (ties: the smallest id); when a vertex leaves the queue, its
