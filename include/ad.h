@@ -322,7 +322,12 @@ ad_status ad_sparsify_fit_both(const ad_graph *g, ad_dtype rho_dtype, const void
  * output.  Workspace: ad_edge_dist_select_workspace_size bytes (the
  * distance plan, 4 bytes per CSR entry, and the selection workspace of both
  * orders).  The other arguments are those of ad_sparsify and
- * ad_sparsify_fit_both; the fit SYNCHRONISES `stream`. */
+ * ad_sparsify_fit_both (all buffers DEVICE and caller-owned except
+ * e_used_host); ad_edge_dist_sparsify is asynchronous, ad_edge_dist_fit_both
+ * SYNCHRONISES `stream`.  Errors: AD_ERR_INVALID_ARG for R outside [1, 64],
+ * an x_dtype other than AD_F64 / AD_F32, a bad orientation or target, or a
+ * NULL buffer that is needed; AD_ERR_WORKSPACE for a short or misaligned
+ * workspace; all before any work is enqueued. */
 size_t ad_edge_dist_select_workspace_size(const ad_graph *g);
 ad_status ad_edge_dist_sparsify(const ad_graph *g, int32_t R, ad_dtype x_dtype, const void *x,
                                 const double *minmax, float *rho, ad_orient orient,
