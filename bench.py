@@ -109,6 +109,10 @@ def sweep_traffic() -> "float | None":
 
 
 def oracle_threads() -> int:
+    """Threads the oracle's OpenMP loops use (OpenMP's own count once the
+    oracle is loaded; before that the environment's or the affinity mask's)."""
+    if "oracle" in sys.modules:
+        return sys.modules["oracle"].max_threads()
     threads = len(os.sched_getaffinity(0))
     omp = os.environ.get("OMP_NUM_THREADS")
     return int(omp) if omp and omp.isdigit() else threads
@@ -449,6 +453,17 @@ def run_chung_lu(args, api, torch, dev):
                           f"{R} vectors, {args.cpu_sweeps} of the {K} sweeps, then rescale and "
                           f"distances; {t_cpu:.2f}s wall on {cores} threads (about {t_cpu * cores:.0f} "
                           "core-seconds); selection not included")}
+        if args.cpu_sweeps_1t > 0:
+            oracle.set_threads(1)
+            log(f"CPU baseline: oracle, R={R}, {args.cpu_sweeps_1t} sweeps, 1 thread")
+            t0 = time.perf_counter()
+            oracle.algebraic_distance(g_run, R, args.cpu_sweeps_1t, OMEGA, seed=SEED_VEC)
+            t_1 = time.perf_counter() - t0
+            oracle.set_threads(cores)
+            cpu["single_thread"] = {
+                "value": nnz * R * args.cpu_sweeps_1t / t_1, "unit": "edge-vector updates/s", "cores": 1,
+                "sample": (f"the same oracle call with {args.cpu_sweeps_1t} sweeps on one thread, "
+                           f"{t_1:.2f}s wall including start vectors, rescale and distances")}
 
     config = {
         "workload": (f"Chung-Lu power-law graph n=2^20, m={c['m']}, gamma={c['gamma']}, "
@@ -859,6 +874,8 @@ def main() -> int:
                     default="chung-lu")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=6, help="sweeps in the oracle's bounded CPU sample")
+    ap.add_argument("--cpu-sweeps-1t", type=int, default=2,
+                    help="sweeps in the oracle's one-thread sample of the Chung-Lu workload (0: none)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="batch workload: oracle time budget for its graph sample")
     ap.add_argument("--layout", choices=["degree", "given"], default="degree")

@@ -77,6 +77,8 @@ def _load():
     P = ctypes.c_void_p
     i64, i32, u64, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
     lib.orc_philox4x64_10.argtypes = [P, P, P]
+    lib.orc_set_threads.argtypes = [i32]
+    lib.orc_max_threads.restype = i32
     lib.orc_start_value.argtypes = [u64, u64, i32, i32]
     lib.orc_start_value.restype = f64
     lib.orc_start_vectors.argtypes = [i64, i32, u64, u64, P, P]
@@ -135,7 +137,15 @@ def _c(a, dtype):
 
 
 def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (timing only: the
+    results do not depend on the count)."""
     os.environ["OMP_NUM_THREADS"] = str(n)
+    _load().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    """Threads the oracle's next OpenMP loop will use."""
+    return int(_load().orc_max_threads())
 
 
 def philox4x64_10(counter, key) -> np.ndarray:
