@@ -1320,6 +1320,23 @@ constexpr int DIGIT = 11;
 constexpr int NBINS = 1 << DIGIT;
 constexpr double GRID = 1099511627776.0;   // 2^40
 
+// The select's digits of a grid index (at most 2^40, so 41 bits), most
+// significant first: 11 + 11 + 11 + 8 bits.
+constexpr int NPASS = 4;
+constexpr int DIGIT_SHIFT[NPASS] = {30, 19, 8, 0};
+constexpr int DIGIT_WIDTH[NPASS] = {11, 11, 11, 8};
+static_assert(DIGIT_SHIFT[0] + DIGIT_WIDTH[0] == 41 && (1ull << 40) >> DIGIT_SHIFT[0] < NBINS,
+              "the first digit holds the top bits of every grid index");
+
+// Edges per thread per step of the fit's grid-stride loops (loads issued
+// together).
+constexpr int FIT_U = 4;
+
+// Two grid indices in one 16-byte load.
+struct alignas(16) U64x2 {
+    unsigned long long a, b;
+};
+
 // logs[v] = log(v) for v = 1 .. count - 1 (logs[0] unused), and
 // logs[count + v] = 1 / log(v) for v >= 2.
 __global__ void k_log_table(int64_t count, double *__restrict__ logs) {
@@ -1372,8 +1389,9 @@ struct BinRun {
 };
 
 // G_o[e] = the smaller of edge e's two sides' grid indices, and the
-// histogram of the first radix digit of G_o (bits 3 * DIGIT .. 4 * DIGIT - 1),
-// for every fitted orientation o < nfit from one read of the side records.
+// histogram of the first radix digit of G_o (its bits from DIGIT_SHIFT[0]
+// up), for every fitted orientation o < nfit from one read of the side
+// records.  hist must be zero on entry.
 __global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const uint4 *__restrict__ recs,
                                                     const double *__restrict__ logs, int64_t nlogs, int nfit,
                                                     FitArrays fa) {
@@ -1381,18 +1399,31 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const uint4 *__r
     for (int b = threadIdx.x; b < 2 * NBINS; b += SBLOCK) h[b / NBINS][b % NBINS] = 0;
     __syncthreads();
     BinRun run[2];
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const uint4 a = recs[2 * e], b = recs[2 * e + 1];
-        const double ia = logs[nlogs + a.x], ib = logs[nlogs + b.x];
+    constexpr int64_t STEP = (int64_t)SBLOCK * FIT_U;
+    for (int64_t b0 = (int64_t)blockIdx.x * STEP; b0 < m; b0 += (int64_t)gridDim.x * STEP) {
+        uint4 a[FIT_U] = {}, b[FIT_U] = {};
 #pragma unroll
-        for (int o = 0; o < 2; ++o) {
-            if (o >= nfit) break;
-            const unsigned long long ga = side_grid(a.x, rec_rank(a, o), ia, logs);
-            const unsigned long long gb = side_grid(b.x, rec_rank(b, o), ib, logs);
-            const unsigned long long g = ga < gb ? ga : gb;
-            fa.G[o][e] = g;
-            run[o].add(h[o], (int)((g >> (3 * DIGIT)) & (NBINS - 1)));
+        for (int u = 0; u < FIT_U; ++u) {
+            const int64_t e = b0 + u * SBLOCK + threadIdx.x;
+            if (e < m) {
+                a[u] = recs[2 * e];
+                b[u] = recs[2 * e + 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < FIT_U; ++u) {
+            const int64_t e = b0 + u * SBLOCK + threadIdx.x;
+            if (e >= m) continue;
+            const double ia = logs[nlogs + a[u].x], ib = logs[nlogs + b[u].x];
+#pragma unroll
+            for (int o = 0; o < 2; ++o) {
+                if (o >= nfit) break;
+                const unsigned long long ga = side_grid(a[u].x, rec_rank(a[u], o), ia, logs);
+                const unsigned long long gb = side_grid(b[u].x, rec_rank(b[u], o), ib, logs);
+                const unsigned long long g = ga < gb ? ga : gb;
+                fa.G[o][e] = g;
+                run[o].add(h[o], (int)((g >> DIGIT_SHIFT[0]) & (NBINS - 1)));
+            }
         }
     }
 #pragma unroll
@@ -1404,44 +1435,124 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const uint4 *__r
             if (h[o][b]) atomicAdd(&fa.hist[o][b], h[o][b]);
 }
 
-// state[2o] = prefix of selected digits, state[2o + 1] = rank still to skip
-// (1-based inside the prefix), for o < nfit.
-__global__ void k_select_init(unsigned long long *state, unsigned long long K, int nfit) {
-    for (int o = 0; o < nfit; ++o) {
-        state[2 * o] = 0;
-        state[2 * o + 1] = K;
-    }
+// Values of G_o matching the select's first digit, gathered by the second
+// pass so that the last two passes read only them.  n[o] counts every
+// match; when it exceeds cap the list is incomplete and the later passes
+// read G_o again.
+struct CandArrays {
+    unsigned long long *v[2];   // [cap] per fitted orientation
+    unsigned long long *n;      // [2]
+    int64_t cap;
+};
+
+// Zero the histograms and the candidate counts; state[2o] = prefix of
+// selected digits, state[2o + 1] = rank still to skip (1-based inside the
+// prefix), for o < nfit.  One block.
+__global__ __launch_bounds__(SBLOCK) void k_select_init(unsigned long long *state, unsigned long long K, int nfit,
+                                                       unsigned int *hist, unsigned long long *cand_n) {
+    for (int b = threadIdx.x; b < 2 * NBINS; b += SBLOCK) hist[b] = 0;
+    if (threadIdx.x < 2) cand_n[threadIdx.x] = 0;
+    if (threadIdx.x == 0)
+        for (int o = 0; o < nfit; ++o) {
+            state[2 * o] = 0;
+            state[2 * o + 1] = K;
+        }
 }
 
-// Histogram of the next digit of G_o among the edges that match the selected
-// prefix; orientation o = blockIdx.y.
-__global__ __launch_bounds__(SBLOCK) void k_radix_hist(int64_t m, FitArrays fa, int shift, int pass,
-                                                      const unsigned long long *__restrict__ state) {
+constexpr int STAGE = 2048;   // LDS staging of a block's candidates (entries)
+
+// Append the block's staged candidates to the global list (one reservation
+// per block and flush).  Every thread calls it, after a barrier that follows
+// the last staging write.
+__device__ __forceinline__ void stage_flush(const unsigned long long *stage, unsigned int *n_stage,
+                                            unsigned long long *base_sh, unsigned long long *dst,
+                                            unsigned long long *dst_n, int64_t cap) {
+    const unsigned int ns = *n_stage;
+    if (threadIdx.x == 0 && ns) *base_sh = atomicAdd(dst_n, (unsigned long long)ns);
+    __syncthreads();
+    if (ns) {
+        const unsigned long long base = *base_sh;
+        for (unsigned int i = threadIdx.x; i < ns; i += SBLOCK)
+            if (base + i < (unsigned long long)cap) dst[base + i] = stage[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *n_stage = 0;
+    __syncthreads();
+}
+
+// Histogram of the digit at `shift` (`width` bits) of G_o among the values
+// whose higher digits equal the selected prefix; orientation o = blockIdx.y.
+// COMPACT (the second digit's pass) also appends those values to the
+// candidate list; the later passes read the list instead of G_o when it is
+// complete.
+template <bool COMPACT>
+__global__ __launch_bounds__(SBLOCK) void k_radix_hist(int64_t m, FitArrays fa, CandArrays cs, int shift,
+                                                      int width, const unsigned long long *__restrict__ state) {
     __shared__ unsigned int h[NBINS];
+    __shared__ unsigned long long stage[COMPACT ? STAGE : 1];
+    __shared__ unsigned int n_stage;
+    __shared__ unsigned long long base_sh;
     const int o = blockIdx.y;
-    const unsigned long long *__restrict__ G = fa.G[o];
+    const unsigned long long *__restrict__ src = fa.G[o];
+    int64_t count = m;
+    if (!COMPACT) {
+        const unsigned long long nc = cs.n[o];
+        if (nc <= (unsigned long long)cs.cap) {
+            src = cs.v[o];
+            count = (int64_t)nc;
+        }
+    }
     for (int b = threadIdx.x; b < NBINS; b += SBLOCK) h[b] = 0;
+    if (threadIdx.x == 0) n_stage = 0;
     __syncthreads();
     const unsigned long long prefix = state[2 * o];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned long long below = lane ? (~0ull >> (WAVE - lane)) : 0ull;
     BinRun run;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const unsigned long long g = G[e];
-        if (pass > 0 && (g >> (shift + DIGIT)) != prefix) continue;
-        run.add(h, (int)((g >> shift) & (NBINS - 1)));
+    constexpr int64_t STEP = (int64_t)SBLOCK * FIT_U;
+    for (int64_t b0 = (int64_t)blockIdx.x * STEP; b0 < count; b0 += (int64_t)gridDim.x * STEP) {
+        unsigned long long v[FIT_U];
+#pragma unroll
+        for (int u = 0; u < FIT_U; ++u) {
+            const int64_t e = b0 + u * SBLOCK + threadIdx.x;
+            v[u] = e < count ? src[e] : ~0ull;     // ~0 matches no prefix (prefixes stay below 2^33)
+        }
+#pragma unroll
+        for (int u = 0; u < FIT_U; ++u) {
+            const bool match = (v[u] >> (shift + width)) == prefix;
+            if (match) run.add(h, (int)((v[u] >> shift) & (NBINS - 1)));
+            if (COMPACT) {
+                const unsigned long long mask = __ballot(match);
+                if (mask) {
+                    const int leader = __ffsll((long long)mask) - 1;
+                    unsigned int off = 0;
+                    if (lane == leader) off = atomicAdd(&n_stage, (unsigned int)__popcll(mask));
+                    off = __shfl(off, leader, WAVE);
+                    if (match) stage[off + (unsigned int)__popcll(mask & below)] = v[u];
+                }
+            }
+        }
+        if (COMPACT) {
+            __syncthreads();
+            if (n_stage > STAGE - STEP) stage_flush(stage, &n_stage, &base_sh, cs.v[o], &cs.n[o], cs.cap);
+        }
     }
     run.flush(h);
+    if (COMPACT) {
+        __syncthreads();
+        stage_flush(stage, &n_stage, &base_sh, cs.v[o], &cs.n[o], cs.cap);
+    }
     __syncthreads();
     for (int b = threadIdx.x; b < NBINS; b += SBLOCK)
         if (h[b]) atomicAdd(&fa.hist[o][b], h[b]);
 }
 
-// The bin holding the state's rank, appended to the prefix; orientation
-// o = blockIdx.x.
-__global__ __launch_bounds__(SBLOCK) void k_radix_pick(FitArrays fa, unsigned long long *state_all) {
+// The bin holding the state's rank, appended (`width` bits) to the prefix,
+// and the histogram cleared for the next pass; orientation o = blockIdx.x.
+__global__ __launch_bounds__(SBLOCK) void k_radix_pick(FitArrays fa, unsigned long long *state_all, int width) {
     __shared__ unsigned long long part[SBLOCK];
     constexpr int PER = NBINS / SBLOCK;
-    const unsigned int *__restrict__ hist = fa.hist[blockIdx.x];
+    unsigned int *hist = fa.hist[blockIdx.x];
     unsigned long long *state = state_all + 2 * blockIdx.x;
     unsigned long long c = 0;
     for (int q = 0; q < PER; ++q) c += hist[threadIdx.x * PER + q];
@@ -1454,9 +1565,11 @@ __global__ __launch_bounds__(SBLOCK) void k_radix_pick(FitArrays fa, unsigned lo
         while (chunk < SBLOCK - 1 && run + part[chunk] < need) run += part[chunk++];
         int bin = chunk * PER;
         while (bin < chunk * PER + PER - 1 && run + hist[bin] < need) run += hist[bin++];
-        state[0] = (state[0] << DIGIT) | (unsigned long long)bin;
+        state[0] = (state[0] << width) | (unsigned long long)bin;
         state[1] = need - run;
     }
+    __syncthreads();
+    for (int b = threadIdx.x; b < NBINS; b += SBLOCK) hist[b] = 0;
 }
 
 // The exact check of a candidate grid point g_hi per orientation (and of
@@ -1466,6 +1579,7 @@ struct CountArgs {
     const unsigned long long *G[2];
     unsigned long long g_hi[2];
     int use_lo[2], active[2];
+    int keep_aligned[2];          // keep[o] is 4-byte aligned
     uint8_t *keep[2];
 };
 
@@ -1477,31 +1591,77 @@ struct CountArgs {
 constexpr unsigned long long FIT_MARGIN = 1ull << 16;
 
 // Exact kept counts at the two grid points of every active orientation, and
-// keep[] at the upper point.
+// keep[] at the upper point.  A thread takes four consecutive edges at a
+// time (two 16-byte loads of G per orientation, one 4-byte store of keep when
+// keep is 4-byte aligned).
 __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__restrict__ recs, int nfit,
                                                      CountArgs ca, unsigned long long *__restrict__ counts) {
     unsigned long long c[2][2] = {{0, 0}, {0, 0}};
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    constexpr int QU = FIT_U / 2;                      // quads per thread per step
+    const int64_t nq = (m + 3) / 4;
+    constexpr int64_t STEP = (int64_t)SBLOCK * QU;
+    for (int64_t q0 = (int64_t)blockIdx.x * STEP; q0 < nq; q0 += (int64_t)gridDim.x * STEP) {
+        unsigned long long gv[2][QU][4];
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
             if (o >= nfit || !ca.active[o]) continue;
-            const unsigned long long g = ca.G[o][e], hi = ca.g_hi[o];
-            const unsigned long long lo = hi > 0 ? hi - 1 : 0;
-            bool k_hi, k_lo;
-            if (g + FIT_MARGIN < lo) {
-                k_hi = k_lo = true;
-            } else if (g > hi + FIT_MARGIN) {
-                k_hi = k_lo = false;
-            } else {
-                const uint4 a = recs[2 * e], b = recs[2 * e + 1];
-                const uint32_t ra = rec_rank(a, o), rb = rec_rank(b, o);
-                k_hi = ra < (uint32_t)ca.tab_hi[o][a.x] || rb < (uint32_t)ca.tab_hi[o][b.x];
-                k_lo = ca.use_lo[o] && (ra < (uint32_t)ca.tab_lo[o][a.x] || rb < (uint32_t)ca.tab_lo[o][b.x]);
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int64_t q = q0 + u * SBLOCK + threadIdx.x;
+                const int64_t e0 = 4 * q;
+                if (e0 + 3 < m) {
+                    const U64x2 *G2 = reinterpret_cast<const U64x2 *>(ca.G[o] + e0);
+                    const U64x2 x = G2[0], y = G2[1];
+                    gv[o][u][0] = x.a;
+                    gv[o][u][1] = x.b;
+                    gv[o][u][2] = y.a;
+                    gv[o][u][3] = y.b;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) gv[o][u][t] = e0 + t < m ? ca.G[o][e0 + t] : 0ull;
+                }
             }
-            ca.keep[o][e] = k_hi ? 1 : 0;
-            c[o][0] += k_hi;
-            if (ca.use_lo[o]) c[o][1] += k_lo;
+        }
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+            if (o >= nfit || !ca.active[o]) continue;
+            const unsigned long long hi = ca.g_hi[o];
+            const unsigned long long lo = hi > 0 ? hi - 1 : 0;
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int64_t q = q0 + u * SBLOCK + threadIdx.x;
+                const int64_t e0 = 4 * q;
+                if (e0 >= m) continue;
+                uint32_t kb = 0;                       // keep bytes, little-endian
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int64_t e = e0 + t;
+                    if (e >= m) break;
+                    const unsigned long long g = gv[o][u][t];
+                    bool k_hi, k_lo;
+                    if (g + FIT_MARGIN < lo) {
+                        k_hi = k_lo = true;
+                    } else if (g > hi + FIT_MARGIN) {
+                        k_hi = k_lo = false;
+                    } else {
+                        const uint4 a = recs[2 * e], b = recs[2 * e + 1];
+                        const uint32_t ra = rec_rank(a, o), rb = rec_rank(b, o);
+                        k_hi = ra < (uint32_t)ca.tab_hi[o][a.x] || rb < (uint32_t)ca.tab_hi[o][b.x];
+                        k_lo = ca.use_lo[o] &&
+                               (ra < (uint32_t)ca.tab_lo[o][a.x] || rb < (uint32_t)ca.tab_lo[o][b.x]);
+                    }
+                    kb |= (k_hi ? 1u : 0u) << (8 * t);
+                    c[o][0] += k_hi;
+                    if (ca.use_lo[o]) c[o][1] += k_lo;
+                }
+                if (ca.keep_aligned[o] && e0 + 3 < m) {
+                    *reinterpret_cast<uint32_t *>(ca.keep[o] + e0) = kb;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (e0 + t < m) ca.keep[o][e0 + t] = (uint8_t)(kb >> (8 * t));
+                }
+            }
         }
     }
 #pragma unroll
@@ -1529,6 +1689,8 @@ struct SelLayout {
     ScanScratch scan;
     uint4 *recs;                  // [2m] side records (Emit, MODE_REC*)
     unsigned long long *G, *G2;   // [m] grid indices per fitted orientation (G2 when both)
+    unsigned long long *cand, *cand2, *cand_n;   // select candidates (CandArrays), per orientation
+    int64_t cand_cap;
     unsigned int *hist;           // [2][NBINS]
     unsigned long long *state;    // [4]: two words per fitted orientation
     unsigned long long *counts;   // [4]: counts at the upper and lower grid point, per orientation
@@ -1567,6 +1729,10 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     l.recs = c.take<uint4>(2 * m);
     l.G = c.take<unsigned long long>(m);
     l.G2 = both ? c.take<unsigned long long>(m) : nullptr;
+    l.cand_cap = std::min<int64_t>(m, std::max<int64_t>(1 << 16, m / 16));
+    l.cand = c.take<unsigned long long>(l.cand_cap);
+    l.cand2 = both ? c.take<unsigned long long>(l.cand_cap) : nullptr;
+    l.cand_n = c.take<unsigned long long>(2);
     l.hist = c.take<unsigned int>(2 * NBINS);
     l.state = c.take<unsigned long long>(4);
     l.counts = c.take<unsigned long long>(4);
@@ -2141,26 +2307,27 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
     const int64_t m = g->m;
     const size_t tl = (size_t)g->d_max + 1;
     ad_status s;
-    const unsigned hist_blocks = (unsigned)std::min<int64_t>(HIST_BLOCKS, ceil_div(m, SBLOCK));
-    const unsigned count_blocks = (unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, SBLOCK));
+    const unsigned hist_blocks = (unsigned)std::min<int64_t>(HIST_BLOCKS, ceil_div(m, (int64_t)SBLOCK * FIT_U));
+    const unsigned count_blocks = (unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, (int64_t)SBLOCK * 2 * FIT_U));
     const FitArrays fa{{L.G, L.G2}, {L.hist, L.hist + NBINS}};
-    hipLaunchKernelGGL(k_select_init, dim3(1), dim3(1), 0, stream, L.state, (unsigned long long)K, nfit);
+    const CandArrays cs{{L.cand, L.cand2}, L.cand_n, L.cand_cap};
+    hipLaunchKernelGGL(k_select_init, dim3(1), dim3(SBLOCK), 0, stream, L.state, (unsigned long long)K, nfit,
+                       L.hist, L.cand_n);
     AD_LAUNCH_CHECK("k_select_init");
-    s = fill_i32((int32_t *)L.hist, 0, 2 * NBINS, stream);
-    if (s != AD_OK) return s;
     hipLaunchKernelGGL(k_fit_grid, dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, L.recs, L.logs,
                        (int64_t)g->d_max + 2, nfit, fa);
     AD_LAUNCH_CHECK("k_fit_grid");
-    hipLaunchKernelGGL(k_radix_pick, dim3(nfit), dim3(SBLOCK), 0, stream, fa, L.state);
+    hipLaunchKernelGGL(k_radix_pick, dim3(nfit), dim3(SBLOCK), 0, stream, fa, L.state, DIGIT_WIDTH[0]);
     AD_LAUNCH_CHECK("k_radix_pick");
-    for (int pass = 1; pass < 4; ++pass) {
-        const int shift = (3 - pass) * DIGIT;
-        s = fill_i32((int32_t *)L.hist, 0, 2 * NBINS, stream);
-        if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks, nfit), dim3(SBLOCK), 0, stream, m, fa, shift, pass,
-                           L.state);
+    for (int pass = 1; pass < NPASS; ++pass) {
+        if (pass == 1)
+            hipLaunchKernelGGL(k_radix_hist<true>, dim3(hist_blocks, nfit), dim3(SBLOCK), 0, stream, m, fa, cs,
+                               DIGIT_SHIFT[pass], DIGIT_WIDTH[pass], L.state);
+        else
+            hipLaunchKernelGGL(k_radix_hist<false>, dim3(hist_blocks, nfit), dim3(SBLOCK), 0, stream, m, fa, cs,
+                               DIGIT_SHIFT[pass], DIGIT_WIDTH[pass], L.state);
         AD_LAUNCH_CHECK("k_radix_hist");
-        hipLaunchKernelGGL(k_radix_pick, dim3(nfit), dim3(SBLOCK), 0, stream, fa, L.state);
+        hipLaunchKernelGGL(k_radix_pick, dim3(nfit), dim3(SBLOCK), 0, stream, fa, L.state, DIGIT_WIDTH[pass]);
         AD_LAUNCH_CHECK("k_radix_pick");
     }
     unsigned long long st_host[4] = {0, 0, 0, 0};
@@ -2185,6 +2352,7 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
             ca.G[o] = o == 0 ? L.G : L.G2;
             ca.g_hi[o] = (unsigned long long)g_try[o];
             ca.keep[o] = keep[o];
+            ca.keep_aligned[o] = ((uintptr_t)keep[o] & 3) == 0 ? 1 : 0;
             ca.active[o] = done[o] ? 0 : 1;
             ca.use_lo[o] = g_try[o] > 0 ? 1 : 0;
             if (done[o]) continue;

@@ -441,6 +441,38 @@ def test_fit_matches_oracle(api, mixed, orient, target):
     assert int(_np(n_kept)[0]) == kept_o
 
 
+@pytest.mark.parametrize("offset", [1, 2, 4])
+def test_fit_keep_offsets_and_odd_edge_count(api, mixed, offset):
+    """The fit's count pass stores four keep flags at once only into a 4-byte
+    aligned keep array, and reads the grid indices in pairs and quads: keep
+    arrays at every offset, and an edge count that is odd and not a multiple
+    of four, give the oracle's exponent and mask."""
+    announce(f"fit keep offset {offset}, odd m")
+    g0, _ = mixed
+    mm = g0.m - (g0.m % 4 + 1) % 4                      # leave m = 3 (mod 4)
+    g = G.from_edges(g0.n, g0.edge_u[:mm], g0.edge_v[:mm], g0.edge_w[:mm] if g0.edge_w is not None else None)
+    assert g.m % 4 == 3
+    rho = oracle.algebraic_distance(g, 8, 12, 0.5, seed=3).astype(np.float32)
+    dg = _dg(api, g)
+    rt = torch.from_numpy(rho).cuda()
+    buf = torch.full((g.m + 16,), 7, dtype=torch.uint8, device="cuda")
+    buf2 = torch.full((g.m + 16,), 7, dtype=torch.uint8, device="cuda")
+    for orient in (0, 1):
+        keep = buf[offset:offset + g.m]
+        _, n_kept, e = api.sparsify_fit(dg, rt, orient, 0.3, keep=keep)
+        e_o, keep_o, kept_o = oracle.fit_exponent(g, rho.astype(np.float64), orient, 0.3)
+        assert e == e_o
+        assert np.array_equal(_np(keep), keep_o)
+        assert int(_np(n_kept)[0]) == kept_o
+        assert int(buf[offset + g.m]) == 7 and int(buf[offset - 1]) == 7
+    kl, kg, nk, (el, eg) = api.sparsify_fit_both(dg, rt, 0.3, keep_local=buf[offset:offset + g.m],
+                                                 keep_global=buf2[offset + 1:offset + 1 + g.m])
+    for o, (k, e) in enumerate(((kl, el), (kg, eg))):
+        e_o, keep_o, kept_o = oracle.fit_exponent(g, rho.astype(np.float64), o, 0.3)
+        assert e == e_o and np.array_equal(_np(k), keep_o) and int(_np(nk)[o]) == kept_o
+    assert int(buf2[offset + 1 + g.m]) == 7 and int(buf2[offset]) == 7
+
+
 def test_end_to_end_masks_chung_lu(api):
     announce("end-to-end masks Chung-Lu")
     g = G.chung_lu(1 << 14, 240_000, seed=8)
