@@ -1445,13 +1445,16 @@ struct CandArrays {
     int64_t cap;
 };
 
-// Zero the histograms and the candidate counts; state[2o] = prefix of
+// Zero the histograms, the candidate counts and the first check's counts
+// (six words); state[2o] = prefix of
 // selected digits, state[2o + 1] = rank still to skip (1-based inside the
 // prefix), for o < nfit.  One block.
 __global__ __launch_bounds__(SBLOCK) void k_select_init(unsigned long long *state, unsigned long long K, int nfit,
-                                                       unsigned int *hist, unsigned long long *cand_n) {
+                                                       unsigned int *hist, unsigned long long *cand_n,
+                                                       unsigned long long *counts) {
     for (int b = threadIdx.x; b < 2 * NBINS; b += SBLOCK) hist[b] = 0;
     if (threadIdx.x < 2) cand_n[threadIdx.x] = 0;
+    if (threadIdx.x < 6) counts[threadIdx.x] = 0;
     if (threadIdx.x == 0)
         for (int o = 0; o < nfit; ++o) {
             state[2 * o] = 0;
@@ -1464,9 +1467,9 @@ constexpr int STAGE = 2048;   // LDS staging of a block's candidates (entries)
 // Append the block's staged candidates to the global list (one reservation
 // per block and flush).  Every thread calls it, after a barrier that follows
 // the last staging write.
-__device__ __forceinline__ void stage_flush(const unsigned long long *stage, unsigned int *n_stage,
-                                            unsigned long long *base_sh, unsigned long long *dst,
-                                            unsigned long long *dst_n, int64_t cap) {
+template <typename T>
+__device__ __forceinline__ void stage_flush(const T *stage, unsigned int *n_stage, unsigned long long *base_sh,
+                                            T *dst, unsigned long long *dst_n, int64_t cap) {
     const unsigned int ns = *n_stage;
     if (threadIdx.x == 0 && ns) *base_sh = atomicAdd(dst_n, (unsigned long long)ns);
     __syncthreads();
@@ -1581,6 +1584,9 @@ struct CountArgs {
     int use_lo[2], active[2];
     int keep_aligned[2];          // keep[o] is 4-byte aligned
     uint8_t *keep[2];
+    uint32_t *list[2];            // edges left to the tables (LIST form), per orientation
+    unsigned long long *list_n;   // [2]: their number (all of them, also beyond list_cap)
+    int64_t list_cap;
 };
 
 // An edge is kept at grid point p exactly when its threshold index is <= p.
@@ -1593,13 +1599,28 @@ constexpr unsigned long long FIT_MARGIN = 1ull << 16;
 // Exact kept counts at the two grid points of every active orientation, and
 // keep[] at the upper point.  A thread takes four consecutive edges at a
 // time (two 16-byte loads of G per orientation, one 4-byte store of keep when
-// keep is 4-byte aligned).
+// keep is 4-byte aligned).  LIST form (launched before the budget tables
+// reach the device): an edge whose estimate does not settle it is not counted
+// but listed for k_fit_margin (ids staged in LDS, one global reservation per
+// block and flush), and its keep flag is left for that kernel to store.
+constexpr int STAGE_M = 4096;   // LDS staging of listed edges per orientation
+
+template <bool LIST>
 __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__restrict__ recs, int nfit,
                                                      CountArgs ca, unsigned long long *__restrict__ counts) {
+    __shared__ uint32_t stage[LIST ? 2 : 1][LIST ? STAGE_M : 1];
+    __shared__ unsigned int n_stage[2];
+    __shared__ unsigned long long base_sh;
     unsigned long long c[2][2] = {{0, 0}, {0, 0}};
     constexpr int QU = FIT_U / 2;                      // quads per thread per step
     const int64_t nq = (m + 3) / 4;
     constexpr int64_t STEP = (int64_t)SBLOCK * QU;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned long long below = lane ? (~0ull >> (WAVE - lane)) : 0ull;
+    if (LIST) {
+        if (threadIdx.x < 2) n_stage[threadIdx.x] = 0;
+        __syncthreads();
+    }
     for (int64_t q0 = (int64_t)blockIdx.x * STEP; q0 < nq; q0 += (int64_t)gridDim.x * STEP) {
         unsigned long long gv[2][QU][4];
 #pragma unroll
@@ -1631,18 +1652,19 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__
             for (int u = 0; u < QU; ++u) {
                 const int64_t q = q0 + u * SBLOCK + threadIdx.x;
                 const int64_t e0 = 4 * q;
-                if (e0 >= m) continue;
                 uint32_t kb = 0;                       // keep bytes, little-endian
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int64_t e = e0 + t;
-                    if (e >= m) break;
+                    const bool valid = e < m;
                     const unsigned long long g = gv[o][u][t];
-                    bool k_hi, k_lo;
-                    if (g + FIT_MARGIN < lo) {
+                    bool k_hi = false, k_lo = false, listed = false;
+                    if (!valid) {
+                    } else if (g + FIT_MARGIN < lo) {
                         k_hi = k_lo = true;
                     } else if (g > hi + FIT_MARGIN) {
-                        k_hi = k_lo = false;
+                    } else if (LIST) {
+                        listed = true;
                     } else {
                         const uint4 a = recs[2 * e], b = recs[2 * e + 1];
                         const uint32_t ra = rec_rank(a, o), rb = rec_rank(b, o);
@@ -1653,7 +1675,18 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__
                     kb |= (k_hi ? 1u : 0u) << (8 * t);
                     c[o][0] += k_hi;
                     if (ca.use_lo[o]) c[o][1] += k_lo;
+                    if (LIST) {
+                        const unsigned long long mask = __ballot(listed);
+                        if (mask) {
+                            const int leader = __ffsll((long long)mask) - 1;
+                            unsigned int off = 0;
+                            if (lane == leader) off = atomicAdd(&n_stage[o], (unsigned int)__popcll(mask));
+                            off = __shfl(off, leader, WAVE);
+                            if (listed) stage[LIST ? o : 0][off + (unsigned int)__popcll(mask & below)] = (uint32_t)e;
+                        }
+                    }
                 }
+                if (e0 >= m) continue;
                 if (ca.keep_aligned[o] && e0 + 3 < m) {
                     *reinterpret_cast<uint32_t *>(ca.keep[o] + e0) = kb;
                 } else {
@@ -1663,6 +1696,20 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__
                 }
             }
         }
+        if (LIST) {
+            __syncthreads();
+#pragma unroll
+            for (int o = 0; o < 2; ++o)
+                if (o < nfit && ca.active[o] && n_stage[o] > STAGE_M - SBLOCK * QU * 4)
+                    stage_flush(stage[LIST ? o : 0], &n_stage[o], &base_sh, ca.list[o], &ca.list_n[o], ca.list_cap);
+        }
+    }
+    if (LIST) {
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < 2; ++o)
+            if (o < nfit && ca.active[o])
+                stage_flush(stage[LIST ? o : 0], &n_stage[o], &base_sh, ca.list[o], &ca.list_n[o], ca.list_cap);
     }
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
@@ -1672,6 +1719,40 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__
         block_add(c[o][1], &counts[2 * o + 1]);
         __syncthreads();
     }
+}
+
+// The listed edges of orientation o = blockIdx.y against the budget tables:
+// counts added, keep flags stored.  Does nothing for an orientation whose
+// list overflowed (the host then counts it again in one full pass).
+__global__ __launch_bounds__(SBLOCK) void k_fit_margin(const uint4 *__restrict__ recs, CountArgs ca,
+                                                      unsigned long long *__restrict__ counts) {
+    const int o = blockIdx.y;
+    if (!ca.active[o]) return;
+    const unsigned long long n = ca.list_n[o];
+    if (n > (unsigned long long)ca.list_cap) return;
+    unsigned long long c_hi = 0, c_lo = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = ca.list[o][i];
+        const uint4 a = recs[2 * e], b = recs[2 * e + 1];
+        const uint32_t ra = rec_rank(a, o), rb = rec_rank(b, o);
+        const bool k_hi = ra < (uint32_t)ca.tab_hi[o][a.x] || rb < (uint32_t)ca.tab_hi[o][b.x];
+        const bool k_lo = ca.use_lo[o] && (ra < (uint32_t)ca.tab_lo[o][a.x] || rb < (uint32_t)ca.tab_lo[o][b.x]);
+        ca.keep[o][e] = k_hi ? 1 : 0;
+        c_hi += k_hi;
+        c_lo += k_lo;
+    }
+    block_add(c_hi, &counts[2 * o]);
+    __syncthreads();
+    block_add(c_lo, &counts[2 * o + 1]);
+}
+
+// dst[i] = src[i] for i < count; src is host memory mapped for the device.
+__global__ __launch_bounds__(SBLOCK) void k_copy_mapped(int32_t *__restrict__ dst, const int32_t *__restrict__ src,
+                                                       int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 __global__ void k_store_count(const unsigned long long *__restrict__ c, int64_t *__restrict__ out) {
@@ -1693,7 +1774,8 @@ struct SelLayout {
     int64_t cand_cap;
     unsigned int *hist;           // [2][NBINS]
     unsigned long long *state;    // [4]: two words per fitted orientation
-    unsigned long long *counts;   // [4]: counts at the upper and lower grid point, per orientation
+    unsigned long long *counts;   // [6]: counts at the upper and lower grid point per orientation, then
+                                  // the listed edges per orientation (k_fit_count LIST form)
     int32_t *tabs;                // [4][d_max + 1]: upper and lower budget tables, per orientation
     double *logs;                 // [2][d_max + 2]: log(v), then 1 / log(v)
     HubScratch hub;               // rows longer than SORT_CAP (d_max > SORT_CAP only)
@@ -1735,7 +1817,7 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     l.cand_n = c.take<unsigned long long>(2);
     l.hist = c.take<unsigned int>(2 * NBINS);
     l.state = c.take<unsigned long long>(4);
-    l.counts = c.take<unsigned long long>(4);
+    l.counts = c.take<unsigned long long>(6);
     l.tabs = c.take<int32_t>(4 * ((size_t)g->d_max + 1));
     l.logs = c.take<double>(2 * ((size_t)g->d_max + 2));
     l.hub = HubScratch{};
@@ -2279,8 +2361,11 @@ static int64_t fit_count_target(int64_t m, double target) {
 
 namespace ad {
 
-// Pinned host staging for the budget tables (grown on demand, kept for the
-// life of the process; one fit at a time uses it).
+// Pinned host staging for the fit's read-backs (the first STAGE_RB 32-bit
+// words) and budget tables (grown on demand, kept for the life of the
+// process; one fit at a time uses it).  Mapped into the device's address
+// space, so that a kernel copies the tables in stream order.
+constexpr size_t STAGE_RB = 32;
 static std::mutex g_stage_mu;
 static int32_t *g_stage = nullptr;
 static size_t g_stage_cap = 0;
@@ -2290,7 +2375,7 @@ static ad_status stage_reserve(size_t count) {
     if (g_stage) AD_HIP(hipHostFree(g_stage));
     g_stage = nullptr;
     g_stage_cap = 0;
-    AD_HIP(hipHostMalloc((void **)&g_stage, count * sizeof(int32_t), hipHostMallocDefault));
+    AD_HIP(hipHostMalloc((void **)&g_stage, count * sizeof(int32_t), hipHostMallocMapped));
     g_stage_cap = count;
     return AD_OK;
 }
@@ -2311,8 +2396,16 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
     const unsigned count_blocks = (unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, (int64_t)SBLOCK * 2 * FIT_U));
     const FitArrays fa{{L.G, L.G2}, {L.hist, L.hist + NBINS}};
     const CandArrays cs{{L.cand, L.cand2}, L.cand_n, L.cand_cap};
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    s = stage_reserve(STAGE_RB + 4 * tl);
+    if (s != AD_OK) return s;
+    unsigned long long *const rb = reinterpret_cast<unsigned long long *>(g_stage);   // read-backs
+    int32_t *const tabs_h = g_stage + STAGE_RB;
+    int32_t *stage_dev = nullptr;
+    AD_HIP(hipHostGetDevicePointer((void **)&stage_dev, g_stage, 0));
+    const int32_t *const tabs_mapped = stage_dev + STAGE_RB;   // tabs_h as the device sees it
     hipLaunchKernelGGL(k_select_init, dim3(1), dim3(SBLOCK), 0, stream, L.state, (unsigned long long)K, nfit,
-                       L.hist, L.cand_n);
+                       L.hist, L.cand_n, L.counts);
     AD_LAUNCH_CHECK("k_select_init");
     hipLaunchKernelGGL(k_fit_grid, dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, L.recs, L.logs,
                        (int64_t)g->d_max + 2, nfit, fa);
@@ -2330,17 +2423,18 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
         hipLaunchKernelGGL(k_radix_pick, dim3(nfit), dim3(SBLOCK), 0, stream, fa, L.state, DIGIT_WIDTH[pass]);
         AD_LAUNCH_CHECK("k_radix_pick");
     }
-    unsigned long long st_host[4] = {0, 0, 0, 0};
-    AD_HIP(hipMemcpyAsync(st_host, L.state, sizeof(st_host), hipMemcpyDeviceToHost, stream));
+    AD_HIP(hipMemcpyAsync(rb, L.state, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
     AD_HIP(hipStreamSynchronize(stream));
     const unsigned long long GMAX = 1ull << 40;
     long long g_try[2];
     bool done[2] = {false, false};
-    for (int o = 0; o < nfit; ++o) g_try[o] = (long long)std::min(st_host[2 * o], GMAX);
-
-    std::lock_guard<std::mutex> lock(g_stage_mu);
-    s = stage_reserve(4 * tl);
-    if (s != AD_OK) return s;
+    for (int o = 0; o < nfit; ++o) g_try[o] = (long long)std::min(rb[2 * o], GMAX);
+    // The first check splits the count: the edges that the estimate settles are
+    // counted while the host builds the budget tables, the listed rest after
+    // the tables arrive.  Later checks (a moved grid point, or a list that
+    // overflowed) count in one pass with the tables.
+    bool split = true;
+    const unsigned margin_blocks = (unsigned)std::min<int64_t>(256, ceil_div(2 * L.cand_cap, SBLOCK));
     for (int attempt = 0; attempt < 64; ++attempt) {
         // budget tables at the candidate grid point and one step below, filled
         // in the pinned staging buffer (one host thread per table for long rows)
@@ -2355,9 +2449,21 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
             ca.keep_aligned[o] = ((uintptr_t)keep[o] & 3) == 0 ? 1 : 0;
             ca.active[o] = done[o] ? 0 : 1;
             ca.use_lo[o] = g_try[o] > 0 ? 1 : 0;
+            ca.list[o] = reinterpret_cast<uint32_t *>(o == 0 ? L.cand : L.cand2);
             if (done[o]) continue;
-            fills.emplace_back(g_stage + (2 * o) * tl, (double)g_try[o] / GRID);
-            if (g_try[o] > 0) fills.emplace_back(g_stage + (2 * o + 1) * tl, (double)(g_try[o] - 1) / GRID);
+            fills.emplace_back(tabs_h + (2 * o) * tl, (double)g_try[o] / GRID);
+            if (g_try[o] > 0) fills.emplace_back(tabs_h + (2 * o + 1) * tl, (double)(g_try[o] - 1) / GRID);
+        }
+        ca.list_n = L.counts + 4;
+        ca.list_cap = 2 * L.cand_cap;
+        if (!split) {                        // the first check's counts were zeroed by k_select_init
+            s = fill_u64(L.counts, 0, 6, stream);
+            if (s != AD_OK) return s;
+        }
+        if (split) {
+            hipLaunchKernelGGL(k_fit_count<true>, dim3(count_blocks), dim3(SBLOCK), 0, stream, m, L.recs, nfit, ca,
+                               L.counts);
+            AD_LAUNCH_CHECK("k_fit_count");
         }
         std::vector<std::thread> th;
         size_t started = 0;                  // tables 1 .. started on their own threads
@@ -2374,14 +2480,29 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
         for (size_t f = 0; f < fills.size(); ++f)
             if (f == 0 || f > started) budget_fill(g->d_max, fills[f].second, fills[f].first);
         for (auto &x : th) x.join();
-        AD_HIP(hipMemcpyAsync(L.tabs, g_stage, 2 * nfit * tl * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        s = fill_u64(L.counts, 0, 4, stream);
-        if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_fit_count, dim3(count_blocks), dim3(SBLOCK), 0, stream, m, L.recs, nfit, ca, L.counts);
-        AD_LAUNCH_CHECK("k_fit_count");
-        unsigned long long hc[4];
-        AD_HIP(hipMemcpyAsync(hc, L.counts, sizeof(hc), hipMemcpyDeviceToHost, stream));
+        // the tables to the device by a kernel reading the mapped staging (a
+        // host-side copy call would wait for the stream's earlier work)
+        const int64_t tab_words = (int64_t)(2 * nfit * tl);
+        hipLaunchKernelGGL(k_copy_mapped, dim3(grid_for(tab_words, SBLOCK)), dim3(SBLOCK), 0, stream, L.tabs,
+                           tabs_mapped, tab_words);
+        AD_LAUNCH_CHECK("k_copy_mapped");
+        if (split) {
+            hipLaunchKernelGGL(k_fit_margin, dim3(margin_blocks, nfit), dim3(SBLOCK), 0, stream, L.recs, ca,
+                               L.counts);
+            AD_LAUNCH_CHECK("k_fit_margin");
+        } else {
+            hipLaunchKernelGGL(k_fit_count<false>, dim3(count_blocks), dim3(SBLOCK), 0, stream, m, L.recs, nfit, ca,
+                               L.counts);
+            AD_LAUNCH_CHECK("k_fit_count");
+        }
+        unsigned long long *const hc = rb + 4;
+        AD_HIP(hipMemcpyAsync(hc, L.counts, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
         AD_HIP(hipStreamSynchronize(stream));
+        bool overflow = false;
+        for (int o = 0; o < nfit; ++o)
+            if (split && !done[o] && hc[4 + o] > (unsigned long long)ca.list_cap) overflow = true;
+        split = false;
+        if (overflow) continue;              // the same points again, in one full pass
         bool all = true;
         for (int o = 0; o < nfit; ++o) {
             if (done[o]) continue;

@@ -473,6 +473,33 @@ def test_fit_keep_offsets_and_odd_edge_count(api, mixed, offset):
     assert int(buf2[offset + 1 + g.m]) == 7 and int(buf2[offset]) == 7
 
 
+@pytest.mark.parametrize("target", [0.3, 0.5])
+def test_fit_on_a_torus_with_tied_thresholds(api, target):
+    """A 4-regular torus (725 x 725, 1,051,250 edges): every side's threshold
+    is one of four values, so about a third of the edges lie at the selected
+    grid point and the exact count cannot rely on the per-edge estimate for
+    them.  There are more of them than the fit's margin list holds, so the
+    count falls back to its one-pass form; exponents and masks equal the
+    oracle's."""
+    announce(f"fit torus target={target}")
+    s_ = 725
+    idx = np.arange(s_ * s_).reshape(s_, s_)
+    u = np.concatenate([idx.ravel(), idx.ravel()])
+    v = np.concatenate([np.roll(idx, 1, 0).ravel(), np.roll(idx, 1, 1).ravel()])
+    g = G.from_edges(s_ * s_, u, v)
+    rho = oracle.algebraic_distance(g, 8, 12, 0.5, seed=3).astype(np.float32)
+    dg = _dg(api, g)
+    rt = torch.from_numpy(rho).cuda()
+    ref = [oracle.fit_exponent(g, rho.astype(np.float64), o, target) for o in (0, 1)]
+    for o in (0, 1):
+        keep, n_kept, e = api.sparsify_fit(dg, rt, o, target)
+        assert e == ref[o][0]
+        assert np.array_equal(_np(keep), ref[o][1]) and int(_np(n_kept)[0]) == ref[o][2]
+    kl, kg, nk, es = api.sparsify_fit_both(dg, rt, target)
+    for o, k in enumerate((kl, kg)):
+        assert es[o] == ref[o][0] and np.array_equal(_np(k), ref[o][1]) and int(_np(nk)[o]) == ref[o][2]
+
+
 def test_end_to_end_masks_chung_lu(api):
     announce("end-to-end masks Chung-Lu")
     g = G.chung_lu(1 << 14, 240_000, seed=8)
