@@ -1445,10 +1445,9 @@ struct CandArrays {
     int64_t cap;
 };
 
-// Zero the histograms, the candidate counts and the first check's counts
-// (six words); state[2o] = prefix of
-// selected digits, state[2o + 1] = rank still to skip (1-based inside the
-// prefix), for o < nfit.  One block.
+// Zero the histograms, the candidate counts and the first check's six
+// counters; state[2o] = prefix of selected digits, state[2o + 1] = rank
+// still to skip (1-based inside the prefix), for o < nfit.  One block.
 __global__ __launch_bounds__(SBLOCK) void k_select_init(unsigned long long *state, unsigned long long K, int nfit,
                                                        unsigned int *hist, unsigned long long *cand_n,
                                                        unsigned long long *counts) {
@@ -1659,10 +1658,10 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__
                     const bool valid = e < m;
                     const unsigned long long g = gv[o][u][t];
                     bool k_hi = false, k_lo = false, listed = false;
-                    if (!valid) {
+                    if (!valid || g > hi + FIT_MARGIN) {
+                        // past the end, or kept at neither point
                     } else if (g + FIT_MARGIN < lo) {
                         k_hi = k_lo = true;
-                    } else if (g > hi + FIT_MARGIN) {
                     } else if (LIST) {
                         listed = true;
                     } else {
