@@ -46,8 +46,13 @@
  *     events before the call returns, so the caller's stream orders all of
  *     the call's work, and a per-device mutex serialises the forks of calls
  *     made from several host threads.  Under stream capture the call stays
- *     on the caller's stream.  The kernel trace (ad_trace_*) keeps a pool
- *     of events per device.
+ *     on the caller's stream.  The retention fits (ad_sparsify_fit,
+ *     ad_sparsify_fit_both, ad_edge_dist_fit_both, ad_sparsify_binned with
+ *     a target) share one pinned, device-mapped host buffer for their
+ *     budget tables and read-backs, grown on demand and kept until the
+ *     process ends; a mutex lets one fit at a time use it, so fits from
+ *     several host threads run one after another.  The kernel trace
+ *     (ad_trace_*) keeps a pool of events per device.
  */
 #ifndef AD_H
 #define AD_H
