@@ -1331,6 +1331,7 @@ static_assert(DIGIT_SHIFT[0] + DIGIT_WIDTH[0] == 41 && (1ull << 40) >> DIGIT_SHI
 // Edges per thread per step of the fit's grid-stride loops (loads issued
 // together).
 constexpr int FIT_U = 4;
+constexpr int FIT_LDS_TB = 1024;   // threads of the grid pass with the log tables in LDS
 
 // Two grid indices in one 16-byte load.
 struct alignas(16) U64x2 {
@@ -1391,20 +1392,28 @@ struct BinRun {
 // G_o[e] = the smaller of edge e's two sides' grid indices, and the
 // histogram of the first radix digit of G_o (its bits from DIGIT_SHIFT[0]
 // up), for every fitted orientation o < nfit from one read of the side
-// records.  hist must be zero on entry.
-__global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const uint4 *__restrict__ recs,
-                                                    const double *__restrict__ logs, int64_t nlogs, int nfit,
-                                                    FitArrays fa) {
+// records.  hist must be zero on entry.  LDS_TAB: the log tables (2 * nlogs
+// doubles) are first copied into dynamic LDS, one workgroup per compute unit
+// (six random table reads per edge cost more from the caches than the
+// records' stream; the values read are the same).
+template <int TB, bool LDS_TAB>
+__global__ __launch_bounds__(TB) void k_fit_grid(int64_t m, const uint4 *__restrict__ recs,
+                                                const double *__restrict__ logs, int64_t nlogs, int nfit,
+                                                FitArrays fa) {
+    extern __shared__ double tab_lds[];
     __shared__ unsigned int h[2][NBINS];
-    for (int b = threadIdx.x; b < 2 * NBINS; b += SBLOCK) h[b / NBINS][b % NBINS] = 0;
+    if (LDS_TAB)
+        for (int64_t i = threadIdx.x; i < 2 * nlogs; i += TB) tab_lds[i] = logs[i];
+    const double *tab = LDS_TAB ? tab_lds : logs;
+    for (int b = threadIdx.x; b < 2 * NBINS; b += TB) h[b / NBINS][b % NBINS] = 0;
     __syncthreads();
     BinRun run[2];
-    constexpr int64_t STEP = (int64_t)SBLOCK * FIT_U;
+    constexpr int64_t STEP = (int64_t)TB * FIT_U;
     for (int64_t b0 = (int64_t)blockIdx.x * STEP; b0 < m; b0 += (int64_t)gridDim.x * STEP) {
         uint4 a[FIT_U] = {}, b[FIT_U] = {};
 #pragma unroll
         for (int u = 0; u < FIT_U; ++u) {
-            const int64_t e = b0 + u * SBLOCK + threadIdx.x;
+            const int64_t e = b0 + u * TB + threadIdx.x;
             if (e < m) {
                 a[u] = recs[2 * e];
                 b[u] = recs[2 * e + 1];
@@ -1412,14 +1421,14 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const uint4 *__r
         }
 #pragma unroll
         for (int u = 0; u < FIT_U; ++u) {
-            const int64_t e = b0 + u * SBLOCK + threadIdx.x;
+            const int64_t e = b0 + u * TB + threadIdx.x;
             if (e >= m) continue;
-            const double ia = logs[nlogs + a[u].x], ib = logs[nlogs + b[u].x];
+            const double ia = tab[nlogs + a[u].x], ib = tab[nlogs + b[u].x];
 #pragma unroll
             for (int o = 0; o < 2; ++o) {
                 if (o >= nfit) break;
-                const unsigned long long ga = side_grid(a[u].x, rec_rank(a[u], o), ia, logs);
-                const unsigned long long gb = side_grid(b[u].x, rec_rank(b[u], o), ib, logs);
+                const unsigned long long ga = side_grid(a[u].x, rec_rank(a[u], o), ia, tab);
+                const unsigned long long gb = side_grid(b[u].x, rec_rank(b[u], o), ib, tab);
                 const unsigned long long g = ga < gb ? ga : gb;
                 fa.G[o][e] = g;
                 run[o].add(h[o], (int)((g >> DIGIT_SHIFT[0]) & (NBINS - 1)));
@@ -1431,7 +1440,7 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_grid(int64_t m, const uint4 *__r
         if (o < nfit) run[o].flush(h[o]);
     __syncthreads();
     for (int o = 0; o < nfit; ++o)
-        for (int b = threadIdx.x; b < NBINS; b += SBLOCK)
+        for (int b = threadIdx.x; b < NBINS; b += TB)
             if (h[o][b]) atomicAdd(&fa.hist[o][b], h[o][b]);
 }
 
@@ -2406,8 +2415,21 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
     hipLaunchKernelGGL(k_select_init, dim3(1), dim3(SBLOCK), 0, stream, L.state, (unsigned long long)K, nfit,
                        L.hist, L.cand_n, L.counts);
     AD_LAUNCH_CHECK("k_select_init");
-    hipLaunchKernelGGL(k_fit_grid, dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, L.recs, L.logs,
-                       (int64_t)g->d_max + 2, nfit, fa);
+    const int64_t nlogs = (int64_t)g->d_max + 2;
+    int dev = 0, lds_max = 0, n_cu = 0;
+    const bool lds_tab = hipGetDevice(&dev) == hipSuccess &&
+                         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+                         hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                         (int64_t)lds_max >= 2 * nlogs * (int64_t)sizeof(double) + 2 * NBINS * 4 + 1024;
+    if (lds_tab) {
+        const unsigned blocks = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>(n_cu, ceil_div(m, (int64_t)FIT_LDS_TB * FIT_U)));
+        hipLaunchKernelGGL((k_fit_grid<FIT_LDS_TB, true>), dim3(blocks), dim3(FIT_LDS_TB),
+                           (size_t)(2 * nlogs) * sizeof(double), stream, m, L.recs, L.logs, nlogs, nfit, fa);
+    } else {
+        hipLaunchKernelGGL((k_fit_grid<SBLOCK, false>), dim3(hist_blocks), dim3(SBLOCK), 0, stream, m, L.recs,
+                           L.logs, nlogs, nfit, fa);
+    }
     AD_LAUNCH_CHECK("k_fit_grid");
     hipLaunchKernelGGL(k_radix_pick, dim3(nfit), dim3(SBLOCK), 0, stream, fa, L.state, DIGIT_WIDTH[0]);
     AD_LAUNCH_CHECK("k_radix_pick");
