@@ -1287,21 +1287,29 @@ __global__ __launch_bounds__(SBLOCK) void k_hub_emit(const int64_t *__restrict__
     }
 }
 
-// Block-wide sum of per-thread counts; thread 0 adds it to *out (one atomic
-// per block; integer addition, so the total does not depend on order).
-__device__ __forceinline__ void block_add(unsigned long long c, unsigned long long *out) {
+// Block-wide sum of per-thread counts, valid in thread 0.
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long c) {
     __shared__ unsigned long long part[SBLOCK / WAVE];
     for (int d = WAVE / 2; d >= 1; d >>= 1) c += shfl_down(c, d);
     if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x >> 6] = c;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
         for (int w = 0; w < SBLOCK / WAVE; ++w) t += part[w];
-        if (t) atomicAdd(out, t);
-    }
+    return t;
+}
+
+// Block-wide sum of per-thread counts; thread 0 adds it to *out (one atomic
+// per block; integer addition, so the total does not depend on order).
+// Atomics on one address from many blocks serialise at the memory side, so
+// grids that use it stay small.
+__device__ __forceinline__ void block_add(unsigned long long c, unsigned long long *out) {
+    const unsigned long long t = block_sum(c);
+    if (threadIdx.x == 0 && t) atomicAdd(out, t);
 }
 
 constexpr int COUNT_BLOCKS = 2048;
+constexpr int SUM_BLOCKS = 256;    // grids that end in block_add
 constexpr int HIST_BLOCKS = 2048;
 
 // Sum of a byte mask into a 64-bit device counter.
@@ -1604,8 +1612,8 @@ struct CountArgs {
 // are classified by the estimate, the rest by the budget tables.
 constexpr unsigned long long FIT_MARGIN = 1ull << 16;
 
-// Exact kept counts at the two grid points of every active orientation, and
-// keep[] at the upper point.  A thread takes four consecutive edges at a
+// Exact kept counts at the two grid points of every active orientation (per
+// block, into part[4 * block ..]), and keep[] at the upper point.  A thread takes four consecutive edges at a
 // time (two 16-byte loads of G per orientation, one 4-byte store of keep when
 // keep is 4-byte aligned).  LIST form (launched before the budget tables
 // reach the device): an edge whose estimate does not settle it is not counted
@@ -1615,7 +1623,7 @@ constexpr int STAGE_M = 4096;   // LDS staging of listed edges per orientation
 
 template <bool LIST>
 __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__restrict__ recs, int nfit,
-                                                     CountArgs ca, unsigned long long *__restrict__ counts) {
+                                                     CountArgs ca, unsigned long long *__restrict__ part) {
     __shared__ uint32_t stage[LIST ? 2 : 1][LIST ? STAGE_M : 1];
     __shared__ unsigned int n_stage[2];
     __shared__ unsigned long long base_sh;
@@ -1719,14 +1727,25 @@ __global__ __launch_bounds__(SBLOCK) void k_fit_count(int64_t m, const uint4 *__
             if (o < nfit && ca.active[o])
                 stage_flush(stage[LIST ? o : 0], &n_stage[o], &base_sh, ca.list[o], &ca.list_n[o], ca.list_cap);
     }
+    // the block's four counts to its own slots (k_sum_counts adds them up)
 #pragma unroll
-    for (int o = 0; o < 2; ++o) {
-        if (o >= nfit || !ca.active[o]) continue;
-        block_add(c[o][0], &counts[2 * o]);
-        __syncthreads();
-        block_add(c[o][1], &counts[2 * o + 1]);
+    for (int k = 0; k < 4; ++k) {
+        const unsigned long long t = block_sum(c[k >> 1][k & 1]);
+        if (threadIdx.x == 0) part[4 * (int64_t)blockIdx.x + k] = t;
         __syncthreads();
     }
+}
+
+// counts[k] += the sum over nblocks blocks of part[4 * b + k], k < 4.  One
+// block; wave k sums count k.
+static_assert(SBLOCK / WAVE == 4, "one wave per count");
+__global__ __launch_bounds__(SBLOCK) void k_sum_counts(const unsigned long long *__restrict__ part, int nblocks,
+                                                      unsigned long long *__restrict__ counts) {
+    const int k = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    unsigned long long c = 0;
+    for (int b = lane; b < nblocks; b += WAVE) c += part[4 * (int64_t)b + k];
+    for (int d = WAVE / 2; d >= 1; d >>= 1) c += shfl_down(c, d);
+    if (lane == 0) counts[k] += c;
 }
 
 // The listed edges of orientation o = blockIdx.y against the budget tables:
@@ -1779,6 +1798,7 @@ struct SelLayout {
     uint4 *recs;                  // [2m] side records (Emit, MODE_REC*)
     unsigned long long *G, *G2;   // [m] grid indices per fitted orientation (G2 when both)
     unsigned long long *cand, *cand2, *cand_n;   // select candidates (CandArrays), per orientation
+    unsigned long long *fit_part;                // [COUNT_BLOCKS][4]: the count pass's per-block counts
     int64_t cand_cap;
     unsigned int *hist;           // [2][NBINS]
     unsigned long long *state;    // [4]: two words per fitted orientation
@@ -1823,6 +1843,7 @@ static size_t sel_layout(const ad_graph *g, void *ws, size_t ws_bytes, SelLayout
     l.cand = c.take<unsigned long long>(l.cand_cap);
     l.cand2 = both ? c.take<unsigned long long>(l.cand_cap) : nullptr;
     l.cand_n = c.take<unsigned long long>(2);
+    l.fit_part = c.take<unsigned long long>(4 * (size_t)COUNT_BLOCKS);
     l.hist = c.take<unsigned int>(2 * NBINS);
     l.state = c.take<unsigned long long>(4);
     l.counts = c.take<unsigned long long>(6);
@@ -2336,7 +2357,7 @@ static ad_status sparsify_count(const ad_graph *g, ad_dtype rho_dtype, const voi
         else
             s = rank_all<double>(g, (const double *)rho, em, L, stream);
         if (s != AD_OK) return s;
-        hipLaunchKernelGGL(k_count_bytes, dim3((unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(g->m, SBLOCK))),
+        hipLaunchKernelGGL(k_count_bytes, dim3((unsigned)std::min<int64_t>(SUM_BLOCKS, ceil_div(g->m, SBLOCK))),
                            dim3(SBLOCK), 0, stream, g->m, keep,
                            L.counts);
         AD_LAUNCH_CHECK("k_count_bytes");
@@ -2455,7 +2476,7 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
     // the tables arrive.  Later checks (a moved grid point, or a list that
     // overflowed) count in one pass with the tables.
     bool split = true;
-    const unsigned margin_blocks = (unsigned)std::min<int64_t>(256, ceil_div(2 * L.cand_cap, SBLOCK));
+    const unsigned margin_blocks = (unsigned)std::min<int64_t>(64, ceil_div(2 * L.cand_cap, SBLOCK));
     for (int attempt = 0; attempt < 64; ++attempt) {
         // budget tables at the candidate grid point and one step below, filled
         // in the pinned staging buffer (one host thread per table for long rows)
@@ -2483,8 +2504,11 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
         }
         if (split) {
             hipLaunchKernelGGL(k_fit_count<true>, dim3(count_blocks), dim3(SBLOCK), 0, stream, m, L.recs, nfit, ca,
-                               L.counts);
+                               L.fit_part);
             AD_LAUNCH_CHECK("k_fit_count");
+            hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(SBLOCK), 0, stream, L.fit_part, (int)count_blocks,
+                               L.counts);
+            AD_LAUNCH_CHECK("k_sum_counts");
         }
         std::vector<std::thread> th;
         size_t started = 0;                  // tables 1 .. started on their own threads
@@ -2513,8 +2537,11 @@ static ad_status fit_from_recs(const ad_graph *g, const SelLayout &L, int nfit, 
             AD_LAUNCH_CHECK("k_fit_margin");
         } else {
             hipLaunchKernelGGL(k_fit_count<false>, dim3(count_blocks), dim3(SBLOCK), 0, stream, m, L.recs, nfit, ca,
-                               L.counts);
+                               L.fit_part);
             AD_LAUNCH_CHECK("k_fit_count");
+            hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(SBLOCK), 0, stream, L.fit_part, (int)count_blocks,
+                               L.counts);
+            AD_LAUNCH_CHECK("k_sum_counts");
         }
         unsigned long long *const hc = rb + 4;
         AD_HIP(hipMemcpyAsync(hc, L.counts, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
@@ -3035,7 +3062,7 @@ static ad_status sparsify_binned_impl(const ad_graph *g, ad_dtype rho_dtype, con
     if (s != AD_OK) return s;
     s = rank_all<float>(g, nullptr, emit_single(MODE_FIXED, AD_LOCAL, B.budget, keep, nullptr), L, stream, B.keys);
     if (s != AD_OK) return s;
-    hipLaunchKernelGGL(k_count_bytes, dim3((unsigned)std::min<int64_t>(COUNT_BLOCKS, ceil_div(m, SBLOCK))),
+    hipLaunchKernelGGL(k_count_bytes, dim3((unsigned)std::min<int64_t>(SUM_BLOCKS, ceil_div(m, SBLOCK))),
                        dim3(SBLOCK), 0, stream, m, keep, L.counts);
     AD_LAUNCH_CHECK("k_count_bytes");
     hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, stream, L.counts, n_kept);
