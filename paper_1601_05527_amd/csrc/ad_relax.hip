@@ -34,6 +34,8 @@
 namespace ad {
 
 constexpr int BLOCK = 256;
+constexpr int MM_SLOTS = 16;       // copies of each graph's min / max codes (k_minmax)
+constexpr int MM_SPLIT = 4;        // k_minmax blocks per CENTRE_ROWS chunk
 constexpr int SWEEP_UNROLL = 8;     // row gathers in flight per lane
 
 // s_i = sum_j w_ij in FP64 (LPR lanes per row, strided partial sums combined
@@ -227,8 +229,11 @@ __global__ __launch_bounds__(BLOCK) void k_centre_finalize(int R, int64_t nblock
             double sh = 0.0;
             if (centre && S > 0.0) sh = rint((tot / S) * 16777216.0) * (1.0 / 16777216.0);
             shift[(int64_t)g * R + r] = sh;
-            mm[(int64_t)g * 2 * R + r] = ~0ull;       // running min code
-            mm[(int64_t)g * 2 * R + R + r] = 0ull;    // running max code
+            for (int sl = 0; sl < MM_SLOTS; ++sl) {
+                unsigned long long *m_ = mm + ((int64_t)sl * sg.G + g) * 2 * R;
+                m_[r] = ~0ull;                        // running min code
+                m_[R + r] = 0ull;                     // running max code
+            }
         }
         __syncthreads();
     }
@@ -409,7 +414,7 @@ __global__ __launch_bounds__(BLOCK) void k_comp_drift(int R, int64_t n_comp, con
     }
 }
 
-// The running min / max codes of every graph start empty.
+// The running min / max codes of every graph (MM_SLOTS copies) start empty.
 __global__ void k_mm_reset(int64_t count, int R, unsigned long long *__restrict__ mm) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= count) return;
@@ -988,8 +993,10 @@ __global__ void k_plan_fill(int64_t n, const int *__restrict__ tile_lg, const un
 }
 
 // Per-vector min and max of x^(k) = x + shift over non-isolated rows
-// (ordered-integer atomics); one block per chunk of CENTRE_ROWS rows of one
-// graph.
+// (ordered-integer atomics); MM_SPLIT blocks per chunk of CENTRE_ROWS rows of
+// one graph, each taking 1 / MM_SPLIT of the chunk's rows.  Block b updates copy
+// b % MM_SLOTS of the codes: atomics on one address from many blocks
+// serialise at the memory side.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_minmax(int64_t n, int R, const int64_t *__restrict__ row_ptr,
                                                  const T *__restrict__ x, const double *__restrict__ shift,
@@ -1003,7 +1010,12 @@ __global__ __launch_bounds__(BLOCK) void k_minmax(int64_t n, int R, const int64_
     const int row_off = t / R;
     int g;
     int64_t r0, r1;
-    seg_span(sg, sg.chunk_off, n, blockIdx.x, CENTRE_ROWS, g, r0, r1);
+    seg_span(sg, sg.chunk_off, n, blockIdx.x / MM_SPLIT, CENTRE_ROWS, g, r0, r1);
+    {
+        const int64_t q = (r1 - r0 + MM_SPLIT - 1) / MM_SPLIT;
+        r0 += (int64_t)(blockIdx.x % MM_SPLIT) * q;
+        r1 = min(r1, r0 + q);
+    }
     double lo = INFINITY, hi = -INFINITY;
     if (row_off < stride) {
         // four rows per step, their loads issued together (min and max do not
@@ -1041,8 +1053,9 @@ __global__ __launch_bounds__(BLOCK) void k_minmax(int64_t n, int R, const int64_
             b = fmax(b, hi_l[q]);
         }
         if (a <= b) {
-            atomicMin(&mm[(int64_t)g * 2 * R + t], ord_encode(a));
-            atomicMax(&mm[(int64_t)g * 2 * R + R + t], ord_encode(b));
+            unsigned long long *m_ = mm + ((int64_t)(blockIdx.x % MM_SLOTS) * sg.G + g) * 2 * R;
+            atomicMin(&m_[t], ord_encode(a));
+            atomicMax(&m_[R + t], ord_encode(b));
         }
     }
 }
@@ -1052,7 +1065,12 @@ __global__ void k_minmax_out(int G, int R, const unsigned long long *__restrict_
     if (idx >= (int64_t)G * R) return;
     const int64_t g = idx / R;
     const int r = (int)(idx - g * R);
-    unsigned long long a = mm[g * 2 * R + r], b = mm[g * 2 * R + R + r];
+    unsigned long long a = ~0ull, b = 0ull;
+    for (int sl = 0; sl < MM_SLOTS; ++sl) {
+        const unsigned long long *m_ = mm + ((int64_t)sl * G + g) * 2 * R;
+        a = min(a, m_[r]);
+        b = max(b, m_[R + r]);
+    }
     bool none = (a == ~0ull);
     out[g * 2 * R + r] = none ? INFINITY : ord_decode(a);
     out[g * 2 * R + R + r] = none ? -INFINITY : ord_decode(b);
@@ -1276,7 +1294,7 @@ static size_t relax_layout(const ad_graph *g, const ad_relax_opts *o, void *ws, 
     l.part_s = c.take<double>(nb);
     l.shift = c.take<double>((size_t)nshift * R);
     l.drift = (comp && o->store == AD_BF16) ? c.take<float>((size_t)nshift * R) : nullptr;
-    l.mm = c.take<unsigned long long>((size_t)sg.G * 2 * R);
+    l.mm = c.take<unsigned long long>((size_t)MM_SLOTS * sg.G * 2 * R);
     sweep_plan_carve(c, n, nt, l.p32);
     if (o->store == AD_BF16) sweep_plan_carve(c, n, nt, l.p16);
     const size_t xb = f64 ? 8 : 4;
@@ -1436,7 +1454,7 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
                                comp->n_comp, comp->chunk_start, L.part, L.part_s, 1, shift);
             AD_LAUNCH_CHECK("k_comp_finalize");
         }
-        const int64_t mmc = (int64_t)sg.G * 2 * R;
+        const int64_t mmc = (int64_t)MM_SLOTS * sg.G * 2 * R;
         hipLaunchKernelGGL(k_mm_reset, dim3((unsigned)ceil_div(mmc, BLOCK)), dim3(BLOCK), 0, st, mmc, R, L.mm);
         AD_LAUNCH_CHECK("k_mm_reset");
     } else {
@@ -1522,10 +1540,10 @@ static ad_status relax_impl(const ad_graph *g, const ad_relax_opts *o, const voi
 
     if (n > 0 && nb > 0) {
         if (out64)
-            hipLaunchKernelGGL((k_minmax<double>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, g->row_ptr,
+            hipLaunchKernelGGL((k_minmax<double>), dim3((unsigned)(nb * MM_SPLIT)), dim3(BLOCK), 0, st, n, R, g->row_ptr,
                                (const double *)x_out, shift, comp_of, L.mm, sg);
         else
-            hipLaunchKernelGGL((k_minmax<float>), dim3((unsigned)nb), dim3(BLOCK), 0, st, n, R, g->row_ptr,
+            hipLaunchKernelGGL((k_minmax<float>), dim3((unsigned)(nb * MM_SPLIT)), dim3(BLOCK), 0, st, n, R, g->row_ptr,
                                (const float *)x_out, shift, comp_of, L.mm, sg);
         AD_LAUNCH_CHECK("k_minmax");
     }
