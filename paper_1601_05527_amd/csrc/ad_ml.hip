@@ -161,7 +161,7 @@ __global__ __launch_bounds__(MBLOCK) void k_ml_ahead_list(int64_t n, const int64
 // One round of the seed traversal over the undecided vertices (state 0;
 // 1 = seed, 2 = not a seed): a vertex with a strongly coupled seed is not a
 // seed; one whose strongly coupled vertices ahead of it are all decided
-// becomes a seed; the others wait and are counted in *left.  Only the
+// becomes a seed; the others wait, and *left is set to 1 if any does.  Only the
 // strongly coupled vertices ahead of i matter while i is undecided (one
 // behind i cannot be decided a seed before i is decided), so a round reads
 // i's list of those; and since a decided state never changes, a waiting
@@ -250,8 +250,11 @@ __global__ __launch_bounds__(MBLOCK) void k_ml_seed_round(int64_t n, const uint3
             }
         }
     }
-    for (int o = WAVE / 2; o >= 1; o >>= 1) waiting += __shfl_xor(waiting, o, WAVE);
-    if (lane == 0 && waiting) atomicAdd(left, waiting);
+    // a flag, not a count: the host only asks whether any vertex waits, and
+    // an atomic add from every wave on one address serialises at the memory
+    // side (each writer stores the same value; the host reads it after the
+    // round's kernel has completed)
+    if (__ballot(waiting != 0) != 0ull && lane == 0) *left = 1ull;
 }
 
 __global__ void k_ml_seed_flags(int64_t n, const uint8_t *__restrict__ state, unsigned int *__restrict__ flag,
@@ -393,7 +396,7 @@ struct AggLayout {
     int32_t *alist;               // [nnz / 2] those lists (a strong edge is ahead from one end only)
     unsigned int *rank;           // [n] seed flags, scanned in place into aggregate ids
     unsigned int *total;          // [1] number of seeds
-    unsigned long long *left;     // [SEED_BATCH] vertices still undecided after each round of a batch
+    unsigned long long *left;     // [SEED_BATCH] 1 when a vertex is still undecided after a round of a batch
     ScanScratch scan;
 };
 
