@@ -697,7 +697,7 @@ static ad_status place_csr(int64_t n, int64_t m, const int32_t *ea, const int32_
             s = fill_i32((int32_t *)L.upper_cnt, 0, n, st);
             if (s != AD_OK) return s;
         }
-        hipLaunchKernelGGL(k_degree_max, dim3(std::min<unsigned>(1024, igrid(n))), dim3(IBLOCK), 0, st, n, L.deg,
+        hipLaunchKernelGGL(k_degree_max, dim3(std::min<unsigned>(256, igrid(n))), dim3(IBLOCK), 0, st, n, L.deg,
                            L.flags + 1);
         AD_LAUNCH_CHECK("k_degree_max");
     }

@@ -777,7 +777,7 @@ static ad_status ml_level(const ad_graph *g, const ad_ml_opts *o, int l, uint8_t
     if (ms > 0) {
         ML_TRY(dev_alloc(dmx, sizeof(unsigned int)));
         ML_TRY(fill_i32(dmx.get<int32_t>(), 0, 1, st));
-        hipLaunchKernelGGL(k_ml_degree_max, dim3(std::min<unsigned>(1024, mgrid(n))), dim3(MBLOCK), 0, st, n,
+        hipLaunchKernelGGL(k_ml_degree_max, dim3(std::min<unsigned>(256, mgrid(n))), dim3(MBLOCK), 0, st, n,
                            srp.get<const int64_t>(), dmx.get<unsigned int>());
         AD_LAUNCH_CHECK("k_ml_degree_max");
         unsigned int sdmax = 0;
@@ -885,7 +885,7 @@ extern "C" ad_status ad_ml_sparsify(const ad_graph *g, const ad_ml_opts *o, uint
         DevMem cnt;
         ML_TRY(dev_alloc(cnt, sizeof(unsigned long long)));
         ML_TRY(fill_u64(cnt.get<unsigned long long>(), 0, 1, stream));
-        hipLaunchKernelGGL(k_ml_count, dim3(std::min<unsigned>(1024, mgrid(g->m))), dim3(MBLOCK), 0, stream, g->m,
+        hipLaunchKernelGGL(k_ml_count, dim3(std::min<unsigned>(256, mgrid(g->m))), dim3(MBLOCK), 0, stream, g->m,
                            keep, cnt.get<unsigned long long>());
         AD_LAUNCH_CHECK("k_ml_count");
         unsigned long long kept = 0;

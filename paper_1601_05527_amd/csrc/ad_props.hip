@@ -770,7 +770,7 @@ extern "C" ad_status ad_graph_properties(const ad_graph *g, int64_t *lambda, dou
     if (s != AD_OK) return s;
     s = fill_u64(L.roots, 0, 1, stream);
     if (s != AD_OK) return s;
-    hipLaunchKernelGGL(k_count_roots, dim3(std::min<unsigned>(1024, pgrid(n))), dim3(PBLOCK), 0, stream, n, parent,
+    hipLaunchKernelGGL(k_count_roots, dim3(std::min<unsigned>(256, pgrid(n))), dim3(PBLOCK), 0, stream, n, parent,
                        L.roots);
     AD_LAUNCH_CHECK("k_count_roots");
     double psum[PREDUCE_BLOCKS];
